@@ -1,0 +1,249 @@
+"""CPU oracle for TS-SpGEMM -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously-correct reference implementations (``oracle.cpp``,
+ordered-map Gustavson in FP64, ordered-set boolean products, Algorithm 3 BFS,
+queue BFS, FP64 gradients). Only ``tests/``, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package. It imports
+nothing from the GPU library and the GPU library imports nothing from it.
+
+Every function takes host numpy arrays (CSR: int32 row pointers and column
+indices; values converted to float64 or int64 here) and returns numpy arrays.
+Section / equation / algorithm citations refer to the paper "Distributed-Memory
+Parallel Algorithms for Sparse Matrix and Sparse Tall-and-Skinny Matrix
+Multiplication" (SC'24).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.cpp into liboracle.so with g++ (no GPU code involved)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", _SRC, "-o", tmp, "-lpthread"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _configure(path: str):
+    """Open the shared library at `path` and declare its C signatures."""
+    lib = ctypes.CDLL(path)
+    i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+    lib.oracle_row_flops.restype = None
+    lib.oracle_row_flops.argtypes = [i64, vp, vp, vp, vp]
+    for name in ("oracle_spgemm_f64", "oracle_spgemm_i64"):
+        f = getattr(lib, name)
+        f.restype = vp
+        f.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, i64, ctypes.c_int]
+    lib.oracle_spgemm_bool.restype = vp
+    lib.oracle_spgemm_bool.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, i64, ctypes.c_int]
+    lib.oracle_res_rows.restype = i64
+    lib.oracle_res_rows.argtypes = [vp]
+    lib.oracle_res_nnz.restype = i64
+    lib.oracle_res_nnz.argtypes = [vp]
+    lib.oracle_res_copy.restype = None
+    lib.oracle_res_copy.argtypes = [vp, vp, vp, vp]
+    lib.oracle_res_free.restype = None
+    lib.oracle_res_free.argtypes = [vp]
+    lib.oracle_transpose.restype = None
+    lib.oracle_transpose.argtypes = [i64, i64, vp, vp, vp, vp, vp]
+    lib.oracle_msbfs.restype = i32
+    lib.oracle_msbfs.argtypes = [i64, vp, vp, vp, i32, vp, vp]
+    lib.oracle_bfs_queue.restype = None
+    lib.oracle_bfs_queue.argtypes = [i64, vp, vp, vp, i32, vp, ctypes.c_int]
+    lib.oracle_grad_a.restype = ctypes.c_int
+    lib.oracle_grad_a.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.oracle_grad_b.restype = ctypes.c_int
+    lib.oracle_grad_b.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.oracle_grad_a_rows.restype = ctypes.c_int
+    lib.oracle_grad_a_rows.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+    lib.oracle_grad_b_rows.restype = ctypes.c_int
+    lib.oracle_grad_b_rows.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        _lib = _configure(_LIB)
+    return _lib
+
+
+def use_library(path: str | None):
+    """Point this module at another build of oracle.cpp (used by the tests that
+    plant mistakes in a copy of the source); None restores the default."""
+    global _lib
+    _lib = None if path is None else _configure(path)
+
+
+def _i32(x):
+    return np.ascontiguousarray(x, dtype=np.int32)
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _ptr(x):
+    return None if x is None else x.ctypes.data
+
+
+def _rows_arg(rows):
+    if rows is None:
+        return None, 0
+    r = _i32(rows)
+    return r, len(r)
+
+
+def _take(h, with_val: bool):
+    lib = _load()
+    nr = lib.oracle_res_rows(h)
+    nnz = lib.oracle_res_nnz(h)
+    rp = np.empty(nr + 1, dtype=np.int64)
+    ci = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64) if with_val else None
+    lib.oracle_res_copy(h, rp.ctypes.data, ci.ctypes.data, _ptr(val))
+    lib.oracle_res_free(h)
+    return rp, ci, val
+
+
+def row_flops(arp, aci, brp) -> np.ndarray:
+    """Multiplications per output row (Sec. II-A definition of flops)."""
+    arp, aci, brp = _i32(arp), _i32(aci), _i32(brp)
+    n = len(arp) - 1
+    out = np.empty(n, dtype=np.int64)
+    _load().oracle_row_flops(n, arp.ctypes.data, aci.ctypes.data, brp.ctypes.data, out.ctypes.data)
+    return out
+
+
+def spgemm(arp, aci, aval, brp, bci, bval, rows=None, threads: int = 1):
+    """Plus-times C = A B in FP64 (Eq. 1). Returns (rp int64, ci int32, val f64)
+    for all rows, or for the listed `rows` (rp then indexes that list)."""
+    arp, aci, brp, bci = _i32(arp), _i32(aci), _i32(brp), _i32(bci)
+    aval, bval = _f64(aval), _f64(bval)
+    r, nsel = _rows_arg(rows)
+    h = _load().oracle_spgemm_f64(len(arp) - 1, arp.ctypes.data, aci.ctypes.data, aval.ctypes.data, brp.ctypes.data,
+                                  bci.ctypes.data, bval.ctypes.data, _ptr(r), nsel, threads)
+    return _take(h, True)
+
+
+def spgemm_int(arp, aci, aval, brp, bci, bval, rows=None, threads: int = 1):
+    """Plus-times over integers (int64 accumulation); values returned as int64.
+    Raises if any entry does not fit int32 (inputs must keep sums small)."""
+    arp, aci, brp, bci = _i32(arp), _i32(aci), _i32(brp), _i32(bci)
+    av = np.ascontiguousarray(aval, dtype=np.int64)
+    bv = np.ascontiguousarray(bval, dtype=np.int64)
+    r, nsel = _rows_arg(rows)
+    h = _load().oracle_spgemm_i64(len(arp) - 1, arp.ctypes.data, aci.ctypes.data, av.ctypes.data, brp.ctypes.data,
+                                  bci.ctypes.data, bv.ctypes.data, _ptr(r), nsel, threads)
+    rp, ci, val = _take(h, True)
+    vi = val.astype(np.int64)
+    if len(vi) and (vi.max() > 2**31 - 1 or vi.min() < -(2**31)):
+        raise OverflowError("integer product does not fit int32")
+    return rp, ci, vi
+
+
+def spgemm_bool(arp, aci, brp, bci, mask_rp=None, mask_ci=None, rows=None, threads: int = 1):
+    """(AND, OR) product pattern, minus the complement mask when given."""
+    arp, aci, brp, bci = _i32(arp), _i32(aci), _i32(brp), _i32(bci)
+    mrp = None if mask_rp is None else _i32(mask_rp)
+    mci = None if mask_ci is None else _i32(mask_ci)
+    r, nsel = _rows_arg(rows)
+    h = _load().oracle_spgemm_bool(len(arp) - 1, arp.ctypes.data, aci.ctypes.data, brp.ctypes.data, bci.ctypes.data,
+                                   _ptr(mrp), _ptr(mci), _ptr(r), nsel, threads)
+    rp, ci, _ = _take(h, False)
+    return rp, ci
+
+
+def transpose(arp, aci, ncols: int):
+    """CSR transpose by a row-order walk. Returns (trp, tci, perm)."""
+    arp, aci = _i32(arp), _i32(aci)
+    n = len(arp) - 1
+    trp = np.empty(ncols + 1, dtype=np.int32)
+    tci = np.empty(len(aci), dtype=np.int32)
+    perm = np.empty(len(aci), dtype=np.int32)
+    _load().oracle_transpose(n, ncols, arp.ctypes.data, aci.ctypes.data, trp.ctypes.data, tci.ctypes.data,
+                             perm.ctypes.data)
+    return trp, tci, perm
+
+
+def msbfs(arp, aci, sources):
+    """Algorithm 3 with ordered sets. Returns (levels n x d int32, per-iteration nnz(F))."""
+    arp, aci, src = _i32(arp), _i32(aci), _i32(sources)
+    n, d = len(arp) - 1, len(src)
+    lev = np.empty((n, d), dtype=np.int32)
+    fn = np.zeros(4096, dtype=np.int64)
+    it = _load().oracle_msbfs(n, arp.ctypes.data, aci.ctypes.data, src.ctypes.data, d, lev.ctypes.data,
+                              fn.ctypes.data)
+    return lev, fn[:it]
+
+
+def bfs_queue(arp, aci, sources, threads: int = 1):
+    """One plain queue BFS per source (independent check of Algorithm 3)."""
+    arp, aci, src = _i32(arp), _i32(aci), _i32(sources)
+    n, d = len(arp) - 1, len(src)
+    lev = np.empty((n, d), dtype=np.int32)
+    _load().oracle_bfs_queue(n, arp.ctypes.data, aci.ctypes.data, src.ctypes.data, d, lev.ctypes.data, threads)
+    return lev
+
+
+def grad_a(arp, aci, brp, bci, bval, crp, cci, g):
+    """dL/dA on pat(A) for L = sum(C o W), G = W on pat(C)."""
+    arp, aci, brp, bci, crp, cci = map(_i32, (arp, aci, brp, bci, crp, cci))
+    bval, g = _f64(bval), _f64(g)
+    out = np.empty(len(aci), dtype=np.float64)
+    rc = _load().oracle_grad_a(len(arp) - 1, arp.ctypes.data, aci.ctypes.data, brp.ctypes.data, bci.ctypes.data,
+                               bval.ctypes.data, crp.ctypes.data, cci.ctypes.data, g.ctypes.data, out.ctypes.data)
+    if rc:
+        raise ValueError("G is missing an entry of pat(C) needed by dL/dA")
+    return out
+
+
+def grad_b(arp, aci, aval, brp, bci, crp, cci, g):
+    """dL/dB on pat(B) for L = sum(C o W), G = W on pat(C)."""
+    arp, aci, brp, bci, crp, cci = map(_i32, (arp, aci, brp, bci, crp, cci))
+    aval, g = _f64(aval), _f64(g)
+    out = np.empty(len(bci), dtype=np.float64)
+    rc = _load().oracle_grad_b(len(arp) - 1, arp.ctypes.data, aci.ctypes.data, aval.ctypes.data, brp.ctypes.data,
+                               bci.ctypes.data, crp.ctypes.data, cci.ctypes.data, g.ctypes.data, out.ctypes.data)
+    if rc:
+        raise ValueError("G is missing an entry of pat(C) needed by dL/dB")
+    return out
+
+
+def grad_a_rows(arp, aci, brp, bci, bval, crp, cci, g, rows):
+    """dL/dA restricted to the A entries of the listed rows (concatenated)."""
+    arp, aci, brp, bci, crp, cci, rows = map(_i32, (arp, aci, brp, bci, crp, cci, rows))
+    bval, g = _f64(bval), _f64(g)
+    out = np.empty(int(sum(int(arp[i + 1]) - int(arp[i]) for i in rows)), dtype=np.float64)
+    rc = _load().oracle_grad_a_rows(arp.ctypes.data, aci.ctypes.data, brp.ctypes.data, bci.ctypes.data,
+                                    bval.ctypes.data, crp.ctypes.data, cci.ctypes.data, g.ctypes.data,
+                                    rows.ctypes.data, len(rows), out.ctypes.data)
+    if rc:
+        raise ValueError("G is missing an entry of pat(C) needed by dL/dA")
+    return out
+
+
+def grad_b_rows(arp, aci, aval, brp, bci, crp, cci, g, krows):
+    """dL/dB restricted to the B entries of the listed rows (concatenated)."""
+    arp, aci, brp, bci, crp, cci, krows = map(_i32, (arp, aci, brp, bci, crp, cci, krows))
+    aval, g = _f64(aval), _f64(g)
+    out = np.empty(int(sum(int(brp[k + 1]) - int(brp[k]) for k in krows)), dtype=np.float64)
+    rc = _load().oracle_grad_b_rows(len(arp) - 1, arp.ctypes.data, aci.ctypes.data, aval.ctypes.data,
+                                    brp.ctypes.data, bci.ctypes.data, crp.ctypes.data, cci.ctypes.data,
+                                    g.ctypes.data, krows.ctypes.data, len(krows), out.ctypes.data)
+    if rc:
+        raise ValueError("G is missing an entry of pat(C) needed by dL/dB")
+    return out
