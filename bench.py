@@ -1,0 +1,223 @@
+"""Benchmark of the TS-SpGEMM hot path on one MI355X.
+
+One step = one full plain TS-SpGEMM C = A B (symbolic phase: B bitmap, row
+binning, bitmap-accumulator pattern, popcount scan, numeric binning, one host
+sync for nnz(C); numeric phase: the LDS dense-strip kernel) over the R-MAT
+scale-20 (edge factor 16) x (n x 128, Poisson(25.6) entries per row) workload,
+all inputs resident in HBM. Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--scale S]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_numeric.hip", "core.hpp", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2408_11988_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per numeric launch from the committed rocprofv3 counter summary,
+    or None when the summary is missing or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        t = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return float(e["bytes_per_launch"])
+
+
+def copy_bandwidth_gbs(torch):
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(10):
+        b.copy_(a)
+    e.record()
+    e.synchronize()
+    t = s.elapsed_time(e) / 10 / 1e3
+    del a, b
+    return 2 * 4 * n / t / 1e9
+
+
+def cpu_baseline(a, b, flops_rows, target_s=12.0):
+    """The oracle as it stands, on a random sample of rows of the same workload."""
+    import numpy as np
+
+    import oracle
+
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    rng = np.random.default_rng(1234)
+    n = a.nrows
+    probe = rng.choice(n, size=min(n, 20000), replace=False).astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.spgemm(a.rp, a.ci, a.val, b.rp, b.ci, b.val, rows=probe, threads=threads)
+    t_probe = time.perf_counter() - t0
+    f_probe = max(1, int(flops_rows[probe].sum()))
+    est_full = t_probe * float(flops_rows.sum()) / f_probe
+    frac = min(1.0, target_s / max(est_full, 1e-9))
+    if frac >= 1.0:
+        rows = None
+        sample = "all rows"
+        fl = int(flops_rows.sum())
+    else:
+        k = max(1, int(frac * n))
+        rows = np.sort(rng.choice(n, size=k, replace=False)).astype(np.int32)
+        sample = f"{k} uniformly sampled rows of {n} ({100.0 * k / n:.1f}%)"
+        fl = int(flops_rows[rows].sum())
+    t0 = time.perf_counter()
+    oracle.spgemm(a.rp, a.ci, a.val, b.rp, b.ci, b.val, rows=rows, threads=threads)
+    t = time.perf_counter() - t0
+    return {"value": round(2.0 * fl / t / 1e9, 4), "unit": "GFLOPS", "cores": threads, "kind": "oracle",
+            "sample": f"{sample}; {fl} multiplications in {t:.2f} s (ordered-map Gustavson, FP64)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--d", type=int, default=128)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: TS-SpGEMM here is one rank's local multiply "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_11988_amd import DeviceCsr, _lib
+
+    lib = _lib.load()
+    torch.cuda.set_device(0)
+    workload = f"rmat{args.scale}_d{args.d}_plain"
+    log(f"generating R-MAT scale {args.scale} x d={args.d}")
+    a, b = synth.workload_rmat_plain(scale=args.scale, d=args.d)
+    A = DeviceCsr.from_host(a)
+    B = DeviceCsr.from_host(b)
+    da, db = A.desc(), B.desc()
+    n, d = a.nrows, b.ncols
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    c_rowptr = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    plan = ctypes.c_void_p(None)
+    nnz = ctypes.c_int64(0)
+
+    def symbolic():
+        _lib.check(lib.tsspgemm_symbolic(ctypes.byref(da), ctypes.byref(db), _lib.PLUS_TIMES_F32, None, None,
+                                         ctypes.c_void_p(c_rowptr.data_ptr()), ctypes.byref(nnz),
+                                         ctypes.byref(plan), sp), "symbolic")
+        return int(nnz.value)
+
+    nnz_c = symbolic()
+    c_colidx = torch.empty(nnz_c, dtype=torch.int32, device="cuda")
+    c_vals = torch.empty(nnz_c, dtype=torch.float32, device="cuda")
+
+    def numeric():
+        _lib.check(lib.tsspgemm_numeric(plan, ctypes.byref(da), ctypes.byref(db),
+                                        ctypes.c_void_p(c_colidx.data_ptr()), ctypes.c_void_p(c_vals.data_ptr()),
+                                        sp), "numeric")
+
+    st = [ctypes.c_int64() for _ in range(6)]
+    lib.tsspgemm_plan_stats(plan, *[ctypes.byref(x) for x in st])
+    flops, _, light_rows, wave_rows, block_rows, split_rows = [int(x.value) for x in st]
+    log(f"nnz(A)={a.nnz} nnz(B)={b.nnz} nnz(C)={nnz_c} flops={flops} rows: light={light_rows} wave={wave_rows} "
+        f"block={block_rows} split={split_rows}")
+
+    for _ in range(args.warmup):
+        symbolic()
+        numeric()
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        symbolic()
+        ev[k][1].record(stream)
+        numeric()
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_sym = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    ms_num = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+    log(f"step {ms_step:.3f} ms  symbolic {ms_sym:.3f} ms  numeric {ms_num:.3f} ms")
+
+    bytes_alg = (4 * (n + 1) + 8 * a.nnz) + (4 * (n + 1) + 8 * b.nnz) + (4 * (n + 1) + 8 * nnz_c)
+    achieved = bytes_alg / (ms_num / 1e3) / 1e9
+    traffic = measured_traffic(workload)
+    copy_bw = copy_bandwidth_gbs(torch)
+
+    result = {
+        "metric": "TS-SpGEMM GFLOPS (2x mults/s) + % HBM roofline; batched & fwd+bwd vs plain",
+        "value": round(2.0 * flops / (ms_step / 1e3) / 1e9, 3),
+        "unit": "GFLOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "precision": "FP32 inputs and outputs; products and sums in FP64, one rounding to FP32",
+        "data": "synthetic (seeded R-MAT and Poisson tall-skinny B; inputs resident in HBM)",
+        "config": {"workload": f"R-MAT scale {args.scale} (edge factor 16, symmetrised) x B n x {args.d} "
+                               f"Poisson({0.2 * args.d:g}) entries/row, plus-times FP32",
+                   "n": n, "d": d, "nnz_a": a.nnz, "nnz_b": b.nnz, "nnz_c": nnz_c, "flops": flops},
+        "ms_symbolic": round(ms_sym, 4),
+        "ms_numeric": round(ms_num, 4),
+        "gflops_numeric_only": round(2.0 * flops / (ms_num / 1e3) / 1e9, 3),
+        "output_nnz_per_s": round(nnz_c / (ms_step / 1e3), 1),
+        "roofline": {"bound": "hbm", "kernel": "k_numeric", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "bytes_alg_per_launch": bytes_alg},
+        "copy_bw_gbs": round(copy_bw, 1),
+    }
+    if not args.no_cpu:
+        log("timing the oracle on the host")
+        import oracle
+
+        flops_rows = oracle.row_flops(a.rp, a.ci, b.rp)
+        result["cpu_baseline"] = cpu_baseline(a, b, flops_rows)
+    else:
+        result["cpu_baseline"] = None
+    lib.tsspgemm_plan_destroy(plan)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/* tsspgemm.h -- C ABI of the TS-SpGEMM library for AMD Instinct MI355X (gfx950).
+ *
+ * TS-SpGEMM (Sec. II-A of "Distributed-Memory Parallel Algorithms for Sparse
+ * Matrix and Sparse Tall-and-Skinny Matrix Multiplication", SC'24): C = A B
+ * where A is a square n x n sparse matrix and B is a tall-and-skinny sparse
+ * n x d matrix (d << n), over plus-times or over the Boolean (AND, OR)
+ * semiring, the latter optionally with a complement mask (the multi-source
+ * BFS step of Sec. IV-A, Algorithm 3). The local multiply is row-wise
+ * Gustavson (Sec. III-A, Eq. 1) with a dense accumulator of width d for
+ * d <= 1024 and a hash accumulator above (Sec. III-C).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array pointer is a DEVICE pointer unless its comment says HOST.
+ *  - The caller allocates every input and output buffer and keeps it alive
+ *    until the work queued on `stream` has finished. The library owns only
+ *    the workspace inside a plan / batch handle (freed by the matching
+ *    *_destroy call) and a per-device scratch cache that it reuses between
+ *    calls. Inputs are never modified.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is stream-ordered; only calls documented as "synchronizes" block
+ *    the host (they return a count the caller needs to size an output).
+ *  - CSR layout: rowptr[nrows+1] (rowptr[0] = 0, non-decreasing), colidx[nnz]
+ *    strictly increasing within each row and in [0, ncols), int32; values in
+ *    the order of colidx (float32 for PLUS_TIMES_F32, int32 for
+ *    PLUS_TIMES_I32, unused and may be NULL for OR_AND). nnz must fit int32.
+ *    With the environment variable TSSPGEMM_VALIDATE=1 inputs are checked on
+ *    the device and TSSPGEMM_ERR_MALFORMED is returned for a broken one.
+ *  - Return value: TSSPGEMM_OK (0) or a negative error code below. No C++
+ *    exception crosses this boundary. tsspgemm_last_error() gives a message
+ *    (thread-local) for the last failing call on this thread.
+ */
+#ifndef TSSPGEMM_H
+#define TSSPGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSSPGEMM_OK 0
+#define TSSPGEMM_ERR_INVALID_ARG (-1) /* null pointer, shape mismatch, bad enum   */
+#define TSSPGEMM_ERR_MALFORMED (-2)   /* CSR invariant broken (validation on)     */
+#define TSSPGEMM_ERR_OVERFLOW (-3)    /* nnz(C) or a row count exceeds INT32_MAX   */
+#define TSSPGEMM_ERR_CAPACITY (-4)    /* caller's output too small; size returned  */
+#define TSSPGEMM_ERR_UNSUPPORTED (-5) /* semiring / mask / size combination        */
+#define TSSPGEMM_ERR_HIP (-6)         /* HIP runtime error (message kept)          */
+#define TSSPGEMM_ERR_NOMEM (-7)       /* device workspace allocation failed        */
+
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  const int32_t* rowptr; /* nrows + 1 */
+  const int32_t* colidx; /* nnz */
+  const void* vals;      /* nnz values or NULL (pattern only) */
+} tsspgemm_csr;
+
+typedef enum {
+  TSSPGEMM_PLUS_TIMES_F32 = 0, /* float inputs, FP64 accumulation, float output */
+  TSSPGEMM_PLUS_TIMES_I32 = 1, /* int32, wrap-around (two's complement) sums     */
+  TSSPGEMM_OR_AND = 2          /* pattern only: (AND, OR) semiring               */
+} tsspgemm_semiring;
+
+typedef enum {
+  TSSPGEMM_MASK_NONE = 0,
+  TSSPGEMM_MASK_COMPLEMENT_CSR = 1,   /* drop C(i,j) when (i,j) is stored in csr       */
+  TSSPGEMM_MASK_COMPLEMENT_BITMAP = 2 /* drop C(i,j) when bit j of bits row i is set   */
+} tsspgemm_mask_kind;
+
+typedef struct {
+  int32_t kind;            /* tsspgemm_mask_kind */
+  const tsspgemm_csr* csr; /* n x d pattern (kind 1) */
+  const uint32_t* bits;    /* n rows x tsspgemm_bitmap_words(d) words, bit j of row i at
+                              word j/32, bit j%32 (kind 2) */
+} tsspgemm_mask;
+
+/* Tuning knobs. A NULL tuning pointer, or a zero field, means "default".
+ * Results (structure and values) do not depend on any of these. */
+typedef struct {
+  int32_t group_lanes;     /* lanes that stream one B row: 4,8,16,32,64 (0: from mean B row length) */
+  int32_t wave_max_flops;  /* rows with at most this many products use one wavefront             */
+  int32_t split_flops;     /* rows above this are split into chunks of about this many products   */
+  int32_t sym_split_nnz;   /* symbolic pass: rows with more A entries than this are split         */
+  int32_t accumulator;     /* 0 auto, 1 dense strip (d <= 1024), 2 hash                            */
+  int32_t light_max_flops; /* rows with at most this many products use one lane group            */
+} tsspgemm_tuning;
+
+typedef struct tsspgemm_plan_s* tsspgemm_plan;
+
+/* Number of 32-bit words per row of a bitmap of width d as used by this
+ * library (d/32 rounded up to a power of two). */
+int32_t tsspgemm_bitmap_words(int32_t d);
+
+/* Symbolic phase (Sec. III-A, Eq. 1 structure; the symbolic nnz count of
+ * Sec. III-D): computes flops per row (Sec. II-A), bins rows by work, the
+ * output pattern as a bitmap accumulator, and C's row pointers.
+ *   A: n x n, B: n x d (vals unused). sr: tsspgemm_semiring the plan is for.
+ *   M: complement mask or NULL. tune: NULL for defaults.
+ *   c_rowptr: caller-allocated, n + 1 int32, written.
+ *   c_nnz: HOST out, nnz(C). Synchronizes `stream`.
+ *   plan: in/out. If *plan is non-NULL its workspace is reused (grown as
+ *   needed); otherwise a new plan is created. Destroy with tsspgemm_plan_destroy.
+ * Errors: INVALID_ARG, UNSUPPORTED (d > 1024 with the dense accumulator
+ * forced), OVERFLOW (nnz(C) > INT32_MAX), NOMEM, HIP. */
+int tsspgemm_symbolic(const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t sr, const tsspgemm_mask* M,
+                      const tsspgemm_tuning* tune, int32_t* c_rowptr, int64_t* c_nnz, tsspgemm_plan* plan,
+                      void* stream);
+
+/* Numeric phase (Sec. III-A, Eq. 1 values; Sec. III-C accumulators): fills
+ * C's column indices and values in the positions fixed by the plan. A and B
+ * must have the patterns the plan was built with; their values may differ
+ * between calls (so one plan serves every training step).
+ *   c_colidx: nnz(C) int32, c_vals: nnz(C) float/int32 (NULL for OR_AND).
+ * Asynchronous. Errors: INVALID_ARG, HIP. */
+int tsspgemm_numeric(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* c_colidx,
+                     void* c_vals, void* stream);
+
+/* Statistics of the last symbolic call on `plan` (HOST out pointers, any may
+ * be NULL): total products (flops, Sec. II-A), nnz(C), and the number of
+ * rows handled per lane group / per wavefront / per workgroup / split. */
+int tsspgemm_plan_stats(tsspgemm_plan plan, int64_t* flops, int64_t* c_nnz, int64_t* light_rows,
+                        int64_t* wave_rows, int64_t* block_rows, int64_t* split_rows);
+
+void tsspgemm_plan_destroy(tsspgemm_plan plan);
+
+/* One masked Boolean TS-SpGEMM (the N = A F, F = N \ S step of Algorithm 3,
+ * Sec. IV-A): C = (A F over (AND, OR)) with the complement mask `visited`.
+ *   F: n x d pattern. visited: mask (kind 1 or 2) or NULL.
+ *   c_rowptr: n + 1 int32 (always written). c_colidx: capacity int32.
+ *   c_nnz: HOST out. Synchronizes. If nnz(C) > c_capacity, returns
+ *   TSSPGEMM_ERR_CAPACITY with *c_nnz and c_rowptr filled so the caller can
+ *   grow and call again. */
+int tsspgemm_masked_bool(const tsspgemm_csr* A, const tsspgemm_csr* F, const tsspgemm_mask* visited,
+                         int32_t* c_rowptr, int32_t* c_colidx, int64_t c_capacity, int64_t* c_nnz, void* stream);
+
+/* Multi-source BFS (Sec. IV-A, Algorithm 3) from d sources by repeated masked
+ * Boolean TS-SpGEMM until every frontier is empty.
+ *   A: n x n pattern. sources: d distinct vertex ids (device).
+ *   levels: n x d int32 row-major: level[v*d + s] = BFS depth of v from
+ *   sources[s] (0 at the source, -1 if unreachable).
+ *   iterations: HOST out, number of non-empty frontiers after the first.
+ *   frontier_nnz: HOST array of `capacity` int64 or NULL: nnz(F) per iteration.
+ *   Synchronizes once per iteration. d <= 1024. */
+int tsspgemm_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, int32_t* levels, int32_t* iterations,
+                   int64_t* frontier_nnz, int32_t capacity, void* stream);
+
+/* CSR transpose of A's pattern (the single-GPU form of the column-partitioned
+ * copy A^c of Sec. III-A): at_rowptr (ncols+1), at_colidx (nnz) with rows
+ * listed in ascending order, at_perm (nnz): position in A of each entry.
+ * Asynchronous. */
+int tsspgemm_transpose(const tsspgemm_csr* A, int32_t* at_rowptr, int32_t* at_colidx, int32_t* at_perm,
+                       void* stream);
+
+/* Backward of a plus-times TS-SpGEMM for a loss L with G = dL/dC given on
+ * C's pattern (G->rowptr/colidx equal C's, G->vals float):
+ *   grad_a[p] = sum over j in pat(B_k) of G(i,j) B(k,j) for the p-th entry
+ *   (i,k) of A (an SDDMM on A's pattern);
+ *   grad_b[q] = sum over i with (i,k) in pat(A) of A(i,k) G(i,j) for the q-th
+ *   entry (k,j) of B (A^T G sampled on B's pattern), using A^T from
+ *   tsspgemm_transpose.
+ * plan: the forward plan of C = A B (its output bitmap speeds up lookups) or
+ * NULL. Asynchronous. */
+int tsspgemm_grad_a(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_csr* B, const tsspgemm_csr* G,
+                    float* grad_a, void* stream);
+int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,
+                    const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_b, void* stream);
+
+/* Batched plus-times TS-SpGEMM: `count` independent instances C_t = A_t B_t.
+ * tsspgemm_batched_plan (synchronizes) sizes everything once:
+ *   As, Bs: HOST arrays of `count` descriptors (device data).
+ *   pool_capacity: HOST out, entries needed in the shared output pool.
+ *   rowptr_total: HOST out, sum of (n_t + 1).
+ * tsspgemm_batched_run queues the whole batch (symbolic, scan, numeric) with
+ * no host synchronisation and no allocation, so it may be captured in a HIP
+ * graph: c_rowptrs (rowptr_total int32; instance t's row pointers start at
+ * sum_{s<t} (n_s + 1) and are relative to its own output), pool_colidx /
+ * pool_vals (pool_capacity), c_offsets (count + 1 int64: instance t's output
+ * occupies [c_offsets[t], c_offsets[t+1]) of the pool). */
+typedef struct tsspgemm_batch_s* tsspgemm_batch;
+int tsspgemm_batched_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr* Bs,
+                          const tsspgemm_tuning* tune, tsspgemm_batch* out, int64_t* pool_capacity,
+                          int64_t* rowptr_total, void* stream);
+int tsspgemm_batched_run(tsspgemm_batch batch, int32_t* c_rowptrs, int32_t* pool_colidx, float* pool_vals,
+                         int64_t* c_offsets, void* stream);
+void tsspgemm_batched_destroy(tsspgemm_batch batch);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* tsspgemm_last_error(void);
+
+/* Library version string. */
+const char* tsspgemm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSSPGEMM_H */

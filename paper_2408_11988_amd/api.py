@@ -1,0 +1,220 @@
+"""Python face of libtsspgemm.so: marshals torch device tensors into the C ABI.
+
+Nothing here computes: shapes are checked, buffers are allocated with torch
+on the current device, and the library is called on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import TSSpGEMMError  # noqa: F401
+
+SEMIRINGS = {"plus_times": _lib.PLUS_TIMES_F32, "plus_times_f32": _lib.PLUS_TIMES_F32,
+             "plus_times_i32": _lib.PLUS_TIMES_I32, "or_and": _lib.OR_AND}
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class DeviceCsr:
+    """CSR on the GPU: int32 rowptr (nrows+1), int32 colidx (nnz), values or None."""
+
+    nrows: int
+    ncols: int
+    rowptr: torch.Tensor
+    colidx: torch.Tensor
+    vals: torch.Tensor | None = None
+
+    @property
+    def nnz(self) -> int:
+        return int(self.colidx.numel())
+
+    @staticmethod
+    def from_host(m, device="cuda", dtype=torch.float32, with_values=True) -> "DeviceCsr":
+        """From any host CSR with .nrows .ncols .rp .ci (.val) numpy arrays."""
+        rp = torch.from_numpy(np.ascontiguousarray(m.rp, dtype=np.int32)).to(device)
+        ci = torch.from_numpy(np.ascontiguousarray(m.ci, dtype=np.int32)).to(device)
+        v = None
+        if with_values and getattr(m, "val", None) is not None:
+            v = torch.from_numpy(np.ascontiguousarray(m.val)).to(device=device, dtype=dtype)
+        return DeviceCsr(int(m.nrows), int(m.ncols), rp, ci, v)
+
+    def with_vals(self, vals: torch.Tensor | None) -> "DeviceCsr":
+        return DeviceCsr(self.nrows, self.ncols, self.rowptr, self.colidx, vals)
+
+    def desc(self) -> _lib.CsrDesc:
+        if self.rowptr.dtype != torch.int32 or self.colidx.dtype != torch.int32:
+            raise TypeError("rowptr and colidx must be int32")
+        if not (self.rowptr.is_cuda and self.colidx.is_cuda):
+            raise TypeError("CSR arrays must live on the GPU")
+        if self.rowptr.numel() != self.nrows + 1:
+            raise ValueError("rowptr must have nrows + 1 entries")
+        for t in (self.rowptr, self.colidx, self.vals):
+            if t is not None and not t.is_contiguous():
+                raise ValueError("CSR arrays must be contiguous")
+        return _lib.CsrDesc(self.nrows, self.ncols, self.nnz, self.rowptr.data_ptr(),
+                            self.colidx.data_ptr() if self.nnz else None,
+                            self.vals.data_ptr() if self.vals is not None and self.nnz else None)
+
+    def to_host(self):
+        return (self.rowptr.cpu().numpy(), self.colidx.cpu().numpy(),
+                None if self.vals is None else self.vals.cpu().numpy())
+
+
+def _tuning(t: dict | None):
+    if not t:
+        return None
+    return ctypes.byref(_lib.Tuning(int(t.get("group_lanes", 0)), int(t.get("wave_max_flops", 0)),
+                                    int(t.get("split_flops", 0)), int(t.get("sym_split_nnz", 0)),
+                                    int(t.get("accumulator", 0)), int(t.get("light_max_flops", 0))))
+
+
+class Plan:
+    """Owns a tsspgemm_plan (symbolic result + workspace); reusable."""
+
+    def __init__(self):
+        self.handle = ctypes.c_void_p(None)
+        self.semiring = None
+        self.c_rowptr = None
+        self.nnz = 0
+
+    def stats(self) -> dict:
+        vals = [ctypes.c_int64() for _ in range(6)]
+        _lib.check(_lib.load().tsspgemm_plan_stats(self.handle, *[ctypes.byref(v) for v in vals]), "plan_stats")
+        keys = ("flops", "nnz", "light_rows", "wave_rows", "block_rows", "split_rows")
+        return {k: int(v.value) for k, v in zip(keys, vals)}
+
+    def __del__(self):
+        try:
+            if self.handle and self.handle.value:
+                _lib.load().tsspgemm_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def _mask_desc(mask, keep):
+    """mask: None, a DeviceCsr (complement by pattern) or a uint32/int32 bitmap tensor."""
+    if mask is None:
+        return None
+    if isinstance(mask, DeviceCsr):
+        d = mask.desc()
+        keep.append(d)
+        return ctypes.byref(_lib.MaskDesc(_lib.MASK_COMPLEMENT_CSR, ctypes.pointer(d), None))
+    if isinstance(mask, torch.Tensor):
+        if not mask.is_cuda or mask.dtype not in (torch.int32, torch.uint32) or not mask.is_contiguous():
+            raise TypeError("bitmap mask must be a contiguous int32/uint32 CUDA tensor")
+        return ctypes.byref(_lib.MaskDesc(_lib.MASK_COMPLEMENT_BITMAP, None, mask.data_ptr()))
+    raise TypeError("mask must be None, a DeviceCsr or a bitmap tensor")
+
+
+def symbolic(A: DeviceCsr, B: DeviceCsr, semiring="plus_times", mask=None, tuning: dict | None = None,
+             plan: Plan | None = None, stream=None):
+    """Run the symbolic phase. Returns (plan, c_rowptr int32 tensor, nnz(C))."""
+    sr = SEMIRINGS[semiring]
+    plan = plan or Plan()
+    c_rowptr = torch.empty(A.nrows + 1, dtype=torch.int32, device=A.rowptr.device)
+    nnz = ctypes.c_int64(0)
+    keep = []
+    da, db = A.desc(), B.desc()
+    rc = _lib.load().tsspgemm_symbolic(ctypes.byref(da), ctypes.byref(db), sr, _mask_desc(mask, keep),
+                                       _tuning(tuning), ctypes.c_void_p(c_rowptr.data_ptr()), ctypes.byref(nnz),
+                                       ctypes.byref(plan.handle), _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_symbolic")
+    plan.semiring = semiring
+    plan.c_rowptr = c_rowptr
+    plan.nnz = int(nnz.value)
+    return plan, c_rowptr, int(nnz.value)
+
+
+def numeric(plan: Plan, A: DeviceCsr, B: DeviceCsr, c_colidx: torch.Tensor, c_vals: torch.Tensor | None,
+            stream=None):
+    da, db = A.desc(), B.desc()
+    rc = _lib.load().tsspgemm_numeric(plan.handle, ctypes.byref(da), ctypes.byref(db), _ptr(c_colidx),
+                                      _ptr(c_vals), _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_numeric")
+
+
+def spgemm(A: DeviceCsr, B: DeviceCsr, semiring="plus_times", mask=None, tuning: dict | None = None,
+           plan: Plan | None = None, stream=None, return_plan=False):
+    """C = A B (Eq. 1) over `semiring`; C is a DeviceCsr (values None for or_and)."""
+    plan, c_rowptr, nnz = symbolic(A, B, semiring, mask, tuning, plan, stream)
+    dev = A.rowptr.device
+    c_colidx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    c_vals = None
+    if semiring in ("plus_times", "plus_times_f32"):
+        c_vals = torch.empty(nnz, dtype=torch.float32, device=dev)
+    elif semiring == "plus_times_i32":
+        c_vals = torch.empty(nnz, dtype=torch.int32, device=dev)
+    numeric(plan, A, B, c_colidx, c_vals, stream)
+    C = DeviceCsr(A.nrows, B.ncols, c_rowptr, c_colidx, c_vals)
+    return (C, plan) if return_plan else C
+
+
+def masked_bool(A: DeviceCsr, F: DeviceCsr, visited=None, capacity: int | None = None, stream=None) -> DeviceCsr:
+    """One (AND, OR) product with complement mask (Algorithm 3's N \\ S)."""
+    dev = A.rowptr.device
+    c_rowptr = torch.empty(A.nrows + 1, dtype=torch.int32, device=dev)
+    cap = capacity if capacity is not None else max(1, min(A.nrows * F.ncols, 1 << 26))
+    keep = []
+    da, df = A.desc(), F.desc()
+    mdesc = _mask_desc(visited, keep)
+    lib = _lib.load()
+    while True:
+        c_colidx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        nnz = ctypes.c_int64(0)
+        rc = lib.tsspgemm_masked_bool(ctypes.byref(da), ctypes.byref(df), mdesc, ctypes.c_void_p(c_rowptr.data_ptr()),
+                                      ctypes.c_void_p(c_colidx.data_ptr()), cap, ctypes.byref(nnz), _stream_ptr(stream))
+        if rc == _lib.ERR_CAPACITY:
+            cap = int(nnz.value)
+            continue
+        _lib.check(rc, "tsspgemm_masked_bool")
+        return DeviceCsr(A.nrows, F.ncols, c_rowptr, c_colidx[:int(nnz.value)].contiguous())
+
+
+def msbfs(A: DeviceCsr, sources: torch.Tensor, stream=None):
+    """Multi-source BFS (Algorithm 3). Returns (levels n x d int32, per-iteration nnz(F))."""
+    d = int(sources.numel())
+    levels = torch.empty((A.nrows, d), dtype=torch.int32, device=A.rowptr.device)
+    it = ctypes.c_int32(0)
+    cap = 4096
+    fn = (ctypes.c_int64 * cap)()
+    src = sources.to(device=A.rowptr.device, dtype=torch.int32).contiguous()
+    da = A.desc()
+    rc = _lib.load().tsspgemm_msbfs(ctypes.byref(da), ctypes.c_void_p(src.data_ptr()), d,
+                                    ctypes.c_void_p(levels.data_ptr()), ctypes.byref(it), fn, cap, _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_msbfs")
+    return levels, [int(fn[t]) for t in range(min(it.value, cap))]
+
+
+def transpose(A: DeviceCsr, stream=None):
+    """A^T as (DeviceCsr pattern, perm) where perm maps A^T entries to A entries."""
+    dev = A.rowptr.device
+    at_rp = torch.empty(A.ncols + 1, dtype=torch.int32, device=dev)
+    at_ci = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    perm = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    da = A.desc()
+    rc = _lib.load().tsspgemm_transpose(ctypes.byref(da), ctypes.c_void_p(at_rp.data_ptr()),
+                                        ctypes.c_void_p(at_ci.data_ptr()), ctypes.c_void_p(perm.data_ptr()),
+                                        _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_transpose")
+    return DeviceCsr(A.ncols, A.nrows, at_rp, at_ci[:A.nnz]), perm[:A.nnz]
+
+
+def bitmap_words(d: int) -> int:
+    return int(_lib.load().tsspgemm_bitmap_words(d))
+
+
+def version() -> str:
+    return _lib.load().tsspgemm_version().decode()

@@ -1,0 +1,420 @@
+// C ABI of the TS-SpGEMM library: argument checks, plans and their device
+// workspace, and the ordering of the kernels of each call. Declarations and
+// contracts are in include/tsspgemm.h.
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "api_internal.hpp"
+
+namespace tss {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+const std::string& get_error() { return g_last_error; }
+
+int DevBuf::ensure(size_t bytes) {
+  if (bytes <= cap) return TSSPGEMM_OK;
+  if (p) {
+    hipError_t e = hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (e != hipSuccess) {
+      set_error(std::string("hipFree: ") + hipGetErrorString(e));
+      return TSSPGEMM_ERR_HIP;
+    }
+  }
+  size_t want = bytes < 256 ? 256 : bytes;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    set_error("device workspace allocation of " + std::to_string(want) + " bytes failed: " + hipGetErrorString(e));
+    return TSSPGEMM_ERR_NOMEM;
+  }
+  cap = want;
+  return TSSPGEMM_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+bool validate_enabled() {
+  const char* v = std::getenv("TSSPGEMM_VALIDATE");
+  return v && v[0] == '1';
+}
+
+int check_csr(const tsspgemm_csr* m, const char* name, bool need_vals) {
+  if (!m) {
+    set_error(std::string(name) + " is NULL");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (m->nrows < 0 || m->ncols < 0 || m->nnz < 0) {
+    set_error(std::string(name) + ": negative shape or nnz");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (m->nrows > INT32_MAX - 1 || m->ncols > INT32_MAX || m->nnz > INT32_MAX) {
+    set_error(std::string(name) + ": shape or nnz exceeds int32 indexing");
+    return TSSPGEMM_ERR_OVERFLOW;
+  }
+  if (!m->rowptr || (m->nnz > 0 && !m->colidx) || (need_vals && m->nnz > 0 && !m->vals)) {
+    set_error(std::string(name) + ": NULL array");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  return TSSPGEMM_OK;
+}
+
+// Device check of CSR invariants (only with TSSPGEMM_VALIDATE=1); synchronizes.
+int validate_on_device(const tsspgemm_csr* m, const char* name, Counters* dctr, Counters* hctr, hipStream_t st) {
+  int rc = launch_zero_bytes(dctr, sizeof(Counters), st);
+  if (rc) return rc;
+  rc = launch_validate_csr(m->nrows, m->ncols, m->nnz, m->rowptr, m->colidx, dctr, st);
+  if (rc) return rc;
+  TSS_HIP(hipMemcpyAsync(hctr, dctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  TSS_HIP(hipStreamSynchronize(st));
+  if (hctr->malformed) {
+    set_error(std::string(name) + ": malformed CSR (row pointers or sorted unique in-range columns)");
+    return TSSPGEMM_ERR_MALFORMED;
+  }
+  return TSSPGEMM_OK;
+}
+
+static int plan_alloc_host(Plan* p) {
+  if (p->host_ctr) return TSSPGEMM_OK;
+  void* h = nullptr;
+  TSS_HIP(hipHostMalloc(&h, sizeof(Counters), hipHostMallocDefault));
+  p->host_ctr = (Counters*)h;
+  return TSSPGEMM_OK;
+}
+
+void plan_free(Plan* p) {
+  for (DevBuf* b : {&p->bbits, &p->cbits, &p->flops, &p->cnt, &p->scan, &p->sym_items, &p->num_items,
+                    &p->split_rows, &p->partial, &p->ctr, &p->maskbits})
+    b->release();
+  if (p->host_ctr) (void)hipHostFree(p->host_ctr);
+  p->host_ctr = nullptr;
+}
+
+void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tuning* out) {
+  tsspgemm_tuning r{};
+  if (t) r = *t;
+  if (r.group_lanes == 0) {
+    const double mean = B->nrows > 0 ? (double)B->nnz / (double)B->nrows : 0.0;
+    int gl = 4;
+    while (gl < 64 && gl < mean) gl <<= 1;
+    r.group_lanes = gl;
+  }
+  if (r.light_max_flops <= 0) r.light_max_flops = 2048;
+  if (r.wave_max_flops <= 0) r.wave_max_flops = 65536;
+  if (r.split_flops <= 0) r.split_flops = 262144;
+  if (r.wave_max_flops < r.light_max_flops) r.wave_max_flops = r.light_max_flops;
+  if (r.split_flops < r.wave_max_flops) r.split_flops = r.wave_max_flops;
+  if (r.sym_split_nnz <= 0) r.sym_split_nnz = 2048;
+  *out = r;
+}
+
+// Symbolic phase shared by tsspgemm_symbolic and tsspgemm_masked_bool.
+int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, const tsspgemm_mask* M,
+                 const tsspgemm_tuning* tune, int32_t* c_rowptr, int64_t* c_nnz, hipStream_t st) {
+  int rc;
+  if ((rc = check_csr(A, "A", false)) || (rc = check_csr(B, "B", false))) return rc;
+  if (A->nrows != A->ncols) {
+    set_error("A must be square (n x n)");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (B->nrows != A->ncols) {
+    set_error("B must have as many rows as A has columns");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (!c_rowptr || !c_nnz) {
+    set_error("c_rowptr and c_nnz must not be NULL");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (sr < 0 || sr > 2) {
+    set_error("unknown semiring");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (M && M->kind != TSSPGEMM_MASK_NONE) {
+    if (M->kind == TSSPGEMM_MASK_COMPLEMENT_CSR) {
+      if ((rc = check_csr(M->csr, "mask", false))) return rc;
+      if (M->csr->nrows != A->nrows || M->csr->ncols != B->ncols) {
+        set_error("mask must be n x d");
+        return TSSPGEMM_ERR_INVALID_ARG;
+      }
+    } else if (M->kind == TSSPGEMM_MASK_COMPLEMENT_BITMAP) {
+      if (!M->bits && A->nrows > 0) {
+        set_error("bitmap mask without bits");
+        return TSSPGEMM_ERR_INVALID_ARG;
+      }
+    } else {
+      set_error("unknown mask kind");
+      return TSSPGEMM_ERR_INVALID_ARG;
+    }
+  }
+  tsspgemm_tuning tn;
+  resolve_tuning(tune, B, &tn);
+  if (B->ncols > kMaxDenseD) {
+    set_error("d > 1024 needs the hash accumulator, which this build does not provide");
+    return TSSPGEMM_ERR_UNSUPPORTED;
+  }
+  const int64_t n = A->nrows, d = B->ncols;
+  const int wp = bitmap_words(d);
+  p->n = n;
+  p->d = d;
+  p->wp = wp;
+  p->sr = sr;
+  p->tune = tn;
+  p->crp = c_rowptr;
+  p->a_nnz = A->nnz;
+  p->b_nnz = B->nnz;
+  if ((rc = plan_alloc_host(p))) return rc;
+  const int64_t sym_cap = n + A->nnz / tn.sym_split_nnz + 2;
+  const int64_t num_cap = 2 * n + A->nnz / 64 + 2;
+  if ((rc = p->ctr.ensure(sizeof(Counters))) || (rc = p->bbits.ensure((size_t)n * wp * 4)) ||
+      (rc = p->cbits.ensure((size_t)n * wp * 4)) || (rc = p->flops.ensure((size_t)n * 8)) ||
+      (rc = p->cnt.ensure((size_t)n * 4)) || (rc = p->scan.ensure((size_t)scan_block_sums_capacity(n) * 8)) ||
+      (rc = p->sym_items.ensure((size_t)sym_cap * sizeof(Item))) ||
+      (rc = p->num_items.ensure((size_t)num_cap * sizeof(Item))) ||
+      (rc = p->split_rows.ensure((size_t)(n + 1) * sizeof(SplitRow))))
+    return rc;
+  Counters* ctr = (Counters*)p->ctr.p;
+
+  if (validate_enabled()) {
+    if ((rc = validate_on_device(A, "A", ctr, p->host_ctr, st)) || (rc = validate_on_device(B, "B", ctr, p->host_ctr, st)))
+      return rc;
+    if (M && M->kind == TSSPGEMM_MASK_COMPLEMENT_CSR && (rc = validate_on_device(M->csr, "mask", ctr, p->host_ctr, st)))
+      return rc;
+  }
+
+  Problem pr{};
+  pr.n = (int32_t)n;
+  pr.d = (int32_t)d;
+  pr.wp = wp;
+  pr.arp = A->rowptr;
+  pr.aci = A->colidx;
+  pr.aval = A->vals;
+  pr.brp = B->rowptr;
+  pr.bci = B->colidx;
+  pr.bval = B->vals;
+  pr.bbits = (const uint32_t*)p->bbits.p;
+  pr.cbits = (uint32_t*)p->cbits.p;
+  pr.flops = (int64_t*)p->flops.p;
+  pr.crp = c_rowptr;
+
+  if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
+  if ((rc = launch_csr_to_bitmap(n, B->rowptr, B->colidx, wp, (uint32_t*)p->bbits.p, st))) return rc;
+  const uint32_t* mask = nullptr;
+  if (M && M->kind == TSSPGEMM_MASK_COMPLEMENT_CSR) {
+    if ((rc = p->maskbits.ensure((size_t)n * wp * 4))) return rc;
+    if ((rc = launch_csr_to_bitmap(n, M->csr->rowptr, M->csr->colidx, wp, (uint32_t*)p->maskbits.p, st))) return rc;
+    mask = (const uint32_t*)p->maskbits.p;
+  } else if (M && M->kind == TSSPGEMM_MASK_COMPLEMENT_BITMAP) {
+    mask = M->bits;
+  }
+  if ((rc = launch_sym_bin(pr, tn.sym_split_nnz, (Item*)p->sym_items.p, ctr, st))) return rc;
+  SymParams sp{};
+  sp.pr = pr;
+  sp.items = (const Item*)p->sym_items.p;
+  sp.ctr = ctr;
+  sp.mask = mask;
+  if ((rc = launch_symbolic(sp, sym_cap, st))) return rc;
+  if ((rc = launch_sym_split_mask(pr, (const Item*)p->sym_items.p, mask, ctr, sym_cap, st))) return rc;
+  if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
+  if (sr != TSSPGEMM_OR_AND) {
+    const NumThresholds th{tn.light_max_flops, tn.wave_max_flops, tn.split_flops};
+    if ((rc = launch_num_bin(pr, th, (Item*)p->num_items.p, (SplitRow*)p->split_rows.p, ctr, st)))
+      return rc;
+  }
+  TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  TSS_HIP(hipStreamSynchronize(st));
+  const Counters& h = *p->host_ctr;
+  p->nnz = h.nnz_total;
+  p->flops_total = h.flops_total;
+  p->n_split_items = h.num_split_items;
+  p->n_block_items = h.num_block_items;
+  p->n_wave_rows = h.num_wave_rows;
+  p->n_light_rows = h.num_light_rows;
+  p->n_split_rows = h.num_split_rows;
+  *c_nnz = h.nnz_total;
+  if (h.nnz_total > INT32_MAX) {
+    set_error("nnz(C) = " + std::to_string(h.nnz_total) + " exceeds INT32_MAX");
+    return TSSPGEMM_ERR_OVERFLOW;
+  }
+  if (sr != TSSPGEMM_OR_AND && p->n_split_items > 0) {
+    const size_t esz = sr == TSSPGEMM_PLUS_TIMES_F32 ? 8 : 4;
+    if ((rc = p->partial.ensure((size_t)p->n_split_items * d * esz))) return rc;
+  }
+  p->ready = true;
+  return TSSPGEMM_OK;
+}
+
+int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* c_colidx, void* c_vals,
+                hipStream_t st) {
+  int rc;
+  if (!p || !p->ready) {
+    set_error("numeric: plan is NULL or its symbolic phase did not succeed");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  const bool vals = p->sr != TSSPGEMM_OR_AND;
+  if ((rc = check_csr(A, "A", vals)) || (rc = check_csr(B, "B", vals))) return rc;
+  if (A->nrows != p->n || B->ncols != p->d || A->nnz != p->a_nnz || B->nnz != p->b_nnz) {
+    set_error("numeric: A or B differs in shape or nnz from the plan's symbolic call");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (p->nnz > 0 && (!c_colidx || (vals && !c_vals))) {
+    set_error("numeric: NULL output array");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  Problem pr{};
+  pr.n = (int32_t)p->n;
+  pr.d = (int32_t)p->d;
+  pr.wp = p->wp;
+  pr.arp = A->rowptr;
+  pr.aci = A->colidx;
+  pr.aval = A->vals;
+  pr.brp = B->rowptr;
+  pr.bci = B->colidx;
+  pr.bval = B->vals;
+  pr.bbits = (const uint32_t*)p->bbits.p;
+  pr.cbits = (uint32_t*)p->cbits.p;
+  pr.flops = (int64_t*)p->flops.p;
+  pr.crp = p->crp;
+  pr.cci = c_colidx;
+  pr.cval = c_vals;
+  if (p->nnz == 0) return TSSPGEMM_OK;
+  if (!vals) return launch_emit_pattern(pr, st);
+  NumParams np{};
+  np.pr = pr;
+  np.items = (const Item*)p->num_items.p;
+  np.n_wg_items = (int32_t)(p->n_split_items + p->n_block_items);
+  np.n_heavy_records = (int32_t)(p->n_split_items + p->n_block_items + p->n_wave_rows);
+  np.n_light = (int32_t)p->n_light_rows;
+  np.partial = (double*)p->partial.p;
+  np.ipartial = (int32_t*)p->partial.p;
+  const int64_t grid = np.n_wg_items + (p->n_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
+  if ((rc = launch_numeric(p->sr, p->tune.group_lanes, np, grid, st))) return rc;
+  return launch_split_finalize(p->sr, pr, (const SplitRow*)p->split_rows.p, (int32_t)p->n_split_rows,
+                               (const double*)p->partial.p, (const int32_t*)p->partial.p, st);
+}
+
+// Plans reused by the one-shot entry points (masked_bool), one per device.
+static std::mutex g_cache_mu;
+static Plan* g_cache[64];
+
+Plan* cached_plan(int dev) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  if (dev < 0 || dev >= 64) return nullptr;
+  if (!g_cache[dev]) g_cache[dev] = new (std::nothrow) Plan();
+  return g_cache[dev];
+}
+
+}  // namespace tss
+
+using namespace tss;
+
+extern "C" {
+
+int32_t tsspgemm_bitmap_words(int32_t d) { return d < 0 ? 0 : bitmap_words(d); }
+
+int tsspgemm_symbolic(const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t sr, const tsspgemm_mask* M,
+                      const tsspgemm_tuning* tune, int32_t* c_rowptr, int64_t* c_nnz, tsspgemm_plan* plan,
+                      void* stream) {
+  try {
+    if (!plan) {
+      set_error("plan must not be NULL");
+      return TSSPGEMM_ERR_INVALID_ARG;
+    }
+    Plan* p = (Plan*)*plan;
+    bool fresh = false;
+    if (!p) {
+      p = new (std::nothrow) Plan();
+      if (!p) {
+        set_error("out of host memory");
+        return TSSPGEMM_ERR_NOMEM;
+      }
+      fresh = true;
+    }
+    (void)hipGetDevice(&p->dev);
+    p->ready = false;
+    int rc = run_symbolic(p, A, B, sr, M, tune, c_rowptr, c_nnz, (hipStream_t)stream);
+    if (rc != TSSPGEMM_OK && fresh && rc != TSSPGEMM_ERR_OVERFLOW) {
+      plan_free(p);
+      delete p;
+      return rc;
+    }
+    *plan = (tsspgemm_plan)p;
+    return rc;
+  } catch (...) {
+    set_error("unexpected C++ exception");
+    return TSSPGEMM_ERR_HIP;
+  }
+}
+
+int tsspgemm_numeric(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* c_colidx,
+                     void* c_vals, void* stream) {
+  try {
+    return run_numeric((Plan*)plan, A, B, c_colidx, c_vals, (hipStream_t)stream);
+  } catch (...) {
+    set_error("unexpected C++ exception");
+    return TSSPGEMM_ERR_HIP;
+  }
+}
+
+int tsspgemm_plan_stats(tsspgemm_plan plan, int64_t* flops, int64_t* c_nnz, int64_t* light_rows, int64_t* wave_rows,
+                        int64_t* block_rows, int64_t* split_rows) {
+  Plan* p = (Plan*)plan;
+  if (!p) {
+    set_error("plan is NULL");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (flops) *flops = p->flops_total;
+  if (c_nnz) *c_nnz = p->nnz;
+  if (light_rows) *light_rows = p->n_light_rows;
+  if (wave_rows) *wave_rows = p->n_wave_rows;
+  if (block_rows) *block_rows = p->n_block_items;
+  if (split_rows) *split_rows = p->n_split_rows;
+  return TSSPGEMM_OK;
+}
+
+void tsspgemm_plan_destroy(tsspgemm_plan plan) {
+  Plan* p = (Plan*)plan;
+  if (!p) return;
+  plan_free(p);
+  delete p;
+}
+
+int tsspgemm_masked_bool(const tsspgemm_csr* A, const tsspgemm_csr* F, const tsspgemm_mask* visited,
+                         int32_t* c_rowptr, int32_t* c_colidx, int64_t c_capacity, int64_t* c_nnz, void* stream) {
+  try {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    Plan* p = cached_plan(dev);
+    if (!p) {
+      set_error("no plan cache for this device");
+      return TSSPGEMM_ERR_NOMEM;
+    }
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->ready = false;
+    int rc = run_symbolic(p, A, F, TSSPGEMM_OR_AND, visited, nullptr, c_rowptr, c_nnz, (hipStream_t)stream);
+    if (rc) return rc;
+    if (*c_nnz > c_capacity) {
+      set_error("output capacity " + std::to_string(c_capacity) + " < nnz(C) = " + std::to_string(*c_nnz));
+      return TSSPGEMM_ERR_CAPACITY;
+    }
+    return run_numeric(p, A, F, c_colidx, nullptr, (hipStream_t)stream);
+  } catch (...) {
+    set_error("unexpected C++ exception");
+    return TSSPGEMM_ERR_HIP;
+  }
+}
+
+const char* tsspgemm_last_error(void) { return get_error().c_str(); }
+
+const char* tsspgemm_version(void) { return "tsspgemm-gfx950 0.1"; }
+
+}  // extern "C"

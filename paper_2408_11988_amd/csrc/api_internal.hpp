@@ -1,0 +1,47 @@
+// Host-side state shared by the C-ABI translation units.
+#pragma once
+
+#include <mutex>
+
+#include "core.hpp"
+
+namespace tss {
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int ensure(size_t bytes);
+  void release();
+};
+
+struct Plan {
+  int dev = 0;
+  int sr = 0;
+  int64_t n = 0, d = 0;
+  int wp = 1;
+  int64_t a_nnz = 0, b_nnz = 0;
+  tsspgemm_tuning tune{};
+  bool ready = false;
+  int32_t* crp = nullptr;  // caller's C row pointers (from the symbolic call)
+  // device workspace
+  DevBuf bbits, cbits, flops, cnt, scan, sym_items, num_items, split_rows, partial, ctr, maskbits;
+  Counters* host_ctr = nullptr;  // pinned
+  // results of the last symbolic call
+  int64_t nnz = 0, flops_total = 0, n_split_items = 0, n_block_items = 0, n_wave_rows = 0, n_light_rows = 0;
+  int64_t n_split_rows = 0;
+  std::mutex mu;
+};
+
+int check_csr(const tsspgemm_csr* m, const char* name, bool need_vals);
+bool validate_enabled();
+int validate_on_device(const tsspgemm_csr* m, const char* name, Counters* dctr, Counters* hctr, hipStream_t st);
+void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tuning* out);
+int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, const tsspgemm_mask* M,
+                 const tsspgemm_tuning* tune, int32_t* c_rowptr, int64_t* c_nnz, hipStream_t st);
+int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* c_colidx, void* c_vals,
+                hipStream_t st);
+void plan_free(Plan* p);
+Plan* cached_plan(int dev);
+
+}  // namespace tss

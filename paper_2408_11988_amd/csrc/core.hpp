@@ -1,0 +1,113 @@
+// Internal interfaces between the C-ABI layer and the kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace tss {
+
+// A unit of row work: entries [p0, p1) of A's row `row`.
+// aux: for symbolic items, kSplitFlag marks a chunk of a split row; for
+// numeric split chunks, the index of the chunk's partial-sum slot.
+struct Item {
+  int32_t row, p0, p1, aux;
+};
+constexpr int32_t kSplitFlag = 1 << 30;
+constexpr int32_t kNoSlot = 0x7fffffff;  // numeric workgroup item that is a whole row
+
+constexpr int kBins = 32;  // work classes by floor(log2(work)); heavier first
+constexpr int kNumClasses = 4;  // numeric: 0 split chunks, 1 workgroup rows, 2 wavefront rows, 3 light rows
+
+// Product-count thresholds of the numeric work classes.
+struct NumThresholds {
+  int64_t light_max, wave_max, split;
+};
+
+// Device-side counters of one plan (zeroed by a kernel before each use).
+struct Counters {
+  int32_t sym_count[kBins];
+  int32_t sym_cursor[kBins];
+  int32_t num_count[kNumClasses][kBins];
+  int32_t num_cursor[kNumClasses][kBins];
+  int32_t sym_total;
+  int32_t sym_split_rows;
+  int32_t num_split_items;
+  int32_t num_block_items;
+  int32_t num_wave_rows;
+  int32_t num_light_rows;
+  int32_t num_split_rows;
+  int32_t malformed;
+  int64_t flops_total;
+  int64_t nnz_total;
+};
+
+struct SplitRow {
+  int32_t row, first, count, pad;
+};
+
+// Everything a row kernel needs about one TS-SpGEMM instance.
+struct Problem {
+  int32_t n;   // rows of A and B (A is n x n)
+  int32_t d;   // columns of B and C
+  int32_t wp;  // bitmap words per row
+  const int32_t* arp;
+  const int32_t* aci;
+  const void* aval;
+  const int32_t* brp;
+  const int32_t* bci;
+  const void* bval;
+  const uint32_t* bbits;  // B pattern, n x wp
+  uint32_t* cbits;        // C pattern, n x wp
+  int64_t* flops;         // per row
+  const int32_t* crp;     // C row pointers
+  int32_t* cci;
+  void* cval;
+};
+
+struct SymParams {
+  Problem pr;
+  const Item* items;
+  Counters* ctr;
+  const uint32_t* mask;    // complement mask bitmap (n x wp) or null
+  const uint32_t* active;  // wp words: columns that can still change, or null (all)
+  const uint32_t* fnz;     // 1 bit per B row: row non-empty; null = no filter
+};
+
+// Item list layout: [split chunks][workgroup rows][wavefront rows][light rows].
+struct NumParams {
+  Problem pr;
+  const Item* items;
+  int32_t n_wg_items;       // split chunks + workgroup rows (one record per workgroup)
+  int32_t n_heavy_records;  // + wavefront rows (one record per wavefront)
+  int32_t n_light;          // light rows (one record per lane group)
+  double* partial;          // split-chunk partial sums (slots x d), FP64
+  int32_t* ipartial;        // same for the integer semiring
+};
+
+// ---------------------------------------------------------------- launchers
+// All return TSSPGEMM_OK or an error code; all are asynchronous on `st`.
+int launch_zero_bytes(void* p, size_t bytes, hipStream_t st);
+int launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+int launch_csr_to_bitmap(int64_t n, const int32_t* rp, const int32_t* ci, int wp, uint32_t* bits, hipStream_t st);
+int launch_nonempty_bits(int64_t n, const int32_t* rp, uint32_t* bits, hipStream_t st);
+int launch_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                        Counters* ctr, hipStream_t st);
+
+int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st);
+int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st);
+int launch_sym_split_mask(const Problem& pr, const Item* items, const uint32_t* mask, Counters* ctr,
+                          int64_t max_items, hipStream_t st);
+
+// popcount of each C bitmap row, exclusive scan -> c_rowptr, nnz(C) -> ctr
+int launch_count_scan(const Problem& pr, int32_t* cnt, int64_t* block_sums, int32_t* c_rowptr, Counters* ctr,
+                      hipStream_t st);
+int64_t scan_block_sums_capacity(int64_t n);
+
+int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
+                   hipStream_t st);
+
+int launch_numeric(int sr, int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st);
+int launch_split_finalize(int sr, const Problem& pr, const SplitRow* rows, int32_t nrows, const double* partial,
+                          const int32_t* ipartial, hipStream_t st);
+int launch_emit_pattern(const Problem& pr, hipStream_t st);
+
+}  // namespace tss

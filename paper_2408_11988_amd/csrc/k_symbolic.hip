@@ -1,0 +1,539 @@
+// Symbolic phase of row-wise Gustavson TS-SpGEMM (Sec. III-A, Eq. 1): for
+// every row i, flops_i = number of products A(i,k) B(k,j) (Sec. II-A) and the
+// output pattern pat(C_i) = union of pat(B_k) over k in pat(A_i), minus an
+// optional complement mask (Algorithm 3's N \ S). The union is formed in a
+// d-bit bitmap per row -- the dense (SPA-like) accumulator of Sec. III-C,
+// here held in registers: a slot of `wp` lanes owns one B row's bitmap words,
+// a wavefront ORs 64/wp B rows per step and reduces across slots at the end.
+//
+// Also here: the B-pattern bitmap build, the work binning of rows by A-row
+// length, and the popcount + exclusive scan that turns C's bitmaps into
+// C's row pointers.
+#include "core.hpp"
+
+namespace tss {
+
+// ================================================================ utilities
+
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+int launch_zero_bytes(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return TSSPGEMM_OK;
+  // byte counts used in this library are multiples of 4
+  int64_t n = (int64_t)(bytes / 4);
+  unsigned g = grid_for(n, 256 * 8);
+  if (g > 4096) g = 4096;
+  k_zero_u32<<<g, 256, 0, st>>>((uint32_t*)p, n);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+int launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
+  if (n == 0) return TSSPGEMM_OK;
+  unsigned g = grid_for(n, 256 * 8);
+  if (g > 8192) g = 8192;
+  k_fill_i32<<<g, 256, 0, st>>>(p, n, v);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+// CSR pattern -> bitmap rows. A workgroup owns kBmRows consecutive rows: it
+// stages their row pointers and an all-zero bitmap in LDS, streams the rows'
+// entries with consecutive threads on consecutive entries (coalesced), finds
+// each entry's row by binary search over the staged pointers, sets the bit
+// with an LDS atomicOr, and writes the finished bitmap rows out contiguously.
+constexpr int kBmRows = 256;
+
+__global__ __launch_bounds__(256) void k_csr_to_bitmap(int64_t n, const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, int wp,
+                                                       uint32_t* __restrict__ bits) {
+  extern __shared__ __align__(16) uint32_t sm[];
+  int32_t* srp = (int32_t*)sm;
+  uint32_t* sb = sm + kBmRows + 1;
+  const int64_t r0 = (int64_t)blockIdx.x * kBmRows;
+  const int nr = (int)min((int64_t)kBmRows, n - r0);
+  for (int t = threadIdx.x; t <= nr; t += blockDim.x) srp[t] = rp[r0 + t];
+  for (int t = threadIdx.x; t < nr * wp; t += blockDim.x) sb[t] = 0u;
+  __syncthreads();
+  const int q0 = srp[0], q1 = srp[nr];
+  for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    const int j = ci[q];
+    int lo = 0, hi = nr;  // srp[lo] <= q < srp[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (srp[mid] <= q)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    atomicOr(&sb[lo * wp + (j >> 5)], 1u << (j & 31));
+  }
+  __syncthreads();
+  uint32_t* out = bits + r0 * wp;
+  for (int t = threadIdx.x; t < nr * wp; t += blockDim.x) out[t] = sb[t];
+}
+
+int launch_csr_to_bitmap(int64_t n, const int32_t* rp, const int32_t* ci, int wp, uint32_t* bits, hipStream_t st) {
+  if (n == 0) return TSSPGEMM_OK;
+  const size_t lds = (size_t)(kBmRows + 1 + kBmRows * wp) * 4;
+  k_csr_to_bitmap<<<grid_for(n, kBmRows), 256, lds, st>>>(n, rp, ci, wp, bits);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+// bit r of `bits` = row r of the CSR is non-empty
+__global__ void k_nonempty_bits(int64_t n, const int32_t* __restrict__ rp, uint32_t* __restrict__ bits) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  bool ne = r < n && rp[r + 1] > rp[r];
+  uint64_t b = __ballot(ne);
+  if ((threadIdx.x & 63) == 0 && r < n) {
+    int64_t w = r >> 5;  // r is a multiple of 64 here
+    bits[w] = (uint32_t)b;
+    if (r + 32 < n) bits[w + 1] = (uint32_t)(b >> 32);
+  }
+}
+
+int launch_nonempty_bits(int64_t n, const int32_t* rp, uint32_t* bits, hipStream_t st) {
+  if (n == 0) return TSSPGEMM_OK;
+  k_nonempty_bits<<<grid_for(n, 256), 256, 0, st>>>(n, rp, bits);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+// CSR invariants: rp[0] = 0, rp non-decreasing, rp[n] = nnz, columns strictly
+// increasing within a row and inside [0, ncols).
+__global__ void k_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t* __restrict__ rp,
+                               const int32_t* __restrict__ ci, Counters* ctr) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int a = rp[r], b = rp[r + 1];
+  bool bad = (r == 0 && a != 0) || (r == nrows - 1 && b != nnz) || b < a || a < 0 || b > nnz;
+  if (!bad) {
+    int prev = -1;
+    for (int q = a; q < b; ++q) {
+      const int j = ci[q];
+      if (j <= prev || j >= ncols) {
+        bad = true;
+        break;
+      }
+      prev = j;
+    }
+  }
+  if (bad) atomicOr(&ctr->malformed, 1);
+}
+
+int launch_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                        Counters* ctr, hipStream_t st) {
+  if (nrows == 0) return TSSPGEMM_OK;
+  k_validate_csr<<<grid_for(nrows, 256), 256, 0, st>>>(nrows, ncols, nnz, rp, ci, ctr);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+// ================================================================ binning (symbolic)
+
+// Rows with at most kSlotRowMax A entries ("light" rows, the bulk of a
+// power-law graph) are processed straight from the row index, one row per
+// slot of wp lanes. Heavier rows are binned into an item list (heaviest
+// first) and take a whole wavefront, or several when split.
+constexpr int kSlotRowMax = 32;
+
+// Work class of a row with m > 0 entries: floor(log2 m) mapped so that heavier
+// rows get smaller bin numbers; bin 0 holds the chunks of split rows.
+__device__ __forceinline__ int bin_of(int64_t work) {
+  const int e = 63 - __clzll((unsigned long long)work);
+  const int b = kBins - 1 - e;
+  return b < 1 ? 1 : b;
+}
+
+// bin and item count of row i in the heavy-row list (count 0: not listed)
+__device__ __forceinline__ void sym_bin(int m, int32_t split_nnz, int& bin, int& count) {
+  if (m <= kSlotRowMax) {
+    bin = 0;
+    count = 0;
+  } else if (m <= split_nnz) {
+    bin = bin_of(m);
+    count = 1;
+  } else {
+    bin = 0;
+    count = (m + split_nnz - 1) / split_nnz;
+  }
+}
+
+__global__ void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
+  __shared__ int32_t hist[kBins];
+  if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < pr.n) {
+    const int m = pr.arp[i + 1] - pr.arp[i];
+    int bin, count;
+    sym_bin(m, split_nnz, bin, count);
+    if (count) atomicAdd(&hist[bin], count);
+    if (m > split_nnz) {
+      // split row: its chunks OR into a zeroed bitmap and add into a zeroed count
+      for (int w = 0; w < pr.wp; ++w) pr.cbits[i * pr.wp + w] = 0u;
+      pr.flops[i] = 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kBins && hist[threadIdx.x]) atomicAdd(&ctr->sym_count[threadIdx.x], hist[threadIdx.x]);
+}
+
+// single thread: bin offsets (stored in the cursors) and the item total
+__global__ void k_sym_bin_scan(Counters* ctr) {
+  int32_t off = 0;
+  for (int b = 0; b < kBins; ++b) {
+    ctr->sym_cursor[b] = off;
+    off += ctr->sym_count[b];
+  }
+  ctr->sym_total = off;
+}
+
+// Items are placed with one global reservation per bin per workgroup; the
+// slot inside the workgroup's range comes from an LDS counter.
+__global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Counters* ctr) {
+  __shared__ int32_t cnt[kBins], base[kBins];
+  if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int a = 0, m = 0, bin = 0, count = 0, local = 0;
+  if (i < pr.n) {
+    a = pr.arp[i];
+    m = pr.arp[i + 1] - a;
+    sym_bin(m, split_nnz, bin, count);
+    if (count) local = atomicAdd(&cnt[bin], count);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBins && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&ctr->sym_cursor[threadIdx.x], cnt[threadIdx.x]);
+  __syncthreads();
+  if (!count) return;
+  const int pos = base[bin] + local;
+  if (m <= split_nnz) {
+    items[pos] = Item{(int32_t)i, a, a + m, 0};
+  } else {
+    for (int c = 0; c < count; ++c) {
+      const int p0 = a + c * split_nnz;
+      items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + split_nnz), kSplitFlag | c};
+    }
+  }
+}
+
+int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st) {
+  if (pr.n == 0) {
+    k_sym_bin_scan<<<1, 1, 0, st>>>(ctr);
+    TSS_CHECK_LAUNCH();
+    return TSSPGEMM_OK;
+  }
+  const unsigned g = grid_for(pr.n, 256);
+  k_sym_bin_count<<<g, 256, 0, st>>>(pr, split_nnz, ctr);
+  k_sym_bin_scan<<<1, 1, 0, st>>>(ctr);
+  k_sym_bin_fill<<<g, 256, 0, st>>>(pr, split_nnz, items, ctr);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+// ================================================================ symbolic
+
+// Light rows. WP = bitmap words per row (power of two, 1..32); a slot of WP
+// lanes owns one row (lane = slot * WP + word) and walks its A entries,
+// OR-ing the B rows' bitmap words; 64/WP rows per wavefront are in flight.
+template <int WP>
+__global__ __launch_bounds__(kBlock) void k_symbolic_light(SymParams sp) {
+  constexpr int NS = kWave / WP;
+  const Problem& pr = sp.pr;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = lane / WP, w = lane % WP;
+  const int64_t row = ((int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * NS + slot;
+  const uint32_t* __restrict__ bb = pr.bbits;
+  const int32_t* __restrict__ aci = pr.aci;
+  if (row >= pr.n) return;
+  const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
+  if (p1 - p0 > kSlotRowMax) return;  // a heavy row: done from the item list
+  uint32_t mword = 0u;
+  bool work = p1 > p0;
+  if (sp.mask) {
+    mword = sp.mask[row * WP + w];
+    uint32_t need = ~mword & (sp.active ? sp.active[w] : 0xffffffffu);
+#pragma unroll
+    for (int o = 1; o < WP; o <<= 1) need |= shfl_xor_u32(need, o);
+    work = work && need != 0u;
+  }
+  uint32_t acc = 0u;
+  int fl = 0;
+  if (work) {
+    const uint32_t* __restrict__ fnz = sp.fnz;
+    int p = p0;
+    if (fnz == nullptr) {
+      for (; p + 3 < p1; p += 4) {
+        const int k0 = aci[p], k1 = aci[p + 1], k2 = aci[p + 2], k3 = aci[p + 3];
+        const uint32_t x0 = bb[(int64_t)k0 * WP + w], x1 = bb[(int64_t)k1 * WP + w];
+        const uint32_t x2 = bb[(int64_t)k2 * WP + w], x3 = bb[(int64_t)k3 * WP + w];
+        acc |= (x0 | x1) | (x2 | x3);
+        fl += __popc(x0) + __popc(x1) + __popc(x2) + __popc(x3);
+      }
+    }
+    for (; p < p1; ++p) {
+      const int k = aci[p];
+      if (fnz == nullptr || ((fnz[k >> 5] >> (k & 31)) & 1u)) {
+        const uint32_t x = bb[(int64_t)k * WP + w];
+        acc |= x;
+        fl += __popc(x);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < WP; o <<= 1) fl += __shfl_xor(fl, o, kWave);
+  pr.cbits[row * WP + w] = acc & ~mword;
+  if (w == 0) pr.flops[row] = fl;
+}
+
+// Heavy rows and chunks of split rows, from the item list. A wavefront per
+// item: lane = slot * WP + word, 64/WP B rows in flight, OR-reduced across
+// slots at the end. Wavefronts walk the list with a grid stride; items are
+// ordered heaviest first, so every wavefront gets a similar mix.
+template <int WP>
+__global__ __launch_bounds__(kBlock) void k_symbolic(SymParams sp) {
+  constexpr int NS = kWave / WP;  // slots (B rows in flight) per wavefront
+  const Problem& pr = sp.pr;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = lane / WP, w = lane % WP;
+  const int total = sp.ctr->sym_total;
+  const int wave_global = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int wave_stride = gridDim.x * kWavesPerBlock;
+  const uint32_t* __restrict__ bb = sp.pr.bbits;
+  const int32_t* __restrict__ aci = pr.aci;
+  const uint32_t* __restrict__ fnz = sp.fnz;
+
+  for (int t = wave_global; t < total; t += wave_stride) {
+    const Item it = sp.items[t];
+    const bool split = (it.aux & kSplitFlag) != 0;
+    const int64_t row = it.row;
+    uint32_t mword = 0;
+    bool skip = false;
+    if (sp.mask) {
+      mword = sp.mask[row * WP + w];
+      if (!split) {
+        const uint32_t act = sp.active ? sp.active[w] : 0xffffffffu;
+        // every column that could be produced is masked out: nothing to do
+        skip = __ballot((~mword & act) != 0u) == 0ull;
+      }
+    }
+    uint32_t acc = 0u;
+    int fl = 0;
+    if (!skip) {
+      int p = it.p0 + slot;
+      if (fnz == nullptr) {
+        for (; p + 3 * NS < it.p1; p += 4 * NS) {
+          const int k0 = aci[p], k1 = aci[p + NS], k2 = aci[p + 2 * NS], k3 = aci[p + 3 * NS];
+          const uint32_t x0 = bb[(int64_t)k0 * WP + w], x1 = bb[(int64_t)k1 * WP + w];
+          const uint32_t x2 = bb[(int64_t)k2 * WP + w], x3 = bb[(int64_t)k3 * WP + w];
+          acc |= (x0 | x1) | (x2 | x3);
+          fl += __popc(x0) + __popc(x1) + __popc(x2) + __popc(x3);
+        }
+        for (; p < it.p1; p += NS) {
+          const uint32_t x = bb[(int64_t)aci[p] * WP + w];
+          acc |= x;
+          fl += __popc(x);
+        }
+      } else {
+        for (; p < it.p1; p += NS) {
+          const int k = aci[p];
+          if ((fnz[k >> 5] >> (k & 31)) & 1u) {
+            const uint32_t x = bb[(int64_t)k * WP + w];
+            acc |= x;
+            fl += __popc(x);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int o = WP; o < kWave; o <<= 1) acc |= shfl_xor_u32(acc, o);
+    const long long fsum = wave_sum_i64((long long)fl);
+    if (slot == 0) {
+      if (split) {
+        if (acc) atomicOr(&pr.cbits[row * WP + w], acc);
+      } else {
+        pr.cbits[row * WP + w] = acc & ~mword;
+      }
+    }
+    if (lane == 0) {
+      if (split)
+        atomicAdd((unsigned long long*)&pr.flops[row], (unsigned long long)fsum);
+      else
+        pr.flops[row] = fsum;
+    }
+  }
+}
+
+int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st) {
+  const int64_t n = sp.pr.n;
+  if (n == 0) return TSSPGEMM_OK;
+  const int ns = kWave / sp.pr.wp;
+  const unsigned g_light = grid_for(n, ns * kWavesPerBlock);
+  // heavy items: enough wavefronts to fill the chip, never more than items
+  const int64_t waves = max_items < 256 * 32 ? max_items : 256 * 32;
+  const unsigned g_heavy = grid_for(waves, kWavesPerBlock);
+#define TSS_SYM_CASE(W)                                               \
+  case W:                                                             \
+    k_symbolic_light<W><<<g_light, kBlock, 0, st>>>(sp);              \
+    if (max_items > 0) k_symbolic<W><<<g_heavy, kBlock, 0, st>>>(sp); \
+    break;
+  switch (sp.pr.wp) {
+    TSS_SYM_CASE(1)
+    TSS_SYM_CASE(2)
+    TSS_SYM_CASE(4)
+    TSS_SYM_CASE(8)
+    TSS_SYM_CASE(16)
+    TSS_SYM_CASE(32)
+    default: set_error("symbolic: unsupported bitmap width"); return TSSPGEMM_ERR_UNSUPPORTED;
+  }
+#undef TSS_SYM_CASE
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+// Split rows were OR-ed chunk by chunk; apply the complement mask once all
+// chunks are in (one thread per split row, found from its chunk 0 item).
+__global__ void k_sym_split_mask(Problem pr, const Item* items, const uint32_t* mask, const Counters* ctr) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ctr->sym_total) return;
+  const Item it = items[t];
+  if ((it.aux & kSplitFlag) == 0 || (it.aux & ~kSplitFlag) != 0) return;
+  for (int w = 0; w < pr.wp; ++w) pr.cbits[(int64_t)it.row * pr.wp + w] &= ~mask[(int64_t)it.row * pr.wp + w];
+}
+
+int launch_sym_split_mask(const Problem& pr, const Item* items, const uint32_t* mask, Counters* ctr,
+                          int64_t max_items, hipStream_t st) {
+  if (max_items == 0 || mask == nullptr) return TSSPGEMM_OK;
+  k_sym_split_mask<<<grid_for(max_items, 256), 256, 0, st>>>(pr, items, mask, ctr);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+// ================================================================ count + scan
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanRows = kScanThreads * kScanPer;
+
+int64_t scan_block_sums_capacity(int64_t n) { return 2 * ((n + kScanRows - 1) / kScanRows + 1); }
+
+// exclusive scan of v over the 1024 threads of the block; returns the prefix,
+// total in *tot. Uses a 16-entry shared array.
+__device__ __forceinline__ long long block_exscan_1024(long long v, long long* sh, long long* tot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  long long x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    long long y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    long long s = lane < 16 ? sh[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      long long y = __shfl_up(s, o, kWave);
+      if (lane >= o) s += y;
+    }
+    if (lane < 16) sh[16 + lane] = s;  // inclusive prefix of wave totals
+  }
+  __syncthreads();
+  const long long before = wave ? sh[16 + wave - 1] : 0;
+  *tot = sh[16 + 15];
+  __syncthreads();
+  return before + x - v;
+}
+
+// Per block of rows: popcount of each C bitmap row (nnz of the row) and the
+// block totals of nnz and of products; block_sums holds nb nnz totals
+// followed by nb product totals.
+__global__ __launch_bounds__(kScanThreads) void k_count_rows(Problem pr, int32_t* cnt, int64_t* block_sums) {
+  __shared__ long long sh[32];
+  const int64_t base = (int64_t)blockIdx.x * kScanRows;
+  long long s = 0, f = 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    const int64_t i = base + u * kScanThreads + threadIdx.x;
+    if (i < pr.n) {
+      int c = 0;
+      const uint32_t* b = pr.cbits + i * pr.wp;
+      for (int w = 0; w < pr.wp; ++w) c += __popc(b[w]);
+      cnt[i] = c;
+      s += c;
+      f += pr.flops[i];
+    }
+  }
+  long long tot, ftot;
+  block_exscan_1024(s, sh, &tot);
+  block_exscan_1024(f, sh, &ftot);
+  if (threadIdx.x == 0) {
+    block_sums[blockIdx.x] = tot;
+    block_sums[gridDim.x + blockIdx.x] = ftot;
+  }
+}
+
+// one workgroup: exclusive scan of the block sums, nnz(C) into the counters
+__global__ __launch_bounds__(kScanThreads) void k_scan_block_sums(int64_t nblocks, int64_t* block_sums,
+                                                                   Counters* ctr) {
+  __shared__ long long sh[32];
+  long long carry = 0, fcarry = 0;
+  for (int64_t b0 = 0; b0 < nblocks; b0 += kScanThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const long long v = b < nblocks ? block_sums[b] : 0;
+    const long long f = b < nblocks ? block_sums[nblocks + b] : 0;
+    long long tot, ftot;
+    const long long ex = block_exscan_1024(v, sh, &tot);
+    block_exscan_1024(f, sh, &ftot);
+    if (b < nblocks) block_sums[b] = carry + ex;
+    carry += tot;
+    fcarry += ftot;
+  }
+  if (threadIdx.x == 0) {
+    ctr->nnz_total = carry;
+    ctr->flops_total = fcarry;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_write_rowptr(Problem pr, const int32_t* cnt,
+                                                               const int64_t* block_sums, int32_t* crp,
+                                                               const Counters* ctr) {
+  __shared__ long long sh[32];
+  const int64_t base = (int64_t)blockIdx.x * kScanRows;
+  long long carry = block_sums[blockIdx.x];
+  for (int u = 0; u < kScanPer; ++u) {
+    const int64_t i = base + u * kScanThreads + threadIdx.x;
+    const long long v = i < pr.n ? cnt[i] : 0;
+    long long tot;
+    const long long ex = block_exscan_1024(v, sh, &tot);
+    // int32 row pointers: the host rejects nnz(C) > INT32_MAX before use
+    if (i < pr.n) crp[i] = (int32_t)(carry + ex);
+    carry += tot;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) crp[pr.n] = (int32_t)ctr->nnz_total;
+}
+
+int launch_count_scan(const Problem& pr, int32_t* cnt, int64_t* block_sums, int32_t* c_rowptr, Counters* ctr,
+                      hipStream_t st) {
+  const int64_t nb = (pr.n + kScanRows - 1) / kScanRows;
+  if (nb > 0) k_count_rows<<<(unsigned)nb, kScanThreads, 0, st>>>(pr, cnt, block_sums);
+  k_scan_block_sums<<<1, kScanThreads, 0, st>>>(nb, block_sums, ctr);
+  if (nb > 0)
+    k_write_rowptr<<<(unsigned)nb, kScanThreads, 0, st>>>(pr, cnt, block_sums, c_rowptr, ctr);
+  else
+    k_fill_i32<<<1, 64, 0, st>>>(c_rowptr, 1, 0);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+}  // namespace tss

@@ -1,0 +1,280 @@
+"""GPU parity of the plain TS-SpGEMM (symbolic + numeric) against the oracle.
+
+Structure and integer / Boolean values are compared bit for bit; FP32
+plus-times values within relative 1e-5 of the FP64 oracle (tests/gpu_util.py).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests._util import random_csr
+from tests.gpu_util import compare_bool, compare_f32, compare_int, note, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+D_VALUES = [1, 5, 31, 32, 33, 64, 100, 128, 255, 256, 512, 1000, 1024]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+    import paper_2408_11988_amd as tss
+
+    note(f"library {tss.version()}")
+
+
+def _tss():
+    import paper_2408_11988_amd as tss
+
+    return tss
+
+
+@pytest.mark.parametrize("d", D_VALUES)
+def test_plus_times_random(d):
+    rng = np.random.default_rng(1000 + d)
+    n = 300
+    a = random_csr(rng, n, n, 0.03, empty_rows=0.2, dense_rows=2)
+    b = random_csr(rng, n, d, min(0.5, 6.0 / d + 0.02), empty_rows=0.1)
+    note(f"plus_times random n={n} d={d} nnzA={a.nnz} nnzB={b.nnz}")
+    C = _tss().spgemm(to_dev(a), to_dev(b))
+    torch.cuda.synchronize()
+    frac = compare_f32(a, b, C)
+    assert frac > 0.999
+
+
+@pytest.mark.parametrize("d", [7, 64, 300])
+def test_plus_times_signed(d):
+    rng = np.random.default_rng(2000 + d)
+    n = 257
+    a = random_csr(rng, n, n, 0.05, kind="normal", empty_rows=0.1, dense_rows=1)
+    b = random_csr(rng, n, d, 0.2, kind="normal")
+    note(f"plus_times signed n={n} d={d}")
+    C = _tss().spgemm(to_dev(a), to_dev(b))
+    torch.cuda.synchronize()
+    compare_f32(a, b, C, signed=True)
+
+
+@pytest.mark.parametrize("d", [3, 64, 129, 1024])
+def test_int32_exact(d):
+    rng = np.random.default_rng(3000 + d)
+    n = 200
+    a = random_csr(rng, n, n, 0.05, kind="int", dense_rows=1)
+    b = random_csr(rng, n, d, 0.1, kind="int")
+    note(f"int32 n={n} d={d}")
+    C = _tss().spgemm(to_dev(a, dtype=torch.int32), to_dev(b, dtype=torch.int32), semiring="plus_times_i32")
+    torch.cuda.synchronize()
+    compare_int(a, b, C)
+
+
+@pytest.mark.parametrize("d", [1, 40, 64, 512, 1024])
+def test_or_and_and_masks(d):
+    rng = np.random.default_rng(4000 + d)
+    n = 220
+    a = random_csr(rng, n, n, 0.04, dense_rows=1)
+    b = random_csr(rng, n, d, 0.05)
+    m = random_csr(rng, n, d, 0.3)
+    tss = _tss()
+    note(f"or_and n={n} d={d}")
+    A, B = to_dev(a, with_values=False), to_dev(b, with_values=False)
+    C = tss.spgemm(A, B, semiring="or_and")
+    torch.cuda.synchronize()
+    compare_bool(a, b, C)
+    note(f"or_and csr mask n={n} d={d}")
+    M = to_dev(m, with_values=False)
+    C = tss.spgemm(A, B, semiring="or_and", mask=M)
+    compare_bool(a, b, C, mask=m)
+    note(f"masked_bool csr mask n={n} d={d}")
+    C = tss.masked_bool(A, B, M)
+    compare_bool(a, b, C, mask=m)
+    # the same mask as a bitmap
+    wp = tss.bitmap_words(d)
+    bits = np.zeros((n, wp), dtype=np.uint32)
+    rows = np.repeat(np.arange(n), np.diff(m.rp))
+    np.bitwise_or.at(bits, (rows, m.ci // 32), (np.uint32(1) << (m.ci % 32).astype(np.uint32)))
+    note(f"masked_bool bitmap mask n={n} d={d}")
+    C = tss.masked_bool(A, B, torch.from_numpy(bits.view(np.int32)).cuda())
+    compare_bool(a, b, C, mask=m)
+    # plus-times with a complement mask drops the masked entries, values unchanged
+    note(f"plus_times csr mask n={n} d={d}")
+    a2 = synth.Csr(n, n, a.rp, a.ci, rng.random(a.nnz).astype(np.float32))
+    b2 = synth.Csr(n, d, b.rp, b.ci, rng.random(b.nnz).astype(np.float32))
+    C = tss.spgemm(to_dev(a2), to_dev(b2), mask=M)
+    g_rp, g_ci, g_val = C.to_host()
+    rp, ci = oracle.spgemm_bool(a.rp, a.ci, b.rp, b.ci, m.rp, m.ci)
+    assert np.array_equal(g_rp.astype(np.int64), rp) and np.array_equal(g_ci, ci)
+    frp, fci, fval = oracle.spgemm(a2.rp, a2.ci, a2.val, b2.rp, b2.ci, b2.val)
+    full = {(i, j): v for i in range(n) for j, v in zip(fci[frp[i]:frp[i + 1]], fval[frp[i]:frp[i + 1]])}
+    ref = np.array([full[(i, j)] for i in range(n) for j in g_ci[g_rp[i]:g_rp[i + 1]]])
+    assert np.all(np.abs(g_val - ref) <= 1e-5 * np.abs(ref))
+
+
+def test_modes_and_tuning_do_not_change_results():
+    """Wavefront, workgroup and split rows, and every group width, give the
+    same bits (fixed accumulation orders)."""
+    rng = np.random.default_rng(5)
+    n, d = 600, 128
+    a = random_csr(rng, n, n, 0.02, dense_rows=6)
+    b = random_csr(rng, n, d, 0.15)
+    tss = _tss()
+    A, B = to_dev(a), to_dev(b)
+    note("tuning reference run")
+    ref, plan = tss.spgemm(A, B, return_plan=True)
+    compare_f32(a, b, ref)
+    ref_h = ref.to_host()
+    configs = [dict(group_lanes=g) for g in (4, 8, 16, 32, 64)]
+    configs += [dict(light_max_flops=1, wave_max_flops=16, split_flops=64),
+                dict(light_max_flops=1, wave_max_flops=1, split_flops=1),
+                dict(light_max_flops=200, wave_max_flops=260, split_flops=1000),
+                dict(light_max_flops=1 << 30, wave_max_flops=1 << 30, split_flops=1 << 30),
+                dict(wave_max_flops=500, split_flops=100000, sym_split_nnz=3), dict(sym_split_nnz=1)]
+    for cfg in configs:
+        note(f"tuning {cfg}")
+        C, p = tss.spgemm(A, B, tuning=cfg, return_plan=True)
+        got = C.to_host()
+        for x, y in zip(ref_h, got):
+            assert np.array_equal(x, y), cfg
+        st = p.stats()
+        assert st["flops"] == plan.stats()["flops"]
+    # rows here have ~230 +- 70 products, the dense rows ~11500: all four classes occur
+    st = tss.spgemm(A, B, tuning=dict(light_max_flops=200, wave_max_flops=260, split_flops=1000),
+                    return_plan=True)[1].stats()
+    assert st["split_rows"] > 0 and st["block_rows"] > 0 and st["wave_rows"] > 0 and st["light_rows"] > 0
+
+
+def test_plan_reuse_and_determinism():
+    a, b = synth.workload_er_small()
+    tss = _tss()
+    A, B = to_dev(a), to_dev(b)
+    note("ER 4096 x 64 (config 1)")
+    C1, plan = tss.spgemm(A, B, return_plan=True)
+    torch.cuda.synchronize()
+    frac = compare_f32(a, b, C1)
+    assert frac > 0.999
+    assert plan.stats()["flops"] == int(oracle.row_flops(a.rp, a.ci, b.rp).sum())
+    note("plan reuse, new values")
+    b2 = b.with_values((b.val * 0.5 + 0.25).astype(np.float32))
+    B2 = to_dev(b2)
+    C2 = tss.spgemm(A, B2, plan=plan)
+    compare_f32(a, b2, C2)
+    c_ci = torch.empty_like(C2.colidx)
+    c_v = torch.empty_like(C2.vals)
+    tss.numeric(plan, A, B2, c_ci, c_v)
+    assert torch.equal(c_ci, C2.colidx) and torch.equal(c_v, C2.vals)
+
+
+def test_rmat_scale16_full():
+    a, b = synth.workload_rmat_plain(scale=16, d=128)
+    tss = _tss()
+    note(f"R-MAT 16 d=128 nnzA={a.nnz} nnzB={b.nnz}")
+    C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True)
+    torch.cuda.synchronize()
+    frac = compare_f32(a, b, C, threads=8)
+    assert frac > 0.999
+    st = plan.stats()
+    assert st["nnz"] == C.nnz
+
+
+def test_rmat_scale20_d128_sampled():
+    """Full-size plain workload (R-MAT scale 20, d = 128): every row checked for
+    the invariants, the heaviest and random rows against the oracle."""
+    a, b = synth.workload_rmat_plain(scale=20, d=128)
+    tss = _tss()
+    note(f"R-MAT 20 d=128 nnzA={a.nnz} nnzB={b.nnz}")
+    C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True)
+    torch.cuda.synchronize()
+    g_rp, g_ci, _ = C.to_host()
+    flops = oracle.row_flops(a.rp, a.ci, b.rp)
+    assert plan.stats()["flops"] == int(flops.sum())
+    cnt = np.diff(g_rp.astype(np.int64))
+    assert np.all(cnt <= np.minimum(128, flops)) and np.all((cnt == 0) == (flops == 0))
+    rows = np.repeat(np.arange(a.nrows), cnt)
+    key = rows * 128 + g_ci.astype(np.int64)
+    assert np.all(np.diff(key) > 0) and g_ci.min() >= 0 and g_ci.max() < 128
+    rng = np.random.default_rng(20)
+    heavy = np.argsort(flops)[-24:]
+    sample = np.unique(np.concatenate([heavy, rng.choice(a.nrows, 3000, replace=False), [0, a.nrows - 1]]))
+    note(f"oracle on {len(sample)} sampled rows")
+    frac = compare_f32(a, b, C, rows=sample.astype(np.int32), threads=16)
+    assert frac > 0.999
+
+
+def test_edge_cases():
+    tss = _tss()
+    rng = np.random.default_rng(9)
+    # no rows
+    z = synth.Csr(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    zb = synth.Csr(0, 8, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    note("n = 0")
+    C = tss.spgemm(to_dev(z), to_dev(zb))
+    assert C.nnz == 0 and C.rowptr.cpu().tolist() == [0]
+    # empty A, empty B
+    n, d = 100, 64
+    ea = synth.Csr(n, n, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    b = random_csr(rng, n, d, 0.1)
+    note("empty A")
+    C = tss.spgemm(to_dev(ea), to_dev(b))
+    assert C.nnz == 0 and int(C.rowptr.cpu()[-1]) == 0
+    eb = synth.Csr(n, d, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    a = random_csr(rng, n, n, 0.1)
+    note("empty B")
+    C = tss.spgemm(to_dev(a), to_dev(eb))
+    assert C.nnz == 0
+    # identity
+    eye = synth.Csr(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n, np.float32))
+    note("identity")
+    C = tss.spgemm(to_dev(eye), to_dev(b))
+    r, c, v = C.to_host()
+    assert np.array_equal(r, b.rp) and np.array_equal(c, b.ci) and np.array_equal(v, b.val)
+
+
+def test_error_paths_on_device():
+    tss = _tss()
+    from paper_2408_11988_amd import _lib
+
+    rng = np.random.default_rng(10)
+    n = 64
+    a = random_csr(rng, n, n, 0.1)
+    big = random_csr(rng, n, 2048, 0.01)
+    note("d = 2048 without a hash accumulator")
+    with pytest.raises(_lib.TSSpGEMMError) as e:
+        tss.spgemm(to_dev(a), to_dev(big))
+    assert e.value.code == _lib.ERR_UNSUPPORTED
+    b = random_csr(rng, n, 32, 0.3)
+    A, B = to_dev(a, with_values=False), to_dev(b, with_values=False)
+    full = tss.masked_bool(A, B)
+    note("masked_bool capacity too small")
+    import ctypes
+
+    rp = torch.empty(n + 1, dtype=torch.int32, device="cuda")
+    ci = torch.empty(4, dtype=torch.int32, device="cuda")
+    nnz = ctypes.c_int64(0)
+    da, db = A.desc(), B.desc()
+    rc = _lib.load().tsspgemm_masked_bool(ctypes.byref(da), ctypes.byref(db), None, ctypes.c_void_p(rp.data_ptr()),
+                                          ctypes.c_void_p(ci.data_ptr()), 4, ctypes.byref(nnz),
+                                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == _lib.ERR_CAPACITY and nnz.value == full.nnz
+    assert torch.equal(rp, full.rowptr)
+    # validation mode catches an unsorted row before any other kernel reads it
+    bad = synth.Csr(n, n, a.rp.copy(), a.ci.copy(), a.val)
+    r0 = int(np.argmax(np.diff(a.rp) >= 2))
+    bad.ci[a.rp[r0]], bad.ci[a.rp[r0] + 1] = a.ci[a.rp[r0] + 1], a.ci[a.rp[r0]]
+    os.environ["TSSPGEMM_VALIDATE"] = "1"
+    try:
+        note("validation: unsorted row")
+        with pytest.raises(_lib.TSSpGEMMError) as e:
+            tss.spgemm(to_dev(bad), to_dev(b))
+        assert e.value.code == _lib.ERR_MALFORMED
+        oob = synth.Csr(n, 32, b.rp.copy(), b.ci.copy(), b.val)
+        oob.ci[-1] = 40  # column outside [0, d)
+        note("validation: column out of range")
+        with pytest.raises(_lib.TSSpGEMMError) as e:
+            tss.spgemm(to_dev(a), to_dev(oob))
+        assert e.value.code == _lib.ERR_MALFORMED
+        note("validation: good input passes")
+        compare_f32(a, b, tss.spgemm(to_dev(a), to_dev(b)))
+    finally:
+        del os.environ["TSSPGEMM_VALIDATE"]
