@@ -134,13 +134,18 @@ int tsspgemm_masked_bool(const tsspgemm_csr* A, const tsspgemm_csr* F, const tss
                          int32_t* c_rowptr, int32_t* c_colidx, int64_t c_capacity, int64_t* c_nnz, void* stream);
 
 /* Multi-source BFS (Sec. IV-A, Algorithm 3) from d sources by repeated masked
- * Boolean TS-SpGEMM until every frontier is empty.
- *   A: n x n pattern. sources: d distinct vertex ids (device).
- *   levels: n x d int32 row-major: level[v*d + s] = BFS depth of v from
- *   sources[s] (0 at the source, -1 if unreachable).
- *   iterations: HOST out, number of non-empty frontiers after the first.
- *   frontier_nnz: HOST array of `capacity` int64 or NULL: nnz(F) per iteration.
- *   Synchronizes once per iteration. d <= 1024. */
+ * Boolean TS-SpGEMM until every frontier is empty. Vertex i is reached from
+ * k when A(i,k) != 0 (the product A F).
+ *   A: n x n pattern. sources: d vertex ids in [0, n) (device).
+ *   levels: n x d int32 row-major, fully written: level[v*d + s] = BFS depth
+ *   of v from sources[s] (0 at the source, -1 if unreachable).
+ *   iterations: HOST out, number of masked products performed (the last one
+ *   yields the empty frontier).
+ *   frontier_nnz: HOST array of `capacity` int64 or NULL: nnz(F) after each
+ *   product (the last entry is 0).
+ *   Synchronizes once per iteration. 1 <= d <= 1024. A source outside
+ *   [0, n) gives TSSPGEMM_ERR_INVALID_ARG. Device memory: one n x d bitmap per
+ *   iteration plus two more, and O(n) workspace. */
 int tsspgemm_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, int32_t* levels, int32_t* iterations,
                    int64_t* frontier_nnz, int32_t capacity, void* stream);
 

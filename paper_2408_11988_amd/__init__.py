@@ -13,7 +13,11 @@ from .api import (  # noqa: F401
     DeviceCsr,
     Plan,
     TSSpGEMMError,
+    TSSpGEMMFunction,
+    TSSpGEMMOp,
     bitmap_words,
+    grad_a,
+    grad_b,
     masked_bool,
     msbfs,
     numeric,

@@ -218,3 +218,79 @@ def bitmap_words(d: int) -> int:
 
 def version() -> str:
     return _lib.load().tsspgemm_version().decode()
+
+
+def grad_a(plan: Plan, A: DeviceCsr, B: DeviceCsr, G: DeviceCsr, stream=None) -> torch.Tensor:
+    """dL/dA on pat(A) (an SDDMM): out[p] = sum_j G(i,j) B(k,j) for the p-th entry (i,k)."""
+    out = torch.empty(max(A.nnz, 1), dtype=torch.float32, device=A.rowptr.device)
+    da, db, dg = A.desc(), B.desc(), G.desc()
+    rc = _lib.load().tsspgemm_grad_a(plan.handle, ctypes.byref(da), ctypes.byref(db), ctypes.byref(dg),
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_grad_a")
+    return out[:A.nnz]
+
+
+def grad_b(plan: Plan, AT: DeviceCsr, perm: torch.Tensor, A: DeviceCsr, B: DeviceCsr, G: DeviceCsr,
+           stream=None) -> torch.Tensor:
+    """dL/dB on pat(B): out[q] = sum_i A(i,k) G(i,j) for the q-th entry (k,j) (A^T G sampled)."""
+    out = torch.empty(max(B.nnz, 1), dtype=torch.float32, device=B.rowptr.device)
+    dat, da, db, dg = AT.desc(), A.desc(), B.desc(), G.desc()
+    rc = _lib.load().tsspgemm_grad_b(plan.handle, ctypes.byref(dat), _ptr(perm), ctypes.byref(da), ctypes.byref(db),
+                                     ctypes.byref(dg), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_grad_b")
+    return out[:B.nnz]
+
+
+class TSSpGEMMOp:
+    """C = A B with fixed patterns and trainable values (the sparse layer of a
+    training loop). The symbolic plan and A^T are built once; every call runs
+    only the numeric phase, and backward runs dL/dA and dL/dB on the GPU."""
+
+    def __init__(self, A: DeviceCsr, B: DeviceCsr, tuning: dict | None = None):
+        self.A = A.with_vals(None)
+        self.B = B.with_vals(None)
+        self.plan, self.c_rowptr, self.nnz = symbolic(self.A, self.B, "plus_times", tuning=tuning)
+        self.c_colidx = torch.empty(self.nnz, dtype=torch.int32, device=A.rowptr.device)
+        self._at = None
+
+    def transpose(self):
+        if self._at is None:
+            self._at = transpose(self.A)
+        return self._at
+
+    def c_pattern(self) -> DeviceCsr:
+        return DeviceCsr(self.A.nrows, self.B.ncols, self.c_rowptr, self.c_colidx, None)
+
+    def forward_values(self, a_vals: torch.Tensor, b_vals: torch.Tensor) -> torch.Tensor:
+        c_vals = torch.empty(self.nnz, dtype=torch.float32, device=a_vals.device)
+        numeric(self.plan, self.A.with_vals(a_vals.contiguous()), self.B.with_vals(b_vals.contiguous()),
+                self.c_colidx, c_vals)
+        return c_vals
+
+    def __call__(self, a_vals: torch.Tensor, b_vals: torch.Tensor) -> torch.Tensor:
+        return TSSpGEMMFunction.apply(a_vals, b_vals, self)
+
+
+class TSSpGEMMFunction(torch.autograd.Function):
+    """Autograd node of TSSpGEMMOp: values of A and B in, values of C out."""
+
+    @staticmethod
+    def forward(ctx, a_vals, b_vals, op: TSSpGEMMOp):
+        ctx.save_for_backward(a_vals, b_vals)
+        ctx.op = op
+        return op.forward_values(a_vals, b_vals)
+
+    @staticmethod
+    def backward(ctx, g):
+        a_vals, b_vals = ctx.saved_tensors
+        op = ctx.op
+        A = op.A.with_vals(a_vals.contiguous())
+        B = op.B.with_vals(b_vals.contiguous())
+        G = op.c_pattern().with_vals(g.contiguous().to(torch.float32))
+        ga = gb = None
+        if ctx.needs_input_grad[0]:
+            ga = grad_a(op.plan, A, B, G)
+        if ctx.needs_input_grad[1]:
+            AT, perm = op.transpose()
+            gb = grad_b(op.plan, AT, perm, A, B, G)
+        return ga, gb, None

@@ -94,7 +94,8 @@ static int plan_alloc_host(Plan* p) {
 
 void plan_free(Plan* p) {
   for (DevBuf* b : {&p->bbits, &p->cbits, &p->flops, &p->cnt, &p->scan, &p->sym_items, &p->num_items,
-                    &p->split_rows, &p->partial, &p->ctr, &p->maskbits})
+                    &p->split_rows, &p->partial, &p->ctr, &p->maskbits, &p->gb_items, &p->gb_split,
+                    &p->gb_partial, &p->gb_ctr})
     b->release();
   if (p->host_ctr) (void)hipHostFree(p->host_ctr);
   p->host_ctr = nullptr;
@@ -222,6 +223,7 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   sp.items = (const Item*)p->sym_items.p;
   sp.ctr = ctr;
   sp.mask = mask;
+  if ((rc = launch_sym_split_zero(pr, (const Item*)p->sym_items.p, ctr, sym_cap, st))) return rc;
   if ((rc = launch_symbolic(sp, sym_cap, st))) return rc;
   if ((rc = launch_sym_split_mask(pr, (const Item*)p->sym_items.p, mask, ctr, sym_cap, st))) return rc;
   if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;

@@ -7,10 +7,28 @@
 
 namespace tss {
 
-// Grow-only device buffer.
+// Grow-only device buffer; owns its allocation (move-only).
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), cap(o.cap) {
+    o.p = nullptr;
+    o.cap = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      cap = o.cap;
+      o.p = nullptr;
+      o.cap = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { release(); }
   int ensure(size_t bytes);
   void release();
 };
@@ -26,11 +44,16 @@ struct Plan {
   int32_t* crp = nullptr;  // caller's C row pointers (from the symbolic call)
   // device workspace
   DevBuf bbits, cbits, flops, cnt, scan, sym_items, num_items, split_rows, partial, ctr, maskbits;
+  DevBuf gb_items, gb_split, gb_partial, gb_ctr;  // dL/dB work lists
   Counters* host_ctr = nullptr;  // pinned
   // results of the last symbolic call
   int64_t nnz = 0, flops_total = 0, n_split_items = 0, n_block_items = 0, n_wave_rows = 0, n_light_rows = 0;
   int64_t n_split_rows = 0;
   std::mutex mu;
+  ~Plan() {
+    if (host_ctr) (void)hipHostFree(host_ctr);
+    host_ctr = nullptr;
+  }
 };
 
 int check_csr(const tsspgemm_csr* m, const char* name, bool need_vals);

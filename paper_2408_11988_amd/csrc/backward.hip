@@ -1,0 +1,463 @@
+// Backward of C = A B for a loss L with G = dL/dC given on C's pattern.
+//
+//  dL/dA(i,k) = sum over j in pat(B_k) of G(i,j) B(k,j)   (an SDDMM on pat(A))
+//  dL/dB(k,j) = sum over i in pat(A^T_k) of A(i,k) G(i,j) (A^T G sampled on pat(B))
+//
+// Every needed G(i,j) lies in pat(C): if A(i,k) and B(k,j) are stored, the
+// structural product stores C(i,j). Both passes accumulate in FP64 in a fixed
+// order and round once to FP32.
+//
+// dL/dA reuses the forward plan's binned rows: a row's G values are staged in
+// an LDS strip of width d, and each A entry (i,k) is a dot product of B row k
+// with that strip, taken by a group of GL lanes and reduced across the group.
+//
+// dL/dB walks A^T (from tsspgemm_transpose): a group of GL lanes owns the
+// entries of one B row k (lane = column j) and runs over the rows i of A^T
+// row k; G(i,j) is found at C.rowptr[i] + rank of j in C's bitmap row i (the
+// symbolic pass's accumulator). Long A^T rows are cut into chunks whose
+// partial sums a second kernel adds in chunk order.
+#include "api_internal.hpp"
+
+namespace tss {
+
+constexpr int kGbChunk = 512;  // A^T entries per dL/dB work item
+
+__device__ __forceinline__ void gsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over the GL lanes of a group (lanes aligned to GL), FP64.
+template <int GL>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < GL; o <<= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+struct GradAParams {
+  Problem pr;             // A, B, C pattern (crp, cbits) of the forward plan
+  const int32_t* gci;     // G = dL/dC on C's pattern
+  const float* gval;
+  float* grad_a;
+  const Item* items;
+  int32_t n_wg_items, n_heavy_records, n_light;
+};
+
+// Dot products for A entries [p0, p1) of one row, groups g0, g0+gstride, ...
+template <int GL>
+__device__ __forceinline__ void grad_a_range(const GradAParams& gp, int p0, int p1, int g0, int gstride,
+                                             const float* strip) {
+  constexpr int U = 4;
+  const int gl = threadIdx.x % GL;
+  const Problem& pr = gp.pr;
+  const float* __restrict__ bval = (const float*)pr.bval;
+  for (int p = p0 + g0 * U; p < p1; p += gstride * U) {
+    int q[U], qe[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      q[u] = 0;
+      qe[u] = 0;
+      if (p + u < p1) {
+        const int k = pr.aci[p + u];
+        q[u] = pr.brp[k];
+        qe[u] = pr.brp[k + 1];
+      }
+    }
+    double s[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s[u] = 0.0;
+      for (int t = q[u] + gl; t < qe[u]; t += GL) s[u] += (double)bval[t] * (double)strip[pr.bci[t]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double v = group_sum<GL>(s[u]);
+      if (gl == 0 && p + u < p1) gp.grad_a[p + u] = (float)v;
+    }
+  }
+}
+
+// Workgroup items (split chunks, workgroup rows) and wavefront rows.
+template <int GL>
+__global__ __launch_bounds__(kBlock) void k_grad_a(GradAParams gp) {
+  extern __shared__ __align__(16) float gstrip[];
+  const Problem& pr = gp.pr;
+  const int d = pr.d;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = blockIdx.x;
+  constexpr int GPW = kWave / GL;
+  if (g < gp.n_wg_items) {
+    const Item it = gp.items[g];
+    float* strip = gstrip;
+    for (int q = pr.crp[it.row] + threadIdx.x; q < pr.crp[it.row + 1]; q += kBlock) strip[gp.gci[q]] = gp.gval[q];
+    __syncthreads();
+    grad_a_range<GL>(gp, it.p0, it.p1, threadIdx.x / GL, kBlock / GL, strip);
+  } else {
+    const int64_t idx = (int64_t)gp.n_wg_items + 4 * (int64_t)(g - gp.n_wg_items) + wave;
+    if (idx >= gp.n_heavy_records) return;
+    const Item it = gp.items[idx];
+    float* strip = gstrip + wave * d;
+    for (int q = pr.crp[it.row] + lane; q < pr.crp[it.row + 1]; q += kWave) strip[gp.gci[q]] = gp.gval[q];
+    gsync();
+    grad_a_range<GL>(gp, it.p0, it.p1, lane / GL, GPW, strip);
+  }
+}
+
+// Light rows: one group (and one strip) per row.
+template <int GL>
+__global__ __launch_bounds__(kBlock) void k_grad_a_light(GradAParams gp) {
+  extern __shared__ __align__(16) float gstrip[];
+  constexpr int G = kBlock / GL;
+  const Problem& pr = gp.pr;
+  const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
+  float* strip = gstrip + grp * pr.d;
+  const Item* items = gp.items + gp.n_heavy_records;
+  for (int64_t t = (int64_t)blockIdx.x * G + grp; t < gp.n_light; t += (int64_t)gridDim.x * G) {
+    const Item it = items[t];
+    for (int q = pr.crp[it.row] + gl; q < pr.crp[it.row + 1]; q += GL) strip[gp.gci[q]] = gp.gval[q];
+    gsync();
+    grad_a_range<GL>(gp, it.p0, it.p1, 0, 1, strip);
+    gsync();
+  }
+}
+
+// A entries of rows without products (every B row empty) get 0.
+__global__ void k_zero_f32(float* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+// ---------------------------------------------------------------- dL/dB
+
+struct GradBParams {
+  Problem pr;                // A values, B pattern, C pattern (crp, cbits)
+  const int32_t* atrp;       // A^T row pointers (n + 1)
+  const int32_t* atci;       // A^T rows i
+  const int32_t* perm;       // position in A of each A^T entry
+  const float* gval;         // G on C's pattern
+  float* grad_b;
+  Item* items;               // [split chunks][whole rows]: row = k, [p0,p1) range of A^T entries
+  SplitRow* split_rows;
+  double* partial;           // chunk partial sums (slot x d)
+  Counters* ctr;             // num_count/num_cursor classes 0 (chunks) and 3 (rows)
+};
+
+// cost of B row k: A^T entries x B entries
+__global__ void k_gb_bin_count(GradBParams gb) {
+  __shared__ int32_t hist[2 * kBins];
+  if (threadIdx.x < 2 * kBins) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < gb.pr.n) {
+    const int m = gb.atrp[k + 1] - gb.atrp[k];
+    const int lb = gb.pr.brp[k + 1] - gb.pr.brp[k];
+    if (m > 0 && lb > 0) {
+      if (m > kGbChunk)
+        atomicAdd(&hist[0], (m + kGbChunk - 1) / kGbChunk);
+      else
+        atomicAdd(&hist[kBins + (kBins - 1 - (31 - __clz(m * lb)))], 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kBins && hist[threadIdx.x]) {
+    const int cls = threadIdx.x < kBins ? 0 : 3;
+    atomicAdd(&gb.ctr->num_count[cls][threadIdx.x % kBins], hist[threadIdx.x]);
+  }
+}
+
+__global__ void k_gb_bin_scan(Counters* ctr) {
+  int32_t off = 0;
+  int32_t tot[2] = {0, 0};
+  const int cls[2] = {0, 3};
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < kBins; ++b) {
+      ctr->num_cursor[cls[c]][b] = off;
+      off += ctr->num_count[cls[c]][b];
+      tot[c] += ctr->num_count[cls[c]][b];
+    }
+  ctr->num_split_items = tot[0];
+  ctr->num_light_rows = tot[1];
+}
+
+__global__ void k_gb_bin_fill(GradBParams gb) {
+  __shared__ int32_t cnt[2 * kBins], base[2 * kBins];
+  __shared__ int32_t nsplit, split_base;
+  if (threadIdx.x < 2 * kBins) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) nsplit = 0;
+  __syncthreads();
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int a = 0, m = 0, key = -1, count = 0, local = 0, slocal = 0;
+  if (k < gb.pr.n) {
+    a = gb.atrp[k];
+    m = gb.atrp[k + 1] - a;
+    const int lb = gb.pr.brp[k + 1] - gb.pr.brp[k];
+    if (m > 0 && lb > 0) {
+      if (m > kGbChunk) {
+        key = 0;
+        count = (m + kGbChunk - 1) / kGbChunk;
+        slocal = atomicAdd(&nsplit, 1);
+      } else {
+        key = kBins + (kBins - 1 - (31 - __clz(m * lb)));
+        count = 1;
+      }
+      local = atomicAdd(&cnt[key], count);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kBins && cnt[threadIdx.x]) {
+    const int cls = threadIdx.x < kBins ? 0 : 3;
+    base[threadIdx.x] = atomicAdd(&gb.ctr->num_cursor[cls][threadIdx.x % kBins], cnt[threadIdx.x]);
+  }
+  if (threadIdx.x == 0 && nsplit) split_base = atomicAdd(&gb.ctr->num_split_rows, nsplit);
+  __syncthreads();
+  if (count == 0) return;
+  const int pos = base[key] + local;
+  if (key == 0) {
+    for (int c = 0; c < count; ++c) {
+      const int p0 = a + c * kGbChunk;
+      gb.items[pos + c] = Item{(int32_t)k, p0, min(a + m, p0 + kGbChunk), pos + c};
+    }
+    gb.split_rows[split_base + slocal] = SplitRow{(int32_t)k, pos, count, 0};
+  } else {
+    gb.items[pos] = Item{(int32_t)k, a, a + m, kNoSlot};
+  }
+}
+
+// rank of column j among the set bits of a bitmap row (bits below j)
+__device__ __forceinline__ int bitmap_rank(const uint32_t* cb, int j) {
+  int r = 0;
+  const int w = j >> 5;
+  for (int x = 0; x < w; ++x) r += __popc(cb[x]);
+  return r + __popc(cb[w] & ((1u << (j & 31)) - 1u));
+}
+
+// One group of GL lanes per item, items walked with a grid stride. Lanes own
+// the B row's entries (GL at a time); a lane's sum runs over the item's
+// A^T entries in order.
+template <int GL>
+__global__ __launch_bounds__(kBlock) void k_grad_b(GradBParams gb) {
+  constexpr int G = kBlock / GL;
+  constexpr int U = 4;
+  const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
+  const Problem& pr = gb.pr;
+  const float* __restrict__ aval = (const float*)pr.aval;
+  const int total = gb.ctr->num_split_items + gb.ctr->num_light_rows;
+  for (int64_t t = (int64_t)blockIdx.x * G + grp; t < total; t += (int64_t)gridDim.x * G) {
+    const Item it = gb.items[t];
+    const int k = it.row;
+    const int q0 = pr.brp[k], q1 = pr.brp[k + 1];
+    for (int qb = q0; qb < q1; qb += GL) {
+      const int q = qb + gl;
+      const bool own = q < q1;
+      const int j = own ? pr.bci[q] : 0;
+      double acc = 0.0;
+      for (int x = it.p0; x < it.p1; x += U) {
+        int i[U];
+        float a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          i[u] = -1;
+          a[u] = 0.0f;
+          if (x + u < it.p1) {
+            i[u] = gb.atci[x + u];
+            a[u] = aval[gb.perm[x + u]];
+          }
+        }
+        float g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          g[u] = 0.0f;
+          if (own && i[u] >= 0) {
+            const uint32_t* cb = pr.cbits + (int64_t)i[u] * pr.wp;
+            g[u] = gb.gval[pr.crp[i[u]] + bitmap_rank(cb, j)];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)g[u];
+      }
+      if (own) {
+        if (it.aux == kNoSlot)
+          gb.grad_b[q] = (float)acc;
+        else
+          gb.partial[(int64_t)it.aux * pr.d + (q - q0)] = acc;
+      }
+    }
+  }
+}
+
+__global__ void k_grad_b_finalize(GradBParams gb) {
+  const int nrows = gb.ctr->num_split_rows;
+  for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const SplitRow s = gb.split_rows[r];
+    const int q0 = gb.pr.brp[s.row], q1 = gb.pr.brp[s.row + 1];
+    for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+      double acc = 0.0;
+      for (int c = 0; c < s.count; ++c) acc += gb.partial[(int64_t)(s.first + c) * gb.pr.d + (q - q0)];
+      gb.grad_b[q] = (float)acc;
+    }
+  }
+}
+
+static int check_grad_args(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, const tsspgemm_csr* G,
+                           const void* out, const char* who) {
+  int rc;
+  if (!p || !p->ready || p->sr != TSSPGEMM_PLUS_TIMES_F32) {
+    set_error(std::string(who) + ": needs the plus-times FP32 plan of the forward product");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if ((rc = check_csr(A, "A", true)) || (rc = check_csr(B, "B", true)) || (rc = check_csr(G, "G", true))) return rc;
+  if (A->nrows != p->n || B->ncols != p->d || A->nnz != p->a_nnz || B->nnz != p->b_nnz || G->nrows != p->n ||
+      G->ncols != p->d || G->nnz != p->nnz) {
+    set_error(std::string(who) + ": A, B or G does not match the forward plan");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (!out) {
+    set_error(std::string(who) + ": NULL output");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  return TSSPGEMM_OK;
+}
+
+static Problem plan_problem(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B) {
+  Problem pr{};
+  pr.n = (int32_t)p->n;
+  pr.d = (int32_t)p->d;
+  pr.wp = p->wp;
+  pr.arp = A->rowptr;
+  pr.aci = A->colidx;
+  pr.aval = A->vals;
+  pr.brp = B->rowptr;
+  pr.bci = B->colidx;
+  pr.bval = B->vals;
+  pr.bbits = (const uint32_t*)p->bbits.p;
+  pr.cbits = (uint32_t*)p->cbits.p;
+  pr.flops = (int64_t*)p->flops.p;
+  pr.crp = p->crp;
+  return pr;
+}
+
+int light_group_lanes(int group_lanes, int64_t d, int sr);
+
+static int run_grad_a(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_a,
+                      hipStream_t st) {
+  int rc;
+  if ((rc = check_grad_args(p, A, B, G, grad_a, "grad_a"))) return rc;
+  if (A->nnz == 0) return TSSPGEMM_OK;
+  GradAParams gp{};
+  gp.pr = plan_problem(p, A, B);
+  gp.gci = G->colidx;
+  gp.gval = (const float*)G->vals;
+  gp.grad_a = grad_a;
+  gp.items = (const Item*)p->num_items.p;
+  gp.n_wg_items = (int32_t)(p->n_split_items + p->n_block_items);
+  gp.n_heavy_records = (int32_t)(p->n_split_items + p->n_block_items + p->n_wave_rows);
+  gp.n_light = (int32_t)p->n_light_rows;
+  const unsigned gz = grid_for(A->nnz, 256 * 4) > 8192 ? 8192 : grid_for(A->nnz, 256 * 4);
+  k_zero_f32<<<gz, 256, 0, st>>>(grad_a, A->nnz);
+  const int gl = p->tune.group_lanes;
+  const int64_t grid = gp.n_wg_items + (p->n_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
+  const size_t lds = (size_t)kWavesPerBlock * p->d * 4;
+  const int lgl = light_group_lanes(gl, p->d, TSSPGEMM_PLUS_TIMES_I32);  // float strips: 4 bytes
+  const size_t llds = (size_t)(kBlock / lgl) * p->d * 4;
+  int64_t lgrid = (gp.n_light + (kBlock / lgl) - 1) / (kBlock / lgl);
+  if (lgrid > 2048) lgrid = 2048;
+#define TSS_GA(GLV)                                                                              \
+  case GLV:                                                                                      \
+    if (grid > 0) k_grad_a<GLV><<<(unsigned)grid, kBlock, lds, st>>>(gp);                        \
+    break;
+#define TSS_GAL(GLV)                                                                             \
+  case GLV:                                                                                      \
+    if (lgrid > 0) k_grad_a_light<GLV><<<(unsigned)lgrid, kBlock, llds, st>>>(gp);               \
+    break;
+  switch (gl) {
+    TSS_GA(4) TSS_GA(8) TSS_GA(16) TSS_GA(32) TSS_GA(64)
+    default: set_error("grad_a: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  switch (lgl) {
+    TSS_GAL(4) TSS_GAL(8) TSS_GAL(16) TSS_GAL(32) TSS_GAL(64)
+    default: set_error("grad_a: bad light group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  }
+#undef TSS_GA
+#undef TSS_GAL
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+static int run_grad_b(Plan* p, const tsspgemm_csr* AT, const int32_t* perm, const tsspgemm_csr* A,
+                      const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_b, hipStream_t st) {
+  int rc;
+  if ((rc = check_grad_args(p, A, B, G, grad_b, "grad_b"))) return rc;
+  if ((rc = check_csr(AT, "AT", false))) return rc;
+  if (AT->nrows != p->n || AT->nnz != A->nnz || (A->nnz > 0 && !perm)) {
+    set_error("grad_b: AT / perm do not match A");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (B->nnz == 0) return TSSPGEMM_OK;
+  const int64_t n = p->n, nnz = A->nnz;
+  // a row of m > kGbChunk entries has ceil(m / kGbChunk) <= 2 m / kGbChunk chunks
+  const int64_t chunk_cap = 2 * nnz / kGbChunk + 2;
+  if ((rc = p->gb_items.ensure((size_t)(n + chunk_cap) * sizeof(Item))) ||
+      (rc = p->gb_split.ensure((size_t)(n + 1) * sizeof(SplitRow))) ||
+      (rc = p->gb_partial.ensure((size_t)chunk_cap * p->d * 8)) || (rc = p->gb_ctr.ensure(sizeof(Counters))))
+    return rc;
+  GradBParams gb{};
+  gb.pr = plan_problem(p, A, B);
+  gb.atrp = AT->rowptr;
+  gb.atci = AT->colidx;
+  gb.perm = perm;
+  gb.gval = (const float*)G->vals;
+  gb.grad_b = grad_b;
+  gb.items = (Item*)p->gb_items.p;
+  gb.split_rows = (SplitRow*)p->gb_split.p;
+  gb.partial = (double*)p->gb_partial.p;
+  gb.ctr = (Counters*)p->gb_ctr.p;
+  const unsigned gz = grid_for(B->nnz, 256 * 4) > 8192 ? 8192 : grid_for(B->nnz, 256 * 4);
+  k_zero_f32<<<gz, 256, 0, st>>>(grad_b, B->nnz);
+  if ((rc = launch_zero_bytes(gb.ctr, sizeof(Counters), st))) return rc;
+  const unsigned g = grid_for(n, 256);
+  k_gb_bin_count<<<g, 256, 0, st>>>(gb);
+  k_gb_bin_scan<<<1, 1, 0, st>>>(gb.ctr);
+  k_gb_bin_fill<<<g, 256, 0, st>>>(gb);
+  const int gl = p->tune.group_lanes;
+  const unsigned grid = 2048;
+#define TSS_GB(GLV)                                   \
+  case GLV:                                           \
+    k_grad_b<GLV><<<grid, kBlock, 0, st>>>(gb);       \
+    break;
+  switch (gl) {
+    TSS_GB(4) TSS_GB(8) TSS_GB(16) TSS_GB(32) TSS_GB(64)
+    default: set_error("grad_b: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  }
+#undef TSS_GB
+  k_grad_b_finalize<<<1024, 256, 0, st>>>(gb);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+}  // namespace tss
+
+extern "C" {
+
+int tsspgemm_grad_a(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_csr* B, const tsspgemm_csr* G,
+                    float* grad_a, void* stream) {
+  try {
+    return tss::run_grad_a((tss::Plan*)plan, A, B, G, grad_a, (hipStream_t)stream);
+  } catch (...) {
+    tss::set_error("unexpected C++ exception");
+    return TSSPGEMM_ERR_HIP;
+  }
+}
+
+int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,
+                    const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_b, void* stream) {
+  try {
+    return tss::run_grad_b((tss::Plan*)plan, AT, at_perm, A, B, G, grad_b, (hipStream_t)stream);
+  } catch (...) {
+    tss::set_error("unexpected C++ exception");
+    return TSSPGEMM_ERR_HIP;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,256 @@
+// Multi-source BFS by repeated masked Boolean TS-SpGEMM (Sec. IV-A,
+// Algorithm 3): N = A F over (AND, OR), F = N \ S, S = S v N, until F is empty.
+//
+// Every matrix of the loop is kept as a bitmap of d bits per row (d <= 1024):
+// F (the frontier, the "B" of the multiply), S (visited, the complement
+// mask) and N. One iteration is the symbolic pass of the library (bitmap
+// accumulator, row binning of A done once) with two row filters that do not
+// change the result: A entries whose frontier row is empty are skipped (a
+// 1-bit-per-row summary of F), and rows whose unvisited columns all belong to
+// sources whose frontier is already empty are skipped (a d-bit "active" word
+// mask). The masked product is directly N \ S, i.e. the next frontier.
+// Levels are written once, at the end, from the kept frontiers N_0..N_T: a
+// wavefront owns 64 consecutive columns of a row, so every store is
+// coalesced, and never-reached pairs get -1 in the same pass.
+#include <string>
+#include <vector>
+
+#include "api_internal.hpp"
+
+namespace tss {
+
+// N_0: bit j of row sources[j]; a source outside [0, n) sets the error flag.
+__global__ void k_bfs_seed(const int32_t* __restrict__ src, int32_t d, int64_t n, int wp, uint32_t* __restrict__ n0,
+                           int64_t* __restrict__ bad) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d) return;
+  const int32_t v = src[j];
+  if (v < 0 || v >= n) {
+    atomicOr((unsigned long long*)bad, 1ull);
+    return;
+  }
+  atomicOr(&n0[(int64_t)v * wp + (j >> 5)], 1u << (j & 31));
+}
+
+// S |= N, the per-row frontier summary bits, and per-workgroup partial counts
+// and column ORs of N (reduced by k_bfs_reduce). One thread per row.
+__global__ __launch_bounds__(256) void k_bfs_update(int64_t n, int wp, const uint32_t* __restrict__ N,
+                                                    uint32_t* __restrict__ S, uint32_t* __restrict__ fnz,
+                                                    uint32_t* __restrict__ part_or, int64_t* __restrict__ part_cnt) {
+  __shared__ uint32_t sor[32];
+  __shared__ unsigned long long scnt;
+  if (threadIdx.x < 32) sor[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) scnt = 0ull;
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int cnt = 0;
+  bool nz = false;
+  if (i < n) {
+    for (int w = 0; w < wp; ++w) {
+      const uint32_t x = N[i * wp + w];
+      if (x) {
+        nz = true;
+        cnt += __popc(x);
+        S[i * wp + w] |= x;
+        atomicOr(&sor[w], x);
+      }
+    }
+  }
+  const uint64_t b = __ballot(nz);
+  const int lane = threadIdx.x & 63;
+  const int64_t r0 = i - lane;  // first row of this wavefront, a multiple of 64
+  if (lane == 0 && r0 < n) fnz[r0 >> 5] = (uint32_t)b;
+  if (lane == 32 && r0 + 32 < n) fnz[(r0 >> 5) + 1] = (uint32_t)(b >> 32);
+  const int wsum = wave_sum_i32(cnt);
+  if (lane == 0 && wsum) atomicAdd(&scnt, (unsigned long long)wsum);
+  __syncthreads();
+  if (threadIdx.x < wp) part_or[(int64_t)blockIdx.x * wp + threadIdx.x] = sor[threadIdx.x];
+  if (threadIdx.x == 0) part_cnt[blockIdx.x] = (int64_t)scnt;
+}
+
+// One workgroup: OR of the partial column masks -> active, sum -> count.
+__global__ __launch_bounds__(1024) void k_bfs_reduce(int64_t nblocks, int wp, const uint32_t* __restrict__ part_or,
+                                                     const int64_t* __restrict__ part_cnt,
+                                                     uint32_t* __restrict__ active, int64_t* __restrict__ count) {
+  __shared__ uint32_t sor[32];
+  __shared__ unsigned long long scnt;
+  if (threadIdx.x < 32) sor[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) scnt = 0ull;
+  __syncthreads();
+  unsigned long long c = 0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += blockDim.x) c += (unsigned long long)part_cnt[b];
+  for (int64_t t = threadIdx.x; t < nblocks * wp; t += blockDim.x) {
+    const uint32_t x = part_or[t];
+    if (x) atomicOr(&sor[t % wp], x);
+  }
+  atomicAdd(&scnt, c);
+  __syncthreads();
+  if (threadIdx.x < wp) active[threadIdx.x] = sor[threadIdx.x];
+  if (threadIdx.x == 0) *count = (int64_t)scnt;
+}
+
+// level[i*d + j] = t for the frontier N_t holding bit j of row i, else -1.
+// A wavefront covers 64 columns of one row; the frontier words are uniform
+// across it.
+__global__ __launch_bounds__(256) void k_bfs_levels(int64_t n, int32_t d, int wp, int32_t nfront,
+                                                    const uint32_t* const* __restrict__ fronts,
+                                                    int32_t* __restrict__ levels) {
+  const int lane = threadIdx.x & 63;
+  const int nch = (d + 63) >> 6;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t row = wave / nch;
+  const int c = (int)(wave % nch);
+  if (row >= n) return;
+  const int j = 64 * c + lane;
+  const int w = j >> 5;
+  int lev = -1;
+  if (j < d) {
+    for (int t = 0; t < nfront; ++t) {
+      const uint32_t x = fronts[t][row * wp + w];
+      if ((x >> (j & 31)) & 1u) {
+        lev = t;
+        break;
+      }
+    }
+    levels[row * d + j] = lev;
+  }
+}
+
+struct BfsWork {
+  DevBuf S, fnz, active, part_or, part_cnt, count, fronts_dev;
+  std::vector<DevBuf> fronts;
+  int64_t* host_count = nullptr;  // pinned: [nnz of the frontier, bad-source flag]
+  ~BfsWork() {
+    if (host_count) (void)hipHostFree(host_count);
+  }
+};
+
+static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, int32_t* levels,
+                     int32_t* iterations, int64_t* frontier_nnz, int32_t capacity, hipStream_t st) {
+  int rc;
+  if ((rc = check_csr(A, "A", false))) return rc;
+  if (A->nrows != A->ncols) {
+    set_error("A must be square (n x n)");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (d < 1 || d > kMaxDenseD) {
+    set_error("msbfs: d must be in [1, 1024]");
+    return d < 1 ? TSSPGEMM_ERR_INVALID_ARG : TSSPGEMM_ERR_UNSUPPORTED;
+  }
+  if (!sources || !levels || !iterations) {
+    set_error("msbfs: NULL argument");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  const int64_t n = A->nrows;
+  const int wp = bitmap_words(d);
+  Plan p;
+  BfsWork w;
+  TSS_HIP(hipHostMalloc((void**)&w.host_count, 2 * sizeof(int64_t), hipHostMallocDefault));
+  p.n = n;
+  p.d = d;
+  p.wp = wp;
+  tsspgemm_tuning tn{};
+  tsspgemm_csr bdummy{n, d, 0, A->rowptr, nullptr, nullptr};
+  resolve_tuning(nullptr, &bdummy, &tn);
+  const int64_t sym_cap = n + A->nnz / tn.sym_split_nnz + 2;
+  const int64_t nblk = (n + 255) / 256;
+  if ((rc = p.ctr.ensure(sizeof(Counters))) || (rc = p.flops.ensure((size_t)n * 8)) ||
+      (rc = p.sym_items.ensure((size_t)sym_cap * sizeof(Item))) || (rc = w.S.ensure((size_t)n * wp * 4)) ||
+      (rc = w.fnz.ensure((size_t)(n / 32 + 4) * 4)) || (rc = w.active.ensure(32 * 4)) ||
+      (rc = w.part_or.ensure((size_t)(nblk + 1) * wp * 4)) || (rc = w.part_cnt.ensure((size_t)(nblk + 1) * 8)) ||
+      (rc = w.count.ensure(16)))
+    return rc;
+  TSS_HIP(hipHostMalloc((void**)&p.host_ctr, sizeof(Counters), hipHostMallocDefault));
+  if (validate_enabled() && (rc = validate_on_device(A, "A", (Counters*)p.ctr.p, p.host_ctr, st))) return rc;
+  Counters* ctr = (Counters*)p.ctr.p;
+  Problem pr{};
+  pr.n = (int32_t)n;
+  pr.d = d;
+  pr.wp = wp;
+  pr.arp = A->rowptr;
+  pr.aci = A->colidx;
+  pr.flops = (int64_t*)p.flops.p;
+  if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
+  if ((rc = launch_sym_bin(pr, tn.sym_split_nnz, (Item*)p.sym_items.p, ctr, st))) return rc;
+
+  auto new_front = [&](uint32_t** out) -> int {
+    w.fronts.emplace_back();
+    int r = w.fronts.back().ensure((size_t)n * wp * 4);
+    *out = (uint32_t*)w.fronts.back().p;
+    return r;
+  };
+  auto update = [&](const uint32_t* N, int64_t* cnt_out) -> int {
+    if (n > 0)
+      k_bfs_update<<<(unsigned)nblk, 256, 0, st>>>(n, wp, N, (uint32_t*)w.S.p, (uint32_t*)w.fnz.p,
+                                                    (uint32_t*)w.part_or.p, (int64_t*)w.part_cnt.p);
+    k_bfs_reduce<<<1, 1024, 0, st>>>(n > 0 ? nblk : 0, wp, (const uint32_t*)w.part_or.p,
+                                     (const int64_t*)w.part_cnt.p, (uint32_t*)w.active.p, (int64_t*)w.count.p);
+    TSS_CHECK_LAUNCH();
+    TSS_HIP(hipMemcpyAsync(w.host_count, w.count.p, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    TSS_HIP(hipStreamSynchronize(st));
+    *cnt_out = *w.host_count;
+    return TSSPGEMM_OK;
+  };
+
+  // N_0 = one-hot sources; S = N_0
+  uint32_t* f0 = nullptr;
+  if ((rc = new_front(&f0))) return rc;
+  if ((rc = launch_zero_bytes(f0, (size_t)n * wp * 4, st)) || (rc = launch_zero_bytes(w.S.p, (size_t)n * wp * 4, st)) ||
+      (rc = launch_zero_bytes(w.count.p, 16, st)))
+    return rc;
+  k_bfs_seed<<<grid_for(d, 256), 256, 0, st>>>(sources, d, n, wp, f0, (int64_t*)w.count.p + 1);
+  TSS_CHECK_LAUNCH();
+  int64_t cnt = 0;
+  if ((rc = update(f0, &cnt))) return rc;
+  if (w.host_count[1]) {
+    set_error("msbfs: a source vertex is outside [0, n)");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  int32_t it = 0;
+  while (cnt > 0) {
+    ++it;
+    uint32_t* nt = nullptr;
+    if ((rc = new_front(&nt))) return rc;
+    pr.bbits = (const uint32_t*)w.fronts[w.fronts.size() - 2].p;
+    pr.cbits = nt;
+    SymParams sp{};
+    sp.pr = pr;
+    sp.items = (const Item*)p.sym_items.p;
+    sp.ctr = ctr;
+    sp.mask = (const uint32_t*)w.S.p;
+    sp.active = (const uint32_t*)w.active.p;
+    sp.fnz = (const uint32_t*)w.fnz.p;
+    if ((rc = launch_sym_split_zero(pr, sp.items, ctr, sym_cap, st)) || (rc = launch_symbolic(sp, sym_cap, st)) ||
+        (rc = launch_sym_split_mask(pr, sp.items, sp.mask, ctr, sym_cap, st)))
+      return rc;
+    if ((rc = update(nt, &cnt))) return rc;
+    if (frontier_nnz && it <= capacity) frontier_nnz[it - 1] = cnt;
+  }
+  // levels from the kept frontiers N_0 .. N_T (the last one is empty)
+  const int32_t nfront = (int32_t)w.fronts.size() - 1;
+  std::vector<const uint32_t*> fp(nfront);
+  for (int t = 0; t < nfront; ++t) fp[t] = (const uint32_t*)w.fronts[t].p;
+  if ((rc = w.fronts_dev.ensure(sizeof(void*) * (nfront + 1)))) return rc;
+  TSS_HIP(hipMemcpyAsync(w.fronts_dev.p, fp.data(), sizeof(void*) * nfront, hipMemcpyHostToDevice, st));
+  const int64_t waves = n * ((d + 63) / 64);
+  if (waves > 0) {
+    k_bfs_levels<<<grid_for(waves, 4), 256, 0, st>>>(n, d, wp, nfront, (const uint32_t* const*)w.fronts_dev.p,
+                                                      levels);
+    TSS_CHECK_LAUNCH();
+  }
+  TSS_HIP(hipStreamSynchronize(st));
+  *iterations = it;
+  return TSSPGEMM_OK;
+}
+
+}  // namespace tss
+
+extern "C" int tsspgemm_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, int32_t* levels,
+                              int32_t* iterations, int64_t* frontier_nnz, int32_t capacity, void* stream) {
+  try {
+    return tss::run_msbfs(A, sources, d, levels, iterations, frontier_nnz, capacity, (hipStream_t)stream);
+  } catch (...) {
+    tss::set_error("unexpected C++ exception");
+    return TSSPGEMM_ERR_HIP;
+  }
+}

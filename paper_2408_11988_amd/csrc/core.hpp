@@ -94,6 +94,7 @@ int launch_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t
 
 int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st);
 int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st);
+int launch_sym_split_zero(const Problem& pr, const Item* items, Counters* ctr, int64_t max_items, hipStream_t st);
 int launch_sym_split_mask(const Problem& pr, const Item* items, const uint32_t* mask, Counters* ctr,
                           int64_t max_items, hipStream_t st);
 
@@ -101,6 +102,8 @@ int launch_sym_split_mask(const Problem& pr, const Item* items, const uint32_t* 
 int launch_count_scan(const Problem& pr, int32_t* cnt, int64_t* block_sums, int32_t* c_rowptr, Counters* ctr,
                       hipStream_t st);
 int64_t scan_block_sums_capacity(int64_t n);
+int64_t exscan_workspace_bytes(int64_t n);
+int launch_exscan_i32(const int32_t* in, int64_t n, int32_t* out, int64_t* block_sums, hipStream_t st);
 
 int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
                    hipStream_t st);

@@ -178,11 +178,6 @@ __global__ void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
     int bin, count;
     sym_bin(m, split_nnz, bin, count);
     if (count) atomicAdd(&hist[bin], count);
-    if (m > split_nnz) {
-      // split row: its chunks OR into a zeroed bitmap and add into a zeroed count
-      for (int w = 0; w < pr.wp; ++w) pr.cbits[i * pr.wp + w] = 0u;
-      pr.flops[i] = 0;
-    }
   }
   __syncthreads();
   if (threadIdx.x < kBins && hist[threadIdx.x]) atomicAdd(&ctr->sym_count[threadIdx.x], hist[threadIdx.x]);
@@ -401,6 +396,24 @@ int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st) {
   return TSSPGEMM_OK;
 }
 
+// Split rows are OR-ed / added chunk by chunk: zero their bitmap row and
+// product count first (one thread per item, acting on chunk 0 items).
+__global__ void k_sym_split_zero(Problem pr, const Item* items, const Counters* ctr) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= ctr->sym_total) return;
+  const Item it = items[t];
+  if ((it.aux & kSplitFlag) == 0 || (it.aux & ~kSplitFlag) != 0) return;
+  for (int w = 0; w < pr.wp; ++w) pr.cbits[(int64_t)it.row * pr.wp + w] = 0u;
+  pr.flops[it.row] = 0;
+}
+
+int launch_sym_split_zero(const Problem& pr, const Item* items, Counters* ctr, int64_t max_items, hipStream_t st) {
+  if (max_items == 0) return TSSPGEMM_OK;
+  k_sym_split_zero<<<grid_for(max_items, 256), 256, 0, st>>>(pr, items, ctr);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
 // Split rows were OR-ed chunk by chunk; apply the complement mask once all
 // chunks are in (one thread per split row, found from its chunk 0 item).
 __global__ void k_sym_split_mask(Problem pr, const Item* items, const uint32_t* mask, const Counters* ctr) {
@@ -532,6 +545,72 @@ int launch_count_scan(const Problem& pr, int32_t* cnt, int64_t* block_sums, int3
     k_write_rowptr<<<(unsigned)nb, kScanThreads, 0, st>>>(pr, cnt, block_sums, c_rowptr, ctr);
   else
     k_fill_i32<<<1, 64, 0, st>>>(c_rowptr, 1, 0);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+// ================================================================ generic exclusive scan
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sum_i32(int64_t n, const int32_t* __restrict__ in,
+                                                              int64_t* __restrict__ block_sums) {
+  __shared__ long long sh[32];
+  const int64_t base = (int64_t)blockIdx.x * kScanRows;
+  long long s = 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    const int64_t i = base + u * kScanThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  long long tot;
+  block_exscan_1024(s, sh, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_blocks_i64(int64_t nblocks, int64_t* block_sums,
+                                                                 int64_t* total) {
+  __shared__ long long sh[32];
+  long long carry = 0;
+  for (int64_t b0 = 0; b0 < nblocks; b0 += kScanThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const long long v = b < nblocks ? block_sums[b] : 0;
+    long long tot;
+    const long long ex = block_exscan_1024(v, sh, &tot);
+    if (b < nblocks) block_sums[b] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_write_i32(int64_t n, const int32_t* __restrict__ in,
+                                                                const int64_t* __restrict__ block_sums,
+                                                                int32_t* __restrict__ out) {
+  __shared__ long long sh[32];
+  const int64_t base = (int64_t)blockIdx.x * kScanRows;
+  long long carry = block_sums[blockIdx.x];
+  for (int u = 0; u < kScanPer; ++u) {
+    const int64_t i = base + u * kScanThreads + threadIdx.x;
+    const long long v = i < n ? in[i] : 0;
+    long long tot;
+    const long long ex = block_exscan_1024(v, sh, &tot);
+    if (i < n) out[i] = (int32_t)(carry + ex);
+    if (i == n - 1) out[n] = (int32_t)(carry + ex + v);
+    carry += tot;
+  }
+}
+
+int64_t exscan_workspace_bytes(int64_t n) { return 8 * ((n + kScanRows - 1) / kScanRows + 1); }
+
+// out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total, int32).
+int launch_exscan_i32(const int32_t* in, int64_t n, int32_t* out, int64_t* block_sums, hipStream_t st) {
+  const int64_t nb = (n + kScanRows - 1) / kScanRows;
+  if (nb == 0) {
+    k_fill_i32<<<1, 64, 0, st>>>(out, 1, 0);
+    TSS_CHECK_LAUNCH();
+    return TSSPGEMM_OK;
+  }
+  k_scan_sum_i32<<<(unsigned)nb, kScanThreads, 0, st>>>(n, in, block_sums);
+  k_scan_blocks_i64<<<1, kScanThreads, 0, st>>>(nb, block_sums, nullptr);
+  k_scan_write_i32<<<(unsigned)nb, kScanThreads, 0, st>>>(n, in, block_sums, out);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }
