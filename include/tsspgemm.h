@@ -170,23 +170,40 @@ int tsspgemm_grad_a(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_cs
 int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,
                     const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_b, void* stream);
 
-/* Batched plus-times TS-SpGEMM: `count` independent instances C_t = A_t B_t.
- * tsspgemm_batched_plan (synchronizes) sizes everything once:
+/* Batched plus-times TS-SpGEMM: `count` independent instances C_t = A_t B_t
+ * (FP32 values, d_t <= 1024), every phase one launch over all instances, the
+ * work of all instances binned into one list (heaviest first).
+ * tsspgemm_batched_plan sizes everything once (it runs the symbolic phase;
+ * synchronizes); the patterns of A_t and B_t must not change afterwards,
+ * their values may.
  *   As, Bs: HOST arrays of `count` descriptors (device data).
- *   pool_capacity: HOST out, entries needed in the shared output pool.
+ *   tune: NULL, or a HOST array of `count` tunings (instance thresholds; the
+ *   group width of the whole batch comes from tune[0]).
+ *   pool_capacity: HOST out, sum of nnz(C_t) = entries of the output pool.
  *   rowptr_total: HOST out, sum of (n_t + 1).
- * tsspgemm_batched_run queues the whole batch (symbolic, scan, numeric) with
- * no host synchronisation and no allocation, so it may be captured in a HIP
- * graph: c_rowptrs (rowptr_total int32; instance t's row pointers start at
- * sum_{s<t} (n_s + 1) and are relative to its own output), pool_colidx /
- * pool_vals (pool_capacity), c_offsets (count + 1 int64: instance t's output
- * occupies [c_offsets[t], c_offsets[t+1]) of the pool). */
+ * tsspgemm_batched_run queues the whole batch (symbolic, scans, numeric) on
+ * `stream` with no host synchronisation and no allocation (so it can be
+ * captured in a HIP graph):
+ *   c_rowptrs: rowptr_total int32; instance t's row pointers start at
+ *   sum_{s<t} (n_s + 1) and are relative to its own output.
+ *   pool_colidx / pool_vals: pool_capacity entries.
+ *   c_offsets: count + 1 int64 (device); instance t's output occupies
+ *   [c_offsets[t], c_offsets[t+1]) of the pool.
+ * tsspgemm_batched_capture records that same run into a HIP graph kept in the
+ * batch (the output arrays are fixed at capture time) and
+ * tsspgemm_batched_launch replays it on `stream`.
+ * tsspgemm_batched_flops copies the products of each instance (count int64,
+ * HOST) from the last completed run or plan. */
 typedef struct tsspgemm_batch_s* tsspgemm_batch;
 int tsspgemm_batched_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr* Bs,
                           const tsspgemm_tuning* tune, tsspgemm_batch* out, int64_t* pool_capacity,
                           int64_t* rowptr_total, void* stream);
 int tsspgemm_batched_run(tsspgemm_batch batch, int32_t* c_rowptrs, int32_t* pool_colidx, float* pool_vals,
                          int64_t* c_offsets, void* stream);
+int tsspgemm_batched_capture(tsspgemm_batch batch, int32_t* c_rowptrs, int32_t* pool_colidx, float* pool_vals,
+                             int64_t* c_offsets);
+int tsspgemm_batched_launch(tsspgemm_batch batch, void* stream);
+int tsspgemm_batched_flops(tsspgemm_batch batch, int64_t* flops);
 void tsspgemm_batched_destroy(tsspgemm_batch batch);
 
 /* Message for the last failing call on this thread ("" if none). */

@@ -72,6 +72,9 @@ _SIGNATURES = {
     "tsspgemm_grad_b": (ctypes.c_int, [vp, P(CsrDesc), vp, P(CsrDesc), P(CsrDesc), P(CsrDesc), vp, vp]),
     "tsspgemm_batched_plan": (ctypes.c_int, [i32, P(CsrDesc), P(CsrDesc), P(Tuning), P(vp), P(i64), P(i64), vp]),
     "tsspgemm_batched_run": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+    "tsspgemm_batched_capture": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+    "tsspgemm_batched_launch": (ctypes.c_int, [vp, vp]),
+    "tsspgemm_batched_flops": (ctypes.c_int, [vp, P(i64)]),
     "tsspgemm_batched_destroy": (None, [vp]),
     "tsspgemm_last_error": (ctypes.c_char_p, []),
     "tsspgemm_version": (ctypes.c_char_p, []),

@@ -1,0 +1,110 @@
+"""Empirical tuning of the work-class thresholds and the lane-group width.
+
+The paper tunes its tile width and height empirically and ships defaults
+(Sec. V-A, V-B); on the GPU the knobs are the group width that streams a B
+row and the product-count thresholds that send a row to a lane group, a
+wavefront, a workgroup, or split chunks. None of them changes a result (the
+structure and every value are identical for any choice), only time.
+
+The search is a coordinate descent: group width first, then the light-row
+threshold, then the wavefront / split thresholds, each candidate timed on the
+instance's numeric phase (its symbolic phase rebinds rows for the candidate).
+Results are cached per feature key in a JSON file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from .api import DeviceCsr, numeric, symbolic
+
+GROUP_LANES = (8, 16, 32, 64)
+LIGHT_MAX = (256, 1024, 2048, 8192)
+WAVE_SPLIT = ((16384, 131072), (65536, 262144), (131072, 524288))
+DEFAULT = {"group_lanes": 0, "light_max_flops": 2048, "wave_max_flops": 65536, "split_flops": 262144}
+
+
+def features(A: DeviceCsr, B: DeviceCsr, flops: int) -> str:
+    """Tuning key: d class, log2 of mean products per non-empty row, log2 of
+    the longest A row, and B's density class."""
+    n = max(A.nrows, 1)
+    arow = torch.diff(A.rowptr)
+    nonempty = max(int((arow > 0).sum()), 1)
+    maxrow = int(arow.max()) if A.nrows else 0
+    dens = B.nnz / max(1, B.nrows * max(B.ncols, 1))
+    return "d{}_f{}_m{}_b{}".format(
+        int(math.ceil(math.log2(max(B.ncols, 1)))), int(round(math.log2(max(flops / nonempty, 1)))),
+        int(round(math.log2(max(maxrow, 1)))), int(round(math.log2(max(dens * 1000, 1)))) if n else 0)
+
+
+def _time_numeric(A, B, tuning, reps=3):
+    plan, rp, nnz = symbolic(A, B, "plus_times", tuning=tuning)
+    ci = torch.empty(max(nnz, 1), dtype=torch.int32, device=A.rowptr.device)
+    cv = torch.empty(max(nnz, 1), dtype=torch.float32, device=A.rowptr.device)
+    numeric(plan, A, B, ci, cv)  # warm
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        s.record()
+        numeric(plan, A, B, ci, cv)
+        e.record()
+        e.synchronize()
+        times.append(s.elapsed_time(e))
+    times.sort()
+    return times[len(times) // 2], plan
+
+
+class Autotuner:
+    def __init__(self, path: str | None = None):
+        self.path = path
+        self.cache = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.cache = json.load(f)
+
+    def save(self):
+        if self.path:
+            os.makedirs(os.path.dirname(os.path.abspath(self.path)), exist_ok=True)
+            tmp = self.path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.cache, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.path)
+
+    def tune(self, A: DeviceCsr, B: DeviceCsr, reps: int = 3) -> dict:
+        t0, plan = _time_numeric(A, B, DEFAULT, reps)
+        key = features(A, B, plan.stats()["flops"])
+        if key in self.cache:
+            return dict(self.cache[key])
+        best, best_t = dict(DEFAULT), t0
+        for gl in GROUP_LANES:
+            cand = dict(best, group_lanes=gl)
+            t, _ = _time_numeric(A, B, cand, reps)
+            if t < best_t:
+                best, best_t = cand, t
+        for lm in LIGHT_MAX:
+            cand = dict(best, light_max_flops=lm)
+            t, _ = _time_numeric(A, B, cand, reps)
+            if t < best_t:
+                best, best_t = cand, t
+        for wm, sp in WAVE_SPLIT:
+            cand = dict(best, wave_max_flops=wm, split_flops=sp)
+            t, _ = _time_numeric(A, B, cand, reps)
+            if t < best_t:
+                best, best_t = cand, t
+        best["ms"] = round(best_t, 4)
+        self.cache[key] = best
+        return dict(best)
+
+    def tune_batch(self, pairs, reps: int = 3) -> list:
+        """Per-instance thresholds; the batch's group width is the one chosen
+        for the instance with the most work."""
+        res = [self.tune(A, B, reps) for A, B in pairs]
+        if res:
+            heavy = max(range(len(res)), key=lambda t: res[t].get("ms", 0.0))
+            gl = res[heavy].get("group_lanes", 0)
+            for r in res:
+                r["group_lanes"] = gl
+        return res

@@ -41,6 +41,8 @@ def _compile(src: str) -> str:
 def build() -> str:
     """Compile every csrc/*.hip for gfx950 and link libtsspgemm.so (always rebuilds)."""
     os.makedirs(BUILD, exist_ok=True)
+    for stale in glob.glob(os.path.join(BUILD, "*.o")):
+        os.remove(stale)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))

@@ -1,0 +1,804 @@
+// Batched plus-times TS-SpGEMM: many independent products C_t = A_t B_t of
+// uneven n, d and density, each phase one launch over all instances.
+//
+// A batch plan keeps, in device memory, one descriptor per instance (its
+// arrays, its slices of the batch workspace, its work-class thresholds) and
+// prefix sums of per-instance block counts; a kernel finds its instance by
+// binary search over those prefix sums. Work items of all instances share one
+// binned list ordered heaviest first, so the persistent numeric kernels
+// balance across instances. The output pool offsets of the instances come
+// from a device-side scan over the instances' nnz, so a run needs no host
+// synchronisation and no allocation and can be captured in a HIP graph
+// (tsspgemm_batched_capture / tsspgemm_batched_launch).
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "api_internal.hpp"
+#include "dev_numeric.hpp"
+#include "dev_symbolic.hpp"
+
+namespace tss {
+
+struct BInst {
+  Problem pr;  // crp / cci / cval are set on the device by k_b_scan
+  NumThresholds th;
+  int32_t* cnt;    // nnz of each C row (workspace)
+  int64_t rp_off;  // start of the instance's row pointers in the caller's array
+};
+
+struct BatchDev {
+  BInst* insts;
+  int32_t count;
+  int32_t dmax;
+  int32_t sym_split;
+  int32_t pad;
+  const int64_t* row_off;  // prefix sums over instances: rows
+  const int64_t* bm_off;   // bitmap blocks (kBmRows rows)
+  const int64_t* lw_off;   // light symbolic wavefronts (64 / wp rows each)
+  const int64_t* sb_off;   // scan blocks (kScanRows rows)
+  int64_t total_rows, total_sb;
+  Item* sym_items;
+  int32_t* sym_inst;
+  Item* num_items;
+  int32_t* num_inst;
+  SplitRow* split_rows;  // pad = instance
+  double* partial;       // slot x dmax
+  int64_t* block_sums;   // [total_sb] nnz sums, then [total_sb] product sums
+  int64_t* inst_flops;   // products per instance
+  Counters* ctr;
+  int32_t* c_rowptrs;  // run outputs
+  int32_t* pool_ci;
+  float* pool_val;
+  int64_t* c_off;
+};
+
+__device__ __forceinline__ int find_inst(const int64_t* off, int count, int64_t x) {
+  int lo = 0, hi = count;  // off[lo] <= x < off[hi]; empty instances are skipped
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_b_zero(Counters* ctr) {
+  uint32_t* p = (uint32_t*)ctr;
+  for (size_t t = threadIdx.x; t < sizeof(Counters) / 4; t += blockDim.x) p[t] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_b_bitmap(BatchDev b) {
+  extern __shared__ __align__(16) uint32_t sm[];
+  const int t = find_inst(b.bm_off, b.count, blockIdx.x);
+  const Problem& pr = b.insts[t].pr;
+  bitmap_block(pr.n, pr.brp, pr.bci, pr.wp, (uint32_t*)pr.bbits, (int64_t)(blockIdx.x - b.bm_off[t]) * kBmRows, sm);
+}
+
+// ---------------------------------------------------------------- symbolic
+
+__global__ void k_b_sym_bin_count(BatchDev b) {
+  __shared__ int32_t hist[kBins];
+  if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r < b.total_rows) {
+    const int t = find_inst(b.row_off, b.count, r);
+    const Problem& pr = b.insts[t].pr;
+    const int64_t i = r - b.row_off[t];
+    int bin, count;
+    sym_bin(pr.arp[i + 1] - pr.arp[i], b.sym_split, bin, count);
+    if (count) atomicAdd(&hist[bin], count);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBins && hist[threadIdx.x]) atomicAdd(&b.ctr->sym_count[threadIdx.x], hist[threadIdx.x]);
+}
+
+__global__ void k_b_sym_bin_scan(Counters* ctr) {
+  int32_t off = 0;
+  for (int x = 0; x < kBins; ++x) {
+    ctr->sym_cursor[x] = off;
+    off += ctr->sym_count[x];
+  }
+  ctr->sym_total = off;
+}
+
+__global__ void k_b_sym_bin_fill(BatchDev b) {
+  __shared__ int32_t cnt[kBins], base[kBins];
+  if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int t = 0, a = 0, m = 0, bin = 0, count = 0, local = 0;
+  int64_t i = 0;
+  if (r < b.total_rows) {
+    t = find_inst(b.row_off, b.count, r);
+    const Problem& pr = b.insts[t].pr;
+    i = r - b.row_off[t];
+    a = pr.arp[i];
+    m = pr.arp[i + 1] - a;
+    sym_bin(m, b.sym_split, bin, count);
+    if (count) local = atomicAdd(&cnt[bin], count);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBins && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&b.ctr->sym_cursor[threadIdx.x], cnt[threadIdx.x]);
+  __syncthreads();
+  if (!count) return;
+  const int pos = base[bin] + local;
+  if (m <= b.sym_split) {
+    b.sym_items[pos] = Item{(int32_t)i, a, a + m, 0};
+    b.sym_inst[pos] = t;
+  } else {
+    for (int c = 0; c < count; ++c) {
+      const int p0 = a + c * b.sym_split;
+      b.sym_items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + b.sym_split), kSplitFlag | c};
+      b.sym_inst[pos + c] = t;
+    }
+  }
+}
+
+__global__ void k_b_sym_split_zero(BatchDev b) {
+  const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (x >= b.ctr->sym_total) return;
+  const Item it = b.sym_items[x];
+  if ((it.aux & kSplitFlag) == 0 || (it.aux & ~kSplitFlag) != 0) return;
+  const Problem& pr = b.insts[b.sym_inst[x]].pr;
+  for (int w = 0; w < pr.wp; ++w) pr.cbits[(int64_t)it.row * pr.wp + w] = 0u;
+  pr.flops[it.row] = 0;
+}
+
+// light rows: a slot of wp lanes per row (wp varies by instance)
+__global__ __launch_bounds__(kBlock) void k_b_sym_light(BatchDev b) {
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (gw >= b.lw_off[b.count]) return;
+  const int t = find_inst(b.lw_off, b.count, gw);
+  const Problem& pr = b.insts[t].pr;
+  const int wp = pr.wp, ns = kWave / wp;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = lane / wp, w = lane & (wp - 1);
+  const int64_t row = (gw - b.lw_off[t]) * ns + slot;
+  if (row >= pr.n) return;
+  const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
+  if (p1 - p0 > kSlotRowMax) return;
+  uint32_t acc = 0u;
+  int fl = 0;
+  int p = p0;
+  for (; p + 3 < p1; p += 4) {
+    const int k0 = pr.aci[p], k1 = pr.aci[p + 1], k2 = pr.aci[p + 2], k3 = pr.aci[p + 3];
+    const uint32_t x0 = pr.bbits[(int64_t)k0 * wp + w], x1 = pr.bbits[(int64_t)k1 * wp + w];
+    const uint32_t x2 = pr.bbits[(int64_t)k2 * wp + w], x3 = pr.bbits[(int64_t)k3 * wp + w];
+    acc |= (x0 | x1) | (x2 | x3);
+    fl += __popc(x0) + __popc(x1) + __popc(x2) + __popc(x3);
+  }
+  for (; p < p1; ++p) {
+    const uint32_t x = pr.bbits[(int64_t)pr.aci[p] * wp + w];
+    acc |= x;
+    fl += __popc(x);
+  }
+  for (int o = 1; o < wp; o <<= 1) fl += __shfl_xor(fl, o, kWave);
+  pr.cbits[row * wp + w] = acc;
+  if (w == 0) pr.flops[row] = fl;
+}
+
+// heavy rows and split chunks from the item list, one wavefront per item
+__global__ __launch_bounds__(kBlock) void k_b_symbolic(BatchDev b) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int total = b.ctr->sym_total;
+  for (int x = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); x < total; x += gridDim.x * kWavesPerBlock) {
+    const Item it = b.sym_items[x];
+    const Problem& pr = b.insts[b.sym_inst[x]].pr;
+    const int wp = pr.wp, ns = kWave / wp;
+    const int slot = lane / wp, w = lane & (wp - 1);
+    const bool split = (it.aux & kSplitFlag) != 0;
+    uint32_t acc = 0u;
+    int fl = 0;
+    for (int p = it.p0 + slot; p < it.p1; p += ns) {
+      const uint32_t v = pr.bbits[(int64_t)pr.aci[p] * wp + w];
+      acc |= v;
+      fl += __popc(v);
+    }
+    for (int o = wp; o < kWave; o <<= 1) acc |= shfl_xor_u32(acc, o);
+    const long long fsum = wave_sum_i64((long long)fl);
+    if (slot == 0) {
+      if (split) {
+        if (acc) atomicOr(&pr.cbits[(int64_t)it.row * wp + w], acc);
+      } else {
+        pr.cbits[(int64_t)it.row * wp + w] = acc;
+      }
+    }
+    if (lane == 0) {
+      if (split)
+        atomicAdd((unsigned long long*)&pr.flops[it.row], (unsigned long long)fsum);
+      else
+        pr.flops[it.row] = fsum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- counts and scans
+
+__global__ __launch_bounds__(kScanThreads) void k_b_count_rows(BatchDev b) {
+  __shared__ long long sh[32];
+  const int t = find_inst(b.sb_off, b.count, blockIdx.x);
+  const BInst& in = b.insts[t];
+  const Problem& pr = in.pr;
+  const int64_t base = (blockIdx.x - b.sb_off[t]) * (int64_t)kScanRows;
+  long long s = 0, f = 0;
+  for (int u = 0; u < kScanPer; ++u) {
+    const int64_t i = base + u * kScanThreads + threadIdx.x;
+    if (i < pr.n) {
+      int c = 0;
+      for (int w = 0; w < pr.wp; ++w) c += __popc(pr.cbits[i * pr.wp + w]);
+      in.cnt[i] = c;
+      s += c;
+      f += pr.flops[i];
+    }
+  }
+  long long tot, ftot;
+  block_exscan_1024(s, sh, &tot);
+  block_exscan_1024(f, sh, &ftot);
+  if (threadIdx.x == 0) {
+    b.block_sums[blockIdx.x] = tot;
+    b.block_sums[b.total_sb + blockIdx.x] = ftot;
+  }
+}
+
+// one workgroup: per-instance scans of the block sums, instance offsets in
+// the output pool, and the instances' output pointers
+__global__ __launch_bounds__(kScanThreads) void k_b_scan(BatchDev b) {
+  __shared__ long long sh[32];
+  long long pool = 0;
+  for (int t = 0; t < b.count; ++t) {
+    const int64_t b0 = b.sb_off[t], b1 = b.sb_off[t + 1];
+    long long carry = 0, fcarry = 0;
+    for (int64_t x0 = b0; x0 < b1; x0 += kScanThreads) {
+      const int64_t x = x0 + threadIdx.x;
+      const long long v = x < b1 ? b.block_sums[x] : 0;
+      const long long f = x < b1 ? b.block_sums[b.total_sb + x] : 0;
+      long long tot, ftot;
+      const long long ex = block_exscan_1024(v, sh, &tot);
+      block_exscan_1024(f, sh, &ftot);
+      if (x < b1) b.block_sums[x] = carry + ex;
+      carry += tot;
+      fcarry += ftot;
+    }
+    if (threadIdx.x == 0) {
+      BInst& in = b.insts[t];
+      b.c_off[t] = pool;
+      b.inst_flops[t] = fcarry;
+      in.pr.crp = b.c_rowptrs ? b.c_rowptrs + in.rp_off : nullptr;
+      in.pr.cci = b.pool_ci ? b.pool_ci + pool : nullptr;
+      in.pr.cval = b.pool_val ? (void*)(b.pool_val + pool) : nullptr;
+    }
+    pool += carry;
+  }
+  if (threadIdx.x == 0) {
+    b.c_off[b.count] = pool;
+    b.ctr->nnz_total = pool;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_b_write_rowptr(BatchDev b) {
+  __shared__ long long sh[32];
+  const int t = find_inst(b.sb_off, b.count, blockIdx.x);
+  const BInst& in = b.insts[t];
+  const int64_t n = in.pr.n;
+  int32_t* crp = b.c_rowptrs + in.rp_off;
+  const int64_t base = (blockIdx.x - b.sb_off[t]) * (int64_t)kScanRows;
+  long long carry = b.block_sums[blockIdx.x];
+  for (int u = 0; u < kScanPer; ++u) {
+    const int64_t i = base + u * kScanThreads + threadIdx.x;
+    const long long v = i < n ? in.cnt[i] : 0;
+    long long tot;
+    const long long ex = block_exscan_1024(v, sh, &tot);
+    if (i < n) crp[i] = (int32_t)(carry + ex);
+    if (i == n - 1) crp[n] = (int32_t)(carry + ex + v);
+    carry += tot;
+  }
+}
+
+// instances without rows still get rowptr[0] = 0
+__global__ void k_b_empty_rowptr(BatchDev b) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < b.count && b.insts[t].pr.n == 0) b.c_rowptrs[b.insts[t].rp_off] = 0;
+}
+
+// ---------------------------------------------------------------- numeric binning
+
+__global__ void k_b_num_bin_count(BatchDev b) {
+  __shared__ int32_t hist[kNumClasses * kBins];
+  for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x) hist[x] = 0;
+  __syncthreads();
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r < b.total_rows) {
+    const int t = find_inst(b.row_off, b.count, r);
+    const BInst& in = b.insts[t];
+    const int64_t i = r - b.row_off[t];
+    const int64_t f = in.pr.flops[i];
+    if (f > 0) {
+      const int cls = num_class(f, in.th);
+      if (cls == 0) {
+        const int m = in.pr.arp[i + 1] - in.pr.arp[i];
+        const int ce = chunk_entries(m, f, in.th.split);
+        atomicAdd(&hist[0], (m + ce - 1) / ce);
+      } else {
+        atomicAdd(&hist[cls * kBins + num_bin(f)], 1);
+      }
+    }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x)
+    if (hist[x]) atomicAdd(&(&b.ctr->num_count[0][0])[x], hist[x]);
+}
+
+__global__ void k_b_num_bin_scan(Counters* ctr) {
+  int32_t off = 0;
+  int32_t tot[kNumClasses] = {0, 0, 0, 0};
+  for (int c = 0; c < kNumClasses; ++c)
+    for (int x = 0; x < kBins; ++x) {
+      ctr->num_cursor[c][x] = off;
+      off += ctr->num_count[c][x];
+      tot[c] += ctr->num_count[c][x];
+    }
+  ctr->num_split_items = tot[0];
+  ctr->num_block_items = tot[1];
+  ctr->num_wave_rows = tot[2];
+  ctr->num_light_rows = tot[3];
+}
+
+__global__ void k_b_num_bin_fill(BatchDev b) {
+  __shared__ int32_t cnt[kNumClasses * kBins], base[kNumClasses * kBins];
+  __shared__ int32_t nsplit, split_base;
+  for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x) cnt[x] = 0;
+  if (threadIdx.x == 0) nsplit = 0;
+  __syncthreads();
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int t = 0, a = 0, m = 0, cls = 0, key = 0, count = 0, local = 0, ce = 0, slocal = 0;
+  int64_t i = 0;
+  if (r < b.total_rows) {
+    t = find_inst(b.row_off, b.count, r);
+    const BInst& in = b.insts[t];
+    i = r - b.row_off[t];
+    const int64_t f = in.pr.flops[i];
+    if (f > 0) {
+      a = in.pr.arp[i];
+      m = in.pr.arp[i + 1] - a;
+      cls = num_class(f, in.th);
+      if (cls == 0) {
+        ce = chunk_entries(m, f, in.th.split);
+        count = (m + ce - 1) / ce;
+        slocal = atomicAdd(&nsplit, 1);
+      } else {
+        count = 1;
+        key = cls * kBins + num_bin(f);
+      }
+      local = atomicAdd(&cnt[key], count);
+    }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x)
+    if (cnt[x]) base[x] = atomicAdd(&(&b.ctr->num_cursor[0][0])[x], cnt[x]);
+  if (threadIdx.x == 0 && nsplit) split_base = atomicAdd(&b.ctr->num_split_rows, nsplit);
+  __syncthreads();
+  if (count == 0) return;
+  const int pos = base[key] + local;
+  if (cls == 0) {
+    for (int c = 0; c < count; ++c) {
+      const int p0 = a + c * ce;
+      b.num_items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + ce), pos + c};
+      b.num_inst[pos + c] = t;
+    }
+    b.split_rows[split_base + slocal] = SplitRow{(int32_t)i, pos, count, t};
+  } else {
+    b.num_items[pos] = Item{(int32_t)i, a, a + m, cls == 1 ? kNoSlot : 0};
+    b.num_inst[pos] = t;
+  }
+}
+
+// ---------------------------------------------------------------- numeric
+
+// Workgroup items, then wavefront rows, each walked with a grid stride.
+template <int GL>
+__global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
+  using S = SemiringT<float>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* strips = (double*)smem;
+  int4* stage = (int4*)(smem + (size_t)kWavesPerBlock * b.dmax * sizeof(double));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int n_wg = b.ctr->num_split_items + b.ctr->num_block_items;
+  const int n_heavy = n_wg + b.ctr->num_wave_rows;
+  for (int g = blockIdx.x; g < n_wg; g += gridDim.x) {
+    const Item it = b.num_items[g];
+    const Problem& pr = b.insts[b.num_inst[g]].pr;
+    const int d = pr.d;
+    for (int j = threadIdx.x; j < kWavesPerBlock * d; j += kBlock) strips[j] = 0.0;
+    __syncthreads();
+    accumulate_range<GL, float>(pr, it.p0, it.p1, wave, kWavesPerBlock, strips + wave * d, stage + wave * kWave);
+    __syncthreads();
+    for (int j = threadIdx.x; j < d; j += kBlock)
+      strips[j] = S::add(S::add(S::add(strips[j], strips[d + j]), strips[2 * d + j]), strips[3 * d + j]);
+    __syncthreads();
+    if (it.aux != kNoSlot) {
+      double* dst = b.partial + (int64_t)it.aux * b.dmax;
+      for (int j = threadIdx.x; j < d; j += kBlock) dst[j] = strips[j];
+    } else {
+      emit_row<float>(pr, it.row, strips, wave, kWavesPerBlock);
+    }
+    __syncthreads();
+  }
+  const int n_groups = (b.ctr->num_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
+  double* strip = strips + wave * b.dmax;
+  for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
+    const int64_t x = (int64_t)n_wg + 4 * (int64_t)g + wave;
+    if (x < n_heavy) {
+      const Item it = b.num_items[x];
+      const Problem& pr = b.insts[b.num_inst[x]].pr;
+      for (int j = lane; j < pr.d; j += kWave) strip[j] = 0.0;
+      wave_sync();
+      accumulate_range<GL, float>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
+      wave_sync();
+      emit_row<float>(pr, it.row, strip, 0, 1);
+      wave_sync();
+    }
+  }
+}
+
+template <int GL>
+__global__ __launch_bounds__(kBlock) void k_b_numeric_light(BatchDev b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int G = kBlock / GL;
+  const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
+  double* strip = (double*)smem + grp * b.dmax;
+  const int first = b.ctr->num_split_items + b.ctr->num_block_items + b.ctr->num_wave_rows;
+  const int n_light = b.ctr->num_light_rows;
+  for (int64_t x = (int64_t)blockIdx.x * G + grp; x < n_light; x += (int64_t)gridDim.x * G) {
+    const Item it = b.num_items[first + x];
+    const Problem& pr = b.insts[b.num_inst[first + x]].pr;
+    for (int j = gl; j < pr.d; j += GL) strip[j] = 0.0;
+    wave_sync();
+    accumulate_light<GL, float>(pr, it.p0, it.p1, strip, gl);
+    wave_sync();
+    emit_group<GL, float>(pr, it.row, strip, gl);
+    wave_sync();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_split_finalize(BatchDev b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* strip = (double*)smem;
+  const int nrows = b.ctr->num_split_rows;
+  for (int r = blockIdx.x; r < nrows; r += gridDim.x) {
+    const SplitRow s = b.split_rows[r];
+    const Problem& pr = b.insts[s.pad].pr;
+    for (int j = threadIdx.x; j < pr.d; j += kBlock) {
+      double acc = 0.0;
+      for (int c = 0; c < s.count; ++c) acc += b.partial[(int64_t)(s.first + c) * b.dmax + j];
+      strip[j] = acc;
+    }
+    __syncthreads();
+    emit_row<float>(pr, s.row, strip, threadIdx.x >> 6, kWavesPerBlock);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+struct Batch {
+  int32_t count = 0, dmax = 1, gl = 32, lgl = 32;
+  std::vector<BInst> host_insts;
+  DevBuf insts, offs, work, sym_items, sym_inst, num_items, num_inst, split_rows, partial, block_sums, inst_flops,
+      ctr, tmp_rowptrs, tmp_off;
+  int64_t total_rows = 0, total_bm = 0, total_lw = 0, total_sb = 0, rowptr_total = 0;
+  int64_t sym_cap = 0, num_cap = 0, pool = 0;
+  BatchDev dev{};
+  Counters* host_ctr = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~Batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (host_ctr) (void)hipHostFree(host_ctr);
+  }
+};
+
+static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
+  BatchDev b = bt->dev;
+  k_b_zero<<<1, 256, 0, st>>>(b.ctr);
+  if (bt->total_bm > 0)
+    k_b_bitmap<<<(unsigned)bt->total_bm, 256, (size_t)(kBmRows + 1 + kBmRows * bitmap_words(bt->dmax)) * 4, st>>>(b);
+  const unsigned gr = grid_for(bt->total_rows, 256);
+  if (bt->total_rows > 0) k_b_sym_bin_count<<<gr, 256, 0, st>>>(b);
+  k_b_sym_bin_scan<<<1, 1, 0, st>>>(b.ctr);
+  if (bt->total_rows > 0) k_b_sym_bin_fill<<<gr, 256, 0, st>>>(b);
+  if (bt->sym_cap > 0) k_b_sym_split_zero<<<grid_for(bt->sym_cap, 256), 256, 0, st>>>(b);
+  if (bt->total_lw > 0) k_b_sym_light<<<grid_for(bt->total_lw, kWavesPerBlock), kBlock, 0, st>>>(b);
+  k_b_symbolic<<<2048, kBlock, 0, st>>>(b);
+  if (bt->total_sb > 0) k_b_count_rows<<<(unsigned)bt->total_sb, kScanThreads, 0, st>>>(b);
+  k_b_scan<<<1, kScanThreads, 0, st>>>(b);
+  if (bt->total_sb > 0) k_b_write_rowptr<<<(unsigned)bt->total_sb, kScanThreads, 0, st>>>(b);
+  k_b_empty_rowptr<<<grid_for(bt->count, 256), 256, 0, st>>>(b);
+  if (bt->total_rows > 0) k_b_num_bin_count<<<gr, 256, 0, st>>>(b);
+  k_b_num_bin_scan<<<1, 1, 0, st>>>(b.ctr);
+  if (bt->total_rows > 0) k_b_num_bin_fill<<<gr, 256, 0, st>>>(b);
+  TSS_CHECK_LAUNCH();
+  if (!numeric) return TSSPGEMM_OK;
+  const size_t lds = (size_t)kWavesPerBlock * bt->dmax * 8 + kWavesPerBlock * kWave * sizeof(int4);
+  const size_t llds = (size_t)(kBlock / bt->lgl) * bt->dmax * 8;
+#define TSS_BN(GLV)                                              \
+  case GLV:                                                      \
+    k_b_numeric<GLV><<<2048, kBlock, lds, st>>>(b);              \
+    break;
+#define TSS_BL(GLV)                                              \
+  case GLV:                                                      \
+    k_b_numeric_light<GLV><<<2048, kBlock, llds, st>>>(b);       \
+    break;
+  switch (bt->gl) {
+    TSS_BN(4) TSS_BN(8) TSS_BN(16) TSS_BN(32) TSS_BN(64)
+    default: set_error("batched: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  switch (bt->lgl) {
+    TSS_BL(4) TSS_BL(8) TSS_BL(16) TSS_BL(32) TSS_BL(64)
+    default: set_error("batched: bad light group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  }
+#undef TSS_BN
+#undef TSS_BL
+  k_b_split_finalize<<<1024, kBlock, (size_t)bt->dmax * 8, st>>>(b);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+int light_group_lanes(int group_lanes, int64_t d, int sr);
+
+static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr* Bs, const tsspgemm_tuning* tunes,
+                      Batch* bt, int64_t* pool_capacity, int64_t* rowptr_total, hipStream_t st) {
+  int rc;
+  if (count < 0 || (count > 0 && (!As || !Bs)) || !pool_capacity || !rowptr_total) {
+    set_error("batched_plan: bad arguments");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  bt->count = count;
+  std::vector<int64_t> row_off(count + 1, 0), bm_off(count + 1, 0), lw_off(count + 1, 0), sb_off(count + 1, 0);
+  int64_t ws_bytes = 0, sym_cap = 0, num_cap = 0, rp_total = 0;
+  std::vector<int64_t> ws_at(count);
+  int dmax = 1;
+  for (int t = 0; t < count; ++t) {
+    const tsspgemm_csr *A = &As[t], *B = &Bs[t];
+    if ((rc = check_csr(A, "A", true)) || (rc = check_csr(B, "B", true))) {
+      set_error("batched_plan: instance " + std::to_string(t) + ": " + get_error());
+      return rc;
+    }
+    if (A->nrows != A->ncols || B->nrows != A->ncols) {
+      set_error("batched_plan: instance " + std::to_string(t) + ": A must be n x n and B n x d");
+      return TSSPGEMM_ERR_INVALID_ARG;
+    }
+    if (B->ncols > kMaxDenseD) {
+      set_error("batched_plan: instance " + std::to_string(t) + ": d > 1024");
+      return TSSPGEMM_ERR_UNSUPPORTED;
+    }
+    const int64_t n = A->nrows;
+    const int wp = bitmap_words(B->ncols);
+    dmax = std::max<int>(dmax, (int)B->ncols);
+    row_off[t + 1] = row_off[t] + n;
+    bm_off[t + 1] = bm_off[t] + (n + kBmRows - 1) / kBmRows;
+    lw_off[t + 1] = lw_off[t] + (n + (kWave / wp) - 1) / (kWave / wp);
+    sb_off[t + 1] = sb_off[t] + (n + kScanRows - 1) / kScanRows;
+    ws_at[t] = ws_bytes;
+    ws_bytes += ((2 * n * wp * 4 + n * 8 + n * 4) + 255) / 256 * 256;
+    rp_total += n + 1;
+    tsspgemm_tuning tn;
+    resolve_tuning(tunes ? &tunes[t] : nullptr, B, &tn);
+    sym_cap += n + A->nnz / tn.sym_split_nnz + 2;
+    num_cap += 2 * n + A->nnz / 64 + 2;
+  }
+  bt->dmax = dmax;
+  {
+    // one group width for the batch: tunes[0] if given, else from the mean
+    // B row length over all instances
+    int64_t bn = 0, bnnz = 0;
+    for (int t = 0; t < count; ++t) {
+      bn += Bs[t].nrows;
+      bnnz += Bs[t].nnz;
+    }
+    const tsspgemm_csr mean_b{bn, dmax, bnnz, nullptr, nullptr, nullptr};
+    tsspgemm_tuning t0;
+    resolve_tuning(tunes ? &tunes[0] : nullptr, &mean_b, &t0);
+    bt->gl = t0.group_lanes;
+    bt->lgl = light_group_lanes(bt->gl, dmax, TSSPGEMM_PLUS_TIMES_F32);
+    bt->dev.sym_split = t0.sym_split_nnz;
+  }
+  bt->total_rows = row_off[count];
+  bt->total_bm = bm_off[count];
+  bt->total_lw = lw_off[count];
+  bt->total_sb = sb_off[count];
+  bt->rowptr_total = rp_total;
+  bt->sym_cap = sym_cap;
+  bt->num_cap = num_cap;
+  if ((rc = bt->insts.ensure(sizeof(BInst) * (count + 1))) || (rc = bt->offs.ensure(sizeof(int64_t) * 4 * (count + 1))) ||
+      (rc = bt->work.ensure((size_t)ws_bytes + 256)) || (rc = bt->sym_items.ensure(sizeof(Item) * (sym_cap + 1))) ||
+      (rc = bt->sym_inst.ensure(4 * (sym_cap + 1))) || (rc = bt->num_items.ensure(sizeof(Item) * (num_cap + 1))) ||
+      (rc = bt->num_inst.ensure(4 * (num_cap + 1))) ||
+      (rc = bt->split_rows.ensure(sizeof(SplitRow) * (bt->total_rows + 1))) ||
+      (rc = bt->block_sums.ensure(16 * (bt->total_sb + 1))) || (rc = bt->inst_flops.ensure(8 * (count + 1))) ||
+      (rc = bt->ctr.ensure(sizeof(Counters))) || (rc = bt->tmp_rowptrs.ensure(4 * (rp_total + 1))) ||
+      (rc = bt->tmp_off.ensure(8 * (count + 1))))
+    return rc;
+  TSS_HIP(hipHostMalloc((void**)&bt->host_ctr, sizeof(Counters), hipHostMallocDefault));
+  bt->host_insts.resize(count);
+  int64_t rp_off = 0;
+  for (int t = 0; t < count; ++t) {
+    const tsspgemm_csr *A = &As[t], *B = &Bs[t];
+    const int64_t n = A->nrows;
+    const int wp = bitmap_words(B->ncols);
+    char* base = (char*)bt->work.p + ws_at[t];
+    BInst& in = bt->host_insts[t];
+    in = BInst{};
+    in.pr.n = (int32_t)n;
+    in.pr.d = (int32_t)B->ncols;
+    in.pr.wp = wp;
+    in.pr.arp = A->rowptr;
+    in.pr.aci = A->colidx;
+    in.pr.aval = A->vals;
+    in.pr.brp = B->rowptr;
+    in.pr.bci = B->colidx;
+    in.pr.bval = B->vals;
+    in.pr.bbits = (const uint32_t*)base;
+    in.pr.cbits = (uint32_t*)(base + n * wp * 4);
+    in.pr.flops = (int64_t*)(base + 2 * n * wp * 4);
+    in.cnt = (int32_t*)(base + 2 * n * wp * 4 + n * 8);
+    tsspgemm_tuning tn;
+    resolve_tuning(tunes ? &tunes[t] : nullptr, B, &tn);
+    in.th = NumThresholds{tn.light_max_flops, tn.wave_max_flops, tn.split_flops};
+    in.rp_off = rp_off;
+    rp_off += n + 1;
+  }
+  int64_t* offs = (int64_t*)bt->offs.p;
+  TSS_HIP(hipMemcpyAsync(bt->insts.p, bt->host_insts.data(), sizeof(BInst) * count, hipMemcpyHostToDevice, st));
+  TSS_HIP(hipMemcpyAsync(offs, row_off.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  TSS_HIP(hipMemcpyAsync(offs + (count + 1), bm_off.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  TSS_HIP(hipMemcpyAsync(offs + 2 * (count + 1), lw_off.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  TSS_HIP(hipMemcpyAsync(offs + 3 * (count + 1), sb_off.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  BatchDev& b = bt->dev;
+  b.insts = (BInst*)bt->insts.p;
+  b.count = count;
+  b.dmax = dmax;
+  b.row_off = offs;
+  b.bm_off = offs + (count + 1);
+  b.lw_off = offs + 2 * (count + 1);
+  b.sb_off = offs + 3 * (count + 1);
+  b.total_rows = bt->total_rows;
+  b.total_sb = bt->total_sb;
+  b.sym_items = (Item*)bt->sym_items.p;
+  b.sym_inst = (int32_t*)bt->sym_inst.p;
+  b.num_items = (Item*)bt->num_items.p;
+  b.num_inst = (int32_t*)bt->num_inst.p;
+  b.split_rows = (SplitRow*)bt->split_rows.p;
+  b.block_sums = (int64_t*)bt->block_sums.p;
+  b.inst_flops = (int64_t*)bt->inst_flops.p;
+  b.ctr = (Counters*)bt->ctr.p;
+  // a symbolic pass at plan time sizes the output pool and the split slots
+  b.c_rowptrs = (int32_t*)bt->tmp_rowptrs.p;
+  b.pool_ci = nullptr;
+  b.pool_val = nullptr;
+  b.c_off = (int64_t*)bt->tmp_off.p;
+  b.partial = nullptr;
+  if ((rc = enqueue_run(bt, st, false))) return rc;
+  TSS_HIP(hipMemcpyAsync(bt->host_ctr, b.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  TSS_HIP(hipStreamSynchronize(st));
+  bt->pool = bt->host_ctr->nnz_total;
+  if ((rc = bt->partial.ensure((size_t)(bt->host_ctr->num_split_items + 1) * dmax * 8))) return rc;
+  b.partial = (double*)bt->partial.p;
+  *pool_capacity = bt->pool;
+  *rowptr_total = rp_total;
+  return TSSPGEMM_OK;
+}
+
+static int batch_bind(Batch* bt, int32_t* c_rowptrs, int32_t* pool_colidx, float* pool_vals, int64_t* c_offsets) {
+  if (!bt || !c_rowptrs || !c_offsets || (bt->pool > 0 && (!pool_colidx || !pool_vals))) {
+    set_error("batched_run: NULL argument");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  bt->dev.c_rowptrs = c_rowptrs;
+  bt->dev.pool_ci = pool_colidx;
+  bt->dev.pool_val = pool_vals;
+  bt->dev.c_off = c_offsets;
+  return TSSPGEMM_OK;
+}
+
+}  // namespace tss
+
+using namespace tss;
+
+extern "C" {
+
+int tsspgemm_batched_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr* Bs, const tsspgemm_tuning* tune,
+                          tsspgemm_batch* out, int64_t* pool_capacity, int64_t* rowptr_total, void* stream) {
+  try {
+    if (!out) {
+      set_error("batched_plan: out is NULL");
+      return TSSPGEMM_ERR_INVALID_ARG;
+    }
+    Batch* bt = new (std::nothrow) Batch();
+    if (!bt) {
+      set_error("out of host memory");
+      return TSSPGEMM_ERR_NOMEM;
+    }
+    int rc = batch_plan(count, As, Bs, tune, bt, pool_capacity, rowptr_total, (hipStream_t)stream);
+    if (rc) {
+      delete bt;
+      *out = nullptr;
+      return rc;
+    }
+    *out = (tsspgemm_batch)bt;
+    return TSSPGEMM_OK;
+  } catch (...) {
+    set_error("unexpected C++ exception");
+    return TSSPGEMM_ERR_HIP;
+  }
+}
+
+int tsspgemm_batched_run(tsspgemm_batch batch, int32_t* c_rowptrs, int32_t* pool_colidx, float* pool_vals,
+                         int64_t* c_offsets, void* stream) {
+  Batch* bt = (Batch*)batch;
+  int rc = batch_bind(bt, c_rowptrs, pool_colidx, pool_vals, c_offsets);
+  if (rc) return rc;
+  return enqueue_run(bt, (hipStream_t)stream, true);
+}
+
+int tsspgemm_batched_capture(tsspgemm_batch batch, int32_t* c_rowptrs, int32_t* pool_colidx, float* pool_vals,
+                             int64_t* c_offsets) {
+  Batch* bt = (Batch*)batch;
+  int rc = batch_bind(bt, c_rowptrs, pool_colidx, pool_vals, c_offsets);
+  if (rc) return rc;
+  if (bt->exec) {
+    (void)hipGraphExecDestroy(bt->exec);
+    bt->exec = nullptr;
+  }
+  if (bt->graph) {
+    (void)hipGraphDestroy(bt->graph);
+    bt->graph = nullptr;
+  }
+  if (!bt->cap_stream) TSS_HIP(hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking));
+  TSS_HIP(hipStreamBeginCapture(bt->cap_stream, hipStreamCaptureModeThreadLocal));
+  rc = enqueue_run(bt, bt->cap_stream, true);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(bt->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    return TSSPGEMM_ERR_HIP;
+  }
+  bt->graph = g;
+  TSS_HIP(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+  return TSSPGEMM_OK;
+}
+
+int tsspgemm_batched_launch(tsspgemm_batch batch, void* stream) {
+  Batch* bt = (Batch*)batch;
+  if (!bt || !bt->exec) {
+    set_error("batched_launch: no captured graph (call tsspgemm_batched_capture first)");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  TSS_HIP(hipGraphLaunch(bt->exec, (hipStream_t)stream));
+  return TSSPGEMM_OK;
+}
+
+int tsspgemm_batched_flops(tsspgemm_batch batch, int64_t* flops_host) {
+  Batch* bt = (Batch*)batch;
+  if (!bt || !flops_host) {
+    set_error("batched_flops: NULL argument");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (bt->count > 0)
+    TSS_HIP(hipMemcpy(flops_host, bt->inst_flops.p, 8 * bt->count, hipMemcpyDeviceToHost));
+  return TSSPGEMM_OK;
+}
+
+void tsspgemm_batched_destroy(tsspgemm_batch batch) { delete (Batch*)batch; }
+
+}  // extern "C"

@@ -24,123 +24,9 @@
 // Output: the row's pattern is already known as a bitmap (symbolic phase);
 // a lane owns column j of a chunk, and its output slot is the popcount of the
 // set bits below it, so columns come out sorted without a sort.
-#include "core.hpp"
+#include "dev_numeric.hpp"
 
 namespace tss {
-
-template <typename T>
-struct SemiringT;
-template <>
-struct SemiringT<float> {  // plus-times over FP32 inputs, FP64 accumulation
-  using acc = double;
-  __device__ static acc prod(float a, float b) { return (double)a * (double)b; }
-  __device__ static float out(acc x) { return (float)x; }
-  __device__ static acc add(acc x, acc y) { return x + y; }
-};
-template <>
-struct SemiringT<int32_t> {  // plus-times over int32, wrap-around
-  using acc = int32_t;
-  __device__ static acc prod(int32_t a, int32_t b) { return (int32_t)((uint32_t)a * (uint32_t)b); }
-  __device__ static int32_t out(acc x) { return x; }
-  __device__ static acc add(acc x, acc y) { return (int32_t)((uint32_t)x + (uint32_t)y); }
-};
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void lds_add(double* p, double v) { atomicAdd(p, v); }
-__device__ __forceinline__ void lds_add(int32_t* p, int32_t v) { atomicAdd((unsigned int*)p, (unsigned int)v); }
-
-constexpr int kHeavyUnroll = 4;  // A entries per group per step, wavefront / workgroup rows
-constexpr int kLightUnroll = 4;  // A entries per group per step, light rows
-
-// ---------------------------------------------------------------- wavefront / workgroup rows
-
-// Accumulate entries [p_begin, p_end) of one A row into `strip`, taking
-// 64-entry batches number wstart, wstart + wstride, ... (one wavefront).
-template <int GL, typename T>
-__device__ __forceinline__ void accumulate_range(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
-                                                 typename SemiringT<T>::acc* strip, int4* stage) {
-  using S = SemiringT<T>;
-  constexpr int GPW = kWave / GL;
-  constexpr int U = kHeavyUnroll;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int grp = lane / GL, gl = lane % GL;
-  const int32_t* __restrict__ aci = pr.aci;
-  const T* __restrict__ aval = (const T*)pr.aval;
-  const int32_t* __restrict__ brp = pr.brp;
-  const int32_t* __restrict__ bci = pr.bci;
-  const T* __restrict__ bval = (const T*)pr.bval;
-
-  for (int base = p_begin + kWave * wstart; base < p_end; base += kWave * wstride) {
-    const int nb = min(kWave, p_end - base);
-    int4 e = make_int4(0, 0, 0, 0);
-    if (lane < nb) {
-      const int k = aci[base + lane];
-      T a = aval[base + lane];
-      e.x = brp[k];
-      e.y = brp[k + 1];
-      e.z = __builtin_bit_cast(int32_t, a);
-    }
-    wave_sync();
-    stage[lane] = e;
-    wave_sync();
-    for (int s = 0; s < nb; s += U * GPW) {
-      int q[U], qe[U], jj[U];
-      T av[U], bv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int src = s + u * GPW + grp;
-        int4 r = make_int4(0, 0, 0, 0);
-        if (src < nb) r = stage[src];
-        q[u] = r.x + gl;
-        qe[u] = r.y;
-        av[u] = __builtin_bit_cast(T, r.z);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (q[u] < qe[u]) {
-          jj[u] = bci[q[u]];
-          bv[u] = bval[q[u]];
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (q[u] < qe[u]) lds_add(&strip[jj[u]], S::prod(av[u], bv[u]));
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        for (int qq = q[u] + GL; qq < qe[u]; qq += GL) lds_add(&strip[bci[qq]], S::prod(av[u], bval[qq]));
-    }
-    wave_sync();
-  }
-}
-
-// Write row `row` of C from a strip: wavefront `wave_id` of `nwaves` handles
-// 64-column chunks wave_id, wave_id + nwaves, ...
-template <typename T>
-__device__ __forceinline__ void emit_row(const Problem& pr, int64_t row, const typename SemiringT<T>::acc* strip,
-                                         int wave_id, int nwaves) {
-  using S = SemiringT<T>;
-  const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t* cb = pr.cbits + row * pr.wp;
-  const int nch = (pr.d + 63) >> 6;
-  int base = pr.crp[row];
-  for (int w = 0; w < 2 * wave_id && w < pr.wp; ++w) base += __popc(cb[w]);
-  for (int c = wave_id; c < nch; c += nwaves) {
-    const uint32_t lo = cb[2 * c];
-    const uint32_t hi = (2 * c + 1 < pr.wp) ? cb[2 * c + 1] : 0u;
-    const uint64_t m = (uint64_t)lo | ((uint64_t)hi << 32);
-    if ((m >> lane) & 1ull) {
-      const int pos = base + lanes_below(m);
-      const int j = 64 * c + lane;
-      pr.cci[pos] = j;
-      ((T*)pr.cval)[pos] = S::out(strip[j]);
-    }
-    for (int w = 2 * c; w < 2 * (c + nwaves) && w < pr.wp; ++w) base += __popc(cb[w]);
-  }
-}
 
 template <int GL, typename T>
 __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
@@ -195,89 +81,22 @@ __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   }
 }
 
-// ---------------------------------------------------------------- light rows
-
-// Write row `row` from a group's strip; the group's GL lanes handle GL-column
-// chunks in order (GL <= 64, a power of two, so a chunk never straddles a
-// 64-bit pair of bitmap words).
-template <int GL, typename T>
-__device__ __forceinline__ void emit_group(const Problem& pr, int64_t row, const typename SemiringT<T>::acc* strip,
-                                           int gl) {
-  using S = SemiringT<T>;
-  const uint32_t* cb = pr.cbits + row * pr.wp;
-  int base = pr.crp[row];
-  const uint64_t below = (gl == 0) ? 0ull : ((~0ull) >> (64 - gl));
-  for (int c0 = 0; c0 < pr.d; c0 += GL) {
-    uint64_t m;
-    if constexpr (GL == 64) {
-      const int w = c0 >> 5;
-      m = (uint64_t)cb[w] | ((w + 1 < pr.wp) ? ((uint64_t)cb[w + 1] << 32) : 0ull);
-    } else {
-      m = ((uint64_t)cb[c0 >> 5] >> (c0 & 31)) & ((1ull << GL) - 1ull);
-    }
-    if ((m >> gl) & 1ull) {
-      const int pos = base + __popcll(m & below);
-      const int j = c0 + gl;
-      pr.cci[pos] = j;
-      ((T*)pr.cval)[pos] = S::out(strip[j]);
-    }
-    base += __popcll(m);
-  }
-}
-
 template <int GL, typename T>
 __global__ __launch_bounds__(kBlock) void k_numeric_light(NumParams np) {
-  using S = SemiringT<T>;
-  using Acc = typename S::acc;
+  using Acc = typename SemiringT<T>::acc;
   constexpr int G = kBlock / GL;  // rows in flight per workgroup
-  constexpr int U = kLightUnroll;
   extern __shared__ __align__(16) unsigned char smem[];
   const Problem& pr = np.pr;
   const int d = pr.d;
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
   Acc* strip = (Acc*)smem + grp * d;
-  const int32_t* __restrict__ aci = pr.aci;
-  const T* __restrict__ aval = (const T*)pr.aval;
-  const int32_t* __restrict__ brp = pr.brp;
-  const int32_t* __restrict__ bci = pr.bci;
-  const T* __restrict__ bval = (const T*)pr.bval;
   const Item* items = np.items + np.n_heavy_records;
   const int64_t stride = (int64_t)gridDim.x * G;
   for (int64_t t = (int64_t)blockIdx.x * G + grp; t < np.n_light; t += stride) {
     const Item it = items[t];
     for (int j = gl; j < d; j += GL) strip[j] = Acc(0);
     wave_sync();
-    for (int p = it.p0; p < it.p1; p += U) {
-      int k[U], q[U], qe[U], jj[U];
-      T av[U], bv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const bool v = p + u < it.p1;
-        k[u] = v ? aci[p + u] : -1;
-        av[u] = v ? aval[p + u] : T(0);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        q[u] = 0;
-        qe[u] = 0;
-        if (k[u] >= 0) {
-          q[u] = brp[k[u]] + gl;
-          qe[u] = brp[k[u] + 1];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (q[u] < qe[u]) {
-          jj[u] = bci[q[u]];
-          bv[u] = bval[q[u]];
-        }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (q[u] < qe[u]) lds_add(&strip[jj[u]], S::prod(av[u], bv[u]));
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        for (int qq = q[u] + GL; qq < qe[u]; qq += GL) lds_add(&strip[bci[qq]], S::prod(av[u], bval[qq]));
-    }
+    accumulate_light<GL, T>(pr, it.p0, it.p1, strip, gl);
     wave_sync();
     emit_group<GL, T>(pr, it.row, strip, gl);
     wave_sync();
@@ -420,26 +239,6 @@ int launch_emit_pattern(const Problem& pr, hipStream_t st) {
   k_emit_pattern<<<grid_for(lanes, 256), 256, 0, st>>>(pr);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
-}
-
-// ================================================================ binning (numeric)
-
-// Work class by product count: 3 = light (a lane group), 2 = one wavefront,
-// 1 = one workgroup, 0 = split into chunks of at least kMinChunk A entries.
-constexpr int kMinChunk = 64;
-
-__device__ __forceinline__ int num_class(int64_t f, const NumThresholds& th) {
-  return f <= th.light_max ? 3 : (f <= th.wave_max ? 2 : (f <= th.split ? 1 : 0));
-}
-__device__ __forceinline__ int num_bin(int64_t work) {
-  const int e = 63 - __clzll((unsigned long long)work);
-  const int b = kBins - 1 - e;
-  return b < 0 ? 0 : b;
-}
-__device__ __forceinline__ int chunk_entries(int m, int64_t f, int64_t split) {
-  const int64_t want = (f + split - 1) / split;  // chunks by products
-  int ce = (int)((m + want - 1) / want);
-  return ce < kMinChunk ? kMinChunk : ce;
 }
 
 __global__ void k_num_bin_count(Problem pr, NumThresholds th, Counters* ctr) {

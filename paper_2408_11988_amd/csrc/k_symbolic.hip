@@ -9,7 +9,7 @@
 // Also here: the B-pattern bitmap build, the work binning of rows by A-row
 // length, and the popcount + exclusive scan that turns C's bitmaps into
 // C's row pointers.
-#include "core.hpp"
+#include "dev_symbolic.hpp"
 
 namespace tss {
 
@@ -45,40 +45,11 @@ int launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
   return TSSPGEMM_OK;
 }
 
-// CSR pattern -> bitmap rows. A workgroup owns kBmRows consecutive rows: it
-// stages their row pointers and an all-zero bitmap in LDS, streams the rows'
-// entries with consecutive threads on consecutive entries (coalesced), finds
-// each entry's row by binary search over the staged pointers, sets the bit
-// with an LDS atomicOr, and writes the finished bitmap rows out contiguously.
-constexpr int kBmRows = 256;
-
 __global__ __launch_bounds__(256) void k_csr_to_bitmap(int64_t n, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci, int wp,
                                                        uint32_t* __restrict__ bits) {
   extern __shared__ __align__(16) uint32_t sm[];
-  int32_t* srp = (int32_t*)sm;
-  uint32_t* sb = sm + kBmRows + 1;
-  const int64_t r0 = (int64_t)blockIdx.x * kBmRows;
-  const int nr = (int)min((int64_t)kBmRows, n - r0);
-  for (int t = threadIdx.x; t <= nr; t += blockDim.x) srp[t] = rp[r0 + t];
-  for (int t = threadIdx.x; t < nr * wp; t += blockDim.x) sb[t] = 0u;
-  __syncthreads();
-  const int q0 = srp[0], q1 = srp[nr];
-  for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
-    const int j = ci[q];
-    int lo = 0, hi = nr;  // srp[lo] <= q < srp[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (srp[mid] <= q)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    atomicOr(&sb[lo * wp + (j >> 5)], 1u << (j & 31));
-  }
-  __syncthreads();
-  uint32_t* out = bits + r0 * wp;
-  for (int t = threadIdx.x; t < nr * wp; t += blockDim.x) out[t] = sb[t];
+  bitmap_block(n, rp, ci, wp, bits, (int64_t)blockIdx.x * kBmRows, sm);
 }
 
 int launch_csr_to_bitmap(int64_t n, const int32_t* rp, const int32_t* ci, int wp, uint32_t* bits, hipStream_t st) {
@@ -139,34 +110,6 @@ int launch_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t
 }
 
 // ================================================================ binning (symbolic)
-
-// Rows with at most kSlotRowMax A entries ("light" rows, the bulk of a
-// power-law graph) are processed straight from the row index, one row per
-// slot of wp lanes. Heavier rows are binned into an item list (heaviest
-// first) and take a whole wavefront, or several when split.
-constexpr int kSlotRowMax = 32;
-
-// Work class of a row with m > 0 entries: floor(log2 m) mapped so that heavier
-// rows get smaller bin numbers; bin 0 holds the chunks of split rows.
-__device__ __forceinline__ int bin_of(int64_t work) {
-  const int e = 63 - __clzll((unsigned long long)work);
-  const int b = kBins - 1 - e;
-  return b < 1 ? 1 : b;
-}
-
-// bin and item count of row i in the heavy-row list (count 0: not listed)
-__device__ __forceinline__ void sym_bin(int m, int32_t split_nnz, int& bin, int& count) {
-  if (m <= kSlotRowMax) {
-    bin = 0;
-    count = 0;
-  } else if (m <= split_nnz) {
-    bin = bin_of(m);
-    count = 1;
-  } else {
-    bin = 0;
-    count = (m + split_nnz - 1) / split_nnz;
-  }
-}
 
 __global__ void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
   __shared__ int32_t hist[kBins];
@@ -434,39 +377,7 @@ int launch_sym_split_mask(const Problem& pr, const Item* items, const uint32_t* 
 
 // ================================================================ count + scan
 
-constexpr int kScanThreads = 1024;
-constexpr int kScanPer = 4;
-constexpr int kScanRows = kScanThreads * kScanPer;
-
 int64_t scan_block_sums_capacity(int64_t n) { return 2 * ((n + kScanRows - 1) / kScanRows + 1); }
-
-// exclusive scan of v over the 1024 threads of the block; returns the prefix,
-// total in *tot. Uses a 16-entry shared array.
-__device__ __forceinline__ long long block_exscan_1024(long long v, long long* sh, long long* tot) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  long long x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    long long y = __shfl_up(x, o, kWave);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wave] = x;
-  __syncthreads();
-  if (wave == 0) {
-    long long s = lane < 16 ? sh[lane] : 0;
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) {
-      long long y = __shfl_up(s, o, kWave);
-      if (lane >= o) s += y;
-    }
-    if (lane < 16) sh[16 + lane] = s;  // inclusive prefix of wave totals
-  }
-  __syncthreads();
-  const long long before = wave ? sh[16 + wave - 1] : 0;
-  *tot = sh[16 + 15];
-  __syncthreads();
-  return before + x - v;
-}
 
 // Per block of rows: popcount of each C bitmap row (nnz of the row) and the
 // block totals of nnz and of products; block_sums holds nb nnz totals

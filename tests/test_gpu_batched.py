@@ -1,0 +1,153 @@
+"""Batched TS-SpGEMM: per instance bit-identical to the plain call with the
+same tuning, parity with the oracle, HIP-graph replays, and the autotuner
+(whose choices must not change any result)."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests._util import random_csr
+from tests.gpu_util import compare_f32, note, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _instances(seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    shapes = [(300, 64, 0.03, 0.1), (1, 5, 1.0, 0.5), (2000, 128, 0.004, 0.2), (0, 16, 0, 0), (500, 1024, 0.01, 0.01),
+              (700, 33, 0.02, 0.3), (400, 1, 0.05, 0.5), (900, 200, 0.006, 0.05)]
+    for n, d, pa, pb in shapes:
+        if n == 0:
+            a = synth.Csr(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+            b = synth.Csr(0, d, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+        else:
+            a = random_csr(rng, n, n, pa, empty_rows=0.2, dense_rows=1 if n > 10 else 0)
+            b = random_csr(rng, n, d, pb, empty_rows=0.1)
+        out.append((a, b))
+    # an instance whose A is empty
+    b = random_csr(rng, 50, 40, 0.2)
+    out.append((synth.Csr(50, 50, np.zeros(51, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32)), b))
+    return out
+
+
+def _same(c1, c2):
+    for x, y in zip(c1.to_host(), c2.to_host()):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("tuned", [False, True])
+def test_batched_matches_plain_and_oracle(tuned):
+    import paper_2408_11988_amd as tss
+    from paper_2408_11988_amd.batched import Batched
+
+    host = _instances()
+    pairs = [(to_dev(a), to_dev(b)) for a, b in host]
+    tunings = None
+    if tuned:  # forces every work class somewhere in the batch
+        tunings = [dict(group_lanes=16, light_max_flops=64, wave_max_flops=512, split_flops=2048) for _ in host]
+    note(f"batched {len(pairs)} instances tuned={tuned}")
+    bt = Batched(pairs, tunings)
+    bt.run()
+    torch.cuda.synchronize()
+    outs = bt.outputs()
+    assert bt.c_offsets[-1].item() == bt.pool
+    for t, ((a, b), (A, B), C) in enumerate(zip(host, pairs, outs)):
+        plain = tss.spgemm(A, B, tuning=tunings[t] if tunings else dict(group_lanes=bt_group_lanes(pairs)))
+        _same(C, plain)
+        if a.nrows:
+            compare_f32(a, b, C)
+        assert bt.flops()[t] == int(oracle.row_flops(a.rp, a.ci, b.rp).sum()) if a.nrows else bt.flops()[t] == 0
+
+
+def bt_group_lanes(pairs):
+    """Group width the batch picks without a tuning: from the mean B row length."""
+    nn = sum(B.nrows for _, B in pairs)
+    nz = sum(B.nnz for _, B in pairs)
+    mean = nz / nn if nn else 0
+    gl = 4
+    while gl < 64 and gl < mean:
+        gl *= 2
+    return gl
+
+
+def test_graph_replays():
+    import paper_2408_11988_amd as tss
+    from paper_2408_11988_amd.batched import Batched
+
+    host = _instances(1)
+    pairs = [(to_dev(a), to_dev(b)) for a, b in host]
+    tun = [dict(group_lanes=32) for _ in host]
+    bt = Batched(pairs, tun)
+    bt.run()
+    torch.cuda.synchronize()
+    eager = [tuple(x.copy() for x in c.to_host()) for c in bt.outputs()]
+    note("capture")
+    bt.capture()
+    rng = np.random.default_rng(3)
+    for rep in range(4):
+        # unrelated eager work and a synchronisation between replays
+        x = torch.randn(512, 512, device="cuda")
+        (x @ x).sum().item()
+        note(f"replay {rep}")
+        bt.replay()
+        torch.cuda.synchronize()
+        for e, c in zip(eager, bt.outputs()):
+            for u, v in zip(e, c.to_host()):
+                assert np.array_equal(u, v)
+    # new B values (same buffers): a replay recomputes them
+    for (_, B), (a, b) in zip(pairs, host):
+        if B.nnz:
+            B.vals.copy_(torch.from_numpy(rng.random(B.nnz).astype(np.float32)))
+    bt.replay()
+    torch.cuda.synchronize()
+    for t, ((A, B), C) in enumerate(zip(pairs, bt.outputs())):
+        _same(C, tss.spgemm(A, B, tuning=tun[t]))
+
+
+def test_batched_workload_64_instances():
+    import paper_2408_11988_amd as tss
+    from paper_2408_11988_amd.batched import Batched
+
+    params = synth.batched_params()
+    host = [synth.batched_instance(p) for p in params]
+    note(f"64-instance workload: sum n = {sum(a.nrows for a, _ in host)}, sum nnzA = {sum(a.nnz for a, _ in host)}")
+    pairs = [(to_dev(a), to_dev(b)) for a, b in host]
+    bt = Batched(pairs)
+    bt.run()
+    torch.cuda.synchronize()
+    outs = bt.outputs()
+    gl = bt_group_lanes(pairs)
+    for (A, B), C in zip(pairs, outs):
+        _same(C, tss.spgemm(A, B, tuning=dict(group_lanes=gl)))
+    small = np.argsort([a.nnz for a, _ in host])[:4]
+    for t in small:
+        note(f"oracle on instance {t}")
+        compare_f32(host[t][0], host[t][1], outs[t], threads=16)
+
+
+def test_autotuner_does_not_change_results(tmp_path):
+    import paper_2408_11988_amd as tss
+    from paper_2408_11988_amd.autotune import Autotuner
+
+    a, b = synth.workload_rmat_plain(scale=14, d=64)
+    A, B = to_dev(a), to_dev(b)
+    path = tmp_path / "tune.json"
+    at = Autotuner(str(path))
+    note("autotune R-MAT 14")
+    best = at.tune(A, B, reps=2)
+    at.save()
+    assert json.load(open(path))
+    ref = tss.spgemm(A, B)
+    got = tss.spgemm(A, B, tuning={k: v for k, v in best.items() if k != "ms"})
+    _same(ref, got)
+    again = Autotuner(str(path)).tune(A, B, reps=2)  # cached
+    assert {k: v for k, v in again.items()} == best
