@@ -6,7 +6,13 @@ sync for nnz(C); numeric phase: the LDS dense-strip kernel) over the R-MAT
 scale-20 (edge factor 16) x (n x 128, Poisson(25.6) entries per row) workload,
 all inputs resident in HBM. Prints one JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--scale S]
+The same line carries three further measurements of the path (skipped with
+--no-extras): the differentiable layer (numeric forward plus dL/dA and dL/dB on
+R-MAT scale 20 x n x 256 Normal values), the batched run of 64 mixed instances
+replayed from one HIP graph against the same 64 products as plain calls, and
+multi-source BFS (Algorithm 3) from 512 sources on R-MAT scale 22.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras] [--scale S]
 """
 from __future__ import annotations
 
@@ -30,7 +36,7 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("k_numeric.hip", "core.hpp", "common.hpp"):
+    for f in ("k_numeric.hip", "dev_numeric.hpp", "core.hpp", "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2408_11988_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -98,6 +104,161 @@ def cpu_baseline(a, b, flops_rows, target_s=12.0):
             "sample": f"{sample}; {fl} multiplications in {t:.2f} s (ordered-map Gustavson, FP64)"}
 
 
+def _events(n):
+    import torch
+
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def bench_fwd_bwd(steps: int, warmup: int) -> dict:
+    """Differentiable layer: R-MAT scale 20 x B n x 256 (5%, N(0,1)), loss sum(C o W).
+    Forward = numeric phase on the cached plan; backward = dL/dA + dL/dB (A^T cached)."""
+    import torch
+
+    import synth
+    from paper_2408_11988_amd import DeviceCsr, TSSpGEMMOp
+
+    log("fwd+bwd: generating R-MAT 20 x d=256 (5%)")
+    a, b = synth.workload_embedding(scale=20, d=256, density=0.05)
+    A, B = DeviceCsr.from_host(a), DeviceCsr.from_host(b)
+    op = TSSpGEMMOp(A, B)
+    op.transpose()
+    flops = op.plan.stats()["flops"]
+    av = A.vals.clone().requires_grad_(True)
+    bv = B.vals.clone().requires_grad_(True)
+    c = op(av, bv)
+    w = torch.randn(c.numel(), device="cuda", generator=torch.Generator("cuda").manual_seed(7))
+    for _ in range(warmup):
+        av.grad = bv.grad = None
+        (op(av, bv) * w).sum().backward()
+    torch.cuda.synchronize()
+    ef, eb = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e = _events(3)
+        av.grad = bv.grad = None
+        e[0].record()
+        c = op(av, bv)
+        e[1].record()
+        (c * w).sum().backward()
+        e[2].record()
+        ef.append(e)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    ms_f = sum(x[0].elapsed_time(x[1]) for x in ef) / steps
+    ms_b = sum(x[1].elapsed_time(x[2]) for x in ef) / steps
+    return {"workload": "R-MAT scale 20 x B n x 256 Bernoulli(0.05) N(0,1), loss sum(C o W)",
+            "flops_fwd": flops, "nnz_c": op.nnz, "ms_fwd": round(ms_f, 4), "ms_bwd": round(ms_b, 4),
+            "ms_fwd_bwd": round(ms_step, 4), "gflops_fwd": round(2 * flops / ms_f / 1e6, 2),
+            "gflops_bwd": round(2 * 2 * flops / ms_b / 1e6, 2),
+            "gflops_fwd_bwd": round(2 * 3 * flops / ms_step / 1e6, 2),
+            "note": "bwd = dL/dA (SDDMM on pat(A)) + dL/dB (A^T G sampled on pat(B)), each as many products as fwd;"
+                    " ms_bwd includes the loss reduction"}
+
+
+def bench_batched(steps: int, warmup: int) -> dict:
+    """64 instances (n log-uniform in [2^14, 2^18], d in {32..256}, ER or R-MAT,
+    B density log-uniform in [1%, 50%]): one graph replay vs 64 plain calls."""
+    import tempfile
+
+    import torch
+
+    import synth
+    from paper_2408_11988_amd import DeviceCsr, spgemm
+    from paper_2408_11988_amd.autotune import Autotuner
+    from paper_2408_11988_amd.batched import Batched
+
+    log("batched: generating 64 instances")
+    host = [synth.batched_instance(p) for p in synth.batched_params()]
+    pairs = [(DeviceCsr.from_host(a), DeviceCsr.from_host(b)) for a, b in host]
+    t0 = time.perf_counter()
+    tuner = Autotuner(os.path.join(tempfile.gettempdir(), "tsspgemm_autotune_bench.json"))
+    tunings = tuner.tune_batch(pairs, reps=2)
+    tuner.save()
+    t_tune = time.perf_counter() - t0
+    clean = [{k: v for k, v in t.items() if k != "ms"} for t in tunings]
+    bt = Batched(pairs, clean)
+    bt.capture()
+    for _ in range(warmup):
+        bt.replay()
+    torch.cuda.synchronize()
+    e = _events(2)
+    e[0].record()
+    for _ in range(steps):
+        bt.replay()
+    e[1].record()
+    torch.cuda.synchronize()
+    ms_graph = e[0].elapsed_time(e[1]) / steps
+    flops = sum(bt.flops())
+    # the same 64 products as plain calls, one after the other (each synchronizes for nnz)
+    for _ in range(warmup):
+        for (A, B), t in zip(pairs, clean):
+            spgemm(A, B, tuning=t)
+    torch.cuda.synchronize()
+    reps = max(1, steps // 4)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for (A, B), t in zip(pairs, clean):
+            spgemm(A, B, tuning=t)
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3 / reps
+    return {"workload": "64 instances: n log-uniform [2^14, 2^18], d in {32,64,128,256}, ER/R-MAT (deg 4-32), "
+                        "B density log-uniform [1%, 50%], plus-times FP32",
+            "sum_n": sum(a.nrows for a, _ in host), "sum_nnz_a": sum(a.nnz for a, _ in host), "flops": flops,
+            "nnz_c": bt.pool, "ms_graph_replay": round(ms_graph, 4), "ms_64_plain_calls": round(ms_seq, 4),
+            "gflops_graph": round(2 * flops / ms_graph / 1e6, 2), "gflops_plain_calls": round(2 * flops / ms_seq / 1e6, 2),
+            "speedup_vs_plain_calls": round(ms_seq / ms_graph, 3), "autotune_s": round(t_tune, 2)}
+
+
+def bench_bfs(cpu: bool) -> dict:
+    """Multi-source BFS, R-MAT scale 22, 512 sources: masked Boolean TS-SpGEMM until
+    every frontier is empty, levels n x 512 int32."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_11988_amd import DeviceCsr, msbfs
+
+    log("bfs: generating R-MAT 22")
+    a, srcs = synth.workload_bfs(scale=22, d=512)
+    A = DeviceCsr.from_host(a, with_values=False)
+    src = torch.from_numpy(srcs).cuda()
+    lev, fn = msbfs(A, src)  # warm-up (allocations)
+    del lev
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        lev, fn = msbfs(A, src)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        if len(times) < 3:
+            del lev
+    ms = sorted(times)[1]
+    deg = torch.diff(A.rowptr).to(torch.int64)
+    reached = (lev >= 0).sum(dim=1).to(torch.int64)
+    products = int((deg * reached).sum())  # AND products over the run = sum_s sum_{v reached} deg(v)
+    pairs = int(reached.sum())
+    out = {"workload": "R-MAT scale 22 (edge factor 16, symmetrised, pattern), 512 sources, Boolean masked",
+           "n": a.nrows, "nnz_a": a.nnz, "iterations": len(fn), "frontier_nnz": fn, "ms_total": round(ms, 3),
+           "reached_pairs": pairs, "and_products": products,
+           "gflops": round(2 * products / ms / 1e6, 2), "traversed_edges_per_s": round(products / ms * 1e3, 1),
+           "levels_bytes": a.nrows * 512 * 4}
+    if cpu:
+        import oracle
+
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+        k = 32
+        t0 = time.perf_counter()
+        oracle.bfs_queue(a.rp, a.ci, srcs[:k], threads=threads)
+        t = time.perf_counter() - t0
+        edges = int((deg * (lev[:, :k] >= 0).sum(dim=1).to(torch.int64)).sum())
+        out["cpu_baseline"] = {"value": round(edges / t, 1), "unit": "traversed edges/s", "cores": threads,
+                               "kind": "oracle", "sample": f"queue BFS from {k} of the 512 sources, {t:.2f} s"}
+    del lev
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,14 +267,23 @@ def main():
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the plain workload")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB a few times (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: TS-SpGEMM here is one rank's local multiply "
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        torch.cuda.set_device(0)
+        bw = copy_bandwidth_gbs(torch)
+        print(json.dumps({"copy_bytes_read_per_launch": 1 << 30, "copy_bytes_written_per_launch": 1 << 30,
+                          "launches": 12, "copy_bw_gbs": round(bw, 1)}), flush=True)
+        return
 
     import synth
     from paper_2408_11988_amd import DeviceCsr, _lib
@@ -202,9 +372,12 @@ def main():
         "ms_numeric": round(ms_num, 4),
         "gflops_numeric_only": round(2.0 * flops / (ms_num / 1e3) / 1e9, 3),
         "output_nnz_per_s": round(nnz_c / (ms_step / 1e3), 1),
-        "roofline": {"bound": "hbm", "kernel": "k_numeric", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS,
+        "roofline": {"bound": "hbm", "kernel": "numeric phase (k_numeric + k_numeric_light + k_split_finalize)",
+                     "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "bytes_alg_per_launch": bytes_alg},
+                     "traffic": traffic, "bytes_alg_per_launch": bytes_alg,
+                     "bytes_gather_model": 8 * flops + 8 * a.nnz,
+                     "traffic_gbs": round(traffic / (ms_num / 1e3) / 1e9, 1) if traffic else None},
         "copy_bw_gbs": round(copy_bw, 1),
     }
     if not args.no_cpu:
@@ -216,6 +389,17 @@ def main():
     else:
         result["cpu_baseline"] = None
     lib.tsspgemm_plan_destroy(plan)
+    del c_colidx, c_vals, A, B
+    if not args.no_extras:
+        result["fwd_bwd"] = bench_fwd_bwd(max(3, args.steps // 2), args.warmup)
+        log(f"fwd+bwd {result['fwd_bwd']['ms_fwd']} + {result['fwd_bwd']['ms_bwd']} ms")
+        torch.cuda.empty_cache()
+        result["batched"] = bench_batched(max(4, args.steps // 2), args.warmup)
+        log(f"batched graph {result['batched']['ms_graph_replay']} ms vs plain calls "
+            f"{result['batched']['ms_64_plain_calls']} ms")
+        torch.cuda.empty_cache()
+        result["bfs"] = bench_bfs(not args.no_cpu)
+        log(f"bfs {result['bfs']['ms_total']} ms, {result['bfs']['iterations']} iterations")
     print(json.dumps(result), flush=True)
 
 
