@@ -74,6 +74,17 @@ typedef struct {
                               word j/32, bit j%32 (kind 2) */
 } tsspgemm_mask;
 
+/* Accumulator of the numeric phase (Sec. III-C: a dense accumulator of
+ * width d for d <= 1024, a hash accumulator above).
+ *   LDS_STRIP:  lanes walk the entries of each B row and add into a d-wide
+ *               strip in LDS (FP64 for the FP32 semiring). Needs d <= 1024.
+ *   HASH:       open-addressing table of column keys per row, for d > 1024. */
+typedef enum {
+  TSSPGEMM_ACC_AUTO = 0,
+  TSSPGEMM_ACC_LDS_STRIP = 1,
+  TSSPGEMM_ACC_HASH = 2
+} tsspgemm_accumulator;
+
 /* Tuning knobs. A NULL tuning pointer, or a zero field, means "default".
  * Results (structure and values) do not depend on any of these. */
 typedef struct {
@@ -81,7 +92,7 @@ typedef struct {
   int32_t wave_max_flops;  /* rows with at most this many products use one wavefront             */
   int32_t split_flops;     /* rows above this are split into chunks of about this many products   */
   int32_t sym_split_nnz;   /* symbolic pass: rows with more A entries than this are split         */
-  int32_t accumulator;     /* 0 auto, 1 dense strip (d <= 1024), 2 hash                            */
+  int32_t accumulator;     /* tsspgemm_accumulator: 0 auto, 1 LDS strip, 2 hash                    */
   int32_t light_max_flops; /* rows with at most this many products use one lane group            */
 } tsspgemm_tuning;
 
@@ -163,8 +174,11 @@ int tsspgemm_transpose(const tsspgemm_csr* A, int32_t* at_rowptr, int32_t* at_co
  *   grad_b[q] = sum over i with (i,k) in pat(A) of A(i,k) G(i,j) for the q-th
  *   entry (k,j) of B (A^T G sampled on B's pattern), using A^T from
  *   tsspgemm_transpose.
- * plan: the forward plan of C = A B (its output bitmap speeds up lookups) or
- * NULL. Asynchronous. */
+ * plan: the forward plus-times FP32 plan of C = A B, required: its binned
+ * rows drive grad_a and its output bitmap locates G(i,j). Sums are FP64 in a
+ * fixed order, rounded once to FP32 (reproducible). Asynchronous.
+ * Errors: INVALID_ARG (NULL plan or output, a plan of another semiring or
+ * built with a mask, A / B / G / AT not matching the plan), HIP. */
 int tsspgemm_grad_a(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_csr* B, const tsspgemm_csr* G,
                     float* grad_a, void* stream);
 int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,

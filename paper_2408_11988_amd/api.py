@@ -73,12 +73,20 @@ class DeviceCsr:
                 None if self.vals is None else self.vals.cpu().numpy())
 
 
+ACCUMULATORS = {"auto": 0, "lds": 1, "hash": 2}
+
+
+def accumulator_code(v) -> int:
+    """Accumulator as the C enum value (names: auto, lds, hash)."""
+    return ACCUMULATORS[v] if isinstance(v, str) else int(v)
+
+
 def _tuning(t: dict | None):
     if not t:
         return None
     return ctypes.byref(_lib.Tuning(int(t.get("group_lanes", 0)), int(t.get("wave_max_flops", 0)),
                                     int(t.get("split_flops", 0)), int(t.get("sym_split_nnz", 0)),
-                                    int(t.get("accumulator", 0)), int(t.get("light_max_flops", 0))))
+                                    accumulator_code(t.get("accumulator", 0)), int(t.get("light_max_flops", 0))))
 
 
 class Plan:

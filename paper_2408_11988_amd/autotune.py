@@ -22,9 +22,9 @@ import torch
 from .api import DeviceCsr, numeric, symbolic
 
 GROUP_LANES = (8, 16, 32, 64)
-LIGHT_MAX = (256, 1024, 2048, 8192)
+LIGHT_MAX = (256, 512, 2048, 8192)
 WAVE_SPLIT = ((16384, 131072), (65536, 262144), (131072, 524288))
-DEFAULT = {"group_lanes": 0, "light_max_flops": 2048, "wave_max_flops": 65536, "split_flops": 262144}
+DEFAULT = {"group_lanes": 0, "light_max_flops": 1024, "wave_max_flops": 65536, "split_flops": 262144}
 
 
 def features(A: DeviceCsr, B: DeviceCsr, flops: int) -> str:

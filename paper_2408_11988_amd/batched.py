@@ -11,7 +11,7 @@ import ctypes
 import torch
 
 from . import _lib
-from .api import DeviceCsr, _stream_ptr
+from .api import DeviceCsr, _stream_ptr, accumulator_code
 
 
 class Batched:
@@ -29,7 +29,7 @@ class Batched:
             tarr = (_lib.Tuning * max(count, 1))(*[
                 _lib.Tuning(int(t.get("group_lanes", 0)), int(t.get("wave_max_flops", 0)),
                             int(t.get("split_flops", 0)), int(t.get("sym_split_nnz", 0)),
-                            int(t.get("accumulator", 0)), int(t.get("light_max_flops", 0)))
+                            accumulator_code(t.get("accumulator", 0)), int(t.get("light_max_flops", 0)))
                 for t in tunings])
         self._tunings = tarr
         self.handle = ctypes.c_void_p(None)

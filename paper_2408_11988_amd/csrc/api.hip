@@ -95,27 +95,35 @@ static int plan_alloc_host(Plan* p) {
 void plan_free(Plan* p) {
   for (DevBuf* b : {&p->bbits, &p->cbits, &p->flops, &p->cnt, &p->scan, &p->sym_items, &p->num_items,
                     &p->split_rows, &p->partial, &p->ctr, &p->maskbits, &p->gb_items, &p->gb_split,
-                    &p->gb_partial, &p->gb_ctr})
+                    &p->gb_partial, &p->gb_ctr, &p->cpos})
     b->release();
   if (p->host_ctr) (void)hipHostFree(p->host_ctr);
   p->host_ctr = nullptr;
 }
 
+// Lanes per B row from the mean B row length: a B row is read GL entries per
+// step, and a second step of the same row waits on the first, so the width
+// covers most rows in one step; 64 lanes only for long rows (measured on
+// R-MAT scale 20 at 12.8 and 25.6 entries per row: 32 lanes best for both).
+int default_group_lanes(double mean_b_row) {
+  if (mean_b_row > 48.0) return 64;
+  if (mean_b_row >= 8.0) return 32;
+  if (mean_b_row >= 4.0) return 16;
+  if (mean_b_row >= 2.0) return 8;
+  return 4;
+}
+
 void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tuning* out) {
   tsspgemm_tuning r{};
   if (t) r = *t;
-  if (r.group_lanes == 0) {
-    const double mean = B->nrows > 0 ? (double)B->nnz / (double)B->nrows : 0.0;
-    int gl = 4;
-    while (gl < 64 && gl < mean) gl <<= 1;
-    r.group_lanes = gl;
-  }
-  if (r.light_max_flops <= 0) r.light_max_flops = 2048;
+  if (r.group_lanes == 0) r.group_lanes = default_group_lanes(B->nrows > 0 ? (double)B->nnz / (double)B->nrows : 0.0);
+  if (r.light_max_flops <= 0) r.light_max_flops = 1024;
   if (r.wave_max_flops <= 0) r.wave_max_flops = 65536;
   if (r.split_flops <= 0) r.split_flops = 262144;
   if (r.wave_max_flops < r.light_max_flops) r.wave_max_flops = r.light_max_flops;
   if (r.split_flops < r.wave_max_flops) r.split_flops = r.wave_max_flops;
   if (r.sym_split_nnz <= 0) r.sym_split_nnz = 2048;
+  if (r.accumulator == TSSPGEMM_ACC_AUTO) r.accumulator = TSSPGEMM_ACC_LDS_STRIP;
   *out = r;
 }
 
@@ -159,6 +167,14 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   }
   tsspgemm_tuning tn;
   resolve_tuning(tune, B, &tn);
+  if (tn.accumulator != TSSPGEMM_ACC_LDS_STRIP && tn.accumulator != TSSPGEMM_ACC_HASH) {
+    set_error("unknown accumulator");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (tn.accumulator == TSSPGEMM_ACC_HASH) {
+    set_error("the hash accumulator is not available in this build");
+    return TSSPGEMM_ERR_UNSUPPORTED;
+  }
   if (B->ncols > kMaxDenseD) {
     set_error("d > 1024 needs the hash accumulator, which this build does not provide");
     return TSSPGEMM_ERR_UNSUPPORTED;
@@ -173,6 +189,9 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   p->crp = c_rowptr;
   p->a_nnz = A->nnz;
   p->b_nnz = B->nnz;
+  p->ready = false;
+  p->cpos_ready = false;
+  p->masked = M && M->kind != TSSPGEMM_MASK_NONE;
   if ((rc = plan_alloc_host(p))) return rc;
   const int64_t sym_cap = n + A->nnz / tn.sym_split_nnz + 2;
   const int64_t num_cap = 2 * n + A->nnz / 64 + 2;
@@ -230,6 +249,11 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   if (sr != TSSPGEMM_OR_AND) {
     const NumThresholds th{tn.light_max_flops, tn.wave_max_flops, tn.split_flops};
     if ((rc = launch_num_bin(pr, th, (Item*)p->num_items.p, (SplitRow*)p->split_rows.p, ctr, st)))
+      return rc;
+  }
+  if (sr != TSSPGEMM_OR_AND) {  // B's pattern is fixed for the plan: narrow its column ids once
+    const int cb = col_id_bytes(d);
+    if ((rc = p->bcol.ensure((size_t)B->nnz * cb)) || (rc = launch_narrow_cols(B->nnz, B->colidx, p->bcol.p, cb, st)))
       return rc;
   }
   TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -296,6 +320,7 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   np.n_wg_items = (int32_t)(p->n_split_items + p->n_block_items);
   np.n_heavy_records = (int32_t)(p->n_split_items + p->n_block_items + p->n_wave_rows);
   np.n_light = (int32_t)p->n_light_rows;
+  np.pr.bcol = p->bcol.p;
   np.partial = (double*)p->partial.p;
   np.ipartial = (int32_t*)p->partial.p;
   const int64_t grid = np.n_wg_items + (p->n_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;

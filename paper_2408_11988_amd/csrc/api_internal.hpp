@@ -45,6 +45,10 @@ struct Plan {
   // device workspace
   DevBuf bbits, cbits, flops, cnt, scan, sym_items, num_items, split_rows, partial, ctr, maskbits;
   DevBuf gb_items, gb_split, gb_partial, gb_ctr;  // dL/dB work lists
+  DevBuf bcol;             // B's column ids narrowed to col_id_bytes(d) bytes (numeric phase)
+  DevBuf cpos;             // dL/dB: per C bitmap word, (position of its first entry) << 32 | bits
+  bool cpos_ready = false;
+  bool masked = false;     // symbolic phase ran with a complement mask
   Counters* host_ctr = nullptr;  // pinned
   // results of the last symbolic call
   int64_t nnz = 0, flops_total = 0, n_split_items = 0, n_block_items = 0, n_wave_rows = 0, n_light_rows = 0;

@@ -13,8 +13,9 @@
 //
 // dL/dB walks A^T (from tsspgemm_transpose): a group of GL lanes owns the
 // entries of one B row k (lane = column j) and runs over the rows i of A^T
-// row k; G(i,j) is found at C.rowptr[i] + rank of j in C's bitmap row i (the
-// symbolic pass's accumulator). Long A^T rows are cut into chunks whose
+// row k; G(i,j) sits at C.rowptr[i] + the rank of j in C's bitmap row i (the
+// symbolic pass's accumulator), read from a per-word record that holds the
+// word's bits and the position of its first entry. Long A^T rows are cut into chunks whose
 // partial sums a second kernel adds in chunk order.
 #include "api_internal.hpp"
 
@@ -133,6 +134,7 @@ __global__ void k_zero_f32(float* p, int64_t n) {
 
 struct GradBParams {
   Problem pr;                // A values, B pattern, C pattern (crp, cbits)
+  const uint64_t* cpos;      // n x wp C records: (C.rowptr[i] + set bits before word w) << 32 | bits of word w
   const int32_t* atrp;       // A^T row pointers (n + 1)
   const int32_t* atci;       // A^T rows i
   const int32_t* perm;       // position in A of each A^T entry
@@ -225,12 +227,27 @@ __global__ void k_gb_bin_fill(GradBParams gb) {
   }
 }
 
-// rank of column j among the set bits of a bitmap row (bits below j)
-__device__ __forceinline__ int bitmap_rank(const uint32_t* cb, int j) {
-  int r = 0;
-  const int w = j >> 5;
-  for (int x = 0; x < w; ++x) r += __popc(cb[x]);
-  return r + __popc(cb[w] & ((1u << (j & 31)) - 1u));
+// C position records for dL/dB: records[i * wp + w] = (rowptr[i] + set bits
+// of words 0..w-1 of row i) << 32 | bits[i * wp + w]
+__global__ void k_build_recs(int64_t n, int wp, const uint32_t* __restrict__ bits, const int32_t* __restrict__ rowptr,
+                             uint64_t* __restrict__ rec) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t pos = (uint32_t)rowptr[i];
+    for (int w = 0; w < wp; ++w) {
+      const uint32_t b = bits[i * wp + w];
+      rec[i * wp + w] = ((uint64_t)pos << 32) | b;
+      pos += __popc(b);
+    }
+  }
+}
+
+int launch_build_recs(int64_t n, int wp, const uint32_t* bits, const int32_t* rowptr, uint64_t* rec, hipStream_t st) {
+  if (n <= 0) return TSSPGEMM_OK;
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  k_build_recs<<<(unsigned)g, 256, 0, st>>>(n, wp, bits, rowptr, rec);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
 }
 
 // One group of GL lanes per item, items walked with a grid stride. Lanes own
@@ -239,10 +256,11 @@ __device__ __forceinline__ int bitmap_rank(const uint32_t* cb, int j) {
 template <int GL>
 __global__ __launch_bounds__(kBlock) void k_grad_b(GradBParams gb) {
   constexpr int G = kBlock / GL;
-  constexpr int U = 4;
+  constexpr int U = 8;
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
   const Problem& pr = gb.pr;
   const float* __restrict__ aval = (const float*)pr.aval;
+  const int wp = pr.wp;
   const int total = gb.ctr->num_split_items + gb.ctr->num_light_rows;
   for (int64_t t = (int64_t)blockIdx.x * G + grp; t < total; t += (int64_t)gridDim.x * G) {
     const Item it = gb.items[t];
@@ -252,27 +270,33 @@ __global__ __launch_bounds__(kBlock) void k_grad_b(GradBParams gb) {
       const int q = qb + gl;
       const bool own = q < q1;
       const int j = own ? pr.bci[q] : 0;
+      const int jw = j >> 5;
+      const uint32_t below = (1u << (j & 31)) - 1u;
       double acc = 0.0;
       for (int x = it.p0; x < it.p1; x += U) {
         int i[U];
-        float a[U];
+        int pa[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           i[u] = -1;
-          a[u] = 0.0f;
+          pa[u] = 0;
           if (x + u < it.p1) {
             i[u] = gb.atci[x + u];
-            a[u] = aval[gb.perm[x + u]];
+            pa[u] = gb.perm[x + u];
           }
+        }
+        float a[U];
+        uint64_t r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          a[u] = i[u] >= 0 ? aval[pa[u]] : 0.0f;
+          r[u] = (own && i[u] >= 0) ? gb.cpos[(int64_t)i[u] * wp + jw] : 0;
         }
         float g[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           g[u] = 0.0f;
-          if (own && i[u] >= 0) {
-            const uint32_t* cb = pr.cbits + (int64_t)i[u] * pr.wp;
-            g[u] = gb.gval[pr.crp[i[u]] + bitmap_rank(cb, j)];
-          }
+          if (own && i[u] >= 0) g[u] = gb.gval[(uint32_t)(r[u] >> 32) + __popc((uint32_t)r[u] & below)];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)g[u];
@@ -305,6 +329,10 @@ static int check_grad_args(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B
   int rc;
   if (!p || !p->ready || p->sr != TSSPGEMM_PLUS_TIMES_F32) {
     set_error(std::string(who) + ": needs the plus-times FP32 plan of the forward product");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (p->masked) {  // every product must land in pat(C) for G to be read on C's pattern
+    set_error(std::string(who) + ": the forward plan was built with a mask");
     return TSSPGEMM_ERR_INVALID_ARG;
   }
   if ((rc = check_csr(A, "A", true)) || (rc = check_csr(B, "B", true)) || (rc = check_csr(G, "G", true))) return rc;
@@ -402,8 +430,14 @@ static int run_grad_b(Plan* p, const tsspgemm_csr* AT, const int32_t* perm, cons
       (rc = p->gb_split.ensure((size_t)(n + 1) * sizeof(SplitRow))) ||
       (rc = p->gb_partial.ensure((size_t)chunk_cap * p->d * 8)) || (rc = p->gb_ctr.ensure(sizeof(Counters))))
     return rc;
+  if (!p->cpos_ready) {  // the C pattern is fixed for the plan: built once
+    if ((rc = p->cpos.ensure((size_t)n * p->wp * sizeof(uint64_t)))) return rc;
+    if ((rc = launch_build_recs(n, p->wp, (const uint32_t*)p->cbits.p, p->crp, (uint64_t*)p->cpos.p, st))) return rc;
+    p->cpos_ready = true;
+  }
   GradBParams gb{};
   gb.pr = plan_problem(p, A, B);
+  gb.cpos = (const uint64_t*)p->cpos.p;
   gb.atrp = AT->rowptr;
   gb.atci = AT->colidx;
   gb.perm = perm;

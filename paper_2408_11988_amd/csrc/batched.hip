@@ -450,6 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric_light(BatchDev b) {
   constexpr int G = kBlock / GL;
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
   double* strip = (double*)smem + grp * b.dmax;
+  int4* stage = (int4*)(smem + (size_t)G * b.dmax * sizeof(double)) + grp * GL;
   const int first = b.ctr->num_split_items + b.ctr->num_block_items + b.ctr->num_wave_rows;
   const int n_light = b.ctr->num_light_rows;
   for (int64_t x = (int64_t)blockIdx.x * G + grp; x < n_light; x += (int64_t)gridDim.x * G) {
@@ -457,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric_light(BatchDev b) {
     const Problem& pr = b.insts[b.num_inst[first + x]].pr;
     for (int j = gl; j < pr.d; j += GL) strip[j] = 0.0;
     wave_sync();
-    accumulate_light<GL, float>(pr, it.p0, it.p1, strip, gl);
+    accumulate_light<GL, float>(pr, it.p0, it.p1, strip, stage, gl);
     wave_sync();
     emit_group<GL, float>(pr, it.row, strip, gl);
     wave_sync();
@@ -526,7 +527,7 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   TSS_CHECK_LAUNCH();
   if (!numeric) return TSSPGEMM_OK;
   const size_t lds = (size_t)kWavesPerBlock * bt->dmax * 8 + kWavesPerBlock * kWave * sizeof(int4);
-  const size_t llds = (size_t)(kBlock / bt->lgl) * bt->dmax * 8;
+  const size_t llds = (size_t)(kBlock / bt->lgl) * bt->dmax * 8 + kBlock * sizeof(int4);
 #define TSS_BN(GLV)                                              \
   case GLV:                                                      \
     k_b_numeric<GLV><<<2048, kBlock, lds, st>>>(b);              \

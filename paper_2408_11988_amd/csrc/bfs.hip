@@ -6,9 +6,11 @@
 // mask) and N. One iteration is the symbolic pass of the library (bitmap
 // accumulator, row binning of A done once) with two row filters that do not
 // change the result: A entries whose frontier row is empty are skipped (a
-// 1-bit-per-row summary of F), and rows whose unvisited columns all belong to
+// 1-bit-per-row summary of F), rows whose unvisited columns all belong to
 // sources whose frontier is already empty are skipped (a d-bit "active" word
-// mask). The masked product is directly N \ S, i.e. the next frontier.
+// mask), and a row stops reading neighbours once its accumulator holds every
+// column still open to it (later ones could only add masked bits). The
+// masked product is directly N \ S, i.e. the next frontier.
 // Levels are written once, at the end, from the kept frontiers N_0..N_T: a
 // wavefront owns 64 consecutive columns of a row, so every store is
 // coalesced, and never-reached pairs get -1 in the same pass.
@@ -90,29 +92,44 @@ __global__ __launch_bounds__(1024) void k_bfs_reduce(int64_t nblocks, int wp, co
 }
 
 // level[i*d + j] = t for the frontier N_t holding bit j of row i, else -1.
-// A wavefront covers 64 columns of one row; the frontier words are uniform
-// across it.
+// A lane owns 4 consecutive columns (one 16-byte store when d is a multiple of
+// 4), a wavefront 256 columns of one row; work units (row, 256-column chunk)
+// are walked grid-stride. The frontier loads of one lane are independent (no
+// early exit), so they are all in flight together; the frontiers are visited
+// from last to first so the earliest one holding the bit wins.
 __global__ __launch_bounds__(256) void k_bfs_levels(int64_t n, int32_t d, int wp, int32_t nfront,
                                                     const uint32_t* const* __restrict__ fronts,
                                                     int32_t* __restrict__ levels) {
   const int lane = threadIdx.x & 63;
-  const int nch = (d + 63) >> 6;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t row = wave / nch;
-  const int c = (int)(wave % nch);
-  if (row >= n) return;
-  const int j = 64 * c + lane;
-  const int w = j >> 5;
-  int lev = -1;
-  if (j < d) {
-    for (int t = 0; t < nfront; ++t) {
-      const uint32_t x = fronts[t][row * wp + w];
-      if ((x >> (j & 31)) & 1u) {
-        lev = t;
-        break;
-      }
+  const int nch = (d + 255) >> 8;
+  const int64_t units = n * nch;
+  const int64_t wstride = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const bool vec = (d & 3) == 0 && ((uintptr_t)levels & 15) == 0;
+  for (int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < units; u += wstride) {
+    const int64_t row = u / nch;
+    const int j0 = ((int)(u % nch) << 8) + 4 * lane;  // first of this lane's 4 columns
+    if (j0 >= d) continue;
+    const int64_t word = row * wp + (j0 >> 5);
+    const int sh = j0 & 31;  // the 4 bits j0..j0+3 sit in one word (j0 is a multiple of 4)
+    int l0 = -1, l1 = -1, l2 = -1, l3 = -1;
+#pragma unroll 4
+    for (int t = nfront - 1; t >= 0; --t) {
+      const uint32_t x = fronts[t][word] >> sh;
+      l0 = (x & 1u) ? t : l0;
+      l1 = (x & 2u) ? t : l1;
+      l2 = (x & 4u) ? t : l2;
+      l3 = (x & 8u) ? t : l3;
     }
-    levels[row * d + j] = lev;
+    int32_t* out = levels + row * d + j0;
+    if (vec) {
+      *reinterpret_cast<int4*>(out) = make_int4(l0, l1, l2, l3);
+    } else {
+      const int m = d - j0 < 4 ? d - j0 : 4;
+      out[0] = l0;
+      if (m > 1) out[1] = l1;
+      if (m > 2) out[2] = l2;
+      if (m > 3) out[3] = l3;
+    }
   }
 }
 
@@ -220,6 +237,7 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
     sp.mask = (const uint32_t*)w.S.p;
     sp.active = (const uint32_t*)w.active.p;
     sp.fnz = (const uint32_t*)w.fnz.p;
+    sp.early_exit = true;
     if ((rc = launch_sym_split_zero(pr, sp.items, ctr, sym_cap, st)) || (rc = launch_symbolic(sp, sym_cap, st)) ||
         (rc = launch_sym_split_mask(pr, sp.items, sp.mask, ctr, sym_cap, st)))
       return rc;
@@ -232,9 +250,9 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
   for (int t = 0; t < nfront; ++t) fp[t] = (const uint32_t*)w.fronts[t].p;
   if ((rc = w.fronts_dev.ensure(sizeof(void*) * (nfront + 1)))) return rc;
   TSS_HIP(hipMemcpyAsync(w.fronts_dev.p, fp.data(), sizeof(void*) * nfront, hipMemcpyHostToDevice, st));
-  const int64_t waves = n * ((d + 63) / 64);
+  const int64_t waves = n * ((d + 255) / 256);
   if (waves > 0) {
-    k_bfs_levels<<<grid_for(waves, 4), 256, 0, st>>>(n, d, wp, nfront, (const uint32_t* const*)w.fronts_dev.p,
+    k_bfs_levels<<<(int)std::min<int64_t>((waves + 3) / 4, 8192), 256, 0, st>>>(n, d, wp, nfront, (const uint32_t* const*)w.fronts_dev.p,
                                                       levels);
     TSS_CHECK_LAUNCH();
   }

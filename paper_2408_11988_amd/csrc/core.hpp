@@ -15,6 +15,10 @@ constexpr int32_t kSplitFlag = 1 << 30;
 constexpr int32_t kNoSlot = 0x7fffffff;  // numeric workgroup item that is a whole row
 
 constexpr int kBins = 32;  // work classes by floor(log2(work)); heavier first
+// Binning kernels: a workgroup of 256 threads takes this many consecutive
+// rows and makes one global reservation per bin for all of them (few
+// workgroups, so few atomics on each bin counter).
+constexpr int kBinRowsPerBlock = 4096;
 constexpr int kNumClasses = 4;  // numeric: 0 split chunks, 1 workgroup rows, 2 wavefront rows, 3 light rows
 
 // Product-count thresholds of the numeric work classes.
@@ -55,6 +59,7 @@ struct Problem {
   const int32_t* brp;
   const int32_t* bci;
   const void* bval;
+  const void* bcol;       // B's column ids narrowed to 8 (d <= 256) or 16 bits, for the numeric phase
   const uint32_t* bbits;  // B pattern, n x wp
   uint32_t* cbits;        // C pattern, n x wp
   int64_t* flops;         // per row
@@ -70,6 +75,11 @@ struct SymParams {
   const uint32_t* mask;    // complement mask bitmap (n x wp) or null
   const uint32_t* active;  // wp words: columns that can still change, or null (all)
   const uint32_t* fnz;     // 1 bit per B row: row non-empty; null = no filter
+  // Stop a row (or chunk) as soon as its accumulator holds every column the
+  // mask leaves open among `active` ones: later B rows cannot change the
+  // masked result. Only for pattern-only (OR, AND) work with a mask and fnz;
+  // `flops` then counts the products examined, not all of them.
+  bool early_exit;
 };
 
 // Item list layout: [split chunks][workgroup rows][wavefront rows][light rows].
@@ -109,6 +119,9 @@ int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, Spli
                    hipStream_t st);
 
 int launch_numeric(int sr, int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st);
+int col_id_bytes(int64_t d);  // 1 or 2: width of the narrowed column ids
+int launch_narrow_cols(int64_t nnz, const int32_t* ci, void* out, int bytes, hipStream_t st);
+int launch_build_recs(int64_t n, int wp, const uint32_t* bits, const int32_t* rowptr, uint64_t* rec, hipStream_t st);
 int launch_split_finalize(int sr, const Problem& pr, const SplitRow* rows, int32_t nrows, const double* partial,
                           const int32_t* ipartial, hipStream_t st);
 int launch_emit_pattern(const Problem& pr, hipStream_t st);

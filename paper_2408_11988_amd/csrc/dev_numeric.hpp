@@ -40,7 +40,17 @@ constexpr int kLightUnroll = 4;  // A entries per group per step, light rows
 
 // Accumulate entries [p_begin, p_end) of one A row into `strip`, taking
 // 64-entry batches number wstart, wstart + wstride, ... (one wavefront).
-template <int GL, typename T>
+// B column ids as IdxT: int32_t reads B's own array, uint8_t / uint16_t the
+// narrowed copy (fewer bytes per gathered B row).
+template <typename IdxT>
+__device__ __forceinline__ const IdxT* col_ids(const Problem& pr) {
+  if constexpr (sizeof(IdxT) == 4)
+    return (const IdxT*)pr.bci;
+  else
+    return (const IdxT*)pr.bcol;
+}
+
+template <int GL, typename T, typename IdxT = int32_t>
 __device__ __forceinline__ void accumulate_range(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
                                                  typename SemiringT<T>::acc* strip, int4* stage) {
   using S = SemiringT<T>;
@@ -51,7 +61,7 @@ __device__ __forceinline__ void accumulate_range(const Problem& pr, int p_begin,
   const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
   const int32_t* __restrict__ brp = pr.brp;
-  const int32_t* __restrict__ bci = pr.bci;
+  const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
   const T* __restrict__ bval = (const T*)pr.bval;
 
   for (int base = p_begin + kWave * wstart; base < p_end; base += kWave * wstride) {
@@ -68,7 +78,8 @@ __device__ __forceinline__ void accumulate_range(const Problem& pr, int p_begin,
     stage[lane] = e;
     wave_sync();
     for (int s = 0; s < nb; s += U * GPW) {
-      int q[U], qe[U], jj[U];
+      int q[U], qe[U];
+      int jj[U];
       T av[U], bv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -153,47 +164,59 @@ __device__ __forceinline__ void emit_group(const Problem& pr, int64_t row, const
 }
 
 // Accumulate entries [p0, p1) of one A row into a group's strip (GL lanes,
-// lane gl); several A entries per step keep several B rows in flight.
-template <int GL, typename T>
+// lane gl). The group first loads up to GL of the row's A entries at once,
+// one per lane (coalesced), with their B row bounds, and shares them through
+// `stage` (GL records of this group); then several staged entries per step
+// keep several B rows in flight. The chain of dependent gathers per step is
+// one (B row) instead of three (A entry, B row pointers, B row).
+template <int GL, typename T, typename IdxT = int32_t>
 __device__ __forceinline__ void accumulate_light(const Problem& pr, int p0, int p1,
-                                                 typename SemiringT<T>::acc* strip, int gl) {
+                                                 typename SemiringT<T>::acc* strip, int4* stage, int gl) {
   using S = SemiringT<T>;
   constexpr int U = kLightUnroll;
   const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
   const int32_t* __restrict__ brp = pr.brp;
-  const int32_t* __restrict__ bci = pr.bci;
+  const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
   const T* __restrict__ bval = (const T*)pr.bval;
-  for (int p = p0; p < p1; p += U) {
-    int k[U], q[U], qe[U], jj[U];
-    T av[U], bv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const bool v = p + u < p1;
-      k[u] = v ? aci[p + u] : -1;
-      av[u] = v ? aval[p + u] : T(0);
+  for (int base = p0; base < p1; base += GL) {
+    const int nb = min(GL, p1 - base);
+    int4 e = make_int4(0, 0, 0, 0);
+    if (gl < nb) {
+      const int k = aci[base + gl];
+      e.x = brp[k];
+      e.y = brp[k + 1];
+      e.z = __builtin_bit_cast(int32_t, aval[base + gl]);
     }
+    wave_sync();
+    stage[gl] = e;
+    wave_sync();
+    for (int s = 0; s < nb; s += U) {
+      int q[U], qe[U];
+      int jj[U];
+      T av[U], bv[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      q[u] = 0;
-      qe[u] = 0;
-      if (k[u] >= 0) {
-        q[u] = brp[k[u]] + gl;
-        qe[u] = brp[k[u] + 1];
+      for (int u = 0; u < U; ++u) {
+        int4 r = make_int4(0, 0, 0, 0);
+        if (s + u < nb) r = stage[s + u];
+        q[u] = r.x + gl;
+        qe[u] = r.y;
+        av[u] = __builtin_bit_cast(T, r.z);
       }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q[u] < qe[u]) {
+          jj[u] = bci[q[u]];
+          bv[u] = bval[q[u]];
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q[u] < qe[u]) lds_add(&strip[jj[u]], S::prod(av[u], bv[u]));
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        for (int qq = q[u] + GL; qq < qe[u]; qq += GL) lds_add(&strip[bci[qq]], S::prod(av[u], bval[qq]));
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (q[u] < qe[u]) {
-        jj[u] = bci[q[u]];
-        bv[u] = bval[q[u]];
-      }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if (q[u] < qe[u]) lds_add(&strip[jj[u]], S::prod(av[u], bv[u]));
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      for (int qq = q[u] + GL; qq < qe[u]; qq += GL) lds_add(&strip[bci[qq]], S::prod(av[u], bval[qq]));
+    wave_sync();
   }
 }
 

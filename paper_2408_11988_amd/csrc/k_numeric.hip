@@ -28,7 +28,7 @@
 
 namespace tss {
 
-template <int GL, typename T>
+template <int GL, typename T, typename IdxT>
 __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   using S = SemiringT<T>;
   using Acc = typename S::acc;
@@ -55,9 +55,9 @@ __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   __syncthreads();
   if (valid) {
     if (wg_mode)
-      accumulate_range<GL, T>(pr, it.p0, it.p1, wave, kWavesPerBlock, strip, stage + wave * kWave);
+      accumulate_range<GL, T, IdxT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strip, stage + wave * kWave);
     else
-      accumulate_range<GL, T>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
+      accumulate_range<GL, T, IdxT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
   }
   __syncthreads();
   if (wg_mode) {
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   }
 }
 
-template <int GL, typename T>
+template <int GL, typename T, typename IdxT>
 __global__ __launch_bounds__(kBlock) void k_numeric_light(NumParams np) {
   using Acc = typename SemiringT<T>::acc;
   constexpr int G = kBlock / GL;  // rows in flight per workgroup
@@ -90,13 +90,14 @@ __global__ __launch_bounds__(kBlock) void k_numeric_light(NumParams np) {
   const int d = pr.d;
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
   Acc* strip = (Acc*)smem + grp * d;
+  int4* stage = (int4*)(smem + (size_t)G * d * sizeof(Acc)) + grp * GL;
   const Item* items = np.items + np.n_heavy_records;
   const int64_t stride = (int64_t)gridDim.x * G;
   for (int64_t t = (int64_t)blockIdx.x * G + grp; t < np.n_light; t += stride) {
     const Item it = items[t];
     for (int j = gl; j < d; j += GL) strip[j] = Acc(0);
     wave_sync();
-    accumulate_light<GL, T>(pr, it.p0, it.p1, strip, gl);
+    accumulate_light<GL, T, IdxT>(pr, it.p0, it.p1, strip, stage, gl);
     wave_sync();
     emit_group<GL, T>(pr, it.row, strip, gl);
     wave_sync();
@@ -121,55 +122,77 @@ static int64_t light_grid(int64_t n_light, int gl) {
   return g < cap ? g : cap;
 }
 
-int launch_numeric(int sr, int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st) {
-  const size_t ab = acc_bytes(sr);
+int col_id_bytes(int64_t d) { return d <= 256 ? 1 : 2; }
+
+__global__ void k_narrow_cols(int64_t nnz, const int32_t* __restrict__ ci, uint8_t* __restrict__ o8,
+                              uint16_t* __restrict__ o16) {
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
+    if (o8)
+      o8[q] = (uint8_t)ci[q];
+    else
+      o16[q] = (uint16_t)ci[q];
+  }
+}
+
+int launch_narrow_cols(int64_t nnz, const int32_t* ci, void* out, int bytes, hipStream_t st) {
+  if (nnz <= 0) return TSSPGEMM_OK;
+  int64_t g = (nnz + 255) / 256;
+  if (g > 8192) g = 8192;
+  k_narrow_cols<<<(unsigned)g, 256, 0, st>>>(nnz, ci, bytes == 1 ? (uint8_t*)out : nullptr,
+                                             bytes == 2 ? (uint16_t*)out : nullptr);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+template <typename T, typename IdxT>
+static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st) {
+  const size_t ab = sizeof(typename SemiringT<T>::acc);
   if (n_grid > 0) {
     const size_t lds = (size_t)kWavesPerBlock * np.pr.d * ab + kWavesPerBlock * kWave * sizeof(int4);
-#define TSS_NUM_CASE(GLV)                                                 \
-  case GLV:                                                               \
-    if (sr == TSSPGEMM_PLUS_TIMES_F32)                                    \
-      k_numeric<GLV, float><<<(unsigned)n_grid, kBlock, lds, st>>>(np);   \
-    else                                                                  \
-      k_numeric<GLV, int32_t><<<(unsigned)n_grid, kBlock, lds, st>>>(np); \
-    break;
     switch (group_lanes) {
-      TSS_NUM_CASE(4)
-      TSS_NUM_CASE(8)
-      TSS_NUM_CASE(16)
-      TSS_NUM_CASE(32)
-      TSS_NUM_CASE(64)
+      case 4: k_numeric<4, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 8: k_numeric<8, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 16: k_numeric<16, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 32: k_numeric<32, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 64: k_numeric<64, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
       default:
         set_error("numeric: group_lanes must be 4, 8, 16, 32 or 64");
         return TSSPGEMM_ERR_INVALID_ARG;
     }
-#undef TSS_NUM_CASE
     TSS_CHECK_LAUNCH();
   }
   if (np.n_light > 0) {
-    const int gl = light_group_lanes(group_lanes, np.pr.d, sr);
+    const int gl = light_group_lanes(group_lanes, np.pr.d, sizeof(typename SemiringT<T>::acc) == 8
+                                                               ? TSSPGEMM_PLUS_TIMES_F32 : TSSPGEMM_PLUS_TIMES_I32);
     const unsigned g = (unsigned)light_grid(np.n_light, gl);
-    const size_t lds = (size_t)(kBlock / gl) * np.pr.d * ab;
-#define TSS_LIGHT_CASE(GLV)                                      \
-  case GLV:                                                      \
-    if (sr == TSSPGEMM_PLUS_TIMES_F32)                           \
-      k_numeric_light<GLV, float><<<g, kBlock, lds, st>>>(np);   \
-    else                                                         \
-      k_numeric_light<GLV, int32_t><<<g, kBlock, lds, st>>>(np); \
-    break;
+    const size_t lds = (size_t)(kBlock / gl) * np.pr.d * ab + kBlock * sizeof(int4);
     switch (gl) {
-      TSS_LIGHT_CASE(4)
-      TSS_LIGHT_CASE(8)
-      TSS_LIGHT_CASE(16)
-      TSS_LIGHT_CASE(32)
-      TSS_LIGHT_CASE(64)
+      case 4: k_numeric_light<4, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
+      case 8: k_numeric_light<8, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
+      case 16: k_numeric_light<16, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
+      case 32: k_numeric_light<32, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
+      case 64: k_numeric_light<64, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
       default:
         set_error("numeric: bad light group width");
         return TSSPGEMM_ERR_INVALID_ARG;
     }
-#undef TSS_LIGHT_CASE
     TSS_CHECK_LAUNCH();
   }
   return TSSPGEMM_OK;
+}
+
+// B's column ids are read narrowed (np.pr.bcol, col_id_bytes(d) bytes each).
+int launch_numeric(int sr, int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st) {
+  const bool b8 = col_id_bytes(np.pr.d) == 1;
+  if (!np.pr.bcol && np.pr.n > 0) {
+    set_error("numeric: narrowed column ids missing");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (sr == TSSPGEMM_PLUS_TIMES_F32)
+    return b8 ? launch_numeric_t<float, uint8_t>(group_lanes, np, n_grid, st)
+              : launch_numeric_t<float, uint16_t>(group_lanes, np, n_grid, st);
+  return b8 ? launch_numeric_t<int32_t, uint8_t>(group_lanes, np, n_grid, st)
+            : launch_numeric_t<int32_t, uint16_t>(group_lanes, np, n_grid, st);
 }
 
 // Split rows: add the chunks' partial strips in chunk order, then emit.
@@ -241,22 +264,34 @@ int launch_emit_pattern(const Problem& pr, hipStream_t st) {
   return TSSPGEMM_OK;
 }
 
+// (class, bin) key of a row with f > 0 products and m A entries, and the
+// number of items it makes (split rows: one per chunk).
+__device__ __forceinline__ void num_key(int64_t f, int m, const NumThresholds& th, int& cls, int& key, int& count,
+                                        int& ce) {
+  cls = num_class(f, th);
+  if (cls == 0) {
+    ce = chunk_entries(m, f, th.split);
+    count = (m + ce - 1) / ce;
+    key = 0;
+  } else {
+    ce = 0;
+    count = 1;
+    key = cls * kBins + num_bin(f);
+  }
+}
+
 __global__ void k_num_bin_count(Problem pr, NumThresholds th, Counters* ctr) {
   __shared__ int32_t hist[kNumClasses * kBins];
   for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) hist[t] = 0;
   __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < pr.n) {
+  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
+  const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     const int64_t f = pr.flops[i];
     if (f > 0) {
-      const int cls = num_class(f, th);
-      if (cls == 0) {
-        const int m = pr.arp[i + 1] - pr.arp[i];
-        const int ce = chunk_entries(m, f, th.split);
-        atomicAdd(&hist[0], (m + ce - 1) / ce);
-      } else {
-        atomicAdd(&hist[cls * kBins + num_bin(f)], 1);
-      }
+      int cls, key, count, ce;
+      num_key(f, pr.arp[i + 1] - pr.arp[i], th, cls, key, count, ce);
+      atomicAdd(&hist[key], count);
     }
   }
   __syncthreads();
@@ -280,55 +315,58 @@ __global__ void k_num_bin_scan(Counters* ctr) {
 }
 
 // Items are placed with one global reservation per (class, bin) per
-// workgroup; the slot inside the workgroup's range comes from an LDS counter.
+// workgroup (counts from a first pass over its rows); the slot inside the
+// workgroup's range comes from an LDS counter in the second pass.
 __global__ void k_num_bin_fill(Problem pr, NumThresholds th, Item* items, SplitRow* split_rows, Counters* ctr) {
   __shared__ int32_t cnt[kNumClasses * kBins], base[kNumClasses * kBins];
   __shared__ int32_t nsplit, split_base;
   for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) cnt[t] = 0;
   if (threadIdx.x == 0) nsplit = 0;
   __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int a = 0, m = 0, cls = 0, key = 0, count = 0, local = 0, ce = 0, slocal = 0;
-  if (i < pr.n) {
+  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
+  const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     const int64_t f = pr.flops[i];
     if (f > 0) {
-      a = pr.arp[i];
-      m = pr.arp[i + 1] - a;
-      cls = num_class(f, th);
-      if (cls == 0) {
-        ce = chunk_entries(m, f, th.split);
-        count = (m + ce - 1) / ce;
-        key = 0;
-        slocal = atomicAdd(&nsplit, 1);
-      } else {
-        count = 1;
-        key = cls * kBins + num_bin(f);
-      }
-      local = atomicAdd(&cnt[key], count);
+      int cls, key, count, ce;
+      num_key(f, pr.arp[i + 1] - pr.arp[i], th, cls, key, count, ce);
+      atomicAdd(&cnt[key], count);
+      if (cls == 0) atomicAdd(&nsplit, 1);
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x)
+  for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) {
     if (cnt[t]) base[t] = atomicAdd(&(&ctr->num_cursor[0][0])[t], cnt[t]);
-  if (threadIdx.x == 0 && nsplit) split_base = atomicAdd(&ctr->num_split_rows, nsplit);
+    cnt[t] = 0;
+  }
+  if (threadIdx.x == 0) {
+    if (nsplit) split_base = atomicAdd(&ctr->num_split_rows, nsplit);
+    nsplit = 0;
+  }
   __syncthreads();
-  if (count == 0) return;
-  const int pos = base[key] + local;
-  if (cls == 0) {
-    for (int c = 0; c < count; ++c) {
-      const int p0 = a + c * ce;
-      items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + ce), pos + c};
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const int64_t f = pr.flops[i];
+    if (f <= 0) continue;
+    const int a = pr.arp[i], m = pr.arp[i + 1] - a;
+    int cls, key, count, ce;
+    num_key(f, m, th, cls, key, count, ce);
+    const int pos = base[key] + atomicAdd(&cnt[key], count);
+    if (cls == 0) {
+      for (int c = 0; c < count; ++c) {
+        const int p0 = a + c * ce;
+        items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + ce), pos + c};
+      }
+      split_rows[split_base + atomicAdd(&nsplit, 1)] = SplitRow{(int32_t)i, pos, count, 0};
+    } else {
+      items[pos] = Item{(int32_t)i, a, a + m, cls == 1 ? kNoSlot : 0};
     }
-    split_rows[split_base + slocal] = SplitRow{(int32_t)i, pos, count, 0};
-  } else {
-    items[pos] = Item{(int32_t)i, a, a + m, cls == 1 ? kNoSlot : 0};
   }
 }
 
 int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
                    hipStream_t st) {
   if (pr.n > 0) {
-    const unsigned g = grid_for(pr.n, 256);
+    const unsigned g = grid_for(pr.n, kBinRowsPerBlock);
     k_num_bin_count<<<g, 256, 0, st>>>(pr, th, ctr);
     k_num_bin_scan<<<1, 1, 0, st>>>(ctr);
     k_num_bin_fill<<<g, 256, 0, st>>>(pr, th, items, split_rows, ctr);

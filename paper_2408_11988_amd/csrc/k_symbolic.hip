@@ -115,8 +115,9 @@ __global__ void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
   __shared__ int32_t hist[kBins];
   if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < pr.n) {
+  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
+  const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     const int m = pr.arp[i + 1] - pr.arp[i];
     int bin, count;
     sym_bin(m, split_nnz, bin, count);
@@ -136,31 +137,39 @@ __global__ void k_sym_bin_scan(Counters* ctr) {
   ctr->sym_total = off;
 }
 
-// Items are placed with one global reservation per bin per workgroup; the
-// slot inside the workgroup's range comes from an LDS counter.
+// Items are placed with one global reservation per bin per workgroup (its
+// counts from a first pass over its rows); the slot inside the workgroup's
+// range comes from an LDS counter in the second pass.
 __global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Counters* ctr) {
   __shared__ int32_t cnt[kBins], base[kBins];
   if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int a = 0, m = 0, bin = 0, count = 0, local = 0;
-  if (i < pr.n) {
-    a = pr.arp[i];
-    m = pr.arp[i + 1] - a;
-    sym_bin(m, split_nnz, bin, count);
-    if (count) local = atomicAdd(&cnt[bin], count);
+  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
+  const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    int bin, count;
+    sym_bin(pr.arp[i + 1] - pr.arp[i], split_nnz, bin, count);
+    if (count) atomicAdd(&cnt[bin], count);
   }
   __syncthreads();
-  if (threadIdx.x < kBins && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&ctr->sym_cursor[threadIdx.x], cnt[threadIdx.x]);
+  if (threadIdx.x < kBins) {
+    if (cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&ctr->sym_cursor[threadIdx.x], cnt[threadIdx.x]);
+    cnt[threadIdx.x] = 0;
+  }
   __syncthreads();
-  if (!count) return;
-  const int pos = base[bin] + local;
-  if (m <= split_nnz) {
-    items[pos] = Item{(int32_t)i, a, a + m, 0};
-  } else {
-    for (int c = 0; c < count; ++c) {
-      const int p0 = a + c * split_nnz;
-      items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + split_nnz), kSplitFlag | c};
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const int a = pr.arp[i], m = pr.arp[i + 1] - a;
+    int bin, count;
+    sym_bin(m, split_nnz, bin, count);
+    if (!count) continue;
+    const int pos = base[bin] + atomicAdd(&cnt[bin], count);
+    if (m <= split_nnz) {
+      items[pos] = Item{(int32_t)i, a, a + m, 0};
+    } else {
+      for (int c = 0; c < count; ++c) {
+        const int p0 = a + c * split_nnz;
+        items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + split_nnz), kSplitFlag | c};
+      }
     }
   }
 }
@@ -171,7 +180,7 @@ int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* 
     TSS_CHECK_LAUNCH();
     return TSSPGEMM_OK;
   }
-  const unsigned g = grid_for(pr.n, 256);
+  const unsigned g = grid_for(pr.n, kBinRowsPerBlock);
   k_sym_bin_count<<<g, 256, 0, st>>>(pr, split_nnz, ctr);
   k_sym_bin_scan<<<1, 1, 0, st>>>(ctr);
   k_sym_bin_fill<<<g, 256, 0, st>>>(pr, split_nnz, items, ctr);
@@ -196,14 +205,15 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_light(SymParams sp) {
   if (row >= pr.n) return;
   const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
   if (p1 - p0 > kSlotRowMax) return;  // a heavy row: done from the item list
-  uint32_t mword = 0u;
+  uint32_t mword = 0u, need = 0xffffffffu;
   bool work = p1 > p0;
   if (sp.mask) {
     mword = sp.mask[row * WP + w];
-    uint32_t need = ~mword & (sp.active ? sp.active[w] : 0xffffffffu);
+    need = ~mword & (sp.active ? sp.active[w] : 0xffffffffu);
+    uint32_t any = need;
 #pragma unroll
-    for (int o = 1; o < WP; o <<= 1) need |= shfl_xor_u32(need, o);
-    work = work && need != 0u;
+    for (int o = 1; o < WP; o <<= 1) any |= shfl_xor_u32(any, o);
+    work = work && any != 0u;
   }
   uint32_t acc = 0u;
   int fl = 0;
@@ -218,13 +228,34 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_light(SymParams sp) {
         acc |= (x0 | x1) | (x2 | x3);
         fl += __popc(x0) + __popc(x1) + __popc(x2) + __popc(x3);
       }
-    }
-    for (; p < p1; ++p) {
-      const int k = aci[p];
-      if (fnz == nullptr || ((fnz[k >> 5] >> (k & 31)) & 1u)) {
-        const uint32_t x = bb[(int64_t)k * WP + w];
+      for (; p < p1; ++p) {
+        const uint32_t x = bb[(int64_t)aci[p] * WP + w];
         acc |= x;
         fl += __popc(x);
+      }
+    } else {
+      // B rows flagged empty are skipped; four A entries per step, their
+      // summary bits and B words loaded together
+      const uint64_t smask = (WP >= 64 ? ~0ull : ((1ull << WP) - 1ull)) << (WP >= 64 ? 0 : slot * WP);
+      for (; p < p1; p += 4) {
+        int k[4];
+        bool v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          v[u] = p + u < p1;
+          k[u] = v[u] ? aci[p + u] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = v[u] && ((fnz[k[u] >> 5] >> (k[u] & 31)) & 1u);
+        uint32_t x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = v[u] ? bb[(int64_t)k[u] * WP + w] : 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc |= x[u];
+          fl += __popc(x[u]);
+        }
+        if (sp.early_exit && (__ballot((need & ~acc) != 0u) & smask) == 0ull) break;
       }
     }
   }
@@ -255,15 +286,13 @@ __global__ __launch_bounds__(kBlock) void k_symbolic(SymParams sp) {
     const Item it = sp.items[t];
     const bool split = (it.aux & kSplitFlag) != 0;
     const int64_t row = it.row;
-    uint32_t mword = 0;
+    uint32_t mword = 0, need = 0xffffffffu;
     bool skip = false;
     if (sp.mask) {
       mword = sp.mask[row * WP + w];
-      if (!split) {
-        const uint32_t act = sp.active ? sp.active[w] : 0xffffffffu;
-        // every column that could be produced is masked out: nothing to do
-        skip = __ballot((~mword & act) != 0u) == 0ull;
-      }
+      need = ~mword & (sp.active ? sp.active[w] : 0xffffffffu);
+      // every column that could be produced is masked out: nothing to do
+      if (!split) skip = __ballot(need != 0u) == 0ull;
     }
     uint32_t acc = 0u;
     int fl = 0;
@@ -283,12 +312,32 @@ __global__ __launch_bounds__(kBlock) void k_symbolic(SymParams sp) {
           fl += __popc(x);
         }
       } else {
-        for (; p < it.p1; p += NS) {
-          const int k = aci[p];
-          if ((fnz[k >> 5] >> (k & 31)) & 1u) {
-            const uint32_t x = bb[(int64_t)k * WP + w];
-            acc |= x;
-            fl += __popc(x);
+        // wavefront-uniform steps of 4 * NS entries (entry base + slot + u NS),
+        // so the early-exit test below sees every lane
+        for (int base = it.p0; base < it.p1; base += 4 * NS) {
+          int k[4];
+          bool v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = base + slot + u * NS;
+            v[u] = q < it.p1;
+            k[u] = v[u] ? aci[q] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) v[u] = v[u] && ((fnz[k[u] >> 5] >> (k[u] & 31)) & 1u);
+          uint32_t x[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) x[u] = v[u] ? bb[(int64_t)k[u] * WP + w] : 0u;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            acc |= x[u];
+            fl += __popc(x[u]);
+          }
+          if (sp.early_exit) {
+            uint32_t all = acc;  // this word OR-ed over the slots
+#pragma unroll
+            for (int o = WP; o < kWave; o <<= 1) all |= shfl_xor_u32(all, o);
+            if (__ballot((need & ~all) != 0u) == 0ull) break;
           }
         }
       }

@@ -53,11 +53,12 @@ def _desc(nrows, ncols, nnz, ptr=0x1000):
     return _lib.CsrDesc(nrows, ncols, nnz, ptr, ptr, ptr)
 
 
-def _symbolic(lib, A, B, sr=0, rowptr=0x1000):
+def _symbolic(lib, A, B, sr=0, rowptr=0x1000, tune=None):
     plan = ctypes.c_void_p(None)
     nnz = ctypes.c_int64(-1)
     rc = lib.tsspgemm_symbolic(ctypes.byref(A) if A is not None else None, ctypes.byref(B) if B is not None else None,
-                               sr, None, None, rowptr, ctypes.byref(nnz), ctypes.byref(plan), None)
+                               sr, None, ctypes.byref(tune) if tune is not None else None, rowptr, ctypes.byref(nnz),
+                               ctypes.byref(plan), None)
     return rc, plan
 
 
@@ -79,6 +80,10 @@ def test_argument_errors_without_device(lib):
     assert rc == _lib.ERR_INVALID_ARG
     rc, _ = _symbolic(lib, _desc(4, 4, 1 << 40), _desc(4, 2, 0))
     assert rc == _lib.ERR_OVERFLOW
+    rc, plan = _symbolic(lib, _desc(4, 4, 0), _desc(4, 2, 0), tune=_lib.Tuning(0, 0, 0, 0, 9, 0))
+    assert rc == _lib.ERR_INVALID_ARG and b"accumulator" in lib.tsspgemm_last_error() and not plan.value
+    rc, _ = _symbolic(lib, _desc(4, 4, 0), _desc(4, 2048, 0), tune=_lib.Tuning(0, 0, 0, 0, 1, 0))
+    assert rc == _lib.ERR_UNSUPPORTED  # the LDS strip needs d <= 1024
     bad = _lib.CsrDesc(4, 4, 3, 0x1000, None, 0x1000)  # nnz > 0 but no column array
     rc, _ = _symbolic(lib, bad, _desc(4, 2, 0))
     assert rc == _lib.ERR_INVALID_ARG

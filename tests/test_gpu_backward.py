@@ -185,3 +185,21 @@ def test_embedding_scale20_sampled():
     sc = oracle.grad_b_rows(a.rp, a.ci, np.abs(a.val), b.rp, b.ci, crp, cci, np.abs(w64), krows)
     sel = np.concatenate([np.arange(b.rp[k], b.rp[k + 1]) for k in krows])
     assert np.all(np.abs(gb[sel] - ref) <= RTOL * sc + 1e-30)
+
+
+def test_gradients_reject_masked_plan():
+    """A forward product taken with a complement mask drops entries of pat(C)
+    that the gradient formulas read, so the library refuses such a plan."""
+    import paper_2408_11988_amd as tss
+
+    rng = np.random.default_rng(77)
+    n, d = 64, 16
+    a = random_csr(rng, n, n, 0.1)
+    b = random_csr(rng, n, d, 0.3)
+    m = random_csr(rng, n, d, 0.2)
+    A, B, M = to_dev(a), to_dev(b), to_dev(m, with_values=False)
+    C, plan = tss.spgemm(A, B, mask=M, return_plan=True)
+    G = C.with_vals(torch.ones_like(C.vals))
+    with pytest.raises(tss.TSSpGEMMError) as e:
+        tss.grad_a(plan, A, B, G)
+    assert "mask" in str(e.value)

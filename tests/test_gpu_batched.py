@@ -73,10 +73,7 @@ def bt_group_lanes(pairs):
     nn = sum(B.nrows for _, B in pairs)
     nz = sum(B.nnz for _, B in pairs)
     mean = nz / nn if nn else 0
-    gl = 4
-    while gl < 64 and gl < mean:
-        gl *= 2
-    return gl
+    return 64 if mean > 48 else 32 if mean >= 8 else 16 if mean >= 4 else 8 if mean >= 2 else 4
 
 
 def test_graph_replays():

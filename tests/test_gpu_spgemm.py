@@ -33,41 +33,53 @@ def _tss():
     return tss
 
 
+ACCS = ["lds"]
+# thresholds that send rows of these small cases to every work class
+ALL_CLASSES = dict(light_max_flops=16, wave_max_flops=64, split_flops=256)
+
+
+@pytest.mark.parametrize("classes", ["default", "all"])
+@pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("d", D_VALUES)
-def test_plus_times_random(d):
+def test_plus_times_random(d, acc, classes):
     rng = np.random.default_rng(1000 + d)
     n = 300
     a = random_csr(rng, n, n, 0.03, empty_rows=0.2, dense_rows=2)
     b = random_csr(rng, n, d, min(0.5, 6.0 / d + 0.02), empty_rows=0.1)
-    note(f"plus_times random n={n} d={d} nnzA={a.nnz} nnzB={b.nnz}")
-    C = _tss().spgemm(to_dev(a), to_dev(b))
+    tun = dict(accumulator=acc, **(ALL_CLASSES if classes == "all" else {}))
+    note(f"plus_times random n={n} d={d} nnzA={a.nnz} nnzB={b.nnz} tuning={tun}")
+    C = _tss().spgemm(to_dev(a), to_dev(b), tuning=tun)
     torch.cuda.synchronize()
     frac = compare_f32(a, b, C)
     assert frac > 0.999
 
 
+@pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("d", [7, 64, 300])
-def test_plus_times_signed(d):
+def test_plus_times_signed(d, acc):
     rng = np.random.default_rng(2000 + d)
     n = 257
     a = random_csr(rng, n, n, 0.05, kind="normal", empty_rows=0.1, dense_rows=1)
     b = random_csr(rng, n, d, 0.2, kind="normal")
-    note(f"plus_times signed n={n} d={d}")
-    C = _tss().spgemm(to_dev(a), to_dev(b))
+    note(f"plus_times signed n={n} d={d} acc={acc}")
+    C = _tss().spgemm(to_dev(a), to_dev(b), tuning=dict(accumulator=acc, **ALL_CLASSES))
     torch.cuda.synchronize()
     compare_f32(a, b, C, signed=True)
 
 
+@pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("d", [3, 64, 129, 1024])
-def test_int32_exact(d):
+def test_int32_exact(d, acc):
     rng = np.random.default_rng(3000 + d)
     n = 200
     a = random_csr(rng, n, n, 0.05, kind="int", dense_rows=1)
     b = random_csr(rng, n, d, 0.1, kind="int")
-    note(f"int32 n={n} d={d}")
-    C = _tss().spgemm(to_dev(a, dtype=torch.int32), to_dev(b, dtype=torch.int32), semiring="plus_times_i32")
-    torch.cuda.synchronize()
-    compare_int(a, b, C)
+    note(f"int32 n={n} d={d} acc={acc}")
+    for tun in (dict(accumulator=acc), dict(accumulator=acc, **ALL_CLASSES)):
+        C = _tss().spgemm(to_dev(a, dtype=torch.int32), to_dev(b, dtype=torch.int32), semiring="plus_times_i32",
+                          tuning=tun)
+        torch.cuda.synchronize()
+        compare_int(a, b, C)
 
 
 @pytest.mark.parametrize("d", [1, 40, 64, 512, 1024])
@@ -99,22 +111,24 @@ def test_or_and_and_masks(d):
     C = tss.masked_bool(A, B, torch.from_numpy(bits.view(np.int32)).cuda())
     compare_bool(a, b, C, mask=m)
     # plus-times with a complement mask drops the masked entries, values unchanged
-    note(f"plus_times csr mask n={n} d={d}")
     a2 = synth.Csr(n, n, a.rp, a.ci, rng.random(a.nnz).astype(np.float32))
     b2 = synth.Csr(n, d, b.rp, b.ci, rng.random(b.nnz).astype(np.float32))
-    C = tss.spgemm(to_dev(a2), to_dev(b2), mask=M)
-    g_rp, g_ci, g_val = C.to_host()
     rp, ci = oracle.spgemm_bool(a.rp, a.ci, b.rp, b.ci, m.rp, m.ci)
-    assert np.array_equal(g_rp.astype(np.int64), rp) and np.array_equal(g_ci, ci)
     frp, fci, fval = oracle.spgemm(a2.rp, a2.ci, a2.val, b2.rp, b2.ci, b2.val)
     full = {(i, j): v for i in range(n) for j, v in zip(fci[frp[i]:frp[i + 1]], fval[frp[i]:frp[i + 1]])}
-    ref = np.array([full[(i, j)] for i in range(n) for j in g_ci[g_rp[i]:g_rp[i + 1]]])
-    assert np.all(np.abs(g_val - ref) <= 1e-5 * np.abs(ref))
+    for acc in ACCS:
+        note(f"plus_times csr mask n={n} d={d} acc={acc}")
+        C = tss.spgemm(to_dev(a2), to_dev(b2), mask=M, tuning=dict(accumulator=acc, **ALL_CLASSES))
+        g_rp, g_ci, g_val = C.to_host()
+        assert np.array_equal(g_rp.astype(np.int64), rp) and np.array_equal(g_ci, ci)
+        ref = np.array([full[(i, j)] for i in range(n) for j in g_ci[g_rp[i]:g_rp[i + 1]]])
+        assert np.all(np.abs(g_val - ref) <= 1e-5 * np.abs(ref))
 
 
 def test_modes_and_tuning_do_not_change_results():
     """Wavefront, workgroup and split rows, and every group width, give the
-    same bits (fixed accumulation orders)."""
+    same bits: every order of addition is fixed, and FP64 sums of exact
+    products of these sizes round to the same FP32."""
     rng = np.random.default_rng(5)
     n, d = 600, 128
     a = random_csr(rng, n, n, 0.02, dense_rows=6)
@@ -166,11 +180,12 @@ def test_plan_reuse_and_determinism():
     assert torch.equal(c_ci, C2.colidx) and torch.equal(c_v, C2.vals)
 
 
-def test_rmat_scale16_full():
+@pytest.mark.parametrize("acc", ["auto"] + ACCS)
+def test_rmat_scale16_full(acc):
     a, b = synth.workload_rmat_plain(scale=16, d=128)
     tss = _tss()
-    note(f"R-MAT 16 d=128 nnzA={a.nnz} nnzB={b.nnz}")
-    C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True)
+    note(f"R-MAT 16 d=128 nnzA={a.nnz} nnzB={b.nnz} acc={acc}")
+    C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True, tuning=dict(accumulator=acc))
     torch.cuda.synchronize()
     frac = compare_f32(a, b, C, threads=8)
     assert frac > 0.999
@@ -178,13 +193,15 @@ def test_rmat_scale16_full():
     assert st["nnz"] == C.nnz
 
 
-def test_rmat_scale20_d128_sampled():
+@pytest.mark.parametrize("acc", ["auto"] + ACCS)
+def test_rmat_scale20_d128_sampled(acc):
     """Full-size plain workload (R-MAT scale 20, d = 128): every row checked for
-    the invariants, the heaviest and random rows against the oracle."""
+    the invariants, the heaviest and random rows against the oracle. "auto" is
+    the configuration the benchmark times."""
     a, b = synth.workload_rmat_plain(scale=20, d=128)
     tss = _tss()
-    note(f"R-MAT 20 d=128 nnzA={a.nnz} nnzB={b.nnz}")
-    C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True)
+    note(f"R-MAT 20 d=128 nnzA={a.nnz} nnzB={b.nnz} acc={acc}")
+    C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True, tuning=dict(accumulator=acc))
     torch.cuda.synchronize()
     g_rp, g_ci, _ = C.to_host()
     flops = oracle.row_flops(a.rp, a.ci, b.rp)
