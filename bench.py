@@ -190,16 +190,17 @@ def bench_batched(steps: int, warmup: int) -> dict:
     torch.cuda.synchronize()
     ms_graph = e[0].elapsed_time(e[1]) / steps
     flops = sum(bt.flops())
-    # the same 64 products as plain calls, one after the other (each synchronizes for nnz)
+    # the same 64 products as plain calls with default tuning, one after the
+    # other (each synchronizes for nnz)
     for _ in range(warmup):
-        for (A, B), t in zip(pairs, clean):
-            spgemm(A, B, tuning=t)
+        for A, B in pairs:
+            spgemm(A, B)
     torch.cuda.synchronize()
     reps = max(1, steps // 4)
     t0 = time.perf_counter()
     for _ in range(reps):
-        for (A, B), t in zip(pairs, clean):
-            spgemm(A, B, tuning=t)
+        for A, B in pairs:
+            spgemm(A, B)
     torch.cuda.synchronize()
     ms_seq = (time.perf_counter() - t0) * 1e3 / reps
     return {"workload": "64 instances: n log-uniform [2^14, 2^18], d in {32,64,128,256}, ER/R-MAT (deg 4-32), "

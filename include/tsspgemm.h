@@ -7,7 +7,7 @@
  * semiring, the latter optionally with a complement mask (the multi-source
  * BFS step of Sec. IV-A, Algorithm 3). The local multiply is row-wise
  * Gustavson (Sec. III-A, Eq. 1) with a dense accumulator of width d for
- * d <= 1024 and a hash accumulator above (Sec. III-C).
+ * d <= 1024 and a hash accumulator above (Sec. III-C), up to d = 65536.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -104,14 +104,17 @@ int32_t tsspgemm_bitmap_words(int32_t d);
 
 /* Symbolic phase (Sec. III-A, Eq. 1 structure; the symbolic nnz count of
  * Sec. III-D): computes flops per row (Sec. II-A), bins rows by work, the
- * output pattern as a bitmap accumulator, and C's row pointers.
+ * output pattern (a d-bit bitmap per row for d <= 1024; per-row hash sets
+ * for the hash accumulator) and C's row pointers.
  *   A: n x n, B: n x d (vals unused). sr: tsspgemm_semiring the plan is for.
  *   M: complement mask or NULL. tune: NULL for defaults.
  *   c_rowptr: caller-allocated, n + 1 int32, written.
  *   c_nnz: HOST out, nnz(C). Synchronizes `stream`.
  *   plan: in/out. If *plan is non-NULL its workspace is reused (grown as
  *   needed); otherwise a new plan is created. Destroy with tsspgemm_plan_destroy.
- * Errors: INVALID_ARG, UNSUPPORTED (d > 1024 with the dense accumulator
+ *   With the hash accumulator the mask is copied into the plan (the numeric
+ *   phase tests it again); the caller's mask may be freed after this call.
+ * Errors: INVALID_ARG, UNSUPPORTED (d > 65536, or d > 1024 with the LDS strip
  * forced), OVERFLOW (nnz(C) > INT32_MAX), NOMEM, HIP. */
 int tsspgemm_symbolic(const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t sr, const tsspgemm_mask* M,
                       const tsspgemm_tuning* tune, int32_t* c_rowptr, int64_t* c_nnz, tsspgemm_plan* plan,
@@ -122,6 +125,9 @@ int tsspgemm_symbolic(const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t sr, 
  * must have the patterns the plan was built with; their values may differ
  * between calls (so one plan serves every training step).
  *   c_colidx: nnz(C) int32, c_vals: nnz(C) float/int32 (NULL for OR_AND).
+ * FP32 values are summed in FP64 and rounded once. With the LDS strip every
+ * order of addition is fixed (results repeat bit for bit); the hash
+ * accumulator adds with atomics in an order that may vary.
  * Asynchronous. Errors: INVALID_ARG, HIP. */
 int tsspgemm_numeric(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* c_colidx,
                      void* c_vals, void* stream);

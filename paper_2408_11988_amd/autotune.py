@@ -99,12 +99,54 @@ class Autotuner:
         return dict(best)
 
     def tune_batch(self, pairs, reps: int = 3) -> list:
-        """Per-instance thresholds; the batch's group width is the one chosen
-        for the instance with the most work."""
-        res = [self.tune(A, B, reps) for A, B in pairs]
-        if res:
-            heavy = max(range(len(res)), key=lambda t: res[t].get("ms", 0.0))
-            gl = res[heavy].get("group_lanes", 0)
-            for r in res:
-                r["group_lanes"] = gl
-        return res
+        """Thresholds and group width for a batch. One set of kernels runs
+        every instance, so the candidates are timed on the whole batched run
+        (coordinate descent as in tune(), same candidate lists), and every
+        instance gets the winner. Cached under the sorted instance keys."""
+        from .batched import Batched
+
+        if not pairs:
+            return []
+        keys = []
+        for A, B in pairs:
+            fl = int((torch.diff(B.rowptr).to(torch.int64)[A.colidx.to(torch.int64)]).sum()) if A.nnz else 0
+            keys.append(features(A, B, fl))
+        key = "batch:" + "|".join(sorted(keys))
+        if key in self.cache:
+            best = dict(self.cache[key])
+        else:
+            def run_ms(cfg):
+                bt = Batched(pairs, [cfg] * len(pairs))
+                bt.run()
+                s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                times = []
+                for _ in range(reps):
+                    s.record()
+                    bt.run()
+                    e.record()
+                    e.synchronize()
+                    times.append(s.elapsed_time(e))
+                times.sort()
+                return times[len(times) // 2]
+
+            best = {k: v for k, v in DEFAULT.items()}
+            best_t = run_ms(best)
+            for gl in GROUP_LANES:
+                cand = dict(best, group_lanes=gl)
+                t = run_ms(cand)
+                if t < best_t:
+                    best, best_t = cand, t
+            for lm in LIGHT_MAX:
+                cand = dict(best, light_max_flops=lm)
+                t = run_ms(cand)
+                if t < best_t:
+                    best, best_t = cand, t
+            for wm, sp in WAVE_SPLIT:
+                cand = dict(best, wave_max_flops=wm, split_flops=sp)
+                t = run_ms(cand)
+                if t < best_t:
+                    best, best_t = cand, t
+            best["ms"] = round(best_t, 4)
+            self.cache[key] = dict(best)
+        cfg = {k: v for k, v in best.items() if k != "ms"}
+        return [dict(cfg) for _ in pairs]

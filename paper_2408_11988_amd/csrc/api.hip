@@ -99,6 +99,7 @@ void plan_free(Plan* p) {
     b->release();
   if (p->host_ctr) (void)hipHostFree(p->host_ctr);
   p->host_ctr = nullptr;
+  p->hstrips_zeroed = 0;
 }
 
 // Lanes per B row from the mean B row length: a B row is read GL entries per
@@ -123,8 +124,97 @@ void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tu
   if (r.wave_max_flops < r.light_max_flops) r.wave_max_flops = r.light_max_flops;
   if (r.split_flops < r.wave_max_flops) r.split_flops = r.wave_max_flops;
   if (r.sym_split_nnz <= 0) r.sym_split_nnz = 2048;
-  if (r.accumulator == TSSPGEMM_ACC_AUTO) r.accumulator = TSSPGEMM_ACC_LDS_STRIP;
+  if (r.accumulator == TSSPGEMM_ACC_AUTO)
+    r.accumulator = B->ncols > kMaxDenseD ? TSSPGEMM_ACC_HASH : TSSPGEMM_ACC_LDS_STRIP;
   *out = r;
+}
+
+// Symbolic phase with the hash accumulator: per-row distinct-column counts
+// (k_hash.hip), then the same count scan as the bitmap path. The mask is
+// copied into the plan, since the numeric phase tests it again.
+static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, const tsspgemm_mask* M,
+                             const tsspgemm_tuning& tn, int32_t* c_rowptr, int64_t* c_nnz, hipStream_t st) {
+  int rc;
+  const int64_t n = A->nrows, d = B->ncols;
+  p->n = n;
+  p->d = d;
+  p->wp = bitmap_words((int32_t)(d < 1 ? 1 : d));
+  p->sr = sr;
+  p->tune = tn;
+  p->tune.accumulator = TSSPGEMM_ACC_HASH;
+  p->crp = c_rowptr;
+  p->a_nnz = A->nnz;
+  p->b_nnz = B->nnz;
+  p->ready = false;
+  p->cpos_ready = false;
+  p->hash = true;
+  p->masked = M && M->kind != TSSPGEMM_MASK_NONE;
+  if ((rc = plan_alloc_host(p))) return rc;
+  if ((rc = p->ctr.ensure(sizeof(Counters))) || (rc = p->flops.ensure((size_t)n * 8)) ||
+      (rc = p->cnt.ensure((size_t)n * 4)) || (rc = p->scan.ensure((size_t)scan_block_sums_capacity(n) * 8)))
+    return rc;
+  Counters* ctr = (Counters*)p->ctr.p;
+  if (validate_enabled()) {
+    if ((rc = validate_on_device(A, "A", ctr, p->host_ctr, st)) || (rc = validate_on_device(B, "B", ctr, p->host_ctr, st)))
+      return rc;
+    if (M && M->kind == TSSPGEMM_MASK_COMPLEMENT_CSR && (rc = validate_on_device(M->csr, "mask", ctr, p->host_ctr, st)))
+      return rc;
+  }
+  p->hmask = HashMask{};
+  if (M && M->kind == TSSPGEMM_MASK_COMPLEMENT_CSR) {
+    const tsspgemm_csr* m = M->csr;
+    if ((rc = p->hmask_rp.ensure((size_t)(n + 1) * 4)) || (rc = p->hmask_ci.ensure((size_t)m->nnz * 4))) return rc;
+    TSS_HIP(hipMemcpyAsync(p->hmask_rp.p, m->rowptr, (size_t)(n + 1) * 4, hipMemcpyDeviceToDevice, st));
+    if (m->nnz > 0)
+      TSS_HIP(hipMemcpyAsync(p->hmask_ci.p, m->colidx, (size_t)m->nnz * 4, hipMemcpyDeviceToDevice, st));
+    p->hmask.rp = (const int32_t*)p->hmask_rp.p;
+    p->hmask.ci = (const int32_t*)p->hmask_ci.p;
+  } else if (M && M->kind == TSSPGEMM_MASK_COMPLEMENT_BITMAP) {
+    const size_t bytes = (size_t)n * p->wp * 4;
+    if ((rc = p->hmask_bits.ensure(bytes))) return rc;
+    if (bytes) TSS_HIP(hipMemcpyAsync(p->hmask_bits.p, M->bits, bytes, hipMemcpyDeviceToDevice, st));
+    p->hmask.bits = (const uint32_t*)p->hmask_bits.p;
+    p->hmask.wpm = p->wp;
+  }
+  Problem pr{};
+  pr.n = (int32_t)n;
+  pr.d = (int32_t)d;
+  pr.wp = p->wp;
+  pr.arp = A->rowptr;
+  pr.aci = A->colidx;
+  pr.brp = B->rowptr;
+  pr.bci = B->colidx;
+  pr.flops = (int64_t*)p->flops.p;
+  pr.crp = c_rowptr;
+  if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
+  if ((rc = launch_hash_symbolic(pr, p->hmask, (int32_t*)p->cnt.p, &ctr->hash_error, st))) return rc;
+  pr.cbits = nullptr;  // counts come from cnt
+  if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
+  TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  TSS_HIP(hipStreamSynchronize(st));
+  const Counters& h = *p->host_ctr;
+  if (h.hash_error) {
+    set_error("hash accumulator: inconsistent row table");
+    return TSSPGEMM_ERR_HIP;
+  }
+  p->nnz = h.nnz_total;
+  p->flops_total = h.flops_total;
+  p->n_split_items = p->n_block_items = p->n_wave_rows = p->n_light_rows = p->n_split_rows = 0;
+  *c_nnz = h.nnz_total;
+  if (h.nnz_total > INT32_MAX) {
+    set_error("nnz(C) = " + std::to_string(h.nnz_total) + " exceeds INT32_MAX");
+    return TSSPGEMM_ERR_OVERFLOW;
+  }
+  if (sr != TSSPGEMM_OR_AND && n > 0) {
+    const size_t bytes = (size_t)hash_dense_workers(d) * d * (sr == TSSPGEMM_PLUS_TIMES_F32 ? 8 : 4);
+    if ((rc = p->hstrips.ensure(bytes))) return rc;
+    if (p->hstrips_zeroed < bytes) {  // the long-row kernel leaves its strips all-zero
+      if ((rc = launch_zero_bytes(p->hstrips.p, bytes, st))) return rc;
+      p->hstrips_zeroed = bytes;
+    }
+  }
+  p->ready = true;
+  return TSSPGEMM_OK;
 }
 
 // Symbolic phase shared by tsspgemm_symbolic and tsspgemm_masked_bool.
@@ -171,14 +261,18 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
     set_error("unknown accumulator");
     return TSSPGEMM_ERR_INVALID_ARG;
   }
-  if (tn.accumulator == TSSPGEMM_ACC_HASH) {
-    set_error("the hash accumulator is not available in this build");
+  if (B->ncols > kMaxDenseD && tn.accumulator == TSSPGEMM_ACC_LDS_STRIP) {
+    set_error("the LDS strip accumulator needs d <= 1024");
     return TSSPGEMM_ERR_UNSUPPORTED;
   }
-  if (B->ncols > kMaxDenseD) {
-    set_error("d > 1024 needs the hash accumulator, which this build does not provide");
-    return TSSPGEMM_ERR_UNSUPPORTED;
+  if (B->ncols > kMaxDenseD || tn.accumulator == TSSPGEMM_ACC_HASH) {
+    if (B->ncols > kHashMaxD) {
+      set_error("d > " + std::to_string(kHashMaxD) + " is not supported");
+      return TSSPGEMM_ERR_UNSUPPORTED;
+    }
+    return run_symbolic_hash(p, A, B, sr, M, tn, c_rowptr, c_nnz, st);
   }
+  p->hash = false;
   const int64_t n = A->nrows, d = B->ncols;
   const int wp = bitmap_words(d);
   p->n = n;
@@ -313,6 +407,7 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   pr.cci = c_colidx;
   pr.cval = c_vals;
   if (p->nnz == 0) return TSSPGEMM_OK;
+  if (p->hash) return launch_hash_numeric(p->sr, pr, p->hmask, p->hstrips.p, &((Counters*)p->ctr.p)->hash_error, st);
   if (!vals) return launch_emit_pattern(pr, st);
   NumParams np{};
   np.pr = pr;

@@ -49,6 +49,11 @@ struct Plan {
   DevBuf cpos;             // dL/dB: per C bitmap word, (position of its first entry) << 32 | bits
   bool cpos_ready = false;
   bool masked = false;     // symbolic phase ran with a complement mask
+  bool hash = false;       // hash accumulator plan (no bitmaps, no work lists)
+  DevBuf hmask_rp, hmask_ci, hmask_bits;  // hash plan: copy of the complement mask
+  HashMask hmask{};
+  DevBuf hstrips;          // hash plan: private d-wide strips of the long-row kernel (kept zero)
+  size_t hstrips_zeroed = 0;
   Counters* host_ctr = nullptr;  // pinned
   // results of the last symbolic call
   int64_t nnz = 0, flops_total = 0, n_split_items = 0, n_block_items = 0, n_wave_rows = 0, n_light_rows = 0;

@@ -18,6 +18,7 @@
 // word's bits and the position of its first entry. Long A^T rows are cut into chunks whose
 // partial sums a second kernel adds in chunk order.
 #include "api_internal.hpp"
+#include "dev_numeric.hpp"
 
 namespace tss {
 
@@ -46,42 +47,68 @@ struct GradAParams {
   int32_t n_wg_items, n_heavy_records, n_light;
 };
 
-// Dot products for A entries [p0, p1) of one row, groups g0, g0+gstride, ...
-template <int GL>
-__device__ __forceinline__ void grad_a_range(const GradAParams& gp, int p0, int p1, int g0, int gstride,
-                                             const float* strip) {
+// Dot products of staged A entries: stage[e] = (start, end) of B row k for
+// the entry base + e of the row, e in [0, nb); group grp of ngroups takes
+// blocks of U entries grp * U, (grp + ngroups) * U, ... Lanes of a group walk
+// the B row (column ids narrowed to IdxT) against the row's G strip; each
+// dot product is summed over the group in FP64 and rounded once.
+template <int GL, typename IdxT>
+__device__ __forceinline__ void grad_a_staged(const GradAParams& gp, int base, int nb, const int2* stage, int grp,
+                                              int ngroups, const float* strip) {
   constexpr int U = 4;
   const int gl = threadIdx.x % GL;
   const Problem& pr = gp.pr;
   const float* __restrict__ bval = (const float*)pr.bval;
-  for (int p = p0 + g0 * U; p < p1; p += gstride * U) {
+  const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
+  for (int e0 = grp * U; e0 < nb; e0 += ngroups * U) {
     int q[U], qe[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      q[u] = 0;
-      qe[u] = 0;
-      if (p + u < p1) {
-        const int k = pr.aci[p + u];
-        q[u] = pr.brp[k];
-        qe[u] = pr.brp[k + 1];
+      int2 r = make_int2(0, 0);
+      if (e0 + u < nb) r = stage[e0 + u];
+      q[u] = r.x + gl;
+      qe[u] = r.y;
+    }
+    int jj[U];
+    float bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      jj[u] = 0;
+      bv[u] = 0.0f;
+      if (q[u] < qe[u]) {
+        jj[u] = bci[q[u]];
+        bv[u] = bval[q[u]];
       }
     }
-    double s[U];
+    double sum[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      s[u] = 0.0;
-      for (int t = q[u] + gl; t < qe[u]; t += GL) s[u] += (double)bval[t] * (double)strip[pr.bci[t]];
+      sum[u] = q[u] < qe[u] ? (double)bv[u] * (double)strip[jj[u]] : 0.0;
+      for (int t = q[u] + GL; t < qe[u]; t += GL) sum[u] += (double)bval[t] * (double)strip[bci[t]];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const double v = group_sum<GL>(s[u]);
-      if (gl == 0 && p + u < p1) gp.grad_a[p + u] = (float)v;
+      const double v = group_sum<GL>(sum[u]);
+      if (gl == 0 && e0 + u < nb) gp.grad_a[base + e0 + u] = (float)v;
     }
   }
 }
 
-// Workgroup items (split chunks, workgroup rows) and wavefront rows.
-template <int GL>
+// Stage entries [base, base + nb) of A (nb <= the caller's lanes): lane t of
+// the stagers loads entry base + t and its B row bounds.
+__device__ __forceinline__ void grad_a_stage(const Problem& pr, int base, int nb, int t, int2* stage) {
+  int2 e = make_int2(0, 0);
+  if (t < nb) {
+    const int k = pr.aci[base + t];
+    e = make_int2(pr.brp[k], pr.brp[k + 1]);
+  }
+  stage[t] = e;
+}
+
+// Workgroup items (split chunks, workgroup rows) and wavefront rows. A
+// wavefront stages 64 A entries at a time (coalesced) and its 64/GL groups
+// share them.
+template <int GL, typename IdxT>
 __global__ __launch_bounds__(kBlock) void k_grad_a(GradAParams gp) {
   extern __shared__ __align__(16) float gstrip[];
   const Problem& pr = gp.pr;
@@ -89,38 +116,56 @@ __global__ __launch_bounds__(kBlock) void k_grad_a(GradAParams gp) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = blockIdx.x;
   constexpr int GPW = kWave / GL;
+  int2* stage = (int2*)(gstrip + kWavesPerBlock * d) + wave * kWave;
   if (g < gp.n_wg_items) {
     const Item it = gp.items[g];
     float* strip = gstrip;
     for (int q = pr.crp[it.row] + threadIdx.x; q < pr.crp[it.row + 1]; q += kBlock) strip[gp.gci[q]] = gp.gval[q];
     __syncthreads();
-    grad_a_range<GL>(gp, it.p0, it.p1, threadIdx.x / GL, kBlock / GL, strip);
+    for (int base = it.p0 + kWave * wave; base < it.p1; base += kWave * kWavesPerBlock) {
+      const int nb = min(kWave, it.p1 - base);
+      grad_a_stage(pr, base, nb, lane, stage);
+      wave_sync();
+      grad_a_staged<GL, IdxT>(gp, base, nb, stage, lane / GL, GPW, strip);
+      wave_sync();
+    }
   } else {
     const int64_t idx = (int64_t)gp.n_wg_items + 4 * (int64_t)(g - gp.n_wg_items) + wave;
     if (idx >= gp.n_heavy_records) return;
     const Item it = gp.items[idx];
     float* strip = gstrip + wave * d;
     for (int q = pr.crp[it.row] + lane; q < pr.crp[it.row + 1]; q += kWave) strip[gp.gci[q]] = gp.gval[q];
-    gsync();
-    grad_a_range<GL>(gp, it.p0, it.p1, lane / GL, GPW, strip);
+    wave_sync();
+    for (int base = it.p0; base < it.p1; base += kWave) {
+      const int nb = min(kWave, it.p1 - base);
+      grad_a_stage(pr, base, nb, lane, stage);
+      wave_sync();
+      grad_a_staged<GL, IdxT>(gp, base, nb, stage, lane / GL, GPW, strip);
+      wave_sync();
+    }
   }
 }
 
-// Light rows: one group (and one strip) per row.
-template <int GL>
+// Light rows: one group (one strip, GL staged entries) per row.
+template <int GL, typename IdxT>
 __global__ __launch_bounds__(kBlock) void k_grad_a_light(GradAParams gp) {
   extern __shared__ __align__(16) float gstrip[];
   constexpr int G = kBlock / GL;
   const Problem& pr = gp.pr;
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
   float* strip = gstrip + grp * pr.d;
+  int2* stage = (int2*)(gstrip + G * pr.d) + grp * GL;
   const Item* items = gp.items + gp.n_heavy_records;
   for (int64_t t = (int64_t)blockIdx.x * G + grp; t < gp.n_light; t += (int64_t)gridDim.x * G) {
     const Item it = items[t];
     for (int q = pr.crp[it.row] + gl; q < pr.crp[it.row + 1]; q += GL) strip[gp.gci[q]] = gp.gval[q];
-    gsync();
-    grad_a_range<GL>(gp, it.p0, it.p1, 0, 1, strip);
-    gsync();
+    for (int base = it.p0; base < it.p1; base += GL) {
+      const int nb = min(GL, it.p1 - base);
+      grad_a_stage(pr, base, nb, gl, stage);
+      wave_sync();
+      grad_a_staged<GL, IdxT>(gp, base, nb, stage, 0, 1, strip);
+      wave_sync();
+    }
   }
 }
 
@@ -251,13 +296,17 @@ int launch_build_recs(int64_t n, int wp, const uint32_t* bits, const int32_t* ro
 }
 
 // One group of GL lanes per item, items walked with a grid stride. Lanes own
-// the B row's entries (GL at a time); a lane's sum runs over the item's
-// A^T entries in order.
+// the B row's entries (GL at a time); a lane's sum runs over the item's A^T
+// entries in order. The group loads GL A^T entries at once (row i and the
+// value A(i,k), coalesced) and shares them through LDS, so the per-entry
+// chain is the record of G's row and the G value only.
 template <int GL>
 __global__ __launch_bounds__(kBlock) void k_grad_b(GradBParams gb) {
   constexpr int G = kBlock / GL;
   constexpr int U = 8;
+  __shared__ int2 stage_s[kBlock];
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
+  int2* stage = stage_s + grp * GL;
   const Problem& pr = gb.pr;
   const float* __restrict__ aval = (const float*)pr.aval;
   const int wp = pr.wp;
@@ -273,33 +322,39 @@ __global__ __launch_bounds__(kBlock) void k_grad_b(GradBParams gb) {
       const int jw = j >> 5;
       const uint32_t below = (1u << (j & 31)) - 1u;
       double acc = 0.0;
-      for (int x = it.p0; x < it.p1; x += U) {
-        int i[U];
-        int pa[U];
+      for (int xb = it.p0; xb < it.p1; xb += GL) {
+        const int nb = min(GL, it.p1 - xb);
+        int2 e = make_int2(0, 0);
+        if (gl < nb) {
+          e.x = gb.atci[xb + gl];
+          e.y = __builtin_bit_cast(int32_t, aval[gb.perm[xb + gl]]);
+        }
+        wave_sync();
+        stage[gl] = e;
+        wave_sync();
+        for (int s = 0; s < nb; s += U) {
+          int i[U];
+          float a[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          i[u] = -1;
-          pa[u] = 0;
-          if (x + u < it.p1) {
-            i[u] = gb.atci[x + u];
-            pa[u] = gb.perm[x + u];
+          for (int u = 0; u < U; ++u) {
+            int2 r = make_int2(-1, 0);
+            if (s + u < nb) r = stage[s + u];
+            i[u] = r.x;
+            a[u] = __builtin_bit_cast(float, r.y);
           }
-        }
-        float a[U];
-        uint64_t r[U];
+          uint64_t r[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          a[u] = i[u] >= 0 ? aval[pa[u]] : 0.0f;
-          r[u] = (own && i[u] >= 0) ? gb.cpos[(int64_t)i[u] * wp + jw] : 0;
-        }
-        float g[U];
+          for (int u = 0; u < U; ++u) r[u] = (own && i[u] >= 0) ? gb.cpos[(int64_t)i[u] * wp + jw] : 0ull;
+          float g[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          g[u] = 0.0f;
-          if (own && i[u] >= 0) g[u] = gb.gval[(uint32_t)(r[u] >> 32) + __popc((uint32_t)r[u] & below)];
-        }
+          for (int u = 0; u < U; ++u) {
+            g[u] = 0.0f;
+            if (own && i[u] >= 0) g[u] = gb.gval[(uint32_t)(r[u] >> 32) + __popc((uint32_t)r[u] & below)];
+          }
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)g[u];
+          for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)g[u];
+        }
+        wave_sync();
       }
       if (own) {
         if (it.aux == kNoSlot)
@@ -330,6 +385,10 @@ static int check_grad_args(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B
   if (!p || !p->ready || p->sr != TSSPGEMM_PLUS_TIMES_F32) {
     set_error(std::string(who) + ": needs the plus-times FP32 plan of the forward product");
     return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  if (p->hash) {
+    set_error(std::string(who) + ": gradients need a plan with the dense accumulator (d <= 1024)");
+    return TSSPGEMM_ERR_UNSUPPORTED;
   }
   if (p->masked) {  // every product must land in pat(C) for G to be read on C's pattern
     set_error(std::string(who) + ": the forward plan was built with a mask");
@@ -384,20 +443,36 @@ static int run_grad_a(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, con
   gp.n_light = (int32_t)p->n_light_rows;
   const unsigned gz = grid_for(A->nnz, 256 * 4) > 8192 ? 8192 : grid_for(A->nnz, 256 * 4);
   k_zero_f32<<<gz, 256, 0, st>>>(grad_a, A->nnz);
-  const int gl = p->tune.group_lanes;
+  // a group per B row of dot product: the smallest power of two covering the
+  // mean B row length (the reduction over the group costs log2(GL) steps)
+  const double mean_b = p->n > 0 ? (double)B->nnz / (double)p->n : 0.0;
+  int gl = 4;
+  while (gl < 64 && gl < mean_b) gl <<= 1;
   const int64_t grid = gp.n_wg_items + (p->n_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
-  const size_t lds = (size_t)kWavesPerBlock * p->d * 4;
+  const size_t lds = (size_t)kWavesPerBlock * p->d * 4 + kBlock * sizeof(int2);
   const int lgl = light_group_lanes(gl, p->d, TSSPGEMM_PLUS_TIMES_I32);  // float strips: 4 bytes
-  const size_t llds = (size_t)(kBlock / lgl) * p->d * 4;
+  const size_t llds = (size_t)(kBlock / lgl) * p->d * 4 + kBlock * sizeof(int2);
   int64_t lgrid = (gp.n_light + (kBlock / lgl) - 1) / (kBlock / lgl);
   if (lgrid > 2048) lgrid = 2048;
-#define TSS_GA(GLV)                                                                              \
-  case GLV:                                                                                      \
-    if (grid > 0) k_grad_a<GLV><<<(unsigned)grid, kBlock, lds, st>>>(gp);                        \
+  const bool b8 = col_id_bytes(p->d) == 1;
+  gp.pr.bcol = p->bcol.p;
+#define TSS_GA(GLV)                                                                                    \
+  case GLV:                                                                                            \
+    if (grid > 0) {                                                                                    \
+      if (b8)                                                                                          \
+        k_grad_a<GLV, uint8_t><<<(unsigned)grid, kBlock, lds, st>>>(gp);                               \
+      else                                                                                             \
+        k_grad_a<GLV, uint16_t><<<(unsigned)grid, kBlock, lds, st>>>(gp);                              \
+    }                                                                                                  \
     break;
-#define TSS_GAL(GLV)                                                                             \
-  case GLV:                                                                                      \
-    if (lgrid > 0) k_grad_a_light<GLV><<<(unsigned)lgrid, kBlock, llds, st>>>(gp);               \
+#define TSS_GAL(GLV)                                                                                   \
+  case GLV:                                                                                            \
+    if (lgrid > 0) {                                                                                   \
+      if (b8)                                                                                          \
+        k_grad_a_light<GLV, uint8_t><<<(unsigned)lgrid, kBlock, llds, st>>>(gp);                       \
+      else                                                                                             \
+        k_grad_a_light<GLV, uint16_t><<<(unsigned)lgrid, kBlock, llds, st>>>(gp);                      \
+    }                                                                                                  \
     break;
   switch (gl) {
     TSS_GA(4) TSS_GA(8) TSS_GA(16) TSS_GA(32) TSS_GA(64)

@@ -122,7 +122,9 @@ __global__ __launch_bounds__(256) void k_bfs_levels(int64_t n, int32_t d, int wp
     }
     int32_t* out = levels + row * d + j0;
     if (vec) {
-      *reinterpret_cast<int4*>(out) = make_int4(l0, l1, l2, l3);
+      typedef int v4i __attribute__((ext_vector_type(4)));
+      const v4i v = {l0, l1, l2, l3};
+      __builtin_nontemporal_store(v, reinterpret_cast<v4i*>(out));  // streamed out, never re-read here
     } else {
       const int m = d - j0 < 4 ? d - j0 : 4;
       out[0] = l0;

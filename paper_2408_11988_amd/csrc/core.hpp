@@ -40,6 +40,8 @@ struct Counters {
   int32_t num_light_rows;
   int32_t num_split_rows;
   int32_t malformed;
+  int32_t hash_error;  // hash accumulator: a table or count was inconsistent
+  int32_t pad0;
   int64_t flops_total;
   int64_t nnz_total;
 };
@@ -125,5 +127,17 @@ int launch_build_recs(int64_t n, int wp, const uint32_t* bits, const int32_t* ro
 int launch_split_finalize(int sr, const Problem& pr, const SplitRow* rows, int32_t nrows, const double* partial,
                           const int32_t* ipartial, hipStream_t st);
 int launch_emit_pattern(const Problem& pr, hipStream_t st);
+
+// Hash accumulator (d > kMaxDenseD, or chosen by tuning), d <= kHashMaxD.
+constexpr int64_t kHashMaxD = 65536;
+struct HashMask {
+  const int32_t* rp;     // complement mask as CSR (sorted rows), or null
+  const int32_t* ci;
+  const uint32_t* bits;  // complement mask as bitmap rows of wpm words, or null
+  int64_t wpm;
+};
+int launch_hash_symbolic(const Problem& pr, const HashMask& m, int32_t* cnt, int32_t* err, hipStream_t st);
+int64_t hash_dense_workers(int64_t d);
+int launch_hash_numeric(int sr, const Problem& pr, const HashMask& m, void* strips, int32_t* err, hipStream_t st);
 
 }  // namespace tss

@@ -440,9 +440,13 @@ __global__ __launch_bounds__(kScanThreads) void k_count_rows(Problem pr, int32_t
     const int64_t i = base + u * kScanThreads + threadIdx.x;
     if (i < pr.n) {
       int c = 0;
-      const uint32_t* b = pr.cbits + i * pr.wp;
-      for (int w = 0; w < pr.wp; ++w) c += __popc(b[w]);
-      cnt[i] = c;
+      if (pr.cbits) {  // bitmap accumulator: count = popcount of the row
+        const uint32_t* b = pr.cbits + i * pr.wp;
+        for (int w = 0; w < pr.wp; ++w) c += __popc(b[w]);
+        cnt[i] = c;
+      } else {  // counts already in cnt (hash accumulator)
+        c = cnt[i];
+      }
       s += c;
       f += pr.flops[i];
     }

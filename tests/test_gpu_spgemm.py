@@ -17,6 +17,7 @@ from tests.gpu_util import compare_bool, compare_f32, compare_int, note, require
 pytestmark = pytest.mark.gpu
 
 D_VALUES = [1, 5, 31, 32, 33, 64, 100, 128, 255, 256, 512, 1000, 1024]
+WIDE_D = [1025, 2048, 5000, 65536]  # past the dense accumulator: the hash accumulator
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -33,7 +34,7 @@ def _tss():
     return tss
 
 
-ACCS = ["lds"]
+ACCS = ["lds", "hash"]
 # thresholds that send rows of these small cases to every work class
 ALL_CLASSES = dict(light_max_flops=16, wave_max_flops=64, split_flops=256)
 
@@ -54,6 +55,25 @@ def test_plus_times_random(d, acc, classes):
     assert frac > 0.999
 
 
+@pytest.mark.parametrize("d", WIDE_D)
+def test_plus_times_wide(d):
+    """d > 1024 (hash accumulator chosen automatically): a few dense A rows
+    make rows with hundreds to thousands of outputs (long-row kernel, d-bit
+    bitmap in the symbolic pass), the rest stay in the LDS tables."""
+    rng = np.random.default_rng(1500 + d)
+    n = 400
+    a = random_csr(rng, n, n, 0.02, empty_rows=0.2, dense_rows=3)
+    b = random_csr(rng, n, d, min(0.3, 12.0 / d), empty_rows=0.1)
+    note(f"plus_times wide n={n} d={d} nnzA={a.nnz} nnzB={b.nnz}")
+    C, plan = _tss().spgemm(to_dev(a), to_dev(b), return_plan=True)
+    torch.cuda.synchronize()
+    frac = compare_f32(a, b, C)
+    assert frac > 0.999
+    assert plan.stats()["flops"] == int(oracle.row_flops(a.rp, a.ci, b.rp).sum())
+    cnt = np.diff(C.rowptr.cpu().numpy())
+    assert cnt.max() > 512 and 0 < np.median(cnt[cnt > 0]) <= 512  # both numeric kernels ran
+
+
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("d", [7, 64, 300])
 def test_plus_times_signed(d, acc):
@@ -68,12 +88,14 @@ def test_plus_times_signed(d, acc):
 
 
 @pytest.mark.parametrize("acc", ACCS)
-@pytest.mark.parametrize("d", [3, 64, 129, 1024])
+@pytest.mark.parametrize("d", [3, 64, 129, 1024, 3000])
 def test_int32_exact(d, acc):
     rng = np.random.default_rng(3000 + d)
     n = 200
     a = random_csr(rng, n, n, 0.05, kind="int", dense_rows=1)
-    b = random_csr(rng, n, d, 0.1, kind="int")
+    b = random_csr(rng, n, d, min(0.1, 20.0 / d), kind="int")
+    if d > 1024 and acc == "lds":
+        pytest.skip("the LDS strip needs d <= 1024")
     note(f"int32 n={n} d={d} acc={acc}")
     for tun in (dict(accumulator=acc), dict(accumulator=acc, **ALL_CLASSES)):
         C = _tss().spgemm(to_dev(a, dtype=torch.int32), to_dev(b, dtype=torch.int32), semiring="plus_times_i32",
@@ -82,7 +104,7 @@ def test_int32_exact(d, acc):
         compare_int(a, b, C)
 
 
-@pytest.mark.parametrize("d", [1, 40, 64, 512, 1024])
+@pytest.mark.parametrize("d", [1, 40, 64, 512, 1024, 2000])
 def test_or_and_and_masks(d):
     rng = np.random.default_rng(4000 + d)
     n = 220
@@ -116,7 +138,7 @@ def test_or_and_and_masks(d):
     rp, ci = oracle.spgemm_bool(a.rp, a.ci, b.rp, b.ci, m.rp, m.ci)
     frp, fci, fval = oracle.spgemm(a2.rp, a2.ci, a2.val, b2.rp, b2.ci, b2.val)
     full = {(i, j): v for i in range(n) for j, v in zip(fci[frp[i]:frp[i + 1]], fval[frp[i]:frp[i + 1]])}
-    for acc in ACCS:
+    for acc in ACCS if d <= 1024 else ["hash"]:
         note(f"plus_times csr mask n={n} d={d} acc={acc}")
         C = tss.spgemm(to_dev(a2), to_dev(b2), mask=M, tuning=dict(accumulator=acc, **ALL_CLASSES))
         g_rp, g_ci, g_val = C.to_host()
@@ -153,6 +175,13 @@ def test_modes_and_tuning_do_not_change_results():
             assert np.array_equal(x, y), cfg
         st = p.stats()
         assert st["flops"] == plan.stats()["flops"]
+    # the hash accumulator: same structure, values within the tolerance (its
+    # sums may run in another order)
+    note("hash accumulator")
+    C = tss.spgemm(A, B, tuning=dict(accumulator="hash"))
+    got = C.to_host()
+    assert np.array_equal(ref_h[0], got[0]) and np.array_equal(ref_h[1], got[1])
+    compare_f32(a, b, C)
     # rows here have ~230 +- 70 products, the dense rows ~11500: all four classes occur
     st = tss.spgemm(A, B, tuning=dict(light_max_flops=200, wave_max_flops=260, split_flops=1000),
                     return_plan=True)[1].stats()
@@ -256,9 +285,19 @@ def test_error_paths_on_device():
     n = 64
     a = random_csr(rng, n, n, 0.1)
     big = random_csr(rng, n, 2048, 0.01)
-    note("d = 2048 without a hash accumulator")
+    note("d = 2048 with the LDS strip forced")
     with pytest.raises(_lib.TSSpGEMMError) as e:
-        tss.spgemm(to_dev(a), to_dev(big))
+        tss.spgemm(to_dev(a), to_dev(big), tuning=dict(accumulator="lds"))
+    assert e.value.code == _lib.ERR_UNSUPPORTED
+    huge = synth.Csr(n, 70000, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    note("d = 70000: beyond the hash accumulator")
+    with pytest.raises(_lib.TSSpGEMMError) as e:
+        tss.spgemm(to_dev(a), to_dev(huge))
+    assert e.value.code == _lib.ERR_UNSUPPORTED
+    note("gradients of a hash plan")
+    C, plan = tss.spgemm(to_dev(a), to_dev(big), return_plan=True)
+    with pytest.raises(_lib.TSSpGEMMError) as e:
+        tss.grad_a(plan, to_dev(a), to_dev(big), C.with_vals(torch.ones_like(C.vals)))
     assert e.value.code == _lib.ERR_UNSUPPORTED
     b = random_csr(rng, n, 32, 0.3)
     A, B = to_dev(a, with_values=False), to_dev(b, with_values=False)
