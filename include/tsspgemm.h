@@ -85,6 +85,15 @@ typedef enum {
   TSSPGEMM_ACC_HASH = 2
 } tsspgemm_accumulator;
 
+/* How the lanes of a group cover the products of the A entries they stage
+ * (LDS strip accumulator).
+ *   PER_B_ROW: each B row is read by group_lanes lanes, several rows in
+ *              flight; lanes past a short row's end idle.
+ *   FLAT:      the staged entries' products form one list (a scan of the B
+ *              row lengths) and lane t takes products t, t + width, ...;
+ *              pays when B rows are short next to the group width. */
+typedef enum { TSSPGEMM_PRODUCTS_AUTO = 0, TSSPGEMM_PRODUCTS_PER_B_ROW = 1, TSSPGEMM_PRODUCTS_FLAT = 2 } tsspgemm_products;
+
 /* Tuning knobs. A NULL tuning pointer, or a zero field, means "default".
  * Results (structure and values) do not depend on any of these. */
 typedef struct {
@@ -94,6 +103,7 @@ typedef struct {
   int32_t sym_split_nnz;   /* symbolic pass: rows with more A entries than this are split         */
   int32_t accumulator;     /* tsspgemm_accumulator: 0 auto, 1 LDS strip, 2 hash                    */
   int32_t light_max_flops; /* rows with at most this many products use one lane group            */
+  int32_t products;        /* tsspgemm_products: how lanes cover a row's products                  */
 } tsspgemm_tuning;
 
 typedef struct tsspgemm_plan_s* tsspgemm_plan;
@@ -184,7 +194,8 @@ int tsspgemm_transpose(const tsspgemm_csr* A, int32_t* at_rowptr, int32_t* at_co
  * rows drive grad_a and its output bitmap locates G(i,j). Sums are FP64 in a
  * fixed order, rounded once to FP32 (reproducible). Asynchronous.
  * Errors: INVALID_ARG (NULL plan or output, a plan of another semiring or
- * built with a mask, A / B / G / AT not matching the plan), HIP. */
+ * built with a mask, A / B / G / AT not matching the plan), UNSUPPORTED (a
+ * hash-accumulator plan), NOMEM, HIP. */
 int tsspgemm_grad_a(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_csr* B, const tsspgemm_csr* G,
                     float* grad_a, void* stream);
 int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,

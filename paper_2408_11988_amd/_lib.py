@@ -43,7 +43,7 @@ class MaskDesc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("group_lanes", ctypes.c_int32), ("wave_max_flops", ctypes.c_int32), ("split_flops", ctypes.c_int32),
                 ("sym_split_nnz", ctypes.c_int32), ("accumulator", ctypes.c_int32),
-                ("light_max_flops", ctypes.c_int32)]
+                ("light_max_flops", ctypes.c_int32), ("products", ctypes.c_int32)]
 
 
 class TSSpGEMMError(RuntimeError):

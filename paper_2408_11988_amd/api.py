@@ -81,12 +81,21 @@ def accumulator_code(v) -> int:
     return ACCUMULATORS[v] if isinstance(v, str) else int(v)
 
 
+PRODUCTS = {"auto": 0, "rows": 1, "flat": 2}
+
+
+def tuning_struct(t: dict) -> _lib.Tuning:
+    """A tuning dict (missing keys: defaults) as the C struct."""
+    prod = t.get("products", 0)
+    return _lib.Tuning(int(t.get("group_lanes", 0)), int(t.get("wave_max_flops", 0)), int(t.get("split_flops", 0)),
+                       int(t.get("sym_split_nnz", 0)), accumulator_code(t.get("accumulator", 0)),
+                       int(t.get("light_max_flops", 0)), PRODUCTS[prod] if isinstance(prod, str) else int(prod))
+
+
 def _tuning(t: dict | None):
     if not t:
         return None
-    return ctypes.byref(_lib.Tuning(int(t.get("group_lanes", 0)), int(t.get("wave_max_flops", 0)),
-                                    int(t.get("split_flops", 0)), int(t.get("sym_split_nnz", 0)),
-                                    accumulator_code(t.get("accumulator", 0)), int(t.get("light_max_flops", 0))))
+    return ctypes.byref(tuning_struct(t))
 
 
 class Plan:

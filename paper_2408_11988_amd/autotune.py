@@ -6,8 +6,9 @@ row and the product-count thresholds that send a row to a lane group, a
 wavefront, a workgroup, or split chunks. None of them changes a result (the
 structure and every value are identical for any choice), only time.
 
-The search is a coordinate descent: group width first, then the light-row
-threshold, then the wavefront / split thresholds, each candidate timed on the
+The search is a coordinate descent: group width first, then the product
+layout (per B row or flat), then the light-row threshold, then the wavefront /
+split thresholds, each candidate timed on the
 instance's numeric phase (its symbolic phase rebinds rows for the candidate).
 Results are cached per feature key in a JSON file.
 """
@@ -24,7 +25,8 @@ from .api import DeviceCsr, numeric, symbolic
 GROUP_LANES = (8, 16, 32, 64)
 LIGHT_MAX = (256, 512, 2048, 8192)
 WAVE_SPLIT = ((16384, 131072), (65536, 262144), (131072, 524288))
-DEFAULT = {"group_lanes": 0, "light_max_flops": 1024, "wave_max_flops": 65536, "split_flops": 262144}
+PRODUCTS = ("rows", "flat")
+DEFAULT = {"group_lanes": 0, "light_max_flops": 1024, "wave_max_flops": 65536, "split_flops": 262144, "products": 0}
 
 
 def features(A: DeviceCsr, B: DeviceCsr, flops: int) -> str:
@@ -84,6 +86,11 @@ class Autotuner:
             t, _ = _time_numeric(A, B, cand, reps)
             if t < best_t:
                 best, best_t = cand, t
+        for pl in PRODUCTS:
+            cand = dict(best, products=pl)
+            t, _ = _time_numeric(A, B, cand, reps)
+            if t < best_t:
+                best, best_t = cand, t
         for lm in LIGHT_MAX:
             cand = dict(best, light_max_flops=lm)
             t, _ = _time_numeric(A, B, cand, reps)
@@ -133,6 +140,11 @@ class Autotuner:
             best_t = run_ms(best)
             for gl in GROUP_LANES:
                 cand = dict(best, group_lanes=gl)
+                t = run_ms(cand)
+                if t < best_t:
+                    best, best_t = cand, t
+            for pl in PRODUCTS:
+                cand = dict(best, products=pl)
                 t = run_ms(cand)
                 if t < best_t:
                     best, best_t = cand, t

@@ -11,7 +11,7 @@ import ctypes
 import torch
 
 from . import _lib
-from .api import DeviceCsr, _stream_ptr, accumulator_code
+from .api import DeviceCsr, _stream_ptr, tuning_struct
 
 
 class Batched:
@@ -26,11 +26,7 @@ class Batched:
         tarr = None
         if tunings is not None:
             assert len(tunings) == count
-            tarr = (_lib.Tuning * max(count, 1))(*[
-                _lib.Tuning(int(t.get("group_lanes", 0)), int(t.get("wave_max_flops", 0)),
-                            int(t.get("split_flops", 0)), int(t.get("sym_split_nnz", 0)),
-                            accumulator_code(t.get("accumulator", 0)), int(t.get("light_max_flops", 0)))
-                for t in tunings])
+            tarr = (_lib.Tuning * max(count, 1))(*[tuning_struct(t) for t in tunings])
         self._tunings = tarr
         self.handle = ctypes.c_void_p(None)
         pool = ctypes.c_int64(0)

@@ -102,28 +102,38 @@ void plan_free(Plan* p) {
   p->hstrips_zeroed = 0;
 }
 
-// Lanes per B row from the mean B row length: a B row is read GL entries per
-// step, and a second step of the same row waits on the first, so the width
-// covers most rows in one step; 64 lanes only for long rows (measured on
-// R-MAT scale 20 at 12.8 and 25.6 entries per row: 32 lanes best for both).
+// Lanes per B row: the smallest power of two (8..64) covering the mean B row
+// length, so a B row is mostly read in one step. Measured on R-MAT at 1.9,
+// 2.6, 12.8, 25.6 and 64 entries per B row (8, 8, 16, 32 and 64 lanes best
+// with per-B-row products).
 int default_group_lanes(double mean_b_row) {
-  if (mean_b_row > 48.0) return 64;
-  if (mean_b_row >= 8.0) return 32;
-  if (mean_b_row >= 4.0) return 16;
-  if (mean_b_row >= 2.0) return 8;
-  return 4;
+  int gl = 8;
+  while (gl < 64 && gl < mean_b_row) gl <<= 1;
+  return gl;
+}
+
+static double mean_b_row(const tsspgemm_csr* B) { return B->nrows > 0 ? (double)B->nnz / (double)B->nrows : 0.0; }
+
+// Flat product lists for long B rows (a lane then has several independent
+// loads per step where a per-B-row group would walk the row's tail serially);
+// per B row otherwise, since a lane of the flat layout walks the staged
+// entries and short rows make that walk long.
+int default_products(double mean_b_row, int group_lanes) {
+  (void)group_lanes;
+  return mean_b_row >= 48.0 ? TSSPGEMM_PRODUCTS_FLAT : TSSPGEMM_PRODUCTS_PER_B_ROW;
 }
 
 void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tuning* out) {
   tsspgemm_tuning r{};
   if (t) r = *t;
-  if (r.group_lanes == 0) r.group_lanes = default_group_lanes(B->nrows > 0 ? (double)B->nnz / (double)B->nrows : 0.0);
+  if (r.group_lanes == 0) r.group_lanes = default_group_lanes(mean_b_row(B));
   if (r.light_max_flops <= 0) r.light_max_flops = 1024;
   if (r.wave_max_flops <= 0) r.wave_max_flops = 65536;
   if (r.split_flops <= 0) r.split_flops = 262144;
   if (r.wave_max_flops < r.light_max_flops) r.wave_max_flops = r.light_max_flops;
   if (r.split_flops < r.wave_max_flops) r.split_flops = r.wave_max_flops;
   if (r.sym_split_nnz <= 0) r.sym_split_nnz = 2048;
+  if (r.products == TSSPGEMM_PRODUCTS_AUTO) r.products = default_products(mean_b_row(B), r.group_lanes);
   if (r.accumulator == TSSPGEMM_ACC_AUTO)
     r.accumulator = B->ncols > kMaxDenseD ? TSSPGEMM_ACC_HASH : TSSPGEMM_ACC_LDS_STRIP;
   *out = r;
@@ -261,6 +271,10 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
     set_error("unknown accumulator");
     return TSSPGEMM_ERR_INVALID_ARG;
   }
+  if (tn.products != TSSPGEMM_PRODUCTS_PER_B_ROW && tn.products != TSSPGEMM_PRODUCTS_FLAT) {
+    set_error("unknown product layout");
+    return TSSPGEMM_ERR_INVALID_ARG;
+  }
   if (B->ncols > kMaxDenseD && tn.accumulator == TSSPGEMM_ACC_LDS_STRIP) {
     set_error("the LDS strip accumulator needs d <= 1024");
     return TSSPGEMM_ERR_UNSUPPORTED;
@@ -321,7 +335,13 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   pr.crp = c_rowptr;
 
   if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
-  if ((rc = launch_csr_to_bitmap(n, B->rowptr, B->colidx, wp, (uint32_t*)p->bbits.p, st))) return rc;
+  // B's bitmap; for value semirings the same pass narrows B's column ids
+  // (the numeric phase reads them; B's pattern is fixed for the plan)
+  const int cb = sr != TSSPGEMM_OR_AND ? col_id_bytes(d) : 0;
+  if (cb && (rc = p->bcol.ensure((size_t)B->nnz * cb))) return rc;
+  if ((rc = launch_csr_to_bitmap(n, B->rowptr, B->colidx, wp, (uint32_t*)p->bbits.p, st, cb ? p->bcol.p : nullptr,
+                                 cb)))
+    return rc;
   const uint32_t* mask = nullptr;
   if (M && M->kind == TSSPGEMM_MASK_COMPLEMENT_CSR) {
     if ((rc = p->maskbits.ensure((size_t)n * wp * 4))) return rc;
@@ -343,11 +363,6 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   if (sr != TSSPGEMM_OR_AND) {
     const NumThresholds th{tn.light_max_flops, tn.wave_max_flops, tn.split_flops};
     if ((rc = launch_num_bin(pr, th, (Item*)p->num_items.p, (SplitRow*)p->split_rows.p, ctr, st)))
-      return rc;
-  }
-  if (sr != TSSPGEMM_OR_AND) {  // B's pattern is fixed for the plan: narrow its column ids once
-    const int cb = col_id_bytes(d);
-    if ((rc = p->bcol.ensure((size_t)B->nnz * cb)) || (rc = launch_narrow_cols(B->nnz, B->colidx, p->bcol.p, cb, st)))
       return rc;
   }
   TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -419,7 +434,8 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   np.partial = (double*)p->partial.p;
   np.ipartial = (int32_t*)p->partial.p;
   const int64_t grid = np.n_wg_items + (p->n_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
-  if ((rc = launch_numeric(p->sr, p->tune.group_lanes, np, grid, st))) return rc;
+  if ((rc = launch_numeric(p->sr, p->tune.group_lanes, p->tune.products == TSSPGEMM_PRODUCTS_FLAT, np, grid, st)))
+    return rc;
   return launch_split_finalize(p->sr, pr, (const SplitRow*)p->split_rows.p, (int32_t)p->n_split_rows,
                                (const double*)p->partial.p, (const int32_t*)p->partial.p, st);
 }

@@ -399,7 +399,7 @@ __global__ void k_b_num_bin_fill(BatchDev b) {
 // ---------------------------------------------------------------- numeric
 
 // Workgroup items, then wavefront rows, each walked with a grid stride.
-template <int GL>
+template <int GL, bool FLAT>
 __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
   using S = SemiringT<float>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
     const int d = pr.d;
     for (int j = threadIdx.x; j < kWavesPerBlock * d; j += kBlock) strips[j] = 0.0;
     __syncthreads();
-    accumulate_range<GL, float>(pr, it.p0, it.p1, wave, kWavesPerBlock, strips + wave * d, stage + wave * kWave);
+    accumulate_range<GL, float, int32_t, FLAT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strips + wave * d, stage + wave * kWave);
     __syncthreads();
     for (int j = threadIdx.x; j < d; j += kBlock)
       strips[j] = S::add(S::add(S::add(strips[j], strips[d + j]), strips[2 * d + j]), strips[3 * d + j]);
@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
       const Problem& pr = b.insts[b.num_inst[x]].pr;
       for (int j = lane; j < pr.d; j += kWave) strip[j] = 0.0;
       wave_sync();
-      accumulate_range<GL, float>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
+      accumulate_range<GL, float, int32_t, FLAT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
       wave_sync();
       emit_row<float>(pr, it.row, strip, 0, 1);
       wave_sync();
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
   }
 }
 
-template <int GL>
+template <int GL, bool FLAT>
 __global__ __launch_bounds__(kBlock) void k_b_numeric_light(BatchDev b) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int G = kBlock / GL;
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric_light(BatchDev b) {
     const Problem& pr = b.insts[b.num_inst[first + x]].pr;
     for (int j = gl; j < pr.d; j += GL) strip[j] = 0.0;
     wave_sync();
-    accumulate_light<GL, float>(pr, it.p0, it.p1, strip, stage, gl);
+    accumulate_light<GL, float, int32_t, FLAT>(pr, it.p0, it.p1, strip, stage, gl);
     wave_sync();
     emit_group<GL, float>(pr, it.row, strip, gl);
     wave_sync();
@@ -487,6 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_b_split_finalize(BatchDev b) {
 
 struct Batch {
   int32_t count = 0, dmax = 1, gl = 32, lgl = 32;
+  bool flat = false;  // flat product lists (tsspgemm_products) for the whole batch
   std::vector<BInst> host_insts;
   DevBuf insts, offs, work, sym_items, sym_inst, num_items, num_inst, split_rows, partial, block_sums, inst_flops,
       ctr, tmp_rowptrs, tmp_off;
@@ -528,15 +529,21 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   if (!numeric) return TSSPGEMM_OK;
   const size_t lds = (size_t)kWavesPerBlock * bt->dmax * 8 + kWavesPerBlock * kWave * sizeof(int4);
   const size_t llds = (size_t)(kBlock / bt->lgl) * bt->dmax * 8 + kBlock * sizeof(int4);
-#define TSS_BN(GLV)                                              \
-  case GLV:                                                      \
-    k_b_numeric<GLV><<<2048, kBlock, lds, st>>>(b);              \
+#define TSS_BN(GLV)                                                   \
+  case GLV:                                                           \
+    if (bt->flat)                                                     \
+      k_b_numeric<GLV, true><<<2048, kBlock, lds, st>>>(b);           \
+    else                                                              \
+      k_b_numeric<GLV, false><<<2048, kBlock, lds, st>>>(b);          \
     break;
-#define TSS_BL(GLV)                                              \
-  case GLV:                                                      \
-    k_b_numeric_light<GLV><<<2048, kBlock, llds, st>>>(b);       \
+#define TSS_BL(GLV)                                                   \
+  case GLV:                                                           \
+    if (bt->flat)                                                     \
+      k_b_numeric_light<GLV, true><<<2048, kBlock, llds, st>>>(b);    \
+    else                                                              \
+      k_b_numeric_light<GLV, false><<<2048, kBlock, llds, st>>>(b);   \
     break;
-  switch (bt->gl) {
+  switch (bt->flat ? 64 : bt->gl) {
     TSS_BN(4) TSS_BN(8) TSS_BN(16) TSS_BN(32) TSS_BN(64)
     default: set_error("batched: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
   }
@@ -608,6 +615,7 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     resolve_tuning(tunes ? &tunes[0] : nullptr, &mean_b, &t0);
     bt->gl = t0.group_lanes;
     bt->lgl = light_group_lanes(bt->gl, dmax, TSSPGEMM_PLUS_TIMES_F32);
+    bt->flat = t0.products == TSSPGEMM_PRODUCTS_FLAT;
     bt->dev.sym_split = t0.sym_split_nnz;
   }
   bt->total_rows = row_off[count];

@@ -99,7 +99,9 @@ struct NumParams {
 // All return TSSPGEMM_OK or an error code; all are asynchronous on `st`.
 int launch_zero_bytes(void* p, size_t bytes, hipStream_t st);
 int launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
-int launch_csr_to_bitmap(int64_t n, const int32_t* rp, const int32_t* ci, int wp, uint32_t* bits, hipStream_t st);
+// CSR pattern -> n x wp bitmap; with `narrow`, also the column ids as 1- or 2-byte values
+int launch_csr_to_bitmap(int64_t n, const int32_t* rp, const int32_t* ci, int wp, uint32_t* bits, hipStream_t st,
+                         void* narrow = nullptr, int narrow_bytes = 0);
 int launch_nonempty_bits(int64_t n, const int32_t* rp, uint32_t* bits, hipStream_t st);
 int launch_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t* rp, const int32_t* ci,
                         Counters* ctr, hipStream_t st);
@@ -120,9 +122,8 @@ int launch_exscan_i32(const int32_t* in, int64_t n, int32_t* out, int64_t* block
 int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
                    hipStream_t st);
 
-int launch_numeric(int sr, int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st);
+int launch_numeric(int sr, int group_lanes, bool flat, const NumParams& np, int64_t n_grid, hipStream_t st);
 int col_id_bytes(int64_t d);  // 1 or 2: width of the narrowed column ids
-int launch_narrow_cols(int64_t nnz, const int32_t* ci, void* out, int bytes, hipStream_t st);
 int launch_build_recs(int64_t n, int wp, const uint32_t* bits, const int32_t* rowptr, uint64_t* rec, hipStream_t st);
 int launch_split_finalize(int sr, const Problem& pr, const SplitRow* rows, int32_t nrows, const double* partial,
                           const int32_t* ipartial, hipStream_t st);

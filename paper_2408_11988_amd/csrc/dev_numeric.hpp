@@ -38,8 +38,6 @@ constexpr int kLightUnroll = 4;  // A entries per group per step, light rows
 
 // ---------------------------------------------------------------- wavefront / workgroup rows
 
-// Accumulate entries [p_begin, p_end) of one A row into `strip`, taking
-// 64-entry batches number wstart, wstart + wstride, ... (one wavefront).
 // B column ids as IdxT: int32_t reads B's own array, uint8_t / uint16_t the
 // narrowed copy (fewer bytes per gathered B row).
 template <typename IdxT>
@@ -50,8 +48,13 @@ __device__ __forceinline__ const IdxT* col_ids(const Problem& pr) {
     return (const IdxT*)pr.bcol;
 }
 
+// Accumulate entries [p_begin, p_end) of one A row into `strip`, taking
+// 64-entry batches number wstart, wstart + wstride, ... (one wavefront): the
+// batch is staged (entry, B row bounds, value) through LDS, and the 64/GL
+// groups of the wavefront each take a B row, GL entries per step, U rows per
+// group in flight ("per B row" product layout).
 template <int GL, typename T, typename IdxT = int32_t>
-__device__ __forceinline__ void accumulate_range(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
+__device__ __forceinline__ void accumulate_range_rows(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
                                                  typename SemiringT<T>::acc* strip, int4* stage) {
   using S = SemiringT<T>;
   constexpr int GPW = kWave / GL;
@@ -105,6 +108,89 @@ __device__ __forceinline__ void accumulate_range(const Problem& pr, int p_begin,
     }
     wave_sync();
   }
+}
+
+// Accumulate entries [p_begin, p_end) of one A row into `strip`, taking
+// 64-entry batches number wstart, wstart + wstride, ... (one wavefront). A
+// batch is staged as in accumulate_light, with the whole wavefront as the
+// group: lane t loads entry t and its B row bounds (coalesced), a wavefront
+// scan of the B row lengths makes the batch's products one flat list, and
+// lane t takes products t, t + 64, ... (U per step, independent loads).
+template <typename T, typename IdxT = int32_t>
+__device__ __forceinline__ void accumulate_range_flat(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
+                                                 typename SemiringT<T>::acc* strip, int4* stage) {
+  using S = SemiringT<T>;
+  constexpr int U = kHeavyUnroll;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t* __restrict__ aci = pr.aci;
+  const T* __restrict__ aval = (const T*)pr.aval;
+  const int32_t* __restrict__ brp = pr.brp;
+  const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
+  const T* __restrict__ bval = (const T*)pr.bval;
+
+  for (int base = p_begin + kWave * wstart; base < p_end; base += kWave * wstride) {
+    const int nb = min(kWave, p_end - base);
+    int q0 = 0, len = 0;
+    T a = T(0);
+    if (lane < nb) {
+      const int k = aci[base + lane];
+      a = aval[base + lane];
+      q0 = brp[k];
+      len = brp[k + 1] - q0;
+    }
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(incl, o, kWave);
+      if (lane >= o) incl += y;
+    }
+    const int total = __shfl(incl, kWave - 1, kWave);
+    wave_sync();
+    stage[lane] = make_int4(q0 - (incl - len), incl, __builtin_bit_cast(int32_t, a), 0);
+    wave_sync();
+    int e = 0;
+    int4 cur = stage[0];
+    for (int f0 = 0; f0 < total; f0 += U * kWave) {
+      int q[U];
+      T av[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int f = f0 + u * kWave + lane;
+        q[u] = -1;
+        av[u] = T(0);
+        if (f < total) {
+          while (cur.y <= f) cur = stage[++e];
+          q[u] = cur.x + f;
+          av[u] = __builtin_bit_cast(T, cur.z);
+        }
+      }
+      int jj[U];
+      T bv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        jj[u] = 0;
+        bv[u] = T(0);
+        if (q[u] >= 0) {
+          jj[u] = bci[q[u]];
+          bv[u] = bval[q[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q[u] >= 0) lds_add(&strip[jj[u]], S::prod(av[u], bv[u]));
+    }
+    wave_sync();
+  }
+}
+
+// Product layout of a wavefront's batch: per B row (FLAT false) or flat.
+template <int GL, typename T, typename IdxT, bool FLAT>
+__device__ __forceinline__ void accumulate_range(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
+                                                 typename SemiringT<T>::acc* strip, int4* stage) {
+  if constexpr (FLAT)
+    accumulate_range_flat<T, IdxT>(pr, p_begin, p_end, wstart, wstride, strip, stage);
+  else
+    accumulate_range_rows<GL, T, IdxT>(pr, p_begin, p_end, wstart, wstride, strip, stage);
 }
 
 // Write row `row` of C from a strip: wavefront `wave_id` of `nwaves` handles
@@ -164,13 +250,10 @@ __device__ __forceinline__ void emit_group(const Problem& pr, int64_t row, const
 }
 
 // Accumulate entries [p0, p1) of one A row into a group's strip (GL lanes,
-// lane gl). The group first loads up to GL of the row's A entries at once,
-// one per lane (coalesced), with their B row bounds, and shares them through
-// `stage` (GL records of this group); then several staged entries per step
-// keep several B rows in flight. The chain of dependent gathers per step is
-// one (B row) instead of three (A entry, B row pointers, B row).
+// lane gl), per B row: the group stages up to GL A entries with their B row
+// bounds, then takes U staged B rows per step, GL entries of each at a time.
 template <int GL, typename T, typename IdxT = int32_t>
-__device__ __forceinline__ void accumulate_light(const Problem& pr, int p0, int p1,
+__device__ __forceinline__ void accumulate_light_rows(const Problem& pr, int p0, int p1,
                                                  typename SemiringT<T>::acc* strip, int4* stage, int gl) {
   using S = SemiringT<T>;
   constexpr int U = kLightUnroll;
@@ -218,6 +301,91 @@ __device__ __forceinline__ void accumulate_light(const Problem& pr, int p0, int 
     }
     wave_sync();
   }
+}
+
+// Accumulate entries [p0, p1) of one A row into a group's strip (GL lanes,
+// lane gl). The group loads up to GL of the row's A entries at once, one per
+// lane (coalesced), with their B row bounds, and a scan over the group turns
+// the B row lengths into offsets: the products of the staged entries form one
+// flat list, and lane gl takes products gl, gl + GL, ... (U of them per step,
+// all loads independent). A lane finds the staged entry of its product by
+// moving forward through the offsets (its product index only grows), so short
+// B rows do not leave lanes idle and a step has one dependent gather.
+// stage[e] = (start of B row - offset of e, end offset of e, A value bits).
+template <int GL, typename T, typename IdxT = int32_t>
+__device__ __forceinline__ void accumulate_light_flat(const Problem& pr, int p0, int p1,
+                                                 typename SemiringT<T>::acc* strip, int4* stage, int gl) {
+  using S = SemiringT<T>;
+  constexpr int U = kLightUnroll;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t* __restrict__ aci = pr.aci;
+  const T* __restrict__ aval = (const T*)pr.aval;
+  const int32_t* __restrict__ brp = pr.brp;
+  const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
+  const T* __restrict__ bval = (const T*)pr.bval;
+  for (int base = p0; base < p1; base += GL) {
+    const int nb = min(GL, p1 - base);
+    int q0 = 0, len = 0;
+    T a = T(0);
+    if (gl < nb) {
+      const int k = aci[base + gl];
+      a = aval[base + gl];
+      q0 = brp[k];
+      len = brp[k + 1] - q0;
+    }
+    int incl = len;  // inclusive scan of the lengths over the group
+#pragma unroll
+    for (int o = 1; o < GL; o <<= 1) {
+      const int y = __shfl_up(incl, o, kWave);
+      if (gl >= o) incl += y;
+    }
+    const int total = __shfl(incl, (lane & ~(GL - 1)) + GL - 1, kWave);
+    wave_sync();
+    stage[gl] = make_int4(q0 - (incl - len), incl, __builtin_bit_cast(int32_t, a), 0);
+    wave_sync();
+    int e = 0;
+    int4 cur = stage[0];
+    for (int f0 = 0; f0 < total; f0 += U * GL) {
+      int q[U];
+      T av[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int f = f0 + u * GL + gl;
+        q[u] = -1;
+        av[u] = T(0);
+        if (f < total) {
+          while (cur.y <= f) cur = stage[++e];
+          q[u] = cur.x + f;
+          av[u] = __builtin_bit_cast(T, cur.z);
+        }
+      }
+      int jj[U];
+      T bv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        jj[u] = 0;
+        bv[u] = T(0);
+        if (q[u] >= 0) {
+          jj[u] = bci[q[u]];
+          bv[u] = bval[q[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q[u] >= 0) lds_add(&strip[jj[u]], S::prod(av[u], bv[u]));
+    }
+    wave_sync();
+  }
+}
+
+// Product layout of a lane group's row: per B row (FLAT false) or flat.
+template <int GL, typename T, typename IdxT, bool FLAT>
+__device__ __forceinline__ void accumulate_light(const Problem& pr, int p0, int p1,
+                                                 typename SemiringT<T>::acc* strip, int4* stage, int gl) {
+  if constexpr (FLAT)
+    accumulate_light_flat<GL, T, IdxT>(pr, p0, p1, strip, stage, gl);
+  else
+    accumulate_light_rows<GL, T, IdxT>(pr, p0, p1, strip, stage, gl);
 }
 
 // ================================================================ binning (numeric)

@@ -12,11 +12,13 @@ namespace tss {
 // (coalesced), finds each entry's row by binary search over the staged
 // pointers, sets the bit with an LDS atomicOr, and writes the finished bitmap
 // rows out contiguously. `sm` holds kBmRows + 1 + kBmRows * wp words.
+// Optionally each column id is also written narrowed to 8 or 16 bits.
 constexpr int kBmRows = 256;
 
 __device__ __forceinline__ void bitmap_block(int64_t n, const int32_t* __restrict__ rp,
                                              const int32_t* __restrict__ ci, int wp, uint32_t* __restrict__ bits,
-                                             int64_t r0, uint32_t* sm) {
+                                             int64_t r0, uint32_t* sm, uint8_t* __restrict__ narrow8 = nullptr,
+                                             uint16_t* __restrict__ narrow16 = nullptr) {
   int32_t* srp = (int32_t*)sm;
   uint32_t* sb = sm + kBmRows + 1;
   const int nr = (int)min((int64_t)kBmRows, n - r0);
@@ -35,6 +37,8 @@ __device__ __forceinline__ void bitmap_block(int64_t n, const int32_t* __restric
         hi = mid;
     }
     atomicOr(&sb[lo * wp + (j >> 5)], 1u << (j & 31));
+    if (narrow8) narrow8[q] = (uint8_t)j;  // the same pass narrows the column ids
+    if (narrow16) narrow16[q] = (uint16_t)j;
   }
   __syncthreads();
   uint32_t* out = bits + r0 * wp;

@@ -28,7 +28,7 @@
 
 namespace tss {
 
-template <int GL, typename T, typename IdxT>
+template <int GL, typename T, typename IdxT, bool FLAT>
 __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   using S = SemiringT<T>;
   using Acc = typename S::acc;
@@ -55,9 +55,9 @@ __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   __syncthreads();
   if (valid) {
     if (wg_mode)
-      accumulate_range<GL, T, IdxT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strip, stage + wave * kWave);
+      accumulate_range<GL, T, IdxT, FLAT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strip, stage + wave * kWave);
     else
-      accumulate_range<GL, T, IdxT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
+      accumulate_range<GL, T, IdxT, FLAT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
   }
   __syncthreads();
   if (wg_mode) {
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   }
 }
 
-template <int GL, typename T, typename IdxT>
+template <int GL, typename T, typename IdxT, bool FLAT>
 __global__ __launch_bounds__(kBlock) void k_numeric_light(NumParams np) {
   using Acc = typename SemiringT<T>::acc;
   constexpr int G = kBlock / GL;  // rows in flight per workgroup
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_numeric_light(NumParams np) {
     const Item it = items[t];
     for (int j = gl; j < d; j += GL) strip[j] = Acc(0);
     wave_sync();
-    accumulate_light<GL, T, IdxT>(pr, it.p0, it.p1, strip, stage, gl);
+    accumulate_light<GL, T, IdxT, FLAT>(pr, it.p0, it.p1, strip, stage, gl);
     wave_sync();
     emit_group<GL, T>(pr, it.row, strip, gl);
     wave_sync();
@@ -124,37 +124,17 @@ static int64_t light_grid(int64_t n_light, int gl) {
 
 int col_id_bytes(int64_t d) { return d <= 256 ? 1 : 2; }
 
-__global__ void k_narrow_cols(int64_t nnz, const int32_t* __restrict__ ci, uint8_t* __restrict__ o8,
-                              uint16_t* __restrict__ o16) {
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
-    if (o8)
-      o8[q] = (uint8_t)ci[q];
-    else
-      o16[q] = (uint16_t)ci[q];
-  }
-}
-
-int launch_narrow_cols(int64_t nnz, const int32_t* ci, void* out, int bytes, hipStream_t st) {
-  if (nnz <= 0) return TSSPGEMM_OK;
-  int64_t g = (nnz + 255) / 256;
-  if (g > 8192) g = 8192;
-  k_narrow_cols<<<(unsigned)g, 256, 0, st>>>(nnz, ci, bytes == 1 ? (uint8_t*)out : nullptr,
-                                             bytes == 2 ? (uint16_t*)out : nullptr);
-  TSS_CHECK_LAUNCH();
-  return TSSPGEMM_OK;
-}
-
-template <typename T, typename IdxT>
+template <typename T, typename IdxT, bool FLAT>
 static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st) {
   const size_t ab = sizeof(typename SemiringT<T>::acc);
   if (n_grid > 0) {
     const size_t lds = (size_t)kWavesPerBlock * np.pr.d * ab + kWavesPerBlock * kWave * sizeof(int4);
-    switch (group_lanes) {
-      case 4: k_numeric<4, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
-      case 8: k_numeric<8, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
-      case 16: k_numeric<16, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
-      case 32: k_numeric<32, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
-      case 64: k_numeric<64, T, IdxT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+    switch (FLAT ? 64 : group_lanes) {  // the flat layout uses the whole wavefront
+      case 4: k_numeric<4, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 8: k_numeric<8, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 16: k_numeric<16, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 32: k_numeric<32, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 64: k_numeric<64, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
       default:
         set_error("numeric: group_lanes must be 4, 8, 16, 32 or 64");
         return TSSPGEMM_ERR_INVALID_ARG;
@@ -167,11 +147,11 @@ static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid
     const unsigned g = (unsigned)light_grid(np.n_light, gl);
     const size_t lds = (size_t)(kBlock / gl) * np.pr.d * ab + kBlock * sizeof(int4);
     switch (gl) {
-      case 4: k_numeric_light<4, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
-      case 8: k_numeric_light<8, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
-      case 16: k_numeric_light<16, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
-      case 32: k_numeric_light<32, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
-      case 64: k_numeric_light<64, T, IdxT><<<g, kBlock, lds, st>>>(np); break;
+      case 4: k_numeric_light<4, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
+      case 8: k_numeric_light<8, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
+      case 16: k_numeric_light<16, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
+      case 32: k_numeric_light<32, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
+      case 64: k_numeric_light<64, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
       default:
         set_error("numeric: bad light group width");
         return TSSPGEMM_ERR_INVALID_ARG;
@@ -181,18 +161,24 @@ static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid
   return TSSPGEMM_OK;
 }
 
+template <typename T, typename IdxT>
+static int launch_numeric_l(int group_lanes, bool flat, const NumParams& np, int64_t n_grid, hipStream_t st) {
+  return flat ? launch_numeric_t<T, IdxT, true>(group_lanes, np, n_grid, st)
+              : launch_numeric_t<T, IdxT, false>(group_lanes, np, n_grid, st);
+}
+
 // B's column ids are read narrowed (np.pr.bcol, col_id_bytes(d) bytes each).
-int launch_numeric(int sr, int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st) {
+int launch_numeric(int sr, int group_lanes, bool flat, const NumParams& np, int64_t n_grid, hipStream_t st) {
   const bool b8 = col_id_bytes(np.pr.d) == 1;
   if (!np.pr.bcol && np.pr.n > 0) {
     set_error("numeric: narrowed column ids missing");
     return TSSPGEMM_ERR_INVALID_ARG;
   }
   if (sr == TSSPGEMM_PLUS_TIMES_F32)
-    return b8 ? launch_numeric_t<float, uint8_t>(group_lanes, np, n_grid, st)
-              : launch_numeric_t<float, uint16_t>(group_lanes, np, n_grid, st);
-  return b8 ? launch_numeric_t<int32_t, uint8_t>(group_lanes, np, n_grid, st)
-            : launch_numeric_t<int32_t, uint16_t>(group_lanes, np, n_grid, st);
+    return b8 ? launch_numeric_l<float, uint8_t>(group_lanes, flat, np, n_grid, st)
+              : launch_numeric_l<float, uint16_t>(group_lanes, flat, np, n_grid, st);
+  return b8 ? launch_numeric_l<int32_t, uint8_t>(group_lanes, flat, np, n_grid, st)
+            : launch_numeric_l<int32_t, uint16_t>(group_lanes, flat, np, n_grid, st);
 }
 
 // Split rows: add the chunks' partial strips in chunk order, then emit.

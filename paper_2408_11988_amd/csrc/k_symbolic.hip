@@ -47,15 +47,19 @@ int launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st) {
 
 __global__ __launch_bounds__(256) void k_csr_to_bitmap(int64_t n, const int32_t* __restrict__ rp,
                                                        const int32_t* __restrict__ ci, int wp,
-                                                       uint32_t* __restrict__ bits) {
+                                                       uint32_t* __restrict__ bits, uint8_t* narrow8,
+                                                       uint16_t* narrow16) {
   extern __shared__ __align__(16) uint32_t sm[];
-  bitmap_block(n, rp, ci, wp, bits, (int64_t)blockIdx.x * kBmRows, sm);
+  bitmap_block(n, rp, ci, wp, bits, (int64_t)blockIdx.x * kBmRows, sm, narrow8, narrow16);
 }
 
-int launch_csr_to_bitmap(int64_t n, const int32_t* rp, const int32_t* ci, int wp, uint32_t* bits, hipStream_t st) {
+int launch_csr_to_bitmap(int64_t n, const int32_t* rp, const int32_t* ci, int wp, uint32_t* bits, hipStream_t st,
+                         void* narrow, int narrow_bytes) {
   if (n == 0) return TSSPGEMM_OK;
   const size_t lds = (size_t)(kBmRows + 1 + kBmRows * wp) * 4;
-  k_csr_to_bitmap<<<grid_for(n, kBmRows), 256, lds, st>>>(n, rp, ci, wp, bits);
+  k_csr_to_bitmap<<<grid_for(n, kBmRows), 256, lds, st>>>(n, rp, ci, wp, bits,
+                                                          narrow_bytes == 1 ? (uint8_t*)narrow : nullptr,
+                                                          narrow_bytes == 2 ? (uint16_t*)narrow : nullptr);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }

@@ -80,9 +80,9 @@ def test_argument_errors_without_device(lib):
     assert rc == _lib.ERR_INVALID_ARG
     rc, _ = _symbolic(lib, _desc(4, 4, 1 << 40), _desc(4, 2, 0))
     assert rc == _lib.ERR_OVERFLOW
-    rc, plan = _symbolic(lib, _desc(4, 4, 0), _desc(4, 2, 0), tune=_lib.Tuning(0, 0, 0, 0, 9, 0))
+    rc, plan = _symbolic(lib, _desc(4, 4, 0), _desc(4, 2, 0), tune=_lib.Tuning(0, 0, 0, 0, 9, 0, 0))
     assert rc == _lib.ERR_INVALID_ARG and b"accumulator" in lib.tsspgemm_last_error() and not plan.value
-    rc, _ = _symbolic(lib, _desc(4, 4, 0), _desc(4, 2048, 0), tune=_lib.Tuning(0, 0, 0, 0, 1, 0))
+    rc, _ = _symbolic(lib, _desc(4, 4, 0), _desc(4, 2048, 0), tune=_lib.Tuning(0, 0, 0, 0, 1, 0, 0))
     assert rc == _lib.ERR_UNSUPPORTED  # the LDS strip needs d <= 1024
     bad = _lib.CsrDesc(4, 4, 3, 0x1000, None, 0x1000)  # nnz > 0 but no column array
     rc, _ = _symbolic(lib, bad, _desc(4, 2, 0))

@@ -54,6 +54,7 @@ def test_batched_matches_plain_and_oracle(tuned):
     tunings = None
     if tuned:  # forces every work class somewhere in the batch
         tunings = [dict(group_lanes=16, light_max_flops=64, wave_max_flops=512, split_flops=2048) for _ in host]
+        tunings[0]["products"] = "flat"  # the batch's layout comes from the first tuning
     note(f"batched {len(pairs)} instances tuned={tuned}")
     bt = Batched(pairs, tunings)
     bt.run()
@@ -73,7 +74,10 @@ def bt_group_lanes(pairs):
     nn = sum(B.nrows for _, B in pairs)
     nz = sum(B.nnz for _, B in pairs)
     mean = nz / nn if nn else 0
-    return 64 if mean > 48 else 32 if mean >= 8 else 16 if mean >= 4 else 8 if mean >= 2 else 4
+    gl = 8
+    while gl < 64 and gl < mean:
+        gl *= 2
+    return gl
 
 
 def test_graph_replays():

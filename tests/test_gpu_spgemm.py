@@ -39,7 +39,7 @@ ACCS = ["lds", "hash"]
 ALL_CLASSES = dict(light_max_flops=16, wave_max_flops=64, split_flops=256)
 
 
-@pytest.mark.parametrize("classes", ["default", "all"])
+@pytest.mark.parametrize("classes", ["default", "all", "all_flat"])
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("d", D_VALUES)
 def test_plus_times_random(d, acc, classes):
@@ -47,7 +47,9 @@ def test_plus_times_random(d, acc, classes):
     n = 300
     a = random_csr(rng, n, n, 0.03, empty_rows=0.2, dense_rows=2)
     b = random_csr(rng, n, d, min(0.5, 6.0 / d + 0.02), empty_rows=0.1)
-    tun = dict(accumulator=acc, **(ALL_CLASSES if classes == "all" else {}))
+    tun = dict(accumulator=acc, **(ALL_CLASSES if classes.startswith("all") else {}))
+    if classes == "all_flat":
+        tun["products"] = "flat"
     note(f"plus_times random n={n} d={d} nnzA={a.nnz} nnzB={b.nnz} tuning={tun}")
     C = _tss().spgemm(to_dev(a), to_dev(b), tuning=tun)
     torch.cuda.synchronize()
@@ -162,9 +164,12 @@ def test_modes_and_tuning_do_not_change_results():
     compare_f32(a, b, ref)
     ref_h = ref.to_host()
     configs = [dict(group_lanes=g) for g in (4, 8, 16, 32, 64)]
+    configs += [dict(group_lanes=g, products=pl) for g in (8, 32, 64) for pl in ("rows", "flat")]
     configs += [dict(light_max_flops=1, wave_max_flops=16, split_flops=64),
                 dict(light_max_flops=1, wave_max_flops=1, split_flops=1),
                 dict(light_max_flops=200, wave_max_flops=260, split_flops=1000),
+                dict(light_max_flops=200, wave_max_flops=260, split_flops=1000, products="flat"),
+                dict(light_max_flops=200, wave_max_flops=260, split_flops=1000, products="rows"),
                 dict(light_max_flops=1 << 30, wave_max_flops=1 << 30, split_flops=1 << 30),
                 dict(wave_max_flops=500, split_flops=100000, sym_split_nnz=3), dict(sym_split_nnz=1)]
     for cfg in configs:
