@@ -83,8 +83,9 @@ __global__ void k_b_sym_bin_count(BatchDev b) {
   __shared__ int32_t hist[kBins];
   if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r < b.total_rows) {
+  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
+  const int64_t r1 = min(b.total_rows, r0 + kBinRowsPerBlock);
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
     const int t = find_inst(b.row_off, b.count, r);
     const Problem& pr = b.insts[t].pr;
     const int64_t i = r - b.row_off[t];
@@ -109,31 +110,40 @@ __global__ void k_b_sym_bin_fill(BatchDev b) {
   __shared__ int32_t cnt[kBins], base[kBins];
   if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int t = 0, a = 0, m = 0, bin = 0, count = 0, local = 0;
-  int64_t i = 0;
-  if (r < b.total_rows) {
-    t = find_inst(b.row_off, b.count, r);
+  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
+  const int64_t r1 = min(b.total_rows, r0 + kBinRowsPerBlock);
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {  // counts of this workgroup's rows
+    const int t = find_inst(b.row_off, b.count, r);
     const Problem& pr = b.insts[t].pr;
-    i = r - b.row_off[t];
-    a = pr.arp[i];
-    m = pr.arp[i + 1] - a;
-    sym_bin(m, b.sym_split, bin, count);
-    if (count) local = atomicAdd(&cnt[bin], count);
+    const int64_t i = r - b.row_off[t];
+    int bin, count;
+    sym_bin(pr.arp[i + 1] - pr.arp[i], b.sym_split, bin, count);
+    if (count) atomicAdd(&cnt[bin], count);
   }
   __syncthreads();
-  if (threadIdx.x < kBins && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&b.ctr->sym_cursor[threadIdx.x], cnt[threadIdx.x]);
+  if (threadIdx.x < kBins) {
+    if (cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&b.ctr->sym_cursor[threadIdx.x], cnt[threadIdx.x]);
+    cnt[threadIdx.x] = 0;
+  }
   __syncthreads();
-  if (!count) return;
-  const int pos = base[bin] + local;
-  if (m <= b.sym_split) {
-    b.sym_items[pos] = Item{(int32_t)i, a, a + m, 0};
-    b.sym_inst[pos] = t;
-  } else {
-    for (int c = 0; c < count; ++c) {
-      const int p0 = a + c * b.sym_split;
-      b.sym_items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + b.sym_split), kSplitFlag | c};
-      b.sym_inst[pos + c] = t;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const int t = find_inst(b.row_off, b.count, r);
+    const Problem& pr = b.insts[t].pr;
+    const int64_t i = r - b.row_off[t];
+    const int a = pr.arp[i], m = pr.arp[i + 1] - a;
+    int bin, count;
+    sym_bin(m, b.sym_split, bin, count);
+    if (!count) continue;
+    const int pos = base[bin] + atomicAdd(&cnt[bin], count);
+    if (m <= b.sym_split) {
+      b.sym_items[pos] = Item{(int32_t)i, a, a + m, 0};
+      b.sym_inst[pos] = t;
+    } else {
+      for (int c = 0; c < count; ++c) {
+        const int p0 = a + c * b.sym_split;
+        b.sym_items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + b.sym_split), kSplitFlag | c};
+        b.sym_inst[pos + c] = t;
+      }
     }
   }
 }
@@ -244,38 +254,43 @@ __global__ __launch_bounds__(kScanThreads) void k_b_count_rows(BatchDev b) {
   }
 }
 
-// one workgroup: per-instance scans of the block sums, instance offsets in
-// the output pool, and the instances' output pointers
+// One workgroup: an exclusive scan of the block sums of all instances in
+// order (nnz and products). An instance's C pool offset is the scan at its
+// first block; k_b_write_rowptr subtracts it to get offsets inside the
+// instance. Also sets every instance's C pointers into the pools.
 __global__ __launch_bounds__(kScanThreads) void k_b_scan(BatchDev b) {
   __shared__ long long sh[32];
-  long long pool = 0;
-  for (int t = 0; t < b.count; ++t) {
-    const int64_t b0 = b.sb_off[t], b1 = b.sb_off[t + 1];
-    long long carry = 0, fcarry = 0;
-    for (int64_t x0 = b0; x0 < b1; x0 += kScanThreads) {
-      const int64_t x = x0 + threadIdx.x;
-      const long long v = x < b1 ? b.block_sums[x] : 0;
-      const long long f = x < b1 ? b.block_sums[b.total_sb + x] : 0;
-      long long tot, ftot;
-      const long long ex = block_exscan_1024(v, sh, &tot);
-      block_exscan_1024(f, sh, &ftot);
-      if (x < b1) b.block_sums[x] = carry + ex;
-      carry += tot;
-      fcarry += ftot;
+  long long carry = 0, fcarry = 0;
+  for (int64_t x0 = 0; x0 < b.total_sb; x0 += kScanThreads) {
+    const int64_t x = x0 + threadIdx.x;
+    const long long v = x < b.total_sb ? b.block_sums[x] : 0;
+    const long long f = x < b.total_sb ? b.block_sums[b.total_sb + x] : 0;
+    long long tot, ftot;
+    const long long ex = block_exscan_1024(v, sh, &tot);
+    const long long fex = block_exscan_1024(f, sh, &ftot);
+    if (x < b.total_sb) {
+      b.block_sums[x] = carry + ex;
+      b.block_sums[b.total_sb + x] = fcarry + fex;
     }
-    if (threadIdx.x == 0) {
-      BInst& in = b.insts[t];
-      b.c_off[t] = pool;
-      b.inst_flops[t] = fcarry;
-      in.pr.crp = b.c_rowptrs ? b.c_rowptrs + in.rp_off : nullptr;
-      in.pr.cci = b.pool_ci ? b.pool_ci + pool : nullptr;
-      in.pr.cval = b.pool_val ? (void*)(b.pool_val + pool) : nullptr;
-    }
-    pool += carry;
+    carry += tot;
+    fcarry += ftot;
+  }
+  __syncthreads();  // the scanned sums are read back below by other threads
+  for (int t = threadIdx.x; t < b.count; t += kScanThreads) {
+    const int64_t s0 = b.sb_off[t], s1 = b.sb_off[t + 1];
+    const long long pool = s0 < b.total_sb ? b.block_sums[s0] : carry;
+    const long long f0 = s0 < b.total_sb ? b.block_sums[b.total_sb + s0] : fcarry;
+    const long long f1 = s1 < b.total_sb ? b.block_sums[b.total_sb + s1] : fcarry;
+    BInst& in = b.insts[t];
+    b.c_off[t] = pool;
+    b.inst_flops[t] = f1 - f0;
+    in.pr.crp = b.c_rowptrs ? b.c_rowptrs + in.rp_off : nullptr;
+    in.pr.cci = b.pool_ci ? b.pool_ci + pool : nullptr;
+    in.pr.cval = b.pool_val ? (void*)(b.pool_val + pool) : nullptr;
   }
   if (threadIdx.x == 0) {
-    b.c_off[b.count] = pool;
-    b.ctr->nnz_total = pool;
+    b.c_off[b.count] = carry;
+    b.ctr->nnz_total = carry;
   }
 }
 
@@ -286,7 +301,7 @@ __global__ __launch_bounds__(kScanThreads) void k_b_write_rowptr(BatchDev b) {
   const int64_t n = in.pr.n;
   int32_t* crp = b.c_rowptrs + in.rp_off;
   const int64_t base = (blockIdx.x - b.sb_off[t]) * (int64_t)kScanRows;
-  long long carry = b.block_sums[blockIdx.x];
+  long long carry = b.block_sums[blockIdx.x] - b.c_off[t];  // offset inside instance t
   for (int u = 0; u < kScanPer; ++u) {
     const int64_t i = base + u * kScanThreads + threadIdx.x;
     const long long v = i < n ? in.cnt[i] : 0;
@@ -310,21 +325,17 @@ __global__ void k_b_num_bin_count(BatchDev b) {
   __shared__ int32_t hist[kNumClasses * kBins];
   for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x) hist[x] = 0;
   __syncthreads();
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r < b.total_rows) {
+  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
+  const int64_t r1 = min(b.total_rows, r0 + kBinRowsPerBlock);
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
     const int t = find_inst(b.row_off, b.count, r);
     const BInst& in = b.insts[t];
     const int64_t i = r - b.row_off[t];
     const int64_t f = in.pr.flops[i];
     if (f > 0) {
-      const int cls = num_class(f, in.th);
-      if (cls == 0) {
-        const int m = in.pr.arp[i + 1] - in.pr.arp[i];
-        const int ce = chunk_entries(m, f, in.th.split);
-        atomicAdd(&hist[0], (m + ce - 1) / ce);
-      } else {
-        atomicAdd(&hist[cls * kBins + num_bin(f)], 1);
-      }
+      int cls, key, count, ce;
+      num_key(f, in.pr.arp[i + 1] - in.pr.arp[i], in.th, cls, key, count, ce);
+      atomicAdd(&hist[key], count);
     }
   }
   __syncthreads();
@@ -353,46 +364,51 @@ __global__ void k_b_num_bin_fill(BatchDev b) {
   for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x) cnt[x] = 0;
   if (threadIdx.x == 0) nsplit = 0;
   __syncthreads();
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int t = 0, a = 0, m = 0, cls = 0, key = 0, count = 0, local = 0, ce = 0, slocal = 0;
-  int64_t i = 0;
-  if (r < b.total_rows) {
-    t = find_inst(b.row_off, b.count, r);
+  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
+  const int64_t r1 = min(b.total_rows, r0 + kBinRowsPerBlock);
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {  // counts of this workgroup's rows
+    const int t = find_inst(b.row_off, b.count, r);
     const BInst& in = b.insts[t];
-    i = r - b.row_off[t];
+    const int64_t i = r - b.row_off[t];
     const int64_t f = in.pr.flops[i];
     if (f > 0) {
-      a = in.pr.arp[i];
-      m = in.pr.arp[i + 1] - a;
-      cls = num_class(f, in.th);
-      if (cls == 0) {
-        ce = chunk_entries(m, f, in.th.split);
-        count = (m + ce - 1) / ce;
-        slocal = atomicAdd(&nsplit, 1);
-      } else {
-        count = 1;
-        key = cls * kBins + num_bin(f);
-      }
-      local = atomicAdd(&cnt[key], count);
+      int cls, key, count, ce;
+      num_key(f, in.pr.arp[i + 1] - in.pr.arp[i], in.th, cls, key, count, ce);
+      atomicAdd(&cnt[key], count);
+      if (cls == 0) atomicAdd(&nsplit, 1);
     }
   }
   __syncthreads();
-  for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x)
+  for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x) {
     if (cnt[x]) base[x] = atomicAdd(&(&b.ctr->num_cursor[0][0])[x], cnt[x]);
-  if (threadIdx.x == 0 && nsplit) split_base = atomicAdd(&b.ctr->num_split_rows, nsplit);
+    cnt[x] = 0;
+  }
+  if (threadIdx.x == 0) {
+    if (nsplit) split_base = atomicAdd(&b.ctr->num_split_rows, nsplit);
+    nsplit = 0;
+  }
   __syncthreads();
-  if (count == 0) return;
-  const int pos = base[key] + local;
-  if (cls == 0) {
-    for (int c = 0; c < count; ++c) {
-      const int p0 = a + c * ce;
-      b.num_items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + ce), pos + c};
-      b.num_inst[pos + c] = t;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+    const int t = find_inst(b.row_off, b.count, r);
+    const BInst& in = b.insts[t];
+    const int64_t i = r - b.row_off[t];
+    const int64_t f = in.pr.flops[i];
+    if (f <= 0) continue;
+    const int a = in.pr.arp[i], m = in.pr.arp[i + 1] - a;
+    int cls, key, count, ce;
+    num_key(f, m, in.th, cls, key, count, ce);
+    const int pos = base[key] + atomicAdd(&cnt[key], count);
+    if (cls == 0) {
+      for (int c = 0; c < count; ++c) {
+        const int p0 = a + c * ce;
+        b.num_items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + ce), pos + c};
+        b.num_inst[pos + c] = t;
+      }
+      b.split_rows[split_base + atomicAdd(&nsplit, 1)] = SplitRow{(int32_t)i, pos, count, t};
+    } else {
+      b.num_items[pos] = Item{(int32_t)i, a, a + m, cls == 1 ? kNoSlot : 0};
+      b.num_inst[pos] = t;
     }
-    b.split_rows[split_base + slocal] = SplitRow{(int32_t)i, pos, count, t};
-  } else {
-    b.num_items[pos] = Item{(int32_t)i, a, a + m, cls == 1 ? kNoSlot : 0};
-    b.num_inst[pos] = t;
   }
 }
 
@@ -511,10 +527,10 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   k_b_zero<<<1, 256, 0, st>>>(b.ctr);
   if (bt->total_bm > 0)
     k_b_bitmap<<<(unsigned)bt->total_bm, 256, (size_t)(kBmRows + 1 + kBmRows * bitmap_words(bt->dmax)) * 4, st>>>(b);
-  const unsigned gr = grid_for(bt->total_rows, 256);
-  if (bt->total_rows > 0) k_b_sym_bin_count<<<gr, 256, 0, st>>>(b);
+  const unsigned gbin = grid_for(bt->total_rows, kBinRowsPerBlock);
+  if (bt->total_rows > 0) k_b_sym_bin_count<<<gbin, 256, 0, st>>>(b);
   k_b_sym_bin_scan<<<1, 1, 0, st>>>(b.ctr);
-  if (bt->total_rows > 0) k_b_sym_bin_fill<<<gr, 256, 0, st>>>(b);
+  if (bt->total_rows > 0) k_b_sym_bin_fill<<<gbin, 256, 0, st>>>(b);
   if (bt->sym_cap > 0) k_b_sym_split_zero<<<grid_for(bt->sym_cap, 256), 256, 0, st>>>(b);
   if (bt->total_lw > 0) k_b_sym_light<<<grid_for(bt->total_lw, kWavesPerBlock), kBlock, 0, st>>>(b);
   k_b_symbolic<<<2048, kBlock, 0, st>>>(b);
@@ -522,9 +538,9 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   k_b_scan<<<1, kScanThreads, 0, st>>>(b);
   if (bt->total_sb > 0) k_b_write_rowptr<<<(unsigned)bt->total_sb, kScanThreads, 0, st>>>(b);
   k_b_empty_rowptr<<<grid_for(bt->count, 256), 256, 0, st>>>(b);
-  if (bt->total_rows > 0) k_b_num_bin_count<<<gr, 256, 0, st>>>(b);
+  if (bt->total_rows > 0) k_b_num_bin_count<<<gbin, 256, 0, st>>>(b);
   k_b_num_bin_scan<<<1, 1, 0, st>>>(b.ctr);
-  if (bt->total_rows > 0) k_b_num_bin_fill<<<gr, 256, 0, st>>>(b);
+  if (bt->total_rows > 0) k_b_num_bin_fill<<<gbin, 256, 0, st>>>(b);
   TSS_CHECK_LAUNCH();
   if (!numeric) return TSSPGEMM_OK;
   const size_t lds = (size_t)kWavesPerBlock * bt->dmax * 8 + kWavesPerBlock * kWave * sizeof(int4);

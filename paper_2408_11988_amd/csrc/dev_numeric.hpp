@@ -408,4 +408,20 @@ __device__ __forceinline__ int chunk_entries(int m, int64_t f, int64_t split) {
   return ce < kMinChunk ? kMinChunk : ce;
 }
 
+// (class, bin) key of a row with f > 0 products and m A entries, and the
+// number of items it makes (split rows: one per chunk).
+__device__ __forceinline__ void num_key(int64_t f, int m, const NumThresholds& th, int& cls, int& key, int& count,
+                                        int& ce) {
+  cls = num_class(f, th);
+  if (cls == 0) {
+    ce = chunk_entries(m, f, th.split);
+    count = (m + ce - 1) / ce;
+    key = 0;
+  } else {
+    ce = 0;
+    count = 1;
+    key = cls * kBins + num_bin(f);
+  }
+}
+
 }  // namespace tss

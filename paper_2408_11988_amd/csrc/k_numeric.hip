@@ -250,22 +250,6 @@ int launch_emit_pattern(const Problem& pr, hipStream_t st) {
   return TSSPGEMM_OK;
 }
 
-// (class, bin) key of a row with f > 0 products and m A entries, and the
-// number of items it makes (split rows: one per chunk).
-__device__ __forceinline__ void num_key(int64_t f, int m, const NumThresholds& th, int& cls, int& key, int& count,
-                                        int& ce) {
-  cls = num_class(f, th);
-  if (cls == 0) {
-    ce = chunk_entries(m, f, th.split);
-    count = (m + ce - 1) / ce;
-    key = 0;
-  } else {
-    ce = 0;
-    count = 1;
-    key = cls * kBins + num_bin(f);
-  }
-}
-
 __global__ void k_num_bin_count(Problem pr, NumThresholds th, Counters* ctr) {
   __shared__ int32_t hist[kNumClasses * kBins];
   for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) hist[t] = 0;
