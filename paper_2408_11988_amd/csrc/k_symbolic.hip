@@ -365,6 +365,118 @@ __global__ __launch_bounds__(kBlock) void k_symbolic(SymParams sp) {
   }
 }
 
+// Unmasked symbolic pass, one lane per A entry: a lane loads the whole
+// bitmap row of its entry's B row (WP words, 16-byte loads), so a wavefront
+// has 64 B rows per load instruction in flight. Light rows: a lane owns a
+// row and walks its entries. Heavy items: the lanes of a wavefront take the
+// item's entries in turn and OR their words together at the end.
+template <int WP>
+struct BmRow {
+  uint32_t w[WP];
+};
+
+template <int WP>
+__device__ __forceinline__ void bm_load_or(const uint32_t* __restrict__ src, BmRow<WP>& acc, int& fl) {
+  if constexpr (WP >= 4) {
+#pragma unroll
+    for (int q = 0; q < WP / 4; ++q) {
+      const uint4 x = reinterpret_cast<const uint4*>(src)[q];
+      acc.w[4 * q] |= x.x;
+      acc.w[4 * q + 1] |= x.y;
+      acc.w[4 * q + 2] |= x.z;
+      acc.w[4 * q + 3] |= x.w;
+      fl += __popc(x.x) + __popc(x.y) + __popc(x.z) + __popc(x.w);
+    }
+  } else if constexpr (WP == 2) {
+    const uint2 x = *reinterpret_cast<const uint2*>(src);
+    acc.w[0] |= x.x;
+    acc.w[1] |= x.y;
+    fl += __popc(x.x) + __popc(x.y);
+  } else {
+    const uint32_t x = *src;
+    acc.w[0] |= x;
+    fl += __popc(x);
+  }
+}
+
+template <int WP>
+__device__ __forceinline__ void bm_store(uint32_t* __restrict__ dst, const BmRow<WP>& acc) {
+  if constexpr (WP >= 4) {
+#pragma unroll
+    for (int q = 0; q < WP / 4; ++q)
+      reinterpret_cast<uint4*>(dst)[q] = make_uint4(acc.w[4 * q], acc.w[4 * q + 1], acc.w[4 * q + 2], acc.w[4 * q + 3]);
+  } else if constexpr (WP == 2) {
+    *reinterpret_cast<uint2*>(dst) = make_uint2(acc.w[0], acc.w[1]);
+  } else {
+    *dst = acc.w[0];
+  }
+}
+
+template <int WP>
+__global__ __launch_bounds__(kBlock) void k_symbolic_light_lanes(SymParams sp) {
+  const Problem& pr = sp.pr;
+  const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (row >= pr.n) return;
+  const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
+  if (p1 - p0 > kSlotRowMax) return;  // a heavy row: done from the item list
+  const uint32_t* __restrict__ bb = pr.bbits;
+  BmRow<WP> acc;
+#pragma unroll
+  for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
+  int fl = 0;
+  int p = p0;
+  for (; p + 1 < p1; p += 2) {
+    const int k0 = pr.aci[p], k1 = pr.aci[p + 1];
+    bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
+    bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
+  }
+  if (p < p1) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
+  bm_store<WP>(pr.cbits + row * WP, acc);
+  pr.flops[row] = fl;
+}
+
+template <int WP>
+__global__ __launch_bounds__(kBlock) void k_symbolic_lanes(SymParams sp) {
+  const Problem& pr = sp.pr;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int total = sp.ctr->sym_total;
+  const int wave_global = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int wave_stride = gridDim.x * kWavesPerBlock;
+  const uint32_t* __restrict__ bb = pr.bbits;
+  for (int t = wave_global; t < total; t += wave_stride) {
+    const Item it = sp.items[t];
+    const bool split = (it.aux & kSplitFlag) != 0;
+    const int64_t row = it.row;
+    BmRow<WP> acc;
+#pragma unroll
+    for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
+    int fl = 0;
+    int p = it.p0 + lane;
+    for (; p + kWave < it.p1; p += 2 * kWave) {
+      const int k0 = pr.aci[p], k1 = pr.aci[p + kWave];
+      bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
+      bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
+    }
+    if (p < it.p1) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
+#pragma unroll
+    for (int w = 0; w < WP; ++w)
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) acc.w[w] |= shfl_xor_u32(acc.w[w], o);
+    const long long fsum = wave_sum_i64((long long)fl);
+    if (lane == 0) {
+      if (split) {
+#pragma unroll
+        for (int w = 0; w < WP; ++w)
+          if (acc.w[w]) atomicOr(&pr.cbits[row * WP + w], acc.w[w]);
+        atomicAdd((unsigned long long*)&pr.flops[row], (unsigned long long)fsum);
+      } else {
+        bm_store<WP>(pr.cbits + row * WP, acc);
+        pr.flops[row] = fsum;
+      }
+    }
+  }
+}
+
 int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st) {
   const int64_t n = sp.pr.n;
   if (n == 0) return TSSPGEMM_OK;
@@ -373,10 +485,19 @@ int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st) {
   // heavy items: enough wavefronts to fill the chip, never more than items
   const int64_t waves = max_items < 256 * 32 ? max_items : 256 * 32;
   const unsigned g_heavy = grid_for(waves, kWavesPerBlock);
-#define TSS_SYM_CASE(W)                                               \
-  case W:                                                             \
-    k_symbolic_light<W><<<g_light, kBlock, 0, st>>>(sp);              \
-    if (max_items > 0) k_symbolic<W><<<g_heavy, kBlock, 0, st>>>(sp); \
+  // without a mask, and for bitmap rows of at most 8 words (registers): one
+  // lane per A entry (k_symbolic_*_lanes)
+  const bool lanes = sp.mask == nullptr && sp.fnz == nullptr && sp.pr.wp <= 8;
+  const unsigned g_lanes = grid_for(n, kBlock);
+#define TSS_SYM_CASE(W)                                                           \
+  case W:                                                                         \
+    if (lanes) {                                                                  \
+      k_symbolic_light_lanes<W><<<g_lanes, kBlock, 0, st>>>(sp);                  \
+      if (max_items > 0) k_symbolic_lanes<W><<<g_heavy, kBlock, 0, st>>>(sp);     \
+    } else {                                                                      \
+      k_symbolic_light<W><<<g_light, kBlock, 0, st>>>(sp);                        \
+      if (max_items > 0) k_symbolic<W><<<g_heavy, kBlock, 0, st>>>(sp);           \
+    }                                                                             \
     break;
   switch (sp.pr.wp) {
     TSS_SYM_CASE(1)

@@ -3,139 +3,123 @@
 // single-GPU form of the column-partitioned copy A^c that the paper keeps
 // beside A (Sec. III-A); the backward pass uses it for dL/dB.
 //
-// Steps: column counts (atomics), exclusive scan into the row pointers,
-// scatter of (i, p) pairs with per-column atomic cursors (order within a
-// column then depends on timing), and a segmented sort of each transposed row
-// by i (keys are distinct, so the result is unique): short segments by one
-// thread, segments up to kSortTile by a workgroup bitonic sort in LDS, longer
-// ones by sorting kSortTile-element tiles and merging runs pairwise.
+// A's entries are already in row order, so a stable sort of the entry
+// positions by column gives A^T directly (within a column the rows stay
+// ascending). The sort is a least-significant-digit radix sort with 8-bit
+// digits over the column index (ceil(log2(ncols) / 8) passes). Each pass:
+// per-tile digit histograms (4096 entries a tile), one exclusive scan over
+// them in digit-major order, then a scatter in which every tile ranks its
+// entries stably (entries in index order; within a wavefront, lanes with the
+// same digit are found with eight ballots). Afterwards the row pointers come
+// from the column boundaries of the sorted keys, and each entry's row from a
+// binary search over A's row pointers (in entry order), gathered through the
+// permutation. Deterministic, no atomics on global memory.
 #include "api_internal.hpp"
 
 namespace tss {
 
-constexpr int kSortTile = 4096;  // uint64 elements sorted in LDS by one workgroup (32 KB)
-constexpr int kTinySeg = 16;
+constexpr int kRsThreads = 256;
+constexpr int kRsPer = 16;                        // entries per thread per tile
+constexpr int kRsTile = kRsThreads * kRsPer;      // 4096
+constexpr int kRsDigits = 256;
 
-__global__ void k_col_count(int64_t nnz, const int32_t* __restrict__ aci, int32_t* __restrict__ cnt) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&cnt[aci[p]], 1);
+// hist[digit * ntiles + tile] = entries of the tile whose key has that digit
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(int64_t nnz, const int32_t* __restrict__ keys, int shift,
+                                                        int64_t ntiles, int32_t* __restrict__ hist) {
+  __shared__ int32_t h[kRsDigits];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+  for (int r = 0; r < kRsPer; ++r) {
+    const int64_t e = base + r * kRsThreads + threadIdx.x;
+    if (e < nnz) atomicAdd(&h[(keys[e] >> shift) & (kRsDigits - 1)], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// one thread per entry; its row comes from a binary search over the row
-// pointers (an L2-resident array)
-__global__ void k_scatter_t(int64_t n, int64_t nnz, const int32_t* __restrict__ arp, const int32_t* __restrict__ aci,
-                            int32_t* __restrict__ cursor, uint64_t* __restrict__ pairs) {
+// Stable scatter of one tile. Entries are taken in rounds of 256 (index
+// order); an entry's destination is its digit's offset for this tile, plus
+// the entries with the same digit in earlier rounds, in earlier wavefronts of
+// this round, and in lower lanes of its wavefront.
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(int64_t nnz, const int32_t* __restrict__ keys_in,
+                                                           const int32_t* __restrict__ vals_in, int shift,
+                                                           int64_t ntiles, const int32_t* __restrict__ offs,
+                                                           int32_t* __restrict__ keys_out,
+                                                           int32_t* __restrict__ vals_out) {
+  __shared__ int32_t base_s[kRsDigits];                 // offset of each digit for this tile, advanced per round
+  __shared__ int32_t wcnt[kRsThreads / kWave][kRsDigits];  // per-wavefront digit counts of the round
+  const int wave = threadIdx.x >> 6;
+  base_s[threadIdx.x] = offs[(int64_t)threadIdx.x * ntiles + blockIdx.x];
+  const int64_t tile0 = (int64_t)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsPer; ++r) {
+    for (int w = 0; w < kRsThreads / kWave; ++w) wcnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t e = tile0 + r * kRsThreads + threadIdx.x;
+    const bool valid = e < nnz;
+    int32_t key = 0, val = 0;
+    if (valid) {
+      key = keys_in[e];
+      val = vals_in ? vals_in[e] : (int32_t)e;
+    }
+    const int dg = (key >> shift) & (kRsDigits - 1);
+    // lanes of this wavefront holding the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const uint64_t ones = __ballot(valid && ((dg >> bit) & 1));
+      peers &= ((dg >> bit) & 1) ? ones : ~ones;
+    }
+    const int below = lanes_below(peers);
+    if (valid && below == 0) wcnt[wave][dg] = __popcll(peers);  // the lowest peer reports the count
+    __syncthreads();
+    if (valid) {
+      int pos = base_s[dg] + below;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][dg];
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    int add = 0;
+    for (int w = 0; w < kRsThreads / kWave; ++w) add += wcnt[w][threadIdx.x];
+    base_s[threadIdx.x] += add;
+    __syncthreads();
+  }
+}
+
+// trp[c] = first position of column c in the sorted keys (trp[m] = nnz):
+// each boundary between different keys fills the pointers of the columns
+// it skips over.
+__global__ void k_col_bounds(int64_t nnz, int64_t m, const int32_t* __restrict__ keys, int32_t* __restrict__ trp) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x <= nnz; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t lo = x == 0 ? 0 : (int64_t)keys[x - 1] + 1;  // columns whose first position is x
+    const int64_t hi = x == nnz ? m : (int64_t)keys[x];
+    for (int64_t c = lo; c <= hi && c <= m; ++c) trp[c] = (int32_t)x;
+  }
+}
+
+// rowof[p] = row of A entry p: a binary search over A's row pointers, in
+// entry order (neighbouring threads take the same path through the search)
+__global__ void k_rows_of(int64_t n, int64_t nnz, const int32_t* __restrict__ arp, int32_t* __restrict__ rowof) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
     int64_t lo = 0, hi = n;  // arp[lo] <= p < arp[hi]
     while (hi - lo > 1) {
       const int64_t mid = (lo + hi) >> 1;
-      if (arp[mid] <= p) lo = mid; else hi = mid;
+      if (arp[mid] <= p)
+        lo = mid;
+      else
+        hi = mid;
     }
-    const int32_t q = atomicAdd(&cursor[aci[p]], 1);
-    pairs[q] = ((uint64_t)(uint32_t)lo << 32) | (uint32_t)p;
+    rowof[p] = (int32_t)lo;
   }
 }
 
-// short segments: insertion sort by one thread (in place, global memory)
-__global__ void k_sort_tiny(int64_t m, const int32_t* __restrict__ trp, uint64_t* __restrict__ pairs) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= m) return;
-  const int32_t a = trp[k], b = trp[k + 1];
-  if (b - a < 2 || b - a > kTinySeg) return;
-  for (int32_t x = a + 1; x < b; ++x) {
-    const uint64_t v = pairs[x];
-    int32_t y = x - 1;
-    while (y >= a && pairs[y] > v) {
-      pairs[y + 1] = pairs[y];
-      --y;
-    }
-    pairs[y + 1] = v;
-  }
-}
-
-// Bitonic sort of `len` (<= kSortTile) elements at `base`, by one workgroup.
-__device__ void wg_sort_tile(uint64_t* base, int len, uint64_t* sh) {
-  int p2 = 1;
-  while (p2 < len) p2 <<= 1;
-  for (int t = threadIdx.x; t < p2; t += blockDim.x) sh[t] = t < len ? base[t] : ~0ull;
-  __syncthreads();
-  for (int k = 2; k <= p2; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < p2; t += blockDim.x) {
-        const int u = t ^ j;
-        if (u > t) {
-          const bool up = (t & k) == 0;
-          const uint64_t x = sh[t], y = sh[u];
-          if ((x > y) == up) {
-            sh[t] = y;
-            sh[u] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  for (int t = threadIdx.x; t < len; t += blockDim.x) base[t] = sh[t];
-  __syncthreads();
-}
-
-// segments with kTinySeg < len: sort tiles of kSortTile in LDS
-__global__ __launch_bounds__(256) void k_sort_tiles(int64_t m, const int32_t* __restrict__ trp,
-                                                    uint64_t* __restrict__ pairs) {
-  __shared__ uint64_t sh[kSortTile];
-  for (int64_t k = blockIdx.x; k < m; k += gridDim.x) {
-    const int32_t a = trp[k], b = trp[k + 1];
-    if (b - a <= kTinySeg) continue;
-    for (int32_t t0 = a; t0 < b; t0 += kSortTile) wg_sort_tile(pairs + t0, min(kSortTile, b - t0), sh);
-  }
-}
-
-// One merge pass over segments longer than `run`: adjacent sorted runs of
-// length `run` are merged into runs of 2*run (src -> dst). Each thread places
-// elements by rank (position in own run + lower/upper bound in the other run).
-__global__ __launch_bounds__(256) void k_merge_pass(int64_t m, const int32_t* __restrict__ trp, int32_t run,
-                                                    const uint64_t* __restrict__ src, uint64_t* __restrict__ dst) {
-  for (int64_t k = blockIdx.x; k < m; k += gridDim.x) {
-    const int32_t a = trp[k], b = trp[k + 1];
-    const int32_t len = b - a;
-    if (len <= kSortTile) continue;
-    for (int32_t x = threadIdx.x; x < len; x += blockDim.x) {
-      const int32_t pair0 = (x / (2 * run)) * (2 * run);
-      const int32_t l0 = pair0, l1 = min(pair0 + run, len);
-      const int32_t r0 = l1, r1 = min(pair0 + 2 * run, len);
-      const uint64_t v = src[a + x];
-      int32_t pos;
-      if (x < l1) {  // element of the left run: count of right elements < v
-        int32_t lo = r0, hi = r1;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if (src[a + mid] < v) lo = mid + 1; else hi = mid;
-        }
-        pos = pair0 + (x - l0) + (lo - r0);
-      } else {  // element of the right run: count of left elements <= v (keys distinct)
-        int32_t lo = l0, hi = l1;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if (src[a + mid] < v) lo = mid + 1; else hi = mid;
-        }
-        pos = pair0 + (x - r0) + (lo - l0);
-      }
-      dst[a + pos] = v;
-    }
-  }
-}
-
-__global__ void k_unpack_t(int64_t nnz, const uint64_t* __restrict__ pairs, int32_t* __restrict__ tci,
-                           int32_t* __restrict__ perm) {
-  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t v = pairs[q];
-    tci[q] = (int32_t)(v >> 32);
-    perm[q] = (int32_t)(uint32_t)v;
-  }
-}
-
-__global__ void k_max_seg(int64_t m, const int32_t* __restrict__ trp, int32_t* __restrict__ out) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k < m) atomicMax(out, trp[k + 1] - trp[k]);
+// tci[x] = rowof[perm[x]]
+__global__ void k_gather_rows(int64_t nnz, const int32_t* __restrict__ perm, const int32_t* __restrict__ rowof,
+                              int32_t* __restrict__ tci) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nnz; x += (int64_t)gridDim.x * blockDim.x)
+    tci[x] = rowof[perm[x]];
 }
 
 static int run_transpose(const tsspgemm_csr* A, int32_t* trp, int32_t* tci, int32_t* perm, hipStream_t st) {
@@ -146,44 +130,45 @@ static int run_transpose(const tsspgemm_csr* A, int32_t* trp, int32_t* tci, int3
     return TSSPGEMM_ERR_INVALID_ARG;
   }
   const int64_t n = A->nrows, m = A->ncols, nnz = A->nnz;
-  DevBuf cnt, cursor, pairs, tmp, mx, scan;
-  if ((rc = cnt.ensure((size_t)(m + 1) * 4)) || (rc = cursor.ensure((size_t)(m + 1) * 4)) ||
-      (rc = scan.ensure((size_t)exscan_workspace_bytes(m))) ||
-      (rc = pairs.ensure((size_t)(nnz + 1) * 8)) || (rc = tmp.ensure((size_t)(nnz + 1) * 8)) || (rc = mx.ensure(4)))
+  if (nnz == 0) {
+    if ((rc = launch_fill_i32(trp, m + 1, 0, st))) return rc;
+    TSS_HIP(hipStreamSynchronize(st));
+    return TSSPGEMM_OK;
+  }
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < m) ++bits;
+  const int passes = (bits + 7) / 8;
+  const int64_t ntiles = (nnz + kRsTile - 1) / kRsTile;
+  const int64_t nh = ntiles * kRsDigits;
+  DevBuf k0, v0, k1, v1, hist, offs, scan;
+  if ((rc = k0.ensure((size_t)nnz * 4)) || (rc = v0.ensure((size_t)nnz * 4)) || (rc = k1.ensure((size_t)nnz * 4)) ||
+      (rc = v1.ensure((size_t)nnz * 4)) || (rc = hist.ensure((size_t)nh * 4)) ||
+      (rc = offs.ensure((size_t)(nh + 1) * 4)) || (rc = scan.ensure((size_t)exscan_workspace_bytes(nh))))
     return rc;
-  if ((rc = launch_zero_bytes(cnt.p, (size_t)(m + 1) * 4, st)) || (rc = launch_zero_bytes(mx.p, 4, st))) return rc;
-  if (nnz > 0) k_col_count<<<grid_for(nnz, 256 * 4) > 8192 ? 8192 : grid_for(nnz, 256 * 4), 256, 0, st>>>(
-      nnz, A->colidx, (int32_t*)cnt.p);
-  TSS_CHECK_LAUNCH();
-  if ((rc = launch_exscan_i32((const int32_t*)cnt.p, m, trp, (int64_t*)scan.p, st))) return rc;
-  TSS_HIP(hipMemcpyAsync(cursor.p, trp, (size_t)m * 4, hipMemcpyDeviceToDevice, st));
-  if (nnz > 0) k_scatter_t<<<grid_for(nnz, 256) > 65536 ? 65536 : grid_for(nnz, 256), 256, 0, st>>>(
-      n, nnz, A->rowptr, A->colidx, (int32_t*)cursor.p, (uint64_t*)pairs.p);
-  if (m > 0) {
-    k_sort_tiny<<<grid_for(m, 256), 256, 0, st>>>(m, trp, (uint64_t*)pairs.p);
-    k_sort_tiles<<<(unsigned)(m < 8192 ? m : 8192), 256, 0, st>>>(m, trp, (uint64_t*)pairs.p);
-    k_max_seg<<<grid_for(m, 256), 256, 0, st>>>(m, trp, (int32_t*)mx.p);
+  const int32_t* kin = A->colidx;  // pass 0 reads A's columns, values = positions
+  const int32_t* vin = nullptr;
+  int32_t* kout = (int32_t*)k0.p;
+  int32_t* vout = (int32_t*)v0.p;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = 8 * pass;
+    k_rs_hist<<<(unsigned)ntiles, kRsThreads, 0, st>>>(nnz, kin, shift, ntiles, (int32_t*)hist.p);
+    TSS_CHECK_LAUNCH();
+    if ((rc = launch_exscan_i32((const int32_t*)hist.p, nh, (int32_t*)offs.p, (int64_t*)scan.p, st))) return rc;
+    k_rs_scatter<<<(unsigned)ntiles, kRsThreads, 0, st>>>(nnz, kin, vin, shift, ntiles, (const int32_t*)offs.p,
+                                                          kout, vout);
+    TSS_CHECK_LAUNCH();
+    kin = kout;
+    vin = vout;
+    kout = (kout == (int32_t*)k0.p) ? (int32_t*)k1.p : (int32_t*)k0.p;
+    vout = (vout == (int32_t*)v0.p) ? (int32_t*)v1.p : (int32_t*)v0.p;
   }
-  TSS_CHECK_LAUNCH();
-  int32_t longest = 0;
-  TSS_HIP(hipMemcpyAsync(&longest, mx.p, 4, hipMemcpyDeviceToHost, st));
-  TSS_HIP(hipStreamSynchronize(st));
-  uint64_t* src = (uint64_t*)pairs.p;
-  uint64_t* dst = (uint64_t*)tmp.p;
-  if (longest > kSortTile) {
-    // segments below the cut keep their data in `src`; copy it along so that
-    // the final buffer is complete whichever buffer the passes end in
-    TSS_HIP(hipMemcpyAsync(dst, src, (size_t)nnz * 8, hipMemcpyDeviceToDevice, st));
-    for (int32_t run = kSortTile; run < longest; run *= 2) {
-      k_merge_pass<<<(unsigned)(m < 8192 ? m : 8192), 256, 0, st>>>(m, trp, run, src, dst);
-      TSS_CHECK_LAUNCH();
-      uint64_t* t = src;
-      src = dst;
-      dst = t;
-    }
-  }
-  if (nnz > 0) k_unpack_t<<<grid_for(nnz, 256 * 4) > 8192 ? 8192 : grid_for(nnz, 256 * 4), 256, 0, st>>>(
-      nnz, src, tci, perm);
+  // kin / vin: keys (columns) and A positions in A^T order
+  const unsigned g = grid_for(nnz + 1, 256) > 8192 ? 8192 : grid_for(nnz + 1, 256);
+  k_col_bounds<<<g, 256, 0, st>>>(nnz, m, kin, trp);
+  TSS_HIP(hipMemcpyAsync(perm, vin, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
+  int32_t* rowof = kout;  // the keys buffer the last pass did not write
+  k_rows_of<<<g, 256, 0, st>>>(n, nnz, A->rowptr, rowof);
+  k_gather_rows<<<g, 256, 0, st>>>(nnz, vin, rowof, tci);
   TSS_CHECK_LAUNCH();
   TSS_HIP(hipStreamSynchronize(st));  // the temporary buffers are released on return
   return TSSPGEMM_OK;
