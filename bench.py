@@ -10,7 +10,8 @@ The same line carries three further measurements of the path (skipped with
 --no-extras): the differentiable layer (numeric forward plus dL/dA and dL/dB on
 R-MAT scale 20 x n x 256 Normal values), the batched run of 64 mixed instances
 replayed from one HIP graph against the same 64 products as plain calls, and
-multi-source BFS (Algorithm 3) from 512 sources on R-MAT scale 22.
+multi-source BFS (Algorithm 3) from 512 sources on R-MAT scale 22, and the
+density of B from which the dense-B SpMM beats TS-SpGEMM (Sec. V-C).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras] [--scale S]
 """
@@ -246,6 +247,65 @@ def bench_batched(steps: int, warmup: int) -> dict:
             "autotune_s": round(t_tune, 2)}
 
 
+def bench_spmm_crossover(reps: int = 5) -> dict:
+    """TS-SpGEMM (symbolic + numeric, and numeric alone with the plan reused)
+    against the dense-B SpMM on the same products, for a range of B densities:
+    R-MAT scale 18 (edge factor 16) x n x 128, U(0,1) values (Sec. V-C)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_11988_amd import DeviceCsr, numeric, spmm, symbolic
+
+    a = synth.rmat(18, 16, synth.CONFIG_SEED + 6)
+    a = a.with_values(synth.values(a, "uniform", synth.CONFIG_SEED + 6, synth.S_AVAL))
+    A = DeviceCsr.from_host(a)
+    n, d = a.nrows, 128
+
+    def med(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e = _events(2)
+            e[0].record()
+            fn()
+            e[1].record()
+            e[1].synchronize()
+            ts.append(e[0].elapsed_time(e[1]))
+        return float(np.median(ts))
+
+    rows = []
+    for rho in (0.05, 0.1, 0.2, 0.35, 0.5, 0.65, 0.8, 1.0):
+        b = synth.b_bernoulli(n, d, rho, synth.CONFIG_SEED + 7)
+        b = b.with_values(synth.values(b, "uniform", synth.CONFIG_SEED + 7, synth.S_BVAL))
+        B = DeviceCsr.from_host(b)
+        dense = torch.zeros((n, d), dtype=torch.float32, device="cuda")
+        rr = torch.repeat_interleave(torch.arange(n, device="cuda"), torch.diff(B.rowptr).to(torch.int64))
+        dense[rr, B.colidx.to(torch.int64)] = B.vals
+        plan, _, nnz = symbolic(A, B)
+        ci = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+        cv = torch.empty(max(nnz, 1), dtype=torch.float32, device="cuda")
+
+        def full():
+            _, _, nz = symbolic(A, B, plan=plan)
+            numeric(plan, A, B, ci, cv)
+
+        ms_full = med(full)
+        ms_num = med(lambda: numeric(plan, A, B, ci, cv))
+        ms_spmm = med(lambda: spmm(A, dense))
+        rows.append({"density": rho, "ms_tsspgemm": round(ms_full, 4), "ms_tsspgemm_numeric": round(ms_num, 4),
+                     "ms_spmm": round(ms_spmm, 4), "nnz_c": nnz})
+        del B, dense, plan, ci, cv
+        torch.cuda.empty_cache()
+    cross = next((r["density"] for r in rows if r["ms_spmm"] <= r["ms_tsspgemm"]), None)
+    cross_num = next((r["density"] for r in rows if r["ms_spmm"] <= r["ms_tsspgemm_numeric"]), None)
+    return {"workload": "R-MAT scale 18 (edge factor 16) x B n x 128 Bernoulli(density), U(0,1), plus-times FP32",
+            "nnz_a": a.nnz, "points": rows,
+            "spmm_wins_from_density": cross, "spmm_wins_from_density_vs_numeric_only": cross_num,
+            "note": "SpMM reads the dense B (zeros included) and writes dense C; TS-SpGEMM reads and writes CSR"}
+
+
 def bench_bfs(cpu: bool) -> dict:
     """Multi-source BFS, R-MAT scale 22, 512 sources: masked Boolean TS-SpGEMM until
     every frontier is empty, levels n x 512 int32."""
@@ -433,6 +493,9 @@ def main():
         result["batched"] = bench_batched(max(4, args.steps // 2), args.warmup)
         log(f"batched graph {result['batched']['ms_graph_replay']} ms vs plain calls "
             f"{result['batched']['ms_64_plain_calls']} ms")
+        torch.cuda.empty_cache()
+        result["spmm_crossover"] = bench_spmm_crossover()
+        log(f"spmm crossover at density {result['spmm_crossover']['spmm_wins_from_density']}")
         torch.cuda.empty_cache()
         result["bfs"] = bench_bfs(not args.no_cpu)
         log(f"bfs {result['bfs']['ms_total']} ms, {result['bfs']['iterations']} iterations")

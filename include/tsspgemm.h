@@ -201,6 +201,18 @@ int tsspgemm_grad_a(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_cs
 int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,
                     const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_b, void* stream);
 
+/* Sparse times dense tall-and-skinny (SpMM), the alternative Sec. V-C
+ * compares TS-SpGEMM with: C = A B with B and C dense, plus-times over FP32,
+ * FP64 sums in a fixed order rounded once to FP32.
+ *   A: n x n CSR with float values. B: n rows of d floats, row-major with
+ *   leading dimension ldb >= d (zeros included). C: n x d, leading dimension
+ *   ldc >= d, every entry written (rows of A without entries give 0).
+ *   1 <= d <= 1024 (d = 0 or n = 0: nothing to do).
+ * Uses the device's workspace cache: calls that overlap on one device race.
+ * Asynchronous. Errors: INVALID_ARG, UNSUPPORTED (d > 1024), NOMEM, HIP. */
+int tsspgemm_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C, int64_t ldc,
+                  void* stream);
+
 /* Batched plus-times TS-SpGEMM: `count` independent instances C_t = A_t B_t
  * (FP32 values, d_t <= 1024), every phase one launch over all instances, the
  * work of all instances binned into one list (heaviest first).

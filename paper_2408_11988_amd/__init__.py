@@ -22,6 +22,7 @@ from .api import (  # noqa: F401
     msbfs,
     numeric,
     spgemm,
+    spmm,
     symbolic,
     transpose,
     version,

@@ -258,6 +258,23 @@ def grad_b(plan: Plan, AT: DeviceCsr, perm: torch.Tensor, A: DeviceCsr, B: Devic
     return out[:B.nnz]
 
 
+def spmm(A: DeviceCsr, B: torch.Tensor, stream=None) -> torch.Tensor:
+    """C = A B with B dense (n x d float32, row-major; zeros included): the
+    SpMM alternative of Sec. V-C. Returns C dense (n x d float32)."""
+    if B.dim() != 2 or B.shape[0] != A.ncols:
+        raise ValueError("B must be n x d")
+    B = B.to(device=A.rowptr.device, dtype=torch.float32)
+    if B.stride(1) != 1:
+        B = B.contiguous()
+    n, d = A.nrows, B.shape[1]
+    C = torch.empty((n, d), dtype=torch.float32, device=A.rowptr.device)
+    da = A.desc()
+    rc = _lib.load().tsspgemm_spmm(ctypes.byref(da), _ptr(B), d, B.stride(0), _ptr(C), C.stride(0),
+                                   _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_spmm")
+    return C
+
+
 class TSSpGEMMOp:
     """C = A B with fixed patterns and trainable values (the sparse layer of a
     training loop). The symbolic plan and A^T are built once; every call runs

@@ -53,6 +53,7 @@ struct Plan {
   DevBuf hmask_rp, hmask_ci, hmask_bits;  // hash plan: copy of the complement mask
   HashMask hmask{};
   DevBuf hstrips;          // hash plan: private d-wide strips of the long-row kernel (kept zero)
+  DevBuf sp_chunks, sp_rows, sp_partial, sp_ctr;  // dense-B SpMM workspace (per-device cached plan)
   size_t hstrips_zeroed = 0;
   Counters* host_ctr = nullptr;  // pinned
   // results of the last symbolic call
