@@ -298,8 +298,18 @@ def bench_spmm_crossover(reps: int = 5) -> dict:
                      "ms_spmm": round(ms_spmm, 4), "nnz_c": nnz})
         del B, dense, plan, ci, cv
         torch.cuda.empty_cache()
-    cross = next((r["density"] for r in rows if r["ms_spmm"] <= r["ms_tsspgemm"]), None)
-    cross_num = next((r["density"] for r in rows if r["ms_spmm"] <= r["ms_tsspgemm_numeric"]), None)
+    def wins_from(key):
+        # lowest measured density from which SpMM is at least as fast at it
+        # and at every higher density (None: TS-SpGEMM wins at the densest)
+        out = None
+        for r in reversed(rows):
+            if r["ms_spmm"] > r[key]:
+                break
+            out = r["density"]
+        return out
+
+    cross = wins_from("ms_tsspgemm")
+    cross_num = wins_from("ms_tsspgemm_numeric")
     return {"workload": "R-MAT scale 18 (edge factor 16) x B n x 128 Bernoulli(density), U(0,1), plus-times FP32",
             "nnz_a": a.nnz, "points": rows,
             "spmm_wins_from_density": cross, "spmm_wins_from_density_vs_numeric_only": cross_num,
