@@ -69,6 +69,12 @@ def _configure(path: str):
     lib.oracle_grad_a_rows.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
     lib.oracle_grad_b_rows.restype = ctypes.c_int
     lib.oracle_grad_b_rows.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+    lib.oracle_embed_force.restype = None
+    lib.oracle_embed_force.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
+    lib.oracle_embed_select.restype = None
+    lib.oracle_embed_select.argtypes = [i64, i64, vp, vp, ctypes.c_double, vp, vp]
+    lib.oracle_embed_epoch.restype = ctypes.c_int
+    lib.oracle_embed_epoch.argtypes = [i64, vp, vp, vp, i64, i64, vp, vp, ctypes.c_double, i64, i64, i64]
     return lib
 
 
@@ -247,3 +253,45 @@ def grad_b_rows(arp, aci, aval, brp, bci, crp, cci, g, krows):
     if rc:
         raise ValueError("G is missing an entry of pat(C) needed by dL/dB")
     return out
+
+
+def _f32(x):
+    return np.ascontiguousarray(x, dtype=np.float32)
+
+
+def embed_force(arp, aci, aval, zci, zval, d: int, k: int, i: int) -> np.ndarray:
+    """F_i of the sparse embedding update (Sec. IV-B): sum over the signed
+    graph's row i of w(a, z_i . z_j) z_j, w = 1 - sig (a > 0), -sig (a < 0)."""
+    arp, aci, zci = _i32(arp), _i32(aci), _i32(zci)
+    aval, zval = _f32(aval), _f32(zval)
+    F = np.empty(d, dtype=np.float64)
+    _load().oracle_embed_force(arp.ctypes.data, aci.ctypes.data, aval.ctypes.data, d, k, zci.ctypes.data,
+                               zval.ctypes.data, i, F.ctypes.data)
+    return F
+
+
+def embed_select(zi_dense, F, lr: float, k: int):
+    """u = z_i + lr F rounded to FP32; the k largest |u| (ties: lower column),
+    sorted by column. Returns (columns int32, values float32)."""
+    zi, F = _f64(zi_dense), _f64(F)
+    ci = np.empty(k, dtype=np.int32)
+    val = np.empty(k, dtype=np.float32)
+    _load().oracle_embed_select(len(zi), k, zi.ctypes.data, F.ctypes.data, float(lr), ci.ctypes.data,
+                                val.ctypes.data)
+    return ci, val
+
+
+def embed_epoch(arp, aci, aval, zci, zval, d: int, k: int, lr: float, batch: int, row_begin: int = 0,
+                row_end: int | None = None):
+    """Rows [row_begin, row_end) of the embedding updated in minibatches of
+    `batch` rows (Sec. IV-B). Returns new (zci, zval); the inputs are not
+    modified. lr is used as given (pass the FP32 value the GPU sees)."""
+    arp, aci = _i32(arp), _i32(aci)
+    aval = _f32(aval)
+    n = len(arp) - 1
+    zci, zval = _i32(zci).copy(), _f32(zval).copy()
+    rc = _load().oracle_embed_epoch(n, arp.ctypes.data, aci.ctypes.data, aval.ctypes.data, d, k, zci.ctypes.data,
+                                    zval.ctypes.data, float(lr), batch, row_begin, n if row_end is None else row_end)
+    if rc:
+        raise ValueError("embed_epoch: bad k, batch or row range")
+    return zci, zval

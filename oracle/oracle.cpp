@@ -13,6 +13,10 @@
 //    A(r,c) != 0 of A(r,c) * B(c,:).
 //  * Sec. IV-A, Algorithm 3: multi-source BFS over the (AND, OR) semiring:
 //    N = A F, F = N \ S, S = S v N, repeat while nnz(F) > 0.
+//  * Sec. IV-B: sparse force-directed embedding. Neighbours pull and
+//    negative samples push; the forces are a TS-SpGEMM of the signed graph
+//    with the embedding, followed by an SGD step and re-sparsification of
+//    each updated row to its largest entries; rows are updated in minibatches.
 //  * Backward of L = sum(C o W) (no counterpart in the paper; definitions of
 //    the derivative of a bilinear form): dL/dA(i,k) = sum_j G(i,j) B(k,j) on
 //    pat(A), dL/dB(k,j) = sum_i A(i,k) G(i,j) on pat(B), G = W on pat(C).
@@ -27,9 +31,22 @@
 //    multiply is AND and the add is OR.
 //  * Complement mask: entries whose column is stored in the mask row are
 //    dropped from the output row.
+//  * Embedding forces (the paper names Force2Vec without its formula): the
+//    sigmoid model of negative sampling. For a stored entry (i, j) with sign
+//    a of the signed graph, s = z_i . z_j, sig = 1 / (1 + exp(-s)), weight
+//    w = 1 - sig if a > 0, -sig if a < 0, 0 if a = 0; F_i = sum_j w z_j is the
+//    gradient in z_i of sum log sig(+-z_i . z_j). Update u = z_i + lr F_i in
+//    FP64, rounded once to FP32. "Keeping the highest valued entries" is read
+//    as the k largest |u| (ties: lower column), so every row keeps exactly k
+//    entries (zeros included when fewer are nonzero), sorted by column.
+//    Within a minibatch every row reads the embedding as it was at the start
+//    of the minibatch; minibatches run in row order, each seeing the ones
+//    before it.
 //  * BFS levels: level 0 at the sources, t at the iteration that first adds
 //    the vertex to S, -1 if never reached. "Neighbours" follow A F: vertex i
 //    is reached from k when A(i,k) != 0.
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <deque>
@@ -377,6 +394,70 @@ int oracle_grad_b_rows(int64_t n, const int32_t* arp, const int32_t* aci, const 
     for (int32_t q = brp[k]; q < brp[k + 1]; ++q) out[o++] = acc.count(bci[q]) ? acc[bci[q]] : 0.0;
   }
   return bad ? -1 : 0;
+}
+
+// ---------------------------------------------------------------- embedding
+
+// Force on row i (Sec. IV-B, sigmoid negative-sampling reading): F = sum over
+// the stored entries (i, j, a) of the signed graph, in column order, of
+// w(a, z_i . z_j) z_j. z rows are k entries each, stored at row * k.
+void oracle_embed_force(const int32_t* arp, const int32_t* aci, const float* aval, int64_t d, int64_t k,
+                        const int32_t* zci, const float* zval, int64_t i, double* F) {
+  std::vector<double> zi(d, 0.0);
+  for (int64_t t = 0; t < k; ++t) zi[zci[i * k + t]] = zval[i * k + t];
+  for (int64_t c = 0; c < d; ++c) F[c] = 0.0;
+  for (int32_t p = arp[i]; p < arp[i + 1]; ++p) {
+    const int64_t j = aci[p];
+    const double a = aval[p];
+    double s = 0.0;
+    for (int64_t t = 0; t < k; ++t) s += zi[zci[j * k + t]] * (double)zval[j * k + t];
+    const double sig = 1.0 / (1.0 + std::exp(-s));
+    const double w = a > 0 ? 1.0 - sig : (a < 0 ? -sig : 0.0);
+    for (int64_t t = 0; t < k; ++t) F[zci[j * k + t]] += w * (double)zval[j * k + t];
+  }
+}
+
+// New row i: u = z_i + lr F in FP64, rounded to FP32; the k columns of
+// largest |u| (ties: lower column), written sorted by column.
+void oracle_embed_select(int64_t d, int64_t k, const double* zi, const double* F, double lr, int32_t* out_ci,
+                         float* out_val) {
+  std::vector<float> u(d);
+  for (int64_t c = 0; c < d; ++c) u[c] = (float)(zi[c] + lr * F[c]);
+  std::vector<int32_t> order(d);
+  for (int64_t c = 0; c < d; ++c) order[c] = (int32_t)c;
+  std::sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const float ax = std::fabs(u[x]), ay = std::fabs(u[y]);
+    return ax != ay ? ax > ay : x < y;
+  });
+  std::vector<int32_t> keep(order.begin(), order.begin() + k);
+  std::sort(keep.begin(), keep.end());
+  for (int64_t t = 0; t < k; ++t) {
+    out_ci[t] = keep[t];
+    out_val[t] = u[keep[t]];
+  }
+}
+
+// Rows [row_begin, row_end) updated in minibatches of `batch` rows, in row
+// order; zci / zval (n x k) are updated in place. Returns 0, or 1 on bad
+// arguments.
+int oracle_embed_epoch(int64_t n, const int32_t* arp, const int32_t* aci, const float* aval, int64_t d, int64_t k,
+                       int32_t* zci, float* zval, double lr, int64_t batch, int64_t row_begin, int64_t row_end) {
+  if (k < 1 || k > d || batch < 1 || row_begin < 0 || row_end > n || row_begin > row_end) return 1;
+  std::vector<double> F(d), zi(d);
+  for (int64_t r0 = row_begin; r0 < row_end; r0 += batch) {
+    const int64_t r1 = std::min(row_end, r0 + batch);
+    std::vector<int32_t> new_ci((r1 - r0) * k);
+    std::vector<float> new_val((r1 - r0) * k);
+    for (int64_t i = r0; i < r1; ++i) {  // every row reads the embedding as of r0
+      oracle_embed_force(arp, aci, aval, d, k, zci, zval, i, F.data());
+      std::fill(zi.begin(), zi.end(), 0.0);
+      for (int64_t t = 0; t < k; ++t) zi[zci[i * k + t]] = zval[i * k + t];
+      oracle_embed_select(d, k, zi.data(), F.data(), lr, &new_ci[(i - r0) * k], &new_val[(i - r0) * k]);
+    }
+    std::copy(new_ci.begin(), new_ci.end(), zci + r0 * k);
+    std::copy(new_val.begin(), new_val.end(), zval + r0 * k);
+  }
+  return 0;
 }
 
 }  // extern "C"

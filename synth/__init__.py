@@ -14,6 +14,8 @@ tall-and-skinny matrices, Sec. V-A, Table V):
               permutation.
 * ``b_*``     B patterns: per-entry Bernoulli(p) or Poisson(lam) entries per
               row at uniform distinct columns.
+* embedding   signed graph (+1 neighbours, -1 uniform negative samples) and
+              an initial embedding with exactly k entries per row.
 * values      U(0,1] on the FP32 grid ((m+1) 2^-24) or N(0,1), keyed by the
               entry's (row, col) so they do not depend on the pattern.
 """
@@ -80,6 +82,10 @@ def _load():
         lib.synth_values.argtypes = [vp, vp, i64, i64, i32, i32, u64, u64, vp]
         lib.synth_sources.restype = i32
         lib.synth_sources.argtypes = [vp, i64, i32, u64, vp]
+        lib.synth_negatives.restype = vp
+        lib.synth_negatives.argtypes = [vp, vp, i64, i32, u64]
+        lib.synth_embed_init.restype = None
+        lib.synth_embed_init.argtypes = [i64, i32, i32, u64, vp, vp]
         _lib = lib
     return _lib
 
@@ -173,6 +179,36 @@ def frontier(n: int, srcs: np.ndarray) -> Csr:
     return Csr(n, d, rp, ci)
 
 
+def negatives(a: Csr, ns: int, seed: int) -> Csr:
+    """`ns` distinct negative samples per vertex: uniform among vertices that
+    are neither the vertex nor one of its neighbours in `a`."""
+    return _take(_load().synth_negatives(a.rp.ctypes.data, a.ci.ctypes.data, a.nrows, ns, seed), a.nrows)
+
+
+def signed_graph(a: Csr, neg: Csr) -> Csr:
+    """The union of the neighbours (+1) and the negative samples (-1) of
+    every vertex, as one CSR with sorted columns (the two patterns are
+    disjoint)."""
+    n = a.nrows
+    rows = np.concatenate([np.repeat(np.arange(n), np.diff(a.rp)), np.repeat(np.arange(n), np.diff(neg.rp))])
+    cols = np.concatenate([a.ci, neg.ci]).astype(np.int64)
+    vals = np.concatenate([np.ones(a.nnz, np.float32), -np.ones(neg.nnz, np.float32)])
+    order = np.lexsort((cols, rows))
+    cnt = np.bincount(rows, minlength=n)
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum(cnt)
+    return Csr(n, n, rp.astype(np.int32), cols[order].astype(np.int32), vals[order])
+
+
+def embed_init(n: int, d: int, k: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Initial sparse n x d embedding with exactly k entries per row, stored
+    at row * k (column ids sorted, int32; values float32)."""
+    ci = np.empty(n * k, dtype=np.int32)
+    val = np.empty(n * k, dtype=np.float32)
+    _load().synth_embed_init(n, d, k, seed, ci.ctypes.data, val.ctypes.data)
+    return ci, val
+
+
 def w_on_pattern(c: Csr, seed: int) -> np.ndarray:
     """W[i,j] ~ N(0,1) for a dense n x d matrix W, evaluated on c's pattern only."""
     return values(c, "normal", seed, S_W)
@@ -212,6 +248,19 @@ def workload_embedding(scale: int = 20, d: int = 256, density: float = 0.05,
     b = b_bernoulli(a.nrows, d, density, seed)
     b = b.with_values(values(b, "normal", seed, S_BVAL))
     return a, b
+
+
+def workload_embed_step(scale: int = 17, edge_factor: int = 8, d: int = 128, sparsity: float = 0.8, ns: int = 5,
+                        seed: int = CONFIG_SEED + 8):
+    """Sparse-embedding epoch: R-MAT graph (a Flickr-sized stand-in at scale 17,
+    edge factor 8) with `ns` negative samples per vertex as a signed n x n
+    matrix (+1 neighbour, -1 negative sample), and an initial n x d embedding
+    with k = d - floor(sparsity * d) entries per row. Returns (A, zci, zval, k)."""
+    g = rmat(scale, edge_factor, seed)
+    a = signed_graph(g, negatives(g, ns, seed))
+    k = d - int(math.floor(sparsity * d + 1e-9))
+    zci, zval = embed_init(a.nrows, d, k, seed)
+    return a, zci, zval, k
 
 
 def batched_params(count: int = 64, seed: int = CONFIG_SEED + 4, n_lo: int = 14, n_hi: int = 18):

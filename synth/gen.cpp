@@ -45,7 +45,7 @@ inline float normal_f32(uint64_t key, uint64_t i) {
 // Streams (distinct purposes never share a key).
 enum : uint64_t {
   S_ER_COL = 1, S_RMAT = 2, S_AVAL = 3, S_BPAT = 4, S_BVAL = 5, S_BLEN = 6,
-  S_BCOL = 7, S_SRC = 8, S_W = 9, S_AVALN = 10,
+  S_BCOL = 7, S_SRC = 8, S_W = 9, S_AVALN = 10, S_NEG = 11, S_ZCOL = 12, S_ZVAL = 13,
 };
 
 // Build a CSR with sorted unique columns from per-row unsorted column lists.
@@ -300,6 +300,64 @@ int32_t synth_sources(const int32_t* rp, int64_t n, int32_t d, uint64_t seed, in
     }
   }
   return got;
+}
+
+// Negative samples for a graph embedding: for each vertex i, `ns` distinct
+// vertices drawn uniformly among those that are neither i nor a neighbour of i
+// (rejection in counter order: draw t of row i is draw(key, i * 4096 + t),
+// t < 4096, so a row with almost no non-neighbours may get fewer). Returns
+// the samples as a CSR pattern with sorted columns.
+void* synth_negatives(const int32_t* rp, const int32_t* ci, int64_t n, int32_t ns, uint64_t seed) {
+  uint64_t key = stream_key(seed, S_NEG);
+  std::vector<int32_t> len(n);
+  std::vector<int32_t> cols((size_t)n * ns);
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t* o = cols.data() + (size_t)i * ns;
+    int32_t got = 0;
+    for (uint64_t t = 0; t < 4096 && got < ns; ++t) {
+      const int32_t v = (int32_t)below(draw(key, (uint64_t)i * 4096 + t), (uint64_t)n);
+      if (v == i || std::binary_search(ci + rp[i], ci + rp[i + 1], v)) continue;
+      bool seen = false;
+      for (int32_t q = 0; q < got; ++q) seen |= (o[q] == v);
+      if (!seen) o[got++] = v;
+    }
+    std::sort(o, o + got);
+    len[i] = got;
+  }
+  Result* r = new Result;
+  r->n = n;
+  r->ncols = n;
+  r->rp.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) r->rp[i + 1] = r->rp[i] + len[i];
+  r->ci.resize(r->rp[n]);
+#pragma omp parallel for
+  for (int64_t i = 0; i < n; ++i)
+    std::copy(cols.data() + (size_t)i * ns, cols.data() + (size_t)i * ns + len[i], r->ci.data() + r->rp[i]);
+  return r;
+}
+
+// Initial sparse embedding: every row of the n x d matrix holds exactly k
+// entries at distinct uniform columns (Floyd's algorithm), sorted, stored at
+// row i * k; values N(0,1) scaled by 1/sqrt(k) (rounded once to FP32), keyed
+// by (row, column).
+void synth_embed_init(int64_t n, int32_t d, int32_t k, uint64_t seed, int32_t* ci, float* val) {
+  uint64_t kcol = stream_key(seed, S_ZCOL), kval = stream_key(seed, S_ZVAL);
+  const double scale = 1.0 / std::sqrt((double)k);
+#pragma omp parallel for
+  for (int64_t i = 0; i < n; ++i) {
+    int32_t* o = ci + i * k;
+    int32_t cnt = 0;
+    for (int32_t j = d - k; j < d; ++j) {
+      int32_t t = (int32_t)below(draw(kcol, (uint64_t)(i * d + j)), (uint64_t)(j + 1));
+      bool seen = false;
+      for (int32_t q = 0; q < cnt; ++q) seen |= (o[q] == t);
+      o[cnt++] = seen ? j : t;
+    }
+    std::sort(o, o + k);
+    for (int32_t q = 0; q < k; ++q)
+      val[i * k + q] = (float)((double)normal_f32(kval, (uint64_t)(i * d + o[q])) * scale);
+  }
 }
 
 }  // extern "C"

@@ -38,6 +38,22 @@ MUTANTS = {
     # dL/dA multiplying by G only
     "grad_a_dropped_factor": ("      s += it->second * bval[q];\n      }\n      grad_a[p] = s;",
                               "      s += it->second;\n      }\n      grad_a[p] = s;"),
+    # embedding: attractive weight with the wrong sign
+    "embed_attract_sign": ("const double w = a > 0 ? 1.0 - sig : (a < 0 ? -sig : 0.0);",
+                           "const double w = a > 0 ? sig - 1.0 : (a < 0 ? -sig : 0.0);"),
+    # embedding: sig and 1 - sig swapped
+    "embed_sigmoid_swapped": ("const double w = a > 0 ? 1.0 - sig : (a < 0 ? -sig : 0.0);",
+                              "const double w = a > 0 ? sig : (a < 0 ? sig - 1.0 : 0.0);"),
+    # embedding: top-k by signed value instead of magnitude
+    "embed_topk_signed": ("const float ax = std::fabs(u[x]), ay = std::fabs(u[y]);",
+                          "const float ax = u[x], ay = u[y];"),
+    # embedding: learning rate dropped
+    "embed_lr_dropped": ("u[c] = (float)(zi[c] + lr * F[c]);", "u[c] = (float)(zi[c] + F[c]);"),
+    # embedding: rows written back at once (later rows of a batch see them)
+    "embed_no_minibatch": ("      oracle_embed_select(d, k, zi.data(), F.data(), lr, &new_ci[(i - r0) * k], &new_val[(i - r0) * k]);\n    }",
+                           "      oracle_embed_select(d, k, zi.data(), F.data(), lr, &new_ci[(i - r0) * k], &new_val[(i - r0) * k]);\n"
+                           "      std::copy(&new_ci[(i - r0) * k], &new_ci[(i - r0) * k] + k, zci + i * k);\n"
+                           "      std::copy(&new_val[(i - r0) * k], &new_val[(i - r0) * k] + k, zval + i * k);\n    }"),
 }
 
 
@@ -103,6 +119,13 @@ def _grad_pin_holds():
                 np.allclose(gb, (dense(a).T @ gd)[rows_of(b.rp), b.ci], rtol=1e-12, atol=1e-12))
 
 
+def _embed_pins_hold():
+    from tests import test_oracle_embed as e
+
+    return e.force_is_loglik_gradient() and e.closed_form_holds() and e.topk_property_holds() and \
+        e.minibatch_schedule_holds()
+
+
 PIN_FOR = {
     "dropped_term": _brute_force_pin_holds,
     "wrong_index": _brute_force_pin_holds,
@@ -111,6 +134,11 @@ PIN_FOR = {
     "mask_after_update": _bfs_pin_holds,
     "grad_b_dropped_factor": _grad_pin_holds,
     "grad_a_dropped_factor": _grad_pin_holds,
+    "embed_attract_sign": _embed_pins_hold,
+    "embed_sigmoid_swapped": _embed_pins_hold,
+    "embed_topk_signed": _embed_pins_hold,
+    "embed_lr_dropped": _embed_pins_hold,
+    "embed_no_minibatch": _embed_pins_hold,
 }
 
 

@@ -71,3 +71,31 @@ def test_batched_params_ranges():
         assert 2**14 <= p["n"] <= 2**18 and p["d"] in (32, 64, 128, 256) and 4 <= p["k"] <= 32
         assert 0.01 <= p["density"] <= 0.5 and p["kind"] in ("er", "rmat")
     assert math.isclose(np.mean([p["kind"] == "er" for p in ps]), 0.5, abs_tol=0.2)
+
+
+def test_negatives_and_signed_graph():
+    g = synth.rmat(9, 8, 123)
+    neg = synth.negatives(g, 5, 123)
+    a = synth.signed_graph(g, neg)
+    assert a.nnz == g.nnz + neg.nnz
+    for i in range(g.nrows):
+        nb = set(g.ci[g.rp[i]:g.rp[i + 1]].tolist())
+        ng = neg.ci[neg.rp[i]:neg.rp[i + 1]]
+        assert len(set(ng.tolist())) == len(ng) and i not in ng and not (nb & set(ng.tolist()))
+        assert len(ng) == min(5, g.nrows - 1 - len(nb))
+        row = a.ci[a.rp[i]:a.rp[i + 1]]
+        assert np.all(np.diff(row) > 0)
+        sgn = a.val[a.rp[i]:a.rp[i + 1]]
+        assert set(row[sgn > 0].tolist()) == nb and set(row[sgn < 0].tolist()) == set(ng.tolist())
+    again = synth.negatives(g, 5, 123)
+    assert np.array_equal(again.ci, neg.ci)
+
+
+def test_embed_init_rows():
+    n, d, k = 500, 64, 13
+    ci, val = synth.embed_init(n, d, k, 9)
+    rows = ci.reshape(n, k)
+    assert np.all(np.diff(rows, axis=1) > 0) and rows.min() >= 0 and rows.max() < d
+    assert np.all(val != 0) and abs(float(np.std(val)) * np.sqrt(k) - 1.0) < 0.05
+    ci2, val2 = synth.embed_init(n, d, k, 9)
+    assert np.array_equal(ci, ci2) and np.array_equal(val, val2)
