@@ -316,6 +316,80 @@ def bench_spmm_crossover(reps: int = 5) -> dict:
             "note": "SpMM reads the dense B (zeros included) and writes dense C; TS-SpGEMM reads and writes CSR"}
 
 
+def bench_embed(cpu: bool) -> dict:
+    """Sparse-embedding update (Sec. IV-B): one epoch over an R-MAT 17 graph
+    (edge factor 8) with 5 negative samples per vertex, d = 128 at 80% sparsity
+    (k = 26), lr 0.02, in minibatches of 256 rows (eager launches and one HIP
+    graph of the whole epoch) and of n/2 rows."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_11988_amd import DeviceCsr, embed_epoch
+
+    a, zci, zval, k = synth.workload_embed_step()
+    d, lr = 128, float(np.float32(0.02))
+    n = a.nrows
+    A = DeviceCsr.from_host(a)
+    z0c, z0v = torch.from_numpy(zci).cuda(), torch.from_numpy(zval).cuda()
+    zc, zv = z0c.clone(), z0v.clone()
+
+    def run(batch):
+        embed_epoch(A, zc, zv, d, k, lr, batch)
+
+    def timed(fn, reps=5):
+        ts = []
+        for _ in range(reps):
+            zc.copy_(z0c)
+            zv.copy_(z0v)
+            e = _events(2)
+            e[0].record()
+            fn()
+            e[1].record()
+            e[1].synchronize()
+            ts.append(e[0].elapsed_time(e[1]))
+        return float(np.median(ts))
+
+    half = (n + 1) // 2
+    run(256)
+    torch.cuda.synchronize()
+    ms_256 = timed(lambda: run(256))
+    ms_half = timed(lambda: run(half))
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run(256)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        run(256)
+    ms_256_graph = timed(graph.replay)
+    deg = np.diff(a.rp).astype(np.int64)
+    # algorithmic bytes of one epoch: the workspace copy of Z (read + write),
+    # per row its A row (8 B an entry + 8 B of row pointers), z_i and every
+    # z_j (8 B an entry), the new row, and the copy of the previous
+    # minibatch's rows (read + write)
+    alg = 16 * n * k + int((8 + 8 * deg + 8 * k * (1 + deg) + 8 * k + 16 * k).sum())
+    out = {"workload": f"R-MAT scale 17 (edge factor 8) + 5 negative samples per vertex, n={n}, nnz(A)={a.nnz}, "
+                       f"d={d}, k={k} (80% sparse), lr 0.02",
+           "ms_epoch_b256": round(ms_256, 3), "ms_epoch_b256_graph": round(ms_256_graph, 3),
+           "ms_epoch_b_half": round(ms_half, 3), "minibatches_b256": (n + 255) // 256,
+           "rows_per_s_b256_graph": round(n / ms_256_graph * 1e3, 1),
+           "force_terms_per_s_b_half": round(a.nnz / ms_half * 1e3, 1),
+           "alg_bytes_epoch": alg, "alg_gbs_b_half": round(alg / ms_half / 1e6, 1),
+           "alg_gbs_b256_graph": round(alg / ms_256_graph / 1e6, 1)}
+    if cpu:
+        import oracle
+
+        t0 = time.perf_counter()
+        oracle.embed_epoch(a.rp, a.ci, a.val, zci, zval, d, k, lr, 256)
+        t = time.perf_counter() - t0
+        out["cpu_oracle_ms_epoch_b256"] = round(t * 1e3, 1)
+        out["cpu_oracle_cores"] = 1
+    return out
+
+
 def bench_bfs(cpu: bool) -> dict:
     """Multi-source BFS, R-MAT scale 22, 512 sources: masked Boolean TS-SpGEMM until
     every frontier is empty, levels n x 512 int32."""
@@ -506,6 +580,10 @@ def main():
         torch.cuda.empty_cache()
         result["spmm_crossover"] = bench_spmm_crossover()
         log(f"spmm crossover at density {result['spmm_crossover']['spmm_wins_from_density']}")
+        torch.cuda.empty_cache()
+        result["embed"] = bench_embed(not args.no_cpu)
+        log(f"embed epoch {result['embed']['ms_epoch_b256_graph']} ms (256-row minibatches, graph), "
+            f"{result['embed']['ms_epoch_b_half']} ms (n/2)")
         torch.cuda.empty_cache()
         result["bfs"] = bench_bfs(not args.no_cpu)
         log(f"bfs {result['bfs']['ms_total']} ms, {result['bfs']['iterations']} iterations")

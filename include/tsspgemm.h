@@ -213,6 +213,27 @@ int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* a
 int tsspgemm_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C, int64_t ldc,
                   void* stream);
 
+/* One pass of the sparse force-directed embedding update (Sec. IV-B) over
+ * rows [row_begin, row_end) of Z, in minibatches of batch_rows rows taken in
+ * row order (the minibatch is the tile height of Sec. IV-B).
+ *   A: n x n CSR with float values: > 0 a neighbour (attractive), < 0 a
+ *      negative sample (repulsive), 0 no force. Sorted columns.
+ *   Z: n x d embedding with exactly k entries per row, row i at i * k in
+ *      z_colidx (ascending, distinct columns < d) and z_vals (float). Updated
+ *      in place for the rows in range; other rows are read only.
+ * For each row i of a minibatch, reading Z as it was when the minibatch
+ * started: s = z_i . z_j, sig = 1 / (1 + exp(-s)), F_i = sum over stored
+ * (i, j, a) of w z_j with w = 1 - sig (a > 0), -sig (a < 0); u = z_i + lr F_i
+ * in FP64, rounded once to float; the new row holds the k entries of largest
+ * |u| (ties: lower column), sorted by column.
+ * 1 <= k <= d <= 1024, batch_rows >= 1, 0 <= row_begin <= row_end <= n.
+ * Uses the device's workspace cache (a second n x k copy of Z): calls that
+ * overlap on one device race. Asynchronous; no allocation after the first
+ * call of a given size. Errors: INVALID_ARG, UNSUPPORTED (d > 1024), NOMEM,
+ * HIP. */
+int tsspgemm_embed_epoch(const tsspgemm_csr* A, int64_t d, int64_t k, int32_t* z_colidx, float* z_vals, float lr,
+                         int64_t batch_rows, int64_t row_begin, int64_t row_end, void* stream);
+
 /* Batched plus-times TS-SpGEMM: `count` independent instances C_t = A_t B_t
  * (FP32 values, d_t <= 1024), every phase one launch over all instances, the
  * work of all instances binned into one list (heaviest first).

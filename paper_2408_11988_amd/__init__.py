@@ -16,6 +16,7 @@ from .api import (  # noqa: F401
     TSSpGEMMFunction,
     TSSpGEMMOp,
     bitmap_words,
+    embed_epoch,
     grad_a,
     grad_b,
     masked_bool,

@@ -275,6 +275,22 @@ def spmm(A: DeviceCsr, B: torch.Tensor, stream=None) -> torch.Tensor:
     return C
 
 
+def embed_epoch(A: DeviceCsr, z_colidx: torch.Tensor, z_vals: torch.Tensor, d: int, k: int, lr: float,
+                batch: int, row_begin: int = 0, row_end: int | None = None, stream=None) -> None:
+    """Sparse force-directed embedding update (Sec. IV-B), in place: rows
+    [row_begin, row_end) of Z (n x d, k entries per row at row * k) in
+    minibatches of `batch` rows. A is the signed n x n graph (+1 neighbour,
+    -1 negative sample)."""
+    n = A.nrows
+    for t, dt in ((z_colidx, torch.int32), (z_vals, torch.float32)):
+        if t.dtype != dt or not t.is_contiguous() or t.numel() != n * k or t.device != A.rowptr.device:
+            raise ValueError("z_colidx / z_vals must be contiguous int32 / float32 of n * k on A's device")
+    da = A.desc()
+    rc = _lib.load().tsspgemm_embed_epoch(ctypes.byref(da), d, k, _ptr(z_colidx), _ptr(z_vals), float(lr), batch,
+                                          row_begin, n if row_end is None else row_end, _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_embed_epoch")
+
+
 class TSSpGEMMOp:
     """C = A B with fixed patterns and trainable values (the sparse layer of a
     training loop). The symbolic plan and A^T are built once; every call runs
