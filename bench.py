@@ -448,6 +448,8 @@ def main():
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the plain workload")
+    ap.add_argument("--leg", choices=["fwd_bwd", "batched", "spmm", "embed", "bfs"],
+                    help="run only this extra workload and print its JSON (for profiling one workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB a few times (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -463,6 +465,15 @@ def main():
         bw = copy_bandwidth_gbs(torch)
         print(json.dumps({"copy_bytes_read_per_launch": 1 << 30, "copy_bytes_written_per_launch": 1 << 30,
                           "launches": 12, "copy_bw_gbs": round(bw, 1)}), flush=True)
+        return
+
+    if args.leg:
+        torch.cuda.set_device(0)
+        legs = {"fwd_bwd": lambda: bench_fwd_bwd(args.steps, args.warmup),
+                "batched": lambda: bench_batched(args.steps, args.warmup),
+                "spmm": bench_spmm_crossover, "embed": lambda: bench_embed(not args.no_cpu),
+                "bfs": lambda: bench_bfs(not args.no_cpu)}
+        print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return
 
     import synth
