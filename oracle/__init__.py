@@ -69,6 +69,10 @@ def _configure(path: str):
     lib.oracle_grad_a_rows.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
     lib.oracle_grad_b_rows.restype = ctypes.c_int
     lib.oracle_grad_b_rows.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, i64, vp]
+    lib.oracle_column_slice.restype = i64
+    lib.oracle_column_slice.argtypes = [i64, vp, vp, vp, i32, i32, vp, vp, vp]
+    lib.oracle_merge_rows.restype = vp
+    lib.oracle_merge_rows.argtypes = [i64, i32, vp, vp, vp]
     lib.oracle_embed_force.restype = None
     lib.oracle_embed_force.argtypes = [vp, vp, vp, i64, i64, vp, vp, i64, vp]
     lib.oracle_embed_select.restype = None
@@ -295,3 +299,33 @@ def embed_epoch(arp, aci, aval, zci, zval, d: int, k: int, lr: float, batch: int
     if rc:
         raise ValueError("embed_epoch: bad k, batch or row range")
     return zci, zval
+
+
+def column_slice(arp, aci, aval, c0: int, c1: int):
+    """Columns [c0, c1) of A with their column ids (a column tile, Sec. III-B).
+    Returns (rp int64, ci int32, val float64 or None)."""
+    arp, aci = _i32(arp), _i32(aci)
+    av = None if aval is None else _f64(aval)
+    n = len(arp) - 1
+    rp = np.empty(n + 1, dtype=np.int64)
+    nnz = _load().oracle_column_slice(n, arp.ctypes.data, aci.ctypes.data, _ptr(av), c0, c1, rp.ctypes.data,
+                                      None, None)
+    ci = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    _load().oracle_column_slice(n, arp.ctypes.data, aci.ctypes.data, _ptr(av), c0, c1, rp.ctypes.data,
+                                ci.ctypes.data, val.ctypes.data)
+    return rp, ci, (val if av is not None else None)
+
+
+def merge_rows(parts):
+    """Sum of n-row CSR matrices given as [(rp, ci, val), ...], row by row, the
+    parts added in order in FP64 (the Merge of Algorithm 2).
+    Returns (rp int64, ci int32, val float64)."""
+    if not parts:
+        raise ValueError("merge_rows needs at least one part")
+    keep = [(_i32(rp), _i32(ci), _f64(v)) for rp, ci, v in parts]
+    n = len(keep[0][0]) - 1
+    arr = lambda xs: (ctypes.c_void_p * len(xs))(*[x.ctypes.data for x in xs])
+    h = _load().oracle_merge_rows(n, len(keep), arr([k[0] for k in keep]), arr([k[1] for k in keep]),
+                                  arr([k[2] for k in keep]))
+    return _take(h, True)

@@ -17,6 +17,9 @@
 //    negative samples push; the forces are a TS-SpGEMM of the signed graph
 //    with the embedding, followed by an SGD step and re-sparsification of
 //    each updated row to its largest entries; rows are updated in minibatches.
+//  * Sec. III-B / III-C, Algorithm 2: A is processed tile by tile (a tile
+//    takes a range of A's columns); the partial products of the tiles are
+//    merged into C. The merge of partial outputs is their sum, row by row.
 //  * Backward of L = sum(C o W) (no counterpart in the paper; definitions of
 //    the derivative of a bilinear form): dL/dA(i,k) = sum_j G(i,j) B(k,j) on
 //    pat(A), dL/dB(k,j) = sum_i A(i,k) G(i,j) on pat(B), G = W on pat(C).
@@ -458,6 +461,47 @@ int oracle_embed_epoch(int64_t n, const int32_t* arp, const int32_t* aci, const 
     std::copy(new_val.begin(), new_val.end(), zval + r0 * k);
   }
   return 0;
+}
+
+// ---------------------------------------------------------------- tiles and merge
+
+// Columns [c0, c1) of A, column ids kept: the tile of Sec. III-B taken over
+// the full height. out_rp (n + 1) is filled; returns nnz, and fills out_ci /
+// out_val when they are non-null.
+int64_t oracle_column_slice(int64_t n, const int32_t* arp, const int32_t* aci, const double* aval, int32_t c0,
+                            int32_t c1, int64_t* out_rp, int32_t* out_ci, double* out_val) {
+  int64_t q = 0;
+  out_rp[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int32_t p = arp[i]; p < arp[i + 1]; ++p)
+      if (aci[p] >= c0 && aci[p] < c1) {
+        if (out_ci) out_ci[q] = aci[p];
+        if (out_val) out_val[q] = aval ? aval[p] : 0.0;
+        ++q;
+      }
+    out_rp[i + 1] = q;
+  }
+  return q;
+}
+
+// Merge of partial outputs (Algorithm 2, Merge): the sum of `count` n-row
+// CSR matrices, row by row, adding the parts in order in FP64.
+void* oracle_merge_rows(int64_t n, int32_t count, const int32_t* const* rps, const int32_t* const* cis,
+                        const double* const* vals) {
+  Rows* r = new Rows;
+  r->rp.assign(n + 1, 0);
+  std::vector<std::map<int32_t, double>> acc(n);
+  for (int32_t t = 0; t < count; ++t)
+    for (int64_t i = 0; i < n; ++i)
+      for (int32_t p = rps[t][i]; p < rps[t][i + 1]; ++p) acc[i][cis[t][p]] += vals[t][p];
+  for (int64_t i = 0; i < n; ++i) {
+    r->rp[i + 1] = r->rp[i] + (int64_t)acc[i].size();
+    for (auto& kv : acc[i]) {
+      r->ci.push_back(kv.first);
+      r->val.push_back(kv.second);
+    }
+  }
+  return r;
 }
 
 }  // extern "C"

@@ -38,6 +38,11 @@ MUTANTS = {
     # dL/dA multiplying by G only
     "grad_a_dropped_factor": ("      s += it->second * bval[q];\n      }\n      grad_a[p] = s;",
                               "      s += it->second;\n      }\n      grad_a[p] = s;"),
+    # merge: the last part dropped
+    "merge_drops_last_part": ("  for (int32_t t = 0; t < count; ++t)\n    for (int64_t i = 0; i < n; ++i)",
+                              "  for (int32_t t = 0; t + 1 < count; ++t)\n    for (int64_t i = 0; i < n; ++i)"),
+    # column tile: the upper bound included
+    "slice_upper_bound_included": ("if (aci[p] >= c0 && aci[p] < c1) {", "if (aci[p] >= c0 && aci[p] <= c1) {"),
     # embedding: attractive weight with the wrong sign
     "embed_attract_sign": ("const double w = a > 0 ? 1.0 - sig : (a < 0 ? -sig : 0.0);",
                            "const double w = a > 0 ? sig - 1.0 : (a < 0 ? -sig : 0.0);"),
@@ -119,6 +124,12 @@ def _grad_pin_holds():
                 np.allclose(gb, (dense(a).T @ gd)[rows_of(b.rp), b.ci], rtol=1e-12, atol=1e-12))
 
 
+def _tile_pins_hold():
+    from tests import test_oracle_tiles as t
+
+    return t.slice_matches_dense() and t.merge_matches_dense()
+
+
 def _embed_pins_hold():
     from tests import test_oracle_embed as e
 
@@ -134,6 +145,8 @@ PIN_FOR = {
     "mask_after_update": _bfs_pin_holds,
     "grad_b_dropped_factor": _grad_pin_holds,
     "grad_a_dropped_factor": _grad_pin_holds,
+    "merge_drops_last_part": _tile_pins_hold,
+    "slice_upper_bound_included": _tile_pins_hold,
     "embed_attract_sign": _embed_pins_hold,
     "embed_sigmoid_swapped": _embed_pins_hold,
     "embed_topk_signed": _embed_pins_hold,
