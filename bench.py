@@ -390,6 +390,59 @@ def bench_embed(cpu: bool) -> dict:
     return out
 
 
+def bench_tiles() -> dict:
+    """Column-tiled multiply (Sec. III-B, Algorithm 2 on one GPU) on the plain
+    workload, R-MAT 20 x 128: for T column tiles, the numeric phases of the T
+    tile products (plans made beforehand) and the merge of their outputs,
+    against T = 1 (the plain multiply's numeric phase)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_11988_amd import DeviceCsr, column_slice, merge_rows, numeric, symbolic, tile_edges
+
+    a, b = synth.workload_rmat_plain(scale=20, d=128)
+    A, B = DeviceCsr.from_host(a), DeviceCsr.from_host(b)
+
+    def med(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e = _events(2)
+            e[0].record()
+            fn()
+            e[1].record()
+            e[1].synchronize()
+            ts.append(e[0].elapsed_time(e[1]))
+        return float(np.median(ts))
+
+    rows = []
+    for T in (1, 2, 4, 8, 16, 32):
+        e = tile_edges(a.nrows, T)
+        slices = [column_slice(A, e[t], e[t + 1]) for t in range(T)]
+        plans = []
+        for S in slices:
+            plan, rp, nnz = symbolic(S, B)
+            plans.append((S, plan, rp, torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda"),
+                          torch.empty(max(nnz, 1), dtype=torch.float32, device="cuda")))
+
+        def numerics():
+            for S, plan, rp, ci, cv in plans:
+                numeric(plan, S, B, ci, cv)
+
+        ms_num = med(numerics)
+        parts = [DeviceCsr(a.nrows, b.ncols, rp, ci[:int(rp[-1])], cv[:int(rp[-1])]) for S, plan, rp, ci, cv in plans]
+        ms_merge = med(lambda: merge_rows(parts)) if T > 1 else 0.0
+        rows.append({"tiles": T, "tile_columns": e[1] - e[0], "b_rows_bytes_per_tile": int(5 * (b.rp[e[1]] - b.rp[0])),
+                     "partial_nnz": int(sum(int(p.nnz) for p in parts)), "ms_numeric_sum": round(ms_num, 4),
+                     "ms_merge": round(ms_merge, 4), "ms_numeric_and_merge": round(ms_num + ms_merge, 4)})
+        del plans, parts, slices
+        torch.cuda.empty_cache()
+    return {"workload": "R-MAT scale 20 (edge factor 16) x B n x 128 Poisson(25.6)/row, U(0,1), plus-times FP32",
+            "points": rows,
+            "note": "T = 1 is the plain multiply; B rows of a tile hold 5 B per entry (narrowed id and value)"}
+
+
 def bench_bfs(cpu: bool) -> dict:
     """Multi-source BFS, R-MAT scale 22, 512 sources: masked Boolean TS-SpGEMM until
     every frontier is empty, levels n x 512 int32."""
@@ -448,7 +501,7 @@ def main():
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the plain workload")
-    ap.add_argument("--leg", choices=["fwd_bwd", "batched", "spmm", "embed", "bfs"],
+    ap.add_argument("--leg", choices=["fwd_bwd", "batched", "spmm", "embed", "tiles", "bfs"],
                     help="run only this extra workload and print its JSON (for profiling one workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB a few times (reference for the HBM byte counters) and exit")
@@ -469,7 +522,7 @@ def main():
 
     if args.leg:
         torch.cuda.set_device(0)
-        legs = {"fwd_bwd": lambda: bench_fwd_bwd(args.steps, args.warmup),
+        legs = {"fwd_bwd": lambda: bench_fwd_bwd(args.steps, args.warmup), "tiles": bench_tiles,
                 "batched": lambda: bench_batched(args.steps, args.warmup),
                 "spmm": bench_spmm_crossover, "embed": lambda: bench_embed(not args.no_cpu),
                 "bfs": lambda: bench_bfs(not args.no_cpu)}
@@ -591,6 +644,10 @@ def main():
         torch.cuda.empty_cache()
         result["spmm_crossover"] = bench_spmm_crossover()
         log(f"spmm crossover at density {result['spmm_crossover']['spmm_wins_from_density']}")
+        torch.cuda.empty_cache()
+        result["tiles"] = bench_tiles()
+        log("tiled multiply: " + ", ".join(f"T={r['tiles']} {r['ms_numeric_and_merge']} ms"
+                                           for r in result["tiles"]["points"]))
         torch.cuda.empty_cache()
         result["embed"] = bench_embed(not args.no_cpu)
         log(f"embed epoch {result['embed']['ms_epoch_b256_graph']} ms (256-row minibatches, graph), "

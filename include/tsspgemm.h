@@ -234,6 +234,30 @@ int tsspgemm_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb,
 int tsspgemm_embed_epoch(const tsspgemm_csr* A, int64_t d, int64_t k, int32_t* z_colidx, float* z_vals, float lr,
                          int64_t batch_rows, int64_t row_begin, int64_t row_end, void* stream);
 
+/* Column tile of A (Sec. III-B): A(:, c0:c1), every row, column ids kept, so
+ * that (A(:, c0:c1)) B reads only B's rows c0..c1-1. Two calls: the count
+ * fills out_rowptr (nrows + 1, device) and writes the tile's nnz to *out_nnz
+ * (HOST; synchronizes once); the fill writes out_colidx / out_vals (nnz
+ * entries; out_vals may be NULL for the pattern only). 0 <= c0 <= c1.
+ * Both allocate temporaries. Errors: INVALID_ARG, NOMEM, HIP. */
+int tsspgemm_column_slice_count(const tsspgemm_csr* A, int32_t c0, int32_t c1, int32_t* out_rowptr,
+                                int64_t* out_nnz, void* stream);
+int tsspgemm_column_slice_fill(const tsspgemm_csr* A, int32_t c0, int32_t c1, const int32_t* out_rowptr,
+                               int32_t* out_colidx, float* out_vals, void* stream);
+
+/* Merge of partial outputs (Algorithm 2, Merge; Sec. III-C: a dense
+ * accumulator for small d): C = sum of `count` n x d CSR parts (parts is a
+ * HOST array of descriptors; sorted columns; float values). Output pattern:
+ * the union of the parts' patterns; values: FP64 sums with the parts added in
+ * order, rounded once. 1 <= count <= 64, d <= 1024. The count writes
+ * out_rowptr (n + 1) and *out_nnz (HOST; synchronizes once; allocates
+ * temporaries); the values call writes out_colidx / out_vals (asynchronous).
+ * Errors: INVALID_ARG, UNSUPPORTED (count > 64 or d > 1024), NOMEM, HIP. */
+int tsspgemm_merge_count(int32_t count, const tsspgemm_csr* parts, int32_t* out_rowptr, int64_t* out_nnz,
+                         void* stream);
+int tsspgemm_merge_values(int32_t count, const tsspgemm_csr* parts, const int32_t* out_rowptr, int32_t* out_colidx,
+                          float* out_vals, void* stream);
+
 /* Batched plus-times TS-SpGEMM: `count` independent instances C_t = A_t B_t
  * (FP32 values, d_t <= 1024), every phase one launch over all instances, the
  * work of all instances binned into one list (heaviest first).

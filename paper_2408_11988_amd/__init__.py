@@ -16,15 +16,19 @@ from .api import (  # noqa: F401
     TSSpGEMMFunction,
     TSSpGEMMOp,
     bitmap_words,
+    column_slice,
     embed_epoch,
     grad_a,
     grad_b,
     masked_bool,
+    merge_rows,
     msbfs,
     numeric,
     spgemm,
     spmm,
     symbolic,
+    tile_edges,
+    tiled_spgemm,
     transpose,
     version,
 )

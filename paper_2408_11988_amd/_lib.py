@@ -71,6 +71,10 @@ _SIGNATURES = {
     "tsspgemm_grad_a": (ctypes.c_int, [vp, P(CsrDesc), P(CsrDesc), P(CsrDesc), vp, vp]),
     "tsspgemm_grad_b": (ctypes.c_int, [vp, P(CsrDesc), vp, P(CsrDesc), P(CsrDesc), P(CsrDesc), vp, vp]),
     "tsspgemm_spmm": (ctypes.c_int, [P(CsrDesc), vp, i64, i64, vp, i64, vp]),
+    "tsspgemm_column_slice_count": (ctypes.c_int, [P(CsrDesc), ctypes.c_int32, ctypes.c_int32, vp, P(i64), vp]),
+    "tsspgemm_column_slice_fill": (ctypes.c_int, [P(CsrDesc), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]),
+    "tsspgemm_merge_count": (ctypes.c_int, [ctypes.c_int32, P(CsrDesc), vp, P(i64), vp]),
+    "tsspgemm_merge_values": (ctypes.c_int, [ctypes.c_int32, P(CsrDesc), vp, vp, vp, vp]),
     "tsspgemm_embed_epoch": (ctypes.c_int, [P(CsrDesc), i64, i64, vp, vp, ctypes.c_float, i64, i64, i64, vp]),
     "tsspgemm_batched_plan": (ctypes.c_int, [i32, P(CsrDesc), P(CsrDesc), P(Tuning), P(vp), P(i64), P(i64), vp]),
     "tsspgemm_batched_run": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),

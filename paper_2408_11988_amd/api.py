@@ -275,6 +275,57 @@ def spmm(A: DeviceCsr, B: torch.Tensor, stream=None) -> torch.Tensor:
     return C
 
 
+def column_slice(A: DeviceCsr, c0: int, c1: int, stream=None) -> DeviceCsr:
+    """Column tile A(:, c0:c1) with its column ids (Sec. III-B)."""
+    dev = A.rowptr.device
+    rp = torch.empty(A.nrows + 1, dtype=torch.int32, device=dev)
+    nnz = ctypes.c_int64(0)
+    da = A.desc()
+    lib = _lib.load()
+    _lib.check(lib.tsspgemm_column_slice_count(ctypes.byref(da), c0, c1, _ptr(rp), ctypes.byref(nnz),
+                                               _stream_ptr(stream)), "tsspgemm_column_slice_count")
+    ci = torch.empty(nnz.value, dtype=torch.int32, device=dev)
+    v = None if A.vals is None else torch.empty(nnz.value, dtype=torch.float32, device=dev)
+    _lib.check(lib.tsspgemm_column_slice_fill(ctypes.byref(da), c0, c1, _ptr(rp), _ptr(ci) if nnz.value else None,
+                                              _ptr(v) if v is not None and nnz.value else None, _stream_ptr(stream)),
+               "tsspgemm_column_slice_fill")
+    return DeviceCsr(A.nrows, A.ncols, rp, ci, v)
+
+
+def merge_rows(parts: list, stream=None) -> DeviceCsr:
+    """Sum of n x d CSR parts, row by row, parts added in order (the Merge of
+    Algorithm 2)."""
+    descs = (_lib.CsrDesc * len(parts))(*[p.desc() for p in parts])
+    n, d = parts[0].nrows, parts[0].ncols
+    dev = parts[0].rowptr.device
+    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    nnz = ctypes.c_int64(0)
+    lib = _lib.load()
+    _lib.check(lib.tsspgemm_merge_count(len(parts), descs, _ptr(rp), ctypes.byref(nnz), _stream_ptr(stream)),
+               "tsspgemm_merge_count")
+    ci = torch.empty(nnz.value, dtype=torch.int32, device=dev)
+    v = torch.empty(nnz.value, dtype=torch.float32, device=dev)
+    _lib.check(lib.tsspgemm_merge_values(len(parts), descs, _ptr(rp), _ptr(ci) if nnz.value else None,
+                                         _ptr(v) if nnz.value else None, _stream_ptr(stream)),
+               "tsspgemm_merge_values")
+    return DeviceCsr(n, d, rp, ci, v)
+
+
+def tile_edges(n: int, tiles: int) -> list:
+    """Column boundaries of `tiles` near-equal column tiles of an n-column A."""
+    return [(t * n) // tiles for t in range(tiles + 1)]
+
+
+def tiled_spgemm(A: DeviceCsr, B: DeviceCsr, tiles: int, tuning: dict | None = None, stream=None) -> DeviceCsr:
+    """C = A B computed tile by tile (Sec. III-B, Algorithm 2 on one GPU): for
+    each of `tiles` column ranges of A, the product of that tile with B (it
+    reads only B's rows in the range), then the merge of the partial outputs.
+    Each partial value is rounded to FP32 before the merge."""
+    e = tile_edges(A.ncols, tiles)
+    parts = [spgemm(column_slice(A, e[t], e[t + 1], stream), B, tuning=tuning, stream=stream) for t in range(tiles)]
+    return parts[0] if tiles == 1 else merge_rows(parts, stream)
+
+
 def embed_epoch(A: DeviceCsr, z_colidx: torch.Tensor, z_vals: torch.Tensor, d: int, k: int, lr: float,
                 batch: int, row_begin: int = 0, row_end: int | None = None, stream=None) -> None:
     """Sparse force-directed embedding update (Sec. IV-B), in place: rows
