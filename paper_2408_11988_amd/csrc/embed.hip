@@ -12,7 +12,7 @@
 // One wavefront per work item, with z_i dense in LDS (FP32). The wavefront
 // is split into P groups of GL = 64 / P lanes (GL >= k when possible); group
 // g takes A entries g, g + P, ...: its lanes load z_j (coalesced), form the
-// dot product with z_i, reduce it inside the group, and add w z_j into the
+// dot product with z_i, reduce it inside the group (DPP), and add w z_j into the
 // group's own d-wide FP64 strip in LDS. Each group keeps U z_j rows in
 // flight. The P strips are summed in group order, so every result is
 // deterministic. u then replaces z_i in LDS, and the selection is a radix
@@ -34,6 +34,7 @@
 // W_t.
 #include "api_internal.hpp"
 #include "dev_numeric.hpp"
+#include "dev_reduce.hpp"
 
 namespace tss {
 
@@ -152,8 +153,7 @@ __device__ __forceinline__ void embed_accumulate(const EmbedParams& ep, int p0, 
 #pragma unroll
         for (int q = 0; q < KPL; ++q)
           if ((uint32_t)cc[u][q] < (uint64_t)d) dot += (double)zs[cc[u][q]] * (double)vv[u][q];
-#pragma unroll
-        for (int o = GL / 2; o > 0; o >>= 1) dot += __shfl_xor(dot, o, kWave);
+        dot = group_sum_f64<GL>(dot);
         const double sig = 1.0 / (1.0 + exp(-dot));
         const double w = a[u] > 0.0f ? 1.0 - sig : (a[u] < 0.0f ? -sig : 0.0);
 #pragma unroll
