@@ -12,14 +12,17 @@
 // column still open to it (later ones could only add masked bits). The
 // masked product is directly N \ S, i.e. the next frontier.
 // Levels are written once, at the end, from the kept frontiers N_0..N_T: a
-// wavefront owns 64 consecutive columns of a row, so every store is
-// coalesced, and never-reached pairs get -1 in the same pass.
+// lane owns 4 consecutive columns of a row (one 16-byte store), so every
+// store is coalesced, and never-reached pairs get -1 in the same pass.
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "api_internal.hpp"
 
 namespace tss {
+
+constexpr int kBfsUpdateBlocks = 2048;  // fixed grid of the frontier update
 
 // N_0: bit j of row sources[j]; a source outside [0, n) sets the error flag.
 __global__ void k_bfs_seed(const int32_t* __restrict__ src, int32_t d, int64_t n, int wp, uint32_t* __restrict__ n0,
@@ -34,40 +37,89 @@ __global__ void k_bfs_seed(const int32_t* __restrict__ src, int32_t d, int64_t n
   atomicOr(&n0[(int64_t)v * wp + (j >> 5)], 1u << (j & 31));
 }
 
-// S |= N, the per-row frontier summary bits, and per-workgroup partial counts
-// and column ORs of N (reduced by k_bfs_reduce). One thread per row.
+// S |= N, the non-empty-row summary of N (fnz: bit r of word i >> 5 = row i
+// of N has a bit), and per workgroup the OR of N's words by column word and
+// the number of set bits. A fixed grid strides over tiles of 256 V / wp rows,
+// V = min(4, wp) words per lane (one 4-, 8- or 16-byte load): thread t
+// always holds the same V word columns, so every load is coalesced; the
+// wp / V lanes of a row OR their words with shuffles for its summary bit, and
+// a tile's summary words (32 rows each) are gathered in LDS.
+template <int V>
 __global__ __launch_bounds__(256) void k_bfs_update(int64_t n, int wp, const uint32_t* __restrict__ N,
                                                     uint32_t* __restrict__ S, uint32_t* __restrict__ fnz,
                                                     uint32_t* __restrict__ part_or, int64_t* __restrict__ part_cnt) {
+  using Vec = typename std::conditional<V == 4, uint4, typename std::conditional<V == 2, uint2, uint32_t>::type>::type;
+  constexpr int kMaxTileWords = 256 * V / 32;  // summary words per tile (at most 32)
   __shared__ uint32_t sor[32];
+  __shared__ uint32_t sfnz[kMaxTileWords];
   __shared__ unsigned long long scnt;
-  if (threadIdx.x < 32) sor[threadIdx.x] = 0u;
-  if (threadIdx.x == 0) scnt = 0ull;
+  const int t = threadIdx.x;
+  if (t < 32) sor[t] = 0u;
+  if (t < kMaxTileWords) sfnz[t] = 0u;
+  if (t == 0) scnt = 0ull;
   __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int cnt = 0;
-  bool nz = false;
-  if (i < n) {
-    for (int w = 0; w < wp; ++w) {
-      const uint32_t x = N[i * wp + w];
-      if (x) {
-        nz = true;
-        cnt += __popc(x);
-        S[i * wp + w] |= x;
-        atomicOr(&sor[w], x);
+  const int lpr = wp / V;                  // lanes per row
+  const int w0 = (t % lpr) * V;            // this thread's first word column
+  const int rows = 256 / lpr;              // rows per tile
+  const int64_t ntiles = (n + rows - 1) / rows;
+  uint32_t wor[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) wor[v] = 0u;
+  long long cnt = 0;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int r = t / lpr;
+    const int64_t row = tile * rows + r;
+    uint32_t x[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) x[v] = 0u;
+    if (row < n) {
+      const Vec xv = *reinterpret_cast<const Vec*>(N + row * wp + w0);
+      if constexpr (V == 4) {
+        x[0] = xv.x; x[1] = xv.y; x[2] = xv.z; x[3] = xv.w;
+      } else if constexpr (V == 2) {
+        x[0] = xv.x; x[1] = xv.y;
+      } else {
+        x[0] = xv;
       }
     }
+    uint32_t any = 0u;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      any |= x[v];
+      wor[v] |= x[v];
+      cnt += __popc(x[v]);
+    }
+    if (any) {
+      Vec* sp = reinterpret_cast<Vec*>(S + row * wp + w0);
+      Vec sv = *sp;
+      if constexpr (V == 4) {
+        sv.x |= x[0]; sv.y |= x[1]; sv.z |= x[2]; sv.w |= x[3];
+      } else if constexpr (V == 2) {
+        sv.x |= x[0]; sv.y |= x[1];
+      } else {
+        sv |= x[0];
+      }
+      *sp = sv;
+    }
+    for (int o = 1; o < lpr; o <<= 1) any |= shfl_xor_u32(any, o);
+    if (t % lpr == 0 && any) atomicOr(&sfnz[r >> 5], 1u << (r & 31));
+    __syncthreads();
+    const int tw = (rows + 31) / 32;
+    if (t < tw) {
+      const int64_t fw = tile * rows / 32 + t;  // rows is a multiple of 32
+      if (fw * 32 < n) fnz[fw] = sfnz[t];
+      sfnz[t] = 0u;
+    }
+    __syncthreads();
   }
-  const uint64_t b = __ballot(nz);
-  const int lane = threadIdx.x & 63;
-  const int64_t r0 = i - lane;  // first row of this wavefront, a multiple of 64
-  if (lane == 0 && r0 < n) fnz[r0 >> 5] = (uint32_t)b;
-  if (lane == 32 && r0 + 32 < n) fnz[(r0 >> 5) + 1] = (uint32_t)(b >> 32);
-  const int wsum = wave_sum_i32(cnt);
-  if (lane == 0 && wsum) atomicAdd(&scnt, (unsigned long long)wsum);
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    if (wor[v]) atomicOr(&sor[w0 + v], wor[v]);
+  const long long wsum = wave_sum_i64(cnt);
+  if ((t & (kWave - 1)) == 0 && wsum) atomicAdd(&scnt, (unsigned long long)wsum);
   __syncthreads();
-  if (threadIdx.x < wp) part_or[(int64_t)blockIdx.x * wp + threadIdx.x] = sor[threadIdx.x];
-  if (threadIdx.x == 0) part_cnt[blockIdx.x] = (int64_t)scnt;
+  if (t < wp) part_or[(int64_t)blockIdx.x * wp + t] = sor[t];
+  if (t == 0) part_cnt[blockIdx.x] = (int64_t)scnt;
 }
 
 // One workgroup: OR of the partial column masks -> active, sum -> count.
@@ -172,7 +224,10 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
   tsspgemm_csr bdummy{n, d, 0, A->rowptr, nullptr, nullptr};
   resolve_tuning(nullptr, &bdummy, &tn);
   const int64_t sym_cap = n + A->nnz / tn.sym_split_nnz + 2;
-  const int64_t nblk = (n + 255) / 256;
+  const int upd_v = wp < 4 ? wp : 4;                        // words per lane in k_bfs_update
+  const int64_t upd_rows = 256 / (wp / upd_v);              // rows per tile
+  const int64_t ntiles = (n + upd_rows - 1) / upd_rows;
+  const int64_t nblk = ntiles < kBfsUpdateBlocks ? ntiles : kBfsUpdateBlocks;  // workgroups of k_bfs_update
   if ((rc = p.ctr.ensure(sizeof(Counters))) || (rc = p.flops.ensure((size_t)n * 8)) ||
       (rc = p.sym_items.ensure((size_t)sym_cap * sizeof(Item))) || (rc = w.S.ensure((size_t)n * wp * 4)) ||
       (rc = w.fnz.ensure((size_t)(n / 32 + 4) * 4)) || (rc = w.active.ensure(32 * 4)) ||
@@ -199,9 +254,18 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
     return r;
   };
   auto update = [&](const uint32_t* N, int64_t* cnt_out) -> int {
-    if (n > 0)
-      k_bfs_update<<<(unsigned)nblk, 256, 0, st>>>(n, wp, N, (uint32_t*)w.S.p, (uint32_t*)w.fnz.p,
-                                                    (uint32_t*)w.part_or.p, (int64_t*)w.part_cnt.p);
+    if (n > 0) {
+      auto* so = (uint32_t*)w.S.p;
+      auto* fz = (uint32_t*)w.fnz.p;
+      auto* po = (uint32_t*)w.part_or.p;
+      auto* pc = (int64_t*)w.part_cnt.p;
+      if (upd_v == 4)
+        k_bfs_update<4><<<(unsigned)nblk, 256, 0, st>>>(n, wp, N, so, fz, po, pc);
+      else if (upd_v == 2)
+        k_bfs_update<2><<<(unsigned)nblk, 256, 0, st>>>(n, wp, N, so, fz, po, pc);
+      else
+        k_bfs_update<1><<<(unsigned)nblk, 256, 0, st>>>(n, wp, N, so, fz, po, pc);
+    }
     k_bfs_reduce<<<1, 1024, 0, st>>>(n > 0 ? nblk : 0, wp, (const uint32_t*)w.part_or.p,
                                      (const int64_t*)w.part_cnt.p, (uint32_t*)w.active.p, (int64_t*)w.count.p);
     TSS_CHECK_LAUNCH();
