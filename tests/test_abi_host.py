@@ -100,3 +100,39 @@ def test_python_errors_are_raised():
     with pytest.raises(_lib.TSSpGEMMError) as e:
         _lib.check(_lib.ERR_UNSUPPORTED, "where")
     assert e.value.code == _lib.ERR_UNSUPPORTED and "UNSUPPORTED" in str(e.value)
+
+
+def test_argument_errors_of_the_extra_entry_points(lib):
+    """SpMM, the embedding epoch, column tiles and the merge reject bad
+    arguments on the host, before any device work."""
+    from paper_2408_11988_amd import _lib
+
+    p = ctypes.c_void_p(0x1000)
+    a = _desc(4, 4, 2)
+    rect = _desc(4, 5, 2)
+    # spmm
+    assert lib.tsspgemm_spmm(ctypes.byref(rect), p, 8, 8, p, 8, None) == _lib.ERR_INVALID_ARG
+    assert lib.tsspgemm_spmm(ctypes.byref(a), p, 8, 4, p, 8, None) == _lib.ERR_INVALID_ARG  # ldb < d
+    assert lib.tsspgemm_spmm(ctypes.byref(a), p, 2000, 2000, p, 2000, None) == _lib.ERR_UNSUPPORTED
+    # embedding epoch
+    emb = lambda d, k, b, r0, r1: lib.tsspgemm_embed_epoch(ctypes.byref(a), d, k, p, p, 0.1, b, r0, r1, None)
+    assert emb(8, 9, 4, 0, 4) == _lib.ERR_INVALID_ARG    # k > d
+    assert emb(8, 0, 4, 0, 4) == _lib.ERR_INVALID_ARG    # k < 1
+    assert emb(8, 4, 0, 0, 4) == _lib.ERR_INVALID_ARG    # batch < 1
+    assert emb(8, 4, 2, 3, 2) == _lib.ERR_INVALID_ARG    # row_begin > row_end
+    assert emb(8, 4, 2, 0, 5) == _lib.ERR_INVALID_ARG    # row_end > n
+    assert emb(2048, 4, 2, 0, 4) == _lib.ERR_UNSUPPORTED  # d > 1024
+    assert emb(8, 4, 2, 2, 2) == _lib.OK                 # empty range: nothing to do
+    assert lib.tsspgemm_embed_epoch(ctypes.byref(rect), 8, 4, p, p, 0.1, 2, 0, 4, None) == _lib.ERR_INVALID_ARG
+    # column tiles
+    nnz = ctypes.c_int64(0)
+    assert lib.tsspgemm_column_slice_count(ctypes.byref(a), 3, 2, p, ctypes.byref(nnz), None) == _lib.ERR_INVALID_ARG
+    assert lib.tsspgemm_column_slice_count(ctypes.byref(a), 0, 2, None, ctypes.byref(nnz), None) == _lib.ERR_INVALID_ARG
+    assert lib.tsspgemm_column_slice_fill(ctypes.byref(a), -1, 2, p, p, p, None) == _lib.ERR_INVALID_ARG
+    # merge
+    two = (_lib.CsrDesc * 2)(_desc(4, 8, 2), _desc(4, 9, 2))
+    assert lib.tsspgemm_merge_count(0, two, p, ctypes.byref(nnz), None) == _lib.ERR_INVALID_ARG
+    assert lib.tsspgemm_merge_count(65, two, p, ctypes.byref(nnz), None) == _lib.ERR_UNSUPPORTED
+    assert lib.tsspgemm_merge_count(2, two, p, ctypes.byref(nnz), None) == _lib.ERR_INVALID_ARG  # shapes differ
+    wide = (_lib.CsrDesc * 1)(_desc(4, 2048, 2))
+    assert lib.tsspgemm_merge_values(1, wide, p, p, p, None) == _lib.ERR_UNSUPPORTED
