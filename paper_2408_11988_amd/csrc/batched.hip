@@ -11,6 +11,7 @@
 // synchronisation and no allocation and can be captured in a HIP graph
 // (tsspgemm_batched_capture / tsspgemm_batched_launch).
 #include <algorithm>
+#include <array>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,10 @@ struct BInst {
   NumThresholds th;
   int32_t* cnt;    // nnz of each C row (workspace)
   int64_t rp_off;  // start of the instance's row pointers in the caller's array
+  int32_t gl;      // lanes per B row in the wavefront / workgroup kernel (64 for flat products)
+  int32_t lgl;     // lanes per row group in the light kernel
+  int32_t flat;    // flat product lists
+  int32_t pad;
 };
 
 struct BatchDev {
@@ -32,7 +37,9 @@ struct BatchDev {
   int32_t count;
   int32_t dmax;
   int32_t sym_split;
-  int32_t pad;
+  int32_t idb;  // bytes of the narrowed B column ids (1: dmax <= 256, else 2)
+  int32_t sel_gl, sel_flat;  // numeric launches: the class (group width, layout) this launch runs
+  int32_t lds_d, pad2;       // numeric launches: strip stride in LDS (largest d of the class)
   const int64_t* row_off;  // prefix sums over instances: rows
   const int64_t* bm_off;   // bitmap blocks (kBmRows rows)
   const int64_t* lw_off;   // light symbolic wavefronts (64 / wp rows each)
@@ -74,7 +81,8 @@ __global__ __launch_bounds__(256) void k_b_bitmap(BatchDev b) {
   extern __shared__ __align__(16) uint32_t sm[];
   const int t = find_inst(b.bm_off, b.count, blockIdx.x);
   const Problem& pr = b.insts[t].pr;
-  bitmap_block(pr.n, pr.brp, pr.bci, pr.wp, (uint32_t*)pr.bbits, (int64_t)(blockIdx.x - b.bm_off[t]) * kBmRows, sm);
+  bitmap_block(pr.n, pr.brp, pr.bci, pr.wp, (uint32_t*)pr.bbits, (int64_t)(blockIdx.x - b.bm_off[t]) * kBmRows, sm,
+               b.idb == 1 ? (uint8_t*)pr.bcol : nullptr, b.idb == 2 ? (uint16_t*)pr.bcol : nullptr);
 }
 
 // ---------------------------------------------------------------- symbolic
@@ -415,22 +423,24 @@ __global__ void k_b_num_bin_fill(BatchDev b) {
 // ---------------------------------------------------------------- numeric
 
 // Workgroup items, then wavefront rows, each walked with a grid stride.
-template <int GL, bool FLAT>
+template <int GL, bool FLAT, typename IdxT>
 __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
   using S = SemiringT<float>;
   extern __shared__ __align__(16) unsigned char smem[];
   double* strips = (double*)smem;
-  int4* stage = (int4*)(smem + (size_t)kWavesPerBlock * b.dmax * sizeof(double));
+  int4* stage = (int4*)(smem + (size_t)kWavesPerBlock * b.lds_d * sizeof(double));
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
   const int n_wg = b.ctr->num_split_items + b.ctr->num_block_items;
   const int n_heavy = n_wg + b.ctr->num_wave_rows;
   for (int g = blockIdx.x; g < n_wg; g += gridDim.x) {
+    const BInst& in = b.insts[b.num_inst[g]];
+    if (in.gl != b.sel_gl || in.flat != b.sel_flat) continue;  // another class's launch (whole workgroup)
     const Item it = b.num_items[g];
-    const Problem& pr = b.insts[b.num_inst[g]].pr;
+    const Problem& pr = in.pr;
     const int d = pr.d;
     for (int j = threadIdx.x; j < kWavesPerBlock * d; j += kBlock) strips[j] = 0.0;
     __syncthreads();
-    accumulate_range<GL, float, int32_t, FLAT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strips + wave * d, stage + wave * kWave);
+    accumulate_range<GL, float, IdxT, FLAT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strips + wave * d, stage + wave * kWave);
     __syncthreads();
     for (int j = threadIdx.x; j < d; j += kBlock)
       strips[j] = S::add(S::add(S::add(strips[j], strips[d + j]), strips[2 * d + j]), strips[3 * d + j]);
@@ -444,15 +454,15 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
     __syncthreads();
   }
   const int n_groups = (b.ctr->num_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
-  double* strip = strips + wave * b.dmax;
+  double* strip = strips + wave * b.lds_d;
   for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
     const int64_t x = (int64_t)n_wg + 4 * (int64_t)g + wave;
-    if (x < n_heavy) {
+    if (x < n_heavy && b.insts[b.num_inst[x]].gl == b.sel_gl && b.insts[b.num_inst[x]].flat == b.sel_flat) {
       const Item it = b.num_items[x];
       const Problem& pr = b.insts[b.num_inst[x]].pr;
       for (int j = lane; j < pr.d; j += kWave) strip[j] = 0.0;
       wave_sync();
-      accumulate_range<GL, float, int32_t, FLAT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
+      accumulate_range<GL, float, IdxT, FLAT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
       wave_sync();
       emit_row<float>(pr, it.row, strip, 0, 1);
       wave_sync();
@@ -460,21 +470,23 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
   }
 }
 
-template <int GL, bool FLAT>
+template <int GL, bool FLAT, typename IdxT>
 __global__ __launch_bounds__(kBlock) void k_b_numeric_light(BatchDev b) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int G = kBlock / GL;
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
-  double* strip = (double*)smem + grp * b.dmax;
-  int4* stage = (int4*)(smem + (size_t)G * b.dmax * sizeof(double)) + grp * GL;
+  double* strip = (double*)smem + grp * b.lds_d;
+  int4* stage = (int4*)(smem + (size_t)G * b.lds_d * sizeof(double)) + grp * GL;
   const int first = b.ctr->num_split_items + b.ctr->num_block_items + b.ctr->num_wave_rows;
   const int n_light = b.ctr->num_light_rows;
   for (int64_t x = (int64_t)blockIdx.x * G + grp; x < n_light; x += (int64_t)gridDim.x * G) {
+    const BInst& in = b.insts[b.num_inst[first + x]];
+    if (in.lgl != b.sel_gl || in.flat != b.sel_flat) continue;  // another class's launch (whole group)
     const Item it = b.num_items[first + x];
-    const Problem& pr = b.insts[b.num_inst[first + x]].pr;
+    const Problem& pr = in.pr;
     for (int j = gl; j < pr.d; j += GL) strip[j] = 0.0;
     wave_sync();
-    accumulate_light<GL, float, int32_t, FLAT>(pr, it.p0, it.p1, strip, stage, gl);
+    accumulate_light<GL, float, IdxT, FLAT>(pr, it.p0, it.p1, strip, stage, gl);
     wave_sync();
     emit_group<GL, float>(pr, it.row, strip, gl);
     wave_sync();
@@ -502,8 +514,9 @@ __global__ __launch_bounds__(kBlock) void k_b_split_finalize(BatchDev b) {
 // ---------------------------------------------------------------- host side
 
 struct Batch {
-  int32_t count = 0, dmax = 1, gl = 32, lgl = 32;
-  bool flat = false;  // flat product lists (tsspgemm_products) for the whole batch
+  int32_t count = 0, dmax = 1, idb = 1;
+  // numeric launch classes present in the batch: (group width, flat, largest d)
+  std::vector<std::array<int, 3>> heavy_cls, light_cls;
   std::vector<BInst> host_insts;
   DevBuf insts, offs, work, sym_items, sym_inst, num_items, num_inst, split_rows, partial, block_sums, inst_flops,
       ctr, tmp_rowptrs, tmp_off;
@@ -543,32 +556,47 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   if (bt->total_rows > 0) k_b_num_bin_fill<<<gbin, 256, 0, st>>>(b);
   TSS_CHECK_LAUNCH();
   if (!numeric) return TSSPGEMM_OK;
-  const size_t lds = (size_t)kWavesPerBlock * bt->dmax * 8 + kWavesPerBlock * kWave * sizeof(int4);
-  const size_t llds = (size_t)(kBlock / bt->lgl) * bt->dmax * 8 + kBlock * sizeof(int4);
-#define TSS_BN(GLV)                                                   \
-  case GLV:                                                           \
-    if (bt->flat)                                                     \
-      k_b_numeric<GLV, true><<<2048, kBlock, lds, st>>>(b);           \
-    else                                                              \
-      k_b_numeric<GLV, false><<<2048, kBlock, lds, st>>>(b);          \
+  // one launch per class of instances (group width, product layout), each
+  // taking only its own items from the shared binned list
+#define TSS_BN(GLV)                                                                                    \
+  case GLV:                                                                                            \
+    if (c[1])                                                                                          \
+      (bt->idb == 1 ? k_b_numeric<GLV, true, uint8_t> : k_b_numeric<GLV, true, uint16_t>)<<<2048, kBlock, lds, st>>>(bb); \
+    else                                                                                               \
+      (bt->idb == 1 ? k_b_numeric<GLV, false, uint8_t> : k_b_numeric<GLV, false, uint16_t>)<<<2048, kBlock, lds, st>>>(bb); \
     break;
-#define TSS_BL(GLV)                                                   \
-  case GLV:                                                           \
-    if (bt->flat)                                                     \
-      k_b_numeric_light<GLV, true><<<2048, kBlock, llds, st>>>(b);    \
-    else                                                              \
-      k_b_numeric_light<GLV, false><<<2048, kBlock, llds, st>>>(b);   \
+#define TSS_BL(GLV)                                                                                    \
+  case GLV:                                                                                            \
+    if (c[1])                                                                                          \
+      (bt->idb == 1 ? k_b_numeric_light<GLV, true, uint8_t> : k_b_numeric_light<GLV, true, uint16_t>)<<<2048, kBlock, lds, st>>>(bb); \
+    else                                                                                               \
+      (bt->idb == 1 ? k_b_numeric_light<GLV, false, uint8_t> : k_b_numeric_light<GLV, false, uint16_t>)<<<2048, kBlock, lds, st>>>(bb); \
     break;
-  switch (bt->flat ? 64 : bt->gl) {
-    TSS_BN(4) TSS_BN(8) TSS_BN(16) TSS_BN(32) TSS_BN(64)
-    default: set_error("batched: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  for (const auto& c : bt->heavy_cls) {
+    BatchDev bb = b;
+    bb.sel_gl = c[0];
+    bb.sel_flat = c[1];
+    bb.lds_d = c[2];
+    const size_t lds = (size_t)kWavesPerBlock * c[2] * 8 + kWavesPerBlock * kWave * sizeof(int4);
+    switch (c[0]) {
+      TSS_BN(4) TSS_BN(8) TSS_BN(16) TSS_BN(32) TSS_BN(64)
+      default: set_error("batched: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+    }
   }
-  switch (bt->lgl) {
-    TSS_BL(4) TSS_BL(8) TSS_BL(16) TSS_BL(32) TSS_BL(64)
-    default: set_error("batched: bad light group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  for (const auto& c : bt->light_cls) {
+    BatchDev bb = b;
+    bb.sel_gl = c[0];
+    bb.sel_flat = c[1];
+    bb.lds_d = c[2];
+    const size_t lds = (size_t)(kBlock / c[0]) * c[2] * 8 + kBlock * sizeof(int4);
+    switch (c[0]) {
+      TSS_BL(4) TSS_BL(8) TSS_BL(16) TSS_BL(32) TSS_BL(64)
+      default: set_error("batched: bad light group width"); return TSSPGEMM_ERR_INVALID_ARG;
+    }
   }
 #undef TSS_BN
 #undef TSS_BL
+  TSS_CHECK_LAUNCH();
   k_b_split_finalize<<<1024, kBlock, (size_t)bt->dmax * 8, st>>>(b);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
@@ -611,6 +639,7 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     sb_off[t + 1] = sb_off[t] + (n + kScanRows - 1) / kScanRows;
     ws_at[t] = ws_bytes;
     ws_bytes += ((2 * n * wp * 4 + n * 8 + n * 4) + 255) / 256 * 256;
+    ws_bytes += (B->nnz * 2 + 255) / 256 * 256;  // narrowed column ids (at most 2 bytes each)
     rp_total += n + 1;
     tsspgemm_tuning tn;
     resolve_tuning(tunes ? &tunes[t] : nullptr, B, &tn);
@@ -618,9 +647,13 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     num_cap += 2 * n + A->nnz / 64 + 2;
   }
   bt->dmax = dmax;
+  bt->idb = dmax <= 256 ? 1 : 2;
+  // Without tunings the batch runs one group width and product layout, from
+  // the mean B row length over all instances (one launch per phase; measured
+  // faster on mixed batches than each instance's own default). With tunings,
+  // each instance keeps its own.
+  int batch_gl = 0, batch_products = TSSPGEMM_PRODUCTS_AUTO;
   {
-    // one group width for the batch: tunes[0] if given, else from the mean
-    // B row length over all instances
     int64_t bn = 0, bnnz = 0;
     for (int t = 0; t < count; ++t) {
       bn += Bs[t].nrows;
@@ -629,10 +662,9 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     const tsspgemm_csr mean_b{bn, dmax, bnnz, nullptr, nullptr, nullptr};
     tsspgemm_tuning t0;
     resolve_tuning(tunes ? &tunes[0] : nullptr, &mean_b, &t0);
-    bt->gl = t0.group_lanes;
-    bt->lgl = light_group_lanes(bt->gl, dmax, TSSPGEMM_PLUS_TIMES_F32);
-    bt->flat = t0.products == TSSPGEMM_PRODUCTS_FLAT;
     bt->dev.sym_split = t0.sym_split_nnz;
+    batch_gl = t0.group_lanes;
+    batch_products = t0.products;
   }
   bt->total_rows = row_off[count];
   bt->total_bm = bm_off[count];
@@ -673,10 +705,30 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     in.pr.cbits = (uint32_t*)(base + n * wp * 4);
     in.pr.flops = (int64_t*)(base + 2 * n * wp * 4);
     in.cnt = (int32_t*)(base + 2 * n * wp * 4 + n * 8);
+    in.pr.bcol = base + ((2 * n * wp * 4 + n * 8 + n * 4) + 255) / 256 * 256;
     tsspgemm_tuning tn;
     resolve_tuning(tunes ? &tunes[t] : nullptr, B, &tn);
+    if (!tunes) {
+      tn.group_lanes = batch_gl;
+      tn.products = batch_products;
+    }
     in.th = NumThresholds{tn.light_max_flops, tn.wave_max_flops, tn.split_flops};
     in.rp_off = rp_off;
+    // the instance's group width and product layout (its own tuning's, or the
+    // batch's when no tunings are given)
+    in.flat = tn.products == TSSPGEMM_PRODUCTS_FLAT;
+    in.gl = in.flat ? 64 : tn.group_lanes;
+    in.lgl = light_group_lanes(tn.group_lanes, B->ncols, TSSPGEMM_PLUS_TIMES_F32);
+    auto add_cls = [&](std::vector<std::array<int, 3>>& v, int g) {
+      for (auto& c : v)
+        if (c[0] == g && c[1] == in.flat) {
+          c[2] = std::max<int>(c[2], (int)B->ncols);
+          return;
+        }
+      v.push_back({g, in.flat, std::max<int>(1, (int)B->ncols)});
+    };
+    add_cls(bt->heavy_cls, in.gl);
+    add_cls(bt->light_cls, in.lgl);
     rp_off += n + 1;
   }
   int64_t* offs = (int64_t*)bt->offs.p;
@@ -689,6 +741,7 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
   b.insts = (BInst*)bt->insts.p;
   b.count = count;
   b.dmax = dmax;
+  b.idb = bt->idb;
   b.row_off = offs;
   b.bm_off = offs + (count + 1);
   b.lw_off = offs + 2 * (count + 1);

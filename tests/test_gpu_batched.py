@@ -54,7 +54,7 @@ def test_batched_matches_plain_and_oracle(tuned):
     tunings = None
     if tuned:  # forces every work class somewhere in the batch
         tunings = [dict(group_lanes=16, light_max_flops=64, wave_max_flops=512, split_flops=2048) for _ in host]
-        tunings[0]["products"] = "flat"  # the batch's layout comes from the first tuning
+        tunings[0]["products"] = "flat"  # each tuned instance keeps its own layout: one flat, the rest per B row
     note(f"batched {len(pairs)} instances tuned={tuned}")
     bt = Batched(pairs, tunings)
     bt.run()
@@ -70,7 +70,8 @@ def test_batched_matches_plain_and_oracle(tuned):
 
 
 def bt_group_lanes(pairs):
-    """Group width the batch picks without a tuning: from the mean B row length."""
+    """Group width the batch picks without tunings: from the mean B row length
+    over all instances."""
     nn = sum(B.nrows for _, B in pairs)
     nz = sum(B.nnz for _, B in pairs)
     mean = nz / nn if nn else 0
