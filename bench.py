@@ -443,6 +443,53 @@ def bench_tiles() -> dict:
             "note": "T = 1 is the plain multiply; B rows of a tile hold 5 B per entry (narrowed id and value)"}
 
 
+def bench_er_small(cpu: bool) -> dict:
+    """The small ER case (4096 x 4096, 8 draws per row; B 4096 x 64 at 10%):
+    a whole plain step (symbolic with its nnz synchronisation, then numeric)
+    and the numeric phase alone, medians of 50. Launch-latency bound."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_11988_amd import DeviceCsr, numeric, symbolic
+
+    a, b = synth.workload_er_small()
+    A, B = DeviceCsr.from_host(a), DeviceCsr.from_host(b)
+    plan, _, nnz = symbolic(A, B)
+    ci = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+    cv = torch.empty(max(nnz, 1), dtype=torch.float32, device="cuda")
+    flops = int(plan.stats()["flops"])
+
+    def med(fn, reps=50):
+        for _ in range(5):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts))
+
+    def step():
+        symbolic(A, B, plan=plan)
+        numeric(plan, A, B, ci, cv)
+
+    ms_step = med(step)
+    ms_num = med(lambda: numeric(plan, A, B, ci, cv))
+    out = {"workload": "ER 4096 x 4096 (8 draws per row) x B 4096 x 64 Bernoulli(0.10), U(0,1), plus-times FP32",
+           "nnz_a": a.nnz, "nnz_b": b.nnz, "nnz_c": nnz, "flops": flops, "ms_step": round(ms_step, 4),
+           "ms_numeric": round(ms_num, 4), "gflops_step": round(2 * flops / ms_step / 1e6, 2)}
+    if cpu:
+        import oracle
+
+        t0 = time.perf_counter()
+        oracle.spgemm(a.rp, a.ci, a.val, b.rp, b.ci, b.val, threads=1)
+        out["cpu_oracle_ms_1_thread"] = round((time.perf_counter() - t0) * 1e3, 2)
+    return out
+
+
 def bench_bfs(cpu: bool) -> dict:
     """Multi-source BFS, R-MAT scale 22, 512 sources: masked Boolean TS-SpGEMM until
     every frontier is empty, levels n x 512 int32."""
@@ -501,7 +548,7 @@ def main():
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the plain workload")
-    ap.add_argument("--leg", choices=["fwd_bwd", "batched", "spmm", "embed", "tiles", "bfs"],
+    ap.add_argument("--leg", choices=["er_small", "fwd_bwd", "batched", "spmm", "embed", "tiles", "bfs"],
                     help="run only this extra workload and print its JSON (for profiling one workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB a few times (reference for the HBM byte counters) and exit")
@@ -522,7 +569,8 @@ def main():
 
     if args.leg:
         torch.cuda.set_device(0)
-        legs = {"fwd_bwd": lambda: bench_fwd_bwd(args.steps, args.warmup), "tiles": bench_tiles,
+        legs = {"er_small": lambda: bench_er_small(not args.no_cpu),
+                "fwd_bwd": lambda: bench_fwd_bwd(args.steps, args.warmup), "tiles": bench_tiles,
                 "batched": lambda: bench_batched(args.steps, args.warmup),
                 "spmm": bench_spmm_crossover, "embed": lambda: bench_embed(not args.no_cpu),
                 "bfs": lambda: bench_bfs(not args.no_cpu)}
@@ -635,6 +683,8 @@ def main():
     lib.tsspgemm_plan_destroy(plan)
     del c_colidx, c_vals, A, B
     if not args.no_extras:
+        result["er_small"] = bench_er_small(not args.no_cpu)
+        log(f"ER small step {result['er_small']['ms_step']} ms")
         result["fwd_bwd"] = bench_fwd_bwd(max(3, args.steps // 2), args.warmup)
         log(f"fwd+bwd {result['fwd_bwd']['ms_fwd']} + {result['fwd_bwd']['ms_bwd']} ms")
         torch.cuda.empty_cache()
