@@ -320,7 +320,10 @@ def tiled_spgemm(A: DeviceCsr, B: DeviceCsr, tiles: int, tuning: dict | None = N
     """C = A B computed tile by tile (Sec. III-B, Algorithm 2 on one GPU): for
     each of `tiles` column ranges of A, the product of that tile with B (it
     reads only B's rows in the range), then the merge of the partial outputs.
-    Each partial value is rounded to FP32 before the merge."""
+    Each partial value is rounded to FP32 before the merge. 1 <= tiles <= 64
+    (the merge takes at most 64 parts)."""
+    if not 1 <= tiles <= 64:
+        raise ValueError("tiled_spgemm: tiles must be in [1, 64]")
     e = tile_edges(A.ncols, tiles)
     parts = [spgemm(column_slice(A, e[t], e[t + 1], stream), B, tuning=tuning, stream=stream) for t in range(tiles)]
     return parts[0] if tiles == 1 else merge_rows(parts, stream)

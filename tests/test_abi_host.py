@@ -136,3 +136,11 @@ def test_argument_errors_of_the_extra_entry_points(lib):
     assert lib.tsspgemm_merge_count(2, two, p, ctypes.byref(nnz), None) == _lib.ERR_INVALID_ARG  # shapes differ
     wide = (_lib.CsrDesc * 1)(_desc(4, 2048, 2))
     assert lib.tsspgemm_merge_values(1, wide, p, p, p, None) == _lib.ERR_UNSUPPORTED
+
+
+def test_tiled_spgemm_rejects_tile_counts_outside_the_merge_limit():
+    import paper_2408_11988_amd as tss
+
+    for tiles in (0, 65):
+        with pytest.raises(ValueError):
+            tss.tiled_spgemm(None, None, tiles)
