@@ -422,7 +422,11 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   pr.cci = c_colidx;
   pr.cval = c_vals;
   if (p->nnz == 0) return TSSPGEMM_OK;
-  if (p->hash) return launch_hash_numeric(p->sr, pr, p->hmask, p->hstrips.p, &((Counters*)p->ctr.p)->hash_error, st);
+  if (p->hash) {
+    if ((rc = p->hnext.ensure(64))) return rc;
+    return launch_hash_numeric(p->sr, pr, p->hmask, p->hstrips.p, &((Counters*)p->ctr.p)->hash_error,
+                               (int32_t*)p->hnext.p, st);
+  }
   if (!vals) return launch_emit_pattern(pr, st);
   NumParams np{};
   np.pr = pr;

@@ -53,6 +53,7 @@ struct Plan {
   DevBuf hmask_rp, hmask_ci, hmask_bits;  // hash plan: copy of the complement mask
   HashMask hmask{};
   DevBuf hstrips;          // hash plan: private d-wide strips of the long-row kernel (kept zero)
+  DevBuf hnext;            // hash plan: row counter of the long-row workers
   DevBuf sp_chunks, sp_rows, sp_partial, sp_ctr;  // dense-B SpMM workspace (per-device cached plan)
   DevBuf em_ci, em_val;    // embedding update: second copy of Z (per-device cached plan)
   DevBuf em_cnt, em_split, em_slot_off, em_split_off, em_slot_row, em_split_list, em_partial, em_scan;

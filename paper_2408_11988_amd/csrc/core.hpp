@@ -139,6 +139,7 @@ struct HashMask {
 };
 int launch_hash_symbolic(const Problem& pr, const HashMask& m, int32_t* cnt, int32_t* err, hipStream_t st);
 int64_t hash_dense_workers(int64_t d);
-int launch_hash_numeric(int sr, const Problem& pr, const HashMask& m, void* strips, int32_t* err, hipStream_t st);
+int launch_hash_numeric(int sr, const Problem& pr, const HashMask& m, void* strips, int32_t* err, int32_t* next,
+                        hipStream_t st);  // next: a device counter (4 bytes) for the long-row workers
 
 }  // namespace tss

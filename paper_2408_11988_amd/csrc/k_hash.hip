@@ -33,6 +33,7 @@ constexpr int kSymSlots = 2048;           // LDS words per wavefront (8 KB): set
 constexpr int kNumSlots = 1024;           // numeric table slots per wavefront (power of two)
 constexpr int kHashNumMax = kNumSlots / 2;  // numeric rows up to this many outputs use the table
 constexpr int kHashWaves = 4;             // wavefronts (rows) per workgroup
+constexpr int kDenseFetch = 16;           // rows a dense-row worker takes per fetch
 static_assert(kHashMaxD <= kSymSlots * 32, "the d-bit bitmap of a row must fit a wavefront's LDS words");
 
 __device__ __forceinline__ uint32_t hslot(int32_t j, uint32_t mask) { return ((uint32_t)j * 2654435761u) & mask; }
@@ -285,7 +286,7 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_table(Probl
 template <typename V>
 __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_dense(Problem pr, HashMask hm,
                                                                            typename HashAcc<V>::type* strips,
-                                                                           int32_t* err) {
+                                                                           int32_t* err, int32_t* next) {
   using Acc = typename HashAcc<V>::type;
   __shared__ uint32_t bm_s[kHashWaves][kSymSlots];
   __shared__ int start_s[kHashWaves][kWave], pref_s[kHashWaves][kWave + 1];
@@ -298,10 +299,24 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_dense(Probl
   const V* __restrict__ bval = (const V*)pr.bval;
   for (int t = lane; t < words; t += kWave) bm[t] = 0u;
   wave_sync();
-  for (int64_t row = (int64_t)blockIdx.x * kHashWaves + wave; row < pr.n; row += (int64_t)gridDim.x * kHashWaves) {
-    const int c0 = pr.crp[row], nnz = pr.crp[row + 1] - c0;
+  // rows are taken kDenseFetch at a time from a shared counter (the workers
+  // are bounded by their private strips, so a static stride would leave the
+  // heavy rows of power-law inputs to a few of them)
+  int64_t row = 0, row_end = 0;
+  for (;;) {
+    if (row == row_end) {
+      int c = 0;
+      if (lane == 0) c = atomicAdd(next, 1);
+      c = __shfl(c, 0, kWave);
+      row = (int64_t)c * kDenseFetch;
+      if (row >= pr.n) break;
+      row_end = row + kDenseFetch < pr.n ? row + kDenseFetch : pr.n;
+    }
+    const int64_t r = row++;
+    const int c0 = pr.crp[r], nnz = pr.crp[r + 1] - c0;
     if (nnz <= kHashNumMax) continue;
-    const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
+    const int64_t row_id = r;
+    const int p0 = pr.arp[row_id], p1 = pr.arp[row_id + 1];
     for (int base = p0; base < p1; base += kWave) {
       const int nb = min(kWave, p1 - base);
       const int total = stage_products<V>(pr, base, nb, start_s[wave], pref_s[wave], aval_s[wave]);
@@ -309,7 +324,7 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_dense(Probl
         const int e = staged_entry(pref_s[wave], t);
         const int q = start_s[wave][e] + (t - pref_s[wave][e]);
         const int32_t j = pr.bci[q];
-        if (masked && is_masked(hm, row, j)) continue;
+        if (masked && is_masked(hm, row_id, j)) continue;
         atomicOr(&bm[j >> 5], 1u << (j & 31));
         if constexpr (!std::is_same<V, char>::value) {
           if constexpr (sizeof(Acc) == 8)
@@ -362,10 +377,11 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_dense(Probl
 
 // ---------------------------------------------------------------- launch
 
+// One wavefront per row (no grid stride), so the hardware's workgroup
+// dispatch balances rows of very different lengths.
 int launch_hash_symbolic(const Problem& pr, const HashMask& m, int32_t* cnt, int32_t* err, hipStream_t st) {
   if (pr.n == 0) return TSSPGEMM_OK;
-  int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;
-  if (g > 4096) g = 4096;
+  const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;
   k_hash_symbolic<<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, m, cnt, err);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
@@ -379,22 +395,23 @@ int64_t hash_dense_workers(int64_t d) {
   return w < kHashWaves ? kHashWaves : w;
 }
 
-int launch_hash_numeric(int sr, const Problem& pr, const HashMask& h, void* strips, int32_t* err,
+int launch_hash_numeric(int sr, const Problem& pr, const HashMask& h, void* strips, int32_t* err, int32_t* next,
                         hipStream_t st) {
   if (pr.n == 0) return TSSPGEMM_OK;
-  int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;
-  if (g > 4096) g = 4096;
+  const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;  // table rows: one wavefront per row
   int64_t gd = hash_dense_workers(pr.d) / kHashWaves;
   if (gd > g) gd = g;
+  int rc;
+  if ((rc = launch_zero_bytes(next, 4, st))) return rc;
   if (sr == TSSPGEMM_PLUS_TIMES_F32) {
     k_hash_numeric_table<float><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, err);
-    k_hash_numeric_dense<float><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, (double*)strips, err);
+    k_hash_numeric_dense<float><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, (double*)strips, err, next);
   } else if (sr == TSSPGEMM_PLUS_TIMES_I32) {
     k_hash_numeric_table<int32_t><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, err);
-    k_hash_numeric_dense<int32_t><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, (int32_t*)strips, err);
+    k_hash_numeric_dense<int32_t><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, (int32_t*)strips, err, next);
   } else {
     k_hash_numeric_table<char><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, err);
-    k_hash_numeric_dense<char><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, (int32_t*)strips, err);
+    k_hash_numeric_dense<char><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, (int32_t*)strips, err, next);
   }
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
