@@ -144,7 +144,9 @@ int tsspgemm_numeric(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_c
 
 /* Statistics of the last symbolic call on `plan` (HOST out pointers, any may
  * be NULL): total products (flops, Sec. II-A), nnz(C), and the number of
- * rows handled per lane group / per wavefront / per workgroup / split. */
+ * rows handled per lane group / per wavefront / per workgroup / split. For a
+ * hash-accumulator plan only split_rows is set: the rows whose products are
+ * cut into chunks of A entries taken by separate workgroups. */
 int tsspgemm_plan_stats(tsspgemm_plan plan, int64_t* flops, int64_t* c_nnz, int64_t* light_rows,
                         int64_t* wave_rows, int64_t* block_rows, int64_t* split_rows);
 

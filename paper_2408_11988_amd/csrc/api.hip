@@ -142,6 +142,21 @@ void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tu
 // Symbolic phase with the hash accumulator: per-row distinct-column counts
 // (k_hash.hip), then the same count scan as the bitmap path. The mask is
 // copied into the plan, since the numeric phase tests it again.
+static HashSplit hash_split_view(Plan* p) {
+  HashSplit hs{};
+  hs.slot_of_row = (int32_t*)p->hs_slot.p;
+  hs.rows = (int32_t*)p->hs_rows.p;
+  hs.items = (int2*)p->hs_items.p;
+  hs.bits = (uint32_t*)p->hs_bits.p;
+  hs.pref = (int32_t*)p->hs_pref.p;
+  hs.acc_off = (int32_t*)p->hs_off.p;
+  hs.acc = p->hs_acc.p;
+  hs.cap = (int32_t)p->hs_cap;
+  hs.split_flops = hash_split_flops(p->d < 1 ? 1 : p->d);
+  hs.ctr = (Counters*)p->ctr.p;
+  return hs;
+}
+
 static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, const tsspgemm_mask* M,
                              const tsspgemm_tuning& tn, int32_t* c_rowptr, int64_t* c_nnz, hipStream_t st) {
   int rc;
@@ -197,7 +212,15 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   pr.flops = (int64_t*)p->flops.p;
   pr.crp = c_rowptr;
   if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
-  if ((rc = launch_hash_symbolic(pr, p->hmask, (int32_t*)p->cnt.p, &ctr->hash_error, st))) return rc;
+  const int64_t words = (d + 31) / 32;
+  p->hs_cap = n > 0 ? hash_split_cap(n, d < 1 ? 1 : d) : 0;
+  const int64_t item_cap = hash_split_item_cap(A->nnz, p->hs_cap);
+  if ((rc = p->hs_slot.ensure((size_t)n * 4)) || (rc = p->hs_rows.ensure((size_t)p->hs_cap * 4)) ||
+      (rc = p->hs_items.ensure((size_t)item_cap * 8)) || (rc = p->hs_bits.ensure((size_t)p->hs_cap * words * 4)) ||
+      (rc = p->hs_pref.ensure((size_t)p->hs_cap * words * 4)) || (rc = p->hs_off.ensure((size_t)p->hs_cap * 4)))
+    return rc;
+  const HashSplit hs = hash_split_view(p);
+  if ((rc = launch_hash_symbolic(pr, p->hmask, hs, (int32_t*)p->cnt.p, &ctr->hash_error, st))) return rc;
   pr.cbits = nullptr;  // counts come from cnt
   if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
   TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -210,11 +233,19 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   p->nnz = h.nnz_total;
   p->flops_total = h.flops_total;
   p->n_split_items = p->n_block_items = p->n_wave_rows = p->n_light_rows = p->n_split_rows = 0;
+  p->hs_rows_n = h.hash_split_rows < p->hs_cap ? h.hash_split_rows : p->hs_cap;
+  p->hs_items_n = h.hash_split_items;
+  p->hs_acc_n = h.hash_split_acc;
+  p->n_split_rows = p->hs_rows_n;
+  p->n_split_items = p->hs_items_n;
   *c_nnz = h.nnz_total;
   if (h.nnz_total > INT32_MAX) {
     set_error("nnz(C) = " + std::to_string(h.nnz_total) + " exceeds INT32_MAX");
     return TSSPGEMM_ERR_OVERFLOW;
   }
+  if (sr != TSSPGEMM_OR_AND && p->hs_acc_n > 0 &&
+      (rc = p->hs_acc.ensure((size_t)p->hs_acc_n * (sr == TSSPGEMM_PLUS_TIMES_F32 ? 8 : 4))))
+    return rc;
   if (sr != TSSPGEMM_OR_AND && n > 0) {
     const size_t bytes = (size_t)hash_dense_workers(d) * d * (sr == TSSPGEMM_PLUS_TIMES_F32 ? 8 : 4);
     if ((rc = p->hstrips.ensure(bytes))) return rc;
@@ -424,8 +455,9 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   if (p->nnz == 0) return TSSPGEMM_OK;
   if (p->hash) {
     if ((rc = p->hnext.ensure(64))) return rc;
-    return launch_hash_numeric(p->sr, pr, p->hmask, p->hstrips.p, &((Counters*)p->ctr.p)->hash_error,
-                               (int32_t*)p->hnext.p, st);
+    return launch_hash_numeric(p->sr, pr, p->hmask, hash_split_view(p), (int32_t)p->hs_rows_n,
+                               (int32_t)p->hs_items_n, p->hs_acc_n, p->hstrips.p,
+                               &((Counters*)p->ctr.p)->hash_error, (int32_t*)p->hnext.p, st);
   }
   if (!vals) return launch_emit_pattern(pr, st);
   NumParams np{};

@@ -54,6 +54,10 @@ struct Plan {
   HashMask hmask{};
   DevBuf hstrips;          // hash plan: private d-wide strips of the long-row kernel (kept zero)
   DevBuf hnext;            // hash plan: row counter of the long-row workers
+  // hash plan, split rows: slot of each row, row of each slot, chunk list,
+  // bitmaps, per-word counts, accumulator offsets, accumulators
+  DevBuf hs_slot, hs_rows, hs_items, hs_bits, hs_pref, hs_off, hs_acc;
+  int64_t hs_cap = 0, hs_rows_n = 0, hs_items_n = 0, hs_acc_n = 0;
   DevBuf sp_chunks, sp_rows, sp_partial, sp_ctr;  // dense-B SpMM workspace (per-device cached plan)
   DevBuf em_ci, em_val;    // embedding update: second copy of Z (per-device cached plan)
   DevBuf em_cnt, em_split, em_slot_off, em_split_off, em_slot_row, em_split_list, em_partial, em_scan;

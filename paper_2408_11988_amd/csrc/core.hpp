@@ -40,7 +40,11 @@ struct Counters {
   int32_t num_light_rows;
   int32_t num_split_rows;
   int32_t malformed;
-  int32_t hash_error;  // hash accumulator: a table or count was inconsistent
+  int32_t hash_error;        // hash accumulator: a table or count was inconsistent
+  int32_t hash_split_rows;   // hash accumulator: rows that claimed a split slot (may exceed the capacity)
+  int32_t hash_split_items;  // hash accumulator: chunks of the split rows
+  int32_t hash_split_next;   // hash accumulator: next chunk for the symbolic chunk workers
+  int32_t hash_split_acc;    // hash accumulator: accumulator slots of the split rows
   int32_t pad0;
   int64_t flops_total;
   int64_t nnz_total;
@@ -137,9 +141,33 @@ struct HashMask {
   const uint32_t* bits;  // complement mask as bitmap rows of wpm words, or null
   int64_t wpm;
 };
-int launch_hash_symbolic(const Problem& pr, const HashMask& m, int32_t* cnt, int32_t* err, hipStream_t st);
+// Rows of a hash plan with many products are cut into chunks of A entries,
+// each taken by its own workgroup: the symbolic phase ORs each chunk's
+// columns into a global bitmap of the row, the numeric phase adds each
+// product at the column's rank in that bitmap (a compact accumulator of the
+// row's outputs).
+struct HashSplit {
+  int32_t* slot_of_row;  // n: the row's split slot, or -1
+  int32_t* rows;         // cap: row of each slot
+  int2* items;           // chunks: (slot, first A entry)
+  uint32_t* bits;        // cap x words: the row's output columns
+  int32_t* pref;         // cap x words: outputs of the row before each word
+  int32_t* acc_off;      // cap: first accumulator of the row
+  void* acc;             // accumulators (FP64, or INT32 for the integer semiring)
+  int32_t cap;           // split slots (0: no row is split)
+  int32_t split_flops;   // rows with more products are split rows
+  Counters* ctr;
+};
+int64_t hash_split_cap(int64_t n, int64_t d);
+int32_t hash_split_flops(int64_t d);
+int64_t hash_split_item_cap(int64_t a_nnz, int64_t cap);
+int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& hs, int32_t* cnt, int32_t* err,
+                         hipStream_t st);
 int64_t hash_dense_workers(int64_t d);
-int launch_hash_numeric(int sr, const Problem& pr, const HashMask& m, void* strips, int32_t* err, int32_t* next,
-                        hipStream_t st);  // next: a device counter (4 bytes) for the long-row workers
+// next: a device counter (4 bytes) for the long-row workers; split_rows,
+// split_items and split_acc: the split counts the symbolic phase ended with
+int launch_hash_numeric(int sr, const Problem& pr, const HashMask& m, const HashSplit& hs, int32_t split_rows,
+                        int32_t split_items, int64_t split_acc, void* strips, int32_t* err, int32_t* next,
+                        hipStream_t st);
 
 }  // namespace tss

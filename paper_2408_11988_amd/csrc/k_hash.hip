@@ -13,14 +13,29 @@
 // two >= 2 min(d, flops_i) slots, or, when that exceeds the table, in an LDS
 // bitmap of d bits.
 // Numeric: rows with at most kHashNumMax outputs accumulate in an LDS table of
-// (column, sum) slots sized from the exact output count; the table is sorted
-// by key in place (bitonic, in LDS; empty slots sort last) and its first
-// nnz_i slots are the row, in ascending columns. Longer rows
+// (column, sum) slots sized from the exact output count (one launch per table
+// size class, so short rows do not hold the LDS of long ones); the occupied
+// slots are compacted to the front and sorted by key (bitonic, in LDS), which
+// gives the row in ascending columns. Longer rows
 // mark an LDS bitmap and add into a private d-wide strip in global memory;
 // the row is written by walking the bitmap (ascending columns) and the strip
 // is cleared behind it.
 // Masked columns are tested per product (binary search in the mask row, or a
 // bit test), so tables only ever hold output columns.
+//
+// Rows with more than hash_split_flops(d) products are split rows (power-law
+// inputs have hubs whose product lists would keep one wavefront busy for the
+// whole launch): chunks of kSplitEntries A entries go to separate workgroups. The
+// symbolic chunks OR their columns into the row's global bitmap (an LDS copy
+// first, then one atomic OR per non-zero word); a count pass gives the row's
+// output count and, per bitmap word, the outputs before it. The numeric
+// chunks add each product at the column's rank in that bitmap, into an LDS
+// array of the row's outputs when they fit (then one global atomic add per
+// output) or straight into the row's global accumulators; an emit pass writes
+// the row in column order. A row of one chunk whose outputs fit in LDS is
+// written by its chunk directly. Split slots are bounded (hash_split_cap);
+// rows past the bound take the one-wavefront path.
+#include <cstdlib>
 #include <type_traits>
 
 #include "api_internal.hpp"
@@ -34,6 +49,10 @@ constexpr int kNumSlots = 1024;           // numeric table slots per wavefront (
 constexpr int kHashNumMax = kNumSlots / 2;  // numeric rows up to this many outputs use the table
 constexpr int kHashWaves = 4;             // wavefronts (rows) per workgroup
 constexpr int kDenseFetch = 16;           // rows a dense-row worker takes per fetch
+constexpr int kSplitWaves = 4;            // wavefronts per chunk workgroup
+constexpr int kSplitEntries = kSplitWaves * kWave;  // A entries per chunk (a wavefront stages 64)
+constexpr int kRankWords = 256;           // up to this many bitmap words (d <= 8192): narrow kernels
+constexpr int kSplitSymBlocks = 2048;     // symbolic chunk workers (chunks are taken from a counter)
 static_assert(kHashMaxD <= kSymSlots * 32, "the d-bit bitmap of a row must fit a wavefront's LDS words");
 
 __device__ __forceinline__ uint32_t hslot(int32_t j, uint32_t mask) { return ((uint32_t)j * 2654435761u) & mask; }
@@ -111,8 +130,8 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 
 // ---------------------------------------------------------------- symbolic
 
-__global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr, HashMask hm, int32_t* cnt,
-                                                                      int32_t* err) {
+__global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr, HashMask hm, HashSplit hs,
+                                                                      int32_t* cnt, int32_t* err) {
   __shared__ uint32_t sm[kHashWaves][kSymSlots];
   __shared__ int start_s[kHashWaves][kWave], pref_s[kHashWaves][kWave + 1];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
@@ -129,6 +148,28 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr
     }
     fl = wave_sum_ll(fl);
     if (lane == 0) pr.flops[row] = fl;
+    if (fl > hs.split_flops && hs.cap > 0) {
+      int slot = 0;
+      if (lane == 0) slot = atomicAdd(&hs.ctr->hash_split_rows, 1);
+      slot = __shfl(slot, 0, kWave);
+      if (slot < hs.cap) {
+        // chunks of this row: (slot, first A entry); the count pass writes cnt
+        const int nch = (p1 - p0 + kSplitEntries - 1) / kSplitEntries;
+        int first = 0;
+        if (lane == 0) {
+          first = atomicAdd(&hs.ctr->hash_split_items, nch);
+          hs.rows[slot] = (int32_t)row;
+          hs.slot_of_row[row] = slot;
+        }
+        first = __shfl(first, 0, kWave);
+        for (int c = lane; c < nch; c += kWave) hs.items[first + c] = make_int2(slot, p0 + c * kSplitEntries);
+        const int words = (pr.d + 31) >> 5;
+        uint32_t* gb = hs.bits + (int64_t)slot * words;
+        for (int t = lane; t < words; t += kWave) gb[t] = 0u;
+        continue;
+      }
+    }
+    if (lane == 0) hs.slot_of_row[row] = -1;
     if (fl == 0) {
       if (lane == 0) cnt[row] = 0;
       continue;
@@ -173,6 +214,103 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr
     const long long c = wave_sum_ll(fresh);
     if (lane == 0) cnt[row] = (int32_t)c;
     wave_sync();
+  }
+}
+
+// Split kernels come in three widths by bitmap words: up to 64 (d <= 2048,
+// every row's outputs fit an LDS array of 2048), up to kRankWords and up to
+// kSymSlots (LDS arrays of 4096 outputs). Smaller LDS use leaves room for
+// more workgroups per CU.
+__host__ __device__ constexpr int split_width(int words) {
+  return words <= 64 ? 64 : words <= kRankWords ? kRankWords : kSymSlots;
+}
+__host__ __device__ constexpr int split_lds_outputs(int width) { return width <= 64 ? 2048 : 4096; }
+
+// A split row of one chunk whose outputs fit the chunk's LDS array: the
+// chunk writes the row itself (value semirings).
+__device__ __forceinline__ bool split_direct(const Problem& pr, int row, int cnt) {
+  return pr.arp[row + 1] - pr.arp[row] <= kSplitEntries &&
+         cnt <= split_lds_outputs(split_width((pr.d + 31) >> 5));
+}
+
+// Symbolic chunks of split rows. The workers take chunks from a counter
+// until the chunk list (written by k_hash_symbolic) is used up.
+template <int WC>
+__global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_symbolic(Problem pr, HashMask hm, HashSplit hs) {
+  __shared__ uint32_t bm[WC];
+  __shared__ int start_s[kSplitWaves][kWave], pref_s[kSplitWaves][kWave + 1];
+  __shared__ int item_s;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int words = (pr.d + 31) >> 5;
+  const bool masked = hm.rp || hm.bits;
+  const int n_items = hs.ctr->hash_split_items;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = atomicAdd(&hs.ctr->hash_split_next, 1);
+    for (int t = threadIdx.x; t < words; t += blockDim.x) bm[t] = 0u;
+    __syncthreads();
+    const int it = item_s;
+    if (it >= n_items) break;
+    const int2 itm = hs.items[it];
+    const int row = hs.rows[itm.x];
+    const int a1 = min(itm.y + kSplitEntries, pr.arp[row + 1]);
+    const int base = itm.y + wave * kWave;
+    if (base < a1) {
+      const int nb = min(kWave, a1 - base);
+      const int total = stage_products<char>(pr, base, nb, start_s[wave], pref_s[wave], nullptr);
+      for (int t = lane; t < total; t += kWave) {
+        const int e = staged_entry(pref_s[wave], t);
+        const int32_t j = pr.bci[start_s[wave][e] + (t - pref_s[wave][e])];
+        if (masked && is_masked(hm, row, j)) continue;
+        atomicOr(&bm[j >> 5], 1u << (j & 31));
+      }
+    }
+    __syncthreads();
+    uint32_t* gb = hs.bits + (int64_t)itm.x * words;
+    for (int t = threadIdx.x; t < words; t += blockDim.x) {
+      const uint32_t w = bm[t];
+      if (w) atomicOr(&gb[t], w);
+    }
+    __syncthreads();
+  }
+}
+
+// Per split row: output count (cnt), outputs before each bitmap word (pref)
+// and the row's first accumulator (acc_off).
+__global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_count(Problem pr, HashSplit hs, int32_t* cnt) {
+  __shared__ int wsum[kSplitWaves];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int words = (pr.d + 31) >> 5;
+  const int nsplit = min(hs.ctr->hash_split_rows, hs.cap);
+  for (int slot = blockIdx.x; slot < nsplit; slot += gridDim.x) {
+    const uint32_t* gb = hs.bits + (int64_t)slot * words;
+    int32_t* gp = hs.pref + (int64_t)slot * words;
+    int run = 0;
+    for (int w0 = 0; w0 < words; w0 += kSplitWaves * kWave) {
+      const int w = w0 + threadIdx.x;
+      const int c = w < words ? __popc(gb[w]) : 0;
+      int incl = c;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+      }
+      if (lane == kWave - 1) wsum[wave] = incl;
+      __syncthreads();
+      int before = run, tot = 0;
+#pragma unroll
+      for (int v = 0; v < kSplitWaves; ++v) {
+        if (v < wave) before += wsum[v];
+        tot += wsum[v];
+      }
+      if (w < words) gp[w] = before + incl - c;
+      run += tot;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int row = hs.rows[slot];
+      cnt[row] = run;
+      hs.acc_off[slot] = split_direct(pr, row, run) ? 0 : atomicAdd(&hs.ctr->hash_split_acc, run);
+    }
   }
 }
 
@@ -222,22 +360,34 @@ __device__ __forceinline__ void wave_bitonic(uint32_t* key, Acc* val, int n2) {
   }
 }
 
-template <typename V>
-__global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_table(Problem pr, HashMask hm, int32_t* err) {
+// Rows with TSZ/4 < nnz_i <= TSZ/2 outputs (the smallest class from one
+// output): a table of at most TSZ slots per wavefront.
+// RANK (d <= 32 x kRankWords): the row is put in column order by each
+// column's rank in an LDS bitmap of the row (no sort).
+template <typename V, int TSZ, bool RANK>
+__global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_table(Problem pr, HashMask hm,
+                                                                           const int32_t* slot_of_row,
+                                                                           int32_t* err) {
   using Acc = typename HashAcc<V>::type;
-  __shared__ uint32_t keys_s[kHashWaves][kNumSlots];
-  __shared__ Acc vals_s[kHashWaves][kNumSlots];
+  static_assert(TSZ >= 2 * kWave && TSZ <= kNumSlots, "table class");
+  constexpr int RW = RANK ? kRankWords : 1;
+  __shared__ uint32_t keys_s[kHashWaves][TSZ];
+  __shared__ Acc vals_s[kHashWaves][TSZ];
   __shared__ int start_s[kHashWaves][kWave], pref_s[kHashWaves][kWave + 1];
   __shared__ V aval_s[kHashWaves][kWave];
+  __shared__ uint32_t rbm_s[kHashWaves][RW];
+  __shared__ uint16_t rpw_s[kHashWaves][RW];
+  constexpr int lo = TSZ == 2 * kWave ? 0 : TSZ / 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
   uint32_t* keys = keys_s[wave];
   Acc* vals = vals_s[wave];
   const bool masked = hm.rp || hm.bits;
   const V* __restrict__ bval = (const V*)pr.bval;
+  const uint64_t below = lane == 0 ? 0ull : ~0ull >> (kWave - lane);
   for (int64_t row = (int64_t)blockIdx.x * kHashWaves + wave; row < pr.n; row += (int64_t)gridDim.x * kHashWaves) {
     const int c0 = pr.crp[row], nnz = pr.crp[row + 1] - c0;
-    if (nnz == 0 || nnz > kHashNumMax) continue;
-    const uint32_t tsz = pow2_at_least(2u * (uint32_t)nnz);  // <= kNumSlots
+    if (nnz <= lo || nnz > TSZ / 2 || slot_of_row[row] >= 0) continue;
+    const uint32_t tsz = pow2_at_least(2u * (uint32_t)nnz);  // <= TSZ
     for (uint32_t t = lane; t < tsz; t += kWave) {
       keys[t] = kEmpty;
       vals[t] = Acc(0);
@@ -269,14 +419,81 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_table(Probl
       }
       wave_sync();
     }
-    // sort the whole table by key: empty slots (all ones) go last, the row's
-    // nnz columns come first in ascending order
-    wave_bitonic<Acc>(keys, vals, (int)tsz);
+    if constexpr (RANK) {
+      // bitmap of the row's columns, outputs before each word, then every
+      // occupied slot goes to position (outputs before its word) + (set bits
+      // below it in the word)
+      uint32_t* bm = rbm_s[wave];
+      uint16_t* pw = rpw_s[wave];
+      const int words = (pr.d + 31) >> 5;
+      for (int w = lane; w < words; w += kWave) bm[w] = 0u;
+      wave_sync();
+      for (uint32_t t = lane; t < tsz; t += kWave) {
+        const uint32_t k = keys[t];
+        if (k != kEmpty) atomicOr(&bm[k >> 5], 1u << (k & 31));
+      }
+      wave_sync();
+      constexpr int WPL = kRankWords / kWave;  // words per lane
+      int cw[WPL], sum = 0;
+#pragma unroll
+      for (int u = 0; u < WPL; ++u) {
+        const int w = lane * WPL + u;
+        cw[u] = w < words ? __popc(bm[w]) : 0;
+        sum += cw[u];
+      }
+      int incl = sum;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+      }
+      int run = incl - sum;
+#pragma unroll
+      for (int u = 0; u < WPL; ++u) {
+        const int w = lane * WPL + u;
+        if (w < words) pw[w] = (uint16_t)run;
+        run += cw[u];
+      }
+      if (lane == kWave - 1 && incl != nnz) atomicOr(err, 1);
+      wave_sync();
+      for (uint32_t t = lane; t < tsz; t += kWave) {
+        const uint32_t k = keys[t];
+        if (k == kEmpty) continue;
+        const int pos = pw[k >> 5] + __popc(bm[k >> 5] & ((1u << (k & 31)) - 1u));
+        if (pos < nnz) {
+          pr.cci[c0 + pos] = (int32_t)k;
+          if constexpr (!std::is_same<V, char>::value) ((V*)pr.cval)[c0 + pos] = SemiringT<V>::out(vals[t]);
+        }
+      }
+      wave_sync();
+      continue;
+    }
+    // compact the occupied slots to the front (in slot order; every slot is
+    // read before any of its block is written), then sort nnz_i of them
+    int used = 0;
+    for (uint32_t c = 0; c < tsz; c += kWave) {
+      const uint32_t key = keys[c + lane];
+      const Acc v = vals[c + lane];
+      const bool occ = key != kEmpty;
+      const uint64_t bal = __ballot(occ);
+      const int pos = used + __popcll(bal & below);
+      wave_sync();
+      if (occ) {
+        keys[pos] = key;
+        vals[pos] = v;
+      }
+      used += __popcll(bal);
+      wave_sync();
+    }
+    if (used != nnz && lane == 0) atomicOr(err, 1);
+    const uint32_t p2 = pow2_at_least((uint32_t)nnz);
+    for (uint32_t t = (uint32_t)used + lane; t < p2; t += kWave) keys[t] = kEmpty;
+    wave_sync();
+    wave_bitonic<Acc>(keys, vals, (int)p2);
     for (int t = lane; t < nnz; t += kWave) {
       pr.cci[c0 + t] = (int32_t)keys[t];
       if constexpr (!std::is_same<V, char>::value) ((V*)pr.cval)[c0 + t] = SemiringT<V>::out(vals[t]);
     }
-    if (lane == 0 && (keys[nnz - 1] == kEmpty || ((uint32_t)nnz < tsz && keys[nnz] != kEmpty))) atomicOr(err, 1);
     wave_sync();
   }
 }
@@ -285,6 +502,7 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_table(Probl
 // d-wide strip in global memory (kept all-zero between rows).
 template <typename V>
 __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_dense(Problem pr, HashMask hm,
+                                                                           const int32_t* slot_of_row,
                                                                            typename HashAcc<V>::type* strips,
                                                                            int32_t* err, int32_t* next) {
   using Acc = typename HashAcc<V>::type;
@@ -314,7 +532,7 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_dense(Probl
     }
     const int64_t r = row++;
     const int c0 = pr.crp[r], nnz = pr.crp[r + 1] - c0;
-    if (nnz <= kHashNumMax) continue;
+    if (nnz <= kHashNumMax || slot_of_row[r] >= 0) continue;
     const int64_t row_id = r;
     const int p0 = pr.arp[row_id], p1 = pr.arp[row_id + 1];
     for (int base = p0; base < p1; base += kWave) {
@@ -375,15 +593,164 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_dense(Probl
   }
 }
 
+template <typename A>
+__device__ __forceinline__ void global_add(A* p, A v) {
+  if constexpr (sizeof(A) == 8)
+    atomicAdd(p, v);
+  else
+    atomicAdd((unsigned int*)p, (unsigned int)v);
+}
+
+// Numeric chunk of a split row (one workgroup per chunk). The accumulators
+// are zero when it starts; the chunks of a row add in any order.
+template <typename V, int WC>
+__global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_numeric(Problem pr, HashMask hm, HashSplit hs,
+                                                                            int32_t* err) {
+  using Acc = typename HashAcc<V>::type;
+  constexpr int LC = split_lds_outputs(WC);
+  __shared__ uint32_t bm[WC];
+  __shared__ int32_t bp[WC];
+  __shared__ Acc acc[LC];
+  __shared__ int start_s[kSplitWaves][kWave], pref_s[kSplitWaves][kWave + 1];
+  __shared__ V aval_s[kSplitWaves][kWave];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int words = (pr.d + 31) >> 5;
+  const int2 itm = hs.items[blockIdx.x];
+  const int row = hs.rows[itm.x];
+  const int cnt = pr.crp[row + 1] - pr.crp[row];
+  const bool in_lds = cnt <= LC;
+  const uint32_t* gb = hs.bits + (int64_t)itm.x * words;
+  const int32_t* gp = hs.pref + (int64_t)itm.x * words;
+  Acc* gacc = (Acc*)hs.acc + hs.acc_off[itm.x];
+  for (int t = threadIdx.x; t < words; t += blockDim.x) {
+    bm[t] = gb[t];
+    bp[t] = gp[t];
+  }
+  if (in_lds)
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) acc[t] = Acc(0);
+  __syncthreads();
+  const bool masked = hm.rp || hm.bits;
+  const V* __restrict__ bval = (const V*)pr.bval;
+  const int a1 = min(itm.y + kSplitEntries, pr.arp[row + 1]);
+  const int base = itm.y + wave * kWave;
+  if (base < a1) {
+    const int nb = min(kWave, a1 - base);
+    const int total = stage_products<V>(pr, base, nb, start_s[wave], pref_s[wave], aval_s[wave]);
+    for (int t = lane; t < total; t += kWave) {
+      const int e = staged_entry(pref_s[wave], t);
+      const int q = start_s[wave][e] + (t - pref_s[wave][e]);
+      const int32_t j = pr.bci[q];
+      if (masked && is_masked(hm, row, j)) continue;
+      const uint32_t word = bm[j >> 5], bit = 1u << (j & 31);
+      if (!(word & bit)) {  // a column the symbolic phase did not see: inputs changed
+        atomicOr(err, 1);
+        continue;
+      }
+      const int pos = bp[j >> 5] + __popc(word & (bit - 1u));
+      const Acc v = hash_prod<V>(aval_s[wave][e], bval[q]);
+      if (in_lds)
+        lds_add(&acc[pos], v);
+      else
+        global_add(&gacc[pos], v);
+    }
+  }
+  if (!in_lds) return;
+  __syncthreads();
+  if (split_direct(pr, row, cnt)) {  // the whole row: write it in column order
+    const int c0 = pr.crp[row];
+    for (int w = threadIdx.x; w < words; w += blockDim.x) {
+      uint32_t word = bm[w];
+      int pos = bp[w];
+      while (word) {
+        const int b = __ffs(word) - 1;
+        word &= word - 1;
+        pr.cci[c0 + pos] = (w << 5) + b;
+        ((V*)pr.cval)[c0 + pos] = SemiringT<V>::out(acc[pos]);
+        ++pos;
+      }
+    }
+    return;
+  }
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+    const Acc v = acc[t];
+    if (v != Acc(0)) global_add(&gacc[t], v);
+  }
+}
+
+// Writes a split row (one workgroup per row): columns in bitmap order and,
+// for value semirings, the row's accumulators.
+template <typename V>
+__global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_emit(Problem pr, HashSplit hs) {
+  using Acc = typename HashAcc<V>::type;
+  const int slot = blockIdx.x;
+  const int words = (pr.d + 31) >> 5;
+  const int row = hs.rows[slot];
+  const int c0 = pr.crp[row];
+  if constexpr (!std::is_same<V, char>::value)
+    if (split_direct(pr, row, pr.crp[row + 1] - c0)) return;  // written by its chunk
+  const uint32_t* gb = hs.bits + (int64_t)slot * words;
+  const int32_t* gp = hs.pref + (int64_t)slot * words;
+  const Acc* gacc = (const Acc*)hs.acc + hs.acc_off[slot];
+  for (int w = threadIdx.x; w < words; w += blockDim.x) {
+    uint32_t word = gb[w];
+    int pos = gp[w];
+    while (word) {
+      const int b = __ffs(word) - 1;
+      word &= word - 1;
+      pr.cci[c0 + pos] = (w << 5) + b;
+      if constexpr (!std::is_same<V, char>::value) ((V*)pr.cval)[c0 + pos] = SemiringT<V>::out(gacc[pos]);
+      ++pos;
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launch
+
+int64_t hash_split_cap(int64_t n, int64_t d) {
+  // bitmap and per-word counts of a slot: 8 bytes per word, at most 256 MB
+  // in all; the accumulators of all slots (at most cap x d) index in int32
+  const int64_t words = (d + 31) / 32;
+  int64_t cap = (int64_t)(256ll << 20) / (words * 8);
+  if (cap > (1ll << 30) / d) cap = (1ll << 30) / d;
+  if (cap > n) cap = n;
+  if (const char* e = std::getenv("TSSPGEMM_HASH_SPLIT_CAP")) {  // tests: force rows past the bound
+    const long long v = std::atoll(e);
+    if (v >= 0 && v < cap) cap = v;
+  }
+  return cap;
+}
+
+int32_t hash_split_flops(int64_t d) {
+  // up to 256 bitmap words a split slot is cheap: every row that may have
+  // more outputs than the LDS table holds is split; above, only long rows
+  return (d + 31) / 32 <= 256 ? kHashNumMax : 4 * kHashNumMax;
+}
+
+int64_t hash_split_item_cap(int64_t a_nnz, int64_t cap) {
+  // a row of deg A entries makes ceil(deg / kSplitEntries) <= deg / kSplitEntries + 1 chunks
+  return a_nnz / kSplitEntries + cap + 1;
+}
 
 // One wavefront per row (no grid stride), so the hardware's workgroup
 // dispatch balances rows of very different lengths.
-int launch_hash_symbolic(const Problem& pr, const HashMask& m, int32_t* cnt, int32_t* err, hipStream_t st) {
+int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& hs, int32_t* cnt, int32_t* err,
+                         hipStream_t st) {
   if (pr.n == 0) return TSSPGEMM_OK;
   const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;
-  k_hash_symbolic<<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, m, cnt, err);
+  k_hash_symbolic<<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, m, hs, cnt, err);
   TSS_CHECK_LAUNCH();
+  if (hs.cap > 0) {
+    const int wc = split_width((pr.d + 31) >> 5);
+    if (wc == 64)
+      k_hash_split_symbolic<64><<<kSplitSymBlocks, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
+    else if (wc == kRankWords)
+      k_hash_split_symbolic<kRankWords><<<kSplitSymBlocks, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
+    else
+      k_hash_split_symbolic<kSymSlots><<<kSplitSymBlocks, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
+    const int64_t gc = hs.cap < kSplitSymBlocks ? hs.cap : kSplitSymBlocks;
+    k_hash_split_count<<<(unsigned)gc, kSplitWaves * kWave, 0, st>>>(pr, hs, cnt);
+    TSS_CHECK_LAUNCH();
+  }
   return TSSPGEMM_OK;
 }
 
@@ -395,7 +762,42 @@ int64_t hash_dense_workers(int64_t d) {
   return w < kHashWaves ? kHashWaves : w;
 }
 
-int launch_hash_numeric(int sr, const Problem& pr, const HashMask& h, void* strips, int32_t* err, int32_t* next,
+template <typename V, bool RANK>
+static void table_classes(const Problem& pr, const HashMask& h, const HashSplit& hs, int64_t g, int32_t* err,
+                          hipStream_t st) {
+  k_hash_numeric_table<V, 128, RANK><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, err);
+  k_hash_numeric_table<V, 256, RANK><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, err);
+  k_hash_numeric_table<V, 512, RANK><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, err);
+  k_hash_numeric_table<V, kNumSlots, RANK><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, err);
+}
+
+template <typename V, typename Acc>
+static void hash_numeric_kernels(const Problem& pr, const HashMask& h, const HashSplit& hs, int32_t split_rows,
+                                 int32_t split_items, int64_t g, int64_t gd, void* strips, int32_t* err,
+                                 int32_t* next, hipStream_t st) {
+  const bool narrow = ((pr.d + 31) >> 5) <= kRankWords;
+  if (narrow) {
+    table_classes<V, true>(pr, h, hs, g, err, st);
+  } else {
+    table_classes<V, false>(pr, h, hs, g, err, st);
+  }
+  k_hash_numeric_dense<V><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, (Acc*)strips, err,
+                                                                        next);
+  if constexpr (!std::is_same<V, char>::value) {  // pattern-only rows need no accumulation
+    const int wc = split_width((pr.d + 31) >> 5);
+    const unsigned gi = (unsigned)split_items;
+    if (split_items > 0 && wc == 64)
+      k_hash_split_numeric<V, 64><<<gi, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+    else if (split_items > 0 && wc == kRankWords)
+      k_hash_split_numeric<V, kRankWords><<<gi, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+    else if (split_items > 0)
+      k_hash_split_numeric<V, kSymSlots><<<gi, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+  }
+  if (split_rows > 0) k_hash_split_emit<V><<<(unsigned)split_rows, kSplitWaves * kWave, 0, st>>>(pr, hs);
+}
+
+int launch_hash_numeric(int sr, const Problem& pr, const HashMask& h, const HashSplit& hs, int32_t split_rows,
+                        int32_t split_items, int64_t split_acc, void* strips, int32_t* err, int32_t* next,
                         hipStream_t st) {
   if (pr.n == 0) return TSSPGEMM_OK;
   const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;  // table rows: one wavefront per row
@@ -403,16 +805,15 @@ int launch_hash_numeric(int sr, const Problem& pr, const HashMask& h, void* stri
   if (gd > g) gd = g;
   int rc;
   if ((rc = launch_zero_bytes(next, 4, st))) return rc;
-  if (sr == TSSPGEMM_PLUS_TIMES_F32) {
-    k_hash_numeric_table<float><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, err);
-    k_hash_numeric_dense<float><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, (double*)strips, err, next);
-  } else if (sr == TSSPGEMM_PLUS_TIMES_I32) {
-    k_hash_numeric_table<int32_t><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, err);
-    k_hash_numeric_dense<int32_t><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, (int32_t*)strips, err, next);
-  } else {
-    k_hash_numeric_table<char><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, err);
-    k_hash_numeric_dense<char><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, (int32_t*)strips, err, next);
-  }
+  const size_t acc_bytes = sr == TSSPGEMM_PLUS_TIMES_F32 ? 8 : 4;
+  if (sr != TSSPGEMM_OR_AND && split_acc > 0 && (rc = launch_zero_bytes(hs.acc, (size_t)split_acc * acc_bytes, st)))
+    return rc;
+  if (sr == TSSPGEMM_PLUS_TIMES_F32)
+    hash_numeric_kernels<float, double>(pr, h, hs, split_rows, split_items, g, gd, strips, err, next, st);
+  else if (sr == TSSPGEMM_PLUS_TIMES_I32)
+    hash_numeric_kernels<int32_t, int32_t>(pr, h, hs, split_rows, split_items, g, gd, strips, err, next, st);
+  else
+    hash_numeric_kernels<char, int32_t>(pr, h, hs, split_rows, split_items, g, gd, strips, err, next, st);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }

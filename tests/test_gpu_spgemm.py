@@ -60,8 +60,9 @@ def test_plus_times_random(d, acc, classes):
 @pytest.mark.parametrize("d", WIDE_D)
 def test_plus_times_wide(d):
     """d > 1024 (hash accumulator chosen automatically): a few dense A rows
-    make rows with hundreds to thousands of outputs (long-row kernel, d-bit
-    bitmap in the symbolic pass), the rest stay in the LDS tables."""
+    make rows with hundreds to thousands of outputs (split rows, or the
+    long-row kernel; the d-bit bitmap in the symbolic pass), the rest stay in
+    the LDS tables."""
     rng = np.random.default_rng(1500 + d)
     n = 400
     a = random_csr(rng, n, n, 0.02, empty_rows=0.2, dense_rows=3)
@@ -339,3 +340,56 @@ def test_error_paths_on_device():
         compare_f32(a, b, tss.spgemm(to_dev(a), to_dev(b)))
     finally:
         del os.environ["TSSPGEMM_VALIDATE"]
+
+
+@pytest.mark.parametrize("d", [2048, 9000])
+def test_hash_split_rows(d, monkeypatch):
+    """Hash accumulator on a power-law A: hub rows are split into chunks of A
+    entries (several chunks each). At d = 2048 they sum in LDS first, at
+    d = 9000 the widest go straight to global accumulators. The split-slot
+    bound is then forced down (rows past it take the one-wavefront path) and
+    to zero; the structure must not change and the values stay within the
+    tolerance. Also the integer semiring (exact) and OR-AND with a mask."""
+    tss = _tss()
+    g = synth.rmat(11, 16, 6100 + d)
+    a = g.with_values(synth.values(g, "uniform", 6101, synth.S_AVAL))
+    b = synth.b_poisson(a.nrows, d, 40.0, 6102 + d)
+    b = b.with_values(synth.values(b, "uniform", 6103, synth.S_BVAL))
+    flops = oracle.row_flops(a.rp, a.ci, b.rp)
+    thr = 512 if (d + 31) // 32 <= 256 else 2048  # split rows: more products than this
+    assert np.max(np.diff(a.rp)) > 512 and np.sum(flops > 2048) > 8  # split rows of several chunks
+    ref = None
+    for cap in (None, "3", "0"):
+        if cap is None:
+            monkeypatch.delenv("TSSPGEMM_HASH_SPLIT_CAP", raising=False)
+        else:
+            monkeypatch.setenv("TSSPGEMM_HASH_SPLIT_CAP", cap)
+        note(f"hash split rows n={a.nrows} nnzA={a.nnz} d={d} split cap={cap}")
+        C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True)
+        torch.cuda.synchronize()
+        split = plan.stats()["split_rows"]
+        want = {None: int(np.sum(flops > thr)), "3": 3, "0": 0}[cap]
+        assert split == want, (split, want)
+        frac = compare_f32(a, b, C, threads=8)
+        assert frac > 0.999
+        g_rp, g_ci, _ = C.to_host()
+        if ref is None:
+            ref = (g_rp, g_ci)
+        assert np.array_equal(g_rp, ref[0]) and np.array_equal(g_ci, ref[1])
+        if cap is None:
+            cnt = np.diff(g_rp.astype(np.int64))
+            assert cnt[flops > 2048].max() > (4096 if d > 4096 else 512)
+    monkeypatch.delenv("TSSPGEMM_HASH_SPLIT_CAP", raising=False)
+    ai = synth.Csr(a.nrows, a.ncols, a.rp, a.ci, (np.arange(a.nnz) % 7 - 3).astype(np.int32))
+    bi = synth.Csr(b.nrows, b.ncols, b.rp, b.ci, (np.arange(b.nnz) % 5 - 2).astype(np.int32))
+    note(f"hash split rows int32 d={d}")
+    C = tss.spgemm(to_dev(ai, dtype=torch.int32), to_dev(bi, dtype=torch.int32), semiring="plus_times_i32")
+    torch.cuda.synchronize()
+    compare_int(ai, bi, C)
+    rng = np.random.default_rng(6104 + d)
+    m = random_csr(rng, a.nrows, d, 0.2)
+    note(f"hash split rows or_and with a csr mask d={d}")
+    C = tss.spgemm(to_dev(a, with_values=False), to_dev(b, with_values=False), semiring="or_and",
+                   mask=to_dev(m, with_values=False))
+    torch.cuda.synchronize()
+    compare_bool(a, b, C, mask=m)
