@@ -443,6 +443,49 @@ def bench_tiles() -> dict:
             "note": "T = 1 is the plain multiply; B rows of a tile hold 5 B per entry (narrowed id and value)"}
 
 
+def bench_wide_d() -> dict:
+    """Varying d with the product count fixed (Sec. V's d sweep shape): R-MAT
+    scale 18 x B n x d with Poisson(25.6) entries per row, plus-times FP32.
+    d <= 1024 uses the LDS strip, larger d the hash accumulator (Sec. III-C).
+    Medians of 7 symbolic and 7 numeric calls on one plan."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_11988_amd import DeviceCsr, numeric, symbolic
+
+    def med(fn, reps=7):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e = _events(2)
+            e[0].record()
+            fn()
+            e[1].record()
+            e[1].synchronize()
+            ts.append(e[0].elapsed_time(e[1]))
+        return float(np.median(ts))
+
+    rows = []
+    for d in (128, 512, 1024, 2048, 4096, 16384, 65536):
+        a, b = synth.workload_wide_d(d)
+        A, B = DeviceCsr.from_host(a), DeviceCsr.from_host(b)
+        plan, _, nnz = symbolic(A, B)
+        st = plan.stats()
+        ci = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+        cv = torch.empty(max(nnz, 1), dtype=torch.float32, device="cuda")
+        ms_sym = med(lambda: symbolic(A, B, plan=plan))
+        ms_num = med(lambda: numeric(plan, A, B, ci, cv))
+        rows.append({"d": d, "accumulator": "lds" if d <= 1024 else "hash", "nnz_c": int(nnz),
+                     "flops": int(st["flops"]), "split_rows": int(st["split_rows"]) if d > 1024 else None,
+                     "ms_symbolic": round(ms_sym, 4), "ms_numeric": round(ms_num, 4),
+                     "gflops_step": round(2 * st["flops"] / (ms_sym + ms_num) / 1e6, 1)})
+        del plan, ci, cv, A, B
+        torch.cuda.empty_cache()
+    return {"workload": "R-MAT scale 18 (edge factor 16) x B n x d Poisson(25.6)/row, U(0,1), plus-times FP32",
+            "points": rows}
+
+
 def bench_er_small(cpu: bool) -> dict:
     """The small ER case (4096 x 4096, 8 draws per row; B 4096 x 64 at 10%):
     a whole plain step (symbolic with its nnz synchronisation, then numeric)
@@ -548,7 +591,7 @@ def main():
     ap.add_argument("--d", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the plain workload")
-    ap.add_argument("--leg", choices=["er_small", "fwd_bwd", "batched", "spmm", "embed", "tiles", "bfs"],
+    ap.add_argument("--leg", choices=["er_small", "fwd_bwd", "batched", "spmm", "embed", "tiles", "bfs", "wide_d"],
                     help="run only this extra workload and print its JSON (for profiling one workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB a few times (reference for the HBM byte counters) and exit")
@@ -573,7 +616,7 @@ def main():
                 "fwd_bwd": lambda: bench_fwd_bwd(args.steps, args.warmup), "tiles": bench_tiles,
                 "batched": lambda: bench_batched(args.steps, args.warmup),
                 "spmm": bench_spmm_crossover, "embed": lambda: bench_embed(not args.no_cpu),
-                "bfs": lambda: bench_bfs(not args.no_cpu)}
+                "bfs": lambda: bench_bfs(not args.no_cpu), "wide_d": bench_wide_d}
         print(json.dumps({args.leg: legs[args.leg]()}), flush=True)
         return
 
@@ -705,6 +748,9 @@ def main():
         torch.cuda.empty_cache()
         result["bfs"] = bench_bfs(not args.no_cpu)
         log(f"bfs {result['bfs']['ms_total']} ms, {result['bfs']['iterations']} iterations")
+        torch.cuda.empty_cache()
+        result["wide_d"] = bench_wide_d()
+        log("varying d: " + ", ".join(f"d={r['d']} {r['gflops_step']} GFLOPS" for r in result["wide_d"]["points"]))
     print(json.dumps(result), flush=True)
 
 

@@ -151,8 +151,9 @@ static HashSplit hash_split_view(Plan* p) {
   hs.pref = (int32_t*)p->hs_pref.p;
   hs.acc_off = (int32_t*)p->hs_off.p;
   hs.acc = p->hs_acc.p;
+  hs.wins = (int2*)p->hs_wins.p;
   hs.cap = (int32_t)p->hs_cap;
-  hs.split_flops = hash_split_flops(p->d < 1 ? 1 : p->d);
+  hs.split_flops = p->hs_split_flops;
   hs.ctr = (Counters*)p->ctr.p;
   return hs;
 }
@@ -212,15 +213,24 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   pr.flops = (int64_t*)p->flops.p;
   pr.crp = c_rowptr;
   if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
+  // products per row and their histogram first: the split threshold and the
+  // split slots follow from it
+  if ((rc = launch_hash_flops(pr, ctr->hash_hist, st))) return rc;
+  TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  TSS_HIP(hipStreamSynchronize(st));
   const int64_t words = (d + 31) / 32;
-  p->hs_cap = n > 0 ? hash_split_cap(n, d < 1 ? 1 : d) : 0;
+  hash_split_choose(p->host_ctr->hash_hist, d < 1 ? 1 : d, &p->hs_split_flops, &p->hs_cap);
   const int64_t item_cap = hash_split_item_cap(A->nnz, p->hs_cap);
   if ((rc = p->hs_slot.ensure((size_t)n * 4)) || (rc = p->hs_rows.ensure((size_t)p->hs_cap * 4)) ||
       (rc = p->hs_items.ensure((size_t)item_cap * 8)) || (rc = p->hs_bits.ensure((size_t)p->hs_cap * words * 4)) ||
-      (rc = p->hs_pref.ensure((size_t)p->hs_cap * words * 4)) || (rc = p->hs_off.ensure((size_t)p->hs_cap * 4)))
+      (rc = p->hs_pref.ensure((size_t)p->hs_cap * words * 4)) || (rc = p->hs_off.ensure((size_t)p->hs_cap * 4)) ||
+      (rc = p->hs_wins.ensure((size_t)hash_split_window_cap(p->hs_cap, d < 1 ? 1 : d) * 8)))
     return rc;
   const HashSplit hs = hash_split_view(p);
-  if ((rc = launch_hash_symbolic(pr, p->hmask, hs, (int32_t*)p->cnt.p, &ctr->hash_error, st))) return rc;
+  // every candidate split: the rows left have fewer than kHashSplitMin products
+  p->hs_all_split = p->hs_cap == hash_split_candidates(p->host_ctr->hash_hist);
+  if ((rc = launch_hash_symbolic(pr, p->hmask, hs, p->hs_all_split, (int32_t*)p->cnt.p, &ctr->hash_error, st)))
+    return rc;
   pr.cbits = nullptr;  // counts come from cnt
   if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
   TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
@@ -236,6 +246,7 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   p->hs_rows_n = h.hash_split_rows < p->hs_cap ? h.hash_split_rows : p->hs_cap;
   p->hs_items_n = h.hash_split_items;
   p->hs_acc_n = h.hash_split_acc;
+  p->hs_win_n = h.hash_win_items;
   p->n_split_rows = p->hs_rows_n;
   p->n_split_items = p->hs_items_n;
   *c_nnz = h.nnz_total;
@@ -456,7 +467,8 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   if (p->hash) {
     if ((rc = p->hnext.ensure(64))) return rc;
     return launch_hash_numeric(p->sr, pr, p->hmask, hash_split_view(p), (int32_t)p->hs_rows_n,
-                               (int32_t)p->hs_items_n, p->hs_acc_n, p->hstrips.p,
+                               (int32_t)p->hs_items_n, p->hs_acc_n, (int32_t)p->hs_win_n, !p->hs_all_split,
+                               p->hstrips.p,
                                &((Counters*)p->ctr.p)->hash_error, (int32_t*)p->hnext.p, st);
   }
   if (!vals) return launch_emit_pattern(pr, st);

@@ -56,8 +56,9 @@ struct Plan {
   DevBuf hnext;            // hash plan: row counter of the long-row workers
   // hash plan, split rows: slot of each row, row of each slot, chunk list,
   // bitmaps, per-word counts, accumulator offsets, accumulators
-  DevBuf hs_slot, hs_rows, hs_items, hs_bits, hs_pref, hs_off, hs_acc;
-  int64_t hs_cap = 0, hs_rows_n = 0, hs_items_n = 0, hs_acc_n = 0;
+  DevBuf hs_slot, hs_rows, hs_items, hs_bits, hs_pref, hs_off, hs_acc, hs_wins;
+  int64_t hs_cap = 0, hs_rows_n = 0, hs_items_n = 0, hs_acc_n = 0, hs_win_n = 0, hs_split_flops = 0;
+  bool hs_all_split = false;  // every row with kHashSplitMin products or more is split
   DevBuf sp_chunks, sp_rows, sp_partial, sp_ctr;  // dense-B SpMM workspace (per-device cached plan)
   DevBuf em_ci, em_val;    // embedding update: second copy of Z (per-device cached plan)
   DevBuf em_cnt, em_split, em_slot_off, em_split_off, em_slot_row, em_split_list, em_partial, em_scan;

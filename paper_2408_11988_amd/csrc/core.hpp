@@ -45,7 +45,8 @@ struct Counters {
   int32_t hash_split_items;  // hash accumulator: chunks of the split rows
   int32_t hash_split_next;   // hash accumulator: next chunk for the symbolic chunk workers
   int32_t hash_split_acc;    // hash accumulator: accumulator slots of the split rows
-  int32_t pad0;
+  int32_t hash_win_items;    // hash accumulator: output windows of the widest split rows
+  int32_t hash_hist[64];     // hash accumulator: rows by floor(log2(products)), from kHashSplitMin up
   int64_t flops_total;
   int64_t nnz_total;
 };
@@ -153,21 +154,34 @@ struct HashSplit {
   uint32_t* bits;        // cap x words: the row's output columns
   int32_t* pref;         // cap x words: outputs of the row before each word
   int32_t* acc_off;      // cap: first accumulator of the row
+  int2* wins;            // output windows of rows wider than a chunk's LDS array: (slot, window)
   void* acc;             // accumulators (FP64, or INT32 for the integer semiring)
   int32_t cap;           // split slots (0: no row is split)
-  int32_t split_flops;   // rows with more products are split rows
+  int64_t split_flops;   // rows with at least this many products are split rows
   Counters* ctr;
 };
-int64_t hash_split_cap(int64_t n, int64_t d);
-int32_t hash_split_flops(int64_t d);
+// Products per row into pr.flops, and the histogram of floor(log2) of the
+// products of rows with at least kHashSplitMin of them.
+constexpr int64_t kHashSplitMin = 512;
+int launch_hash_flops(const Problem& pr, int32_t* hist, hipStream_t st);
+// From that histogram: the split threshold (a power of two >= kHashSplitMin
+// whose rows' bitmaps fit the split budget) and the number of rows at or
+// above it.
+void hash_split_choose(const int32_t* hist, int64_t d, int64_t* split_flops, int64_t* rows);
 int64_t hash_split_item_cap(int64_t a_nnz, int64_t cap);
-int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& hs, int32_t* cnt, int32_t* err,
-                         hipStream_t st);
+int64_t hash_split_window_cap(int64_t cap, int64_t d);
+// small_rows_only: every row that is not split has fewer than kHashSplitMin products
+int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& hs, bool small_rows_only,
+                         int32_t* cnt, int32_t* err, hipStream_t st);
 int64_t hash_dense_workers(int64_t d);
 // next: a device counter (4 bytes) for the long-row workers; split_rows,
-// split_items and split_acc: the split counts the symbolic phase ended with
+// split_items and split_acc: the split counts the symbolic phase ended with;
+// long_rows: some row that is not split may have more outputs than the LDS
+// tables hold (else the long-row kernel is not launched)
 int launch_hash_numeric(int sr, const Problem& pr, const HashMask& m, const HashSplit& hs, int32_t split_rows,
-                        int32_t split_items, int64_t split_acc, void* strips, int32_t* err, int32_t* next,
-                        hipStream_t st);
+                        int32_t split_items, int64_t split_acc, int32_t win_items, bool long_rows, void* strips,
+                        int32_t* err, int32_t* next, hipStream_t st);
+// Rows at or above kHashSplitMin products in the histogram.
+int64_t hash_split_candidates(const int32_t* hist);
 
 }  // namespace tss

@@ -23,18 +23,25 @@
 // Masked columns are tested per product (binary search in the mask row, or a
 // bit test), so tables only ever hold output columns.
 //
-// Rows with more than hash_split_flops(d) products are split rows (power-law
-// inputs have hubs whose product lists would keep one wavefront busy for the
-// whole launch): chunks of kSplitEntries A entries go to separate workgroups. The
+// Rows with at least hash_split_choose's threshold of products are split rows
+// (power-law inputs have hubs whose product lists would keep one wavefront
+// busy for the whole launch): chunks of kSplitEntries A entries go to
+// separate workgroups. The threshold is kHashSplitMin unless the rows above it
+// would need more bitmap memory than the split budget; then it is the least
+// power of two whose rows fit, so the longest rows are always split. The
 // symbolic chunks OR their columns into the row's global bitmap (an LDS copy
 // first, then one atomic OR per non-zero word); a count pass gives the row's
 // output count and, per bitmap word, the outputs before it. The numeric
 // chunks add each product at the column's rank in that bitmap, into an LDS
 // array of the row's outputs when they fit (then one global atomic add per
-// output) or straight into the row's global accumulators; an emit pass writes
-// the row in column order. A row of one chunk whose outputs fit in LDS is
-// written by its chunk directly. Split slots are bounded (hash_split_cap);
-// rows past the bound take the one-wavefront path.
+// output); an emit pass writes the row in column order. A row of one chunk
+// whose outputs fit in LDS is written by its chunk directly. A row with more
+// outputs than that LDS array is cut into windows of output positions
+// instead: a workgroup per window walks all of the row's products, keeps
+// those whose column ranks fall in its window, and writes the window (wide
+// rows have little reuse per column, so global atomic adds would cost one
+// per product). Rows below the threshold, or past a slot
+// bound forced for tests, take the one-wavefront paths.
 #include <cstdlib>
 #include <type_traits>
 
@@ -109,6 +116,52 @@ __device__ __forceinline__ int stage_products(const Problem& pr, int base, int n
   return __shfl(incl, kWave - 1, kWave);
 }
 
+// As stage_products, but only the products of columns [c_lo, c_hi): lane t's
+// B row is cut to that range by binary search (B rows are sorted).
+template <typename T>
+__device__ __forceinline__ int stage_window(const Problem& pr, int base, int nb, int c_lo, int c_hi, int* start,
+                                            int* pref, T* aval_s) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int q0 = 0, len = 0;
+  T a = T(0);
+  if (lane < nb) {
+    const int k = pr.aci[base + lane];
+    int lo = pr.brp[k], hi = pr.brp[k + 1];
+    int l = lo, h = hi;  // first entry >= c_lo
+    while (l < h) {
+      const int m = (l + h) >> 1;
+      if (pr.bci[m] < c_lo)
+        l = m + 1;
+      else
+        h = m;
+    }
+    q0 = l;
+    h = hi;  // first entry >= c_hi
+    while (l < h) {
+      const int m = (l + h) >> 1;
+      if (pr.bci[m] < c_hi)
+        l = m + 1;
+      else
+        h = m;
+    }
+    len = l - q0;
+    a = ((const T*)pr.aval)[base + lane];
+  }
+  int incl = len;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  wave_sync();
+  start[lane] = q0;
+  pref[lane + 1] = incl;
+  if (lane == 0) pref[0] = 0;
+  aval_s[lane] = a;
+  wave_sync();
+  return __shfl(incl, kWave - 1, kWave);
+}
+
 // index e of the staged entry holding flat product t: pref[e] <= t < pref[e + 1]
 __device__ __forceinline__ int staged_entry(const int* pref, int t) {
   int lo = 0, hi = kWave;
@@ -122,6 +175,41 @@ __device__ __forceinline__ int staged_entry(const int* pref, int t) {
   return lo;
 }
 
+// Visits the staged products t = lane, lane + 64, ... < total, kGather per
+// lane at a time: all their B loads are issued before any is used, so a
+// wavefront waits for one round of loads per kGather products.
+// f(e, q, j, b): staged entry, position in B, column, B value (V = char:
+// pattern only, b unused).
+constexpr int kGather = 4;
+template <typename V, typename F>
+__device__ __forceinline__ void for_staged_products(const Problem& pr, int total, const int* start, const int* pref,
+                                                    F&& f) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const V* __restrict__ bval = (const V*)pr.bval;
+  for (int t0 = lane; t0 < total; t0 += kGather * kWave) {
+    int e[kGather], q[kGather];
+    int32_t j[kGather];
+    V b[kGather];
+#pragma unroll
+    for (int u = 0; u < kGather; ++u) {
+      const int t = t0 + u * kWave;
+      e[u] = -1;
+      q[u] = 0;
+      j[u] = 0;
+      b[u] = V(0);
+      if (t < total) {
+        e[u] = staged_entry(pref, t);
+        q[u] = start[e[u]] + (t - pref[e[u]]);
+        j[u] = pr.bci[q[u]];
+        if constexpr (!std::is_same<V, char>::value) b[u] = bval[q[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kGather; ++u)
+      if (e[u] >= 0) f(e[u], q[u], j[u], b[u]);
+  }
+}
+
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) v += __shfl_xor(v, o, kWave);
@@ -130,9 +218,13 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 
 // ---------------------------------------------------------------- symbolic
 
+// SW: LDS words per wavefront. kSymSlots covers any row (a table, or a d-bit
+// bitmap); 2 kHashSplitMin suffices when every row left here has fewer than
+// kHashSplitMin products (its table of 2 min(d, flops_i) slots fits).
+template <int SW>
 __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr, HashMask hm, HashSplit hs,
                                                                       int32_t* cnt, int32_t* err) {
-  __shared__ uint32_t sm[kHashWaves][kSymSlots];
+  __shared__ uint32_t sm[kHashWaves][SW];
   __shared__ int start_s[kHashWaves][kWave], pref_s[kHashWaves][kWave + 1];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
   uint32_t* tab = sm[wave];
@@ -141,14 +233,8 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr
   const bool masked = hm.rp || hm.bits;
   for (int64_t row = (int64_t)blockIdx.x * kHashWaves + wave; row < pr.n; row += (int64_t)gridDim.x * kHashWaves) {
     const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
-    long long fl = 0;
-    for (int p = p0 + lane; p < p1; p += kWave) {
-      const int k = pr.aci[p];
-      fl += pr.brp[k + 1] - pr.brp[k];
-    }
-    fl = wave_sum_ll(fl);
-    if (lane == 0) pr.flops[row] = fl;
-    if (fl > hs.split_flops && hs.cap > 0) {
+    const long long fl = pr.flops[row];  // from k_hash_flops
+    if (fl >= hs.split_flops && hs.cap > 0) {
       int slot = 0;
       if (lane == 0) slot = atomicAdd(&hs.ctr->hash_split_rows, 1);
       slot = __shfl(slot, 0, kWave);
@@ -175,7 +261,7 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr
       continue;
     }
     const int64_t ub = fl < pr.d ? fl : pr.d;
-    const bool table = 2 * ub <= kSymSlots;
+    const bool table = 2 * ub <= SW;
     const uint32_t tsz = table ? pow2_at_least((uint32_t)(2 * ub)) : 0u;
     const int words = table ? (int)tsz : (pr.d + 31) >> 5;
     for (int t = lane; t < words; t += kWave) tab[t] = table ? kEmpty : 0u;
@@ -184,10 +270,8 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr
     for (int base = p0; base < p1; base += kWave) {
       const int nb = min(kWave, p1 - base);
       const int total = stage_products<char>(pr, base, nb, start, pref, nullptr);
-      for (int t = lane; t < total; t += kWave) {
-        const int e = staged_entry(pref, t);
-        const int32_t j = pr.bci[start[e] + (t - pref[e])];
-        if (masked && is_masked(hm, row, j)) continue;
+      for_staged_products<char>(pr, total, start, pref, [&](int, int, int32_t j, char) {
+        if (masked && is_masked(hm, row, j)) return;
         if (table) {
           uint32_t h = hslot(j, tsz - 1);
           uint32_t probes = 0;
@@ -208,7 +292,7 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr
           const uint32_t bit = 1u << (j & 31);
           if (!(atomicOr(&tab[j >> 5], bit) & bit)) ++fresh;
         }
-      }
+      });
       wave_sync();
     }
     const long long c = wave_sum_ll(fresh);
@@ -226,11 +310,39 @@ __host__ __device__ constexpr int split_width(int words) {
 }
 __host__ __device__ constexpr int split_lds_outputs(int width) { return width <= 64 ? 2048 : 4096; }
 
+__device__ __forceinline__ int split_lds(const Problem& pr) { return split_lds_outputs(split_width((pr.d + 31) >> 5)); }
+
 // A split row of one chunk whose outputs fit the chunk's LDS array: the
 // chunk writes the row itself (value semirings).
 __device__ __forceinline__ bool split_direct(const Problem& pr, int row, int cnt) {
-  return pr.arp[row + 1] - pr.arp[row] <= kSplitEntries &&
-         cnt <= split_lds_outputs(split_width((pr.d + 31) >> 5));
+  return pr.arp[row + 1] - pr.arp[row] <= kSplitEntries && cnt <= split_lds(pr);
+}
+
+// A split row with more outputs than that array: written window by window.
+__device__ __forceinline__ bool split_windowed(const Problem& pr, int cnt) { return cnt > split_lds(pr); }
+
+// Products per row (one wavefront per row) and the histogram of the rows
+// that may be split.
+__global__ __launch_bounds__(kHashWaves * kWave) void k_hash_flops(Problem pr, int32_t* hist) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int64_t row = (int64_t)blockIdx.x * kHashWaves + wave;
+  if (row >= pr.n) return;
+  const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
+  long long fl = 0;
+  constexpr int U = 8;  // A entries per lane in flight (hub rows are long)
+  for (int p = p0 + lane; p < p1; p += U * kWave) {
+    int k[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) k[u] = p + u * kWave < p1 ? pr.aci[p + u * kWave] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k[u] >= 0) fl += pr.brp[k[u] + 1] - pr.brp[k[u]];
+  }
+  fl = wave_sum_ll(fl);
+  if (lane == 0) {
+    pr.flops[row] = fl;
+    if (fl >= kHashSplitMin) atomicAdd(&hist[63 - __clzll(fl)], 1);
+  }
 }
 
 // Symbolic chunks of split rows. The workers take chunks from a counter
@@ -240,7 +352,7 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_symbolic(Pro
   __shared__ uint32_t bm[WC];
   __shared__ int start_s[kSplitWaves][kWave], pref_s[kSplitWaves][kWave + 1];
   __shared__ int item_s;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x >> 6;
   const int words = (pr.d + 31) >> 5;
   const bool masked = hm.rp || hm.bits;
   const int n_items = hs.ctr->hash_split_items;
@@ -257,12 +369,10 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_symbolic(Pro
     if (base < a1) {
       const int nb = min(kWave, a1 - base);
       const int total = stage_products<char>(pr, base, nb, start_s[wave], pref_s[wave], nullptr);
-      for (int t = lane; t < total; t += kWave) {
-        const int e = staged_entry(pref_s[wave], t);
-        const int32_t j = pr.bci[start_s[wave][e] + (t - pref_s[wave][e])];
-        if (masked && is_masked(hm, row, j)) continue;
+      for_staged_products<char>(pr, total, start_s[wave], pref_s[wave], [&](int, int, int32_t j, char) {
+        if (masked && is_masked(hm, row, j)) return;
         atomicOr(&bm[j >> 5], 1u << (j & 31));
-      }
+      });
     }
     __syncthreads();
     uint32_t* gb = hs.bits + (int64_t)itm.x * words;
@@ -309,7 +419,14 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_count(Proble
     if (threadIdx.x == 0) {
       const int row = hs.rows[slot];
       cnt[row] = run;
-      hs.acc_off[slot] = split_direct(pr, row, run) ? 0 : atomicAdd(&hs.ctr->hash_split_acc, run);
+      if (split_windowed(pr, run)) {
+        const int lc = split_lds(pr), nw = (run + lc - 1) / lc;
+        const int first = atomicAdd(&hs.ctr->hash_win_items, nw);
+        for (int w = 0; w < nw; ++w) hs.wins[first + w] = make_int2(slot, w);
+        hs.acc_off[slot] = 0;
+      } else {
+        hs.acc_off[slot] = split_direct(pr, row, run) ? 0 : atomicAdd(&hs.ctr->hash_split_acc, run);
+      }
     }
   }
 }
@@ -382,7 +499,6 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_table(Probl
   uint32_t* keys = keys_s[wave];
   Acc* vals = vals_s[wave];
   const bool masked = hm.rp || hm.bits;
-  const V* __restrict__ bval = (const V*)pr.bval;
   const uint64_t below = lane == 0 ? 0ull : ~0ull >> (kWave - lane);
   for (int64_t row = (int64_t)blockIdx.x * kHashWaves + wave; row < pr.n; row += (int64_t)gridDim.x * kHashWaves) {
     const int c0 = pr.crp[row], nnz = pr.crp[row + 1] - c0;
@@ -397,11 +513,8 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_table(Probl
     for (int base = p0; base < p1; base += kWave) {
       const int nb = min(kWave, p1 - base);
       const int total = stage_products<V>(pr, base, nb, start_s[wave], pref_s[wave], aval_s[wave]);
-      for (int t = lane; t < total; t += kWave) {
-        const int e = staged_entry(pref_s[wave], t);
-        const int q = start_s[wave][e] + (t - pref_s[wave][e]);
-        const int32_t j = pr.bci[q];
-        if (masked && is_masked(hm, row, j)) continue;
+      for_staged_products<V>(pr, total, start_s[wave], pref_s[wave], [&](int e, int, int32_t j, V b) {
+        if (masked && is_masked(hm, row, j)) return;
         uint32_t h = hslot(j, tsz - 1);
         uint32_t probes = 0;
         for (;;) {
@@ -415,8 +528,8 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_table(Probl
           }
         }
         if constexpr (!std::is_same<V, char>::value)
-          if (h != kEmpty) lds_add(&vals[h], hash_prod<V>(aval_s[wave][e], bval[q]));
-      }
+          if (h != kEmpty) lds_add(&vals[h], hash_prod<V>(aval_s[wave][e], b));
+      });
       wave_sync();
     }
     if constexpr (RANK) {
@@ -514,7 +627,6 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_dense(Probl
   const int words = (pr.d + 31) >> 5;
   Acc* strip = strips + ((int64_t)blockIdx.x * kHashWaves + wave) * pr.d;
   const bool masked = hm.rp || hm.bits;
-  const V* __restrict__ bval = (const V*)pr.bval;
   for (int t = lane; t < words; t += kWave) bm[t] = 0u;
   wave_sync();
   // rows are taken kDenseFetch at a time from a shared counter (the workers
@@ -538,19 +650,16 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_dense(Probl
     for (int base = p0; base < p1; base += kWave) {
       const int nb = min(kWave, p1 - base);
       const int total = stage_products<V>(pr, base, nb, start_s[wave], pref_s[wave], aval_s[wave]);
-      for (int t = lane; t < total; t += kWave) {
-        const int e = staged_entry(pref_s[wave], t);
-        const int q = start_s[wave][e] + (t - pref_s[wave][e]);
-        const int32_t j = pr.bci[q];
-        if (masked && is_masked(hm, row_id, j)) continue;
+      for_staged_products<V>(pr, total, start_s[wave], pref_s[wave], [&](int e, int, int32_t j, V b) {
+        if (masked && is_masked(hm, row_id, j)) return;
         atomicOr(&bm[j >> 5], 1u << (j & 31));
         if constexpr (!std::is_same<V, char>::value) {
           if constexpr (sizeof(Acc) == 8)
-            atomicAdd(&strip[j], hash_prod<V>(aval_s[wave][e], bval[q]));
+            atomicAdd(&strip[j], hash_prod<V>(aval_s[wave][e], b));
           else
-            atomicAdd((unsigned int*)&strip[j], (unsigned int)hash_prod<V>(aval_s[wave][e], bval[q]));
+            atomicAdd((unsigned int*)&strip[j], (unsigned int)hash_prod<V>(aval_s[wave][e], b));
         }
-      }
+      });
       wave_sync();
     }
     __threadfence_block();  // this wavefront's adds are done before they are read back
@@ -618,7 +727,7 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_numeric(Prob
   const int2 itm = hs.items[blockIdx.x];
   const int row = hs.rows[itm.x];
   const int cnt = pr.crp[row + 1] - pr.crp[row];
-  const bool in_lds = cnt <= LC;
+  if (cnt > LC) return;  // written by its windows
   const uint32_t* gb = hs.bits + (int64_t)itm.x * words;
   const int32_t* gp = hs.pref + (int64_t)itm.x * words;
   Acc* gacc = (Acc*)hs.acc + hs.acc_off[itm.x];
@@ -626,8 +735,7 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_numeric(Prob
     bm[t] = gb[t];
     bp[t] = gp[t];
   }
-  if (in_lds)
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) acc[t] = Acc(0);
+  for (int t = threadIdx.x; t < cnt; t += blockDim.x) acc[t] = Acc(0);
   __syncthreads();
   const bool masked = hm.rp || hm.bits;
   const V* __restrict__ bval = (const V*)pr.bval;
@@ -636,25 +744,53 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_numeric(Prob
   if (base < a1) {
     const int nb = min(kWave, a1 - base);
     const int total = stage_products<V>(pr, base, nb, start_s[wave], pref_s[wave], aval_s[wave]);
-    for (int t = lane; t < total; t += kWave) {
-      const int e = staged_entry(pref_s[wave], t);
-      const int q = start_s[wave][e] + (t - pref_s[wave][e]);
-      const int32_t j = pr.bci[q];
-      if (masked && is_masked(hm, row, j)) continue;
-      const uint32_t word = bm[j >> 5], bit = 1u << (j & 31);
-      if (!(word & bit)) {  // a column the symbolic phase did not see: inputs changed
-        atomicOr(err, 1);
-        continue;
+    // U products per lane per step; the next step's B loads are issued before
+    // this step's adds, so waiting for them does not wait for the adds
+    constexpr int U = 4;
+    int en[U];
+    int32_t jn[U];
+    V bn[U];
+    auto load = [&](int t0) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * kWave;
+        en[u] = -1;
+        if (t < total) {
+          const int e = staged_entry(pref_s[wave], t);
+          const int q = start_s[wave][e] + (t - pref_s[wave][e]);
+          en[u] = e;
+          jn[u] = pr.bci[q];
+          bn[u] = bval[q];
+        }
       }
-      const int pos = bp[j >> 5] + __popc(word & (bit - 1u));
-      const Acc v = hash_prod<V>(aval_s[wave][e], bval[q]);
-      if (in_lds)
-        lds_add(&acc[pos], v);
-      else
-        global_add(&gacc[pos], v);
+    };
+    load(lane);
+    for (int t0 = lane; t0 < total; t0 += U * kWave) {
+      int ec[U];
+      int32_t jc[U];
+      V bc[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        ec[u] = en[u];
+        jc[u] = jn[u];
+        bc[u] = bn[u];
+      }
+      load(t0 + U * kWave);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ec[u] < 0) continue;
+        const int32_t j = jc[u];
+        if (masked && is_masked(hm, row, j)) continue;
+        const uint32_t word = bm[j >> 5], bit = 1u << (j & 31);
+        if (!(word & bit)) {  // a column the symbolic phase did not see: inputs changed
+          atomicOr(err, 1);
+          continue;
+        }
+        const int pos = bp[j >> 5] + __popc(word & (bit - 1u));
+        lds_add(&acc[pos], hash_prod<V>(aval_s[wave][ec[u]], bc[u]));
+      }
     }
   }
-  if (!in_lds) return;
   __syncthreads();
   if (split_direct(pr, row, cnt)) {  // the whole row: write it in column order
     const int c0 = pr.crp[row];
@@ -677,6 +813,105 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_numeric(Prob
   }
 }
 
+// One window of output positions [w LC, (w + 1) LC) of a wide split row
+// (one workgroup per window). The window's columns are [c_lo, c_hi) (the
+// columns at positions lo and hi in the row's bitmap); B rows are sorted, so
+// each A entry's products in the window are one range of its B row, found by
+// binary search. Those products are added in LDS, then the window is written.
+template <typename V, int WC>
+__global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_window(Problem pr, HashMask hm, HashSplit hs,
+                                                                           int32_t* err) {
+  using Acc = typename HashAcc<V>::type;
+  constexpr int LC = split_lds_outputs(WC);
+  __shared__ uint32_t bm[WC];
+  __shared__ int32_t bp[WC];
+  __shared__ Acc acc[LC];
+  __shared__ int start_s[kSplitWaves][kWave], pref_s[kSplitWaves][kWave + 1];
+  __shared__ V aval_s[kSplitWaves][kWave];
+  __shared__ int cols_s[2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int words = (pr.d + 31) >> 5;
+  const int2 wi = hs.wins[blockIdx.x];
+  const int row = hs.rows[wi.x];
+  const int c0 = pr.crp[row], cnt = pr.crp[row + 1] - c0;
+  const int lo = wi.y * LC, hi = min(lo + LC, cnt);
+  const uint32_t* gb = hs.bits + (int64_t)wi.x * words;
+  const int32_t* gp = hs.pref + (int64_t)wi.x * words;
+  if (threadIdx.x == 0 && hi == cnt) cols_s[1] = pr.d;  // the last window: up to the last column
+  for (int t = threadIdx.x; t < words; t += blockDim.x) {
+    uint32_t word = gb[t];
+    const int pos = gp[t];
+    bm[t] = word;
+    bp[t] = pos;
+    // the word holding position lo (or hi) gives c_lo (or c_hi)
+    const int c = __popc(word);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int target = side ? hi : lo;
+      if ((side == 0 || hi < cnt) && pos <= target && target < pos + c) {
+        uint32_t x = word;
+        for (int k = target - pos; k > 0; --k) x &= x - 1;
+        cols_s[side] = (t << 5) + __ffs(x) - 1;
+      }
+    }
+  }
+  for (int t = threadIdx.x; t < hi - lo; t += blockDim.x) acc[t] = Acc(0);
+  __syncthreads();
+  const int c_lo = cols_s[0], c_hi = cols_s[1];
+  const bool masked = hm.rp || hm.bits;
+  const V* __restrict__ bval = (const V*)pr.bval;
+  const int p1 = pr.arp[row + 1];
+  for (int base = pr.arp[row] + wave * kWave; base < p1; base += kSplitWaves * kWave) {
+    const int nb = min(kWave, p1 - base);
+    const int total = stage_window(pr, base, nb, c_lo, c_hi, start_s[wave], pref_s[wave], aval_s[wave]);
+    constexpr int U = 4;  // products per lane per step, loads first
+    int e[U];
+    int32_t j[U];
+    V b[U];
+    for (int t0 = lane; t0 < total; t0 += U * kWave) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int t = t0 + u * kWave;
+        e[u] = -1;
+        if (t < total) {
+          e[u] = staged_entry(pref_s[wave], t);
+          const int q = start_s[wave][e[u]] + (t - pref_s[wave][e[u]]);
+          j[u] = pr.bci[q];
+          b[u] = bval[q];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (e[u] < 0) continue;
+        if (masked && is_masked(hm, row, j[u])) continue;
+        const uint32_t word = bm[j[u] >> 5], bit = 1u << (j[u] & 31);
+        if (!(word & bit)) {  // a column the symbolic phase did not see: inputs changed
+          atomicOr(err, 1);
+          continue;
+        }
+        const int pos = bp[j[u] >> 5] + __popc(word & (bit - 1u));
+        if (pos >= lo && pos < hi) lds_add(&acc[pos - lo], hash_prod<V>(aval_s[wave][e[u]], b[u]));
+      }
+    }
+    wave_sync();  // the staging arrays are rewritten by the next batch
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < words; w += blockDim.x) {
+    uint32_t word = bm[w];
+    int pos = bp[w];
+    if (pos >= hi || pos + __popc(word) <= lo) continue;
+    while (word) {
+      const int bb = __ffs(word) - 1;
+      word &= word - 1;
+      if (pos >= lo && pos < hi) {
+        pr.cci[c0 + pos] = (w << 5) + bb;
+        ((V*)pr.cval)[c0 + pos] = SemiringT<V>::out(acc[pos - lo]);
+      }
+      ++pos;
+    }
+  }
+}
+
 // Writes a split row (one workgroup per row): columns in bitmap order and,
 // for value semirings, the row's accumulators.
 template <typename V>
@@ -686,8 +921,10 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_emit(Problem
   const int words = (pr.d + 31) >> 5;
   const int row = hs.rows[slot];
   const int c0 = pr.crp[row];
-  if constexpr (!std::is_same<V, char>::value)
-    if (split_direct(pr, row, pr.crp[row + 1] - c0)) return;  // written by its chunk
+  if constexpr (!std::is_same<V, char>::value) {
+    const int cnt = pr.crp[row + 1] - c0;
+    if (split_direct(pr, row, cnt) || split_windowed(pr, cnt)) return;  // written by its chunk or windows
+  }
   const uint32_t* gb = hs.bits + (int64_t)slot * words;
   const int32_t* gp = hs.pref + (int64_t)slot * words;
   const Acc* gacc = (const Acc*)hs.acc + hs.acc_off[slot];
@@ -706,24 +943,33 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_emit(Problem
 
 // ---------------------------------------------------------------- launch
 
-int64_t hash_split_cap(int64_t n, int64_t d) {
-  // bitmap and per-word counts of a slot: 8 bytes per word, at most 256 MB
-  // in all; the accumulators of all slots (at most cap x d) index in int32
+int64_t hash_split_candidates(const int32_t* hist) {
+  int64_t c = 0;
+  for (int b = 63 - __builtin_clzll((unsigned long long)kHashSplitMin); b < 64; ++b) c += hist[b];
+  return c;
+}
+
+void hash_split_choose(const int32_t* hist, int64_t d, int64_t* split_flops, int64_t* rows) {
+  // bitmap and per-word counts: 8 bytes per word and split row, at most 1 GB
   const int64_t words = (d + 31) / 32;
-  int64_t cap = (int64_t)(256ll << 20) / (words * 8);
-  if (cap > (1ll << 30) / d) cap = (1ll << 30) / d;
-  if (cap > n) cap = n;
-  if (const char* e = std::getenv("TSSPGEMM_HASH_SPLIT_CAP")) {  // tests: force rows past the bound
+  const int64_t max_rows = (int64_t)(1ll << 30) / (words * 8);
+  int t = 63 - __builtin_clzll((unsigned long long)kHashSplitMin);
+  int64_t above = 0;
+  for (int b = t; b < 64; ++b) above += hist[b];
+  while (above > max_rows && t < 63) above -= hist[t++];
+  int64_t cap = above;
+  if (const char* e = std::getenv("TSSPGEMM_HASH_SPLIT_CAP")) {  // tests: leave split candidates unsplit
     const long long v = std::atoll(e);
     if (v >= 0 && v < cap) cap = v;
   }
-  return cap;
+  *split_flops = 1ll << t;
+  *rows = cap;
 }
 
-int32_t hash_split_flops(int64_t d) {
-  // up to 256 bitmap words a split slot is cheap: every row that may have
-  // more outputs than the LDS table holds is split; above, only long rows
-  return (d + 31) / 32 <= 256 ? kHashNumMax : 4 * kHashNumMax;
+int64_t hash_split_window_cap(int64_t cap, int64_t d) {
+  // a row has at most d outputs: ceil(d / LC) windows
+  const int64_t lc = split_lds_outputs(split_width((int)((d + 31) / 32)));
+  return cap * ((d + lc - 1) / lc);
 }
 
 int64_t hash_split_item_cap(int64_t a_nnz, int64_t cap) {
@@ -733,11 +979,22 @@ int64_t hash_split_item_cap(int64_t a_nnz, int64_t cap) {
 
 // One wavefront per row (no grid stride), so the hardware's workgroup
 // dispatch balances rows of very different lengths.
-int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& hs, int32_t* cnt, int32_t* err,
-                         hipStream_t st) {
+int launch_hash_flops(const Problem& pr, int32_t* hist, hipStream_t st) {
   if (pr.n == 0) return TSSPGEMM_OK;
   const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;
-  k_hash_symbolic<<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, m, hs, cnt, err);
+  k_hash_flops<<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, hist);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& hs, bool small_rows_only,
+                         int32_t* cnt, int32_t* err, hipStream_t st) {
+  if (pr.n == 0) return TSSPGEMM_OK;
+  const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;
+  if (!small_rows_only)
+    k_hash_symbolic<kSymSlots><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, m, hs, cnt, err);
+  else
+    k_hash_symbolic<2 * kHashSplitMin><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, m, hs, cnt, err);
   TSS_CHECK_LAUNCH();
   if (hs.cap > 0) {
     const int wc = split_width((pr.d + 31) >> 5);
@@ -773,16 +1030,17 @@ static void table_classes(const Problem& pr, const HashMask& h, const HashSplit&
 
 template <typename V, typename Acc>
 static void hash_numeric_kernels(const Problem& pr, const HashMask& h, const HashSplit& hs, int32_t split_rows,
-                                 int32_t split_items, int64_t g, int64_t gd, void* strips, int32_t* err,
-                                 int32_t* next, hipStream_t st) {
+                                 int32_t split_items, int32_t win_items, int64_t g, int64_t gd, void* strips,
+                                 int32_t* err, int32_t* next, hipStream_t st) {
   const bool narrow = ((pr.d + 31) >> 5) <= kRankWords;
   if (narrow) {
     table_classes<V, true>(pr, h, hs, g, err, st);
   } else {
     table_classes<V, false>(pr, h, hs, g, err, st);
   }
-  k_hash_numeric_dense<V><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, (Acc*)strips, err,
-                                                                        next);
+  if (gd > 0)
+    k_hash_numeric_dense<V><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, (Acc*)strips, err,
+                                                                          next);
   if constexpr (!std::is_same<V, char>::value) {  // pattern-only rows need no accumulation
     const int wc = split_width((pr.d + 31) >> 5);
     const unsigned gi = (unsigned)split_items;
@@ -792,16 +1050,23 @@ static void hash_numeric_kernels(const Problem& pr, const HashMask& h, const Has
       k_hash_split_numeric<V, kRankWords><<<gi, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
     else if (split_items > 0)
       k_hash_split_numeric<V, kSymSlots><<<gi, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+    const unsigned gw = (unsigned)win_items;
+    if (win_items > 0 && wc == 64)
+      k_hash_split_window<V, 64><<<gw, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+    else if (win_items > 0 && wc == kRankWords)
+      k_hash_split_window<V, kRankWords><<<gw, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+    else if (win_items > 0)
+      k_hash_split_window<V, kSymSlots><<<gw, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
   }
   if (split_rows > 0) k_hash_split_emit<V><<<(unsigned)split_rows, kSplitWaves * kWave, 0, st>>>(pr, hs);
 }
 
 int launch_hash_numeric(int sr, const Problem& pr, const HashMask& h, const HashSplit& hs, int32_t split_rows,
-                        int32_t split_items, int64_t split_acc, void* strips, int32_t* err, int32_t* next,
-                        hipStream_t st) {
+                        int32_t split_items, int64_t split_acc, int32_t win_items, bool long_rows, void* strips,
+                        int32_t* err, int32_t* next, hipStream_t st) {
   if (pr.n == 0) return TSSPGEMM_OK;
   const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;  // table rows: one wavefront per row
-  int64_t gd = hash_dense_workers(pr.d) / kHashWaves;
+  int64_t gd = long_rows ? hash_dense_workers(pr.d) / kHashWaves : 0;  // long-row workers, if any row needs them
   if (gd > g) gd = g;
   int rc;
   if ((rc = launch_zero_bytes(next, 4, st))) return rc;
@@ -809,11 +1074,14 @@ int launch_hash_numeric(int sr, const Problem& pr, const HashMask& h, const Hash
   if (sr != TSSPGEMM_OR_AND && split_acc > 0 && (rc = launch_zero_bytes(hs.acc, (size_t)split_acc * acc_bytes, st)))
     return rc;
   if (sr == TSSPGEMM_PLUS_TIMES_F32)
-    hash_numeric_kernels<float, double>(pr, h, hs, split_rows, split_items, g, gd, strips, err, next, st);
+    hash_numeric_kernels<float, double>(pr, h, hs, split_rows, split_items, win_items, g, gd, strips, err, next,
+                                        st);
   else if (sr == TSSPGEMM_PLUS_TIMES_I32)
-    hash_numeric_kernels<int32_t, int32_t>(pr, h, hs, split_rows, split_items, g, gd, strips, err, next, st);
+    hash_numeric_kernels<int32_t, int32_t>(pr, h, hs, split_rows, split_items, win_items, g, gd, strips, err,
+                                          next, st);
   else
-    hash_numeric_kernels<char, int32_t>(pr, h, hs, split_rows, split_items, g, gd, strips, err, next, st);
+    hash_numeric_kernels<char, int32_t>(pr, h, hs, split_rows, split_items, win_items, g, gd, strips, err,
+                                       next, st);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }

@@ -234,6 +234,17 @@ def workload_rmat_plain(scale: int = 20, d: int = 128, seed: int = CONFIG_SEED +
     return a, b
 
 
+def workload_wide_d(d: int, scale: int = 18, lam: float = 25.6, seed: int = CONFIG_SEED + 9) -> tuple[Csr, Csr]:
+    """The varying-d sweep: R-MAT scale `scale`, edge factor 16, U(0,1); B n x d
+    with Poisson(lam) entries per row (the same product count at every d, so
+    only the output width changes), U(0,1)."""
+    a = rmat(scale, 16, seed)
+    a = a.with_values(values(a, "uniform", seed, S_AVAL))
+    b = b_poisson(a.nrows, d, lam, seed)
+    b = b.with_values(values(b, "uniform", seed, S_BVAL))
+    return a, b
+
+
 def workload_bfs(scale: int = 22, d: int = 512, seed: int = CONFIG_SEED + 3) -> tuple[Csr, np.ndarray]:
     """R-MAT scale `scale` pattern and d distinct non-isolated sources."""
     a = rmat(scale, 16, seed)

@@ -356,7 +356,6 @@ def test_hash_split_rows(d, monkeypatch):
     b = synth.b_poisson(a.nrows, d, 40.0, 6102 + d)
     b = b.with_values(synth.values(b, "uniform", 6103, synth.S_BVAL))
     flops = oracle.row_flops(a.rp, a.ci, b.rp)
-    thr = 512 if (d + 31) // 32 <= 256 else 2048  # split rows: more products than this
     assert np.max(np.diff(a.rp)) > 512 and np.sum(flops > 2048) > 8  # split rows of several chunks
     ref = None
     for cap in (None, "3", "0"):
@@ -368,7 +367,7 @@ def test_hash_split_rows(d, monkeypatch):
         C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True)
         torch.cuda.synchronize()
         split = plan.stats()["split_rows"]
-        want = {None: int(np.sum(flops > thr)), "3": 3, "0": 0}[cap]
+        want = {None: int(np.sum(flops >= 512)), "3": 3, "0": 0}[cap]  # split rows: 512 products or more
         assert split == want, (split, want)
         frac = compare_f32(a, b, C, threads=8)
         assert frac > 0.999
@@ -388,8 +387,45 @@ def test_hash_split_rows(d, monkeypatch):
     compare_int(ai, bi, C)
     rng = np.random.default_rng(6104 + d)
     m = random_csr(rng, a.nrows, d, 0.2)
+    M = to_dev(m, with_values=False)
     note(f"hash split rows or_and with a csr mask d={d}")
-    C = tss.spgemm(to_dev(a, with_values=False), to_dev(b, with_values=False), semiring="or_and",
-                   mask=to_dev(m, with_values=False))
+    C = tss.spgemm(to_dev(a, with_values=False), to_dev(b, with_values=False), semiring="or_and", mask=M)
     torch.cuda.synchronize()
     compare_bool(a, b, C, mask=m)
+    note(f"hash split rows plus_times with a csr mask d={d}")
+    C = tss.spgemm(to_dev(a), to_dev(b), mask=M)
+    g_rp, g_ci, g_val = C.to_host()
+    rp, ci = oracle.spgemm_bool(a.rp, a.ci, b.rp, b.ci, m.rp, m.ci)
+    assert np.array_equal(g_rp.astype(np.int64), rp) and np.array_equal(g_ci, ci)
+    frp, fci, fval = oracle.spgemm(a.rp, a.ci, a.val, b.rp, b.ci, b.val, threads=8)
+    fkey = np.repeat(np.arange(a.nrows, dtype=np.int64), np.diff(frp)) * d + fci
+    gkey = np.repeat(np.arange(a.nrows, dtype=np.int64), np.diff(g_rp.astype(np.int64))) * d + g_ci
+    ref = fval[np.searchsorted(fkey, gkey)]
+    assert np.all(np.abs(g_val - ref) <= 1e-5 * np.abs(ref))
+
+
+@pytest.mark.parametrize("d", [2048, 65536])
+def test_wide_d_rmat18_sampled(d):
+    """The varying-d benchmark workload past d = 1024 (R-MAT scale 18, B with
+    Poisson(25.6) entries per row; hash accumulator, split hub rows): every
+    row checked for the invariants, the heaviest and random rows against the
+    oracle."""
+    a, b = synth.workload_wide_d(d)
+    tss = _tss()
+    note(f"R-MAT 18 d={d} nnzA={a.nnz} nnzB={b.nnz}")
+    C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True)
+    torch.cuda.synchronize()
+    g_rp, g_ci, _ = C.to_host()
+    flops = oracle.row_flops(a.rp, a.ci, b.rp)
+    assert plan.stats()["flops"] == int(flops.sum()) and plan.stats()["split_rows"] > 0
+    cnt = np.diff(g_rp.astype(np.int64))
+    assert np.all(cnt <= np.minimum(d, flops)) and np.all((cnt == 0) == (flops == 0))
+    rows = np.repeat(np.arange(a.nrows), cnt)
+    key = rows * d + g_ci.astype(np.int64)
+    assert np.all(np.diff(key) > 0) and g_ci.min() >= 0 and g_ci.max() < d
+    rng = np.random.default_rng(d)
+    heavy = np.argsort(flops)[-16:]
+    sample = np.unique(np.concatenate([heavy, rng.choice(a.nrows, 2000, replace=False), [0, a.nrows - 1]]))
+    note(f"oracle on {len(sample)} sampled rows")
+    frac = compare_f32(a, b, C, rows=sample.astype(np.int32), threads=16)
+    assert frac > 0.999
