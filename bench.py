@@ -679,6 +679,7 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     ms_sym = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
     ms_num = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+    per_step = sorted(e[0].elapsed_time(e[2]) for e in ev)  # HIP events, one step each
     log(f"step {ms_step:.3f} ms  symbolic {ms_sym:.3f} ms  numeric {ms_num:.3f} ms")
 
     bytes_alg = (4 * (n + 1) + 8 * a.nnz) + (4 * (n + 1) + 8 * b.nnz) + (4 * (n + 1) + 8 * nnz_c)
@@ -705,6 +706,8 @@ def main():
                    "n": n, "d": d, "nnz_a": a.nnz, "nnz_b": b.nnz, "nnz_c": nnz_c, "flops": flops},
         "ms_symbolic": round(ms_sym, 4),
         "ms_numeric": round(ms_num, 4),
+        "ms_step_events": {"median": round(per_step[len(per_step) // 2], 4), "min": round(per_step[0], 4),
+                           "mean": round(sum(per_step) / len(per_step), 4)},
         "gflops_numeric_only": round(2.0 * flops / (ms_num / 1e3) / 1e9, 3),
         "output_nnz_per_s": round(nnz_c / (ms_step / 1e3), 1),
         "roofline": {"bound": "hbm", "kernel": "numeric phase (k_numeric + k_numeric_light + k_split_finalize)",
