@@ -59,7 +59,8 @@ constexpr int kDenseFetch = 16;           // rows a dense-row worker takes per f
 constexpr int kSplitWaves = 4;            // wavefronts per chunk workgroup
 constexpr int kSplitEntries = kSplitWaves * kWave;  // A entries per chunk (a wavefront stages 64)
 constexpr int kRankWords = 256;           // up to this many bitmap words (d <= 8192): narrow kernels
-constexpr int kSplitSymBlocks = 2048;     // symbolic chunk workers (chunks are taken from a counter)
+constexpr int kSplitSymBlocks = 2048;     // symbolic chunk workgroups (chunks are taken from a counter)
+constexpr int kSplitFetch = 4;            // chunks a symbolic chunk workgroup takes per fetch
 static_assert(kHashMaxD <= kSymSlots * 32, "the d-bit bitmap of a row must fit a wavefront's LDS words");
 
 __device__ __forceinline__ uint32_t hslot(int32_t j, uint32_t mask) { return ((uint32_t)j * 2654435761u) & mask; }
@@ -232,30 +233,9 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr
   int* pref = pref_s[wave];
   const bool masked = hm.rp || hm.bits;
   for (int64_t row = (int64_t)blockIdx.x * kHashWaves + wave; row < pr.n; row += (int64_t)gridDim.x * kHashWaves) {
+    if (hs.slot_of_row[row] >= 0) continue;  // a split row (k_hash_split_claim): the count pass writes cnt
     const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
     const long long fl = pr.flops[row];  // from k_hash_flops
-    if (fl >= hs.split_flops && hs.cap > 0) {
-      int slot = 0;
-      if (lane == 0) slot = atomicAdd(&hs.ctr->hash_split_rows, 1);
-      slot = __shfl(slot, 0, kWave);
-      if (slot < hs.cap) {
-        // chunks of this row: (slot, first A entry); the count pass writes cnt
-        const int nch = (p1 - p0 + kSplitEntries - 1) / kSplitEntries;
-        int first = 0;
-        if (lane == 0) {
-          first = atomicAdd(&hs.ctr->hash_split_items, nch);
-          hs.rows[slot] = (int32_t)row;
-          hs.slot_of_row[row] = slot;
-        }
-        first = __shfl(first, 0, kWave);
-        for (int c = lane; c < nch; c += kWave) hs.items[first + c] = make_int2(slot, p0 + c * kSplitEntries);
-        const int words = (pr.d + 31) >> 5;
-        uint32_t* gb = hs.bits + (int64_t)slot * words;
-        for (int t = lane; t < words; t += kWave) gb[t] = 0u;
-        continue;
-      }
-    }
-    if (lane == 0) hs.slot_of_row[row] = -1;
     if (fl == 0) {
       if (lane == 0) cnt[row] = 0;
       continue;
@@ -321,15 +301,12 @@ __device__ __forceinline__ bool split_direct(const Problem& pr, int row, int cnt
 // A split row with more outputs than that array: written window by window.
 __device__ __forceinline__ bool split_windowed(const Problem& pr, int cnt) { return cnt > split_lds(pr); }
 
-// Products per row (one wavefront per row) and the histogram of the rows
-// that may be split.
-__global__ __launch_bounds__(kHashWaves * kWave) void k_hash_flops(Problem pr, int32_t* hist) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-  const int64_t row = (int64_t)blockIdx.x * kHashWaves + wave;
-  if (row >= pr.n) return;
-  const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
+// Sum over A entries [p0, p1) of their B row lengths, one wavefront, U
+// entries per lane in flight.
+template <int U>
+__device__ __forceinline__ long long wave_row_flops(const Problem& pr, int p0, int p1) {
+  const int lane = threadIdx.x & (kWave - 1);
   long long fl = 0;
-  constexpr int U = 8;  // A entries per lane in flight (hub rows are long)
   for (int p = p0 + lane; p < p1; p += U * kWave) {
     int k[U];
 #pragma unroll
@@ -338,30 +315,101 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_flops(Problem pr, i
     for (int u = 0; u < U; ++u)
       if (k[u] >= 0) fl += pr.brp[k[u] + 1] - pr.brp[k[u]];
   }
-  fl = wave_sum_ll(fl);
-  if (lane == 0) {
-    pr.flops[row] = fl;
-    if (fl >= kHashSplitMin) atomicAdd(&hist[63 - __clzll(fl)], 1);
+  return wave_sum_ll(fl);
+}
+
+// Products per row (one wavefront per row). A hub row is a serial chain of
+// its wavefront's loads, so long rows keep more of them in flight.
+__global__ __launch_bounds__(kHashWaves * kWave) void k_hash_flops(Problem pr) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
+  const int64_t row = (int64_t)blockIdx.x * kHashWaves + wave;
+  if (row >= pr.n) return;
+  const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
+  const long long fl = p1 - p0 > 2048 ? wave_row_flops<32>(pr, p0, p1) : wave_row_flops<8>(pr, p0, p1);
+  if (lane == 0) pr.flops[row] = fl;
+}
+
+// Histogram of floor(log2(flops_i)) over rows with at least kHashSplitMin
+// products: LDS counts per workgroup, then one global add per non-zero bin
+// (global atomics on a few addresses from every row would serialize).
+constexpr int kHistBlocks = 256;
+__global__ __launch_bounds__(256) void k_hash_hist(Problem pr, int32_t* hist) {
+  __shared__ int32_t h[64];
+  if (threadIdx.x < 64) h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < pr.n;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const long long fl = pr.flops[row];
+    if (fl >= kHashSplitMin) atomicAdd(&h[63 - __clzll(fl)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// Split slots and chunks for the rows with at least split_flops products.
+// A workgroup takes 256 rows at a time and reserves their slots, then the
+// chunks of those that got one (below cap), with one global add each (global
+// atomics from every row on one counter would serialize). Every row's
+// slot_of_row is written: its slot, or -1.
+__global__ __launch_bounds__(256) void k_hash_split_claim(Problem pr, HashSplit hs) {
+  __shared__ int n_rows_s, n_items_s, base_rows_s, base_items_s;
+  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < pr.n; r0 += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x == 0) {
+      n_rows_s = 0;
+      n_items_s = 0;
+    }
+    __syncthreads();
+    const int64_t row = r0 + threadIdx.x;
+    const bool cand = row < pr.n && hs.cap > 0 && pr.flops[row] >= hs.split_flops;
+    int local = -1;
+    if (cand) local = atomicAdd(&n_rows_s, 1);
+    __syncthreads();
+    if (threadIdx.x == 0 && n_rows_s > 0) base_rows_s = atomicAdd(&hs.ctr->hash_split_rows, n_rows_s);
+    __syncthreads();
+    const int slot = cand ? base_rows_s + local : -1;
+    const bool split = cand && slot < hs.cap;
+    int p0 = 0, nch = 0, item_local = 0;
+    if (split) {
+      p0 = pr.arp[row];
+      nch = (pr.arp[row + 1] - p0 + kSplitEntries - 1) / kSplitEntries;
+      item_local = atomicAdd(&n_items_s, nch);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && n_items_s > 0) base_items_s = atomicAdd(&hs.ctr->hash_split_items, n_items_s);
+    __syncthreads();
+    if (row < pr.n) hs.slot_of_row[row] = split ? slot : -1;
+    if (split) {
+      hs.rows[slot] = (int32_t)row;
+      const int first = base_items_s + item_local;
+      for (int c = 0; c < nch; ++c) hs.items[first + c] = make_int2(slot, p0 + c * kSplitEntries);
+    }
+    __syncthreads();  // the LDS counters are reset for the next rows
   }
 }
 
-// Symbolic chunks of split rows. The workers take chunks from a counter
-// until the chunk list (written by k_hash_symbolic) is used up.
+// Symbolic chunks of split rows. Workgroups take kSplitFetch chunks at a
+// time from a counter until the chunk list is used up (chunks differ in
+// products, so a static stride would leave some workgroups the heavy ones).
 template <int WC>
 __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_symbolic(Problem pr, HashMask hm, HashSplit hs) {
   __shared__ uint32_t bm[WC];
   __shared__ int start_s[kSplitWaves][kWave], pref_s[kSplitWaves][kWave + 1];
-  __shared__ int item_s;
+  __shared__ int fetch_s;
   const int wave = threadIdx.x >> 6;
   const int words = (pr.d + 31) >> 5;
   const bool masked = hm.rp || hm.bits;
   const int n_items = hs.ctr->hash_split_items;
-  for (;;) {
-    if (threadIdx.x == 0) item_s = atomicAdd(&hs.ctr->hash_split_next, 1);
+  for (int it = 0, it_end = 0;; ++it) {
+    if (it == it_end) {
+      __syncthreads();  // every thread has read fetch_s
+      if (threadIdx.x == 0) fetch_s = atomicAdd(&hs.ctr->hash_split_next, kSplitFetch);
+      __syncthreads();
+      it = fetch_s;
+      it_end = min(it + kSplitFetch, n_items);
+    }
+    if (it >= n_items) break;
     for (int t = threadIdx.x; t < words; t += blockDim.x) bm[t] = 0u;
     __syncthreads();
-    const int it = item_s;
-    if (it >= n_items) break;
     const int2 itm = hs.items[it];
     const int row = hs.rows[itm.x];
     const int a1 = min(itm.y + kSplitEntries, pr.arp[row + 1]);
@@ -384,50 +432,71 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_symbolic(Pro
   }
 }
 
-// Per split row: output count (cnt), outputs before each bitmap word (pref)
-// and the row's first accumulator (acc_off).
+// Per split row: output count (cnt), outputs before each bitmap word (pref),
+// the row's first accumulator (acc_off) and its output windows. A workgroup
+// takes kCountSlots consecutive slots and reserves their accumulators and
+// windows with one global add each.
+constexpr int kCountSlots = 16;
 __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_count(Problem pr, HashSplit hs, int32_t* cnt) {
   __shared__ int wsum[kSplitWaves];
+  __shared__ int acc_need[kCountSlots], win_need[kCountSlots];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
   const int words = (pr.d + 31) >> 5;
   const int nsplit = min(hs.ctr->hash_split_rows, hs.cap);
-  for (int slot = blockIdx.x; slot < nsplit; slot += gridDim.x) {
-    const uint32_t* gb = hs.bits + (int64_t)slot * words;
-    int32_t* gp = hs.pref + (int64_t)slot * words;
-    int run = 0;
-    for (int w0 = 0; w0 < words; w0 += kSplitWaves * kWave) {
-      const int w = w0 + threadIdx.x;
-      const int c = w < words ? __popc(gb[w]) : 0;
-      int incl = c;
+  for (int s0 = blockIdx.x * kCountSlots; s0 < nsplit; s0 += gridDim.x * kCountSlots) {
+    const int s1 = min(s0 + kCountSlots, nsplit);
+    for (int slot = s0; slot < s1; ++slot) {
+      const uint32_t* gb = hs.bits + (int64_t)slot * words;
+      int32_t* gp = hs.pref + (int64_t)slot * words;
+      int run = 0;
+      for (int w0 = 0; w0 < words; w0 += kSplitWaves * kWave) {
+        const int w = w0 + threadIdx.x;
+        const int c = w < words ? __popc(gb[w]) : 0;
+        int incl = c;
 #pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int y = __shfl_up(incl, o, kWave);
-        if (lane >= o) incl += y;
-      }
-      if (lane == kWave - 1) wsum[wave] = incl;
-      __syncthreads();
-      int before = run, tot = 0;
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int y = __shfl_up(incl, o, kWave);
+          if (lane >= o) incl += y;
+        }
+        if (lane == kWave - 1) wsum[wave] = incl;
+        __syncthreads();
+        int before = run, tot = 0;
 #pragma unroll
-      for (int v = 0; v < kSplitWaves; ++v) {
-        if (v < wave) before += wsum[v];
-        tot += wsum[v];
+        for (int v = 0; v < kSplitWaves; ++v) {
+          if (v < wave) before += wsum[v];
+          tot += wsum[v];
+        }
+        if (w < words) gp[w] = before + incl - c;
+        run += tot;
+        __syncthreads();
       }
-      if (w < words) gp[w] = before + incl - c;
-      run += tot;
-      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int row = hs.rows[slot];
+        cnt[row] = run;
+        const int lc = split_lds(pr);
+        const bool windowed = split_windowed(pr, run);
+        win_need[slot - s0] = windowed ? (run + lc - 1) / lc : 0;
+        acc_need[slot - s0] = windowed || split_direct(pr, row, run) ? 0 : run;
+      }
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
-      const int row = hs.rows[slot];
-      cnt[row] = run;
-      if (split_windowed(pr, run)) {
-        const int lc = split_lds(pr), nw = (run + lc - 1) / lc;
-        const int first = atomicAdd(&hs.ctr->hash_win_items, nw);
-        for (int w = 0; w < nw; ++w) hs.wins[first + w] = make_int2(slot, w);
-        hs.acc_off[slot] = 0;
-      } else {
-        hs.acc_off[slot] = split_direct(pr, row, run) ? 0 : atomicAdd(&hs.ctr->hash_split_acc, run);
+      int a = 0, w = 0;
+      for (int i = 0; i < s1 - s0; ++i) {
+        a += acc_need[i];
+        w += win_need[i];
+      }
+      int ao = a ? atomicAdd(&hs.ctr->hash_split_acc, a) : 0;
+      int wo = w ? atomicAdd(&hs.ctr->hash_win_items, w) : 0;
+      for (int i = 0; i < s1 - s0; ++i) {
+        const int slot = s0 + i;
+        hs.acc_off[slot] = acc_need[i] ? ao : 0;
+        ao += acc_need[i];
+        for (int k = 0; k < win_need[i]; ++k) hs.wins[wo + k] = make_int2(slot, k);
+        wo += win_need[i];
       }
     }
+    __syncthreads();
   }
 }
 
@@ -982,7 +1051,8 @@ int64_t hash_split_item_cap(int64_t a_nnz, int64_t cap) {
 int launch_hash_flops(const Problem& pr, int32_t* hist, hipStream_t st) {
   if (pr.n == 0) return TSSPGEMM_OK;
   const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;
-  k_hash_flops<<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, hist);
+  k_hash_flops<<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr);
+  k_hash_hist<<<kHistBlocks, 256, 0, st>>>(pr, hist);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }
@@ -990,6 +1060,18 @@ int launch_hash_flops(const Problem& pr, int32_t* hist, hipStream_t st) {
 int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& hs, bool small_rows_only,
                          int32_t* cnt, int32_t* err, hipStream_t st) {
   if (pr.n == 0) return TSSPGEMM_OK;
+  // every row's split slot (or -1) first: the short-row kernel skips split rows
+  if (hs.cap > 0) {
+    const int64_t words = (pr.d + 31) >> 5;
+    int rc = launch_zero_bytes(hs.bits, (size_t)hs.cap * words * 4, st);
+    if (rc) return rc;
+  }
+  {
+    int64_t gcl = (pr.n + 255) / 256;
+    if (gcl > 1024) gcl = 1024;
+    k_hash_split_claim<<<(unsigned)gcl, 256, 0, st>>>(pr, hs);
+    TSS_CHECK_LAUNCH();
+  }
   const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;
   if (!small_rows_only)
     k_hash_symbolic<kSymSlots><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, m, hs, cnt, err);
@@ -1004,7 +1086,8 @@ int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& 
       k_hash_split_symbolic<kRankWords><<<kSplitSymBlocks, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
     else
       k_hash_split_symbolic<kSymSlots><<<kSplitSymBlocks, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
-    const int64_t gc = hs.cap < kSplitSymBlocks ? hs.cap : kSplitSymBlocks;
+    int64_t gc = (hs.cap + kCountSlots - 1) / kCountSlots;
+    if (gc > 4096) gc = 4096;
     k_hash_split_count<<<(unsigned)gc, kSplitWaves * kWave, 0, st>>>(pr, hs, cnt);
     TSS_CHECK_LAUNCH();
   }
