@@ -152,6 +152,8 @@ static HashSplit hash_split_view(Plan* p) {
   hs.acc_off = (int32_t*)p->hs_off.p;
   hs.acc = p->hs_acc.p;
   hs.wins = (int2*)p->hs_wins.p;
+  hs.cls_rows = (int32_t*)p->hs_cls.p;
+  hs.cls_cnt = (int32_t*)p->hs_cls_cnt.p;
   hs.cap = (int32_t)p->hs_cap;
   hs.split_flops = p->hs_split_flops;
   hs.ctr = (Counters*)p->ctr.p;
@@ -224,7 +226,8 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   if ((rc = p->hs_slot.ensure((size_t)n * 4)) || (rc = p->hs_rows.ensure((size_t)p->hs_cap * 4)) ||
       (rc = p->hs_items.ensure((size_t)item_cap * 8)) || (rc = p->hs_bits.ensure((size_t)p->hs_cap * words * 4)) ||
       (rc = p->hs_pref.ensure((size_t)p->hs_cap * words * 4)) || (rc = p->hs_off.ensure((size_t)p->hs_cap * 4)) ||
-      (rc = p->hs_wins.ensure((size_t)hash_split_window_cap(p->hs_cap, d < 1 ? 1 : d) * 8)))
+      (rc = p->hs_wins.ensure((size_t)hash_split_window_cap(p->hs_cap, d < 1 ? 1 : d) * 8)) ||
+      (rc = p->hs_cls.ensure((size_t)n * 16)) || (rc = p->hs_cls_cnt.ensure(16)))
     return rc;
   const HashSplit hs = hash_split_view(p);
   // every candidate split: the rows left have fewer than kHashSplitMin products
@@ -234,7 +237,9 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   pr.cbits = nullptr;  // counts come from cnt
   if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
   TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  if (n > 0) TSS_HIP(hipMemcpyAsync(p->hs_cls_host, p->hs_cls_cnt.p, 16, hipMemcpyDeviceToHost, st));
   TSS_HIP(hipStreamSynchronize(st));
+  if (n == 0) p->hs_cls_host[0] = p->hs_cls_host[1] = p->hs_cls_host[2] = p->hs_cls_host[3] = 0;
   const Counters& h = *p->host_ctr;
   if (h.hash_error) {
     set_error("hash accumulator: inconsistent row table");
@@ -467,8 +472,8 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   if (p->hash) {
     if ((rc = p->hnext.ensure(64))) return rc;
     return launch_hash_numeric(p->sr, pr, p->hmask, hash_split_view(p), (int32_t)p->hs_rows_n,
-                               (int32_t)p->hs_items_n, p->hs_acc_n, (int32_t)p->hs_win_n, !p->hs_all_split,
-                               p->hstrips.p,
+                               (int32_t)p->hs_items_n, p->hs_acc_n, (int32_t)p->hs_win_n, p->hs_cls_host,
+                               !p->hs_all_split, p->hstrips.p,
                                &((Counters*)p->ctr.p)->hash_error, (int32_t*)p->hnext.p, st);
   }
   if (!vals) return launch_emit_pattern(pr, st);

@@ -155,6 +155,8 @@ struct HashSplit {
   int32_t* pref;         // cap x words: outputs of the row before each word
   int32_t* acc_off;      // cap: first accumulator of the row
   int2* wins;            // output windows of rows wider than a chunk's LDS array: (slot, window)
+  int32_t* cls_rows;     // 4 x n: rows of each LDS table size class (outputs <= 64, 128, 256, 512)
+  int32_t* cls_cnt;      // 4: rows in each class
   void* acc;             // accumulators (FP64, or INT32 for the integer semiring)
   int32_t cap;           // split slots (0: no row is split)
   int64_t split_flops;   // rows with at least this many products are split rows
@@ -178,9 +180,10 @@ int64_t hash_dense_workers(int64_t d);
 // split_items and split_acc: the split counts the symbolic phase ended with;
 // long_rows: some row that is not split may have more outputs than the LDS
 // tables hold (else the long-row kernel is not launched)
+// cls_n: rows of each table size class (the counts hs.cls_cnt ended with)
 int launch_hash_numeric(int sr, const Problem& pr, const HashMask& m, const HashSplit& hs, int32_t split_rows,
-                        int32_t split_items, int64_t split_acc, int32_t win_items, bool long_rows, void* strips,
-                        int32_t* err, int32_t* next, hipStream_t st);
+                        int32_t split_items, int64_t split_acc, int32_t win_items, const int32_t* cls_n,
+                        bool long_rows, void* strips, int32_t* err, int32_t* next, hipStream_t st);
 // Rows at or above kHashSplitMin products in the histogram.
 int64_t hash_split_candidates(const int32_t* hist);
 

@@ -500,6 +500,30 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_count(Proble
   }
 }
 
+// Rows left to the LDS tables (not split, 1 to kHashNumMax outputs) into the
+// row list of their size class; reservations per 256 rows and class.
+__global__ __launch_bounds__(256) void k_hash_table_bins(Problem pr, HashSplit hs, const int32_t* cnt) {
+  __shared__ int n_s[4], base_s[4];
+  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x; r0 < pr.n; r0 += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x < 4) n_s[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t row = r0 + threadIdx.x;
+    int c = -1, local = 0;
+    if (row < pr.n && hs.slot_of_row[row] < 0) {
+      const int nz = cnt[row];
+      if (nz > 0 && nz <= kHashNumMax) {
+        c = nz <= 64 ? 0 : nz <= 128 ? 1 : nz <= 256 ? 2 : 3;
+        local = atomicAdd(&n_s[c], 1);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && n_s[threadIdx.x]) base_s[threadIdx.x] = atomicAdd(&hs.cls_cnt[threadIdx.x], n_s[threadIdx.x]);
+    __syncthreads();
+    if (c >= 0) hs.cls_rows[(int64_t)c * pr.n + base_s[c] + local] = (int32_t)row;
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- numeric
 
 // V = float / int32_t (values) or char (pattern only, OR-AND).
@@ -550,28 +574,32 @@ __device__ __forceinline__ void wave_bitonic(uint32_t* key, Acc* val, int n2) {
 // output): a table of at most TSZ slots per wavefront.
 // RANK (d <= 32 x kRankWords): the row is put in column order by each
 // column's rank in an LDS bitmap of the row (no sort).
-template <typename V, int TSZ, bool RANK>
-__global__ __launch_bounds__(kHashWaves * kWave) void k_hash_numeric_table(Problem pr, HashMask hm,
-                                                                           const int32_t* slot_of_row,
-                                                                           int32_t* err) {
+// The rows come from the class's row list (k_hash_table_bins), W wavefronts
+// per workgroup, one row each.
+template <typename V, int TSZ, bool RANK, int W>
+__global__ __launch_bounds__(W * kWave) void k_hash_numeric_table(Problem pr, HashMask hm, const int32_t* list,
+                                                                  int32_t count, int32_t* err) {
   using Acc = typename HashAcc<V>::type;
   static_assert(TSZ >= 2 * kWave && TSZ <= kNumSlots, "table class");
   constexpr int RW = RANK ? kRankWords : 1;
-  __shared__ uint32_t keys_s[kHashWaves][TSZ];
-  __shared__ Acc vals_s[kHashWaves][TSZ];
-  __shared__ int start_s[kHashWaves][kWave], pref_s[kHashWaves][kWave + 1];
-  __shared__ V aval_s[kHashWaves][kWave];
-  __shared__ uint32_t rbm_s[kHashWaves][RW];
-  __shared__ uint16_t rpw_s[kHashWaves][RW];
-  constexpr int lo = TSZ == 2 * kWave ? 0 : TSZ / 4;
+  __shared__ uint32_t keys_s[W][TSZ];
+  __shared__ Acc vals_s[W][TSZ];
+  __shared__ int start_s[W][kWave], pref_s[W][kWave + 1];
+  __shared__ V aval_s[W][kWave];
+  __shared__ uint32_t rbm_s[W][RW];
+  __shared__ uint16_t rpw_s[W][RW];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
   uint32_t* keys = keys_s[wave];
   Acc* vals = vals_s[wave];
   const bool masked = hm.rp || hm.bits;
   const uint64_t below = lane == 0 ? 0ull : ~0ull >> (kWave - lane);
-  for (int64_t row = (int64_t)blockIdx.x * kHashWaves + wave; row < pr.n; row += (int64_t)gridDim.x * kHashWaves) {
+  for (int64_t i = (int64_t)blockIdx.x * W + wave; i < count; i += (int64_t)gridDim.x * W) {
+    const int64_t row = list[i];
     const int c0 = pr.crp[row], nnz = pr.crp[row + 1] - c0;
-    if (nnz <= lo || nnz > TSZ / 2 || slot_of_row[row] >= 0) continue;
+    if (nnz <= 0 || nnz > TSZ / 2) {  // not this class: the pattern changed since the symbolic call
+      if (lane == 0) atomicOr(err, 1);
+      continue;
+    }
     const uint32_t tsz = pow2_at_least(2u * (uint32_t)nnz);  // <= TSZ
     for (uint32_t t = lane; t < tsz; t += kWave) {
       keys[t] = kEmpty;
@@ -1091,6 +1119,12 @@ int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& 
     k_hash_split_count<<<(unsigned)gc, kSplitWaves * kWave, 0, st>>>(pr, hs, cnt);
     TSS_CHECK_LAUNCH();
   }
+  int rc = launch_zero_bytes(hs.cls_cnt, 16, st);
+  if (rc) return rc;
+  int64_t gb = (pr.n + 255) / 256;
+  if (gb > 1024) gb = 1024;
+  k_hash_table_bins<<<(unsigned)gb, 256, 0, st>>>(pr, hs, cnt);
+  TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }
 
@@ -1102,24 +1136,36 @@ int64_t hash_dense_workers(int64_t d) {
   return w < kHashWaves ? kHashWaves : w;
 }
 
+template <typename V, int TSZ, bool RANK, int W>
+static void table_class(const Problem& pr, const HashMask& h, const HashSplit& hs, int c, const int32_t* cls_n,
+                        int32_t* err, hipStream_t st) {
+  if (cls_n[c] == 0) return;
+  const unsigned g = (unsigned)((cls_n[c] + W - 1) / W);
+  k_hash_numeric_table<V, TSZ, RANK, W><<<g, W * kWave, 0, st>>>(pr, h, hs.cls_rows + (int64_t)c * pr.n, cls_n[c],
+                                                                 err);
+}
+
+// One launch per size class, over that class's rows only. Fewer wavefronts
+// share a workgroup as the tables grow, so LDS is allocated in smaller
+// pieces (more resident wavefronts per CU).
 template <typename V, bool RANK>
-static void table_classes(const Problem& pr, const HashMask& h, const HashSplit& hs, int64_t g, int32_t* err,
-                          hipStream_t st) {
-  k_hash_numeric_table<V, 128, RANK><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, err);
-  k_hash_numeric_table<V, 256, RANK><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, err);
-  k_hash_numeric_table<V, 512, RANK><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, err);
-  k_hash_numeric_table<V, kNumSlots, RANK><<<(unsigned)g, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, err);
+static void table_classes(const Problem& pr, const HashMask& h, const HashSplit& hs, const int32_t* cls_n,
+                          int32_t* err, hipStream_t st) {
+  table_class<V, 128, RANK, 4>(pr, h, hs, 0, cls_n, err, st);
+  table_class<V, 256, RANK, 4>(pr, h, hs, 1, cls_n, err, st);
+  table_class<V, 512, RANK, 2>(pr, h, hs, 2, cls_n, err, st);
+  table_class<V, kNumSlots, RANK, 1>(pr, h, hs, 3, cls_n, err, st);
 }
 
 template <typename V, typename Acc>
 static void hash_numeric_kernels(const Problem& pr, const HashMask& h, const HashSplit& hs, int32_t split_rows,
-                                 int32_t split_items, int32_t win_items, int64_t g, int64_t gd, void* strips,
-                                 int32_t* err, int32_t* next, hipStream_t st) {
+                                 int32_t split_items, int32_t win_items, const int32_t* cls_n, int64_t gd,
+                                 void* strips, int32_t* err, int32_t* next, hipStream_t st) {
   const bool narrow = ((pr.d + 31) >> 5) <= kRankWords;
   if (narrow) {
-    table_classes<V, true>(pr, h, hs, g, err, st);
+    table_classes<V, true>(pr, h, hs, cls_n, err, st);
   } else {
-    table_classes<V, false>(pr, h, hs, g, err, st);
+    table_classes<V, false>(pr, h, hs, cls_n, err, st);
   }
   if (gd > 0)
     k_hash_numeric_dense<V><<<(unsigned)gd, kHashWaves * kWave, 0, st>>>(pr, h, hs.slot_of_row, (Acc*)strips, err,
@@ -1145,10 +1191,10 @@ static void hash_numeric_kernels(const Problem& pr, const HashMask& h, const Has
 }
 
 int launch_hash_numeric(int sr, const Problem& pr, const HashMask& h, const HashSplit& hs, int32_t split_rows,
-                        int32_t split_items, int64_t split_acc, int32_t win_items, bool long_rows, void* strips,
-                        int32_t* err, int32_t* next, hipStream_t st) {
+                        int32_t split_items, int64_t split_acc, int32_t win_items, const int32_t* cls_n,
+                        bool long_rows, void* strips, int32_t* err, int32_t* next, hipStream_t st) {
   if (pr.n == 0) return TSSPGEMM_OK;
-  const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;  // table rows: one wavefront per row
+  const int64_t g = (pr.n + kHashWaves - 1) / kHashWaves;  // the long-row workers never outnumber the rows
   int64_t gd = long_rows ? hash_dense_workers(pr.d) / kHashWaves : 0;  // long-row workers, if any row needs them
   if (gd > g) gd = g;
   int rc;
@@ -1157,13 +1203,13 @@ int launch_hash_numeric(int sr, const Problem& pr, const HashMask& h, const Hash
   if (sr != TSSPGEMM_OR_AND && split_acc > 0 && (rc = launch_zero_bytes(hs.acc, (size_t)split_acc * acc_bytes, st)))
     return rc;
   if (sr == TSSPGEMM_PLUS_TIMES_F32)
-    hash_numeric_kernels<float, double>(pr, h, hs, split_rows, split_items, win_items, g, gd, strips, err, next,
-                                        st);
+    hash_numeric_kernels<float, double>(pr, h, hs, split_rows, split_items, win_items, cls_n, gd, strips, err,
+                                        next, st);
   else if (sr == TSSPGEMM_PLUS_TIMES_I32)
-    hash_numeric_kernels<int32_t, int32_t>(pr, h, hs, split_rows, split_items, win_items, g, gd, strips, err,
-                                          next, st);
+    hash_numeric_kernels<int32_t, int32_t>(pr, h, hs, split_rows, split_items, win_items, cls_n, gd, strips,
+                                          err, next, st);
   else
-    hash_numeric_kernels<char, int32_t>(pr, h, hs, split_rows, split_items, win_items, g, gd, strips, err,
+    hash_numeric_kernels<char, int32_t>(pr, h, hs, split_rows, split_items, win_items, cls_n, gd, strips, err,
                                        next, st);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
