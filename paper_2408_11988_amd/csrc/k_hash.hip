@@ -61,6 +61,7 @@ constexpr int kSplitEntries = kSplitWaves * kWave;  // A entries per chunk (a wa
 constexpr int kRankWords = 256;           // up to this many bitmap words (d <= 8192): narrow kernels
 constexpr int kSplitSymBlocks = 2048;     // symbolic chunk workgroups (chunks are taken from a counter)
 constexpr int kSplitFetch = 4;            // chunks a symbolic chunk workgroup takes per fetch
+constexpr int kWinWaves = 4;              // wavefronts per output-window workgroup
 static_assert(kHashMaxD <= kSymSlots * 32, "the d-bit bitmap of a row must fit a wavefront's LDS words");
 
 __device__ __forceinline__ uint32_t hslot(int32_t j, uint32_t mask) { return ((uint32_t)j * 2654435761u) & mask; }
@@ -127,25 +128,27 @@ __device__ __forceinline__ int stage_window(const Problem& pr, int base, int nb,
   T a = T(0);
   if (lane < nb) {
     const int k = pr.aci[base + lane];
-    int lo = pr.brp[k], hi = pr.brp[k + 1];
-    int l = lo, h = hi;  // first entry >= c_lo
-    while (l < h) {
-      const int m = (l + h) >> 1;
-      if (pr.bci[m] < c_lo)
-        l = m + 1;
-      else
-        h = m;
+    // first entries >= c_lo and >= c_hi, the two searches side by side (two
+    // loads in flight per step)
+    int l0 = pr.brp[k], h0 = pr.brp[k + 1], l1 = l0, h1 = h0;
+    while (l0 < h0 || l1 < h1) {
+      const int m0 = (l0 + h0) >> 1, m1 = (l1 + h1) >> 1;
+      const int v0 = l0 < h0 ? pr.bci[m0] : 0, v1 = l1 < h1 ? pr.bci[m1] : 0;
+      if (l0 < h0) {
+        if (v0 < c_lo)
+          l0 = m0 + 1;
+        else
+          h0 = m0;
+      }
+      if (l1 < h1) {
+        if (v1 < c_hi)
+          l1 = m1 + 1;
+        else
+          h1 = m1;
+      }
     }
-    q0 = l;
-    h = hi;  // first entry >= c_hi
-    while (l < h) {
-      const int m = (l + h) >> 1;
-      if (pr.bci[m] < c_hi)
-        l = m + 1;
-      else
-        h = m;
-    }
-    len = l - q0;
+    q0 = l0;
+    len = l1 - l0;
     a = ((const T*)pr.aval)[base + lane];
   }
   int incl = len;
@@ -916,15 +919,15 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_numeric(Prob
 // each A entry's products in the window are one range of its B row, found by
 // binary search. Those products are added in LDS, then the window is written.
 template <typename V, int WC>
-__global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_window(Problem pr, HashMask hm, HashSplit hs,
-                                                                           int32_t* err) {
+__global__ __launch_bounds__(kWinWaves * kWave) void k_hash_split_window(Problem pr, HashMask hm, HashSplit hs,
+                                                                         int32_t* err) {
   using Acc = typename HashAcc<V>::type;
   constexpr int LC = split_lds_outputs(WC);
   __shared__ uint32_t bm[WC];
   __shared__ int32_t bp[WC];
   __shared__ Acc acc[LC];
-  __shared__ int start_s[kSplitWaves][kWave], pref_s[kSplitWaves][kWave + 1];
-  __shared__ V aval_s[kSplitWaves][kWave];
+  __shared__ int start_s[kWinWaves][kWave], pref_s[kWinWaves][kWave + 1];
+  __shared__ V aval_s[kWinWaves][kWave];
   __shared__ int cols_s[2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
   const int words = (pr.d + 31) >> 5;
@@ -958,7 +961,7 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_window(Probl
   const bool masked = hm.rp || hm.bits;
   const V* __restrict__ bval = (const V*)pr.bval;
   const int p1 = pr.arp[row + 1];
-  for (int base = pr.arp[row] + wave * kWave; base < p1; base += kSplitWaves * kWave) {
+  for (int base = pr.arp[row] + wave * kWave; base < p1; base += kWinWaves * kWave) {
     const int nb = min(kWave, p1 - base);
     const int total = stage_window(pr, base, nb, c_lo, c_hi, start_s[wave], pref_s[wave], aval_s[wave]);
     constexpr int U = 4;  // products per lane per step, loads first
@@ -1181,11 +1184,11 @@ static void hash_numeric_kernels(const Problem& pr, const HashMask& h, const Has
       k_hash_split_numeric<V, kSymSlots><<<gi, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
     const unsigned gw = (unsigned)win_items;
     if (win_items > 0 && wc == 64)
-      k_hash_split_window<V, 64><<<gw, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+      k_hash_split_window<V, 64><<<gw, kWinWaves * kWave, 0, st>>>(pr, h, hs, err);
     else if (win_items > 0 && wc == kRankWords)
-      k_hash_split_window<V, kRankWords><<<gw, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+      k_hash_split_window<V, kRankWords><<<gw, kWinWaves * kWave, 0, st>>>(pr, h, hs, err);
     else if (win_items > 0)
-      k_hash_split_window<V, kSymSlots><<<gw, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+      k_hash_split_window<V, kSymSlots><<<gw, kWinWaves * kWave, 0, st>>>(pr, h, hs, err);
   }
   if (split_rows > 0) k_hash_split_emit<V><<<(unsigned)split_rows, kSplitWaves * kWave, 0, st>>>(pr, hs);
 }
