@@ -2,46 +2,54 @@
 // accumulator no longer fits the nearest cache level and a hash table is used
 // instead).
 //
-// Both phases give one wavefront to a row and walk the row's products as one
-// flat list: 64 A entries are staged at a time (their B row start, length and
-// value), an inclusive scan of the lengths lets lane t find its product by a
-// binary search over the staged prefix sums, so every lane has work however
-// short the B rows are.
+// Products are walked as one flat list per group of A entries: 64 A entries
+// are staged at a time (their B row start, length and value), an inclusive
+// scan of the lengths lets lane t find its product by a binary search over
+// the staged prefix sums, so every lane has work however short the B rows
+// are. Lanes issue the B loads of kGather products before using any.
 //
-// Symbolic: the distinct columns of the row (minus masked ones) are counted
-// in an LDS open-addressing set (linear probing, column as key) of a power of
-// two >= 2 min(d, flops_i) slots, or, when that exceeds the table, in an LDS
-// bitmap of d bits.
-// Numeric: rows with at most kHashNumMax outputs accumulate in an LDS table of
-// (column, sum) slots sized from the exact output count (one launch per table
-// size class, so short rows do not hold the LDS of long ones); the occupied
-// slots are compacted to the front and sorted by key (bitonic, in LDS), which
-// gives the row in ascending columns. Longer rows
-// mark an LDS bitmap and add into a private d-wide strip in global memory;
-// the row is written by walking the bitmap (ascending columns) and the strip
-// is cleared behind it.
+// First, products per row (k_hash_flops) and their log2 histogram
+// (k_hash_hist). Rows with at least the threshold hash_split_choose takes
+// from it are split rows: power-law inputs have hubs whose product lists
+// would keep one wavefront busy for the whole launch. The threshold is
+// kHashSplitMin unless the rows above it would need more bitmap memory than
+// the split budget; then it is the least power of two whose rows fit, so the
+// longest rows are always split.
+//
+// Short rows (below the threshold), one wavefront each:
+// - symbolic: the distinct columns (minus masked ones) are counted in an LDS
+//   open-addressing set (linear probing, column as key) of a power of two
+//   >= 2 min(d, flops_i) slots, or, when that exceeds the set, in an LDS
+//   bitmap of d bits;
+// - numeric: rows with at most kHashNumMax outputs accumulate in an LDS table
+//   of (column, sum) slots sized from the exact output count, one launch per
+//   table size class over that class's row list (k_hash_table_bins). The row
+//   is put in column order by rank in an LDS bitmap of the row (d <= 32
+//   kRankWords), or by compacting the occupied slots and sorting them
+//   (bitonic, in LDS). Rows with more outputs (only rows left unsplit by a
+//   forced slot bound) mark an LDS bitmap and add into a private d-wide strip
+//   in global memory; the row is written by walking the bitmap and the strip
+//   is cleared behind it.
+//
+// Split rows: chunks of kSplitEntries A entries, one workgroup each. Symbolic
+// chunks OR their columns into the row's global bitmap (an LDS copy first,
+// then one atomic OR per non-zero word); a count pass gives the row's output
+// count and, per bitmap word, the outputs before it. Numeric chunks add each
+// product at its column's rank in that bitmap, into an LDS array of the
+// row's outputs (then one global atomic add per output); an emit pass writes
+// the row in column order. A row of one chunk is written by its chunk
+// directly. A row with more outputs than that LDS array is cut into windows
+// of output positions instead: a workgroup per window takes each A entry's
+// products in the window's column range (binary search in the sorted B
+// row) and writes the window. Wide rows reuse each column little, so global
+// atomic adds would cost one per product.
+//
+// Slots, chunks, accumulators, windows and class lists are reserved per
+// group of rows or slots with one global atomic add each: device-scope
+// atomics that every row sends to one counter serialize.
+//
 // Masked columns are tested per product (binary search in the mask row, or a
-// bit test), so tables only ever hold output columns.
-//
-// Rows with at least hash_split_choose's threshold of products are split rows
-// (power-law inputs have hubs whose product lists would keep one wavefront
-// busy for the whole launch): chunks of kSplitEntries A entries go to
-// separate workgroups. The threshold is kHashSplitMin unless the rows above it
-// would need more bitmap memory than the split budget; then it is the least
-// power of two whose rows fit, so the longest rows are always split. The
-// symbolic chunks OR their columns into the row's global bitmap (an LDS copy
-// first, then one atomic OR per non-zero word); a count pass gives the row's
-// output count and, per bitmap word, the outputs before it. The numeric
-// chunks add each product at the column's rank in that bitmap, into an LDS
-// array of the row's outputs when they fit (then one global atomic add per
-// output); an emit pass writes the row in column order. A row of one chunk
-// whose outputs fit in LDS is written by its chunk directly. A row with more
-// outputs than that LDS array is cut into windows of output positions
-// instead: a workgroup per window walks all of the row's products, keeps
-// those whose column ranks fall in its window, and writes the window (wide
-// rows have little reuse per column, so global atomic adds would cost one
-// per product). Rows below the threshold, or past a slot
-// bound forced for tests, take the one-wavefront paths.
+// bit test), so tables and bitmaps only ever hold output columns.
 #include <cstdlib>
 #include <type_traits>
 
