@@ -154,6 +154,8 @@ static HashSplit hash_split_view(Plan* p) {
   hs.wins = (int2*)p->hs_wins.p;
   hs.cls_rows = (int32_t*)p->hs_cls.p;
   hs.cls_cnt = (int32_t*)p->hs_cls_cnt.p;
+  hs.chunk_lists = (int32_t*)p->hs_chunk_lists.p;
+  hs.item_cap = (int32_t)p->hs_item_cap;
   hs.cap = (int32_t)p->hs_cap;
   hs.split_flops = p->hs_split_flops;
   hs.ctr = (Counters*)p->ctr.p;
@@ -223,11 +225,13 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   const int64_t words = (d + 31) / 32;
   hash_split_choose(p->host_ctr->hash_hist, d < 1 ? 1 : d, &p->hs_split_flops, &p->hs_cap);
   const int64_t item_cap = hash_split_item_cap(A->nnz, p->hs_cap);
+  p->hs_item_cap = item_cap;
   if ((rc = p->hs_slot.ensure((size_t)n * 4)) || (rc = p->hs_rows.ensure((size_t)p->hs_cap * 4)) ||
       (rc = p->hs_items.ensure((size_t)item_cap * 8)) || (rc = p->hs_bits.ensure((size_t)p->hs_cap * words * 4)) ||
       (rc = p->hs_pref.ensure((size_t)p->hs_cap * words * 4)) || (rc = p->hs_off.ensure((size_t)p->hs_cap * 4)) ||
       (rc = p->hs_wins.ensure((size_t)hash_split_window_cap(p->hs_cap, d < 1 ? 1 : d) * 8)) ||
-      (rc = p->hs_cls.ensure((size_t)n * 16)) || (rc = p->hs_cls_cnt.ensure(16)))
+      (rc = p->hs_cls.ensure((size_t)n * 16)) || (rc = p->hs_cls_cnt.ensure(24)) ||
+      (rc = p->hs_chunk_lists.ensure((size_t)item_cap * 8)))
     return rc;
   const HashSplit hs = hash_split_view(p);
   // every candidate split: the rows left have fewer than kHashSplitMin products
@@ -237,9 +241,10 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   pr.cbits = nullptr;  // counts come from cnt
   if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
   TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
-  if (n > 0) TSS_HIP(hipMemcpyAsync(p->hs_cls_host, p->hs_cls_cnt.p, 16, hipMemcpyDeviceToHost, st));
+  if (n > 0) TSS_HIP(hipMemcpyAsync(p->hs_cls_host, p->hs_cls_cnt.p, 24, hipMemcpyDeviceToHost, st));
   TSS_HIP(hipStreamSynchronize(st));
-  if (n == 0) p->hs_cls_host[0] = p->hs_cls_host[1] = p->hs_cls_host[2] = p->hs_cls_host[3] = 0;
+  if (n == 0)
+    for (int c = 0; c < 6; ++c) p->hs_cls_host[c] = 0;
   const Counters& h = *p->host_ctr;
   if (h.hash_error) {
     set_error("hash accumulator: inconsistent row table");

@@ -58,7 +58,9 @@ struct Plan {
   // bitmaps, per-word counts, accumulator offsets, accumulators
   DevBuf hs_slot, hs_rows, hs_items, hs_bits, hs_pref, hs_off, hs_acc, hs_wins;
   DevBuf hs_cls, hs_cls_cnt;  // hash plan: row lists of the LDS table size classes, and their counts
-  int32_t hs_cls_host[4] = {0, 0, 0, 0};
+  DevBuf hs_chunk_lists;      // hash plan: split-row chunks by class
+  int64_t hs_item_cap = 0;
+  int32_t hs_cls_host[6] = {0, 0, 0, 0, 0, 0};
   int64_t hs_cap = 0, hs_rows_n = 0, hs_items_n = 0, hs_acc_n = 0, hs_win_n = 0, hs_split_flops = 0;
   bool hs_all_split = false;  // every row with kHashSplitMin products or more is split
   DevBuf sp_chunks, sp_rows, sp_partial, sp_ctr;  // dense-B SpMM workspace (per-device cached plan)

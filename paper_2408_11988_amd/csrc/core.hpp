@@ -156,7 +156,9 @@ struct HashSplit {
   int32_t* acc_off;      // cap: first accumulator of the row
   int2* wins;            // output windows of rows wider than a chunk's LDS array: (slot, window)
   int32_t* cls_rows;     // 4 x n: rows of each LDS table size class (outputs <= 64, 128, 256, 512)
-  int32_t* cls_cnt;      // 4: rows in each class
+  int32_t* cls_cnt;      // 6: rows in each table class, then chunks in each chunk class
+  int32_t* chunk_lists;  // 2 x item_cap: chunks of rows with <= 1024 outputs, then of rows with more
+  int32_t item_cap;      // capacity of the chunk list
   void* acc;             // accumulators (FP64, or INT32 for the integer semiring)
   int32_t cap;           // split slots (0: no row is split)
   int64_t split_flops;   // rows with at least this many products are split rows
@@ -180,7 +182,8 @@ int64_t hash_dense_workers(int64_t d);
 // split_items and split_acc: the split counts the symbolic phase ended with;
 // long_rows: some row that is not split may have more outputs than the LDS
 // tables hold (else the long-row kernel is not launched)
-// cls_n: rows of each table size class (the counts hs.cls_cnt ended with)
+// cls_n: rows of each table size class and chunks of each chunk class (the
+// counts hs.cls_cnt ended with)
 int launch_hash_numeric(int sr, const Problem& pr, const HashMask& m, const HashSplit& hs, int32_t split_rows,
                         int32_t split_items, int64_t split_acc, int32_t win_items, const int32_t* cls_n,
                         bool long_rows, void* strips, int32_t* err, int32_t* next, hipStream_t st);

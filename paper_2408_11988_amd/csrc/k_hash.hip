@@ -31,7 +31,7 @@
 //   in global memory; the row is written by walking the bitmap and the strip
 //   is cleared behind it.
 //
-// Split rows: chunks of kSplitEntries A entries, one workgroup each. Symbolic
+// Split rows: chunks of split_chunk_entries A entries, one workgroup each. Symbolic
 // chunks OR their columns into the row's global bitmap (an LDS copy first,
 // then one atomic OR per non-zero word); a count pass gives the row's output
 // count and, per bitmap word, the outputs before it. Numeric chunks add each
@@ -70,6 +70,7 @@ constexpr int kRankWords = 256;           // up to this many bitmap words (d <= 
 constexpr int kSplitSymBlocks = 2048;     // symbolic chunk workgroups (chunks are taken from a counter)
 constexpr int kSplitFetch = 4;            // chunks a symbolic chunk workgroup takes per fetch
 constexpr int kWinWaves = 4;              // wavefronts per output-window workgroup
+constexpr int kSplitSmall = 1024;         // chunks of rows with at most this many outputs use a small LDS array
 static_assert(kHashMaxD <= kSymSlots * 32, "the d-bit bitmap of a row must fit a wavefront's LDS words");
 
 __device__ __forceinline__ uint32_t hslot(int32_t j, uint32_t mask) { return ((uint32_t)j * 2654435761u) & mask; }
@@ -303,10 +304,29 @@ __host__ __device__ constexpr int split_lds_outputs(int width) { return width <=
 
 __device__ __forceinline__ int split_lds(const Problem& pr) { return split_lds_outputs(split_width((pr.d + 31) >> 5)); }
 
+// A entries per numeric chunk of a split row (symbolic chunks are
+// kSplitEntries; a numeric chunk is that many consecutive ones): a multiple
+// of kSplitEntries, enough that a chunk has at least 4 products per output
+// the row may have (up to the chunk LDS array), so the global adds a
+// multi-chunk row's chunks make are at most a quarter of its products; at
+// most kSplitMaxEntries, so hubs still spread over many workgroups.
+constexpr int kSplitMaxEntries = 8 * kSplitEntries;
+__device__ __forceinline__ int split_chunk_entries(const Problem& pr, int64_t row) {
+  const long long fl = pr.flops[row];
+  const long long deg = pr.arp[row + 1] - pr.arp[row];
+  long long est = fl < pr.d ? fl : pr.d;
+  if (est > split_lds(pr)) est = split_lds(pr);
+  long long e = fl > 0 ? (4 * est * deg + fl - 1) / fl : kSplitEntries;
+  e = (e + kSplitEntries - 1) / kSplitEntries * kSplitEntries;
+  if (e < kSplitEntries) e = kSplitEntries;
+  if (e > kSplitMaxEntries) e = kSplitMaxEntries;
+  return (int)e;
+}
+
 // A split row of one chunk whose outputs fit the chunk's LDS array: the
 // chunk writes the row itself (value semirings).
 __device__ __forceinline__ bool split_direct(const Problem& pr, int row, int cnt) {
-  return pr.arp[row + 1] - pr.arp[row] <= kSplitEntries && cnt <= split_lds(pr);
+  return pr.arp[row + 1] - pr.arp[row] <= split_chunk_entries(pr, row) && cnt <= split_lds(pr);
 }
 
 // A split row with more outputs than that array: written window by window.
@@ -424,8 +444,7 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_symbolic(Pro
     const int2 itm = hs.items[it];
     const int row = hs.rows[itm.x];
     const int a1 = min(itm.y + kSplitEntries, pr.arp[row + 1]);
-    const int base = itm.y + wave * kWave;
-    if (base < a1) {
+    for (int base = itm.y + wave * kWave; base < a1; base += kSplitEntries) {
       const int nb = min(kWave, a1 - base);
       const int total = stage_products<char>(pr, base, nb, start_s[wave], pref_s[wave], nullptr);
       for_staged_products<char>(pr, total, start_s[wave], pref_s[wave], [&](int, int, int32_t j, char) {
@@ -531,6 +550,37 @@ __global__ __launch_bounds__(256) void k_hash_table_bins(Problem pr, HashSplit h
     if (threadIdx.x < 4 && n_s[threadIdx.x]) base_s[threadIdx.x] = atomicAdd(&hs.cls_cnt[threadIdx.x], n_s[threadIdx.x]);
     __syncthreads();
     if (c >= 0) hs.cls_rows[(int64_t)c * pr.n + base_s[c] + local] = (int32_t)row;
+    __syncthreads();
+  }
+}
+
+// Numeric chunks of split rows into two lists by their row's outputs: at
+// most kSplitSmall, or more up to the chunk LDS array (windowed rows are left
+// out: their windows write them). Reservations per 256 chunks and class.
+__global__ __launch_bounds__(256) void k_hash_chunk_bins(Problem pr, HashSplit hs, const int32_t* cnt) {
+  __shared__ int n_s[2], base_s[2];
+  const int n_items = hs.ctr->hash_split_items;
+  const int lc = split_lds(pr);
+  for (int i0 = blockIdx.x * blockDim.x; i0 < n_items; i0 += gridDim.x * blockDim.x) {
+    if (threadIdx.x < 2) n_s[threadIdx.x] = 0;
+    __syncthreads();
+    const int i = i0 + threadIdx.x;
+    int c = -1, local = 0;
+    if (i < n_items) {
+      const int2 itm = hs.items[i];
+      const int row = hs.rows[itm.x];
+      const int nz = cnt[row];
+      // symbolic chunks that start a numeric chunk, of rows not written by windows
+      if (nz <= lc && (itm.y - pr.arp[row]) % split_chunk_entries(pr, row) == 0) {
+        c = nz <= kSplitSmall ? 0 : 1;
+        local = atomicAdd(&n_s[c], 1);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 && n_s[threadIdx.x])
+      base_s[threadIdx.x] = atomicAdd(&hs.cls_cnt[4 + threadIdx.x], n_s[threadIdx.x]);
+    __syncthreads();
+    if (c >= 0) hs.chunk_lists[(int64_t)c * hs.item_cap + base_s[c] + local] = i;
     __syncthreads();
   }
 }
@@ -820,11 +870,12 @@ __device__ __forceinline__ void global_add(A* p, A v) {
 
 // Numeric chunk of a split row (one workgroup per chunk). The accumulators
 // are zero when it starts; the chunks of a row add in any order.
-template <typename V, int WC>
+// LC: outputs of the LDS array; chunks come from the list of their class
+// (k_hash_chunk_bins), so every row here has at most LC outputs.
+template <typename V, int WC, int LC>
 __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_numeric(Problem pr, HashMask hm, HashSplit hs,
-                                                                            int32_t* err) {
+                                                                            const int32_t* list, int32_t* err) {
   using Acc = typename HashAcc<V>::type;
-  constexpr int LC = split_lds_outputs(WC);
   __shared__ uint32_t bm[WC];
   __shared__ int32_t bp[WC];
   __shared__ Acc acc[LC];
@@ -832,10 +883,13 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_numeric(Prob
   __shared__ V aval_s[kSplitWaves][kWave];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
   const int words = (pr.d + 31) >> 5;
-  const int2 itm = hs.items[blockIdx.x];
+  const int2 itm = hs.items[list[blockIdx.x]];
   const int row = hs.rows[itm.x];
   const int cnt = pr.crp[row + 1] - pr.crp[row];
-  if (cnt > LC) return;  // written by its windows
+  if (cnt > LC) {  // not this class: the pattern changed since the symbolic call
+    if (threadIdx.x == 0) atomicOr(err, 1);
+    return;
+  }
   const uint32_t* gb = hs.bits + (int64_t)itm.x * words;
   const int32_t* gp = hs.pref + (int64_t)itm.x * words;
   Acc* gacc = (Acc*)hs.acc + hs.acc_off[itm.x];
@@ -847,9 +901,8 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_numeric(Prob
   __syncthreads();
   const bool masked = hm.rp || hm.bits;
   const V* __restrict__ bval = (const V*)pr.bval;
-  const int a1 = min(itm.y + kSplitEntries, pr.arp[row + 1]);
-  const int base = itm.y + wave * kWave;
-  if (base < a1) {
+  const int a1 = min(itm.y + split_chunk_entries(pr, row), pr.arp[row + 1]);
+  for (int base = itm.y + wave * kWave; base < a1; base += kSplitEntries) {
     const int nb = min(kWave, a1 - base);
     const int total = stage_products<V>(pr, base, nb, start_s[wave], pref_s[wave], aval_s[wave]);
     // U products per lane per step; the next step's B loads are issued before
@@ -1130,11 +1183,12 @@ int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& 
     k_hash_split_count<<<(unsigned)gc, kSplitWaves * kWave, 0, st>>>(pr, hs, cnt);
     TSS_CHECK_LAUNCH();
   }
-  int rc = launch_zero_bytes(hs.cls_cnt, 16, st);
+  int rc = launch_zero_bytes(hs.cls_cnt, 24, st);
   if (rc) return rc;
   int64_t gb = (pr.n + 255) / 256;
   if (gb > 1024) gb = 1024;
   k_hash_table_bins<<<(unsigned)gb, 256, 0, st>>>(pr, hs, cnt);
+  if (hs.cap > 0) k_hash_chunk_bins<<<1024, 256, 0, st>>>(pr, hs, cnt);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }
@@ -1183,13 +1237,25 @@ static void hash_numeric_kernels(const Problem& pr, const HashMask& h, const Has
                                                                           next);
   if constexpr (!std::is_same<V, char>::value) {  // pattern-only rows need no accumulation
     const int wc = split_width((pr.d + 31) >> 5);
-    const unsigned gi = (unsigned)split_items;
-    if (split_items > 0 && wc == 64)
-      k_hash_split_numeric<V, 64><<<gi, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
-    else if (split_items > 0 && wc == kRankWords)
-      k_hash_split_numeric<V, kRankWords><<<gi, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
-    else if (split_items > 0)
-      k_hash_split_numeric<V, kSymSlots><<<gi, kSplitWaves * kWave, 0, st>>>(pr, h, hs, err);
+    const int32_t* small = hs.chunk_lists;
+    const int32_t* large = hs.chunk_lists + hs.item_cap;
+    const unsigned gs = (unsigned)cls_n[4], gl = (unsigned)cls_n[5];
+    if (wc == 64) {
+      if (gs) k_hash_split_numeric<V, 64, kSplitSmall><<<gs, kSplitWaves * kWave, 0, st>>>(pr, h, hs, small, err);
+      if (gl) k_hash_split_numeric<V, 64, split_lds_outputs(64)><<<gl, kSplitWaves * kWave, 0, st>>>(pr, h, hs, large, err);
+    } else if (wc == kRankWords) {
+      if (gs)
+        k_hash_split_numeric<V, kRankWords, kSplitSmall><<<gs, kSplitWaves * kWave, 0, st>>>(pr, h, hs, small, err);
+      if (gl)
+        k_hash_split_numeric<V, kRankWords, split_lds_outputs(kRankWords)>
+            <<<gl, kSplitWaves * kWave, 0, st>>>(pr, h, hs, large, err);
+    } else {
+      if (gs)
+        k_hash_split_numeric<V, kSymSlots, kSplitSmall><<<gs, kSplitWaves * kWave, 0, st>>>(pr, h, hs, small, err);
+      if (gl)
+        k_hash_split_numeric<V, kSymSlots, split_lds_outputs(kSymSlots)>
+            <<<gl, kSplitWaves * kWave, 0, st>>>(pr, h, hs, large, err);
+    }
     const unsigned gw = (unsigned)win_items;
     if (win_items > 0 && wc == 64)
       k_hash_split_window<V, 64><<<gw, kWinWaves * kWave, 0, st>>>(pr, h, hs, err);
