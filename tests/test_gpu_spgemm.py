@@ -402,6 +402,41 @@ def test_hash_split_rows(d, monkeypatch):
     gkey = np.repeat(np.arange(a.nrows, dtype=np.int64), np.diff(g_rp.astype(np.int64))) * d + g_ci
     ref = fval[np.searchsorted(fkey, gkey)]
     assert np.all(np.abs(g_val - ref) <= 1e-5 * np.abs(ref))
+    note(f"hash split rows plus_times with the same mask as a bitmap d={d}")
+    wp = tss.bitmap_words(d)
+    bits = np.zeros((a.nrows, wp), dtype=np.uint32)
+    mrows = np.repeat(np.arange(a.nrows), np.diff(m.rp))
+    np.bitwise_or.at(bits, (mrows, m.ci // 32), (np.uint32(1) << (m.ci % 32).astype(np.uint32)))
+    C2 = tss.spgemm(to_dev(a), to_dev(b), mask=torch.from_numpy(bits.view(np.int32)).cuda())
+    r_rp, r_ci, r_val = C2.to_host()
+    assert np.array_equal(r_rp, g_rp) and np.array_equal(r_ci, g_ci)
+    assert np.all(np.abs(r_val - ref) <= 1e-5 * np.abs(ref))
+
+
+def test_hash_plan_reuse_across_shapes():
+    """One plan object through hash-accumulator products of different shapes
+    and widths (its split, window and class buffers grow or are reused),
+    then back to the first: every result against the oracle, the last one
+    bit-identical in structure to the first."""
+    tss = _tss()
+    plan = None
+    first = None
+    for scale, d, lam, seed in ((10, 2048, 30.0, 6200), (11, 9000, 40.0, 6201), (9, 1500, 20.0, 6202),
+                                (10, 2048, 30.0, 6200)):
+        g = synth.rmat(scale, 16, seed)
+        a = g.with_values(synth.values(g, "uniform", seed, synth.S_AVAL))
+        b = synth.b_poisson(a.nrows, d, lam, seed + 1)
+        b = b.with_values(synth.values(b, "uniform", seed + 1, synth.S_BVAL))
+        note(f"hash plan reuse: R-MAT {scale} d={d}")
+        C, plan = tss.spgemm(to_dev(a), to_dev(b), plan=plan, return_plan=True)
+        torch.cuda.synchronize()
+        assert plan.stats()["split_rows"] > 0
+        assert compare_f32(a, b, C, threads=8) > 0.999
+        rp, ci, _ = C.to_host()
+        if first is None:
+            first = (rp, ci)
+        elif (scale, d) == (10, 2048):
+            assert np.array_equal(rp, first[0]) and np.array_equal(ci, first[1])
 
 
 @pytest.mark.parametrize("d", [2048, 65536])
