@@ -390,9 +390,17 @@ __device__ __forceinline__ void accumulate_light(const Problem& pr, int p0, int 
 
 // ================================================================ binning (numeric)
 
-// Work class by product count: 3 = light (a lane group), 2 = one wavefront,
+// Work class by a row's work: 3 = light (a lane group), 2 = one wavefront,
 // 1 = one workgroup, 0 = split into chunks of at least kMinChunk A entries.
+// The work is the product count, but at least kEntryWork per A entry: each
+// entry is staged (its column, B row bounds and value) whether or not its B
+// row holds anything, so a hub row over near-empty B rows is a long serial
+// walk for one wavefront though it has few products.
 constexpr int kMinChunk = 64;
+constexpr int64_t kEntryWork = 16;
+__device__ __forceinline__ int64_t num_work(int64_t f, int m) {
+  return f > kEntryWork * m ? f : kEntryWork * m;
+}
 
 __device__ __forceinline__ int num_class(int64_t f, const NumThresholds& th) {
   return f <= th.light_max ? 3 : (f <= th.wave_max ? 2 : (f <= th.split ? 1 : 0));
@@ -403,24 +411,26 @@ __device__ __forceinline__ int num_bin(int64_t work) {
   return b < 0 ? 0 : b;
 }
 __device__ __forceinline__ int chunk_entries(int m, int64_t f, int64_t split) {
-  const int64_t want = (f + split - 1) / split;  // chunks by products
+  const int64_t want = (f + split - 1) / split;  // chunks by work (num_work)
   int ce = (int)((m + want - 1) / want);
   return ce < kMinChunk ? kMinChunk : ce;
 }
 
-// (class, bin) key of a row with f > 0 products and m A entries, and the
-// number of items it makes (split rows: one per chunk).
+// (class, bin) key of a row with f > 0 products and m A entries (by its
+// work, num_work), and the number of items it makes (split rows: one per
+// chunk).
 __device__ __forceinline__ void num_key(int64_t f, int m, const NumThresholds& th, int& cls, int& key, int& count,
                                         int& ce) {
-  cls = num_class(f, th);
+  const int64_t w = num_work(f, m);
+  cls = num_class(w, th);
   if (cls == 0) {
-    ce = chunk_entries(m, f, th.split);
+    ce = chunk_entries(m, w, th.split);
     count = (m + ce - 1) / ce;
     key = 0;
   } else {
     ce = 0;
     count = 1;
-    key = cls * kBins + num_bin(f);
+    key = cls * kBins + num_bin(w);
   }
 }
 
