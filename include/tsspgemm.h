@@ -78,7 +78,10 @@ typedef struct {
  * width d for d <= 1024, a hash accumulator above).
  *   LDS_STRIP:  lanes walk the entries of each B row and add into a d-wide
  *               strip in LDS (FP64 for the FP32 semiring). Needs d <= 1024.
- *   HASH:       open-addressing table of column keys per row, for d > 1024. */
+ *   HASH:       for d > 1024. Short rows: an LDS open-addressing table of
+ *               (column, sum) per row. Rows with many products: split into
+ *               chunks of A entries over workgroups, with a global bitmap of
+ *               the row's columns and sums at each column's rank in it. */
 typedef enum {
   TSSPGEMM_ACC_AUTO = 0,
   TSSPGEMM_ACC_LDS_STRIP = 1,
@@ -114,8 +117,10 @@ int32_t tsspgemm_bitmap_words(int32_t d);
 
 /* Symbolic phase (Sec. III-A, Eq. 1 structure; the symbolic nnz count of
  * Sec. III-D): computes flops per row (Sec. II-A), bins rows by work, the
- * output pattern (a d-bit bitmap per row for d <= 1024; per-row hash sets
- * for the hash accumulator) and C's row pointers.
+ * output pattern (a d-bit bitmap per row for d <= 1024; per-row LDS hash
+ * sets, or global bitmaps for split rows, with the hash accumulator) and C's
+ * row pointers. With the hash accumulator it synchronizes `stream` twice
+ * (once for the histogram of row products that sets the split rows).
  *   A: n x n, B: n x d (vals unused). sr: tsspgemm_semiring the plan is for.
  *   M: complement mask or NULL. tune: NULL for defaults.
  *   c_rowptr: caller-allocated, n + 1 int32, written.
