@@ -67,8 +67,6 @@ constexpr int kDenseFetch = 16;           // rows a dense-row worker takes per f
 constexpr int kSplitWaves = 4;            // wavefronts per chunk workgroup
 constexpr int kSplitEntries = kSplitWaves * kWave;  // A entries per chunk (a wavefront stages 64)
 constexpr int kRankWords = 256;           // up to this many bitmap words (d <= 8192): narrow kernels
-constexpr int kSplitSymBlocks = 2048;     // symbolic chunk workgroups (chunks are taken from a counter)
-constexpr int kSplitFetch = 4;            // chunks a symbolic chunk workgroup takes per fetch
 constexpr int kWinWaves = 4;              // wavefronts per output-window workgroup
 constexpr int kSplitSmall = 1024;         // chunks of rows with at most this many outputs use a small LDS array
 static_assert(kHashMaxD <= kSymSlots * 32, "the d-bit bitmap of a row must fit a wavefront's LDS words");
@@ -418,27 +416,20 @@ __global__ __launch_bounds__(256) void k_hash_split_claim(Problem pr, HashSplit 
   }
 }
 
-// Symbolic chunks of split rows. Workgroups take kSplitFetch chunks at a
-// time from a counter until the chunk list is used up (chunks differ in
-// products, so a static stride would leave some workgroups the heavy ones).
+// Symbolic chunks of split rows, one per workgroup. The grid is the host's
+// bound on the chunk count (hash_split_item_cap); workgroups past the
+// actual count exit at once. Chunks differ in products, and the hardware's
+// workgroup dispatch balances them without a shared counter.
 template <int WC>
 __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_symbolic(Problem pr, HashMask hm, HashSplit hs) {
   __shared__ uint32_t bm[WC];
   __shared__ int start_s[kSplitWaves][kWave], pref_s[kSplitWaves][kWave + 1];
-  __shared__ int fetch_s;
   const int wave = threadIdx.x >> 6;
   const int words = (pr.d + 31) >> 5;
   const bool masked = hm.rp || hm.bits;
-  const int n_items = hs.ctr->hash_split_items;
-  for (int it = 0, it_end = 0;; ++it) {
-    if (it == it_end) {
-      __syncthreads();  // every thread has read fetch_s
-      if (threadIdx.x == 0) fetch_s = atomicAdd(&hs.ctr->hash_split_next, kSplitFetch);
-      __syncthreads();
-      it = fetch_s;
-      it_end = min(it + kSplitFetch, n_items);
-    }
-    if (it >= n_items) break;
+  const int it = blockIdx.x;
+  if (it >= hs.ctr->hash_split_items) return;
+  {
     for (int t = threadIdx.x; t < words; t += blockDim.x) bm[t] = 0u;
     __syncthreads();
     const int2 itm = hs.items[it];
@@ -1172,12 +1163,13 @@ int launch_hash_symbolic(const Problem& pr, const HashMask& m, const HashSplit& 
   TSS_CHECK_LAUNCH();
   if (hs.cap > 0) {
     const int wc = split_width((pr.d + 31) >> 5);
+    const unsigned gi = (unsigned)hs.item_cap;
     if (wc == 64)
-      k_hash_split_symbolic<64><<<kSplitSymBlocks, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
+      k_hash_split_symbolic<64><<<gi, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
     else if (wc == kRankWords)
-      k_hash_split_symbolic<kRankWords><<<kSplitSymBlocks, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
+      k_hash_split_symbolic<kRankWords><<<gi, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
     else
-      k_hash_split_symbolic<kSymSlots><<<kSplitSymBlocks, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
+      k_hash_split_symbolic<kSymSlots><<<gi, kSplitWaves * kWave, 0, st>>>(pr, m, hs);
     int64_t gc = (hs.cap + kCountSlots - 1) / kCountSlots;
     if (gc > 4096) gc = 4096;
     k_hash_split_count<<<(unsigned)gc, kSplitWaves * kWave, 0, st>>>(pr, hs, cnt);
