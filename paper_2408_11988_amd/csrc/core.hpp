@@ -43,7 +43,7 @@ struct Counters {
   int32_t hash_error;        // hash accumulator: a table or count was inconsistent
   int32_t hash_split_rows;   // hash accumulator: rows that claimed a split slot (may exceed the capacity)
   int32_t hash_split_items;  // hash accumulator: chunks of the split rows
-  int32_t hash_split_next;   // hash accumulator: next chunk for the symbolic chunk workers
+  int32_t pad1;
   int32_t hash_split_acc;    // hash accumulator: accumulator slots of the split rows
   int32_t hash_win_items;    // hash accumulator: output windows of the widest split rows
   int32_t hash_hist[64];     // hash accumulator: rows by floor(log2(products)), from kHashSplitMin up
