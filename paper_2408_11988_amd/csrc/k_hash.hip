@@ -455,23 +455,23 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_symbolic(Pro
 
 // Per split row: output count (cnt), outputs before each bitmap word (pref),
 // the row's first accumulator (acc_off) and its output windows. A workgroup
-// takes kCountSlots consecutive slots and reserves their accumulators and
-// windows with one global add each.
+// takes kCountSlots consecutive slots, one wavefront per slot (64 words a
+// step, a running carry), and reserves their accumulators and windows with
+// one global add each.
 constexpr int kCountSlots = 16;
 __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_count(Problem pr, HashSplit hs, int32_t* cnt) {
-  __shared__ int wsum[kSplitWaves];
   __shared__ int acc_need[kCountSlots], win_need[kCountSlots];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
   const int words = (pr.d + 31) >> 5;
   const int nsplit = min(hs.ctr->hash_split_rows, hs.cap);
   for (int s0 = blockIdx.x * kCountSlots; s0 < nsplit; s0 += gridDim.x * kCountSlots) {
     const int s1 = min(s0 + kCountSlots, nsplit);
-    for (int slot = s0; slot < s1; ++slot) {
+    for (int slot = s0 + wave; slot < s1; slot += kSplitWaves) {
       const uint32_t* gb = hs.bits + (int64_t)slot * words;
       int32_t* gp = hs.pref + (int64_t)slot * words;
       int run = 0;
-      for (int w0 = 0; w0 < words; w0 += kSplitWaves * kWave) {
-        const int w = w0 + threadIdx.x;
+      for (int w0 = 0; w0 < words; w0 += kWave) {
+        const int w = w0 + lane;
         const int c = w < words ? __popc(gb[w]) : 0;
         int incl = c;
 #pragma unroll
@@ -479,19 +479,10 @@ __global__ __launch_bounds__(kSplitWaves * kWave) void k_hash_split_count(Proble
           const int y = __shfl_up(incl, o, kWave);
           if (lane >= o) incl += y;
         }
-        if (lane == kWave - 1) wsum[wave] = incl;
-        __syncthreads();
-        int before = run, tot = 0;
-#pragma unroll
-        for (int v = 0; v < kSplitWaves; ++v) {
-          if (v < wave) before += wsum[v];
-          tot += wsum[v];
-        }
-        if (w < words) gp[w] = before + incl - c;
-        run += tot;
-        __syncthreads();
+        if (w < words) gp[w] = run + incl - c;
+        run += __shfl(incl, kWave - 1, kWave);
       }
-      if (threadIdx.x == 0) {
+      if (lane == 0) {
         const int row = hs.rows[slot];
         cnt[row] = run;
         const int lc = split_lds(pr);
