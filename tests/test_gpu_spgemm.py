@@ -283,6 +283,49 @@ def test_edge_cases():
     assert np.array_equal(r, b.rp) and np.array_equal(c, b.ci) and np.array_equal(v, b.val)
 
 
+@pytest.mark.parametrize("d,tun", [(2048, None), (64, {"accumulator": "hash"})])
+def test_edge_cases_hash(d, tun):
+    """The hash accumulator's edge cases: no rows, empty A, empty B, the
+    identity, and one row of exactly 512 products (the least split row)
+    beside rows of 511 and 513."""
+    tss = _tss()
+    rng = np.random.default_rng(19)
+    z = synth.Csr(0, 0, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    zb = synth.Csr(0, d, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    note(f"hash n = 0, d = {d}")
+    C = tss.spgemm(to_dev(z), to_dev(zb), tuning=tun)
+    assert C.nnz == 0 and C.rowptr.cpu().tolist() == [0]
+    n = 100
+    ea = synth.Csr(n, n, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    b = random_csr(rng, n, d, min(0.1, 8.0 / d))
+    note("hash empty A")
+    C = tss.spgemm(to_dev(ea), to_dev(b), tuning=tun)
+    assert C.nnz == 0 and int(C.rowptr.cpu()[-1]) == 0
+    eb = synth.Csr(n, d, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    a = random_csr(rng, n, n, 0.1)
+    note("hash empty B")
+    C = tss.spgemm(to_dev(a), to_dev(eb), tuning=tun)
+    assert C.nnz == 0
+    eye = synth.Csr(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n, np.float32))
+    note("hash identity")
+    C = tss.spgemm(to_dev(eye), to_dev(b), tuning=tun)
+    r, c, v = C.to_host()
+    assert np.array_equal(r, b.rp) and np.array_equal(c, b.ci) and np.array_equal(v, b.val)
+    # B rows of 8 entries each; A rows of 63, 64 and 65 entries: 504, 512, 520
+    # products (only the last two are split rows)
+    nb = 300
+    bci = np.concatenate([np.sort(rng.choice(d, 8, replace=False)) for _ in range(nb)]).astype(np.int32)
+    bb = synth.Csr(nb, d, np.arange(0, 8 * nb + 1, 8, dtype=np.int32), bci, rng.random(8 * nb).astype(np.float32))
+    rows = [np.sort(rng.choice(nb, m, replace=False)) for m in (63, 64, 65)] + [np.zeros(0, np.int64)] * (nb - 3)
+    arp = np.concatenate([[0], np.cumsum([len(x) for x in rows])]).astype(np.int32)
+    ab = synth.Csr(nb, nb, arp, np.concatenate(rows).astype(np.int32), rng.random(int(arp[-1])).astype(np.float32))
+    note("hash rows at the split threshold")
+    C, plan = tss.spgemm(to_dev(ab), to_dev(bb), tuning=tun, return_plan=True)
+    torch.cuda.synchronize()
+    assert plan.stats()["split_rows"] == 2
+    assert compare_f32(ab, bb, C) > 0.999
+
+
 def test_error_paths_on_device():
     tss = _tss()
     from paper_2408_11988_amd import _lib
