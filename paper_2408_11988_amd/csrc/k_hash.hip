@@ -615,16 +615,16 @@ __device__ __forceinline__ void wave_bitonic(uint32_t* key, Acc* val, int n2) {
 
 // Rows with TSZ/4 < nnz_i <= TSZ/2 outputs (the smallest class from one
 // output): a table of at most TSZ slots per wavefront.
-// RANK (d <= 32 x kRankWords): the row is put in column order by each
-// column's rank in an LDS bitmap of the row (no sort).
+// RANK: the row is put in column order by each column's rank in an LDS
+// bitmap of the row of up to RW words (no sort).
 // The rows come from the class's row list (k_hash_table_bins), W wavefronts
 // per workgroup, one row each.
-template <typename V, int TSZ, bool RANK, int W>
+template <typename V, int TSZ, bool RANK, int W, int RW_ = kRankWords>
 __global__ __launch_bounds__(W * kWave) void k_hash_numeric_table(Problem pr, HashMask hm, const int32_t* list,
                                                                   int32_t count, int32_t* err) {
   using Acc = typename HashAcc<V>::type;
   static_assert(TSZ >= 2 * kWave && TSZ <= kNumSlots, "table class");
-  constexpr int RW = RANK ? kRankWords : 1;
+  constexpr int RW = RANK ? RW_ : 1;
   __shared__ uint32_t keys_s[W][TSZ];
   __shared__ Acc vals_s[W][TSZ];
   __shared__ int start_s[W][kWave], pref_s[W][kWave + 1];
@@ -686,28 +686,45 @@ __global__ __launch_bounds__(W * kWave) void k_hash_numeric_table(Problem pr, Ha
         if (k != kEmpty) atomicOr(&bm[k >> 5], 1u << (k & 31));
       }
       wave_sync();
-      constexpr int WPL = kRankWords / kWave;  // words per lane
-      int cw[WPL], sum = 0;
+      if constexpr (RW <= kRankWords) {  // a lane's words at once, one scan
+        constexpr int WPL = RW / kWave;    // words per lane
+        int cw[WPL], sum = 0;
 #pragma unroll
-      for (int u = 0; u < WPL; ++u) {
-        const int w = lane * WPL + u;
-        cw[u] = w < words ? __popc(bm[w]) : 0;
-        sum += cw[u];
-      }
-      int incl = sum;
+        for (int u = 0; u < WPL; ++u) {
+          const int w = lane * WPL + u;
+          cw[u] = w < words ? __popc(bm[w]) : 0;
+          sum += cw[u];
+        }
+        int incl = sum;
 #pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const int y = __shfl_up(incl, o, kWave);
-        if (lane >= o) incl += y;
-      }
-      int run = incl - sum;
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int y = __shfl_up(incl, o, kWave);
+          if (lane >= o) incl += y;
+        }
+        int run = incl - sum;
 #pragma unroll
-      for (int u = 0; u < WPL; ++u) {
-        const int w = lane * WPL + u;
-        if (w < words) pw[w] = (uint16_t)run;
-        run += cw[u];
+        for (int u = 0; u < WPL; ++u) {
+          const int w = lane * WPL + u;
+          if (w < words) pw[w] = (uint16_t)run;
+          run += cw[u];
+        }
+        if (lane == kWave - 1 && incl != nnz) atomicOr(err, 1);
+      } else {  // wide rows: 64 words a step, a running carry
+        int run = 0;
+        for (int w0 = 0; w0 < words; w0 += kWave) {
+          const int w = w0 + lane;
+          const int c = w < words ? __popc(bm[w]) : 0;
+          int incl = c;
+#pragma unroll
+          for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+          }
+          if (w < words) pw[w] = (uint16_t)(run + incl - c);
+          run += __shfl(incl, kWave - 1, kWave);
+        }
+        if (lane == 0 && run != nnz) atomicOr(err, 1);
       }
-      if (lane == kWave - 1 && incl != nnz) atomicOr(err, 1);
       wave_sync();
       for (uint32_t t = lane; t < tsz; t += kWave) {
         const uint32_t k = keys[t];
@@ -1184,25 +1201,34 @@ int64_t hash_dense_workers(int64_t d) {
   return w < kHashWaves ? kHashWaves : w;
 }
 
-template <typename V, int TSZ, bool RANK, int W>
+template <typename V, int TSZ, bool RANK, int W, int RW = kRankWords>
 static void table_class(const Problem& pr, const HashMask& h, const HashSplit& hs, int c, const int32_t* cls_n,
                         int32_t* err, hipStream_t st) {
   if (cls_n[c] == 0) return;
   const unsigned g = (unsigned)((cls_n[c] + W - 1) / W);
-  k_hash_numeric_table<V, TSZ, RANK, W><<<g, W * kWave, 0, st>>>(pr, h, hs.cls_rows + (int64_t)c * pr.n, cls_n[c],
-                                                                 err);
+  k_hash_numeric_table<V, TSZ, RANK, W, RW><<<g, W * kWave, 0, st>>>(pr, h, hs.cls_rows + (int64_t)c * pr.n,
+                                                                     cls_n[c], err);
 }
 
 // One launch per size class, over that class's rows only. Fewer wavefronts
 // share a workgroup as the tables grow, so LDS is allocated in smaller
 // pieces (more resident wavefronts per CU).
+// Narrow d (RANK): every class orders by rank in a row bitmap. Wide d: the
+// two smaller classes sort; the two larger ones rank in a bitmap of up to
+// kSymSlots words (LDS for fewer resident wavefronts, but a sort of 256 or
+// 512 keys takes dozens of LDS passes).
 template <typename V, bool RANK>
 static void table_classes(const Problem& pr, const HashMask& h, const HashSplit& hs, const int32_t* cls_n,
                           int32_t* err, hipStream_t st) {
   table_class<V, 128, RANK, 4>(pr, h, hs, 0, cls_n, err, st);
   table_class<V, 256, RANK, 4>(pr, h, hs, 1, cls_n, err, st);
-  table_class<V, 512, RANK, 2>(pr, h, hs, 2, cls_n, err, st);
-  table_class<V, kNumSlots, RANK, 1>(pr, h, hs, 3, cls_n, err, st);
+  if constexpr (RANK) {
+    table_class<V, 512, true, 2>(pr, h, hs, 2, cls_n, err, st);
+    table_class<V, kNumSlots, true, 1>(pr, h, hs, 3, cls_n, err, st);
+  } else {
+    table_class<V, 512, true, 2, kSymSlots>(pr, h, hs, 2, cls_n, err, st);
+    table_class<V, kNumSlots, true, 1, kSymSlots>(pr, h, hs, 3, cls_n, err, st);
+  }
 }
 
 template <typename V, typename Acc>
