@@ -18,9 +18,9 @@
 //
 // Short rows (below the threshold), one wavefront each:
 // - symbolic: the distinct columns (minus masked ones) are counted in an LDS
-//   open-addressing set (linear probing, column as key) of a power of two
-//   >= 2 min(d, flops_i) slots, or, when that exceeds the set, in an LDS
-//   bitmap of d bits;
+//   bitmap of d bits for d <= 32 kRankWords, else in an LDS open-addressing
+//   set (linear probing, column as key) of a power of two >= 2 min(d,
+//   flops_i) slots, or, when that exceeds the set, in the d-bit bitmap;
 // - numeric: rows with at most kHashNumMax outputs accumulate in an LDS table
 //   of (column, sum) slots sized from the exact output count, one launch per
 //   table size class over that class's row list (k_hash_table_bins). The row
@@ -251,7 +251,9 @@ __global__ __launch_bounds__(kHashWaves * kWave) void k_hash_symbolic(Problem pr
       continue;
     }
     const int64_t ub = fl < pr.d ? fl : pr.d;
-    const bool table = 2 * ub <= SW;
+    // up to kRankWords words (d <= 8192) the row's d-bit bitmap is the set
+    // (no probing); wider rows use the open-addressing set when it fits
+    const bool table = ((pr.d + 31) >> 5) > kRankWords && 2 * ub <= SW;
     const uint32_t tsz = table ? pow2_at_least((uint32_t)(2 * ub)) : 0u;
     const int words = table ? (int)tsz : (pr.d + 31) >> 5;
     for (int t = lane; t < words; t += kWave) tab[t] = table ? kEmpty : 0u;
