@@ -65,7 +65,7 @@ constexpr int kHashNumMax = kNumSlots / 2;  // numeric rows up to this many outp
 constexpr int kHashWaves = 4;             // wavefronts (rows) per workgroup
 constexpr int kDenseFetch = 16;           // rows a dense-row worker takes per fetch
 constexpr int kSplitWaves = 4;            // wavefronts per chunk workgroup
-constexpr int kSplitEntries = kSplitWaves * kWave;  // A entries per chunk (a wavefront stages 64)
+constexpr int kSplitEntries = kSplitWaves * kWave;  // A entries per symbolic chunk (a wavefront stages 64)
 constexpr int kRankWords = 256;           // up to this many bitmap words (d <= 8192): narrow kernels
 constexpr int kWinWaves = 4;              // wavefronts per output-window workgroup
 constexpr int kSplitSmall = 1024;         // chunks of rows with at most this many outputs use a small LDS array
@@ -306,17 +306,19 @@ __device__ __forceinline__ int split_lds(const Problem& pr) { return split_lds_o
 
 // A entries per numeric chunk of a split row (symbolic chunks are
 // kSplitEntries; a numeric chunk is that many consecutive ones): a multiple
-// of kSplitEntries, enough that a chunk has at least 4 products per output
-// the row may have (up to the chunk LDS array), so the global adds a
-// multi-chunk row's chunks make are at most a quarter of its products; at
-// most kSplitMaxEntries, so hubs still spread over many workgroups.
+// of kSplitEntries, enough that a chunk has at least 8 (d <= 2048) or 4
+// products per output the row may have (up to the chunk LDS array), so the
+// global adds a multi-chunk row's chunks make are at most an eighth or a
+// quarter of its products; at most kSplitMaxEntries, so hubs still spread
+// over many workgroups.
 constexpr int kSplitMaxEntries = 8 * kSplitEntries;
 __device__ __forceinline__ int split_chunk_entries(const Problem& pr, int64_t row) {
   const long long fl = pr.flops[row];
   const long long deg = pr.arp[row + 1] - pr.arp[row];
   long long est = fl < pr.d ? fl : pr.d;
   if (est > split_lds(pr)) est = split_lds(pr);
-  long long e = fl > 0 ? (4 * est * deg + fl - 1) / fl : kSplitEntries;
+  const long long per = split_lds(pr) <= 2048 ? 8 : 4;  // products per output (measured per width)
+  long long e = fl > 0 ? (per * est * deg + fl - 1) / fl : kSplitEntries;
   e = (e + kSplitEntries - 1) / kSplitEntries * kSplitEntries;
   if (e < kSplitEntries) e = kSplitEntries;
   if (e > kSplitMaxEntries) e = kSplitMaxEntries;
