@@ -126,10 +126,12 @@ __device__ __forceinline__ int stage_products(const Problem& pr, int base, int n
 }
 
 // As stage_products, but only the products of columns [c_lo, c_hi): lane t's
-// B row is cut to that range by binary search (B rows are sorted).
+// B row is cut to that range by binary search (B rows are sorted). The
+// first window needs no lower search and the last no upper one: products
+// outside the row's output columns are masked ones, which the caller skips.
 template <typename T>
-__device__ __forceinline__ int stage_window(const Problem& pr, int base, int nb, int c_lo, int c_hi, int* start,
-                                            int* pref, T* aval_s) {
+__device__ __forceinline__ int stage_window(const Problem& pr, int base, int nb, int c_lo, int c_hi, bool first,
+                                            bool last, int* start, int* pref, T* aval_s) {
   const int lane = threadIdx.x & (kWave - 1);
   int q0 = 0, len = 0;
   T a = T(0);
@@ -138,6 +140,8 @@ __device__ __forceinline__ int stage_window(const Problem& pr, int base, int nb,
     // first entries >= c_lo and >= c_hi, the two searches side by side (two
     // loads in flight per step)
     int l0 = pr.brp[k], h0 = pr.brp[k + 1], l1 = l0, h1 = h0;
+    if (first) h0 = l0;  // lower end: the row start
+    if (last) l1 = h1;   // upper end: the row end
     while (l0 < h0 || l1 < h1) {
       const int m0 = (l0 + h0) >> 1, m1 = (l1 + h1) >> 1;
       const int v0 = l0 < h0 ? pr.bci[m0] : 0, v1 = l1 < h1 ? pr.bci[m1] : 0;
@@ -1027,7 +1031,8 @@ __global__ __launch_bounds__(kWinWaves * kWave) void k_hash_split_window(Problem
   const int p1 = pr.arp[row + 1];
   for (int base = pr.arp[row] + wave * kWave; base < p1; base += kWinWaves * kWave) {
     const int nb = min(kWave, p1 - base);
-    const int total = stage_window(pr, base, nb, c_lo, c_hi, start_s[wave], pref_s[wave], aval_s[wave]);
+    const int total = stage_window(pr, base, nb, c_lo, c_hi, lo == 0, hi == cnt, start_s[wave], pref_s[wave],
+                                   aval_s[wave]);
     constexpr int U = 4;  // products per lane per step, loads first
     int e[U];
     int32_t j[U];
