@@ -66,6 +66,7 @@ struct Plan {
   DevBuf sp_chunks, sp_rows, sp_partial, sp_ctr;  // dense-B SpMM workspace (per-device cached plan)
   DevBuf em_ci, em_val;    // embedding update: second copy of Z (per-device cached plan)
   DevBuf em_cnt, em_split, em_slot_off, em_split_off, em_slot_row, em_split_list, em_partial, em_scan;
+  DevBuf em_done;          // embedding update: finished chunks of each long row
   size_t hstrips_zeroed = 0;
   Counters* host_ctr = nullptr;  // pinned
   // results of the last symbolic call

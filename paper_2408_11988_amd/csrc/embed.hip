@@ -22,11 +22,16 @@
 //
 // Work items of a minibatch: a row with at most kEmbedChunk A entries is one
 // item, finished in place; a longer row is cut into items of kEmbedChunk
-// entries that write FP64 partial forces, and a second kernel adds a row's
-// partials in chunk order, then updates and selects. Chunk items come
-// first; a fixed grid of wavefronts strides over the items (their count is
-// read on the device, so an epoch needs no host synchronisation and can be
-// captured into a graph).
+// entries that write FP64 partial forces, and a row's partials are added in
+// chunk order, then the row is updated and selected. In a small minibatch,
+// whose time is mostly launches, each chunk counts itself done on the row
+// (a device-scope atomic between a release and an acquire fence) and the
+// chunk that completes the count finishes the row, so the minibatch is one
+// launch. In a large one a second kernel finishes the long rows: there the
+// fences' L2 write-backs and invalidations would cost more than the launch.
+// Chunk items come first; a fixed grid of wavefronts strides over the items
+// (their count is read on the device, so an epoch needs no host
+// synchronisation and can be captured into a graph).
 //
 // Minibatches ping-pong between the caller's Z and a workspace copy: batch t
 // reads buffer R_t (up to date) and writes its new rows to W_t, which is stale
@@ -40,6 +45,7 @@ namespace tss {
 
 constexpr int kEmbedWaves = 4;                     // wavefronts per workgroup
 constexpr int kEmbedChunk = 128;                   // A entries per work item of a long row
+constexpr int64_t kEmbedFuseRows = 4096;           // minibatches up to this many rows finish long rows in place
 
 struct EmbedParams {
   int64_t n, d, k;
@@ -58,16 +64,19 @@ struct EmbedParams {
   const int32_t* slot_row;    // row of each chunk slot
   const int32_t* split_off;   // exclusive scan of (cnt > 0) (n + 1)
   const int32_t* split_list;  // rows with cnt > 0, in row order
+  int32_t* done;              // chunks of each long row finished so far (zeroed at the epoch's start)
   double* partial;            // chunk slot x d partial forces
+  int fuse;                   // the last chunk of a long row finishes it (no second kernel)
 };
 
 __global__ void k_embed_count(int64_t n, const int32_t* __restrict__ arp, int32_t* __restrict__ cnt,
-                              int32_t* __restrict__ split) {
+                              int32_t* __restrict__ split, int32_t* __restrict__ done) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int len = arp[i + 1] - arp[i];
     const int c = len > kEmbedChunk ? (len + kEmbedChunk - 1) / kEmbedChunk : 0;
     cnt[i] = c;
     split[i] = c > 0;
+    done[i] = 0;
   }
 }
 
@@ -208,6 +217,30 @@ __device__ __forceinline__ void embed_select_write(const EmbedParams& ep, int64_
   }
 }
 
+// A long row once all its chunks are written: partial forces added in chunk
+// order (eight loads issued before their sums), u = z_i + lr F into the
+// wavefront's LDS row `zs` (which holds z_i), then the selection.
+__device__ __forceinline__ void embed_finish_long(const EmbedParams& ep, int64_t i, float* zs, int lane) {
+  const int64_t d = ep.d;
+  const int nc = ep.cnt[i];
+  const double* part = ep.partial + (int64_t)ep.slot_off[i] * d;
+  for (int64_t col = lane; col < d; col += kWave) {  // each lane its own columns
+    double f = 0.0;
+    int c = 0;
+    for (; c + 8 <= nc; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(c + q) * d + col];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) f += v[q];
+    }
+    for (; c < nc; ++c) f += part[(int64_t)c * d + col];
+    zs[col] = (float)((double)zs[col] + ep.lr * f);
+  }
+  wave_sync();
+  embed_select_write(ep, i, zs, lane);
+}
+
 // Items of one minibatch (chunks of long rows, then short rows) and the
 // copy of the previous minibatch's rows.
 template <int P, int KPL>
@@ -250,9 +283,19 @@ __global__ __launch_bounds__(kEmbedWaves * kWave) void k_embed_main(EmbedParams 
         for (int gg = 0; gg < P; ++gg) f += strips[(int64_t)gg * d + col];
         ep.partial[(int64_t)slot * d + col] = f;
       }
+      if (!ep.fuse) continue;
+      // publish this chunk's partials, then count it; the row's last chunk
+      // (in completion order) sees every partial after its acquire
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      int prev = 0;
+      if (lane == 0) prev = __hip_atomic_fetch_add(ep.done + i, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      prev = __shfl(prev, 0, kWave);
+      if (prev != ep.cnt[i] - 1) continue;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      embed_finish_long(ep, i, zs, lane);
     } else {
       const int64_t i = ep.r0 + (it - nch);
-      if (ep.cnt[i] > 0) continue;  // a long row: its chunks and the finalize kernel
+      if (ep.cnt[i] > 0) continue;  // a long row: finished by its last chunk or the finalize kernel
       const int p0 = ep.arp[i], p1 = ep.arp[i + 1];
       int jj0;
       float aa0;
@@ -284,25 +327,7 @@ __global__ __launch_bounds__(kEmbedWaves * kWave) void k_embed_finalize(EmbedPar
   for (int64_t q = gw; q < m1 - m0; q += tw) {
     const int64_t i = ep.split_list[m0 + q];
     embed_load_zi(ep, i, zs, nullptr, 0, lane);
-    const int nc = ep.cnt[i];
-    const double* part = ep.partial + (int64_t)ep.slot_off[i] * d;
-    for (int64_t col = lane; col < d; col += kWave) {  // u replaces z_i in LDS (each lane its own columns)
-      {
-        double f = 0.0;  // chunk order; eight loads issued before their sums
-        int c = 0;
-        for (; c + 8 <= nc; c += 8) {
-          double v[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(c + q) * d + col];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) f += v[q];
-        }
-        for (; c < nc; ++c) f += part[(int64_t)c * d + col];
-        zs[col] = (float)((double)zs[col] + ep.lr * f);
-      }
-    }
-    wave_sync();
-    embed_select_write(ep, i, zs, lane);
+    embed_finish_long(ep, i, zs, lane);
   }
 }
 
@@ -344,7 +369,7 @@ static int launch_embed(const EmbedParams& ep, int P, hipStream_t st) {
       else if (k <= 512) rc = launch_embed_t<1, 8>(ep, grid, st);
       else rc = launch_embed_t<1, 16>(ep, grid, st);
   }
-  if (rc) return rc;
+  if (rc || ep.fuse) return rc;
   const unsigned fgrid = grid < 256 ? grid : 256;
   k_embed_finalize<<<fgrid, kEmbedWaves * kWave, (size_t)kEmbedWaves * 4 * ep.d, st>>>(ep);
   TSS_CHECK_LAUNCH();
@@ -383,6 +408,7 @@ static int run_embed_epoch(const tsspgemm_csr* A, int64_t d, int64_t k, int32_t*
   const int64_t slot_cap = 2 * A->nnz / kEmbedChunk + 1;
   if ((rc = p->em_ci.ensure(zbytes)) || (rc = p->em_val.ensure(zbytes)) ||
       (rc = p->em_cnt.ensure((size_t)n * 4)) || (rc = p->em_split.ensure((size_t)n * 4)) ||
+      (rc = p->em_done.ensure((size_t)n * 4)) ||
       (rc = p->em_slot_off.ensure((size_t)(n + 1) * 4)) || (rc = p->em_split_off.ensure((size_t)(n + 1) * 4)) ||
       (rc = p->em_slot_row.ensure((size_t)slot_cap * 4)) || (rc = p->em_split_list.ensure((size_t)n * 4)) ||
       (rc = p->em_partial.ensure((size_t)slot_cap * d * 8)) ||
@@ -403,10 +429,12 @@ static int run_embed_epoch(const tsspgemm_csr* A, int64_t d, int64_t k, int32_t*
   ep.slot_row = (const int32_t*)p->em_slot_row.p;
   ep.split_off = (const int32_t*)p->em_split_off.p;
   ep.split_list = (const int32_t*)p->em_split_list.p;
+  ep.done = (int32_t*)p->em_done.p;
   ep.partial = (double*)p->em_partial.p;
   {
     const unsigned g = grid_for(n, 256) > 4096 ? 4096 : grid_for(n, 256);
-    k_embed_count<<<g, 256, 0, st>>>(n, A->rowptr, (int32_t*)p->em_cnt.p, (int32_t*)p->em_split.p);
+    k_embed_count<<<g, 256, 0, st>>>(n, A->rowptr, (int32_t*)p->em_cnt.p, (int32_t*)p->em_split.p,
+                                     (int32_t*)p->em_done.p);
     TSS_CHECK_LAUNCH();
     if ((rc = launch_exscan_i32((const int32_t*)p->em_cnt.p, n, (int32_t*)p->em_slot_off.p, (int64_t*)p->em_scan.p,
                                 st)) ||
@@ -431,6 +459,7 @@ static int run_embed_epoch(const tsspgemm_csr* A, int64_t d, int64_t k, int32_t*
     ep.nrows = (row_end - r0) < batch ? (row_end - r0) : batch;
     ep.p0 = prev0;
     ep.pcount = t > 0 ? prevn : 0;
+    ep.fuse = ep.nrows <= kEmbedFuseRows;
     if ((rc = launch_embed(ep, P, st))) return rc;
     prev0 = r0;
     prevn = ep.nrows;
