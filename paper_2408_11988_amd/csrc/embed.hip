@@ -20,11 +20,11 @@
 // columns l, l + 64, ...), after which the ties at the threshold go to the
 // lowest columns.
 //
-// Work items of a minibatch: a row with at most kEmbedChunk A entries is one
-// item, finished in place; a longer row is cut into items of kEmbedChunk
+// Work items of a minibatch: a row with at most `chunk` A entries is one
+// item, finished in place; a longer row is cut into items of `chunk`
 // entries that write FP64 partial forces, and a row's partials are added in
 // chunk order, then the row is updated and selected. In a small minibatch,
-// whose time is mostly launches, each chunk counts itself done on the row
+// whose time is its launch and its longest item, each chunk counts itself done on the row
 // (a device-scope atomic between a release and an acquire fence) and the
 // chunk that completes the count finishes the row, so the minibatch is one
 // launch. In a large one a second kernel finishes the long rows: there the
@@ -44,8 +44,11 @@
 namespace tss {
 
 constexpr int kEmbedWaves = 4;                     // wavefronts per workgroup
-constexpr int kEmbedChunk = 128;                   // A entries per work item of a long row
 constexpr int64_t kEmbedFuseRows = 4096;           // minibatches up to this many rows finish long rows in place
+// A entries per work item of a long row: short chunks shorten a small
+// minibatch's longest dependent chain; in a large one, longer chunks write
+// fewer partials
+constexpr int kEmbedChunkSmall = 32, kEmbedChunkLarge = 64;
 
 struct EmbedParams {
   int64_t n, d, k;
@@ -67,13 +70,14 @@ struct EmbedParams {
   int32_t* done;              // chunks of each long row finished so far (zeroed at the epoch's start)
   double* partial;            // chunk slot x d partial forces
   int fuse;                   // the last chunk of a long row finishes it (no second kernel)
+  int chunk;                  // A entries per work item of a long row
 };
 
-__global__ void k_embed_count(int64_t n, const int32_t* __restrict__ arp, int32_t* __restrict__ cnt,
+__global__ void k_embed_count(int64_t n, int chunk, const int32_t* __restrict__ arp, int32_t* __restrict__ cnt,
                               int32_t* __restrict__ split, int32_t* __restrict__ done) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int len = arp[i + 1] - arp[i];
-    const int c = len > kEmbedChunk ? (len + kEmbedChunk - 1) / kEmbedChunk : 0;
+    const int c = len > chunk ? (len + chunk - 1) / chunk : 0;
     cnt[i] = c;
     split[i] = c > 0;
     done[i] = 0;
@@ -270,8 +274,8 @@ __global__ __launch_bounds__(kEmbedWaves * kWave) void k_embed_main(EmbedParams 
       const int32_t slot = s0 + (int32_t)it;
       const int64_t i = ep.slot_row[slot];
       const int c = slot - ep.slot_off[i];
-      const int p0 = ep.arp[i] + c * kEmbedChunk;
-      const int p1 = min(ep.arp[i + 1], p0 + kEmbedChunk);
+      const int p0 = ep.arp[i] + c * ep.chunk;
+      const int p1 = min(ep.arp[i + 1], p0 + ep.chunk);
       int jj0;
       float aa0;
       embed_stage(ep, p0, p1, lane, jj0, aa0);
@@ -404,8 +408,9 @@ static int run_embed_epoch(const tsspgemm_csr* A, int64_t d, int64_t k, int32_t*
   }
   std::lock_guard<std::mutex> lk(p->mu);
   const size_t zbytes = (size_t)n * (size_t)k * 4;
-  // a row of len > kEmbedChunk entries has ceil(len / kEmbedChunk) < 2 len / kEmbedChunk chunks
-  const int64_t slot_cap = 2 * A->nnz / kEmbedChunk + 1;
+  const int chunk = batch <= kEmbedFuseRows ? kEmbedChunkSmall : kEmbedChunkLarge;
+  // a row of len > chunk entries has ceil(len / chunk) < 2 len / chunk chunks
+  const int64_t slot_cap = 2 * A->nnz / chunk + 1;
   if ((rc = p->em_ci.ensure(zbytes)) || (rc = p->em_val.ensure(zbytes)) ||
       (rc = p->em_cnt.ensure((size_t)n * 4)) || (rc = p->em_split.ensure((size_t)n * 4)) ||
       (rc = p->em_done.ensure((size_t)n * 4)) ||
@@ -430,10 +435,11 @@ static int run_embed_epoch(const tsspgemm_csr* A, int64_t d, int64_t k, int32_t*
   ep.split_off = (const int32_t*)p->em_split_off.p;
   ep.split_list = (const int32_t*)p->em_split_list.p;
   ep.done = (int32_t*)p->em_done.p;
+  ep.chunk = chunk;
   ep.partial = (double*)p->em_partial.p;
   {
     const unsigned g = grid_for(n, 256) > 4096 ? 4096 : grid_for(n, 256);
-    k_embed_count<<<g, 256, 0, st>>>(n, A->rowptr, (int32_t*)p->em_cnt.p, (int32_t*)p->em_split.p,
+    k_embed_count<<<g, 256, 0, st>>>(n, chunk, A->rowptr, (int32_t*)p->em_cnt.p, (int32_t*)p->em_split.p,
                                      (int32_t*)p->em_done.p);
     TSS_CHECK_LAUNCH();
     if ((rc = launch_exscan_i32((const int32_t*)p->em_cnt.p, n, (int32_t*)p->em_slot_off.p, (int64_t*)p->em_scan.p,
