@@ -184,18 +184,25 @@ __device__ __forceinline__ void embed_accumulate(const EmbedParams& ep, int p0, 
 __device__ __forceinline__ void embed_select_write(const EmbedParams& ep, int64_t i, const float* us, int lane) {
   const int64_t d = ep.d, k = ep.k;
   const int M = (int)((d + kWave - 1) / kWave);
-  // T = the largest value with #{c : |u_c| >= T} >= k (the k-th largest key)
+  // T: bits fixed from the top while #{c : |u_c| >= T} >= k holds. The search
+  // ends at the k-th largest key, or earlier once exactly k keys are >= T:
+  // those k keys are then the k largest, with no tie to break (d == k: all).
   uint32_t T = 0;
-  for (int b = 30; b >= 0; --b) {
-    const uint32_t cand = T | (1u << b);
-    int cnt = 0;
-    for (int m = 0; m < M; ++m) {
-      const int64_t c = (int64_t)m * kWave + lane;
-      cnt += __popcll(__ballot(c < d && (__float_as_uint(us[c < d ? c : 0]) & 0x7fffffffu) >= cand));
+  if (d > k) {
+    for (int b = 30; b >= 0; --b) {
+      const uint32_t cand = T | (1u << b);
+      int cnt = 0;
+      for (int m = 0; m < M; ++m) {
+        const int64_t c = (int64_t)m * kWave + lane;
+        cnt += __popcll(__ballot(c < d && (__float_as_uint(us[c < d ? c : 0]) & 0x7fffffffu) >= cand));
+      }
+      if (cnt >= k) {
+        T = cand;
+        if (cnt == k) break;
+      }
     }
-    if (cnt >= k) T = cand;
   }
-  int above = 0;  // #{key > T} < k
+  int above = 0;  // #{key > T} <= k
   for (int m = 0; m < M; ++m) {
     const int64_t c = (int64_t)m * kWave + lane;
     above += __popcll(__ballot(c < d && (__float_as_uint(us[c < d ? c : 0]) & 0x7fffffffu) > T));
