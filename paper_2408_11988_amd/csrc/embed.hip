@@ -188,7 +188,20 @@ __device__ __forceinline__ void embed_select_write(const EmbedParams& ep, int64_
   // ends at the k-th largest key, or earlier once exactly k keys are >= T:
   // those k keys are then the k largest, with no tie to break (d == k: all).
   uint32_t T = 0;
-  if (d > k) {
+  if (d > k && M <= 2) {  // d <= 128: the lane's two keys stay in registers
+    const int64_t c1 = kWave + lane;
+    const uint32_t k0 = lane < d ? __float_as_uint(us[lane]) & 0x7fffffffu : 0u;
+    const uint32_t k1 = c1 < d ? __float_as_uint(us[c1]) & 0x7fffffffu : 0u;
+    const bool in0 = lane < d, in1 = c1 < d;
+    for (int b = 30; b >= 0; --b) {
+      const uint32_t cand = T | (1u << b);
+      const int cnt = __popcll(__ballot(in0 && k0 >= cand)) + __popcll(__ballot(in1 && k1 >= cand));
+      if (cnt >= k) {
+        T = cand;
+        if (cnt == k) break;
+      }
+    }
+  } else if (d > k) {
     for (int b = 30; b >= 0; --b) {
       const uint32_t cand = T | (1u << b);
       int cnt = 0;
