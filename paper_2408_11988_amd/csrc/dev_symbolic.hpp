@@ -7,13 +7,16 @@
 namespace tss {
 
 // CSR pattern -> bitmap rows. A workgroup owns kBmRows consecutive rows
-// starting at r0: it stages their row pointers and an all-zero bitmap in LDS,
-// streams the rows' entries with consecutive threads on consecutive entries
-// (coalesced), finds each entry's row by binary search over the staged
-// pointers, sets the bit with an LDS atomicOr, and writes the finished bitmap
-// rows out contiguously. `sm` holds kBmRows + 1 + kBmRows * wp words.
-// Optionally each column id is also written narrowed to 8 or 16 bits.
+// starting at r0: it stages their row pointers and an all-zero bitmap in LDS.
+// Groups of kBmLanes lanes take the rows in turn; a group streams its row's
+// entries (consecutive lanes on consecutive entries, so the loads are
+// coalesced and no entry has to search for its row), sets each bit with an
+// LDS atomicOr, and the workgroup writes the finished bitmap rows out
+// contiguously. `sm` holds kBmRows + 1 + kBmRows * wp words; blockDim.x is a
+// multiple of kBmLanes. Optionally each column id is also written narrowed
+// to 8 or 16 bits.
 constexpr int kBmRows = 256;
+constexpr int kBmLanes = 8;
 
 __device__ __forceinline__ void bitmap_block(int64_t n, const int32_t* __restrict__ rp,
                                              const int32_t* __restrict__ ci, int wp, uint32_t* __restrict__ bits,
@@ -25,20 +28,17 @@ __device__ __forceinline__ void bitmap_block(int64_t n, const int32_t* __restric
   for (int t = threadIdx.x; t <= nr; t += blockDim.x) srp[t] = rp[r0 + t];
   for (int t = threadIdx.x; t < nr * wp; t += blockDim.x) sb[t] = 0u;
   __syncthreads();
-  const int q0 = srp[0], q1 = srp[nr];
-  for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
-    const int j = ci[q];
-    int lo = 0, hi = nr;  // srp[lo] <= q < srp[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (srp[mid] <= q)
-        lo = mid;
-      else
-        hi = mid;
+  const int grp = threadIdx.x / kBmLanes, gl = threadIdx.x % kBmLanes;
+  const int ngrp = blockDim.x / kBmLanes;
+  for (int r = grp; r < nr; r += ngrp) {
+    uint32_t* row = sb + r * wp;
+    const int q1 = srp[r + 1];
+    for (int q = srp[r] + gl; q < q1; q += kBmLanes) {
+      const int j = ci[q];
+      atomicOr(&row[j >> 5], 1u << (j & 31));
+      if (narrow8) narrow8[q] = (uint8_t)j;  // the same pass narrows the column ids
+      if (narrow16) narrow16[q] = (uint16_t)j;
     }
-    atomicOr(&sb[lo * wp + (j >> 5)], 1u << (j & 31));
-    if (narrow8) narrow8[q] = (uint8_t)j;  // the same pass narrows the column ids
-    if (narrow16) narrow16[q] = (uint16_t)j;
   }
   __syncthreads();
   uint32_t* out = bits + r0 * wp;
