@@ -273,12 +273,13 @@ __global__ __launch_bounds__(kEmbedWaves * kWave) void k_embed_main(EmbedParams 
   constexpr int GL = kWave / P;
   constexpr int U = KPL >= 4 ? 1 : 4 / KPL;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int nw = blockDim.x / kWave;  // wavefronts in this workgroup
   const int g = lane / GL, gl = lane % GL;
   const int64_t d = ep.d, k = ep.k;
   double* strips = reinterpret_cast<double*>(embed_smem) + (int64_t)wave * P * d;
-  float* zs = reinterpret_cast<float*>(embed_smem + (size_t)kEmbedWaves * P * d * sizeof(double)) + wave * d;
-  const int64_t gw = (int64_t)blockIdx.x * kEmbedWaves + wave;
-  const int64_t tw = (int64_t)gridDim.x * kEmbedWaves;
+  float* zs = reinterpret_cast<float*>(embed_smem + (size_t)nw * P * d * sizeof(double)) + wave * d;
+  const int64_t gw = (int64_t)blockIdx.x * nw + wave;
+  const int64_t tw = (int64_t)gridDim.x * nw;
 
   for (int64_t q = gw; q < ep.pcount; q += tw) {
     const int64_t r = (ep.p0 + q) * k;
@@ -364,11 +365,11 @@ static int embed_groups(int64_t d, int64_t k) {
   return P;
 }
 
-static size_t embed_lds(int64_t d, int P) { return (size_t)kEmbedWaves * (8 * (size_t)P * d + 4 * (size_t)d); }
+static size_t embed_lds(int64_t d, int P, int nw) { return (size_t)nw * (8 * (size_t)P * d + 4 * (size_t)d); }
 
 template <int P, int KPL>
-static int launch_embed_t(const EmbedParams& ep, unsigned grid, hipStream_t st) {
-  k_embed_main<P, KPL><<<grid, kEmbedWaves * kWave, embed_lds(ep.d, P), st>>>(ep);
+static int launch_embed_t(const EmbedParams& ep, unsigned grid, int nw, hipStream_t st) {
+  k_embed_main<P, KPL><<<grid, nw * kWave, embed_lds(ep.d, P, nw), st>>>(ep);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }
@@ -380,18 +381,20 @@ static int launch_embed(const EmbedParams& ep, int P, hipStream_t st) {
   int64_t waves = 2 * ep.nrows > ep.pcount ? 2 * ep.nrows : ep.pcount;
   if (waves < 256) waves = 256;
   if (waves > 8192) waves = 8192;
-  const unsigned grid = (unsigned)((waves + kEmbedWaves - 1) / kEmbedWaves);
+  // a small minibatch spreads its wavefronts one per workgroup over the CUs
+  const int nw = ep.fuse ? 1 : kEmbedWaves;
+  const unsigned grid = (unsigned)((waves + nw - 1) / nw);
   int rc;
   switch (P) {
-    case 8: rc = launch_embed_t<8, 1>(ep, grid, st); break;
-    case 4: rc = launch_embed_t<4, 1>(ep, grid, st); break;
-    case 2: rc = launch_embed_t<2, 1>(ep, grid, st); break;
+    case 8: rc = launch_embed_t<8, 1>(ep, grid, nw, st); break;
+    case 4: rc = launch_embed_t<4, 1>(ep, grid, nw, st); break;
+    case 2: rc = launch_embed_t<2, 1>(ep, grid, nw, st); break;
     default:
-      if (k <= 64) rc = launch_embed_t<1, 1>(ep, grid, st);
-      else if (k <= 128) rc = launch_embed_t<1, 2>(ep, grid, st);
-      else if (k <= 256) rc = launch_embed_t<1, 4>(ep, grid, st);
-      else if (k <= 512) rc = launch_embed_t<1, 8>(ep, grid, st);
-      else rc = launch_embed_t<1, 16>(ep, grid, st);
+      if (k <= 64) rc = launch_embed_t<1, 1>(ep, grid, nw, st);
+      else if (k <= 128) rc = launch_embed_t<1, 2>(ep, grid, nw, st);
+      else if (k <= 256) rc = launch_embed_t<1, 4>(ep, grid, nw, st);
+      else if (k <= 512) rc = launch_embed_t<1, 8>(ep, grid, nw, st);
+      else rc = launch_embed_t<1, 16>(ep, grid, nw, st);
   }
   if (rc || ep.fuse) return rc;
   const unsigned fgrid = grid < 256 ? grid : 256;
