@@ -234,10 +234,12 @@ int tsspgemm_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb,
  * in FP64, rounded once to float; the new row holds the k entries of largest
  * |u| (ties: lower column), sorted by column.
  * 1 <= k <= d <= 1024, batch_rows >= 1, 0 <= row_begin <= row_end <= n.
- * Uses the device's workspace cache (a second n x k copy of Z): calls that
- * overlap on one device race. Asynchronous; no allocation after the first
- * call of a given size. Errors: INVALID_ARG, UNSUPPORTED (d > 1024), NOMEM,
- * HIP. */
+ * Uses the device's workspace cache (a second n x k copy of Z, per-row
+ * counters, partial forces of long rows): calls that overlap on one device
+ * race. Asynchronous; no allocation after the first call of a given size
+ * (n, nnz(A), d, and whether batch_rows <= 4096: such minibatches cut long
+ * rows into shorter chunks, with a larger partial-force buffer).
+ * Errors: INVALID_ARG, UNSUPPORTED (d > 1024), NOMEM, HIP. */
 int tsspgemm_embed_epoch(const tsspgemm_csr* A, int64_t d, int64_t k, int32_t* z_colidx, float* z_vals, float lr,
                          int64_t batch_rows, int64_t row_begin, int64_t row_end, void* stream);
 
