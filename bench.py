@@ -36,9 +36,16 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of every HIP source and header of the library: any change to a
+    kernel, a launch or a threshold invalidates the stored counter figures."""
+    import glob
+
     h = hashlib.sha256()
-    for f in ("k_numeric.hip", "dev_numeric.hpp", "core.hpp", "common.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2408_11988_amd", "csrc", f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_2408_11988_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "tsspgemm.h"), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -698,8 +705,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "precision": "FP32 inputs and outputs; products and sums in FP64, one rounding to FP32",
+        "dtype": "f32",
+        "precision": "FP32 inputs and outputs; products and sums accumulated in FP64, one rounding to FP32",
         "data": "synthetic (seeded R-MAT and Poisson tall-skinny B; inputs resident in HBM)",
         "config": {"workload": f"R-MAT scale {args.scale} (edge factor 16, symmetrised) x B n x {args.d} "
                                f"Poisson({0.2 * args.d:g}) entries/row, plus-times FP32",

@@ -98,7 +98,10 @@ typedef enum {
 typedef enum { TSSPGEMM_PRODUCTS_AUTO = 0, TSSPGEMM_PRODUCTS_PER_B_ROW = 1, TSSPGEMM_PRODUCTS_FLAT = 2 } tsspgemm_products;
 
 /* Tuning knobs. A NULL tuning pointer, or a zero field, means "default".
- * Results (structure and values) do not depend on any of these. */
+ * The structure of C does not depend on any of these. Values are FP64 sums
+ * rounded once to FP32 under every setting, each within the tolerance of the
+ * exact sum; the settings add in different orders, so a value may in rare
+ * cases round to a neighbouring FP32 under another setting. */
 typedef struct {
   int32_t group_lanes;     /* lanes that stream one B row: 4,8,16,32,64 (0: from mean B row length) */
   int32_t wave_max_flops;  /* rows with at most this many products use one wavefront             */
@@ -186,7 +189,9 @@ int tsspgemm_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, int
 /* CSR transpose of A's pattern (the single-GPU form of the column-partitioned
  * copy A^c of Sec. III-A): at_rowptr (ncols+1), at_colidx (nnz) with rows
  * listed in ascending order, at_perm (nnz): position in A of each entry.
- * Asynchronous. */
+ * Allocates temporaries (four nnz-sized key/value buffers of the radix sort)
+ * and synchronizes `stream` before freeing them: meant to run once per
+ * pattern, outside timed or captured loops. Errors: INVALID_ARG, NOMEM, HIP. */
 int tsspgemm_transpose(const tsspgemm_csr* A, int32_t* at_rowptr, int32_t* at_colidx, int32_t* at_perm,
                        void* stream);
 

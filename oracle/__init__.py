@@ -58,7 +58,7 @@ def _configure(path: str):
     lib.oracle_transpose.restype = None
     lib.oracle_transpose.argtypes = [i64, i64, vp, vp, vp, vp, vp]
     lib.oracle_msbfs.restype = i32
-    lib.oracle_msbfs.argtypes = [i64, vp, vp, vp, i32, vp, vp]
+    lib.oracle_msbfs.argtypes = [i64, vp, vp, vp, i32, vp, vp, vp]
     lib.oracle_bfs_queue.restype = None
     lib.oracle_bfs_queue.argtypes = [i64, vp, vp, vp, i32, vp, ctypes.c_int]
     lib.oracle_grad_a.restype = ctypes.c_int
@@ -189,15 +189,18 @@ def transpose(arp, aci, ncols: int):
     return trp, tci, perm
 
 
-def msbfs(arp, aci, sources):
-    """Algorithm 3 with ordered sets. Returns (levels n x d int32, per-iteration nnz(F))."""
+def msbfs(arp, aci, sources, return_flops: bool = False):
+    """Algorithm 3 with ordered sets. Returns (levels n x d int32, per-iteration
+    nnz(F)), and with `return_flops` also the multiplications of each
+    iteration's product A F (Sec. II-A flops)."""
     arp, aci, src = _i32(arp), _i32(aci), _i32(sources)
     n, d = len(arp) - 1, len(src)
     lev = np.empty((n, d), dtype=np.int32)
     fn = np.zeros(4096, dtype=np.int64)
+    fl = np.zeros(4096, dtype=np.int64)
     it = _load().oracle_msbfs(n, arp.ctypes.data, aci.ctypes.data, src.ctypes.data, d, lev.ctypes.data,
-                              fn.ctypes.data)
-    return lev, fn[:it]
+                              fn.ctypes.data, fl.ctypes.data)
+    return (lev, fn[:it], fl[:it]) if return_flops else (lev, fn[:it])
 
 
 def bfs_queue(arp, aci, sources, threads: int = 1):

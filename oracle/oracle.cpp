@@ -222,8 +222,12 @@ void oracle_transpose(int64_t n, int64_t m, const int32_t* arp, const int32_t* a
 // Multi-source BFS by Algorithm 3 with ordered sets: F, S, N as per-row sets
 // of source columns. levels is n x d (row-major), -1 where unreachable.
 // Returns the number of iterations with a non-empty frontier.
+// frontier_flops (may be null, capacity 4096): per iteration, the
+// multiplications of that iteration's product A F (Sec. II-A: one per pair of
+// a stored A(i,k) and a stored F(k,s)), counted before F is replaced.
 int32_t oracle_msbfs(int64_t n, const int32_t* arp, const int32_t* aci, const int32_t* src, int32_t d,
-                     int32_t* levels, int64_t* frontier_nnz /* per iteration, may be null, capacity 4096 */) {
+                     int32_t* levels, int64_t* frontier_nnz /* per iteration, may be null, capacity 4096 */,
+                     int64_t* frontier_flops) {
   for (int64_t x = 0; x < n * (int64_t)d; ++x) levels[x] = -1;
   std::vector<std::set<int32_t>> F(n), S(n);
   for (int32_t j = 0; j < d; ++j) {
@@ -240,8 +244,13 @@ int32_t oracle_msbfs(int64_t n, const int32_t* arp, const int32_t* aci, const in
   while (nnzF() > 0) {
     ++iter;
     std::vector<std::set<int32_t>> N(n);
+    int64_t mults = 0;
     for (int64_t i = 0; i < n; ++i)  // N = A F over (AND, OR)
-      for (int32_t p = arp[i]; p < arp[i + 1]; ++p) N[i].insert(F[aci[p]].begin(), F[aci[p]].end());
+      for (int32_t p = arp[i]; p < arp[i + 1]; ++p) {
+        N[i].insert(F[aci[p]].begin(), F[aci[p]].end());
+        mults += (int64_t)F[aci[p]].size();
+      }
+    if (frontier_flops && iter <= 4096) frontier_flops[iter - 1] = mults;
     for (int64_t i = 0; i < n; ++i) {
       std::set<int32_t> next;  // F = N \ S
       for (int32_t j : N[i])

@@ -36,12 +36,17 @@ def abs_csr(m):
     return Csr(m.nrows, m.ncols, m.rp, m.ci, np.abs(m.val))
 
 
-def compare_f32(a, b, C, rows=None, threads=8, signed=False):
+def compare_f32(a, b, C, rows=None, threads=8, signed=False, ref=None):
     """Structure bit-exact, values within RTOL of the FP64 oracle. With `rows`,
-    only those rows are compared (C is the full GPU result). Returns the
+    only those rows are compared (C is the full GPU result). `ref` is the
+    oracle's (rp, ci, val) for all rows when already computed. Returns the
     fraction of values equal to the oracle rounded to FP32."""
     g_rp, g_ci, g_val = C.to_host()
-    rp, ci, val = oracle.spgemm(a.rp, a.ci, a.val, b.rp, b.ci, b.val, rows=rows, threads=threads)
+    if ref is not None:
+        assert rows is None and not signed
+        rp, ci, val = ref
+    else:
+        rp, ci, val = oracle.spgemm(a.rp, a.ci, a.val, b.rp, b.ci, b.val, rows=rows, threads=threads)
     if signed:
         _, _, scale = oracle.spgemm(a.rp, a.ci, np.abs(a.val), b.rp, b.ci, np.abs(b.val), rows=rows, threads=threads)
     else:
@@ -64,6 +69,19 @@ def compare_f32(a, b, C, rows=None, threads=8, signed=False):
     bad = err > RTOL * scale
     assert not bad.any(), f"{bad.sum()} values outside tolerance; worst rel {np.max(err / np.maximum(scale, 1e-300))}"
     return float(np.mean(gv == val.astype(np.float32).astype(np.float64))) if len(val) else 1.0
+
+
+def same_structure_close_values(c1, c2):
+    """Two GPU results of one product: identical structure, values within RTOL
+    of each other (FP64 sums in another order may round to a neighbouring
+    FP32 value). Returns the fraction of bit-identical values."""
+    r1, i1, v1 = c1.to_host()
+    r2, i2, v2 = c2.to_host()
+    assert np.array_equal(r1, r2), "row pointers differ"
+    assert np.array_equal(i1, i2), "column indices differ"
+    x, y = v1.astype(np.float64), v2.astype(np.float64)
+    assert np.all(np.abs(x - y) <= RTOL * np.maximum(np.abs(x), np.abs(y))), "values differ beyond the tolerance"
+    return float(np.mean(v1 == v2)) if len(v1) else 1.0
 
 
 def compare_int(a, b, C):

@@ -85,9 +85,10 @@ def test_rmat_vs_queue_bfs(scale, d):
         assert list(fn) == list(fn3)
 
 
-def test_rmat_scale22_d512_sampled():
-    """Full-size workload: R-MAT scale 22, 512 sources. 16 sampled sources are
-    checked exactly against the queue BFS; every column for the invariants."""
+@pytest.fixture(scope="module")
+def rmat22_levels():
+    """The full-size BFS workload (R-MAT scale 22, 512 sources) run once on the
+    GPU; its levels are kept on the host for the checks below."""
     import paper_2408_11988_amd as tss
 
     a, srcs = synth.workload_bfs(scale=22, d=512)
@@ -95,17 +96,33 @@ def test_rmat_scale22_d512_sampled():
     A = to_dev(a, with_values=False)
     lev, fn = tss.msbfs(A, torch.from_numpy(srcs).cuda())
     torch.cuda.synchronize()
-    d = len(srcs)
-    assert torch.all(lev[torch.from_numpy(srcs).long().cuda(), torch.arange(d, device="cuda")] == 0)
     per_level = [int((lev == t).sum()) for t in range(0, len(fn) + 1)]
+    host = lev.cpu().numpy()
+    del lev, A
+    torch.cuda.empty_cache()
+    return a, srcs, host, fn, per_level
+
+
+def test_rmat_scale22_d512_invariants(rmat22_levels):
+    """Every column: sources at level 0, and the per-iteration frontier sizes
+    equal the level histogram (Algorithm 3)."""
+    a, srcs, lev, fn, per_level = rmat22_levels
+    d = len(srcs)
+    assert np.all(lev[srcs, np.arange(d)] == 0)
     assert per_level[0] == d  # level 0: the sources
     assert per_level[1:len(fn)] == list(fn[:-1]) and fn[-1] == 0 and per_level[len(fn)] == 0
-    rng = np.random.default_rng(22)
-    cols = np.sort(rng.choice(d, size=16, replace=False))
-    note("queue BFS on 16 sampled sources")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("part", range(4))
+def test_rmat_scale22_d512_full(part, rmat22_levels):
+    """Full-size workload: the levels of every source (128 per part) compared
+    exactly with the oracle's queue BFS."""
+    a, srcs, lev, fn, _ = rmat22_levels
+    cols = np.arange(part * 128, (part + 1) * 128)
+    note(f"queue BFS on sources {cols[0]}..{cols[-1]}")
     ref = oracle.bfs_queue(a.rp, a.ci, srcs[cols], threads=16)
-    got = lev[:, torch.from_numpy(cols).long().cuda()].cpu().numpy()
-    assert np.array_equal(got, ref)
+    assert np.array_equal(lev[:, cols], ref)
 
 
 def test_bad_source_is_an_error():

@@ -12,7 +12,7 @@ import torch
 import oracle
 import synth
 from tests._util import random_csr
-from tests.gpu_util import compare_bool, compare_f32, compare_int, note, require_gpu, to_dev
+from tests.gpu_util import compare_bool, compare_f32, compare_int, note, require_gpu, same_structure_close_values, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -90,15 +90,13 @@ def test_plus_times_signed(d, acc):
     compare_f32(a, b, C, signed=True)
 
 
-@pytest.mark.parametrize("acc", ACCS)
-@pytest.mark.parametrize("d", [3, 64, 129, 1024, 3000])
+@pytest.mark.parametrize("d,acc", [(d, acc) for d in (3, 64, 129, 1024, 3000) for acc in ACCS
+                                   if d <= 1024 or acc == "hash"])  # the LDS strip needs d <= 1024
 def test_int32_exact(d, acc):
     rng = np.random.default_rng(3000 + d)
     n = 200
     a = random_csr(rng, n, n, 0.05, kind="int", dense_rows=1)
     b = random_csr(rng, n, d, min(0.1, 20.0 / d), kind="int")
-    if d > 1024 and acc == "lds":
-        pytest.skip("the LDS strip needs d <= 1024")
     note(f"int32 n={n} d={d} acc={acc}")
     for tun in (dict(accumulator=acc), dict(accumulator=acc, **ALL_CLASSES)):
         C = _tss().spgemm(to_dev(a, dtype=torch.int32), to_dev(b, dtype=torch.int32), semiring="plus_times_i32",
@@ -152,8 +150,9 @@ def test_or_and_and_masks(d):
 
 def test_modes_and_tuning_do_not_change_results():
     """Wavefront, workgroup and split rows, and every group width, give the
-    same bits: every order of addition is fixed, and FP64 sums of exact
-    products of these sizes round to the same FP32."""
+    same structure and values within the tolerance. Each setting sums in
+    FP64 in an order of its own, so a value may round to a neighbouring FP32
+    in rare cases; nearly all values are bit-identical."""
     rng = np.random.default_rng(5)
     n, d = 600, 128
     a = random_csr(rng, n, n, 0.02, dense_rows=6)
@@ -176,9 +175,7 @@ def test_modes_and_tuning_do_not_change_results():
     for cfg in configs:
         note(f"tuning {cfg}")
         C, p = tss.spgemm(A, B, tuning=cfg, return_plan=True)
-        got = C.to_host()
-        for x, y in zip(ref_h, got):
-            assert np.array_equal(x, y), cfg
+        assert same_structure_close_values(ref, C) > 0.999, cfg
         st = p.stats()
         assert st["flops"] == plan.stats()["flops"]
     # the hash accumulator: same structure, values within the tolerance (its
@@ -228,12 +225,23 @@ def test_rmat_scale16_full(acc):
     assert st["nnz"] == C.nnz
 
 
-@pytest.mark.parametrize("acc", ["auto"] + ACCS)
-def test_rmat_scale20_d128_sampled(acc):
-    """Full-size plain workload (R-MAT scale 20, d = 128): every row checked for
-    the invariants, the heaviest and random rows against the oracle. "auto" is
-    the configuration the benchmark times."""
+@pytest.fixture(scope="module")
+def rmat20_d128():
+    """The full-size plain workload (R-MAT scale 20, d = 128) and the oracle's
+    product over every row, computed once for the module."""
     a, b = synth.workload_rmat_plain(scale=20, d=128)
+    note(f"oracle on every row of R-MAT 20 d=128 (nnzA={a.nnz} nnzB={b.nnz})")
+    ref = oracle.spgemm(a.rp, a.ci, a.val, b.rp, b.ci, b.val, threads=16)
+    return a, b, ref
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("acc", ["auto"] + ACCS)
+def test_rmat_scale20_d128_full(acc, rmat20_d128):
+    """Full-size plain workload (R-MAT scale 20, d = 128): every row against the
+    oracle (structure bit for bit, values within the tolerance), plus the
+    per-row invariants. "auto" is the configuration the benchmark times."""
+    a, b, ref = rmat20_d128
     tss = _tss()
     note(f"R-MAT 20 d=128 nnzA={a.nnz} nnzB={b.nnz} acc={acc}")
     C, plan = tss.spgemm(to_dev(a), to_dev(b), return_plan=True, tuning=dict(accumulator=acc))
@@ -243,14 +251,8 @@ def test_rmat_scale20_d128_sampled(acc):
     assert plan.stats()["flops"] == int(flops.sum())
     cnt = np.diff(g_rp.astype(np.int64))
     assert np.all(cnt <= np.minimum(128, flops)) and np.all((cnt == 0) == (flops == 0))
-    rows = np.repeat(np.arange(a.nrows), cnt)
-    key = rows * 128 + g_ci.astype(np.int64)
-    assert np.all(np.diff(key) > 0) and g_ci.min() >= 0 and g_ci.max() < 128
-    rng = np.random.default_rng(20)
-    heavy = np.argsort(flops)[-24:]
-    sample = np.unique(np.concatenate([heavy, rng.choice(a.nrows, 3000, replace=False), [0, a.nrows - 1]]))
-    note(f"oracle on {len(sample)} sampled rows")
-    frac = compare_f32(a, b, C, rows=sample.astype(np.int32), threads=16)
+    note(f"compare every row with the oracle, acc={acc}")
+    frac = compare_f32(a, b, C, ref=ref)
     assert frac > 0.999
 
 
@@ -483,11 +485,10 @@ def test_hash_plan_reuse_across_shapes():
 
 
 @pytest.mark.parametrize("d", [2048, 65536])
-def test_wide_d_rmat18_sampled(d):
+def test_wide_d_rmat18_full(d):
     """The varying-d benchmark workload past d = 1024 (R-MAT scale 18, B with
     Poisson(25.6) entries per row; hash accumulator, split hub rows): every
-    row checked for the invariants, the heaviest and random rows against the
-    oracle."""
+    row checked for the invariants and against the oracle."""
     a, b = synth.workload_wide_d(d)
     tss = _tss()
     note(f"R-MAT 18 d={d} nnzA={a.nnz} nnzB={b.nnz}")
@@ -501,9 +502,6 @@ def test_wide_d_rmat18_sampled(d):
     rows = np.repeat(np.arange(a.nrows), cnt)
     key = rows * d + g_ci.astype(np.int64)
     assert np.all(np.diff(key) > 0) and g_ci.min() >= 0 and g_ci.max() < d
-    rng = np.random.default_rng(d)
-    heavy = np.argsort(flops)[-16:]
-    sample = np.unique(np.concatenate([heavy, rng.choice(a.nrows, 2000, replace=False), [0, a.nrows - 1]]))
-    note(f"oracle on {len(sample)} sampled rows")
-    frac = compare_f32(a, b, C, rows=sample.astype(np.int32), threads=16)
+    note(f"oracle on every row, d={d}")
+    frac = compare_f32(a, b, C, threads=16)
     assert frac > 0.999

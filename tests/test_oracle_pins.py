@@ -302,11 +302,18 @@ def test_bfs_closed_forms():
 @pytest.mark.parametrize("scale", [6, 9, 11])
 def test_algorithm3_matches_queue_bfs_and_invariants(scale):
     a, srcs = synth.workload_bfs(scale=scale, d=32)
-    lev3, fnnz = oracle.msbfs(a.rp, a.ci, srcs)
+    lev3, fnnz, fflops = oracle.msbfs(a.rp, a.ci, srcs, return_flops=True)
     levq = oracle.bfs_queue(a.rp, a.ci, srcs, threads=4)
     assert np.array_equal(lev3, levq)
     # sum over iterations of nnz(F) = sum over sources of (|reach(s)| - 1)
     assert fnnz.sum() == (levq >= 0).sum() - len(srcs)
+    # Sec. II-A flops summed over the iterations of Algorithm 3: every reached
+    # (v, s) is in exactly one multiplied frontier, and F(v, s) meets every
+    # stored A(i, v), so sum_t flops(A F_t) = sum_s sum_{v in reach(s)} deg(v)
+    # with deg(v) the entries of column v of A (reach from the queue BFS)
+    deg = np.bincount(a.ci, minlength=a.nrows).astype(np.int64)
+    assert len(fflops) == len(fnnz) and fflops[-1] > 0
+    assert int(fflops.sum()) == int((deg[:, None] * (levq >= 0)).sum())
     # per-iteration frontier sizes are the level histogram
     for t, f in enumerate(fnnz, start=1):
         assert f == (levq == t).sum()
