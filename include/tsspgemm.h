@@ -203,8 +203,11 @@ int tsspgemm_transpose(const tsspgemm_csr* A, int32_t* at_rowptr, int32_t* at_co
  *   entry (k,j) of B (A^T G sampled on B's pattern), using A^T from
  *   tsspgemm_transpose.
  * plan: the forward plus-times FP32 plan of C = A B, required: its binned
- * rows drive grad_a and its output bitmap locates G(i,j). Sums are FP64 in a
- * fixed order, rounded once to FP32 (reproducible). Asynchronous.
+ * rows drive grad_a (G's row i is staged in LDS, so every G(i,j) the row's
+ * products need is read from there). Sums are FP64 in a fixed order,
+ * rounded once to FP32 (reproducible). grad_b runs the two passes of
+ * tsspgemm_backward below (same workspace, same single synchronization at
+ * its first call on a plan); grad_a alone is asynchronous.
  * Errors: INVALID_ARG (NULL plan or output, a plan of another semiring or
  * built with a mask, A / B / G / AT not matching the plan), UNSUPPORTED (a
  * hash-accumulator plan), NOMEM, HIP. */
@@ -212,6 +215,21 @@ int tsspgemm_grad_a(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_cs
                     float* grad_a, void* stream);
 int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,
                     const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_b, void* stream);
+
+/* Both gradients of the same backward in one call (either output may be
+ * NULL, not both; AT / at_perm are needed when grad_b is requested). One
+ * pass over A's rows (the forward plan's binned rows, G's row i in an LDS
+ * strip) forms the dL/dA dot products and writes the G(i, j) each product
+ * (i,k) x (k,j) reads, in one block per A entry; a second pass walks A^T and
+ * sums A(i,k) G(i,j) from those blocks for each entry (k, j) of B. Values
+ * equal those of tsspgemm_grad_a and tsspgemm_grad_b (same sums in the same
+ * order), which run the same passes. Workspace in the plan, allocated at
+ * the first call and kept: 4 bytes per product (the flops of the forward)
+ * and 20 bytes per A entry. The first call on a plan that asks for grad_b
+ * builds the blocks' starts and synchronizes `stream` once (to size the
+ * buffer); later calls are asynchronous. Errors as tsspgemm_grad_b. */
+int tsspgemm_backward(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,
+                      const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_a, float* grad_b, void* stream);
 
 /* Sparse times dense tall-and-skinny (SpMM), the alternative Sec. V-C
  * compares TS-SpGEMM with: C = A B with B and C dense, plus-times over FP32,

@@ -15,6 +15,7 @@ from .api import (  # noqa: F401
     TSSpGEMMError,
     TSSpGEMMFunction,
     TSSpGEMMOp,
+    backward,
     bitmap_words,
     column_slice,
     embed_epoch,

@@ -70,6 +70,7 @@ _SIGNATURES = {
     "tsspgemm_transpose": (ctypes.c_int, [P(CsrDesc), vp, vp, vp, vp]),
     "tsspgemm_grad_a": (ctypes.c_int, [vp, P(CsrDesc), P(CsrDesc), P(CsrDesc), vp, vp]),
     "tsspgemm_grad_b": (ctypes.c_int, [vp, P(CsrDesc), vp, P(CsrDesc), P(CsrDesc), P(CsrDesc), vp, vp]),
+    "tsspgemm_backward": (ctypes.c_int, [vp, P(CsrDesc), vp, P(CsrDesc), P(CsrDesc), P(CsrDesc), vp, vp, vp]),
     "tsspgemm_spmm": (ctypes.c_int, [P(CsrDesc), vp, i64, i64, vp, i64, vp]),
     "tsspgemm_column_slice_count": (ctypes.c_int, [P(CsrDesc), ctypes.c_int32, ctypes.c_int32, vp, P(i64), vp]),
     "tsspgemm_column_slice_fill": (ctypes.c_int, [P(CsrDesc), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]),

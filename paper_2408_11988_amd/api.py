@@ -258,6 +258,26 @@ def grad_b(plan: Plan, AT: DeviceCsr, perm: torch.Tensor, A: DeviceCsr, B: Devic
     return out[:B.nnz]
 
 
+def backward(plan: Plan, AT: DeviceCsr | None, perm: torch.Tensor | None, A: DeviceCsr, B: DeviceCsr, G: DeviceCsr,
+             need_a: bool = True, need_b: bool = True, stream=None):
+    """dL/dA and dL/dB of the same product in one library call (one pass over
+    A's rows for dL/dA and the sampled G, one over A^T for dL/dB). Returns
+    (grad_a or None, grad_b or None)."""
+    if not (need_a or need_b):
+        return None, None
+    dev = A.rowptr.device
+    ga = torch.empty(max(A.nnz, 1), dtype=torch.float32, device=dev) if need_a else None
+    gb = torch.empty(max(B.nnz, 1), dtype=torch.float32, device=dev) if need_b else None
+    da, db, dg = A.desc(), B.desc(), G.desc()
+    dat = AT.desc() if AT is not None else None
+    rc = _lib.load().tsspgemm_backward(plan.handle, ctypes.byref(dat) if dat is not None else None,
+                                       _ptr(perm) if perm is not None else None, ctypes.byref(da), ctypes.byref(db),
+                                       ctypes.byref(dg), _ptr(ga) if ga is not None else None,
+                                       _ptr(gb) if gb is not None else None, _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_backward")
+    return (ga[:A.nnz] if need_a else None), (gb[:B.nnz] if need_b else None)
+
+
 def spmm(A: DeviceCsr, B: torch.Tensor, stream=None) -> torch.Tensor:
     """C = A B with B dense (n x d float32, row-major; zeros included): the
     SpMM alternative of Sec. V-C. Returns C dense (n x d float32)."""
@@ -391,10 +411,7 @@ class TSSpGEMMFunction(torch.autograd.Function):
         A = op.A.with_vals(a_vals.contiguous())
         B = op.B.with_vals(b_vals.contiguous())
         G = op.c_pattern().with_vals(g.contiguous().to(torch.float32))
-        ga = gb = None
-        if ctx.needs_input_grad[0]:
-            ga = grad_a(op.plan, A, B, G)
-        if ctx.needs_input_grad[1]:
-            AT, perm = op.transpose()
-            gb = grad_b(op.plan, AT, perm, A, B, G)
+        need_a, need_b = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        AT, perm = op.transpose() if need_b else (None, None)
+        ga, gb = backward(op.plan, AT, perm, A, B, G, need_a=need_a, need_b=need_b)
         return ga, gb, None

@@ -1,16 +1,20 @@
-"""Empirical tuning of the work-class thresholds and the lane-group width.
+"""Empirical tuning of the accumulator, the work-class thresholds and the
+lane-group width.
 
 The paper tunes its tile width and height empirically and ships defaults
-(Sec. V-A, V-B); on the GPU the knobs are the group width that streams a B
-row and the product-count thresholds that send a row to a lane group, a
-wavefront, a workgroup, or split chunks. None of them changes a result (the
-structure and every value are identical for any choice), only time.
+(Sec. V-A, V-B), and picks the accumulator by d: a dense accumulator (SPA)
+up to d = 1024, a hash above (Sec. III-C). On the GPU the knobs are the
+accumulator (the LDS strip or the hash path; only the hash for d > 1024),
+the group width that streams a B row and the product-count thresholds that
+send a row to a lane group, a wavefront, a workgroup, or split chunks. None
+of them changes the structure of C; values are FP64 sums rounded once under
+every choice (within the tolerance of each other, nearly always identical).
 
-The search is a coordinate descent: group width first, then the product
-layout (per B row or flat), then the light-row threshold, then the wavefront /
-split thresholds, each candidate timed on the
-instance's numeric phase (its symbolic phase rebinds rows for the candidate).
-Results are cached per feature key in a JSON file.
+The search is a coordinate descent: the accumulator first, then (for the LDS
+strip) the group width, the product layout (per B row or flat), the
+light-row threshold and the wavefront / split thresholds, each candidate
+timed on the instance's numeric phase (its symbolic phase rebinds rows for
+the candidate). Results are cached per feature key in a JSON file.
 """
 from __future__ import annotations
 
@@ -26,7 +30,9 @@ GROUP_LANES = (8, 16, 32, 64)
 LIGHT_MAX = (256, 512, 2048, 8192)
 WAVE_SPLIT = ((16384, 131072), (65536, 262144), (131072, 524288))
 PRODUCTS = ("rows", "flat")
-DEFAULT = {"group_lanes": 0, "light_max_flops": 1024, "wave_max_flops": 65536, "split_flops": 262144, "products": 0}
+ACCUMULATORS = ("lds", "hash")
+DEFAULT = {"accumulator": "auto", "group_lanes": 0, "light_max_flops": 1024, "wave_max_flops": 65536,
+           "split_flops": 262144, "products": 0}
 
 
 def features(A: DeviceCsr, B: DeviceCsr, flops: int) -> str:
@@ -81,6 +87,16 @@ class Autotuner:
         if key in self.cache:
             return dict(self.cache[key])
         best, best_t = dict(DEFAULT), t0
+        if B.ncols <= 1024:  # both accumulators apply; above, only the hash
+            for acc in ACCUMULATORS:
+                cand = dict(best, accumulator=acc)
+                t, _ = _time_numeric(A, B, cand, reps)
+                if t < best_t:
+                    best, best_t = cand, t
+        if best["accumulator"] == "hash" or B.ncols > 1024:  # the other knobs are the strip's
+            best["ms"] = round(best_t, 4)
+            self.cache[key] = best
+            return dict(best)
         for gl in GROUP_LANES:
             cand = dict(best, group_lanes=gl)
             t, _ = _time_numeric(A, B, cand, reps)
@@ -114,10 +130,9 @@ class Autotuner:
 
         if not pairs:
             return []
-        keys = []
-        for A, B in pairs:
-            fl = int((torch.diff(B.rowptr).to(torch.int64)[A.colidx.to(torch.int64)]).sum()) if A.nnz else 0
-            keys.append(features(A, B, fl))
+        # products per instance from the library (its symbolic pass at plan time)
+        fls = Batched(pairs).flops()
+        keys = [features(A, B, fl) for (A, B), fl in zip(pairs, fls)]
         key = "batch:" + "|".join(sorted(keys))
         if key in self.cache:
             best = dict(self.cache[key])

@@ -95,7 +95,7 @@ static int plan_alloc_host(Plan* p) {
 void plan_free(Plan* p) {
   for (DevBuf* b : {&p->bbits, &p->cbits, &p->flops, &p->cnt, &p->scan, &p->sym_items, &p->num_items,
                     &p->split_rows, &p->partial, &p->ctr, &p->maskbits, &p->gb_items, &p->gb_split,
-                    &p->gb_partial, &p->gb_ctr, &p->cpos})
+                    &p->gb_partial, &p->gb_ctr, &p->gb_gbuf, &p->gb_pos_a, &p->gb_pos_at, &p->gb_lens, &p->gb_scan})
     b->release();
   if (p->host_ctr) (void)hipHostFree(p->host_ctr);
   p->host_ctr = nullptr;
@@ -176,7 +176,7 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   p->a_nnz = A->nnz;
   p->b_nnz = B->nnz;
   p->ready = false;
-  p->cpos_ready = false;
+  p->gb_pos_ready = false;
   p->hash = true;
   p->masked = M && M->kind != TSSPGEMM_MASK_NONE;
   if ((rc = plan_alloc_host(p))) return rc;
@@ -350,7 +350,7 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   p->a_nnz = A->nnz;
   p->b_nnz = B->nnz;
   p->ready = false;
-  p->cpos_ready = false;
+  p->gb_pos_ready = false;
   p->masked = M && M->kind != TSSPGEMM_MASK_NONE;
   if ((rc = plan_alloc_host(p))) return rc;
   const int64_t sym_cap = n + A->nnz / tn.sym_split_nnz + 2;

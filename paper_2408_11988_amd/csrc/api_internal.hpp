@@ -46,8 +46,12 @@ struct Plan {
   DevBuf bbits, cbits, flops, cnt, scan, sym_items, num_items, split_rows, partial, ctr, maskbits;
   DevBuf gb_items, gb_split, gb_partial, gb_ctr;  // dL/dB work lists
   DevBuf bcol;             // B's column ids narrowed to col_id_bytes(d) bytes (numeric phase)
-  DevBuf cpos;             // dL/dB: per C bitmap word, (position of its first entry) << 32 | bits
-  bool cpos_ready = false;
+  // dL/dB from sampled G: G(i, j) of every product, in blocks per A entry
+  // (A order), and the start of each A entry's block in A order and in A^T
+  // order (built once per plan: the patterns are fixed)
+  DevBuf gb_gbuf, gb_pos_a, gb_pos_at, gb_lens, gb_scan;
+  bool gb_pos_ready = false;
+  int64_t gb_total = 0;     // products of the plan = entries of gb_gbuf (the last block start)
   bool masked = false;     // symbolic phase ran with a complement mask
   bool hash = false;       // hash accumulator plan (no bitmaps, no work lists)
   DevBuf hmask_rp, hmask_ci, hmask_bits;  // hash plan: copy of the complement mask

@@ -4,19 +4,26 @@
 //  dL/dB(k,j) = sum over i in pat(A^T_k) of A(i,k) G(i,j) (A^T G sampled on pat(B))
 //
 // Every needed G(i,j) lies in pat(C): if A(i,k) and B(k,j) are stored, the
-// structural product stores C(i,j). Both passes accumulate in FP64 in a fixed
-// order and round once to FP32.
+// structural product stores C(i,j). Both gradients accumulate in FP64 in a
+// fixed order and round once to FP32.
 //
-// dL/dA reuses the forward plan's binned rows: a row's G values are staged in
-// an LDS strip of width d, and each A entry (i,k) is a dot product of B row k
-// with that strip, taken by a group of GL lanes and reduced across the group.
+// First pass, over A's rows (the forward plan's binned rows): a row's G
+// values are staged in an LDS strip of width d; each A entry (i,k) is a dot
+// product of B row k with that strip (dL/dA), taken by a group of GL lanes
+// and reduced across the group. For dL/dB the same walk writes every G(i,j)
+// it reads into a block per A entry (i,k): the values of G(i, pat(B_k)) in B
+// row order, blocks in A order. The FP32 values are copied, not rounded.
 //
-// dL/dB walks A^T (from tsspgemm_transpose): a group of GL lanes owns the
-// entries of one B row k (lane = column j) and runs over the rows i of A^T
-// row k; G(i,j) sits at C.rowptr[i] + the rank of j in C's bitmap row i (the
-// symbolic pass's accumulator), read from a per-word record that holds the
-// word's bits and the position of its first entry. Long A^T rows are cut into chunks whose
-// partial sums a second kernel adds in chunk order.
+// Second pass, over A^T (from tsspgemm_transpose): a group of GL lanes owns
+// the entries of one B row k (lane = entry) and runs over the entries i of
+// A^T row k in order, adding A(i,k) G(i,j) from block (i,k); consecutive
+// lanes read consecutive floats of a block. Long A^T rows are cut into
+// chunks whose partial sums a third kernel adds in chunk order.
+//
+// A single pass over A^T that looked G(i,j) up in C's row i (a record of
+// C's bitmap word plus a popcount) reread whole cache lines of G for every
+// (B row, A^T entry) pair: about 15 GB per call at R-MAT 20 x 256, against
+// the 1.6 GB of blocks written and read here.
 #include "api_internal.hpp"
 #include "dev_numeric.hpp"
 
@@ -42,32 +49,40 @@ struct GradAParams {
   Problem pr;             // A, B, C pattern (crp, cbits) of the forward plan
   const int32_t* gci;     // G = dL/dC on C's pattern
   const float* gval;
-  float* grad_a;
+  float* grad_a;          // dL/dA, or null (only the sampled G is written)
+  float* gbuf;            // sampled G for dL/dB, or null: G(i, j) for every product of (i,k) and (k,j)
+  const int64_t* pos_a;   // per A entry p = (i,k): start of its block of nnz(B_k) values in gbuf
   const Item* items;
   int32_t n_wg_items, n_heavy_records, n_light;
 };
 
 // Dot products of staged A entries: stage[e] = (start, end) of B row k for
-// the entry base + e of the row, e in [0, nb); group grp of ngroups takes
-// blocks of U entries grp * U, (grp + ngroups) * U, ... Lanes of a group walk
-// the B row (column ids narrowed to IdxT) against the row's G strip; each
-// dot product is summed over the group in FP64 and rounded once.
-template <int GL, typename IdxT>
-__device__ __forceinline__ void grad_a_staged(const GradAParams& gp, int base, int nb, const int2* stage, int grp,
+// the entry base + e of the row (and, with GATHER, the start of the entry's
+// block in gbuf), e in [0, nb); group grp of ngroups takes blocks of U entries
+// grp * U, (grp + ngroups) * U, ... Lanes of a group walk the B row (column
+// ids narrowed to IdxT) against the row's G strip; each dot product is summed
+// over the group in FP64 and rounded once. With GATHER, each G(i, j) the walk
+// reads is also written to the entry's block at the position of j in B row k
+// (lanes of a group write consecutive floats).
+template <int GL, typename IdxT, bool GATHER>
+__device__ __forceinline__ void grad_a_staged(const GradAParams& gp, int base, int nb, const int4* stage, int grp,
                                               int ngroups, const float* strip) {
   constexpr int U = 4;
   const int gl = threadIdx.x % GL;
   const Problem& pr = gp.pr;
   const float* __restrict__ bval = (const float*)pr.bval;
   const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
+  float* __restrict__ gbuf = gp.gbuf;
   for (int e0 = grp * U; e0 < nb; e0 += ngroups * U) {
     int q[U], qe[U];
+    int64_t wb[U];  // gbuf index of B entry q of this entry's row: wb + q
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      int2 r = make_int2(0, 0);
+      int4 r = make_int4(0, 0, 0, 0);
       if (e0 + u < nb) r = stage[e0 + u];
       q[u] = r.x + gl;
       qe[u] = r.y;
+      wb[u] = (int64_t)(((uint64_t)(uint32_t)r.w << 32) | (uint32_t)r.z) - r.x;
     }
     int jj[U];
     float bv[U];
@@ -83,24 +98,43 @@ __device__ __forceinline__ void grad_a_staged(const GradAParams& gp, int base, i
     double sum[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      sum[u] = q[u] < qe[u] ? (double)bv[u] * (double)strip[jj[u]] : 0.0;
-      for (int t = q[u] + GL; t < qe[u]; t += GL) sum[u] += (double)bval[t] * (double)strip[bci[t]];
+      sum[u] = 0.0;
+      if (q[u] < qe[u]) {
+        const float g = strip[jj[u]];
+        sum[u] = (double)bv[u] * (double)g;
+        if constexpr (GATHER) gbuf[wb[u] + q[u]] = g;
+      }
+      for (int t = q[u] + GL; t < qe[u]; t += GL) {
+        const float g = strip[bci[t]];
+        sum[u] += (double)bval[t] * (double)g;
+        if constexpr (GATHER) gbuf[wb[u] + t] = g;
+      }
     }
+    if (gp.grad_a) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const double v = group_sum<GL>(sum[u]);
-      if (gl == 0 && e0 + u < nb) gp.grad_a[base + e0 + u] = (float)v;
+      for (int u = 0; u < U; ++u) {
+        const double v = group_sum<GL>(sum[u]);
+        if (gl == 0 && e0 + u < nb) gp.grad_a[base + e0 + u] = (float)v;
+      }
     }
   }
 }
 
 // Stage entries [base, base + nb) of A (nb <= the caller's lanes): lane t of
-// the stagers loads entry base + t and its B row bounds.
-__device__ __forceinline__ void grad_a_stage(const Problem& pr, int base, int nb, int t, int2* stage) {
-  int2 e = make_int2(0, 0);
+// the stagers loads entry base + t, its B row bounds and (GATHER) the start
+// of its block in gbuf.
+template <bool GATHER>
+__device__ __forceinline__ void grad_a_stage(const GradAParams& gp, int base, int nb, int t, int4* stage) {
+  int4 e = make_int4(0, 0, 0, 0);
   if (t < nb) {
-    const int k = pr.aci[base + t];
-    e = make_int2(pr.brp[k], pr.brp[k + 1]);
+    const int k = gp.pr.aci[base + t];
+    e.x = gp.pr.brp[k];
+    e.y = gp.pr.brp[k + 1];
+    if constexpr (GATHER) {
+      const uint64_t w = (uint64_t)gp.pos_a[base + t];
+      e.z = (int32_t)(uint32_t)w;
+      e.w = (int32_t)(uint32_t)(w >> 32);
+    }
   }
   stage[t] = e;
 }
@@ -108,7 +142,7 @@ __device__ __forceinline__ void grad_a_stage(const Problem& pr, int base, int nb
 // Workgroup items (split chunks, workgroup rows) and wavefront rows. A
 // wavefront stages 64 A entries at a time (coalesced) and its 64/GL groups
 // share them.
-template <int GL, typename IdxT>
+template <int GL, typename IdxT, bool GATHER>
 __global__ __launch_bounds__(kBlock) void k_grad_a(GradAParams gp) {
   extern __shared__ __align__(16) float gstrip[];
   const Problem& pr = gp.pr;
@@ -116,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_a(GradAParams gp) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = blockIdx.x;
   constexpr int GPW = kWave / GL;
-  int2* stage = (int2*)(gstrip + kWavesPerBlock * d) + wave * kWave;
+  int4* stage = (int4*)(gstrip + kWavesPerBlock * ((d + 3) & ~3)) + wave * kWave;
   if (g < gp.n_wg_items) {
     const Item it = gp.items[g];
     float* strip = gstrip;
@@ -124,9 +158,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_a(GradAParams gp) {
     __syncthreads();
     for (int base = it.p0 + kWave * wave; base < it.p1; base += kWave * kWavesPerBlock) {
       const int nb = min(kWave, it.p1 - base);
-      grad_a_stage(pr, base, nb, lane, stage);
+      grad_a_stage<GATHER>(gp, base, nb, lane, stage);
       wave_sync();
-      grad_a_staged<GL, IdxT>(gp, base, nb, stage, lane / GL, GPW, strip);
+      grad_a_staged<GL, IdxT, GATHER>(gp, base, nb, stage, lane / GL, GPW, strip);
       wave_sync();
     }
   } else {
@@ -138,32 +172,32 @@ __global__ __launch_bounds__(kBlock) void k_grad_a(GradAParams gp) {
     wave_sync();
     for (int base = it.p0; base < it.p1; base += kWave) {
       const int nb = min(kWave, it.p1 - base);
-      grad_a_stage(pr, base, nb, lane, stage);
+      grad_a_stage<GATHER>(gp, base, nb, lane, stage);
       wave_sync();
-      grad_a_staged<GL, IdxT>(gp, base, nb, stage, lane / GL, GPW, strip);
+      grad_a_staged<GL, IdxT, GATHER>(gp, base, nb, stage, lane / GL, GPW, strip);
       wave_sync();
     }
   }
 }
 
 // Light rows: one group (one strip, GL staged entries) per row.
-template <int GL, typename IdxT>
+template <int GL, typename IdxT, bool GATHER>
 __global__ __launch_bounds__(kBlock) void k_grad_a_light(GradAParams gp) {
   extern __shared__ __align__(16) float gstrip[];
   constexpr int G = kBlock / GL;
   const Problem& pr = gp.pr;
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
   float* strip = gstrip + grp * pr.d;
-  int2* stage = (int2*)(gstrip + G * pr.d) + grp * GL;
+  int4* stage = (int4*)(gstrip + G * ((pr.d + 3) & ~3)) + grp * GL;
   const Item* items = gp.items + gp.n_heavy_records;
   for (int64_t t = (int64_t)blockIdx.x * G + grp; t < gp.n_light; t += (int64_t)gridDim.x * G) {
     const Item it = items[t];
     for (int q = pr.crp[it.row] + gl; q < pr.crp[it.row + 1]; q += GL) strip[gp.gci[q]] = gp.gval[q];
     for (int base = it.p0; base < it.p1; base += GL) {
       const int nb = min(GL, it.p1 - base);
-      grad_a_stage(pr, base, nb, gl, stage);
+      grad_a_stage<GATHER>(gp, base, nb, gl, stage);
       wave_sync();
-      grad_a_staged<GL, IdxT>(gp, base, nb, stage, 0, 1, strip);
+      grad_a_staged<GL, IdxT, GATHER>(gp, base, nb, stage, 0, 1, strip);
       wave_sync();
     }
   }
@@ -178,13 +212,14 @@ __global__ void k_zero_f32(float* p, int64_t n) {
 // ---------------------------------------------------------------- dL/dB
 
 struct GradBParams {
-  Problem pr;                // A values, B pattern, C pattern (crp, cbits)
-  const uint64_t* cpos;      // n x wp C records: (C.rowptr[i] + set bits before word w) << 32 | bits of word w
+  Problem pr;                // A values, B pattern
   const int32_t* atrp;       // A^T row pointers (n + 1)
   const int32_t* atci;       // A^T rows i
   const int32_t* perm;       // position in A of each A^T entry
   const float* gval;         // G on C's pattern
   float* grad_b;
+  const float* gbuf;         // sampled G written by the first pass (k_grad_b_sampled)
+  const int64_t* pos_at;     // start of each A^T entry's block in gbuf
   Item* items;               // [split chunks][whole rows]: row = k, [p0,p1) range of A^T entries
   SplitRow* split_rows;
   double* partial;           // chunk partial sums (slot x d)
@@ -272,84 +307,55 @@ __global__ void k_gb_bin_fill(GradBParams gb) {
   }
 }
 
-// C position records for dL/dB: records[i * wp + w] = (rowptr[i] + set bits
-// of words 0..w-1 of row i) << 32 | bits[i * wp + w]
-__global__ void k_build_recs(int64_t n, int wp, const uint32_t* __restrict__ bits, const int32_t* __restrict__ rowptr,
-                             uint64_t* __restrict__ rec) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t pos = (uint32_t)rowptr[i];
-    for (int w = 0; w < wp; ++w) {
-      const uint32_t b = bits[i * wp + w];
-      rec[i * wp + w] = ((uint64_t)pos << 32) | b;
-      pos += __popc(b);
-    }
-  }
-}
-
-int launch_build_recs(int64_t n, int wp, const uint32_t* bits, const int32_t* rowptr, uint64_t* rec, hipStream_t st) {
-  if (n <= 0) return TSSPGEMM_OK;
-  int64_t g = (n + 255) / 256;
-  if (g > 8192) g = 8192;
-  k_build_recs<<<(unsigned)g, 256, 0, st>>>(n, wp, bits, rowptr, rec);
-  TSS_CHECK_LAUNCH();
-  return TSSPGEMM_OK;
-}
-
-// One group of GL lanes per item, items walked with a grid stride. Lanes own
-// the B row's entries (GL at a time); a lane's sum runs over the item's A^T
-// entries in order. The group loads GL A^T entries at once (row i and the
-// value A(i,k), coalesced) and shares them through LDS, so the per-entry
-// chain is the record of G's row and the G value only.
+// dL/dB from the sampled G written by the first pass: the block of A entry
+// (i,k) holds G(i, j) for the entries (k, j) of B row k, in B row order, at
+// pos[x] for the x-th entry of A^T. A group of GL lanes owns B row k's
+// entries (GL at a time); a lane's sum runs over the item's A^T entries in
+// order, so each step reads GL consecutive floats of one block. The group
+// stages GL A^T entries at once (block start and A(i,k)) and shares them
+// through LDS; U blocks are read before their sums.
 template <int GL>
-__global__ __launch_bounds__(kBlock) void k_grad_b(GradBParams gb) {
+__global__ __launch_bounds__(kBlock) void k_grad_b_sampled(GradBParams gb) {
   constexpr int G = kBlock / GL;
   constexpr int U = 8;
-  __shared__ int2 stage_s[kBlock];
+  __shared__ int4 stage_s[kBlock];
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
-  int2* stage = stage_s + grp * GL;
+  int4* stage = stage_s + grp * GL;
   const Problem& pr = gb.pr;
   const float* __restrict__ aval = (const float*)pr.aval;
-  const int wp = pr.wp;
+  const float* __restrict__ gbuf = gb.gbuf;
   const int total = gb.ctr->num_split_items + gb.ctr->num_light_rows;
   for (int64_t t = (int64_t)blockIdx.x * G + grp; t < total; t += (int64_t)gridDim.x * G) {
     const Item it = gb.items[t];
     const int k = it.row;
     const int q0 = pr.brp[k], q1 = pr.brp[k + 1];
     for (int qb = q0; qb < q1; qb += GL) {
-      const int q = qb + gl;
-      const bool own = q < q1;
-      const int j = own ? pr.bci[q] : 0;
-      const int jw = j >> 5;
-      const uint32_t below = (1u << (j & 31)) - 1u;
+      const int e = qb - q0 + gl;
+      const bool own = qb + gl < q1;
       double acc = 0.0;
       for (int xb = it.p0; xb < it.p1; xb += GL) {
         const int nb = min(GL, it.p1 - xb);
-        int2 e = make_int2(0, 0);
+        int4 r = make_int4(0, 0, 0, 0);
         if (gl < nb) {
-          e.x = gb.atci[xb + gl];
-          e.y = __builtin_bit_cast(int32_t, aval[gb.perm[xb + gl]]);
+          const uint64_t w = (uint64_t)gb.pos_at[xb + gl];
+          r.x = (int32_t)(uint32_t)w;
+          r.y = (int32_t)(uint32_t)(w >> 32);
+          r.z = __builtin_bit_cast(int32_t, aval[gb.perm[xb + gl]]);
         }
         wave_sync();
-        stage[gl] = e;
+        stage[gl] = r;
         wave_sync();
-        for (int s = 0; s < nb; s += U) {
-          int i[U];
-          float a[U];
+        for (int s0 = 0; s0 < nb; s0 += U) {
+          float a[U], g[U];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            int2 r = make_int2(-1, 0);
-            if (s + u < nb) r = stage[s + u];
-            i[u] = r.x;
-            a[u] = __builtin_bit_cast(float, r.y);
-          }
-          uint64_t r[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) r[u] = (own && i[u] >= 0) ? gb.cpos[(int64_t)i[u] * wp + jw] : 0ull;
-          float g[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
+            a[u] = 0.0f;
             g[u] = 0.0f;
-            if (own && i[u] >= 0) g[u] = gb.gval[(uint32_t)(r[u] >> 32) + __popc((uint32_t)r[u] & below)];
+            if (own && s0 + u < nb) {
+              const int4 x = stage[s0 + u];
+              a[u] = __builtin_bit_cast(float, x.z);
+              g[u] = gbuf[(int64_t)(((uint64_t)(uint32_t)x.y << 32) | (uint32_t)x.x) + e];
+            }
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)g[u];
@@ -358,12 +364,29 @@ __global__ __launch_bounds__(kBlock) void k_grad_b(GradBParams gb) {
       }
       if (own) {
         if (it.aux == kNoSlot)
-          gb.grad_b[q] = (float)acc;
+          gb.grad_b[q0 + e] = (float)acc;
         else
-          gb.partial[(int64_t)it.aux * pr.d + (q - q0)] = acc;
+          gb.partial[(int64_t)it.aux * pr.d + e] = acc;
       }
     }
   }
+}
+
+// Block starts of the sampled G, built once per plan: lens[p] = nnz of the B
+// row of A entry p; pos_a = exclusive prefix sums of lens (A order); pos_at[x]
+// = pos_a[perm[x]] (A^T order).
+__global__ void k_bw_lens(int64_t nnz, const int32_t* __restrict__ aci, const int32_t* __restrict__ brp,
+                          int32_t* __restrict__ lens) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+    const int k = aci[p];
+    lens[p] = brp[k + 1] - brp[k];
+  }
+}
+
+__global__ void k_bw_pos_at(int64_t nnz, const int32_t* __restrict__ perm, const int64_t* __restrict__ pos_a,
+                            int64_t* __restrict__ pos_at) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nnz; x += (int64_t)gridDim.x * blockDim.x)
+    pos_at[x] = pos_a[perm[x]];
 }
 
 __global__ void k_grad_b_finalize(GradBParams gb) {
@@ -427,11 +450,124 @@ static Problem plan_problem(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* 
 
 int light_group_lanes(int group_lanes, int64_t d, int sr);
 
-static int run_grad_a(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_a,
-                      hipStream_t st) {
+// The first pass over A's rows (the forward plan's binned items): dL/dA dot
+// products into grad_a (if non-null) and, with gather, the sampled G into
+// gp.gbuf at gp.pos_a.
+static int launch_grad_a_pass(Plan* p, GradAParams& gp, const tsspgemm_csr* B, bool gather, hipStream_t st) {
+  // a group per B row of dot product: the smallest power of two covering the
+  // mean B row length (the reduction over the group costs log2(GL) steps)
+  const double mean_b = p->n > 0 ? (double)B->nnz / (double)p->n : 0.0;
+  int gl = 4;
+  while (gl < 64 && gl < mean_b) gl <<= 1;
+  const int64_t dq = (p->d + 3) & ~3;  // strips padded so the staged records stay 16-byte aligned
+  const int64_t grid = gp.n_wg_items + (p->n_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
+  const size_t lds = (size_t)kWavesPerBlock * dq * 4 + kBlock * sizeof(int4);
+  const int lgl = light_group_lanes(gl, p->d, TSSPGEMM_PLUS_TIMES_I32);  // float strips: 4 bytes
+  const size_t llds = (size_t)(kBlock / lgl) * dq * 4 + kBlock * sizeof(int4);
+  int64_t lgrid = (gp.n_light + (kBlock / lgl) - 1) / (kBlock / lgl);
+  if (lgrid > 2048) lgrid = 2048;
+  const bool b8 = col_id_bytes(p->d) == 1;
+  gp.pr.bcol = p->bcol.p;
+#define TSS_GA_T(GLV, GA)                                                                              \
+  if (b8)                                                                                              \
+    k_grad_a<GLV, uint8_t, GA><<<(unsigned)grid, kBlock, lds, st>>>(gp);                               \
+  else                                                                                                 \
+    k_grad_a<GLV, uint16_t, GA><<<(unsigned)grid, kBlock, lds, st>>>(gp);
+#define TSS_GA(GLV)                                                                                    \
+  case GLV:                                                                                            \
+    if (grid > 0) {                                                                                    \
+      if (gather) {                                                                                    \
+        TSS_GA_T(GLV, true)                                                                            \
+      } else {                                                                                         \
+        TSS_GA_T(GLV, false)                                                                           \
+      }                                                                                                \
+    }                                                                                                  \
+    break;
+#define TSS_GAL_T(GLV, GA)                                                                             \
+  if (b8)                                                                                              \
+    k_grad_a_light<GLV, uint8_t, GA><<<(unsigned)lgrid, kBlock, llds, st>>>(gp);                       \
+  else                                                                                                 \
+    k_grad_a_light<GLV, uint16_t, GA><<<(unsigned)lgrid, kBlock, llds, st>>>(gp);
+#define TSS_GAL(GLV)                                                                                   \
+  case GLV:                                                                                            \
+    if (lgrid > 0) {                                                                                   \
+      if (gather) {                                                                                    \
+        TSS_GAL_T(GLV, true)                                                                           \
+      } else {                                                                                         \
+        TSS_GAL_T(GLV, false)                                                                          \
+      }                                                                                                \
+    }                                                                                                  \
+    break;
+  switch (gl) {
+    TSS_GA(4) TSS_GA(8) TSS_GA(16) TSS_GA(32) TSS_GA(64)
+    default: set_error("backward: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  }
+  switch (lgl) {
+    TSS_GAL(4) TSS_GAL(8) TSS_GAL(16) TSS_GAL(32) TSS_GAL(64)
+    default: set_error("backward: bad light group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  }
+#undef TSS_GA
+#undef TSS_GAL
+#undef TSS_GA_T
+#undef TSS_GAL_T
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
+
+// Block starts of the sampled G (once per plan): A order by a prefix sum of
+// the B row lengths of A's entries, A^T order through perm.
+static int ensure_sampled_positions(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, const int32_t* perm,
+                                    hipStream_t st) {
+  if (p->gb_pos_ready) return TSSPGEMM_OK;
   int rc;
-  if ((rc = check_grad_args(p, A, B, G, grad_a, "grad_a"))) return rc;
-  if (A->nnz == 0) return TSSPGEMM_OK;
+  const int64_t nnz = A->nnz;
+  if ((rc = p->gb_lens.ensure((size_t)nnz * 4)) || (rc = p->gb_pos_a.ensure((size_t)(nnz + 1) * 8)) ||
+      (rc = p->gb_pos_at.ensure((size_t)nnz * 8)) || (rc = p->gb_scan.ensure((size_t)exscan_workspace_bytes(nnz))))
+    return rc;
+  const unsigned g = grid_for(nnz, 256) > 8192 ? 8192 : grid_for(nnz, 256);
+  k_bw_lens<<<g, 256, 0, st>>>(nnz, A->colidx, B->rowptr, (int32_t*)p->gb_lens.p);
+  TSS_CHECK_LAUNCH();
+  if ((rc = launch_exscan_i32_to_i64((const int32_t*)p->gb_lens.p, nnz, (int64_t*)p->gb_pos_a.p,
+                                     (int64_t*)p->gb_scan.p, st)))
+    return rc;
+  k_bw_pos_at<<<g, 256, 0, st>>>(nnz, perm, (const int64_t*)p->gb_pos_a.p, (int64_t*)p->gb_pos_at.p);
+  TSS_CHECK_LAUNCH();
+  // the buffer of sampled G is sized by the scan's total (synchronizes once per plan)
+  int64_t total = 0;
+  TSS_HIP(hipMemcpyAsync(&total, (const int64_t*)p->gb_pos_a.p + nnz, 8, hipMemcpyDeviceToHost, st));
+  TSS_HIP(hipStreamSynchronize(st));
+  p->gb_total = total;
+  p->gb_pos_ready = true;
+  return TSSPGEMM_OK;
+}
+
+// dL/dA and / or dL/dB (either output may be null, not both). dL/dB reads
+// A^T and perm. With both, the pass over A's rows computes dL/dA and writes
+// the sampled G that the dL/dB pass sums.
+static int run_backward(Plan* p, const tsspgemm_csr* AT, const int32_t* perm, const tsspgemm_csr* A,
+                        const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_a, float* grad_b,
+                        const char* who, hipStream_t st) {
+  int rc;
+  if ((rc = check_grad_args(p, A, B, G, grad_a ? (const void*)grad_a : (const void*)grad_b, who))) return rc;
+  if (grad_b) {
+    if ((rc = check_csr(AT, "AT", false))) return rc;
+    if (AT->nrows != p->n || AT->nnz != A->nnz || (A->nnz > 0 && !perm)) {
+      set_error(std::string(who) + ": AT / perm do not match A");
+      return TSSPGEMM_ERR_INVALID_ARG;
+    }
+  }
+  const int64_t n = p->n, nnz = A->nnz;
+  if (grad_a && nnz > 0) {
+    const unsigned gz = grid_for(nnz, 256 * 4) > 8192 ? 8192 : grid_for(nnz, 256 * 4);
+    k_zero_f32<<<gz, 256, 0, st>>>(grad_a, nnz);
+  }
+  if (grad_b && B->nnz > 0) {
+    const unsigned gz = grid_for(B->nnz, 256 * 4) > 8192 ? 8192 : grid_for(B->nnz, 256 * 4);
+    k_zero_f32<<<gz, 256, 0, st>>>(grad_b, B->nnz);
+  }
+  TSS_CHECK_LAUNCH();
+  if (nnz == 0 || B->nnz == 0) return TSSPGEMM_OK;  // no products: every gradient is 0
+  const bool gather = grad_b != nullptr;
   GradAParams gp{};
   gp.pr = plan_problem(p, A, B);
   gp.gci = G->colidx;
@@ -441,103 +577,50 @@ static int run_grad_a(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, con
   gp.n_wg_items = (int32_t)(p->n_split_items + p->n_block_items);
   gp.n_heavy_records = (int32_t)(p->n_split_items + p->n_block_items + p->n_wave_rows);
   gp.n_light = (int32_t)p->n_light_rows;
-  const unsigned gz = grid_for(A->nnz, 256 * 4) > 8192 ? 8192 : grid_for(A->nnz, 256 * 4);
-  k_zero_f32<<<gz, 256, 0, st>>>(grad_a, A->nnz);
-  // a group per B row of dot product: the smallest power of two covering the
-  // mean B row length (the reduction over the group costs log2(GL) steps)
-  const double mean_b = p->n > 0 ? (double)B->nnz / (double)p->n : 0.0;
-  int gl = 4;
-  while (gl < 64 && gl < mean_b) gl <<= 1;
-  const int64_t grid = gp.n_wg_items + (p->n_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
-  const size_t lds = (size_t)kWavesPerBlock * p->d * 4 + kBlock * sizeof(int2);
-  const int lgl = light_group_lanes(gl, p->d, TSSPGEMM_PLUS_TIMES_I32);  // float strips: 4 bytes
-  const size_t llds = (size_t)(kBlock / lgl) * p->d * 4 + kBlock * sizeof(int2);
-  int64_t lgrid = (gp.n_light + (kBlock / lgl) - 1) / (kBlock / lgl);
-  if (lgrid > 2048) lgrid = 2048;
-  const bool b8 = col_id_bytes(p->d) == 1;
-  gp.pr.bcol = p->bcol.p;
-#define TSS_GA(GLV)                                                                                    \
-  case GLV:                                                                                            \
-    if (grid > 0) {                                                                                    \
-      if (b8)                                                                                          \
-        k_grad_a<GLV, uint8_t><<<(unsigned)grid, kBlock, lds, st>>>(gp);                               \
-      else                                                                                             \
-        k_grad_a<GLV, uint16_t><<<(unsigned)grid, kBlock, lds, st>>>(gp);                              \
-    }                                                                                                  \
-    break;
-#define TSS_GAL(GLV)                                                                                   \
-  case GLV:                                                                                            \
-    if (lgrid > 0) {                                                                                   \
-      if (b8)                                                                                          \
-        k_grad_a_light<GLV, uint8_t><<<(unsigned)lgrid, kBlock, llds, st>>>(gp);                       \
-      else                                                                                             \
-        k_grad_a_light<GLV, uint16_t><<<(unsigned)lgrid, kBlock, llds, st>>>(gp);                      \
-    }                                                                                                  \
-    break;
-  switch (gl) {
-    TSS_GA(4) TSS_GA(8) TSS_GA(16) TSS_GA(32) TSS_GA(64)
-    default: set_error("grad_a: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+  if (gather) {
+    if ((rc = ensure_sampled_positions(p, A, B, perm, st))) return rc;
+    if ((rc = p->gb_gbuf.ensure((size_t)(p->gb_total > 0 ? p->gb_total : 1) * 4))) return rc;
+    gp.gbuf = (float*)p->gb_gbuf.p;
+    gp.pos_a = (const int64_t*)p->gb_pos_a.p;
   }
-  switch (lgl) {
-    TSS_GAL(4) TSS_GAL(8) TSS_GAL(16) TSS_GAL(32) TSS_GAL(64)
-    default: set_error("grad_a: bad light group width"); return TSSPGEMM_ERR_INVALID_ARG;
-  }
-#undef TSS_GA
-#undef TSS_GAL
-  TSS_CHECK_LAUNCH();
-  return TSSPGEMM_OK;
-}
-
-static int run_grad_b(Plan* p, const tsspgemm_csr* AT, const int32_t* perm, const tsspgemm_csr* A,
-                      const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_b, hipStream_t st) {
-  int rc;
-  if ((rc = check_grad_args(p, A, B, G, grad_b, "grad_b"))) return rc;
-  if ((rc = check_csr(AT, "AT", false))) return rc;
-  if (AT->nrows != p->n || AT->nnz != A->nnz || (A->nnz > 0 && !perm)) {
-    set_error("grad_b: AT / perm do not match A");
-    return TSSPGEMM_ERR_INVALID_ARG;
-  }
-  if (B->nnz == 0) return TSSPGEMM_OK;
-  const int64_t n = p->n, nnz = A->nnz;
+  if ((rc = launch_grad_a_pass(p, gp, B, gather, st))) return rc;
+  if (!gather) return TSSPGEMM_OK;
   // a row of m > kGbChunk entries has ceil(m / kGbChunk) <= 2 m / kGbChunk chunks
   const int64_t chunk_cap = 2 * nnz / kGbChunk + 2;
   if ((rc = p->gb_items.ensure((size_t)(n + chunk_cap) * sizeof(Item))) ||
       (rc = p->gb_split.ensure((size_t)(n + 1) * sizeof(SplitRow))) ||
       (rc = p->gb_partial.ensure((size_t)chunk_cap * p->d * 8)) || (rc = p->gb_ctr.ensure(sizeof(Counters))))
     return rc;
-  if (!p->cpos_ready) {  // the C pattern is fixed for the plan: built once
-    if ((rc = p->cpos.ensure((size_t)n * p->wp * sizeof(uint64_t)))) return rc;
-    if ((rc = launch_build_recs(n, p->wp, (const uint32_t*)p->cbits.p, p->crp, (uint64_t*)p->cpos.p, st))) return rc;
-    p->cpos_ready = true;
-  }
   GradBParams gb{};
   gb.pr = plan_problem(p, A, B);
-  gb.cpos = (const uint64_t*)p->cpos.p;
   gb.atrp = AT->rowptr;
   gb.atci = AT->colidx;
   gb.perm = perm;
   gb.gval = (const float*)G->vals;
   gb.grad_b = grad_b;
+  gb.gbuf = (const float*)p->gb_gbuf.p;
+  gb.pos_at = (const int64_t*)p->gb_pos_at.p;
   gb.items = (Item*)p->gb_items.p;
   gb.split_rows = (SplitRow*)p->gb_split.p;
   gb.partial = (double*)p->gb_partial.p;
   gb.ctr = (Counters*)p->gb_ctr.p;
-  const unsigned gz = grid_for(B->nnz, 256 * 4) > 8192 ? 8192 : grid_for(B->nnz, 256 * 4);
-  k_zero_f32<<<gz, 256, 0, st>>>(grad_b, B->nnz);
   if ((rc = launch_zero_bytes(gb.ctr, sizeof(Counters), st))) return rc;
   const unsigned g = grid_for(n, 256);
   k_gb_bin_count<<<g, 256, 0, st>>>(gb);
   k_gb_bin_scan<<<1, 1, 0, st>>>(gb.ctr);
   k_gb_bin_fill<<<g, 256, 0, st>>>(gb);
-  const int gl = p->tune.group_lanes;
+  // lanes per B row: the smallest power of two covering the mean B row length
+  const double mean_b = (double)B->nnz / (double)n;
+  int gl = 4;
+  while (gl < 64 && gl < mean_b) gl <<= 1;
   const unsigned grid = 2048;
-#define TSS_GB(GLV)                                   \
-  case GLV:                                           \
-    k_grad_b<GLV><<<grid, kBlock, 0, st>>>(gb);       \
+#define TSS_GB(GLV)                                           \
+  case GLV:                                                   \
+    k_grad_b_sampled<GLV><<<grid, kBlock, 0, st>>>(gb);       \
     break;
   switch (gl) {
     TSS_GB(4) TSS_GB(8) TSS_GB(16) TSS_GB(32) TSS_GB(64)
-    default: set_error("grad_b: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+    default: set_error("backward: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
   }
 #undef TSS_GB
   k_grad_b_finalize<<<1024, 256, 0, st>>>(gb);
@@ -552,7 +635,12 @@ extern "C" {
 int tsspgemm_grad_a(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_csr* B, const tsspgemm_csr* G,
                     float* grad_a, void* stream) {
   try {
-    return tss::run_grad_a((tss::Plan*)plan, A, B, G, grad_a, (hipStream_t)stream);
+    if (!grad_a) {
+      tss::set_error("grad_a: NULL output");
+      return TSSPGEMM_ERR_INVALID_ARG;
+    }
+    return tss::run_backward((tss::Plan*)plan, nullptr, nullptr, A, B, G, grad_a, nullptr, "grad_a",
+                             (hipStream_t)stream);
   } catch (...) {
     tss::set_error("unexpected C++ exception");
     return TSSPGEMM_ERR_HIP;
@@ -562,7 +650,27 @@ int tsspgemm_grad_a(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_cs
 int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,
                     const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_b, void* stream) {
   try {
-    return tss::run_grad_b((tss::Plan*)plan, AT, at_perm, A, B, G, grad_b, (hipStream_t)stream);
+    if (!grad_b) {
+      tss::set_error("grad_b: NULL output");
+      return TSSPGEMM_ERR_INVALID_ARG;
+    }
+    return tss::run_backward((tss::Plan*)plan, AT, at_perm, A, B, G, nullptr, grad_b, "grad_b",
+                             (hipStream_t)stream);
+  } catch (...) {
+    tss::set_error("unexpected C++ exception");
+    return TSSPGEMM_ERR_HIP;
+  }
+}
+
+int tsspgemm_backward(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,
+                      const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_a, float* grad_b, void* stream) {
+  try {
+    if (!grad_a && !grad_b) {
+      tss::set_error("backward: both outputs are NULL");
+      return TSSPGEMM_ERR_INVALID_ARG;
+    }
+    return tss::run_backward((tss::Plan*)plan, AT, at_perm, A, B, G, grad_a, grad_b, "backward",
+                             (hipStream_t)stream);
   } catch (...) {
     tss::set_error("unexpected C++ exception");
     return TSSPGEMM_ERR_HIP;

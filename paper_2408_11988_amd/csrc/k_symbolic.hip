@@ -687,7 +687,35 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_write_i32(int64_t n, cons
   }
 }
 
+__global__ __launch_bounds__(kScanThreads) void k_scan_write_i64(int64_t n, const int32_t* __restrict__ in,
+                                                                const int64_t* __restrict__ block_sums,
+                                                                int64_t* __restrict__ out) {
+  __shared__ long long sh[32];
+  const int64_t base = (int64_t)blockIdx.x * kScanRows;
+  long long carry = block_sums[blockIdx.x];
+  for (int u = 0; u < kScanPer; ++u) {
+    const int64_t i = base + u * kScanThreads + threadIdx.x;
+    const long long v = i < n ? in[i] : 0;
+    long long tot;
+    const long long ex = block_exscan_1024(v, sh, &tot);
+    if (i < n) out[i] = carry + ex;
+    if (i == n - 1) out[n] = carry + ex + v;
+    carry += tot;
+  }
+}
+
 int64_t exscan_workspace_bytes(int64_t n) { return 8 * ((n + kScanRows - 1) / kScanRows + 1); }
+
+// out[0..n] = exclusive prefix sums of in[0..n) as int64 (out[n] = total).
+int launch_exscan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, int64_t* block_sums, hipStream_t st) {
+  const int64_t nb = (n + kScanRows - 1) / kScanRows;
+  if (nb == 0) return launch_zero_bytes(out, 8, st);
+  k_scan_sum_i32<<<(unsigned)nb, kScanThreads, 0, st>>>(n, in, block_sums);
+  k_scan_blocks_i64<<<1, kScanThreads, 0, st>>>(nb, block_sums, nullptr);
+  k_scan_write_i64<<<(unsigned)nb, kScanThreads, 0, st>>>(n, in, block_sums, out);
+  TSS_CHECK_LAUNCH();
+  return TSSPGEMM_OK;
+}
 
 // out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total, int32).
 int launch_exscan_i32(const int32_t* in, int64_t n, int32_t* out, int64_t* block_sums, hipStream_t st) {

@@ -88,6 +88,44 @@ def test_gradients_random(d):
         assert np.array_equal(ga, ga2) and np.array_equal(gb, gb2), tune
 
 
+@pytest.mark.parametrize("d", [5, 64, 256])
+def test_backward_one_call(d):
+    """tsspgemm_backward (one pass over A's rows writing dL/dA and the sampled
+    G, one over A^T for dL/dB) against the separate calls (bit for bit: the
+    same sums in the same order) and the oracle. A has dense columns, so
+    A^T rows span several dL/dB chunks, and dense rows (workgroup and split
+    rows of the forward plan)."""
+    rng = np.random.default_rng(900 + d)
+    n = 1500
+    a0 = random_csr(rng, n, n, 0.004, kind="normal", empty_rows=0.1, dense_rows=2)
+    pat = np.zeros((n, n), dtype=bool)
+    pat[rows_of(a0.rp), a0.ci] = True
+    pat[:, [7, 900]] = True  # two columns of n entries: A^T rows of 3 chunks
+    rp = np.zeros(n + 1, dtype=np.int32)
+    rp[1:] = np.cumsum(pat.sum(axis=1))
+    ci = np.nonzero(pat)[1].astype(np.int32)
+    a = synth.Csr(n, n, rp, ci, rng.standard_normal(len(ci)).astype(np.float32))
+    b = random_csr(rng, n, d, min(0.5, 6.0 / d + 0.02), kind="normal", empty_rows=0.1)
+    crp, cci, _ = oracle.spgemm(a.rp, a.ci, a.val, b.rp, b.ci, b.val)
+    g = rng.standard_normal(len(cci)).astype(np.float32).astype(np.float64)
+    tss = _tss()
+    for tune in (None, dict(light_max_flops=1, wave_max_flops=8, split_flops=64)):
+        note(f"backward one call n={n} d={d} tuning={tune}")
+        A, B = to_dev(a), to_dev(b)
+        C, plan = tss.spgemm(A, B, tuning=tune, return_plan=True)
+        G = C.with_vals(torch.from_numpy(g.astype(np.float32)).cuda())
+        AT, perm = tss.transpose(A)
+        ga, gb = tss.backward(plan, AT, perm, A, B, G)
+        ga1 = tss.grad_a(plan, A, B, G)
+        gb1 = tss.grad_b(plan, AT, perm, A, B, G)
+        ga_only, _ = tss.backward(plan, None, None, A, B, G, need_b=False)
+        _, gb_only = tss.backward(plan, AT, perm, A, B, G, need_a=False)
+        torch.cuda.synchronize()
+        assert torch.equal(ga, ga1) and torch.equal(gb, gb1)
+        assert torch.equal(ga, ga_only) and torch.equal(gb, gb_only)
+        _check(a, b, ga.cpu().numpy().astype(np.float64), gb.cpu().numpy().astype(np.float64), crp, cci, g)
+
+
 def test_gradients_match_fp64_finite_differences():
     """Differentiable-layer workload at n = 2048 (R-MAT scale 11), d = 32, B 5%
     N(0,1), W N(0,1): GPU gradients against FP64 central differences of the
