@@ -243,6 +243,24 @@ int tsspgemm_backward(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t*
 int tsspgemm_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C, int64_t ldc,
                   void* stream);
 
+/* The same SpMM for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * arguments, result and summation order are those of tsspgemm_spmm (the
+ * same kernels), but the workspace (counters, chunk list, long-row records,
+ * FP64 partial rows) lives in a fixed device array of the library of
+ * TSSPGEMM_SPMM_NOALLOC_MAX_BYTES per GPU, held from the first use on that
+ * GPU until the process ends. No hipMalloc, hipFree or allocating call is
+ * made. The workspace bound is about nnz(A) * d / 8 bytes
+ * (256 + (2 nnz/128 + 1) * (8 + 8 d) + (nnz/128 + 1) * 16, each part rounded
+ * up to 256 bytes); a larger problem returns TSSPGEMM_ERR_CAPACITY, with the
+ * bytes it would need in the message. Every call on one GPU shares that
+ * GPU's array (its counters are cleared by a kernel at the start of each
+ * call): calls that overlap on one GPU, on any streams, race.
+ * Asynchronous. Errors: INVALID_ARG, UNSUPPORTED (d > 1024), CAPACITY, HIP. */
+#define TSSPGEMM_SPMM_NOALLOC_MAX_BYTES (64ll << 20)
+int tsspgemm_spmm_noalloc(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C, int64_t ldc,
+                          void* stream);
+
 /* One pass of the sparse force-directed embedding update (Sec. IV-B) over
  * rows [row_begin, row_end) of Z, in minibatches of batch_rows rows taken in
  * row order (the minibatch is the tile height of Sec. IV-B).

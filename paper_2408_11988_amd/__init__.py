@@ -27,6 +27,7 @@ from .api import (  # noqa: F401
     numeric,
     spgemm,
     spmm,
+    spmm_noalloc,
     symbolic,
     tile_edges,
     tiled_spgemm,

@@ -30,6 +30,8 @@ MASK_NONE = 0
 MASK_COMPLEMENT_CSR = 1
 MASK_COMPLEMENT_BITMAP = 2
 
+SPMM_NOALLOC_MAX_BYTES = 64 << 20  # TSSPGEMM_SPMM_NOALLOC_MAX_BYTES
+
 
 class CsrDesc(ctypes.Structure):
     _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
@@ -72,6 +74,7 @@ _SIGNATURES = {
     "tsspgemm_grad_b": (ctypes.c_int, [vp, P(CsrDesc), vp, P(CsrDesc), P(CsrDesc), P(CsrDesc), vp, vp]),
     "tsspgemm_backward": (ctypes.c_int, [vp, P(CsrDesc), vp, P(CsrDesc), P(CsrDesc), P(CsrDesc), vp, vp, vp]),
     "tsspgemm_spmm": (ctypes.c_int, [P(CsrDesc), vp, i64, i64, vp, i64, vp]),
+    "tsspgemm_spmm_noalloc": (ctypes.c_int, [P(CsrDesc), vp, i64, i64, vp, i64, vp]),
     "tsspgemm_column_slice_count": (ctypes.c_int, [P(CsrDesc), ctypes.c_int32, ctypes.c_int32, vp, P(i64), vp]),
     "tsspgemm_column_slice_fill": (ctypes.c_int, [P(CsrDesc), ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp]),
     "tsspgemm_merge_count": (ctypes.c_int, [ctypes.c_int32, P(CsrDesc), vp, P(i64), vp]),

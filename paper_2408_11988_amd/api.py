@@ -295,6 +295,24 @@ def spmm(A: DeviceCsr, B: torch.Tensor, stream=None) -> torch.Tensor:
     return C
 
 
+def spmm_noalloc(A: DeviceCsr, B: torch.Tensor, C: torch.Tensor, stream=None) -> torch.Tensor:
+    """spmm into the caller's C (n x d float32, unit column stride) through the
+    library's allocation-free entry point: its workspace is a fixed per-GPU
+    device array, so the call allocates nothing (for graph capture or loops
+    that must not allocate). Raises TSSpGEMMError(CAPACITY) for a problem
+    larger than that array."""
+    if B.dim() != 2 or B.shape[0] != A.ncols or B.stride(1) != 1 or B.dtype != torch.float32:
+        raise ValueError("B must be n x d float32 with unit column stride")
+    if C.dim() != 2 or C.shape[0] != A.nrows or C.shape[1] != B.shape[1] or C.stride(1) != 1 or \
+            C.dtype != torch.float32:
+        raise ValueError("C must be n x d float32 with unit column stride")
+    da = A.desc()
+    rc = _lib.load().tsspgemm_spmm_noalloc(ctypes.byref(da), _ptr(B), B.shape[1], B.stride(0), _ptr(C),
+                                           C.stride(0), _stream_ptr(stream))
+    _lib.check(rc, "tsspgemm_spmm_noalloc")
+    return C
+
+
 def column_slice(A: DeviceCsr, c0: int, c1: int, stream=None) -> DeviceCsr:
     """Column tile A(:, c0:c1) with its column ids (Sec. III-B)."""
     dev = A.rowptr.device

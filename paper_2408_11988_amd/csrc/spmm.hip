@@ -14,6 +14,9 @@
 // takes exactly one item and the items are launched as one grid (chunks of
 // long rows first), so the hardware's workgroup dispatch balances the skewed
 // row lengths of power-law inputs. All summation orders are fixed.
+#include <mutex>
+#include <string>
+
 #include "api_internal.hpp"
 #include "dev_numeric.hpp"
 
@@ -241,8 +244,9 @@ static int launch_spmm_v(const SpmmParams& sp, hipStream_t st) {
   return TSSPGEMM_OK;
 }
 
-static int run_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C, int64_t ldc,
-                    hipStream_t st) {
+// Argument checks shared by both entry points; *nothing is set when there is
+// no work (n = 0 or d = 0).
+static int check_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, const float* C, int64_t ldc) {
   int rc;
   if ((rc = check_csr(A, "A", true))) return rc;
   if (A->nrows != A->ncols) {
@@ -257,6 +261,51 @@ static int run_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ld
     set_error("spmm: d > 1024");
     return TSSPGEMM_ERR_UNSUPPORTED;
   }
+  return TSSPGEMM_OK;
+}
+
+// Bounds on the chunk slots and long rows of A: a row of len > kSpmmChunk
+// entries has ceil(len / kSpmmChunk) <= 2 len / kSpmmChunk chunks.
+static int64_t spmm_chunk_cap(int64_t nnz) { return 2 * nnz / kSpmmChunk + 1; }
+static int64_t spmm_long_cap(int64_t nnz) { return nnz / kSpmmChunk + 1; }
+
+// Queues the classification, the item kernel and the finalize on `st`, with
+// the workspace pointers already set in sp (counters zeroed here by a fill
+// kernel, no memset node).
+static int enqueue_spmm(SpmmParams& sp, hipStream_t st) {
+  int rc;
+  if ((rc = launch_zero_bytes(sp.counters, 16, st))) return rc;
+  k_spmm_classify<<<grid_for(sp.n, 256) > 4096 ? 4096 : grid_for(sp.n, 256), 256, 0, st>>>(sp);
+  TSS_CHECK_LAUNCH();
+  // widest lane access that B and C allow: 16 bytes (fewer lanes per row, so
+  // more rows per wavefront), else 8, else 4
+  const auto fits = [&](int v) {
+    return sp.d % v == 0 && sp.ldb % v == 0 && sp.ldc % v == 0 && ((uintptr_t)sp.B % (4 * v)) == 0 &&
+           ((uintptr_t)sp.C % (4 * v)) == 0;
+  };
+  if (fits(4)) return launch_spmm_v<4>(sp, st);
+  return fits(2) ? launch_spmm_v<2>(sp, st) : launch_spmm_v<1>(sp, st);
+}
+
+static SpmmParams spmm_params(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C, int64_t ldc) {
+  SpmmParams sp{};
+  sp.n = A->nrows;
+  sp.d = d;
+  sp.ldb = ldb;
+  sp.ldc = ldc;
+  sp.arp = A->rowptr;
+  sp.aci = A->colidx;
+  sp.aval = (const float*)A->vals;
+  sp.B = B;
+  sp.C = C;
+  sp.slot_items = spmm_chunk_cap(A->nnz);
+  return sp;
+}
+
+static int run_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C, int64_t ldc,
+                    hipStream_t st) {
+  int rc;
+  if ((rc = check_spmm(A, B, d, ldb, C, ldc))) return rc;
   const int64_t n = A->nrows, nnz = A->nnz;
   if (n == 0 || d == 0) return TSSPGEMM_OK;
   int dev = 0;
@@ -267,38 +316,90 @@ static int run_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ld
     return TSSPGEMM_ERR_NOMEM;
   }
   std::lock_guard<std::mutex> lk(p->mu);
-  // a row of len > kSpmmChunk entries has ceil(len / kSpmmChunk) <= 2 len / kSpmmChunk chunks
-  const int64_t chunk_cap = 2 * nnz / kSpmmChunk + 1;
-  const int64_t long_cap = nnz / kSpmmChunk + 1;
+  const int64_t chunk_cap = spmm_chunk_cap(nnz), long_cap = spmm_long_cap(nnz);
   if ((rc = p->sp_chunks.ensure((size_t)chunk_cap * sizeof(int2))) ||
       (rc = p->sp_rows.ensure((size_t)long_cap * sizeof(int4))) ||
       (rc = p->sp_partial.ensure((size_t)chunk_cap * d * 8)) || (rc = p->sp_ctr.ensure(16)))
     return rc;
-  SpmmParams sp{};
-  sp.n = n;
-  sp.d = d;
-  sp.ldb = ldb;
-  sp.ldc = ldc;
-  sp.arp = A->rowptr;
-  sp.aci = A->colidx;
-  sp.aval = (const float*)A->vals;
-  sp.B = B;
-  sp.C = C;
+  SpmmParams sp = spmm_params(A, B, d, ldb, C, ldc);
   sp.chunks = (int2*)p->sp_chunks.p;
   sp.long_rows = (int4*)p->sp_rows.p;
   sp.partial = (double*)p->sp_partial.p;
   sp.counters = (int32_t*)p->sp_ctr.p;
-  sp.slot_items = chunk_cap;
-  if ((rc = launch_zero_bytes(sp.counters, 16, st))) return rc;
-  k_spmm_classify<<<grid_for(n, 256) > 4096 ? 4096 : grid_for(n, 256), 256, 0, st>>>(sp);
-  TSS_CHECK_LAUNCH();
-  // widest lane access that B and C allow: 16 bytes (fewer lanes per row, so
-  // more rows per wavefront), else 8, else 4
-  const auto fits = [&](int v) {
-    return d % v == 0 && ldb % v == 0 && ldc % v == 0 && ((uintptr_t)B % (4 * v)) == 0 && ((uintptr_t)C % (4 * v)) == 0;
-  };
-  if (fits(4)) return launch_spmm_v<4>(sp, st);
-  return fits(2) ? launch_spmm_v<2>(sp, st) : launch_spmm_v<1>(sp, st);
+  return enqueue_spmm(sp, st);
+}
+
+// ---------------------------------------------------------------- allocation-free variant
+
+// The workspace of tsspgemm_spmm_noalloc: counters, chunk list, long-row
+// records and FP64 partial rows, carved from one fixed device array. Each
+// GPU holds its own copy (allocated with the code object, kept until the
+// process ends); the host reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kSpmmScratchBytes = (size_t)TSSPGEMM_SPMM_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kSpmmScratchBytes];
+
+constexpr int kScratchMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchMaxDevices];  // device address of `scratch` on each device, once looked up
+
+// Device address of this device's scratch array (looked up once per device,
+// with that device current).
+static int scratch_address(void** out) {
+  int dev = 0;
+  TSS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchMaxDevices) {
+    set_error("spmm_noalloc: device ordinal beyond the supported 64");
+    return TSSPGEMM_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return TSSPGEMM_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TSSPGEMM_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Bytes of scratch an n x n A with nnz entries needs at width d.
+static size_t spmm_scratch_bytes(int64_t nnz, int64_t d) {
+  const int64_t chunk_cap = spmm_chunk_cap(nnz), long_cap = spmm_long_cap(nnz);
+  return 256 + align256((size_t)chunk_cap * sizeof(int2)) + align256((size_t)long_cap * sizeof(int4)) +
+         align256((size_t)chunk_cap * d * 8);
+}
+
+static int run_spmm_noalloc(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C, int64_t ldc,
+                            hipStream_t st) {
+  int rc;
+  if ((rc = check_spmm(A, B, d, ldb, C, ldc))) return rc;
+  const int64_t n = A->nrows, nnz = A->nnz;
+  if (n == 0 || d == 0) return TSSPGEMM_OK;
+  const size_t need = spmm_scratch_bytes(nnz, d);
+  if (need > kSpmmScratchBytes) {
+    set_error("spmm_noalloc: this A and d need " + std::to_string(need) + " bytes of scratch; the maximum is " +
+              std::to_string(kSpmmScratchBytes) + " (about nnz(A) * d / 8 bytes); use tsspgemm_spmm");
+    return TSSPGEMM_ERR_CAPACITY;
+  }
+  void* base = nullptr;
+  if ((rc = scratch_address(&base))) return rc;
+  char* p = (char*)base;
+  const int64_t chunk_cap = spmm_chunk_cap(nnz), long_cap = spmm_long_cap(nnz);
+  SpmmParams sp = spmm_params(A, B, d, ldb, C, ldc);
+  sp.counters = (int32_t*)p;
+  p += 256;
+  sp.chunks = (int2*)p;
+  p += align256((size_t)chunk_cap * sizeof(int2));
+  sp.long_rows = (int4*)p;
+  p += align256((size_t)long_cap * sizeof(int4));
+  sp.partial = (double*)p;
+  return enqueue_spmm(sp, st);
 }
 
 }  // namespace tss
@@ -307,6 +408,16 @@ extern "C" int tsspgemm_spmm(const tsspgemm_csr* A, const float* B, int64_t d, i
                              void* stream) {
   try {
     return tss::run_spmm(A, B, d, ldb, C, ldc, (hipStream_t)stream);
+  } catch (...) {
+    tss::set_error("unexpected C++ exception");
+    return TSSPGEMM_ERR_HIP;
+  }
+}
+
+extern "C" int tsspgemm_spmm_noalloc(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C,
+                                     int64_t ldc, void* stream) {
+  try {
+    return tss::run_spmm_noalloc(A, B, d, ldb, C, ldc, (hipStream_t)stream);
   } catch (...) {
     tss::set_error("unexpected C++ exception");
     return TSSPGEMM_ERR_HIP;
