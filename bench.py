@@ -112,6 +112,13 @@ def cpu_baseline(a, b, flops_rows, target_s=12.0):
             "sample": f"{sample}; {fl} multiplications in {t:.2f} s (ordered-map Gustavson, FP64)"}
 
 
+def _roofline(bytes_alg: int, ms: float, kernel: str) -> dict:
+    """HBM roofline of one launch (or call) from its algorithmic bytes."""
+    gbs = bytes_alg / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "bytes_alg_per_launch": int(bytes_alg), "ms": round(ms, 4),
+            "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}
+
+
 def _events(n):
     import torch
 
@@ -155,13 +162,39 @@ def bench_fwd_bwd(steps: int, warmup: int) -> dict:
     ms_step = (time.perf_counter() - t0) * 1e3 / steps
     ms_f = sum(x[0].elapsed_time(x[1]) for x in ef) / steps
     ms_b = sum(x[1].elapsed_time(x[2]) for x in ef) / steps
+    # the library's backward call alone (both gradients, G = W on pat(C))
+    from paper_2408_11988_amd import backward
+
+    AT, perm = op.transpose()
+    Av, Bv = op.A.with_vals(av.detach()), op.B.with_vals(bv.detach())
+    G = op.c_pattern().with_vals(w)
+    for _ in range(warmup):
+        backward(op.plan, AT, perm, Av, Bv, G)
+    torch.cuda.synchronize()
+    e = _events(2)
+    e[0].record()
+    for _ in range(steps):
+        backward(op.plan, AT, perm, Av, Bv, G)
+    e[1].record()
+    torch.cuda.synchronize()
+    ms_lib_bwd = e[0].elapsed_time(e[1]) / steps
+    n, nnz_a, nnz_b, nnz_c = a.nrows, a.nnz, b.nnz, op.nnz
+    rp = 4 * (n + 1)
+    fwd_bytes = (rp + 8 * nnz_a) + (rp + 8 * nnz_b) + (rp + 8 * nnz_c)
+    # inputs A (pattern, values), B, G on pat(C), A^T (pattern, permutation);
+    # outputs dL/dA and dL/dB
+    bwd_bytes = (rp + 8 * nnz_a) + (rp + 8 * nnz_b) + (rp + 8 * nnz_c) + (rp + 8 * nnz_a) + 4 * nnz_a + 4 * nnz_b
     return {"workload": "R-MAT scale 20 x B n x 256 Bernoulli(0.05) N(0,1), loss sum(C o W)",
             "flops_fwd": flops, "nnz_c": op.nnz, "ms_fwd": round(ms_f, 4), "ms_bwd": round(ms_b, 4),
+            "ms_bwd_library": round(ms_lib_bwd, 4),
             "ms_fwd_bwd": round(ms_step, 4), "gflops_fwd": round(2 * flops / ms_f / 1e6, 2),
             "gflops_bwd": round(2 * 2 * flops / ms_b / 1e6, 2),
             "gflops_fwd_bwd": round(2 * 3 * flops / ms_step / 1e6, 2),
+            "roofline_fwd": _roofline(fwd_bytes, ms_f, "numeric phase of the forward (one tsspgemm_numeric call)"),
+            "roofline_bwd": _roofline(bwd_bytes, ms_lib_bwd, "tsspgemm_backward (dL/dA and dL/dB, one call)"),
             "note": "bwd = dL/dA (SDDMM on pat(A)) + dL/dB (A^T G sampled on pat(B)), each as many products as fwd;"
-                    " ms_bwd includes the loss reduction"}
+                    " ms_bwd is the autograd backward with the loss's elementwise product and sum; "
+                    "ms_bwd_library is the library call alone"}
 
 
 def bench_batched(steps: int, warmup: int) -> dict:
@@ -241,8 +274,13 @@ def bench_batched(steps: int, warmup: int) -> dict:
     torch.cuda.synchronize()
     ms_num_graph = e[0].elapsed_time(e[1]) / steps
     del graph, plans
+    rp_bytes = sum(3 * 4 * (a.nrows + 1) for a, _ in host)
+    batch_bytes = rp_bytes + sum(8 * (a.nnz + b.nnz) for a, b in host) + 8 * bt.pool
     return {"workload": "64 instances: n log-uniform [2^14, 2^18], d in {32,64,128,256}, ER/R-MAT (deg 4-32), "
                         "B density log-uniform [1%, 50%], plus-times FP32",
+            "roofline": _roofline(batch_bytes, ms_graph, "one graph replay (symbolic + numeric of all 64 instances)"),
+            "roofline_numeric_calls": _roofline(batch_bytes, ms_num_graph,
+                                                "the 64 numeric phases captured as plain calls"),
             "sum_n": sum(a.nrows for a, _ in host), "sum_nnz_a": sum(a.nnz for a, _ in host), "flops": flops,
             "nnz_c": bt.pool, "ms_graph_replay": round(ms_graph, 4), "ms_64_plain_calls": round(ms_seq, 4),
             "gflops_graph": round(2 * flops / ms_graph / 1e6, 2), "gflops_plain_calls": round(2 * flops / ms_seq / 1e6, 2),
@@ -569,7 +607,14 @@ def bench_bfs(cpu: bool) -> dict:
     reached = (lev >= 0).sum(dim=1).to(torch.int64)
     products = int((deg * reached).sum())  # AND products over the run = sum_s sum_{v reached} deg(v)
     pairs = int(reached.sum())
+    # per masked product: A's pattern, the frontier F as CSR, the visited set
+    # as an n x d bitmap, the new frontier N as CSR; then the n x d levels
+    n, d = a.nrows, 512
+    fr = [d] + list(fn)  # nnz(F) entering each product, then after it
+    bfs_bytes = sum((4 * (n + 1) + 4 * a.nnz) + (4 * (n + 1) + 4 * fr[t]) + n * d // 8 + (4 * (n + 1) + 4 * fr[t + 1])
+                    for t in range(len(fn))) + 4 * n * d
     out = {"workload": "R-MAT scale 22 (edge factor 16, symmetrised, pattern), 512 sources, Boolean masked",
+           "roofline": _roofline(bfs_bytes, ms, "the whole multi-source BFS (every masked product and the levels)"),
            "n": a.nrows, "nnz_a": a.nnz, "iterations": len(fn), "frontier_nnz": fn, "ms_total": round(ms, 3),
            "reached_pairs": pairs, "and_products": products,
            "gflops": round(2 * products / ms / 1e6, 2), "traversed_edges_per_s": round(products / ms * 1e3, 1),
@@ -596,6 +641,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=20)
     ap.add_argument("--d", type=int, default=128)
+    ap.add_argument("--products", choices=["auto", "rows", "flat", "vec4"], default="auto",
+                    help="product layout of the plain workload's numeric phase (default: the library's choice)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the plain workload")
     ap.add_argument("--leg", choices=["er_small", "fwd_bwd", "batched", "spmm", "embed", "tiles", "bfs", "wide_d"],
@@ -645,8 +692,12 @@ def main():
     plan = ctypes.c_void_p(None)
     nnz = ctypes.c_int64(0)
 
+    from paper_2408_11988_amd.api import tuning_struct
+
+    tune = None if args.products == "auto" else ctypes.byref(tuning_struct({"products": args.products}))
+
     def symbolic():
-        _lib.check(lib.tsspgemm_symbolic(ctypes.byref(da), ctypes.byref(db), _lib.PLUS_TIMES_F32, None, None,
+        _lib.check(lib.tsspgemm_symbolic(ctypes.byref(da), ctypes.byref(db), _lib.PLUS_TIMES_F32, None, tune,
                                          ctypes.c_void_p(c_rowptr.data_ptr()), ctypes.byref(nnz),
                                          ctypes.byref(plan), sp), "symbolic")
         return int(nnz.value)

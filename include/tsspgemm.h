@@ -94,8 +94,18 @@ typedef enum {
  *              flight; lanes past a short row's end idle.
  *   FLAT:      the staged entries' products form one list (a scan of the B
  *              row lengths) and lane t takes products t, t + width, ...;
- *              pays when B rows are short next to the group width. */
-typedef enum { TSSPGEMM_PRODUCTS_AUTO = 0, TSSPGEMM_PRODUCTS_PER_B_ROW = 1, TSSPGEMM_PRODUCTS_FLAT = 2 } tsspgemm_products;
+ *              pays when B rows are short next to the group width.
+ *   VEC4:      as PER_B_ROW, but each lane reads four consecutive entries of
+ *              the B row (4-aligned chunks: one 16-byte load of values, one
+ *              load of column ids), so a wavefront keeps four times the B row
+ *              bytes in flight per load instruction. Needs B's values 16-byte
+ *              aligned in the numeric call; PER_B_ROW is used otherwise. */
+typedef enum {
+  TSSPGEMM_PRODUCTS_AUTO = 0,
+  TSSPGEMM_PRODUCTS_PER_B_ROW = 1,
+  TSSPGEMM_PRODUCTS_FLAT = 2,
+  TSSPGEMM_PRODUCTS_VEC4 = 3
+} tsspgemm_products;
 
 /* Tuning knobs. A NULL tuning pointer, or a zero field, means "default".
  * The structure of C does not depend on any of these. Values are FP64 sums
@@ -223,11 +233,15 @@ int tsspgemm_grad_b(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* a
  * (i,k) x (k,j) reads, in one block per A entry; a second pass walks A^T and
  * sums A(i,k) G(i,j) from those blocks for each entry (k, j) of B. Values
  * equal those of tsspgemm_grad_a and tsspgemm_grad_b (same sums in the same
- * order), which run the same passes. Workspace in the plan, allocated at
- * the first call and kept: 4 bytes per product (the flops of the forward)
- * and 20 bytes per A entry. The first call on a plan that asks for grad_b
- * builds the blocks' starts and synchronizes `stream` once (to size the
- * buffer); later calls are asynchronous. Errors as tsspgemm_grad_b. */
+ * order), which run the same passes. The block of entry (i,k) holds
+ * A(i,k) and then G(i,j) for j in pat(B_k), padded to a multiple of 64
+ * bytes; blocks are stored in A^T order, so the second pass reads each B
+ * row's blocks contiguously. Workspace in the plan, allocated at the first
+ * call and kept: the blocks (4 bytes per product of the forward plus at most
+ * 64 bytes per A entry), 4 bytes per A entry (its block's place), 16 bytes
+ * per row, and the dL/dB work list. The first call on a plan that asks for
+ * grad_b builds the blocks' starts and synchronizes `stream` once (to size
+ * the buffer); later calls are asynchronous. Errors as tsspgemm_grad_b. */
 int tsspgemm_backward(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t* at_perm, const tsspgemm_csr* A,
                       const tsspgemm_csr* B, const tsspgemm_csr* G, float* grad_a, float* grad_b, void* stream);
 

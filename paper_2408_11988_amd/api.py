@@ -81,7 +81,7 @@ def accumulator_code(v) -> int:
     return ACCUMULATORS[v] if isinstance(v, str) else int(v)
 
 
-PRODUCTS = {"auto": 0, "rows": 1, "flat": 2}
+PRODUCTS = {"auto": 0, "rows": 1, "flat": 2, "vec4": 3}
 
 
 def tuning_struct(t: dict) -> _lib.Tuning:

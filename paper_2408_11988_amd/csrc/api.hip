@@ -95,7 +95,7 @@ static int plan_alloc_host(Plan* p) {
 void plan_free(Plan* p) {
   for (DevBuf* b : {&p->bbits, &p->cbits, &p->flops, &p->cnt, &p->scan, &p->sym_items, &p->num_items,
                     &p->split_rows, &p->partial, &p->ctr, &p->maskbits, &p->gb_items, &p->gb_split,
-                    &p->gb_partial, &p->gb_ctr, &p->gb_gbuf, &p->gb_pos_a, &p->gb_pos_at, &p->gb_lens, &p->gb_scan})
+                    &p->gb_partial, &p->gb_ctr, &p->gb_gbuf, &p->gb_off, &p->gb_slot_a, &p->gb_words, &p->gb_scan})
     b->release();
   if (p->host_ctr) (void)hipHostFree(p->host_ctr);
   p->host_ctr = nullptr;
@@ -126,7 +126,9 @@ int default_products(double mean_b_row, int group_lanes) {
 void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tuning* out) {
   tsspgemm_tuning r{};
   if (t) r = *t;
-  if (r.group_lanes == 0) r.group_lanes = default_group_lanes(mean_b_row(B));
+  // lanes per B row: 4-entry chunks per lane need a quarter of the lanes
+  if (r.group_lanes == 0)
+    r.group_lanes = default_group_lanes(r.products == TSSPGEMM_PRODUCTS_VEC4 ? mean_b_row(B) / 4.0 : mean_b_row(B));
   if (r.light_max_flops <= 0) r.light_max_flops = 1024;
   if (r.wave_max_flops <= 0) r.wave_max_flops = 65536;
   if (r.split_flops <= 0) r.split_flops = 262144;
@@ -177,6 +179,7 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   p->b_nnz = B->nnz;
   p->ready = false;
   p->gb_pos_ready = false;
+  p->gb_items_ready = false;
   p->hash = true;
   p->masked = M && M->kind != TSSPGEMM_MASK_NONE;
   if ((rc = plan_alloc_host(p))) return rc;
@@ -323,7 +326,8 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
     set_error("unknown accumulator");
     return TSSPGEMM_ERR_INVALID_ARG;
   }
-  if (tn.products != TSSPGEMM_PRODUCTS_PER_B_ROW && tn.products != TSSPGEMM_PRODUCTS_FLAT) {
+  if (tn.products != TSSPGEMM_PRODUCTS_PER_B_ROW && tn.products != TSSPGEMM_PRODUCTS_FLAT &&
+      tn.products != TSSPGEMM_PRODUCTS_VEC4) {
     set_error("unknown product layout");
     return TSSPGEMM_ERR_INVALID_ARG;
   }
@@ -351,6 +355,7 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   p->b_nnz = B->nnz;
   p->ready = false;
   p->gb_pos_ready = false;
+  p->gb_items_ready = false;
   p->masked = M && M->kind != TSSPGEMM_MASK_NONE;
   if ((rc = plan_alloc_host(p))) return rc;
   const int64_t sym_cap = n + A->nnz / tn.sym_split_nnz + 2;
@@ -492,8 +497,11 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   np.partial = (double*)p->partial.p;
   np.ipartial = (int32_t*)p->partial.p;
   const int64_t grid = np.n_wg_items + (p->n_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
-  if ((rc = launch_numeric(p->sr, p->tune.group_lanes, p->tune.products == TSSPGEMM_PRODUCTS_FLAT, np, grid, st)))
-    return rc;
+  // 4-entry chunks need B's values 16-byte aligned (the narrowed ids are the
+  // plan's own, aligned); otherwise one entry per lane
+  int products = p->tune.products;
+  if (products == TSSPGEMM_PRODUCTS_VEC4 && ((uintptr_t)B->vals % 16) != 0) products = TSSPGEMM_PRODUCTS_PER_B_ROW;
+  if ((rc = launch_numeric(p->sr, p->tune.group_lanes, products, np, grid, st))) return rc;
   return launch_split_finalize(p->sr, pr, (const SplitRow*)p->split_rows.p, (int32_t)p->n_split_rows,
                                (const double*)p->partial.p, (const int32_t*)p->partial.p, st);
 }

@@ -46,11 +46,14 @@ struct Plan {
   DevBuf bbits, cbits, flops, cnt, scan, sym_items, num_items, split_rows, partial, ctr, maskbits;
   DevBuf gb_items, gb_split, gb_partial, gb_ctr;  // dL/dB work lists
   DevBuf bcol;             // B's column ids narrowed to col_id_bytes(d) bytes (numeric phase)
-  // dL/dB from sampled G: G(i, j) of every product, in blocks per A entry
-  // (A order), and the start of each A entry's block in A order and in A^T
-  // order (built once per plan: the patterns are fixed)
-  DevBuf gb_gbuf, gb_pos_a, gb_pos_at, gb_lens, gb_scan;
+  // dL/dB from sampled G: one block per A entry (i,k) holding A(i,k) and
+  // G(i, pat(B_k)) in a 64-byte-multiple slot, blocks in A^T order; the start
+  // of each B row's blocks and of each A entry's block, and the per-row sizes
+  // and scan space that build them (built once per plan: the patterns are
+  // fixed)
+  DevBuf gb_gbuf, gb_off, gb_slot_a, gb_words, gb_scan;
   bool gb_pos_ready = false;
+  bool gb_items_ready = false;  // the dL/dB work list (gb_items, gb_split, gb_ctr) is built
   int64_t gb_total = 0;     // products of the plan = entries of gb_gbuf (the last block start)
   bool masked = false;     // symbolic phase ran with a complement mask
   bool hash = false;       // hash accumulator plan (no bitmaps, no work lists)

@@ -10,20 +10,26 @@
 // First pass, over A's rows (the forward plan's binned rows): a row's G
 // values are staged in an LDS strip of width d; each A entry (i,k) is a dot
 // product of B row k with that strip (dL/dA), taken by a group of GL lanes
-// and reduced across the group. For dL/dB the same walk writes every G(i,j)
-// it reads into a block per A entry (i,k): the values of G(i, pat(B_k)) in B
-// row order, blocks in A order. The FP32 values are copied, not rounded.
+// and reduced across the group. For dL/dB the same walk writes A(i,k) and
+// every G(i,j) it reads into a block per A entry (i,k): A(i,k), then the
+// values of G(i, pat(B_k)) in B row order. The FP32 values are copied, not
+// rounded. Blocks are in A order, back to back, so the walk writes them
+// contiguously.
 //
 // Second pass, over A^T (from tsspgemm_transpose): a group of GL lanes owns
 // the entries of one B row k (lane = entry) and runs over the entries i of
-// A^T row k in order, adding A(i,k) G(i,j) from block (i,k); consecutive
-// lanes read consecutive floats of a block. Long A^T rows are cut into
+// A^T row k in order, adding A(i,k) G(i,j) from block (i,k) (one or two
+// cache lines per (B row, A^T entry) pair). Long A^T rows are cut into
 // chunks whose partial sums a third kernel adds in chunk order.
 //
-// A single pass over A^T that looked G(i,j) up in C's row i (a record of
-// C's bitmap word plus a popcount) reread whole cache lines of G for every
-// (B row, A^T entry) pair: about 15 GB per call at R-MAT 20 x 256, against
-// the 1.6 GB of blocks written and read here.
+// Measured at R-MAT 20 x 256 (5%), per call: a single pass over A^T that
+// looked G(i,j) up in C's row i (a record of C's bitmap word plus a
+// popcount) fetched about 15 GB; blocks without A(i,k), read with A(i,k)
+// gathered through the permutation, 11.6 GB in the second pass (a cache
+// line per pair for the gather alone); blocks stored in A^T order made the
+// second pass one contiguous read (3.2 GB, 0.75 ms) but scattered the first
+// pass's writes (3.4 GB in 32- and 64-byte pieces), which cost 0.9 ms more
+// there.
 #include "api_internal.hpp"
 #include "dev_numeric.hpp"
 
@@ -50,20 +56,28 @@ struct GradAParams {
   const int32_t* gci;     // G = dL/dC on C's pattern
   const float* gval;
   float* grad_a;          // dL/dA, or null (only the sampled G is written)
-  float* gbuf;            // sampled G for dL/dB, or null: G(i, j) for every product of (i,k) and (k,j)
-  const int64_t* pos_a;   // per A entry p = (i,k): start of its block of nnz(B_k) values in gbuf
+  float* gbuf;            // sampled G for dL/dB, or null: per A entry (i,k) a block of A(i,k) then G(i, pat(B_k))
+  const int32_t* slot_a;  // per A entry: start of its block in gbuf in 16-float units (-1: its B row is empty)
   const Item* items;
   int32_t n_wg_items, n_heavy_records, n_light;
 };
 
+// Floats of the slot of a block of a B row of len entries: A(i,k) and the
+// len G values, rounded up to 16 floats (64 bytes); none for an empty row.
+__device__ __forceinline__ int gb_slot(int len) { return len > 0 ? 16 * ((len + 16) / 16) : 0; }
+
 // Dot products of staged A entries: stage[e] = (start, end) of B row k for
-// the entry base + e of the row (and, with GATHER, the start of the entry's
-// block in gbuf), e in [0, nb); group grp of ngroups takes blocks of U entries
-// grp * U, (grp + ngroups) * U, ... Lanes of a group walk the B row (column
-// ids narrowed to IdxT) against the row's G strip; each dot product is summed
-// over the group in FP64 and rounded once. With GATHER, each G(i, j) the walk
-// reads is also written to the entry's block at the position of j in B row k
-// (lanes of a group write consecutive floats).
+// the entry base + e of the row, e in [0, nb); group grp of ngroups takes
+// blocks of U entries grp * U, (grp + ngroups) * U, ... Lanes of a group walk
+// the B row (column ids narrowed to IdxT) against the row's G strip; each dot
+// product is summed over the group in FP64 and rounded once.
+//
+// With GATHER the stage also holds the entry's slot in gbuf (in 16-float
+// units) and A(i,k), and lane gl walks the slot's positions gl, gl + GL, ...
+// instead of the B row's entries: position 0 takes A(i,k), position p >= 1
+// takes G(i, j) for the (p-1)-th entry (k, j) of B row k (the same product
+// the dot product uses), and positions past the row's end take 0. The lanes
+// of a group thus write whole 64-byte segments, with no partial writes.
 template <int GL, typename IdxT, bool GATHER>
 __device__ __forceinline__ void grad_a_staged(const GradAParams& gp, int base, int nb, const int4* stage, int grp,
                                               int ngroups, const float* strip) {
@@ -74,40 +88,53 @@ __device__ __forceinline__ void grad_a_staged(const GradAParams& gp, int base, i
   const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
   float* __restrict__ gbuf = gp.gbuf;
   for (int e0 = grp * U; e0 < nb; e0 += ngroups * U) {
-    int q[U], qe[U];
-    int64_t wb[U];  // gbuf index of B entry q of this entry's row: wb + q
+    int q0[U], qe[U];
+    int64_t w[U];  // GATHER: start of the slot
+    float av[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      int4 r = make_int4(0, 0, 0, 0);
+      int4 r = make_int4(0, 0, -1, 0);
       if (e0 + u < nb) r = stage[e0 + u];
-      q[u] = r.x + gl;
+      q0[u] = r.x;
       qe[u] = r.y;
-      wb[u] = (int64_t)(((uint64_t)(uint32_t)r.w << 32) | (uint32_t)r.z) - r.x;
+      w[u] = 16 * (int64_t)r.z;
+      av[u] = __builtin_bit_cast(float, r.w);
     }
+    // the first GL positions (GATHER) or entries of each row
+    const int sh = GATHER ? 1 : 0;  // position p holds entry p - 1
     int jj[U];
     float bv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      const int q = q0[u] + gl - sh;
       jj[u] = 0;
       bv[u] = 0.0f;
-      if (q[u] < qe[u]) {
-        jj[u] = bci[q[u]];
-        bv[u] = bval[q[u]];
+      if (q >= q0[u] && q < qe[u]) {
+        jj[u] = bci[q];
+        bv[u] = bval[q];
       }
     }
     double sum[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      sum[u] = 0.0;
-      if (q[u] < qe[u]) {
-        const float g = strip[jj[u]];
-        sum[u] = (double)bv[u] * (double)g;
-        if constexpr (GATHER) gbuf[wb[u] + q[u]] = g;
-      }
-      for (int t = q[u] + GL; t < qe[u]; t += GL) {
-        const float g = strip[bci[t]];
-        sum[u] += (double)bval[t] * (double)g;
-        if constexpr (GATHER) gbuf[wb[u] + t] = g;
+      const int q = q0[u] + gl - sh;
+      const bool in = q >= q0[u] && q < qe[u];
+      const float g = in ? strip[jj[u]] : 0.0f;
+      sum[u] = in ? (double)bv[u] * (double)g : 0.0;
+      if constexpr (GATHER) {
+        const int S = gb_slot(qe[u] - q0[u]);
+        if (gl < S) __builtin_nontemporal_store(gl == 0 ? av[u] : g, gbuf + w[u] + gl);
+        for (int p = gl + GL; p < S; p += GL) {
+          const int t = q0[u] + p - 1;
+          float gt = 0.0f;
+          if (t < qe[u]) {
+            gt = strip[bci[t]];
+            sum[u] += (double)bval[t] * (double)gt;
+          }
+          __builtin_nontemporal_store(gt, gbuf + w[u] + p);
+        }
+      } else {
+        for (int t = q + GL; t < qe[u]; t += GL) sum[u] += (double)bval[t] * (double)strip[bci[t]];
       }
     }
     if (gp.grad_a) {
@@ -121,19 +148,18 @@ __device__ __forceinline__ void grad_a_staged(const GradAParams& gp, int base, i
 }
 
 // Stage entries [base, base + nb) of A (nb <= the caller's lanes): lane t of
-// the stagers loads entry base + t, its B row bounds and (GATHER) the start
-// of its block in gbuf.
+// the stagers loads entry base + t and its B row bounds, and (GATHER) its
+// slot in gbuf (16-float units) and A(i,k).
 template <bool GATHER>
 __device__ __forceinline__ void grad_a_stage(const GradAParams& gp, int base, int nb, int t, int4* stage) {
-  int4 e = make_int4(0, 0, 0, 0);
+  int4 e = make_int4(0, 0, -1, 0);
   if (t < nb) {
     const int k = gp.pr.aci[base + t];
     e.x = gp.pr.brp[k];
     e.y = gp.pr.brp[k + 1];
     if constexpr (GATHER) {
-      const uint64_t w = (uint64_t)gp.pos_a[base + t];
-      e.z = (int32_t)(uint32_t)w;
-      e.w = (int32_t)(uint32_t)(w >> 32);
+      e.z = gp.slot_a[base + t];
+      e.w = __builtin_bit_cast(int32_t, ((const float*)gp.pr.aval)[base + t]);
     }
   }
   stage[t] = e;
@@ -214,12 +240,9 @@ __global__ void k_zero_f32(float* p, int64_t n) {
 struct GradBParams {
   Problem pr;                // A values, B pattern
   const int32_t* atrp;       // A^T row pointers (n + 1)
-  const int32_t* atci;       // A^T rows i
-  const int32_t* perm;       // position in A of each A^T entry
-  const float* gval;         // G on C's pattern
   float* grad_b;
-  const float* gbuf;         // sampled G written by the first pass (k_grad_b_sampled)
-  const int64_t* pos_at;     // start of each A^T entry's block in gbuf
+  const float* gbuf;         // blocks written by the first pass, in A^T order
+  const int64_t* off;        // start of B row k's blocks in gbuf
   Item* items;               // [split chunks][whole rows]: row = k, [p0,p1) range of A^T entries
   SplitRow* split_rows;
   double* partial;           // chunk partial sums (slot x d)
@@ -307,60 +330,50 @@ __global__ void k_gb_bin_fill(GradBParams gb) {
   }
 }
 
-// dL/dB from the sampled G written by the first pass: the block of A entry
-// (i,k) holds G(i, j) for the entries (k, j) of B row k, in B row order, at
-// pos[x] for the x-th entry of A^T. A group of GL lanes owns B row k's
-// entries (GL at a time); a lane's sum runs over the item's A^T entries in
-// order, so each step reads GL consecutive floats of one block. The group
-// stages GL A^T entries at once (block start and A(i,k)) and shares them
-// through LDS; U blocks are read before their sums.
+// dL/dB from the blocks written by the first pass. Blocks are in A^T order:
+// B row k's blocks, one slot of S = gb_slot(nnz(B_k)) floats per entry of
+// A^T row k in order, start at off[k], so an item reads one contiguous range.
+// A group of GL lanes takes the slot positions in windows of GL (position
+// p = window + gl holds G(i, j) of B row k's entry p - 1; position 0 holds
+// A(i,k)); a lane's sum runs over the item's A^T entries in order. Each
+// block is one load per lane; A(i,k) comes from the group's lane 0 by a
+// shuffle in the first window and by a load in later ones. U blocks are
+// read before their sums.
 template <int GL>
-__global__ __launch_bounds__(kBlock) void k_grad_b_sampled(GradBParams gb) {
+__global__ __launch_bounds__(kBlock) void k_grad_b_blocks(GradBParams gb) {
   constexpr int G = kBlock / GL;
   constexpr int U = 8;
-  __shared__ int4 stage_s[kBlock];
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
-  int4* stage = stage_s + grp * GL;
+  const int lane0 = (threadIdx.x & (kWave - 1)) & ~(GL - 1);  // the group's first lane in the wavefront
   const Problem& pr = gb.pr;
-  const float* __restrict__ aval = (const float*)pr.aval;
   const float* __restrict__ gbuf = gb.gbuf;
   const int total = gb.ctr->num_split_items + gb.ctr->num_light_rows;
   for (int64_t t = (int64_t)blockIdx.x * G + grp; t < total; t += (int64_t)gridDim.x * G) {
     const Item it = gb.items[t];
     const int k = it.row;
-    const int q0 = pr.brp[k], q1 = pr.brp[k + 1];
-    for (int qb = q0; qb < q1; qb += GL) {
-      const int e = qb - q0 + gl;
-      const bool own = qb + gl < q1;
+    const int q0 = pr.brp[k], len = pr.brp[k + 1] - q0;
+    const int S = gb_slot(len);
+    const float* blk = gbuf + gb.off[k] + (int64_t)(it.p0 - gb.atrp[k]) * S;
+    const int nx = it.p1 - it.p0;
+    for (int pw = 0; pw <= len; pw += GL) {  // windows holding positions 1..len
+      const int pos = pw + gl, e = pos - 1;
+      const bool own = e >= 0 && e < len;
+      const bool load = pos < S;
       double acc = 0.0;
-      for (int xb = it.p0; xb < it.p1; xb += GL) {
-        const int nb = min(GL, it.p1 - xb);
-        int4 r = make_int4(0, 0, 0, 0);
-        if (gl < nb) {
-          const uint64_t w = (uint64_t)gb.pos_at[xb + gl];
-          r.x = (int32_t)(uint32_t)w;
-          r.y = (int32_t)(uint32_t)(w >> 32);
-          r.z = __builtin_bit_cast(int32_t, aval[gb.perm[xb + gl]]);
-        }
-        wave_sync();
-        stage[gl] = r;
-        wave_sync();
-        for (int s0 = 0; s0 < nb; s0 += U) {
-          float a[U], g[U];
+      for (int x0 = 0; x0 < nx; x0 += U) {
+        float v[U], a[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            a[u] = 0.0f;
-            g[u] = 0.0f;
-            if (own && s0 + u < nb) {
-              const int4 x = stage[s0 + u];
-              a[u] = __builtin_bit_cast(float, x.z);
-              g[u] = gbuf[(int64_t)(((uint64_t)(uint32_t)x.y << 32) | (uint32_t)x.x) + e];
-            }
-          }
+        for (int u = 0; u < U; ++u) v[u] = (load && x0 + u < nx) ? blk[(int64_t)(x0 + u) * S + pos] : 0.0f;
+        if (pw == 0) {
 #pragma unroll
-          for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)g[u];
+          for (int u = 0; u < U; ++u) a[u] = __shfl(v[u], lane0, kWave);
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) a[u] = (own && x0 + u < nx) ? blk[(int64_t)(x0 + u) * S] : 0.0f;
         }
-        wave_sync();
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (own) acc += (double)a[u] * (double)v[u];
       }
       if (own) {
         if (it.aux == kNoSlot)
@@ -372,21 +385,29 @@ __global__ __launch_bounds__(kBlock) void k_grad_b_sampled(GradBParams gb) {
   }
 }
 
-// Block starts of the sampled G, built once per plan: lens[p] = nnz of the B
-// row of A entry p; pos_a = exclusive prefix sums of lens (A order); pos_at[x]
-// = pos_a[perm[x]] (A^T order).
-__global__ void k_bw_lens(int64_t nnz, const int32_t* __restrict__ aci, const int32_t* __restrict__ brp,
-                          int32_t* __restrict__ lens) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
-    const int k = aci[p];
-    lens[p] = brp[k + 1] - brp[k];
-  }
+// Block layout, built once per plan: words[k] = (entries of A^T row k) x
+// slot(nnz(B_k)); off = their exclusive prefix sums; slot_a[perm[x]] = start
+// of the block of A^T entry x, in 16-float units (-1 when B row k is empty).
+__global__ void k_bw_row_words(int64_t n, const int32_t* __restrict__ atrp, const int32_t* __restrict__ brp,
+                               int64_t* __restrict__ words) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    words[k] = (int64_t)(atrp[k + 1] - atrp[k]) * gb_slot(brp[k + 1] - brp[k]);
 }
 
-__global__ void k_bw_pos_at(int64_t nnz, const int32_t* __restrict__ perm, const int64_t* __restrict__ pos_a,
-                            int64_t* __restrict__ pos_at) {
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < nnz; x += (int64_t)gridDim.x * blockDim.x)
-    pos_at[x] = pos_a[perm[x]];
+// one wavefront per A^T row k, lanes over its entries
+__global__ void k_bw_slot_a(int64_t n, const int32_t* __restrict__ atrp, const int32_t* __restrict__ brp,
+                            const int32_t* __restrict__ perm, const int64_t* __restrict__ off,
+                            int32_t* __restrict__ slot_a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t k = w0; k < n; k += nw) {
+    const int x0 = atrp[k], x1 = atrp[k + 1];
+    const int len = brp[k + 1] - brp[k];
+    const int S16 = gb_slot(len) / 16;
+    const int64_t o16 = off[k] / 16;
+    for (int x = x0 + lane; x < x1; x += kWave) slot_a[perm[x]] = len > 0 ? (int32_t)(o16 + (int64_t)(x - x0) * S16) : -1;
+  }
 }
 
 __global__ void k_grad_b_finalize(GradBParams gb) {
@@ -514,28 +535,34 @@ static int launch_grad_a_pass(Plan* p, GradAParams& gp, const tsspgemm_csr* B, b
   return TSSPGEMM_OK;
 }
 
-// Block starts of the sampled G (once per plan): A order by a prefix sum of
-// the B row lengths of A's entries, A^T order through perm.
-static int ensure_sampled_positions(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, const int32_t* perm,
-                                    hipStream_t st) {
+// Block layout of the sampled G (once per plan): B row k's blocks at
+// off[k], in A^T order; slot_a[p] = start of A entry p's block in 16-float
+// units.
+static int ensure_sampled_positions(Plan* p, const tsspgemm_csr* AT, const tsspgemm_csr* A, const tsspgemm_csr* B,
+                                    const int32_t* perm, hipStream_t st) {
   if (p->gb_pos_ready) return TSSPGEMM_OK;
   int rc;
-  const int64_t nnz = A->nnz;
-  if ((rc = p->gb_lens.ensure((size_t)nnz * 4)) || (rc = p->gb_pos_a.ensure((size_t)(nnz + 1) * 8)) ||
-      (rc = p->gb_pos_at.ensure((size_t)nnz * 8)) || (rc = p->gb_scan.ensure((size_t)exscan_workspace_bytes(nnz))))
+  const int64_t n = p->n, nnz = A->nnz;
+  if ((rc = p->gb_words.ensure((size_t)n * 8)) || (rc = p->gb_off.ensure((size_t)(n + 1) * 8)) ||
+      (rc = p->gb_slot_a.ensure((size_t)nnz * 4)) || (rc = p->gb_scan.ensure((size_t)exscan_workspace_bytes(n))))
     return rc;
-  const unsigned g = grid_for(nnz, 256) > 8192 ? 8192 : grid_for(nnz, 256);
-  k_bw_lens<<<g, 256, 0, st>>>(nnz, A->colidx, B->rowptr, (int32_t*)p->gb_lens.p);
+  int64_t* words = (int64_t*)p->gb_words.p;
+  int64_t* off = (int64_t*)p->gb_off.p;
+  const unsigned g = grid_for(n, 256) > 8192 ? 8192 : grid_for(n, 256);
+  k_bw_row_words<<<g, 256, 0, st>>>(n, AT->rowptr, B->rowptr, words);
   TSS_CHECK_LAUNCH();
-  if ((rc = launch_exscan_i32_to_i64((const int32_t*)p->gb_lens.p, nnz, (int64_t*)p->gb_pos_a.p,
-                                     (int64_t*)p->gb_scan.p, st)))
-    return rc;
-  k_bw_pos_at<<<g, 256, 0, st>>>(nnz, perm, (const int64_t*)p->gb_pos_a.p, (int64_t*)p->gb_pos_at.p);
-  TSS_CHECK_LAUNCH();
-  // the buffer of sampled G is sized by the scan's total (synchronizes once per plan)
+  if ((rc = launch_exscan_i64(words, n, off, (int64_t*)p->gb_scan.p, st))) return rc;
+  // the buffer is sized by the scan's total (synchronizes once per plan)
   int64_t total = 0;
-  TSS_HIP(hipMemcpyAsync(&total, (const int64_t*)p->gb_pos_a.p + nnz, 8, hipMemcpyDeviceToHost, st));
+  TSS_HIP(hipMemcpyAsync(&total, off + n, 8, hipMemcpyDeviceToHost, st));
   TSS_HIP(hipStreamSynchronize(st));
+  if (total / 16 > INT32_MAX) {
+    set_error("backward: the sampled G needs more than 2^35 floats");
+    return TSSPGEMM_ERR_UNSUPPORTED;
+  }
+  const unsigned gw = grid_for(n * kWave, 256) > 8192 ? 8192 : grid_for(n * kWave, 256);
+  k_bw_slot_a<<<gw, 256, 0, st>>>(n, AT->rowptr, B->rowptr, perm, off, (int32_t*)p->gb_slot_a.p);
+  TSS_CHECK_LAUNCH();
   p->gb_total = total;
   p->gb_pos_ready = true;
   return TSSPGEMM_OK;
@@ -578,10 +605,10 @@ static int run_backward(Plan* p, const tsspgemm_csr* AT, const int32_t* perm, co
   gp.n_heavy_records = (int32_t)(p->n_split_items + p->n_block_items + p->n_wave_rows);
   gp.n_light = (int32_t)p->n_light_rows;
   if (gather) {
-    if ((rc = ensure_sampled_positions(p, A, B, perm, st))) return rc;
+    if ((rc = ensure_sampled_positions(p, AT, A, B, perm, st))) return rc;
     if ((rc = p->gb_gbuf.ensure((size_t)(p->gb_total > 0 ? p->gb_total : 1) * 4))) return rc;
     gp.gbuf = (float*)p->gb_gbuf.p;
-    gp.pos_a = (const int64_t*)p->gb_pos_a.p;
+    gp.slot_a = (const int32_t*)p->gb_slot_a.p;
   }
   if ((rc = launch_grad_a_pass(p, gp, B, gather, st))) return rc;
   if (!gather) return TSSPGEMM_OK;
@@ -594,21 +621,22 @@ static int run_backward(Plan* p, const tsspgemm_csr* AT, const int32_t* perm, co
   GradBParams gb{};
   gb.pr = plan_problem(p, A, B);
   gb.atrp = AT->rowptr;
-  gb.atci = AT->colidx;
-  gb.perm = perm;
-  gb.gval = (const float*)G->vals;
   gb.grad_b = grad_b;
   gb.gbuf = (const float*)p->gb_gbuf.p;
-  gb.pos_at = (const int64_t*)p->gb_pos_at.p;
+  gb.off = (const int64_t*)p->gb_off.p;
   gb.items = (Item*)p->gb_items.p;
   gb.split_rows = (SplitRow*)p->gb_split.p;
   gb.partial = (double*)p->gb_partial.p;
   gb.ctr = (Counters*)p->gb_ctr.p;
-  if ((rc = launch_zero_bytes(gb.ctr, sizeof(Counters), st))) return rc;
-  const unsigned g = grid_for(n, 256);
-  k_gb_bin_count<<<g, 256, 0, st>>>(gb);
-  k_gb_bin_scan<<<1, 1, 0, st>>>(gb.ctr);
-  k_gb_bin_fill<<<g, 256, 0, st>>>(gb);
+  if (!p->gb_items_ready) {  // the work list depends only on the patterns: built once per plan
+    if ((rc = launch_zero_bytes(gb.ctr, sizeof(Counters), st))) return rc;
+    const unsigned g = grid_for(n, 256);
+    k_gb_bin_count<<<g, 256, 0, st>>>(gb);
+    k_gb_bin_scan<<<1, 1, 0, st>>>(gb.ctr);
+    k_gb_bin_fill<<<g, 256, 0, st>>>(gb);
+    TSS_CHECK_LAUNCH();
+    p->gb_items_ready = true;
+  }
   // lanes per B row: the smallest power of two covering the mean B row length
   const double mean_b = (double)B->nnz / (double)n;
   int gl = 4;
@@ -616,7 +644,7 @@ static int run_backward(Plan* p, const tsspgemm_csr* AT, const int32_t* perm, co
   const unsigned grid = 2048;
 #define TSS_GB(GLV)                                           \
   case GLV:                                                   \
-    k_grad_b_sampled<GLV><<<grid, kBlock, 0, st>>>(gb);       \
+    k_grad_b_blocks<GLV><<<grid, kBlock, 0, st>>>(gb);        \
     break;
   switch (gl) {
     TSS_GB(4) TSS_GB(8) TSS_GB(16) TSS_GB(32) TSS_GB(64)

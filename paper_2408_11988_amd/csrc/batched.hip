@@ -28,7 +28,7 @@ struct BInst {
   int64_t rp_off;  // start of the instance's row pointers in the caller's array
   int32_t gl;      // lanes per B row in the wavefront / workgroup kernel (64 for flat products)
   int32_t lgl;     // lanes per row group in the light kernel
-  int32_t flat;    // flat product lists
+  int32_t flat;    // product layout: kLayoutRows, kLayoutFlat or kLayoutVec
   int32_t pad;
 };
 
@@ -38,7 +38,7 @@ struct BatchDev {
   int32_t dmax;
   int32_t sym_split;
   int32_t idb;  // bytes of the narrowed B column ids (1: dmax <= 256, else 2)
-  int32_t sel_gl, sel_flat;  // numeric launches: the class (group width, layout) this launch runs
+  int32_t sel_gl, sel_flat;  // numeric launches: the class (group width, product layout) this launch runs
   int32_t lds_d, pad2;       // numeric launches: strip stride in LDS (largest d of the class)
   const int64_t* row_off;  // prefix sums over instances: rows
   const int64_t* bm_off;   // bitmap blocks (kBmRows rows)
@@ -53,6 +53,9 @@ struct BatchDev {
   double* partial;       // slot x dmax
   int64_t* block_sums;   // [total_sb] nnz sums, then [total_sb] product sums
   int64_t* inst_flops;   // products per instance
+  int32_t* nb_cnt;       // numeric work list: items per key (class, instance, bin), then
+  int32_t* nb_cur;       //   the fill counter and
+  int32_t* nb_off;       //   the offset of each key (kNumClasses x count x kBins each)
   Counters* ctr;
   int32_t* c_rowptrs;  // run outputs
   int32_t* pool_ci;
@@ -329,16 +332,24 @@ __global__ void k_b_empty_rowptr(BatchDev b) {
 
 // ---------------------------------------------------------------- numeric binning
 
+// The work list is ordered by class, then by instance, then heaviest bin
+// first: key (cls, t, bin). The numeric launches walk it in order, so the
+// wavefronts running at one time gather B rows of one or two instances
+// (whose B fits the caches) rather than of every instance of the batch. A
+// workgroup takes kScanRows rows of one instance (the scan blocks, sb_off).
+__device__ __forceinline__ int nb_key(const BatchDev& b, int cls, int t, int bin) {
+  return (cls * b.count + t) * kBins + bin;
+}
+
 __global__ void k_b_num_bin_count(BatchDev b) {
   __shared__ int32_t hist[kNumClasses * kBins];
   for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x) hist[x] = 0;
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
-  const int64_t r1 = min(b.total_rows, r0 + kBinRowsPerBlock);
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const int t = find_inst(b.row_off, b.count, r);
-    const BInst& in = b.insts[t];
-    const int64_t i = r - b.row_off[t];
+  const int t = find_inst(b.sb_off, b.count, blockIdx.x);
+  const BInst& in = b.insts[t];
+  const int64_t r0 = (blockIdx.x - b.sb_off[t]) * (int64_t)kScanRows;
+  const int64_t r1 = min((int64_t)in.pr.n, r0 + kScanRows);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     const int64_t f = in.pr.flops[i];
     if (f > 0) {
       int cls, key, count, ce;
@@ -348,22 +359,31 @@ __global__ void k_b_num_bin_count(BatchDev b) {
   }
   __syncthreads();
   for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x)
-    if (hist[x]) atomicAdd(&(&b.ctr->num_count[0][0])[x], hist[x]);
+    if (hist[x]) atomicAdd(&b.nb_cnt[nb_key(b, x / kBins, t, x % kBins)], hist[x]);
 }
 
-__global__ void k_b_num_bin_scan(Counters* ctr) {
-  int32_t off = 0;
-  int32_t tot[kNumClasses] = {0, 0, 0, 0};
-  for (int c = 0; c < kNumClasses; ++c)
-    for (int x = 0; x < kBins; ++x) {
-      ctr->num_cursor[c][x] = off;
-      off += ctr->num_count[c][x];
-      tot[c] += ctr->num_count[c][x];
-    }
-  ctr->num_split_items = tot[0];
-  ctr->num_block_items = tot[1];
-  ctr->num_wave_rows = tot[2];
-  ctr->num_light_rows = tot[3];
+// One workgroup: exclusive scan of the key counts into the key offsets, and
+// the class totals.
+__global__ __launch_bounds__(kScanThreads) void k_b_num_bin_scan(BatchDev b) {
+  __shared__ long long sh[32];
+  const int64_t nk = (int64_t)kNumClasses * b.count * kBins;
+  long long carry = 0;
+  for (int64_t x0 = 0; x0 < nk; x0 += kScanThreads) {
+    const int64_t x = x0 + threadIdx.x;
+    const long long v = x < nk ? b.nb_cnt[x] : 0;
+    long long tot;
+    const long long ex = block_exscan_1024(v, sh, &tot);
+    if (x < nk) b.nb_off[x] = (int32_t)(carry + ex);
+    carry += tot;
+  }
+  __syncthreads();  // the offsets are read back below by other threads
+  if (threadIdx.x < kNumClasses) {
+    const int c = threadIdx.x;
+    const int64_t x0 = (int64_t)c * b.count * kBins, x1 = x0 + (int64_t)b.count * kBins;
+    const int32_t lo = x0 < nk ? b.nb_off[x0] : (int32_t)carry;
+    const int32_t hi = x1 < nk ? b.nb_off[x1] : (int32_t)carry;
+    (&b.ctr->num_split_items)[c] = hi - lo;  // split, block, wave, light: consecutive fields
+  }
 }
 
 __global__ void k_b_num_bin_fill(BatchDev b) {
@@ -372,12 +392,11 @@ __global__ void k_b_num_bin_fill(BatchDev b) {
   for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x) cnt[x] = 0;
   if (threadIdx.x == 0) nsplit = 0;
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
-  const int64_t r1 = min(b.total_rows, r0 + kBinRowsPerBlock);
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {  // counts of this workgroup's rows
-    const int t = find_inst(b.row_off, b.count, r);
-    const BInst& in = b.insts[t];
-    const int64_t i = r - b.row_off[t];
+  const int t = find_inst(b.sb_off, b.count, blockIdx.x);
+  const BInst& in = b.insts[t];
+  const int64_t r0 = (blockIdx.x - b.sb_off[t]) * (int64_t)kScanRows;
+  const int64_t r1 = min((int64_t)in.pr.n, r0 + kScanRows);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {  // counts of this workgroup's rows
     const int64_t f = in.pr.flops[i];
     if (f > 0) {
       int cls, key, count, ce;
@@ -388,7 +407,10 @@ __global__ void k_b_num_bin_fill(BatchDev b) {
   }
   __syncthreads();
   for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x) {
-    if (cnt[x]) base[x] = atomicAdd(&(&b.ctr->num_cursor[0][0])[x], cnt[x]);
+    if (cnt[x]) {
+      const int k = nb_key(b, x / kBins, t, x % kBins);
+      base[x] = b.nb_off[k] + atomicAdd(&b.nb_cur[k], cnt[x]);
+    }
     cnt[x] = 0;
   }
   if (threadIdx.x == 0) {
@@ -396,10 +418,7 @@ __global__ void k_b_num_bin_fill(BatchDev b) {
     nsplit = 0;
   }
   __syncthreads();
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const int t = find_inst(b.row_off, b.count, r);
-    const BInst& in = b.insts[t];
-    const int64_t i = r - b.row_off[t];
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     const int64_t f = in.pr.flops[i];
     if (f <= 0) continue;
     const int a = in.pr.arp[i], m = in.pr.arp[i + 1] - a;
@@ -423,7 +442,7 @@ __global__ void k_b_num_bin_fill(BatchDev b) {
 // ---------------------------------------------------------------- numeric
 
 // Workgroup items, then wavefront rows, each walked with a grid stride.
-template <int GL, bool FLAT, typename IdxT>
+template <int GL, int LAYOUT, typename IdxT>
 __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
   using S = SemiringT<float>;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -440,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
     const int d = pr.d;
     for (int j = threadIdx.x; j < kWavesPerBlock * d; j += kBlock) strips[j] = 0.0;
     __syncthreads();
-    accumulate_range<GL, float, IdxT, FLAT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strips + wave * d, stage + wave * kWave);
+    accumulate_range<GL, float, BSep<IdxT>, LAYOUT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strips + wave * d, stage + wave * kWave);
     __syncthreads();
     for (int j = threadIdx.x; j < d; j += kBlock)
       strips[j] = S::add(S::add(S::add(strips[j], strips[d + j]), strips[2 * d + j]), strips[3 * d + j]);
@@ -462,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
       const Problem& pr = b.insts[b.num_inst[x]].pr;
       for (int j = lane; j < pr.d; j += kWave) strip[j] = 0.0;
       wave_sync();
-      accumulate_range<GL, float, IdxT, FLAT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
+      accumulate_range<GL, float, BSep<IdxT>, LAYOUT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
       wave_sync();
       emit_row<float>(pr, it.row, strip, 0, 1);
       wave_sync();
@@ -470,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
   }
 }
 
-template <int GL, bool FLAT, typename IdxT>
+template <int GL, int LAYOUT, typename IdxT>
 __global__ __launch_bounds__(kBlock) void k_b_numeric_light(BatchDev b) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int G = kBlock / GL;
@@ -486,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric_light(BatchDev b) {
     const Problem& pr = in.pr;
     for (int j = gl; j < pr.d; j += GL) strip[j] = 0.0;
     wave_sync();
-    accumulate_light<GL, float, IdxT, FLAT>(pr, it.p0, it.p1, strip, stage, gl);
+    accumulate_light<GL, float, BSep<IdxT>, LAYOUT>(pr, it.p0, it.p1, strip, stage, gl);
     wave_sync();
     emit_group<GL, float>(pr, it.row, strip, gl);
     wave_sync();
@@ -519,7 +538,7 @@ struct Batch {
   std::vector<std::array<int, 3>> heavy_cls, light_cls;
   std::vector<BInst> host_insts;
   DevBuf insts, offs, work, sym_items, sym_inst, num_items, num_inst, split_rows, partial, block_sums, inst_flops,
-      ctr, tmp_rowptrs, tmp_off;
+      ctr, tmp_rowptrs, tmp_off, nbins;
   int64_t total_rows = 0, total_bm = 0, total_lw = 0, total_sb = 0, rowptr_total = 0;
   int64_t sym_cap = 0, num_cap = 0, pool = 0;
   BatchDev dev{};
@@ -551,26 +570,36 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   k_b_scan<<<1, kScanThreads, 0, st>>>(b);
   if (bt->total_sb > 0) k_b_write_rowptr<<<(unsigned)bt->total_sb, kScanThreads, 0, st>>>(b);
   k_b_empty_rowptr<<<grid_for(bt->count, 256), 256, 0, st>>>(b);
-  if (bt->total_rows > 0) k_b_num_bin_count<<<gbin, 256, 0, st>>>(b);
-  k_b_num_bin_scan<<<1, 1, 0, st>>>(b.ctr);
-  if (bt->total_rows > 0) k_b_num_bin_fill<<<gbin, 256, 0, st>>>(b);
+  {
+    int rc = launch_zero_bytes(b.nb_cnt, (size_t)2 * kNumClasses * bt->count * kBins * 4, st);  // counts, cursors
+    if (rc) return rc;
+  }
+  if (bt->total_sb > 0) k_b_num_bin_count<<<(unsigned)bt->total_sb, 256, 0, st>>>(b);
+  k_b_num_bin_scan<<<1, kScanThreads, 0, st>>>(b);
+  if (bt->total_sb > 0) k_b_num_bin_fill<<<(unsigned)bt->total_sb, 256, 0, st>>>(b);
   TSS_CHECK_LAUNCH();
   if (!numeric) return TSSPGEMM_OK;
   // one launch per class of instances (group width, product layout), each
   // taking only its own items from the shared binned list
+#define TSS_BK(K, GLV, L)                                                                              \
+  (bt->idb == 1 ? K<GLV, L, uint8_t> : K<GLV, L, uint16_t>)<<<2048, kBlock, lds, st>>>(bb);
 #define TSS_BN(GLV)                                                                                    \
   case GLV:                                                                                            \
-    if (c[1])                                                                                          \
-      (bt->idb == 1 ? k_b_numeric<GLV, true, uint8_t> : k_b_numeric<GLV, true, uint16_t>)<<<2048, kBlock, lds, st>>>(bb); \
+    if (c[1] == kLayoutFlat)                                                                           \
+      TSS_BK(k_b_numeric, GLV, kLayoutFlat)                                                            \
+    else if (c[1] == kLayoutVec)                                                                       \
+      TSS_BK(k_b_numeric, GLV, kLayoutVec)                                                             \
     else                                                                                               \
-      (bt->idb == 1 ? k_b_numeric<GLV, false, uint8_t> : k_b_numeric<GLV, false, uint16_t>)<<<2048, kBlock, lds, st>>>(bb); \
+      TSS_BK(k_b_numeric, GLV, kLayoutRows)                                                            \
     break;
 #define TSS_BL(GLV)                                                                                    \
   case GLV:                                                                                            \
-    if (c[1])                                                                                          \
-      (bt->idb == 1 ? k_b_numeric_light<GLV, true, uint8_t> : k_b_numeric_light<GLV, true, uint16_t>)<<<2048, kBlock, lds, st>>>(bb); \
+    if (c[1] == kLayoutFlat)                                                                           \
+      TSS_BK(k_b_numeric_light, GLV, kLayoutFlat)                                                      \
+    else if (c[1] == kLayoutVec)                                                                       \
+      TSS_BK(k_b_numeric_light, GLV, kLayoutVec)                                                       \
     else                                                                                               \
-      (bt->idb == 1 ? k_b_numeric_light<GLV, false, uint8_t> : k_b_numeric_light<GLV, false, uint16_t>)<<<2048, kBlock, lds, st>>>(bb); \
+      TSS_BK(k_b_numeric_light, GLV, kLayoutRows)                                                      \
     break;
   for (const auto& c : bt->heavy_cls) {
     BatchDev bb = b;
@@ -596,6 +625,7 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   }
 #undef TSS_BN
 #undef TSS_BL
+#undef TSS_BK
   TSS_CHECK_LAUNCH();
   k_b_split_finalize<<<1024, kBlock, (size_t)bt->dmax * 8, st>>>(b);
   TSS_CHECK_LAUNCH();
@@ -680,6 +710,7 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
       (rc = bt->split_rows.ensure(sizeof(SplitRow) * (bt->total_rows + 1))) ||
       (rc = bt->block_sums.ensure(16 * (bt->total_sb + 1))) || (rc = bt->inst_flops.ensure(8 * (count + 1))) ||
       (rc = bt->ctr.ensure(sizeof(Counters))) || (rc = bt->tmp_rowptrs.ensure(4 * (rp_total + 1))) ||
+      (rc = bt->nbins.ensure((size_t)3 * kNumClasses * (count + 1) * kBins * 4)) ||
       (rc = bt->tmp_off.ensure(8 * (count + 1))))
     return rc;
   TSS_HIP(hipHostMalloc((void**)&bt->host_ctr, sizeof(Counters), hipHostMallocDefault));
@@ -716,8 +747,9 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     in.rp_off = rp_off;
     // the instance's group width and product layout (its own tuning's, or the
     // batch's when no tunings are given)
-    in.flat = tn.products == TSSPGEMM_PRODUCTS_FLAT;
-    in.gl = in.flat ? 64 : tn.group_lanes;
+    in.flat = tn.products == TSSPGEMM_PRODUCTS_FLAT ? kLayoutFlat
+              : (tn.products == TSSPGEMM_PRODUCTS_VEC4 && ((uintptr_t)B->vals % 16) == 0 ? kLayoutVec : kLayoutRows);
+    in.gl = in.flat == kLayoutFlat ? 64 : tn.group_lanes;
     in.lgl = light_group_lanes(tn.group_lanes, B->ncols, TSSPGEMM_PLUS_TIMES_F32);
     auto add_cls = [&](std::vector<std::array<int, 3>>& v, int g) {
       for (auto& c : v)
@@ -755,6 +787,9 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
   b.split_rows = (SplitRow*)bt->split_rows.p;
   b.block_sums = (int64_t*)bt->block_sums.p;
   b.inst_flops = (int64_t*)bt->inst_flops.p;
+  b.nb_cnt = (int32_t*)bt->nbins.p;
+  b.nb_cur = b.nb_cnt + (size_t)kNumClasses * count * kBins;
+  b.nb_off = b.nb_cur + (size_t)kNumClasses * count * kBins;
   b.ctr = (Counters*)bt->ctr.p;
   // a symbolic pass at plan time sizes the output pool and the split slots
   b.c_rowptrs = (int32_t*)bt->tmp_rowptrs.p;

@@ -123,12 +123,12 @@ int launch_count_scan(const Problem& pr, int32_t* cnt, int64_t* block_sums, int3
 int64_t scan_block_sums_capacity(int64_t n);
 int64_t exscan_workspace_bytes(int64_t n);
 int launch_exscan_i32(const int32_t* in, int64_t n, int32_t* out, int64_t* block_sums, hipStream_t st);
-int launch_exscan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, int64_t* block_sums, hipStream_t st);
+int launch_exscan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* block_sums, hipStream_t st);
 
 int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
                    hipStream_t st);
 
-int launch_numeric(int sr, int group_lanes, bool flat, const NumParams& np, int64_t n_grid, hipStream_t st);
+int launch_numeric(int sr, int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st);
 int col_id_bytes(int64_t d);  // 1 or 2: width of the narrowed column ids
 int launch_split_finalize(int sr, const Problem& pr, const SplitRow* rows, int32_t nrows, const double* partial,
                           const int32_t* ipartial, hipStream_t st);

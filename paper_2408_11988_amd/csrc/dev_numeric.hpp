@@ -48,12 +48,28 @@ __device__ __forceinline__ const IdxT* col_ids(const Problem& pr) {
     return (const IdxT*)pr.bcol;
 }
 
+// Readers of B's entries by their position q in B's arrays.
+// BSep: column ids (narrowed to IdxT) and values from two arrays.
+template <typename IdxT>
+struct BSep {
+  using Idx = IdxT;
+  const IdxT* __restrict__ ci;
+  const void* __restrict__ v;
+  __device__ explicit BSep(const Problem& pr) : ci(col_ids<IdxT>(pr)), v(pr.bval) {}
+  __device__ int id(int q) const { return (int)ci[q]; }
+  template <typename T>
+  __device__ T val(int q) const {
+    return ((const T*)v)[q];
+  }
+};
+
+
 // Accumulate entries [p_begin, p_end) of one A row into `strip`, taking
 // 64-entry batches number wstart, wstart + wstride, ... (one wavefront): the
 // batch is staged (entry, B row bounds, value) through LDS, and the 64/GL
 // groups of the wavefront each take a B row, GL entries per step, U rows per
 // group in flight ("per B row" product layout).
-template <int GL, typename T, typename IdxT = int32_t>
+template <int GL, typename T, typename BR>
 __device__ __forceinline__ void accumulate_range_rows(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
                                                  typename SemiringT<T>::acc* strip, int4* stage) {
   using S = SemiringT<T>;
@@ -64,8 +80,7 @@ __device__ __forceinline__ void accumulate_range_rows(const Problem& pr, int p_b
   const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
   const int32_t* __restrict__ brp = pr.brp;
-  const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
-  const T* __restrict__ bval = (const T*)pr.bval;
+  const BR br(pr);
 
   for (int base = p_begin + kWave * wstart; base < p_end; base += kWave * wstride) {
     const int nb = min(kWave, p_end - base);
@@ -96,15 +111,15 @@ __device__ __forceinline__ void accumulate_range_rows(const Problem& pr, int p_b
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (q[u] < qe[u]) {
-          jj[u] = bci[q[u]];
-          bv[u] = bval[q[u]];
+          jj[u] = br.id(q[u]);
+          bv[u] = br.template val<T>(q[u]);
         }
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (q[u] < qe[u]) lds_add(&strip[jj[u]], S::prod(av[u], bv[u]));
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        for (int qq = q[u] + GL; qq < qe[u]; qq += GL) lds_add(&strip[bci[qq]], S::prod(av[u], bval[qq]));
+        for (int qq = q[u] + GL; qq < qe[u]; qq += GL) lds_add(&strip[br.id(qq)], S::prod(av[u], br.template val<T>(qq)));
     }
     wave_sync();
   }
@@ -116,7 +131,7 @@ __device__ __forceinline__ void accumulate_range_rows(const Problem& pr, int p_b
 // group: lane t loads entry t and its B row bounds (coalesced), a wavefront
 // scan of the B row lengths makes the batch's products one flat list, and
 // lane t takes products t, t + 64, ... (U per step, independent loads).
-template <typename T, typename IdxT = int32_t>
+template <typename T, typename BR>
 __device__ __forceinline__ void accumulate_range_flat(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
                                                  typename SemiringT<T>::acc* strip, int4* stage) {
   using S = SemiringT<T>;
@@ -125,8 +140,7 @@ __device__ __forceinline__ void accumulate_range_flat(const Problem& pr, int p_b
   const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
   const int32_t* __restrict__ brp = pr.brp;
-  const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
-  const T* __restrict__ bval = (const T*)pr.bval;
+  const BR br(pr);
 
   for (int base = p_begin + kWave * wstart; base < p_end; base += kWave * wstride) {
     const int nb = min(kWave, p_end - base);
@@ -171,8 +185,8 @@ __device__ __forceinline__ void accumulate_range_flat(const Problem& pr, int p_b
         jj[u] = 0;
         bv[u] = T(0);
         if (q[u] >= 0) {
-          jj[u] = bci[q[u]];
-          bv[u] = bval[q[u]];
+          jj[u] = br.id(q[u]);
+          bv[u] = br.template val<T>(q[u]);
         }
       }
 #pragma unroll
@@ -183,14 +197,143 @@ __device__ __forceinline__ void accumulate_range_flat(const Problem& pr, int p_b
   }
 }
 
-// Product layout of a wavefront's batch: per B row (FLAT false) or flat.
-template <int GL, typename T, typename IdxT, bool FLAT>
+// ---------------------------------------------------------------- 4-entry chunks of B rows
+
+// Product layouts (template argument LAYOUT of the numeric kernels).
+constexpr int kLayoutRows = 0;  // a group of GL lanes per B row, one entry per lane and step
+constexpr int kLayoutFlat = 1;  // the staged entries' products as one flat list
+constexpr int kLayoutVec = 2;   // a group per B row, four consecutive entries per lane and step
+
+// Four consecutive B entries [q, q + 4) with q a multiple of 4: values with
+// one 16-byte load, column ids with one 4-, 8- or 16-byte load (1-, 2- or
+// 4-byte ids); the arrays are 16-byte aligned (checked by the host). A chunk
+// that would pass the end of B (bend = nnz(B)) is read entry by entry.
+template <typename T, typename BR>
+__device__ __forceinline__ void load_chunk4(const BR& br, int q, int bend, int (&j)[4], T (&v)[4]) {
+  using IdxT = typename BR::Idx;
+  if (q + 4 <= bend) {
+    const int4 w4 = *reinterpret_cast<const int4*>((const T*)br.v + q);
+    v[0] = __builtin_bit_cast(T, w4.x);
+    v[1] = __builtin_bit_cast(T, w4.y);
+    v[2] = __builtin_bit_cast(T, w4.z);
+    v[3] = __builtin_bit_cast(T, w4.w);
+    const IdxT* ids = br.ci + q;
+    if constexpr (sizeof(IdxT) == 1) {
+      const uint32_t w = *reinterpret_cast<const uint32_t*>(ids);
+      j[0] = (int)(w & 0xffu);
+      j[1] = (int)((w >> 8) & 0xffu);
+      j[2] = (int)((w >> 16) & 0xffu);
+      j[3] = (int)(w >> 24);
+    } else if constexpr (sizeof(IdxT) == 2) {
+      const uint2 w = *reinterpret_cast<const uint2*>(ids);
+      j[0] = (int)(w.x & 0xffffu);
+      j[1] = (int)(w.x >> 16);
+      j[2] = (int)(w.y & 0xffffu);
+      j[3] = (int)(w.y >> 16);
+    } else {
+      const int4 w = *reinterpret_cast<const int4*>(ids);
+      j[0] = w.x;
+      j[1] = w.y;
+      j[2] = w.z;
+      j[3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      j[t] = 0;
+      v[t] = T(0);
+      if (q + t < bend) {
+        j[t] = br.id(q + t);
+        v[t] = br.template val<T>(q + t);
+      }
+    }
+  }
+}
+
+// Add the entries of chunk [q, q + 4) that lie in the B row [q0, q1).
+template <typename T>
+__device__ __forceinline__ void add_chunk4(typename SemiringT<T>::acc* strip, int q, int q0, int q1, T a,
+                                           const int (&j)[4], const T (&v)[4]) {
+  using S = SemiringT<T>;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    if (q + t >= q0 && q + t < q1) lds_add(&strip[j[t]], S::prod(a, v[t]));
+}
+
+// As accumulate_range_rows, but a lane of a group reads 4-entry chunks of
+// the B row (chunk starts aligned to 4 entries: gl, gl + GL, ... counted from
+// the chunk holding the row's first entry), so one load instruction covers
+// four products and a wavefront keeps four times the B row bytes in flight.
+template <int GL, typename T, typename BR>
+__device__ __forceinline__ void accumulate_range_vec(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
+                                                     typename SemiringT<T>::acc* strip, int4* stage) {
+  constexpr int GPW = kWave / GL;
+  constexpr int U = kHeavyUnroll;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int grp = lane / GL, gl = lane % GL;
+  const int32_t* __restrict__ aci = pr.aci;
+  const T* __restrict__ aval = (const T*)pr.aval;
+  const int32_t* __restrict__ brp = pr.brp;
+  const BR br(pr);
+  const int bend = brp[pr.n];
+
+  for (int base = p_begin + kWave * wstart; base < p_end; base += kWave * wstride) {
+    const int nb = min(kWave, p_end - base);
+    int4 e = make_int4(0, 0, 0, 0);
+    if (lane < nb) {
+      const int k = aci[base + lane];
+      T a = aval[base + lane];
+      e.x = brp[k];
+      e.y = brp[k + 1];
+      e.z = __builtin_bit_cast(int32_t, a);
+    }
+    wave_sync();
+    stage[lane] = e;
+    wave_sync();
+    for (int s = 0; s < nb; s += U * GPW) {
+      int q[U], q0[U], q1[U];
+      T av[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int src = s + u * GPW + grp;
+        int4 r = make_int4(0, 0, 0, 0);
+        if (src < nb) r = stage[src];
+        q0[u] = r.x;
+        q1[u] = r.y;
+        q[u] = (r.x & ~3) + 4 * gl;
+        av[u] = __builtin_bit_cast(T, r.z);
+      }
+      int jj[U][4];
+      T bv[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q[u] < q1[u]) load_chunk4<T>(br, q[u], bend, jj[u], bv[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q[u] < q1[u]) add_chunk4<T>(strip, q[u], q0[u], q1[u], av[u], jj[u], bv[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        for (int qq = q[u] + 4 * GL; qq < q1[u]; qq += 4 * GL) {
+          int j1[4];
+          T v1[4];
+          load_chunk4<T>(br, qq, bend, j1, v1);
+          add_chunk4<T>(strip, qq, q0[u], q1[u], av[u], j1, v1);
+        }
+    }
+    wave_sync();
+  }
+}
+
+// Product layout of a wavefront's batch.
+template <int GL, typename T, typename BR, int LAYOUT>
 __device__ __forceinline__ void accumulate_range(const Problem& pr, int p_begin, int p_end, int wstart, int wstride,
                                                  typename SemiringT<T>::acc* strip, int4* stage) {
-  if constexpr (FLAT)
-    accumulate_range_flat<T, IdxT>(pr, p_begin, p_end, wstart, wstride, strip, stage);
+  if constexpr (LAYOUT == kLayoutFlat)
+    accumulate_range_flat<T, BR>(pr, p_begin, p_end, wstart, wstride, strip, stage);
+  else if constexpr (LAYOUT == kLayoutVec)
+    accumulate_range_vec<GL, T, BR>(pr, p_begin, p_end, wstart, wstride, strip, stage);
   else
-    accumulate_range_rows<GL, T, IdxT>(pr, p_begin, p_end, wstart, wstride, strip, stage);
+    accumulate_range_rows<GL, T, BR>(pr, p_begin, p_end, wstart, wstride, strip, stage);
 }
 
 // Write row `row` of C from a strip: wavefront `wave_id` of `nwaves` handles
@@ -252,7 +395,7 @@ __device__ __forceinline__ void emit_group(const Problem& pr, int64_t row, const
 // Accumulate entries [p0, p1) of one A row into a group's strip (GL lanes,
 // lane gl), per B row: the group stages up to GL A entries with their B row
 // bounds, then takes U staged B rows per step, GL entries of each at a time.
-template <int GL, typename T, typename IdxT = int32_t>
+template <int GL, typename T, typename BR>
 __device__ __forceinline__ void accumulate_light_rows(const Problem& pr, int p0, int p1,
                                                  typename SemiringT<T>::acc* strip, int4* stage, int gl) {
   using S = SemiringT<T>;
@@ -260,8 +403,7 @@ __device__ __forceinline__ void accumulate_light_rows(const Problem& pr, int p0,
   const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
   const int32_t* __restrict__ brp = pr.brp;
-  const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
-  const T* __restrict__ bval = (const T*)pr.bval;
+  const BR br(pr);
   for (int base = p0; base < p1; base += GL) {
     const int nb = min(GL, p1 - base);
     int4 e = make_int4(0, 0, 0, 0);
@@ -289,15 +431,15 @@ __device__ __forceinline__ void accumulate_light_rows(const Problem& pr, int p0,
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (q[u] < qe[u]) {
-          jj[u] = bci[q[u]];
-          bv[u] = bval[q[u]];
+          jj[u] = br.id(q[u]);
+          bv[u] = br.template val<T>(q[u]);
         }
 #pragma unroll
       for (int u = 0; u < U; ++u)
         if (q[u] < qe[u]) lds_add(&strip[jj[u]], S::prod(av[u], bv[u]));
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        for (int qq = q[u] + GL; qq < qe[u]; qq += GL) lds_add(&strip[bci[qq]], S::prod(av[u], bval[qq]));
+        for (int qq = q[u] + GL; qq < qe[u]; qq += GL) lds_add(&strip[br.id(qq)], S::prod(av[u], br.template val<T>(qq)));
     }
     wave_sync();
   }
@@ -312,7 +454,7 @@ __device__ __forceinline__ void accumulate_light_rows(const Problem& pr, int p0,
 // moving forward through the offsets (its product index only grows), so short
 // B rows do not leave lanes idle and a step has one dependent gather.
 // stage[e] = (start of B row - offset of e, end offset of e, A value bits).
-template <int GL, typename T, typename IdxT = int32_t>
+template <int GL, typename T, typename BR>
 __device__ __forceinline__ void accumulate_light_flat(const Problem& pr, int p0, int p1,
                                                  typename SemiringT<T>::acc* strip, int4* stage, int gl) {
   using S = SemiringT<T>;
@@ -321,8 +463,7 @@ __device__ __forceinline__ void accumulate_light_flat(const Problem& pr, int p0,
   const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
   const int32_t* __restrict__ brp = pr.brp;
-  const IdxT* __restrict__ bci = col_ids<IdxT>(pr);
-  const T* __restrict__ bval = (const T*)pr.bval;
+  const BR br(pr);
   for (int base = p0; base < p1; base += GL) {
     const int nb = min(GL, p1 - base);
     int q0 = 0, len = 0;
@@ -366,8 +507,8 @@ __device__ __forceinline__ void accumulate_light_flat(const Problem& pr, int p0,
         jj[u] = 0;
         bv[u] = T(0);
         if (q[u] >= 0) {
-          jj[u] = bci[q[u]];
-          bv[u] = bval[q[u]];
+          jj[u] = br.id(q[u]);
+          bv[u] = br.template val<T>(q[u]);
         }
       }
 #pragma unroll
@@ -378,14 +519,72 @@ __device__ __forceinline__ void accumulate_light_flat(const Problem& pr, int p0,
   }
 }
 
-// Product layout of a lane group's row: per B row (FLAT false) or flat.
-template <int GL, typename T, typename IdxT, bool FLAT>
+// As accumulate_light_rows, with 4-entry chunks of each B row per lane (see
+// accumulate_range_vec).
+template <int GL, typename T, typename BR>
+__device__ __forceinline__ void accumulate_light_vec(const Problem& pr, int p0, int p1,
+                                                     typename SemiringT<T>::acc* strip, int4* stage, int gl) {
+  constexpr int U = kLightUnroll;
+  const int32_t* __restrict__ aci = pr.aci;
+  const T* __restrict__ aval = (const T*)pr.aval;
+  const int32_t* __restrict__ brp = pr.brp;
+  const BR br(pr);
+  const int bend = brp[pr.n];
+  for (int base = p0; base < p1; base += GL) {
+    const int nb = min(GL, p1 - base);
+    int4 e = make_int4(0, 0, 0, 0);
+    if (gl < nb) {
+      const int k = aci[base + gl];
+      e.x = brp[k];
+      e.y = brp[k + 1];
+      e.z = __builtin_bit_cast(int32_t, aval[base + gl]);
+    }
+    wave_sync();
+    stage[gl] = e;
+    wave_sync();
+    for (int s = 0; s < nb; s += U) {
+      int q[U], q0[U], q1[U];
+      T av[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int4 r = make_int4(0, 0, 0, 0);
+        if (s + u < nb) r = stage[s + u];
+        q0[u] = r.x;
+        q1[u] = r.y;
+        q[u] = (r.x & ~3) + 4 * gl;
+        av[u] = __builtin_bit_cast(T, r.z);
+      }
+      int jj[U][4];
+      T bv[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q[u] < q1[u]) load_chunk4<T>(br, q[u], bend, jj[u], bv[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (q[u] < q1[u]) add_chunk4<T>(strip, q[u], q0[u], q1[u], av[u], jj[u], bv[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        for (int qq = q[u] + 4 * GL; qq < q1[u]; qq += 4 * GL) {
+          int j1[4];
+          T v1[4];
+          load_chunk4<T>(br, qq, bend, j1, v1);
+          add_chunk4<T>(strip, qq, q0[u], q1[u], av[u], j1, v1);
+        }
+    }
+    wave_sync();
+  }
+}
+
+// Product layout of a lane group's row.
+template <int GL, typename T, typename BR, int LAYOUT>
 __device__ __forceinline__ void accumulate_light(const Problem& pr, int p0, int p1,
                                                  typename SemiringT<T>::acc* strip, int4* stage, int gl) {
-  if constexpr (FLAT)
-    accumulate_light_flat<GL, T, IdxT>(pr, p0, p1, strip, stage, gl);
+  if constexpr (LAYOUT == kLayoutFlat)
+    accumulate_light_flat<GL, T, BR>(pr, p0, p1, strip, stage, gl);
+  else if constexpr (LAYOUT == kLayoutVec)
+    accumulate_light_vec<GL, T, BR>(pr, p0, p1, strip, stage, gl);
   else
-    accumulate_light_rows<GL, T, IdxT>(pr, p0, p1, strip, stage, gl);
+    accumulate_light_rows<GL, T, BR>(pr, p0, p1, strip, stage, gl);
 }
 
 // ================================================================ binning (numeric)

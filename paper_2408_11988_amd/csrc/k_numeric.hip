@@ -28,7 +28,7 @@
 
 namespace tss {
 
-template <int GL, typename T, typename IdxT, bool FLAT>
+template <int GL, typename T, typename BR, int LAYOUT>
 __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   using S = SemiringT<T>;
   using Acc = typename S::acc;
@@ -55,9 +55,9 @@ __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   __syncthreads();
   if (valid) {
     if (wg_mode)
-      accumulate_range<GL, T, IdxT, FLAT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strip, stage + wave * kWave);
+      accumulate_range<GL, T, BR, LAYOUT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strip, stage + wave * kWave);
     else
-      accumulate_range<GL, T, IdxT, FLAT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
+      accumulate_range<GL, T, BR, LAYOUT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
   }
   __syncthreads();
   if (wg_mode) {
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_numeric(NumParams np) {
   }
 }
 
-template <int GL, typename T, typename IdxT, bool FLAT>
+template <int GL, typename T, typename BR, int LAYOUT>
 __global__ __launch_bounds__(kBlock) void k_numeric_light(NumParams np) {
   using Acc = typename SemiringT<T>::acc;
   constexpr int G = kBlock / GL;  // rows in flight per workgroup
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_numeric_light(NumParams np) {
     const Item it = items[t];
     for (int j = gl; j < d; j += GL) strip[j] = Acc(0);
     wave_sync();
-    accumulate_light<GL, T, IdxT, FLAT>(pr, it.p0, it.p1, strip, stage, gl);
+    accumulate_light<GL, T, BR, LAYOUT>(pr, it.p0, it.p1, strip, stage, gl);
     wave_sync();
     emit_group<GL, T>(pr, it.row, strip, gl);
     wave_sync();
@@ -124,17 +124,17 @@ static int64_t light_grid(int64_t n_light, int gl) {
 
 int col_id_bytes(int64_t d) { return d <= 256 ? 1 : 2; }
 
-template <typename T, typename IdxT, bool FLAT>
+template <typename T, typename BR, int LAYOUT>
 static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st) {
   const size_t ab = sizeof(typename SemiringT<T>::acc);
   if (n_grid > 0) {
     const size_t lds = (size_t)kWavesPerBlock * np.pr.d * ab + kWavesPerBlock * kWave * sizeof(int4);
-    switch (FLAT ? 64 : group_lanes) {  // the flat layout uses the whole wavefront
-      case 4: k_numeric<4, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
-      case 8: k_numeric<8, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
-      case 16: k_numeric<16, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
-      case 32: k_numeric<32, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
-      case 64: k_numeric<64, T, IdxT, FLAT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+    switch (LAYOUT == kLayoutFlat ? 64 : group_lanes) {  // the flat layout uses the whole wavefront
+      case 4: k_numeric<4, T, BR, LAYOUT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 8: k_numeric<8, T, BR, LAYOUT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 16: k_numeric<16, T, BR, LAYOUT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 32: k_numeric<32, T, BR, LAYOUT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
+      case 64: k_numeric<64, T, BR, LAYOUT><<<(unsigned)n_grid, kBlock, lds, st>>>(np); break;
       default:
         set_error("numeric: group_lanes must be 4, 8, 16, 32 or 64");
         return TSSPGEMM_ERR_INVALID_ARG;
@@ -147,11 +147,11 @@ static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid
     const unsigned g = (unsigned)light_grid(np.n_light, gl);
     const size_t lds = (size_t)(kBlock / gl) * np.pr.d * ab + kBlock * sizeof(int4);
     switch (gl) {
-      case 4: k_numeric_light<4, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
-      case 8: k_numeric_light<8, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
-      case 16: k_numeric_light<16, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
-      case 32: k_numeric_light<32, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
-      case 64: k_numeric_light<64, T, IdxT, FLAT><<<g, kBlock, lds, st>>>(np); break;
+      case 4: k_numeric_light<4, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
+      case 8: k_numeric_light<8, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
+      case 16: k_numeric_light<16, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
+      case 32: k_numeric_light<32, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
+      case 64: k_numeric_light<64, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
       default:
         set_error("numeric: bad light group width");
         return TSSPGEMM_ERR_INVALID_ARG;
@@ -161,24 +161,28 @@ static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid
   return TSSPGEMM_OK;
 }
 
-template <typename T, typename IdxT>
-static int launch_numeric_l(int group_lanes, bool flat, const NumParams& np, int64_t n_grid, hipStream_t st) {
-  return flat ? launch_numeric_t<T, IdxT, true>(group_lanes, np, n_grid, st)
-              : launch_numeric_t<T, IdxT, false>(group_lanes, np, n_grid, st);
+template <typename T, typename BR>
+static int launch_numeric_l(int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st) {
+  switch (products) {
+    case TSSPGEMM_PRODUCTS_FLAT: return launch_numeric_t<T, BR, kLayoutFlat>(group_lanes, np, n_grid, st);
+    case TSSPGEMM_PRODUCTS_VEC4: return launch_numeric_t<T, BR, kLayoutVec>(group_lanes, np, n_grid, st);
+    default: return launch_numeric_t<T, BR, kLayoutRows>(group_lanes, np, n_grid, st);
+  }
 }
 
 // B's column ids are read narrowed (np.pr.bcol, col_id_bytes(d) bytes each).
-int launch_numeric(int sr, int group_lanes, bool flat, const NumParams& np, int64_t n_grid, hipStream_t st) {
+// products: tsspgemm_products (resolved, not AUTO).
+int launch_numeric(int sr, int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st) {
   const bool b8 = col_id_bytes(np.pr.d) == 1;
   if (!np.pr.bcol && np.pr.n > 0) {
     set_error("numeric: narrowed column ids missing");
     return TSSPGEMM_ERR_INVALID_ARG;
   }
   if (sr == TSSPGEMM_PLUS_TIMES_F32)
-    return b8 ? launch_numeric_l<float, uint8_t>(group_lanes, flat, np, n_grid, st)
-              : launch_numeric_l<float, uint16_t>(group_lanes, flat, np, n_grid, st);
-  return b8 ? launch_numeric_l<int32_t, uint8_t>(group_lanes, flat, np, n_grid, st)
-            : launch_numeric_l<int32_t, uint16_t>(group_lanes, flat, np, n_grid, st);
+    return b8 ? launch_numeric_l<float, BSep<uint8_t>>(group_lanes, products, np, n_grid, st)
+              : launch_numeric_l<float, BSep<uint16_t>>(group_lanes, products, np, n_grid, st);
+  return b8 ? launch_numeric_l<int32_t, BSep<uint8_t>>(group_lanes, products, np, n_grid, st)
+            : launch_numeric_l<int32_t, BSep<uint16_t>>(group_lanes, products, np, n_grid, st);
 }
 
 // Split rows: add the chunks' partial strips in chunk order, then emit.
@@ -269,29 +273,34 @@ __global__ void k_num_bin_count(Problem pr, NumThresholds th, Counters* ctr) {
     if (hist[t]) atomicAdd(&(&ctr->num_count[0][0])[t], hist[t]);
 }
 
-__global__ void k_num_bin_scan(Counters* ctr) {
-  int32_t off = 0;
-  int32_t tot[kNumClasses] = {0, 0, 0, 0};
-  for (int c = 0; c < kNumClasses; ++c)
-    for (int b = 0; b < kBins; ++b) {
-      ctr->num_cursor[c][b] = off;
-      off += ctr->num_count[c][b];
-      tot[c] += ctr->num_count[c][b];
+// Offsets of the (class, bin) buckets: an exclusive scan of the counts in
+// LDS, done by every fill workgroup (128 values), so no separate scan launch.
+__device__ __forceinline__ void num_bucket_offsets(const Counters* ctr, int32_t* off) {
+  if (threadIdx.x == 0) {
+    int32_t o = 0;
+    for (int t = 0; t < kNumClasses * kBins; ++t) {
+      off[t] = o;
+      o += (&ctr->num_count[0][0])[t];
     }
-  ctr->num_split_items = tot[0];
-  ctr->num_block_items = tot[1];
-  ctr->num_wave_rows = tot[2];
-  ctr->num_light_rows = tot[3];
+  }
 }
 
 // Items are placed with one global reservation per (class, bin) per
-// workgroup (counts from a first pass over its rows); the slot inside the
-// workgroup's range comes from an LDS counter in the second pass.
+// workgroup (counts from a first pass over its rows): the bucket's offset
+// plus the bucket's fill counter (num_cursor, zero at the start); the slot
+// inside the workgroup's range comes from an LDS counter in the second pass.
+// Workgroup 0 also stores the class totals.
 __global__ void k_num_bin_fill(Problem pr, NumThresholds th, Item* items, SplitRow* split_rows, Counters* ctr) {
-  __shared__ int32_t cnt[kNumClasses * kBins], base[kNumClasses * kBins];
+  __shared__ int32_t cnt[kNumClasses * kBins], base[kNumClasses * kBins], off[kNumClasses * kBins];
   __shared__ int32_t nsplit, split_base;
   for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) cnt[t] = 0;
   if (threadIdx.x == 0) nsplit = 0;
+  num_bucket_offsets(ctr, off);
+  if (blockIdx.x == 0 && threadIdx.x < kNumClasses) {
+    int32_t tot = 0;
+    for (int b = 0; b < kBins; ++b) tot += ctr->num_count[threadIdx.x][b];
+    (&ctr->num_split_items)[threadIdx.x] = tot;  // split, block, wave, light: consecutive fields
+  }
   __syncthreads();
   const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
   const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
@@ -306,7 +315,7 @@ __global__ void k_num_bin_fill(Problem pr, NumThresholds th, Item* items, SplitR
   }
   __syncthreads();
   for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) {
-    if (cnt[t]) base[t] = atomicAdd(&(&ctr->num_cursor[0][0])[t], cnt[t]);
+    if (cnt[t]) base[t] = off[t] + atomicAdd(&(&ctr->num_cursor[0][0])[t], cnt[t]);
     cnt[t] = 0;
   }
   if (threadIdx.x == 0) {
@@ -335,13 +344,10 @@ __global__ void k_num_bin_fill(Problem pr, NumThresholds th, Item* items, SplitR
 
 int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
                    hipStream_t st) {
-  if (pr.n > 0) {
+  if (pr.n > 0) {  // (with no rows the zeroed counters are the totals)
     const unsigned g = grid_for(pr.n, kBinRowsPerBlock);
     k_num_bin_count<<<g, 256, 0, st>>>(pr, th, ctr);
-    k_num_bin_scan<<<1, 1, 0, st>>>(ctr);
     k_num_bin_fill<<<g, 256, 0, st>>>(pr, th, items, split_rows, ctr);
-  } else {
-    k_num_bin_scan<<<1, 1, 0, st>>>(ctr);
   }
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;

@@ -131,22 +131,22 @@ __global__ void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
   if (threadIdx.x < kBins && hist[threadIdx.x]) atomicAdd(&ctr->sym_count[threadIdx.x], hist[threadIdx.x]);
 }
 
-// single thread: bin offsets (stored in the cursors) and the item total
-__global__ void k_sym_bin_scan(Counters* ctr) {
-  int32_t off = 0;
-  for (int b = 0; b < kBins; ++b) {
-    ctr->sym_cursor[b] = off;
-    off += ctr->sym_count[b];
-  }
-  ctr->sym_total = off;
-}
-
 // Items are placed with one global reservation per bin per workgroup (its
-// counts from a first pass over its rows); the slot inside the workgroup's
-// range comes from an LDS counter in the second pass.
+// counts from a first pass over its rows): the bin's offset (a scan of the
+// counts, done by every workgroup) plus the bin's fill counter (sym_cursor,
+// zero at the start); the slot inside the workgroup's range comes from an
+// LDS counter in the second pass. Workgroup 0 stores the item total.
 __global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Counters* ctr) {
-  __shared__ int32_t cnt[kBins], base[kBins];
+  __shared__ int32_t cnt[kBins], base[kBins], off[kBins];
   if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    int32_t o = 0;
+    for (int b = 0; b < kBins; ++b) {
+      off[b] = o;
+      o += ctr->sym_count[b];
+    }
+    if (blockIdx.x == 0) ctr->sym_total = o;
+  }
   __syncthreads();
   const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
   const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
@@ -157,7 +157,8 @@ __global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Count
   }
   __syncthreads();
   if (threadIdx.x < kBins) {
-    if (cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&ctr->sym_cursor[threadIdx.x], cnt[threadIdx.x]);
+    if (cnt[threadIdx.x])
+      base[threadIdx.x] = off[threadIdx.x] + atomicAdd(&ctr->sym_cursor[threadIdx.x], cnt[threadIdx.x]);
     cnt[threadIdx.x] = 0;
   }
   __syncthreads();
@@ -179,14 +180,9 @@ __global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Count
 }
 
 int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st) {
-  if (pr.n == 0) {
-    k_sym_bin_scan<<<1, 1, 0, st>>>(ctr);
-    TSS_CHECK_LAUNCH();
-    return TSSPGEMM_OK;
-  }
+  if (pr.n == 0) return TSSPGEMM_OK;  // the zeroed counters are the totals
   const unsigned g = grid_for(pr.n, kBinRowsPerBlock);
   k_sym_bin_count<<<g, 256, 0, st>>>(pr, split_nnz, ctr);
-  k_sym_bin_scan<<<1, 1, 0, st>>>(ctr);
   k_sym_bin_fill<<<g, 256, 0, st>>>(pr, split_nnz, items, ctr);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
@@ -687,7 +683,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_write_i32(int64_t n, cons
   }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_write_i64(int64_t n, const int32_t* __restrict__ in,
+__global__ __launch_bounds__(kScanThreads) void k_scan_sum_i64(int64_t n, const int64_t* __restrict__ in,
+                                                              int64_t* __restrict__ block_sums) {
+  __shared__ long long sh[32];
+  const int64_t base = (int64_t)blockIdx.x * kScanRows;
+  long long s = 0;
+#pragma unroll
+  for (int u = 0; u < kScanPer; ++u) {
+    const int64_t i = base + u * kScanThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  long long tot;
+  block_exscan_1024(s, sh, &tot);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_write_i64(int64_t n, const int64_t* __restrict__ in,
                                                                 const int64_t* __restrict__ block_sums,
                                                                 int64_t* __restrict__ out) {
   __shared__ long long sh[32];
@@ -706,11 +717,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_write_i64(int64_t n, cons
 
 int64_t exscan_workspace_bytes(int64_t n) { return 8 * ((n + kScanRows - 1) / kScanRows + 1); }
 
-// out[0..n] = exclusive prefix sums of in[0..n) as int64 (out[n] = total).
-int launch_exscan_i32_to_i64(const int32_t* in, int64_t n, int64_t* out, int64_t* block_sums, hipStream_t st) {
+// out[0..n] = exclusive prefix sums of in[0..n), int64 (out[n] = total).
+int launch_exscan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* block_sums, hipStream_t st) {
   const int64_t nb = (n + kScanRows - 1) / kScanRows;
   if (nb == 0) return launch_zero_bytes(out, 8, st);
-  k_scan_sum_i32<<<(unsigned)nb, kScanThreads, 0, st>>>(n, in, block_sums);
+  k_scan_sum_i64<<<(unsigned)nb, kScanThreads, 0, st>>>(n, in, block_sums);
   k_scan_blocks_i64<<<1, kScanThreads, 0, st>>>(nb, block_sums, nullptr);
   k_scan_write_i64<<<(unsigned)nb, kScanThreads, 0, st>>>(n, in, block_sums, out);
   TSS_CHECK_LAUNCH();

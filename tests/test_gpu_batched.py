@@ -57,7 +57,9 @@ def test_batched_matches_plain_and_oracle(tuned):
     tunings = None
     if tuned:  # forces every work class somewhere in the batch
         tunings = [dict(group_lanes=16, light_max_flops=64, wave_max_flops=512, split_flops=2048) for _ in host]
-        tunings[0]["products"] = "flat"  # each tuned instance keeps its own layout: one flat, the rest per B row
+        tunings[0]["products"] = "flat"  # each tuned instance keeps its own layout: one flat, two in
+        tunings[2]["products"] = "vec4"  # 4-entry chunks, the rest per B row
+        tunings[6]["products"] = "vec4"
     note(f"batched {len(pairs)} instances tuned={tuned}")
     bt = Batched(pairs, tunings)
     bt.run()

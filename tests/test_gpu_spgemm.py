@@ -39,7 +39,7 @@ ACCS = ["lds", "hash"]
 ALL_CLASSES = dict(light_max_flops=16, wave_max_flops=64, split_flops=256)
 
 
-@pytest.mark.parametrize("classes", ["default", "all", "all_flat"])
+@pytest.mark.parametrize("classes", ["default", "all", "all_flat", "all_vec4"])
 @pytest.mark.parametrize("acc", ACCS)
 @pytest.mark.parametrize("d", D_VALUES)
 def test_plus_times_random(d, acc, classes):
@@ -50,6 +50,8 @@ def test_plus_times_random(d, acc, classes):
     tun = dict(accumulator=acc, **(ALL_CLASSES if classes.startswith("all") else {}))
     if classes == "all_flat":
         tun["products"] = "flat"
+    if classes == "all_vec4":
+        tun["products"] = "vec4"
     note(f"plus_times random n={n} d={d} nnzA={a.nnz} nnzB={b.nnz} tuning={tun}")
     C = _tss().spgemm(to_dev(a), to_dev(b), tuning=tun)
     torch.cuda.synchronize()
@@ -98,7 +100,8 @@ def test_int32_exact(d, acc):
     a = random_csr(rng, n, n, 0.05, kind="int", dense_rows=1)
     b = random_csr(rng, n, d, min(0.1, 20.0 / d), kind="int")
     note(f"int32 n={n} d={d} acc={acc}")
-    for tun in (dict(accumulator=acc), dict(accumulator=acc, **ALL_CLASSES)):
+    for tun in (dict(accumulator=acc), dict(accumulator=acc, **ALL_CLASSES),
+                dict(accumulator=acc, products="vec4", **ALL_CLASSES)):
         C = _tss().spgemm(to_dev(a, dtype=torch.int32), to_dev(b, dtype=torch.int32), semiring="plus_times_i32",
                           tuning=tun)
         torch.cuda.synchronize()
@@ -164,7 +167,9 @@ def test_modes_and_tuning_do_not_change_results():
     compare_f32(a, b, ref)
     ref_h = ref.to_host()
     configs = [dict(group_lanes=g) for g in (4, 8, 16, 32, 64)]
-    configs += [dict(group_lanes=g, products=pl) for g in (8, 32, 64) for pl in ("rows", "flat")]
+    configs += [dict(group_lanes=g, products=pl) for g in (8, 32, 64) for pl in ("rows", "flat", "vec4")]
+    configs += [dict(group_lanes=g, products="vec4") for g in (4, 16)]
+    configs += [dict(light_max_flops=200, wave_max_flops=260, split_flops=1000, products="vec4")]
     configs += [dict(light_max_flops=1, wave_max_flops=16, split_flops=64),
                 dict(light_max_flops=1, wave_max_flops=1, split_flops=1),
                 dict(light_max_flops=200, wave_max_flops=260, split_flops=1000),
