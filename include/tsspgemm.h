@@ -323,14 +323,17 @@ int tsspgemm_merge_values(int32_t count, const tsspgemm_csr* parts, const int32_
                           float* out_vals, void* stream);
 
 /* Batched plus-times TS-SpGEMM: `count` independent instances C_t = A_t B_t
- * (FP32 values, d_t <= 1024), every phase one launch over all instances, the
- * work of all instances binned into one list (heaviest first).
+ * (FP32 values, d_t <= 1024): every symbolic phase one launch over all
+ * instances, the work of all instances binned into one list (by instance,
+ * heaviest first); the numeric phase one pair of launches per class of
+ * instances with the same group widths, product layout and LDS strip size.
  * tsspgemm_batched_plan sizes everything once (it runs the symbolic phase;
  * synchronizes); the patterns of A_t and B_t must not change afterwards,
  * their values may.
  *   As, Bs: HOST arrays of `count` descriptors (device data).
- *   tune: NULL, or a HOST array of `count` tunings (instance thresholds; the
- *   group width of the whole batch comes from tune[0]).
+ *   tune: NULL (one group width and product layout for the whole batch,
+ *   from the mean B row length over all instances), or a HOST array of
+ *   `count` tunings, each instance's own.
  *   pool_capacity: HOST out, sum of nnz(C_t) = entries of the output pool.
  *   rowptr_total: HOST out, sum of (n_t + 1).
  * tsspgemm_batched_run queues the whole batch (symbolic, scans, numeric) on

@@ -10,26 +10,28 @@
 // First pass, over A's rows (the forward plan's binned rows): a row's G
 // values are staged in an LDS strip of width d; each A entry (i,k) is a dot
 // product of B row k with that strip (dL/dA), taken by a group of GL lanes
-// and reduced across the group. For dL/dB the same walk writes A(i,k) and
-// every G(i,j) it reads into a block per A entry (i,k): A(i,k), then the
-// values of G(i, pat(B_k)) in B row order. The FP32 values are copied, not
-// rounded. Blocks are in A order, back to back, so the walk writes them
-// contiguously.
+// and reduced across the group. For dL/dB the same walk copies A(i,k) and
+// every G(i,j) it reads (FP32 values, not rounded) into a block per A entry:
+// A(i,k), then G(i, pat(B_k)) in B row order, zero-padded to a slot of a
+// multiple of 16 floats (64 bytes). Slots are placed in A^T order, so the
+// group's lanes write whole 64-byte segments at scattered places.
 //
-// Second pass, over A^T (from tsspgemm_transpose): a group of GL lanes owns
-// the entries of one B row k (lane = entry) and runs over the entries i of
-// A^T row k in order, adding A(i,k) G(i,j) from block (i,k) (one or two
-// cache lines per (B row, A^T entry) pair). Long A^T rows are cut into
-// chunks whose partial sums a third kernel adds in chunk order.
+// Second pass, over A^T (from tsspgemm_transpose): B row k's blocks are one
+// contiguous range. A group of GL lanes takes the slot positions of B row k
+// (lane = entry) and runs over the entries i of A^T row k in order, adding
+// A(i,k) G(i,j). Long A^T rows are cut into chunks whose partial sums a
+// third kernel adds in chunk order.
 //
 // Measured at R-MAT 20 x 256 (5%), per call: a single pass over A^T that
 // looked G(i,j) up in C's row i (a record of C's bitmap word plus a
 // popcount) fetched about 15 GB; blocks without A(i,k), read with A(i,k)
 // gathered through the permutation, 11.6 GB in the second pass (a cache
-// line per pair for the gather alone); blocks stored in A^T order made the
-// second pass one contiguous read (3.2 GB, 0.75 ms) but scattered the first
-// pass's writes (3.4 GB in 32- and 64-byte pieces), which cost 0.9 ms more
-// there.
+// line per pair for the gather alone); blocks packed back to back in A
+// order made the first pass's writes contiguous but the second pass a
+// gather of one or two cache lines per pair; packed blocks in A^T order
+// scattered the first pass's writes in 32- and 64-byte pieces. The padded
+// A^T-order slots keep the second pass one contiguous read (about 3.4 GB,
+// 0.8 ms) with whole-segment writes in the first.
 #include "api_internal.hpp"
 #include "dev_numeric.hpp"
 

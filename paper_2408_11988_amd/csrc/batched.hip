@@ -29,7 +29,7 @@ struct BInst {
   int32_t gl;      // lanes per B row in the wavefront / workgroup kernel (64 for flat products)
   int32_t lgl;     // lanes per row group in the light kernel
   int32_t flat;    // product layout: kLayoutRows, kLayoutFlat or kLayoutVec
-  int32_t pad;
+  int32_t rank;    // place of the instance in the numeric work list (instances of one launch class are adjacent)
 };
 
 struct BatchDev {
@@ -38,8 +38,8 @@ struct BatchDev {
   int32_t dmax;
   int32_t sym_split;
   int32_t idb;  // bytes of the narrowed B column ids (1: dmax <= 256, else 2)
-  int32_t sel_gl, sel_flat;  // numeric launches: the class (group width, product layout) this launch runs
-  int32_t lds_d, pad2;       // numeric launches: strip stride in LDS (largest d of the class)
+  int32_t r_lo, r_hi;  // numeric launches: the ranks of the instances this launch runs
+  int32_t lds_d, pad2;  // numeric launches: strip stride in LDS (largest d of the class)
   const int64_t* row_off;  // prefix sums over instances: rows
   const int64_t* bm_off;   // bitmap blocks (kBmRows rows)
   const int64_t* lw_off;   // light symbolic wavefronts (64 / wp rows each)
@@ -55,7 +55,10 @@ struct BatchDev {
   int64_t* inst_flops;   // products per instance
   int32_t* nb_cnt;       // numeric work list: items per key (class, instance, bin), then
   int32_t* nb_cur;       //   the fill counter and
-  int32_t* nb_off;       //   the offset of each key (kNumClasses x count x kBins each)
+  int32_t* nb_off;       //   the offset of each key (kNumClasses x count x kBins each, then the total)
+  int32_t* sb_cnt;       // symbolic work list: items per key (instance, bin), the fill
+  int32_t* sb_cur;       //   counter and the offset of each key (count x kBins each)
+  int32_t* sb_kof;
   Counters* ctr;
   int32_t* c_rowptrs;  // run outputs
   int32_t* pool_ci;
@@ -90,57 +93,68 @@ __global__ __launch_bounds__(256) void k_b_bitmap(BatchDev b) {
 
 // ---------------------------------------------------------------- symbolic
 
+// The symbolic work list (rows with more A entries than a light slot takes,
+// and chunks of split rows) is ordered by instance, then heaviest bin first:
+// key (t, bin), so the wavefronts running at one time gather the B bitmap
+// rows of one or two instances. A workgroup takes kScanRows rows of one
+// instance (the scan blocks, sb_off).
 __global__ void k_b_sym_bin_count(BatchDev b) {
   __shared__ int32_t hist[kBins];
   if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
-  const int64_t r1 = min(b.total_rows, r0 + kBinRowsPerBlock);
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const int t = find_inst(b.row_off, b.count, r);
-    const Problem& pr = b.insts[t].pr;
-    const int64_t i = r - b.row_off[t];
+  const int t = find_inst(b.sb_off, b.count, blockIdx.x);
+  const Problem& pr = b.insts[t].pr;
+  const int64_t r0 = (blockIdx.x - b.sb_off[t]) * (int64_t)kScanRows;
+  const int64_t r1 = min((int64_t)pr.n, r0 + kScanRows);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     int bin, count;
     sym_bin(pr.arp[i + 1] - pr.arp[i], b.sym_split, bin, count);
     if (count) atomicAdd(&hist[bin], count);
   }
   __syncthreads();
-  if (threadIdx.x < kBins && hist[threadIdx.x]) atomicAdd(&b.ctr->sym_count[threadIdx.x], hist[threadIdx.x]);
+  if (threadIdx.x < kBins && hist[threadIdx.x]) atomicAdd(&b.sb_cnt[t * kBins + threadIdx.x], hist[threadIdx.x]);
 }
 
-__global__ void k_b_sym_bin_scan(Counters* ctr) {
-  int32_t off = 0;
-  for (int x = 0; x < kBins; ++x) {
-    ctr->sym_cursor[x] = off;
-    off += ctr->sym_count[x];
+// One workgroup: exclusive scan of the (instance, bin) counts into offsets,
+// and the item total.
+__global__ __launch_bounds__(kScanThreads) void k_b_sym_bin_scan(BatchDev b) {
+  __shared__ long long sh[32];
+  const int64_t nk = (int64_t)b.count * kBins;
+  long long carry = 0;
+  for (int64_t x0 = 0; x0 < nk; x0 += kScanThreads) {
+    const int64_t x = x0 + threadIdx.x;
+    const long long v = x < nk ? b.sb_cnt[x] : 0;
+    long long tot;
+    const long long ex = block_exscan_1024(v, sh, &tot);
+    if (x < nk) b.sb_kof[x] = (int32_t)(carry + ex);
+    carry += tot;
   }
-  ctr->sym_total = off;
+  if (threadIdx.x == 0) b.ctr->sym_total = (int32_t)carry;
 }
 
 __global__ void k_b_sym_bin_fill(BatchDev b) {
   __shared__ int32_t cnt[kBins], base[kBins];
   if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
-  const int64_t r1 = min(b.total_rows, r0 + kBinRowsPerBlock);
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {  // counts of this workgroup's rows
-    const int t = find_inst(b.row_off, b.count, r);
-    const Problem& pr = b.insts[t].pr;
-    const int64_t i = r - b.row_off[t];
+  const int t = find_inst(b.sb_off, b.count, blockIdx.x);
+  const Problem& pr = b.insts[t].pr;
+  const int64_t r0 = (blockIdx.x - b.sb_off[t]) * (int64_t)kScanRows;
+  const int64_t r1 = min((int64_t)pr.n, r0 + kScanRows);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {  // counts of this workgroup's rows
     int bin, count;
     sym_bin(pr.arp[i + 1] - pr.arp[i], b.sym_split, bin, count);
     if (count) atomicAdd(&cnt[bin], count);
   }
   __syncthreads();
   if (threadIdx.x < kBins) {
-    if (cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&b.ctr->sym_cursor[threadIdx.x], cnt[threadIdx.x]);
+    if (cnt[threadIdx.x]) {
+      const int k = t * kBins + threadIdx.x;
+      base[threadIdx.x] = b.sb_kof[k] + atomicAdd(&b.sb_cur[k], cnt[threadIdx.x]);
+    }
     cnt[threadIdx.x] = 0;
   }
   __syncthreads();
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const int t = find_inst(b.row_off, b.count, r);
-    const Problem& pr = b.insts[t].pr;
-    const int64_t i = r - b.row_off[t];
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
     const int a = pr.arp[i], m = pr.arp[i + 1] - a;
     int bin, count;
     sym_bin(m, b.sym_split, bin, count);
@@ -332,13 +346,20 @@ __global__ void k_b_empty_rowptr(BatchDev b) {
 
 // ---------------------------------------------------------------- numeric binning
 
-// The work list is ordered by class, then by instance, then heaviest bin
-// first: key (cls, t, bin). The numeric launches walk it in order, so the
-// wavefronts running at one time gather B rows of one or two instances
-// (whose B fits the caches) rather than of every instance of the batch. A
-// workgroup takes kScanRows rows of one instance (the scan blocks, sb_off).
-__device__ __forceinline__ int nb_key(const BatchDev& b, int cls, int t, int bin) {
-  return (cls * b.count + t) * kBins + bin;
+// The work list is ordered by class, then by instance rank, then heaviest
+// bin first: key (cls, rank, bin). The numeric launches walk it in order, so
+// the wavefronts running at one time gather B rows of one or two instances
+// (whose B fits the caches) rather than of every instance of the batch, and
+// the instances of one launch class (ranks [r_lo, r_hi)) hold one contiguous
+// range of each class. A workgroup takes kScanRows rows of one instance (the
+// scan blocks, sb_off).
+__device__ __forceinline__ int nb_key(const BatchDev& b, int cls, int rank, int bin) {
+  return (cls * b.count + rank) * kBins + bin;
+}
+
+// Items of class cls of this launch's instances: [lo, hi) of the work list.
+__device__ __forceinline__ int2 nb_range(const BatchDev& b, int cls) {
+  return make_int2(b.nb_off[nb_key(b, cls, b.r_lo, 0)], b.nb_off[nb_key(b, cls, b.r_hi, 0)]);
 }
 
 __global__ void k_b_num_bin_count(BatchDev b) {
@@ -359,7 +380,7 @@ __global__ void k_b_num_bin_count(BatchDev b) {
   }
   __syncthreads();
   for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x)
-    if (hist[x]) atomicAdd(&b.nb_cnt[nb_key(b, x / kBins, t, x % kBins)], hist[x]);
+    if (hist[x]) atomicAdd(&b.nb_cnt[nb_key(b, x / kBins, in.rank, x % kBins)], hist[x]);
 }
 
 // One workgroup: exclusive scan of the key counts into the key offsets, and
@@ -376,6 +397,7 @@ __global__ __launch_bounds__(kScanThreads) void k_b_num_bin_scan(BatchDev b) {
     if (x < nk) b.nb_off[x] = (int32_t)(carry + ex);
     carry += tot;
   }
+  if (threadIdx.x == 0) b.nb_off[nk] = (int32_t)carry;
   __syncthreads();  // the offsets are read back below by other threads
   if (threadIdx.x < kNumClasses) {
     const int c = threadIdx.x;
@@ -408,7 +430,7 @@ __global__ void k_b_num_bin_fill(BatchDev b) {
   __syncthreads();
   for (int x = threadIdx.x; x < kNumClasses * kBins; x += blockDim.x) {
     if (cnt[x]) {
-      const int k = nb_key(b, x / kBins, t, x % kBins);
+      const int k = nb_key(b, x / kBins, in.rank, x % kBins);
       base[x] = b.nb_off[k] + atomicAdd(&b.nb_cur[k], cnt[x]);
     }
     cnt[x] = 0;
@@ -441,7 +463,10 @@ __global__ void k_b_num_bin_fill(BatchDev b) {
 
 // ---------------------------------------------------------------- numeric
 
-// Workgroup items, then wavefront rows, each walked with a grid stride.
+// One launch per launch class: a workgroup per workgroup item (split
+// chunks, then whole rows), then a workgroup per kWavesPerBlock wavefront
+// rows. The grid is sized from the counts of the plan's symbolic pass (the
+// patterns are fixed); the grid stride only covers larger counts.
 template <int GL, int LAYOUT, typename IdxT>
 __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
   using S = SemiringT<float>;
@@ -449,42 +474,43 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric(BatchDev b) {
   double* strips = (double*)smem;
   int4* stage = (int4*)(smem + (size_t)kWavesPerBlock * b.lds_d * sizeof(double));
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & (kWave - 1);
-  const int n_wg = b.ctr->num_split_items + b.ctr->num_block_items;
-  const int n_heavy = n_wg + b.ctr->num_wave_rows;
-  for (int g = blockIdx.x; g < n_wg; g += gridDim.x) {
-    const BInst& in = b.insts[b.num_inst[g]];
-    if (in.gl != b.sel_gl || in.flat != b.sel_flat) continue;  // another class's launch (whole workgroup)
-    const Item it = b.num_items[g];
-    const Problem& pr = in.pr;
-    const int d = pr.d;
-    for (int j = threadIdx.x; j < kWavesPerBlock * d; j += kBlock) strips[j] = 0.0;
-    __syncthreads();
-    accumulate_range<GL, float, BSep<IdxT>, LAYOUT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strips + wave * d, stage + wave * kWave);
-    __syncthreads();
-    for (int j = threadIdx.x; j < d; j += kBlock)
-      strips[j] = S::add(S::add(S::add(strips[j], strips[d + j]), strips[2 * d + j]), strips[3 * d + j]);
-    __syncthreads();
-    if (it.aux != kNoSlot) {
-      double* dst = b.partial + (int64_t)it.aux * b.dmax;
-      for (int j = threadIdx.x; j < d; j += kBlock) dst[j] = strips[j];
-    } else {
-      emit_row<float>(pr, it.row, strips, wave, kWavesPerBlock);
-    }
-    __syncthreads();
-  }
-  const int n_groups = (b.ctr->num_wave_rows + kWavesPerBlock - 1) / kWavesPerBlock;
-  double* strip = strips + wave * b.lds_d;
-  for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
-    const int64_t x = (int64_t)n_wg + 4 * (int64_t)g + wave;
-    if (x < n_heavy && b.insts[b.num_inst[x]].gl == b.sel_gl && b.insts[b.num_inst[x]].flat == b.sel_flat) {
+  const int2 r0 = nb_range(b, 0), r1 = nb_range(b, 1), r2 = nb_range(b, 2);
+  const int n0 = r0.y - r0.x, n_wg = n0 + (r1.y - r1.x);
+  const int n_blocks = n_wg + (r2.y - r2.x + kWavesPerBlock - 1) / kWavesPerBlock;
+  for (int g = blockIdx.x; g < n_blocks; g += gridDim.x) {
+    if (g < n_wg) {
+      const int x = g < n0 ? r0.x + g : r1.x + (g - n0);
       const Item it = b.num_items[x];
       const Problem& pr = b.insts[b.num_inst[x]].pr;
-      for (int j = lane; j < pr.d; j += kWave) strip[j] = 0.0;
-      wave_sync();
-      accumulate_range<GL, float, BSep<IdxT>, LAYOUT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
-      wave_sync();
-      emit_row<float>(pr, it.row, strip, 0, 1);
-      wave_sync();
+      const int d = pr.d;
+      for (int j = threadIdx.x; j < kWavesPerBlock * d; j += kBlock) strips[j] = 0.0;
+      __syncthreads();
+      accumulate_range<GL, float, BSep<IdxT>, LAYOUT>(pr, it.p0, it.p1, wave, kWavesPerBlock, strips + wave * d,
+                                                       stage + wave * kWave);
+      __syncthreads();
+      for (int j = threadIdx.x; j < d; j += kBlock)
+        strips[j] = S::add(S::add(S::add(strips[j], strips[d + j]), strips[2 * d + j]), strips[3 * d + j]);
+      __syncthreads();
+      if (it.aux != kNoSlot) {
+        double* dst = b.partial + (int64_t)it.aux * b.dmax;
+        for (int j = threadIdx.x; j < d; j += kBlock) dst[j] = strips[j];
+      } else {
+        emit_row<float>(pr, it.row, strips, wave, kWavesPerBlock);
+      }
+      __syncthreads();  // the strips are reused by the next item
+    } else {
+      const int64_t x = r2.x + (int64_t)(g - n_wg) * kWavesPerBlock + wave;
+      if (x < r2.y) {
+        const Item it = b.num_items[x];
+        const Problem& pr = b.insts[b.num_inst[x]].pr;
+        double* strip = strips + wave * b.lds_d;
+        for (int j = lane; j < pr.d; j += kWave) strip[j] = 0.0;
+        wave_sync();
+        accumulate_range<GL, float, BSep<IdxT>, LAYOUT>(pr, it.p0, it.p1, 0, 1, strip, stage + wave * kWave);
+        wave_sync();
+        emit_row<float>(pr, it.row, strip, 0, 1);
+      }
+      __syncthreads();  // a later wavefront-row block of this workgroup reuses the strips
     }
   }
 }
@@ -496,13 +522,10 @@ __global__ __launch_bounds__(kBlock) void k_b_numeric_light(BatchDev b) {
   const int grp = threadIdx.x / GL, gl = threadIdx.x % GL;
   double* strip = (double*)smem + grp * b.lds_d;
   int4* stage = (int4*)(smem + (size_t)G * b.lds_d * sizeof(double)) + grp * GL;
-  const int first = b.ctr->num_split_items + b.ctr->num_block_items + b.ctr->num_wave_rows;
-  const int n_light = b.ctr->num_light_rows;
-  for (int64_t x = (int64_t)blockIdx.x * G + grp; x < n_light; x += (int64_t)gridDim.x * G) {
-    const BInst& in = b.insts[b.num_inst[first + x]];
-    if (in.lgl != b.sel_gl || in.flat != b.sel_flat) continue;  // another class's launch (whole group)
-    const Item it = b.num_items[first + x];
-    const Problem& pr = in.pr;
+  const int2 r3 = nb_range(b, 3);
+  for (int64_t x = r3.x + (int64_t)blockIdx.x * G + grp; x < r3.y; x += (int64_t)gridDim.x * G) {
+    const Item it = b.num_items[x];
+    const Problem& pr = b.insts[b.num_inst[x]].pr;
     for (int j = gl; j < pr.d; j += GL) strip[j] = 0.0;
     wave_sync();
     accumulate_light<GL, float, BSep<IdxT>, LAYOUT>(pr, it.p0, it.p1, strip, stage, gl);
@@ -534,8 +557,14 @@ __global__ __launch_bounds__(kBlock) void k_b_split_finalize(BatchDev b) {
 
 struct Batch {
   int32_t count = 0, dmax = 1, idb = 1;
-  // numeric launch classes present in the batch: (group width, flat, largest d)
-  std::vector<std::array<int, 3>> heavy_cls, light_cls;
+  // Numeric launch classes: instances with the same group widths, product
+  // layout and LDS strip size class run in one pair of launches (heavy and
+  // light), their ranks [r_lo, r_hi) adjacent in the work list.
+  struct LaunchClass {
+    int gl, lgl, flat, dcls, lds_d, r_lo, r_hi;
+    int64_t heavy_blocks, light_blocks;  // grids, from the plan's counts
+  };
+  std::vector<LaunchClass> classes;
   std::vector<BInst> host_insts;
   DevBuf insts, offs, work, sym_items, sym_inst, num_items, num_inst, split_rows, partial, block_sums, inst_flops,
       ctr, tmp_rowptrs, tmp_off, nbins;
@@ -559,10 +588,15 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   k_b_zero<<<1, 256, 0, st>>>(b.ctr);
   if (bt->total_bm > 0)
     k_b_bitmap<<<(unsigned)bt->total_bm, 256, (size_t)(kBmRows + 1 + kBmRows * bitmap_words(bt->dmax)) * 4, st>>>(b);
-  const unsigned gbin = grid_for(bt->total_rows, kBinRowsPerBlock);
-  if (bt->total_rows > 0) k_b_sym_bin_count<<<gbin, 256, 0, st>>>(b);
-  k_b_sym_bin_scan<<<1, 1, 0, st>>>(b.ctr);
-  if (bt->total_rows > 0) k_b_sym_bin_fill<<<gbin, 256, 0, st>>>(b);
+  {
+    // numeric and symbolic counts and cursors
+    int rc = launch_zero_bytes(b.nb_cnt, (size_t)2 * kNumClasses * bt->count * kBins * 4, st);
+    if (!rc) rc = launch_zero_bytes(b.sb_cnt, (size_t)2 * bt->count * kBins * 4, st);
+    if (rc) return rc;
+  }
+  if (bt->total_sb > 0) k_b_sym_bin_count<<<(unsigned)bt->total_sb, 256, 0, st>>>(b);
+  k_b_sym_bin_scan<<<1, kScanThreads, 0, st>>>(b);
+  if (bt->total_sb > 0) k_b_sym_bin_fill<<<(unsigned)bt->total_sb, 256, 0, st>>>(b);
   if (bt->sym_cap > 0) k_b_sym_split_zero<<<grid_for(bt->sym_cap, 256), 256, 0, st>>>(b);
   if (bt->total_lw > 0) k_b_sym_light<<<grid_for(bt->total_lw, kWavesPerBlock), kBlock, 0, st>>>(b);
   k_b_symbolic<<<2048, kBlock, 0, st>>>(b);
@@ -570,57 +604,54 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   k_b_scan<<<1, kScanThreads, 0, st>>>(b);
   if (bt->total_sb > 0) k_b_write_rowptr<<<(unsigned)bt->total_sb, kScanThreads, 0, st>>>(b);
   k_b_empty_rowptr<<<grid_for(bt->count, 256), 256, 0, st>>>(b);
-  {
-    int rc = launch_zero_bytes(b.nb_cnt, (size_t)2 * kNumClasses * bt->count * kBins * 4, st);  // counts, cursors
-    if (rc) return rc;
-  }
   if (bt->total_sb > 0) k_b_num_bin_count<<<(unsigned)bt->total_sb, 256, 0, st>>>(b);
   k_b_num_bin_scan<<<1, kScanThreads, 0, st>>>(b);
   if (bt->total_sb > 0) k_b_num_bin_fill<<<(unsigned)bt->total_sb, 256, 0, st>>>(b);
   TSS_CHECK_LAUNCH();
   if (!numeric) return TSSPGEMM_OK;
-  // one launch per class of instances (group width, product layout), each
-  // taking only its own items from the shared binned list
+  // one pair of launches per launch class, each taking the class's ranges
+  // of the binned list
 #define TSS_BK(K, GLV, L)                                                                              \
-  (bt->idb == 1 ? K<GLV, L, uint8_t> : K<GLV, L, uint16_t>)<<<2048, kBlock, lds, st>>>(bb);
+  (bt->idb == 1 ? K<GLV, L, uint8_t> : K<GLV, L, uint16_t>)<<<grid, kBlock, lds, st>>>(bb);
 #define TSS_BN(GLV)                                                                                    \
   case GLV:                                                                                            \
-    if (c[1] == kLayoutFlat)                                                                           \
+    if (c.flat == kLayoutFlat)                                                                         \
       TSS_BK(k_b_numeric, GLV, kLayoutFlat)                                                            \
-    else if (c[1] == kLayoutVec)                                                                       \
+    else if (c.flat == kLayoutVec)                                                                     \
       TSS_BK(k_b_numeric, GLV, kLayoutVec)                                                             \
     else                                                                                               \
       TSS_BK(k_b_numeric, GLV, kLayoutRows)                                                            \
     break;
 #define TSS_BL(GLV)                                                                                    \
   case GLV:                                                                                            \
-    if (c[1] == kLayoutFlat)                                                                           \
+    if (c.flat == kLayoutFlat)                                                                         \
       TSS_BK(k_b_numeric_light, GLV, kLayoutFlat)                                                      \
-    else if (c[1] == kLayoutVec)                                                                       \
+    else if (c.flat == kLayoutVec)                                                                     \
       TSS_BK(k_b_numeric_light, GLV, kLayoutVec)                                                       \
     else                                                                                               \
       TSS_BK(k_b_numeric_light, GLV, kLayoutRows)                                                      \
     break;
-  for (const auto& c : bt->heavy_cls) {
+  for (size_t ci = 0; ci < bt->classes.size(); ++ci) {
+    const Batch::LaunchClass& c = bt->classes[ci];
     BatchDev bb = b;
-    bb.sel_gl = c[0];
-    bb.sel_flat = c[1];
-    bb.lds_d = c[2];
-    const size_t lds = (size_t)kWavesPerBlock * c[2] * 8 + kWavesPerBlock * kWave * sizeof(int4);
-    switch (c[0]) {
-      TSS_BN(4) TSS_BN(8) TSS_BN(16) TSS_BN(32) TSS_BN(64)
-      default: set_error("batched: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+    bb.r_lo = c.r_lo;
+    bb.r_hi = c.r_hi;
+    bb.lds_d = c.lds_d;
+    if (c.heavy_blocks > 0) {
+      const unsigned grid = (unsigned)c.heavy_blocks;
+      const size_t lds = (size_t)kWavesPerBlock * c.lds_d * 8 + kWavesPerBlock * kWave * sizeof(int4);
+      switch (c.gl) {
+        TSS_BN(4) TSS_BN(8) TSS_BN(16) TSS_BN(32) TSS_BN(64)
+        default: set_error("batched: bad group width"); return TSSPGEMM_ERR_INVALID_ARG;
+      }
     }
-  }
-  for (const auto& c : bt->light_cls) {
-    BatchDev bb = b;
-    bb.sel_gl = c[0];
-    bb.sel_flat = c[1];
-    bb.lds_d = c[2];
-    const size_t lds = (size_t)(kBlock / c[0]) * c[2] * 8 + kBlock * sizeof(int4);
-    switch (c[0]) {
-      TSS_BL(4) TSS_BL(8) TSS_BL(16) TSS_BL(32) TSS_BL(64)
-      default: set_error("batched: bad light group width"); return TSSPGEMM_ERR_INVALID_ARG;
+    if (c.light_blocks > 0) {
+      const unsigned grid = (unsigned)c.light_blocks;
+      const size_t lds = (size_t)(kBlock / c.lgl) * c.lds_d * 8 + kBlock * sizeof(int4);
+      switch (c.lgl) {
+        TSS_BL(4) TSS_BL(8) TSS_BL(16) TSS_BL(32) TSS_BL(64)
+        default: set_error("batched: bad light group width"); return TSSPGEMM_ERR_INVALID_ARG;
+      }
     }
   }
 #undef TSS_BN
@@ -710,7 +741,7 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
       (rc = bt->split_rows.ensure(sizeof(SplitRow) * (bt->total_rows + 1))) ||
       (rc = bt->block_sums.ensure(16 * (bt->total_sb + 1))) || (rc = bt->inst_flops.ensure(8 * (count + 1))) ||
       (rc = bt->ctr.ensure(sizeof(Counters))) || (rc = bt->tmp_rowptrs.ensure(4 * (rp_total + 1))) ||
-      (rc = bt->nbins.ensure((size_t)3 * kNumClasses * (count + 1) * kBins * 4)) ||
+      (rc = bt->nbins.ensure((size_t)3 * (kNumClasses + 1) * (count + 1) * kBins * 4)) ||
       (rc = bt->tmp_off.ensure(8 * (count + 1))))
     return rc;
   TSS_HIP(hipHostMalloc((void**)&bt->host_ctr, sizeof(Counters), hipHostMallocDefault));
@@ -751,17 +782,38 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
               : (tn.products == TSSPGEMM_PRODUCTS_VEC4 && ((uintptr_t)B->vals % 16) == 0 ? kLayoutVec : kLayoutRows);
     in.gl = in.flat == kLayoutFlat ? 64 : tn.group_lanes;
     in.lgl = light_group_lanes(tn.group_lanes, B->ncols, TSSPGEMM_PLUS_TIMES_F32);
-    auto add_cls = [&](std::vector<std::array<int, 3>>& v, int g) {
-      for (auto& c : v)
-        if (c[0] == g && c[1] == in.flat) {
-          c[2] = std::max<int>(c[2], (int)B->ncols);
-          return;
-        }
-      v.push_back({g, in.flat, std::max<int>(1, (int)B->ncols)});
-    };
-    add_cls(bt->heavy_cls, in.gl);
-    add_cls(bt->light_cls, in.lgl);
     rp_off += n + 1;
+  }
+  // Launch classes: the strip size class is the smallest power of two >= 32
+  // holding d, so instances with narrow B get small strips (more resident
+  // wavefronts) rather than the batch's widest. Instances are ranked class
+  // by class, in their order within a class.
+  {
+    auto dcls = [](int d) {
+      int c = 32;
+      while (c < d) c <<= 1;
+      return c;
+    };
+    std::vector<int> order(count);
+    for (int t = 0; t < count; ++t) order[t] = t;
+    auto key = [&](int t) {
+      const BInst& in = bt->host_insts[t];
+      return std::array<int, 4>{in.flat, in.gl, in.lgl, dcls(in.pr.d)};
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
+    bt->classes.clear();
+    for (int r = 0; r < count; ++r) {
+      const int t = order[r];
+      BInst& in = bt->host_insts[t];
+      in.rank = r;
+      const auto k = key(t);
+      if (bt->classes.empty() || bt->classes.back().flat != k[0] || bt->classes.back().gl != k[1] ||
+          bt->classes.back().lgl != k[2] || bt->classes.back().dcls != k[3])
+        bt->classes.push_back({k[1], k[2], k[0], k[3], 1, r, r, 0, 0});
+      Batch::LaunchClass& c = bt->classes.back();
+      c.r_hi = r + 1;
+      c.lds_d = std::max(c.lds_d, (int)in.pr.d);
+    }
   }
   int64_t* offs = (int64_t*)bt->offs.p;
   TSS_HIP(hipMemcpyAsync(bt->insts.p, bt->host_insts.data(), sizeof(BInst) * count, hipMemcpyHostToDevice, st));
@@ -790,6 +842,9 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
   b.nb_cnt = (int32_t*)bt->nbins.p;
   b.nb_cur = b.nb_cnt + (size_t)kNumClasses * count * kBins;
   b.nb_off = b.nb_cur + (size_t)kNumClasses * count * kBins;
+  b.sb_cnt = b.nb_off + (size_t)kNumClasses * count * kBins + kBins;
+  b.sb_cur = b.sb_cnt + (size_t)count * kBins;
+  b.sb_kof = b.sb_cur + (size_t)count * kBins;
   b.ctr = (Counters*)bt->ctr.p;
   // a symbolic pass at plan time sizes the output pool and the split slots
   b.c_rowptrs = (int32_t*)bt->tmp_rowptrs.p;
@@ -799,8 +854,22 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
   b.partial = nullptr;
   if ((rc = enqueue_run(bt, st, false))) return rc;
   TSS_HIP(hipMemcpyAsync(bt->host_ctr, b.ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  const size_t nk = (size_t)kNumClasses * count * kBins;
+  std::vector<int32_t> koff(nk + 1);
+  TSS_HIP(hipMemcpyAsync(koff.data(), b.nb_off, (nk + 1) * 4, hipMemcpyDeviceToHost, st));
   TSS_HIP(hipStreamSynchronize(st));
   bt->pool = bt->host_ctr->nnz_total;
+  // grids of the numeric launches: the work list's counts per launch class
+  // (fixed, since the patterns are)
+  for (auto& c : bt->classes) {
+    auto range = [&](int cls) {
+      return (int64_t)koff[((size_t)cls * count + c.r_hi) * kBins] - koff[((size_t)cls * count + c.r_lo) * kBins];
+    };
+    c.heavy_blocks = range(0) + range(1) + (range(2) + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t per_block = kBlock / c.lgl;
+    c.light_blocks = std::min<int64_t>((range(3) + per_block - 1) / per_block, 2048);
+    c.heavy_blocks = std::min<int64_t>(c.heavy_blocks, INT32_MAX);
+  }
   if ((rc = bt->partial.ensure((size_t)(bt->host_ctr->num_split_items + 1) * dmax * 8))) return rc;
   b.partial = (double*)bt->partial.p;
   *pool_capacity = bt->pool;

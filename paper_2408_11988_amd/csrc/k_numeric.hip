@@ -109,9 +109,10 @@ __global__ __launch_bounds__(kBlock) void k_numeric_light(NumParams np) {
 static size_t acc_bytes(int sr) { return sr == TSSPGEMM_PLUS_TIMES_F32 ? 8 : 4; }
 
 int light_group_lanes(int group_lanes, int64_t d, int sr) {
-  // strips of all groups of a workgroup must fit 64 KB of LDS
+  // strips of all groups of a workgroup within 16 KB of LDS, so that eight
+  // workgroups (32 wavefronts) fit a CU: wide strips take wider groups
   int gl = group_lanes;
-  while (gl < 64 && (size_t)(kBlock / gl) * d * acc_bytes(sr) > 65536) gl <<= 1;
+  while (gl < 64 && (size_t)(kBlock / gl) * d * acc_bytes(sr) > 16384) gl <<= 1;
   return gl;
 }
 
