@@ -28,7 +28,7 @@ from .api import DeviceCsr, numeric, symbolic
 
 GROUP_LANES = (8, 16, 32, 64)
 LIGHT_MAX = (256, 512, 2048, 8192)
-WAVE_SPLIT = ((16384, 131072), (65536, 262144), (131072, 524288))
+WAVE_SPLIT = ((8192, 65536), (16384, 131072), (65536, 262144), (131072, 524288))
 PRODUCTS = ("rows", "flat")
 ACCUMULATORS = ("lds", "hash")
 DEFAULT = {"accumulator": "auto", "group_lanes": 0, "light_max_flops": 1024, "wave_max_flops": 65536,
@@ -63,6 +63,15 @@ def _time_numeric(A, B, tuning, reps=3):
         times.append(s.elapsed_time(e))
     times.sort()
     return times[len(times) // 2], plan
+
+
+def _strip_class(d: int) -> int:
+    """LDS strip size class of the batched numeric phase: the smallest power
+    of two >= max(d, 32)."""
+    c = 32
+    while c < d:
+        c <<= 1
+    return c
 
 
 class Autotuner:
@@ -122,10 +131,13 @@ class Autotuner:
         return dict(best)
 
     def tune_batch(self, pairs, reps: int = 3) -> list:
-        """Thresholds and group width for a batch. One set of kernels runs
-        every instance, so the candidates are timed on the whole batched run
-        (coordinate descent as in tune(), same candidate lists), and every
-        instance gets the winner. Cached under the sorted instance keys."""
+        """Thresholds, group width and product layout for a batch, timed on
+        the whole batched run. First one setting for every instance
+        (coordinate descent as in tune(), same candidate lists); then, class
+        by class of instances with the same LDS strip size (the batched
+        numeric phase runs each such class in launches of its own), the same
+        descent for that class's instances alone. Cached under the
+        instance keys in order."""
         from .batched import Batched
 
         if not pairs:
@@ -133,12 +145,12 @@ class Autotuner:
         # products per instance from the library (its symbolic pass at plan time)
         fls = Batched(pairs).flops()
         keys = [features(A, B, fl) for (A, B), fl in zip(pairs, fls)]
-        key = "batch:" + "|".join(sorted(keys))
+        key = "batch:" + "|".join(keys)  # in instance order: the settings are per instance
         if key in self.cache:
             best = dict(self.cache[key])
         else:
-            def run_ms(cfg):
-                bt = Batched(pairs, [cfg] * len(pairs))
+            def run_ms(cfgs):
+                bt = Batched(pairs, cfgs)
                 bt.run()
                 s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 times = []
@@ -151,29 +163,28 @@ class Autotuner:
                 times.sort()
                 return times[len(times) // 2]
 
-            best = {k: v for k, v in DEFAULT.items()}
-            best_t = run_ms(best)
-            for gl in GROUP_LANES:
-                cand = dict(best, group_lanes=gl)
-                t = run_ms(cand)
-                if t < best_t:
-                    best, best_t = cand, t
-            for pl in PRODUCTS:
-                cand = dict(best, products=pl)
-                t = run_ms(cand)
-                if t < best_t:
-                    best, best_t = cand, t
-            for lm in LIGHT_MAX:
-                cand = dict(best, light_max_flops=lm)
-                t = run_ms(cand)
-                if t < best_t:
-                    best, best_t = cand, t
-            for wm, sp in WAVE_SPLIT:
-                cand = dict(best, wave_max_flops=wm, split_flops=sp)
-                t = run_ms(cand)
-                if t < best_t:
-                    best, best_t = cand, t
-            best["ms"] = round(best_t, 4)
-            self.cache[key] = dict(best)
-        cfg = {k: v for k, v in best.items() if k != "ms"}
-        return [dict(cfg) for _ in pairs]
+            def descend(cfgs, idx, t0):
+                """Coordinate descent over the settings of instances idx."""
+                best_t = t0
+                for values in ([{"group_lanes": g} for g in GROUP_LANES],
+                               [{"products": p} for p in PRODUCTS],
+                               [{"light_max_flops": m} for m in LIGHT_MAX],
+                               [{"wave_max_flops": w, "split_flops": sp} for w, sp in WAVE_SPLIT]):
+                    for change in values:
+                        cand = [dict(c, **change) if i in idx else c for i, c in enumerate(cfgs)]
+                        t = run_ms(cand)
+                        if t < best_t:
+                            cfgs, best_t = cand, t
+                return cfgs, best_t
+
+            everyone = set(range(len(pairs)))
+            cfgs = [dict(DEFAULT) for _ in pairs]
+            cfgs, best_t = descend(cfgs, everyone, run_ms(cfgs))
+            for cls in sorted({_strip_class(B.ncols) for _, B in pairs}):
+                idx = {i for i, (_, B) in enumerate(pairs) if _strip_class(B.ncols) == cls}
+                if len(idx) < len(pairs):
+                    cfgs, best_t = descend(cfgs, idx, best_t)
+            best = {"per_instance": cfgs, "ms": round(best_t, 4)}
+            self.cache[key] = best
+        return [{k: v for k, v in c.items() if k != "ms"} for c in best["per_instance"]]
+

@@ -38,11 +38,12 @@ struct BatchDev {
   int32_t dmax;
   int32_t sym_split;
   int32_t idb;  // bytes of the narrowed B column ids (1: dmax <= 256, else 2)
-  int32_t r_lo, r_hi;  // numeric launches: the ranks of the instances this launch runs
+  int32_t r_lo, r_hi;  // per-class launches: the ranks of the instances this launch runs
   int32_t lds_d, pad2;  // numeric launches: strip stride in LDS (largest d of the class)
   const int64_t* row_off;  // prefix sums over instances: rows
   const int64_t* bm_off;   // bitmap blocks (kBmRows rows)
-  const int64_t* lw_off;   // light symbolic wavefronts (64 / wp rows each)
+  const int64_t* rrow_off;  // rows of the instances in rank order: prefix sums (count + 1)
+  const int64_t* rank_t;    // the instance of each rank
   const int64_t* sb_off;   // scan blocks (kScanRows rows)
   int64_t total_rows, total_sb;
   Item* sym_items;
@@ -78,6 +79,18 @@ __device__ __forceinline__ int find_inst(const int64_t* off, int count, int64_t 
   return lo;
 }
 
+// The rank r in [lo, hi) with off[r] <= x < off[r + 1].
+__device__ __forceinline__ int find_rank(const int64_t* off, int lo, int hi, int64_t x) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 __global__ void k_b_zero(Counters* ctr) {
   uint32_t* p = (uint32_t*)ctr;
   for (size_t t = threadIdx.x; t < sizeof(Counters) / 4; t += blockDim.x) p[t] = 0u;
@@ -94,10 +107,11 @@ __global__ __launch_bounds__(256) void k_b_bitmap(BatchDev b) {
 // ---------------------------------------------------------------- symbolic
 
 // The symbolic work list (rows with more A entries than a light slot takes,
-// and chunks of split rows) is ordered by instance, then heaviest bin first:
-// key (t, bin), so the wavefronts running at one time gather the B bitmap
-// rows of one or two instances. A workgroup takes kScanRows rows of one
-// instance (the scan blocks, sb_off).
+// and chunks of split rows) is ordered by instance rank, then heaviest bin
+// first: key (rank, bin), so the wavefronts running at one time gather the B
+// bitmap rows of one or two instances, and the instances of one bitmap width
+// (adjacent ranks) hold one contiguous range. A workgroup takes kScanRows
+// rows of one instance (the scan blocks, sb_off).
 __global__ void k_b_sym_bin_count(BatchDev b) {
   __shared__ int32_t hist[kBins];
   if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
@@ -112,7 +126,8 @@ __global__ void k_b_sym_bin_count(BatchDev b) {
     if (count) atomicAdd(&hist[bin], count);
   }
   __syncthreads();
-  if (threadIdx.x < kBins && hist[threadIdx.x]) atomicAdd(&b.sb_cnt[t * kBins + threadIdx.x], hist[threadIdx.x]);
+  if (threadIdx.x < kBins && hist[threadIdx.x])
+    atomicAdd(&b.sb_cnt[b.insts[t].rank * kBins + threadIdx.x], hist[threadIdx.x]);
 }
 
 // One workgroup: exclusive scan of the (instance, bin) counts into offsets,
@@ -129,7 +144,10 @@ __global__ __launch_bounds__(kScanThreads) void k_b_sym_bin_scan(BatchDev b) {
     if (x < nk) b.sb_kof[x] = (int32_t)(carry + ex);
     carry += tot;
   }
-  if (threadIdx.x == 0) b.ctr->sym_total = (int32_t)carry;
+  if (threadIdx.x == 0) {
+    b.sb_kof[nk] = (int32_t)carry;
+    b.ctr->sym_total = (int32_t)carry;
+  }
 }
 
 __global__ void k_b_sym_bin_fill(BatchDev b) {
@@ -148,7 +166,7 @@ __global__ void k_b_sym_bin_fill(BatchDev b) {
   __syncthreads();
   if (threadIdx.x < kBins) {
     if (cnt[threadIdx.x]) {
-      const int k = t * kBins + threadIdx.x;
+      const int k = b.insts[t].rank * kBins + threadIdx.x;
       base[threadIdx.x] = b.sb_kof[k] + atomicAdd(&b.sb_cur[k], cnt[threadIdx.x]);
     }
     cnt[threadIdx.x] = 0;
@@ -183,17 +201,89 @@ __global__ void k_b_sym_split_zero(BatchDev b) {
   pr.flops[it.row] = 0;
 }
 
-// light rows: a slot of wp lanes per row (wp varies by instance)
-__global__ __launch_bounds__(kBlock) void k_b_sym_light(BatchDev b) {
-  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (gw >= b.lw_off[b.count]) return;
-  const int t = find_inst(b.lw_off, b.count, gw);
-  const Problem& pr = b.insts[t].pr;
-  const int wp = pr.wp, ns = kWave / wp;
+// The symbolic kernels run once per bitmap width: the instances of ranks
+// [r_lo, r_hi) share it. Light rows are numbered in rank order (rrow_off).
+
+// Bitmaps of at most 8 words: a lane owns a light row and ORs whole B
+// bitmap rows (16-byte loads), as in the single-product pass.
+template <int WP>
+__global__ __launch_bounds__(kBlock) void k_b_sym_light_lanes(BatchDev b) {
+  const int64_t x = b.rrow_off[b.r_lo] + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (x >= b.rrow_off[b.r_hi]) return;
+  const int r = find_rank(b.rrow_off, b.r_lo, b.r_hi, x);
+  const Problem& pr = b.insts[b.rank_t[r]].pr;
+  const int64_t row = x - b.rrow_off[r];
+  const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
+  if (p1 - p0 > kSlotRowMax) return;  // a heavy row: done from the item list
+  const uint32_t* __restrict__ bb = pr.bbits;
+  BmRow<WP> acc;
+#pragma unroll
+  for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
+  int fl = 0;
+  int p = p0;
+  for (; p + 1 < p1; p += 2) {
+    const int k0 = pr.aci[p], k1 = pr.aci[p + 1];
+    bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
+    bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
+  }
+  if (p < p1) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
+  bm_store<WP>(pr.cbits + row * WP, acc);
+  pr.flops[row] = fl;
+}
+
+// Heavy rows and split chunks of ranks [r_lo, r_hi): a wavefront per item,
+// a lane per A entry (whole B bitmap rows), OR-ed across the wavefront.
+template <int WP>
+__global__ __launch_bounds__(kBlock) void k_b_symbolic_lanes(BatchDev b) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int x0 = b.sb_kof[b.r_lo * kBins], x1 = b.sb_kof[b.r_hi * kBins];
+  for (int x = x0 + blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); x < x1; x += gridDim.x * kWavesPerBlock) {
+    const Item it = b.sym_items[x];
+    const Problem& pr = b.insts[b.sym_inst[x]].pr;
+    const uint32_t* __restrict__ bb = pr.bbits;
+    const bool split = (it.aux & kSplitFlag) != 0;
+    BmRow<WP> acc;
+#pragma unroll
+    for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
+    int fl = 0;
+    int p = it.p0 + lane;
+    for (; p + kWave < it.p1; p += 2 * kWave) {
+      const int k0 = pr.aci[p], k1 = pr.aci[p + kWave];
+      bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
+      bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
+    }
+    if (p < it.p1) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
+#pragma unroll
+    for (int w = 0; w < WP; ++w)
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) acc.w[w] |= shfl_xor_u32(acc.w[w], o);
+    const long long fsum = wave_sum_i64((long long)fl);
+    if (lane == 0) {
+      if (split) {
+#pragma unroll
+        for (int w = 0; w < WP; ++w)
+          if (acc.w[w]) atomicOr(&pr.cbits[(int64_t)it.row * WP + w], acc.w[w]);
+        atomicAdd((unsigned long long*)&pr.flops[it.row], (unsigned long long)fsum);
+      } else {
+        bm_store<WP>(pr.cbits + (int64_t)it.row * WP, acc);
+        pr.flops[it.row] = fsum;
+      }
+    }
+  }
+}
+
+// Wider bitmaps (16 or 32 words): a slot of wp lanes per light row, a lane
+// per word.
+__global__ __launch_bounds__(kBlock) void k_b_sym_light(BatchDev b, int wp) {
+  const int ns = kWave / wp;
   const int lane = threadIdx.x & (kWave - 1);
   const int slot = lane / wp, w = lane & (wp - 1);
-  const int64_t row = (gw - b.lw_off[t]) * ns + slot;
-  if (row >= pr.n) return;
+  const int64_t gw = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int64_t x = b.rrow_off[b.r_lo] + gw * ns + slot;
+  if (x >= b.rrow_off[b.r_hi]) return;
+  const int r = find_rank(b.rrow_off, b.r_lo, b.r_hi, x);
+  const Problem& pr = b.insts[b.rank_t[r]].pr;
+  const int64_t row = x - b.rrow_off[r];
   const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
   if (p1 - p0 > kSlotRowMax) return;
   uint32_t acc = 0u;
@@ -207,24 +297,25 @@ __global__ __launch_bounds__(kBlock) void k_b_sym_light(BatchDev b) {
     fl += __popc(x0) + __popc(x1) + __popc(x2) + __popc(x3);
   }
   for (; p < p1; ++p) {
-    const uint32_t x = pr.bbits[(int64_t)pr.aci[p] * wp + w];
-    acc |= x;
-    fl += __popc(x);
+    const uint32_t v = pr.bbits[(int64_t)pr.aci[p] * wp + w];
+    acc |= v;
+    fl += __popc(v);
   }
   for (int o = 1; o < wp; o <<= 1) fl += __shfl_xor(fl, o, kWave);
   pr.cbits[row * wp + w] = acc;
   if (w == 0) pr.flops[row] = fl;
 }
 
-// heavy rows and split chunks from the item list, one wavefront per item
-__global__ __launch_bounds__(kBlock) void k_b_symbolic(BatchDev b) {
+// Wider bitmaps: heavy rows and split chunks, a wavefront per item, a slot
+// of wp lanes per A entry.
+__global__ __launch_bounds__(kBlock) void k_b_symbolic(BatchDev b, int wp) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int total = b.ctr->sym_total;
-  for (int x = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); x < total; x += gridDim.x * kWavesPerBlock) {
+  const int ns = kWave / wp;
+  const int slot = lane / wp, w = lane & (wp - 1);
+  const int x0 = b.sb_kof[b.r_lo * kBins], x1 = b.sb_kof[b.r_hi * kBins];
+  for (int x = x0 + blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); x < x1; x += gridDim.x * kWavesPerBlock) {
     const Item it = b.sym_items[x];
     const Problem& pr = b.insts[b.sym_inst[x]].pr;
-    const int wp = pr.wp, ns = kWave / wp;
-    const int slot = lane / wp, w = lane & (wp - 1);
     const bool split = (it.aux & kSplitFlag) != 0;
     uint32_t acc = 0u;
     int fl = 0;
@@ -565,10 +656,16 @@ struct Batch {
     int64_t heavy_blocks, light_blocks;  // grids, from the plan's counts
   };
   std::vector<LaunchClass> classes;
+  // Symbolic launch groups: instances of one bitmap width, ranks [r_lo, r_hi)
+  struct SymGroup {
+    int wp, r_lo, r_hi;
+    int64_t rows;
+  };
+  std::vector<SymGroup> sym_groups;
   std::vector<BInst> host_insts;
   DevBuf insts, offs, work, sym_items, sym_inst, num_items, num_inst, split_rows, partial, block_sums, inst_flops,
       ctr, tmp_rowptrs, tmp_off, nbins;
-  int64_t total_rows = 0, total_bm = 0, total_lw = 0, total_sb = 0, rowptr_total = 0;
+  int64_t total_rows = 0, total_bm = 0, total_sb = 0, rowptr_total = 0;
   int64_t sym_cap = 0, num_cap = 0, pool = 0;
   BatchDev dev{};
   Counters* host_ctr = nullptr;
@@ -598,8 +695,26 @@ static int enqueue_run(Batch* bt, hipStream_t st, bool numeric) {
   k_b_sym_bin_scan<<<1, kScanThreads, 0, st>>>(b);
   if (bt->total_sb > 0) k_b_sym_bin_fill<<<(unsigned)bt->total_sb, 256, 0, st>>>(b);
   if (bt->sym_cap > 0) k_b_sym_split_zero<<<grid_for(bt->sym_cap, 256), 256, 0, st>>>(b);
-  if (bt->total_lw > 0) k_b_sym_light<<<grid_for(bt->total_lw, kWavesPerBlock), kBlock, 0, st>>>(b);
-  k_b_symbolic<<<2048, kBlock, 0, st>>>(b);
+  // one pair of symbolic launches per bitmap width
+  for (const auto& g : bt->sym_groups) {
+    BatchDev bb = b;
+    bb.r_lo = g.r_lo;
+    bb.r_hi = g.r_hi;
+    if (g.rows == 0) continue;
+    const unsigned gl = grid_for(g.rows, kBlock);
+    switch (g.wp) {
+#define TSS_BSYM(W)                                                  \
+  case W:                                                            \
+    k_b_sym_light_lanes<W><<<gl, kBlock, 0, st>>>(bb);               \
+    k_b_symbolic_lanes<W><<<2048, kBlock, 0, st>>>(bb);              \
+    break;
+      TSS_BSYM(1) TSS_BSYM(2) TSS_BSYM(4) TSS_BSYM(8)
+#undef TSS_BSYM
+      default:
+        k_b_sym_light<<<grid_for(g.rows, (int64_t)(kWave / g.wp) * kWavesPerBlock), kBlock, 0, st>>>(bb, g.wp);
+        k_b_symbolic<<<2048, kBlock, 0, st>>>(bb, g.wp);
+    }
+  }
   if (bt->total_sb > 0) k_b_count_rows<<<(unsigned)bt->total_sb, kScanThreads, 0, st>>>(b);
   k_b_scan<<<1, kScanThreads, 0, st>>>(b);
   if (bt->total_sb > 0) k_b_write_rowptr<<<(unsigned)bt->total_sb, kScanThreads, 0, st>>>(b);
@@ -673,7 +788,7 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     return TSSPGEMM_ERR_INVALID_ARG;
   }
   bt->count = count;
-  std::vector<int64_t> row_off(count + 1, 0), bm_off(count + 1, 0), lw_off(count + 1, 0), sb_off(count + 1, 0);
+  std::vector<int64_t> row_off(count + 1, 0), bm_off(count + 1, 0), sb_off(count + 1, 0);
   int64_t ws_bytes = 0, sym_cap = 0, num_cap = 0, rp_total = 0;
   std::vector<int64_t> ws_at(count);
   int dmax = 1;
@@ -696,7 +811,6 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     dmax = std::max<int>(dmax, (int)B->ncols);
     row_off[t + 1] = row_off[t] + n;
     bm_off[t + 1] = bm_off[t] + (n + kBmRows - 1) / kBmRows;
-    lw_off[t + 1] = lw_off[t] + (n + (kWave / wp) - 1) / (kWave / wp);
     sb_off[t + 1] = sb_off[t] + (n + kScanRows - 1) / kScanRows;
     ws_at[t] = ws_bytes;
     ws_bytes += ((2 * n * wp * 4 + n * 8 + n * 4) + 255) / 256 * 256;
@@ -729,12 +843,11 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
   }
   bt->total_rows = row_off[count];
   bt->total_bm = bm_off[count];
-  bt->total_lw = lw_off[count];
   bt->total_sb = sb_off[count];
   bt->rowptr_total = rp_total;
   bt->sym_cap = sym_cap;
   bt->num_cap = num_cap;
-  if ((rc = bt->insts.ensure(sizeof(BInst) * (count + 1))) || (rc = bt->offs.ensure(sizeof(int64_t) * 4 * (count + 1))) ||
+  if ((rc = bt->insts.ensure(sizeof(BInst) * (count + 1))) || (rc = bt->offs.ensure(sizeof(int64_t) * 5 * (count + 1))) ||
       (rc = bt->work.ensure((size_t)ws_bytes + 256)) || (rc = bt->sym_items.ensure(sizeof(Item) * (sym_cap + 1))) ||
       (rc = bt->sym_inst.ensure(4 * (sym_cap + 1))) || (rc = bt->num_items.ensure(sizeof(Item) * (num_cap + 1))) ||
       (rc = bt->num_inst.ensure(4 * (num_cap + 1))) ||
@@ -747,6 +860,7 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
   TSS_HIP(hipHostMalloc((void**)&bt->host_ctr, sizeof(Counters), hipHostMallocDefault));
   bt->host_insts.resize(count);
   int64_t rp_off = 0;
+  std::vector<int64_t> rank_t(count + 1, 0), rrow_off(count + 1, 0);
   for (int t = 0; t < count; ++t) {
     const tsspgemm_csr *A = &As[t], *B = &Bs[t];
     const int64_t n = A->nrows;
@@ -787,7 +901,8 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
   // Launch classes: the strip size class is the smallest power of two >= 32
   // holding d, so instances with narrow B get small strips (more resident
   // wavefronts) rather than the batch's widest. Instances are ranked class
-  // by class, in their order within a class.
+  // by class (size class first, so that one bitmap width is one range of
+  // ranks), in their order within a class.
   {
     auto dcls = [](int d) {
       int c = 32;
@@ -798,28 +913,36 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     for (int t = 0; t < count; ++t) order[t] = t;
     auto key = [&](int t) {
       const BInst& in = bt->host_insts[t];
-      return std::array<int, 4>{in.flat, in.gl, in.lgl, dcls(in.pr.d)};
+      return std::array<int, 4>{dcls(in.pr.d), in.flat, in.gl, in.lgl};
     };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
     bt->classes.clear();
+    bt->sym_groups.clear();
     for (int r = 0; r < count; ++r) {
       const int t = order[r];
       BInst& in = bt->host_insts[t];
       in.rank = r;
       const auto k = key(t);
-      if (bt->classes.empty() || bt->classes.back().flat != k[0] || bt->classes.back().gl != k[1] ||
-          bt->classes.back().lgl != k[2] || bt->classes.back().dcls != k[3])
-        bt->classes.push_back({k[1], k[2], k[0], k[3], 1, r, r, 0, 0});
+      if (bt->classes.empty() || bt->classes.back().dcls != k[0] || bt->classes.back().flat != k[1] ||
+          bt->classes.back().gl != k[2] || bt->classes.back().lgl != k[3])
+        bt->classes.push_back({k[2], k[3], k[1], k[0], 1, r, r, 0, 0});
       Batch::LaunchClass& c = bt->classes.back();
       c.r_hi = r + 1;
       c.lds_d = std::max(c.lds_d, (int)in.pr.d);
+      if (bt->sym_groups.empty() || bt->sym_groups.back().wp != in.pr.wp)
+        bt->sym_groups.push_back({in.pr.wp, r, r, 0});
+      bt->sym_groups.back().r_hi = r + 1;
+      bt->sym_groups.back().rows += in.pr.n;
+      rank_t[r] = t;
+      rrow_off[r + 1] = rrow_off[r] + in.pr.n;
     }
   }
   int64_t* offs = (int64_t*)bt->offs.p;
   TSS_HIP(hipMemcpyAsync(bt->insts.p, bt->host_insts.data(), sizeof(BInst) * count, hipMemcpyHostToDevice, st));
   TSS_HIP(hipMemcpyAsync(offs, row_off.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
   TSS_HIP(hipMemcpyAsync(offs + (count + 1), bm_off.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
-  TSS_HIP(hipMemcpyAsync(offs + 2 * (count + 1), lw_off.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  TSS_HIP(hipMemcpyAsync(offs + 2 * (count + 1), rrow_off.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
+  TSS_HIP(hipMemcpyAsync(offs + 4 * (count + 1), rank_t.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
   TSS_HIP(hipMemcpyAsync(offs + 3 * (count + 1), sb_off.data(), 8 * (count + 1), hipMemcpyHostToDevice, st));
   BatchDev& b = bt->dev;
   b.insts = (BInst*)bt->insts.p;
@@ -828,7 +951,8 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
   b.idb = bt->idb;
   b.row_off = offs;
   b.bm_off = offs + (count + 1);
-  b.lw_off = offs + 2 * (count + 1);
+  b.rrow_off = offs + 2 * (count + 1);
+  b.rank_t = offs + 4 * (count + 1);
   b.sb_off = offs + 3 * (count + 1);
   b.total_rows = bt->total_rows;
   b.total_sb = bt->total_sb;

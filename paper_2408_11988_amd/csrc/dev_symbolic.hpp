@@ -45,6 +45,51 @@ __device__ __forceinline__ void bitmap_block(int64_t n, const int32_t* __restric
   for (int t = threadIdx.x; t < nr * wp; t += blockDim.x) out[t] = sb[t];
 }
 
+// A bitmap row of WP words held in registers (WP <= 8), OR-ed from B's
+// bitmap rows with 16-byte loads, counting the products (set bits) on the way.
+template <int WP>
+struct BmRow {
+  uint32_t w[WP];
+};
+
+template <int WP>
+__device__ __forceinline__ void bm_load_or(const uint32_t* __restrict__ src, BmRow<WP>& acc, int& fl) {
+  if constexpr (WP >= 4) {
+#pragma unroll
+    for (int q = 0; q < WP / 4; ++q) {
+      const uint4 x = reinterpret_cast<const uint4*>(src)[q];
+      acc.w[4 * q] |= x.x;
+      acc.w[4 * q + 1] |= x.y;
+      acc.w[4 * q + 2] |= x.z;
+      acc.w[4 * q + 3] |= x.w;
+      fl += __popc(x.x) + __popc(x.y) + __popc(x.z) + __popc(x.w);
+    }
+  } else if constexpr (WP == 2) {
+    const uint2 x = *reinterpret_cast<const uint2*>(src);
+    acc.w[0] |= x.x;
+    acc.w[1] |= x.y;
+    fl += __popc(x.x) + __popc(x.y);
+  } else {
+    const uint32_t x = *src;
+    acc.w[0] |= x;
+    fl += __popc(x);
+  }
+}
+
+template <int WP>
+__device__ __forceinline__ void bm_store(uint32_t* __restrict__ dst, const BmRow<WP>& acc) {
+  if constexpr (WP >= 4) {
+#pragma unroll
+    for (int q = 0; q < WP / 4; ++q)
+      reinterpret_cast<uint4*>(dst)[q] = make_uint4(acc.w[4 * q], acc.w[4 * q + 1], acc.w[4 * q + 2], acc.w[4 * q + 3]);
+  } else if constexpr (WP == 2) {
+    *reinterpret_cast<uint2*>(dst) = make_uint2(acc.w[0], acc.w[1]);
+  } else {
+    *dst = acc.w[0];
+  }
+}
+
+
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 4;
 constexpr int kScanRows = kScanThreads * kScanPer;

@@ -164,3 +164,31 @@ def test_autotuner_does_not_change_results(tmp_path):
     _same(ref, got)
     again = Autotuner(str(path)).tune(A, B, reps=2)  # cached
     assert {k: v for k, v in again.items()} == best
+
+
+def test_batch_autotuner_settings_keep_results(tmp_path):
+    """tune_batch's settings (one for the batch, then per class of instances
+    with the same LDS strip size, bitmap widths 1 to 16 words): each
+    instance's structure equals the oracle's and its values are within the
+    tolerance; a second tuner reads the same settings from the cache."""
+    from paper_2408_11988_amd.autotune import Autotuner
+    from paper_2408_11988_amd.batched import Batched
+
+    rng = np.random.default_rng(11)
+    shapes = [(1500, 32, 0.01, 0.1), (1200, 96, 0.01, 0.2), (800, 400, 0.02, 0.05), (2000, 256, 0.004, 0.3),
+              (600, 20, 0.03, 0.2)]
+    host = [(random_csr(rng, n, n, pa, empty_rows=0.1, dense_rows=1), random_csr(rng, n, d, pb))
+            for n, d, pa, pb in shapes]
+    pairs = [(to_dev(a), to_dev(b)) for a, b in host]
+    path = tmp_path / "tune.json"
+    at = Autotuner(str(path))
+    note("tune_batch on 5 instances")
+    tun = at.tune_batch(pairs, reps=1)
+    at.save()
+    assert len(tun) == len(pairs) and json.load(open(path))
+    bt = Batched(pairs, tun)
+    bt.run()
+    torch.cuda.synchronize()
+    for (a, b), C in zip(host, bt.outputs()):
+        compare_f32(a, b, C)
+    assert Autotuner(str(path)).tune_batch(pairs, reps=1) == tun
