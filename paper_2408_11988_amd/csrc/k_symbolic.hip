@@ -412,21 +412,23 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_lanes(SymParams sp) {
       bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
     }
     if (p < it.p1) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
-#pragma unroll
-    for (int w = 0; w < WP; ++w)
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) acc.w[w] |= shfl_xor_u32(acc.w[w], o);
-    const long long fsum = wave_sum_i64((long long)fl);
-    if (lane == 0) {
+    const uint32_t word = bm_wave_or<WP>(acc, lane);  // word bm_word_of<WP>(lane), OR-ed over the wavefront
+    // products: at most 32 * WP per entry, so an int32 sum holds below 2^31 / (32 WP) entries
+    const long long fsum = (int64_t)(it.p1 - it.p0) * 32 * WP < (1ll << 31) ? (long long)wave_sum_i32(fl)
+                                                                              : wave_sum_i64((long long)fl);
+    if ((lane & (kWave / WP - 1)) == 0) {  // the first lane holding each word
+      uint32_t* dst = &pr.cbits[row * WP + bm_word_of<WP>(lane)];
       if (split) {
-#pragma unroll
-        for (int w = 0; w < WP; ++w)
-          if (acc.w[w]) atomicOr(&pr.cbits[row * WP + w], acc.w[w]);
-        atomicAdd((unsigned long long*)&pr.flops[row], (unsigned long long)fsum);
+        if (word) atomicOr(dst, word);
       } else {
-        bm_store<WP>(pr.cbits + row * WP, acc);
-        pr.flops[row] = fsum;
+        *dst = word;
       }
+    }
+    if (lane == 0) {
+      if (split)
+        atomicAdd((unsigned long long*)&pr.flops[row], (unsigned long long)fsum);
+      else
+        pr.flops[row] = fsum;
     }
   }
 }
