@@ -112,11 +112,15 @@ def cpu_baseline(a, b, flops_rows, target_s=12.0):
             "sample": f"{sample}; {fl} multiplications in {t:.2f} s (ordered-map Gustavson, FP64)"}
 
 
-def _roofline(bytes_alg: int, ms: float, kernel: str) -> dict:
-    """HBM roofline of one launch (or call) from its algorithmic bytes."""
+def _roofline(bytes_alg: int, ms: float, kernel: str, traffic_key: str | None = None) -> dict:
+    """HBM roofline of one launch (or call) from its algorithmic bytes; `traffic`
+    is the measured HBM bytes per launch from the committed counter summary
+    (null when it is missing or the kernel sources changed since)."""
     gbs = bytes_alg / (ms / 1e3) / 1e9
+    traffic = measured_traffic(traffic_key) if traffic_key else None
     return {"bound": "hbm", "kernel": kernel, "bytes_alg_per_launch": int(bytes_alg), "ms": round(ms, 4),
-            "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}
+            "achieved": round(gbs, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+            "traffic": traffic}
 
 
 def _events(n):
@@ -190,8 +194,10 @@ def bench_fwd_bwd(steps: int, warmup: int) -> dict:
             "ms_fwd_bwd": round(ms_step, 4), "gflops_fwd": round(2 * flops / ms_f / 1e6, 2),
             "gflops_bwd": round(2 * 2 * flops / ms_b / 1e6, 2),
             "gflops_fwd_bwd": round(2 * 3 * flops / ms_step / 1e6, 2),
-            "roofline_fwd": _roofline(fwd_bytes, ms_f, "numeric phase of the forward (one tsspgemm_numeric call)"),
-            "roofline_bwd": _roofline(bwd_bytes, ms_lib_bwd, "tsspgemm_backward (dL/dA and dL/dB, one call)"),
+            "roofline_fwd": _roofline(fwd_bytes, ms_f, "numeric phase of the forward (one tsspgemm_numeric call)",
+                                      "rmat20_d256_forward"),
+            "roofline_bwd": _roofline(bwd_bytes, ms_lib_bwd, "tsspgemm_backward (dL/dA and dL/dB, one call)",
+                                      "rmat20_d256_backward"),
             "note": "bwd = dL/dA (SDDMM on pat(A)) + dL/dB (A^T G sampled on pat(B)), each as many products as fwd;"
                     " ms_bwd is the autograd backward with the loss's elementwise product and sum; "
                     "ms_bwd_library is the library call alone"}
@@ -278,7 +284,8 @@ def bench_batched(steps: int, warmup: int) -> dict:
     batch_bytes = rp_bytes + sum(8 * (a.nnz + b.nnz) for a, b in host) + 8 * bt.pool
     return {"workload": "64 instances: n log-uniform [2^14, 2^18], d in {32,64,128,256}, ER/R-MAT (deg 4-32), "
                         "B density log-uniform [1%, 50%], plus-times FP32",
-            "roofline": _roofline(batch_bytes, ms_graph, "one graph replay (symbolic + numeric of all 64 instances)"),
+            "roofline": _roofline(batch_bytes, ms_graph, "one graph replay (symbolic + numeric of all 64 instances)",
+                                  "batched_64_replay"),
             "roofline_numeric_calls": _roofline(batch_bytes, ms_num_graph,
                                                 "the 64 numeric phases captured as plain calls"),
             "sum_n": sum(a.nrows for a, _ in host), "sum_nnz_a": sum(a.nnz for a, _ in host), "flops": flops,
@@ -614,7 +621,8 @@ def bench_bfs(cpu: bool) -> dict:
     bfs_bytes = sum((4 * (n + 1) + 4 * a.nnz) + (4 * (n + 1) + 4 * fr[t]) + n * d // 8 + (4 * (n + 1) + 4 * fr[t + 1])
                     for t in range(len(fn))) + 4 * n * d
     out = {"workload": "R-MAT scale 22 (edge factor 16, symmetrised, pattern), 512 sources, Boolean masked",
-           "roofline": _roofline(bfs_bytes, ms, "the whole multi-source BFS (every masked product and the levels)"),
+           "roofline": _roofline(bfs_bytes, ms, "the whole multi-source BFS (every masked product and the levels)",
+                                  "msbfs_rmat22_d512"),
            "n": a.nrows, "nnz_a": a.nnz, "iterations": len(fn), "frontier_nnz": fn, "ms_total": round(ms, 3),
            "reached_pairs": pairs, "and_products": products,
            "gflops": round(2 * products / ms / 1e6, 2), "traversed_edges_per_s": round(products / ms * 1e3, 1),
