@@ -15,8 +15,12 @@
  *  - The caller allocates every input and output buffer and keeps it alive
  *    until the work queued on `stream` has finished. The library owns only
  *    the workspace inside a plan / batch handle (freed by the matching
- *    *_destroy call) and a per-device scratch cache that it reuses between
- *    calls. Inputs are never modified.
+ *    *_destroy call) and a per-device scratch cache that the one-shot entry
+ *    points (masked_bool, spmm, embed_epoch) reuse between calls. Calls on
+ *    different streams that share it are ordered on the device (a call
+ *    waits for the previous call when that one ran on another stream); work
+ *    captured into a HIP graph is not, its replays are the caller's to order.
+ *    Inputs are never modified.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Work is stream-ordered; only calls documented as "synchronizes" block
  *    the host (they return a count the caller needs to size an output).
@@ -252,8 +256,9 @@ int tsspgemm_backward(tsspgemm_plan plan, const tsspgemm_csr* AT, const int32_t*
  *   leading dimension ldb >= d (zeros included). C: n x d, leading dimension
  *   ldc >= d, every entry written (rows of A without entries give 0).
  *   1 <= d <= 1024 (d = 0 or n = 0: nothing to do).
- * Uses the device's workspace cache: calls that overlap on one device race.
- * Asynchronous. Errors: INVALID_ARG, UNSUPPORTED (d > 1024), NOMEM, HIP. */
+ * Uses the device's workspace cache (calls on different streams are
+ * ordered on the device, see the conventions above). Asynchronous.
+ * Errors: INVALID_ARG, UNSUPPORTED (d > 1024), NOMEM, HIP. */
 int tsspgemm_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ldb, float* C, int64_t ldc,
                   void* stream);
 
@@ -290,8 +295,9 @@ int tsspgemm_spmm_noalloc(const tsspgemm_csr* A, const float* B, int64_t d, int6
  * |u| (ties: lower column), sorted by column.
  * 1 <= k <= d <= 1024, batch_rows >= 1, 0 <= row_begin <= row_end <= n.
  * Uses the device's workspace cache (a second n x k copy of Z, per-row
- * counters, partial forces of long rows): calls that overlap on one device
- * race. Asynchronous; no allocation after the first call of a given size
+ * counters, partial forces of long rows; calls on different streams are
+ * ordered on the device, see the conventions above). Asynchronous; no
+ * allocation after the first call of a given size
  * (n, nnz(A), d, and whether batch_rows <= 4096: such minibatches cut long
  * rows into shorter chunks, with a larger partial-force buffer).
  * Errors: INVALID_ARG, UNSUPPORTED (d > 1024), NOMEM, HIP. */

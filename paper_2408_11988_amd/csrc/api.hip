@@ -506,7 +506,9 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
                                (const double*)p->partial.p, (const int32_t*)p->partial.p, st);
 }
 
-// Plans reused by the one-shot entry points (masked_bool), one per device.
+// Workspaces of the one-shot entry points (masked_bool, spmm, embed_epoch),
+// one per device, reused by every call on that device (also across a graph
+// capture: the capture reuses what an eager call sized).
 static std::mutex g_cache_mu;
 static Plan* g_cache[64];
 
@@ -515,6 +517,30 @@ Plan* cached_plan(int dev) {
   if (dev < 0 || dev >= 64) return nullptr;
   if (!g_cache[dev]) g_cache[dev] = new (std::nothrow) Plan();
   return g_cache[dev];
+}
+
+// Calls on different streams that share a cached workspace are ordered on
+// the device: a call waits for the previous call's event when that call ran
+// on another stream, and records its own at the end. Work being captured
+// into a graph neither waits nor records (the caller orders graph replays).
+static bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+int order_after_last(Plan* p, hipStream_t st) {
+  if (!p->ord_valid || p->ord_last == st || capturing(st)) return TSSPGEMM_OK;
+  TSS_HIP(hipStreamWaitEvent(st, p->ord_ev, 0));
+  return TSSPGEMM_OK;
+}
+
+int mark_done(Plan* p, hipStream_t st) {
+  if (capturing(st)) return TSSPGEMM_OK;
+  if (!p->ord_ev) TSS_HIP(hipEventCreateWithFlags(&p->ord_ev, hipEventDisableTiming));
+  TSS_HIP(hipEventRecord(p->ord_ev, st));
+  p->ord_last = st;
+  p->ord_valid = true;
+  return TSSPGEMM_OK;
 }
 
 }  // namespace tss
@@ -603,6 +629,8 @@ int tsspgemm_masked_bool(const tsspgemm_csr* A, const tsspgemm_csr* F, const tss
       return TSSPGEMM_ERR_NOMEM;
     }
     std::lock_guard<std::mutex> lk(p->mu);
+    StreamOrder so(p, (hipStream_t)stream);
+    if (so.rc) return so.rc;
     p->ready = false;
     int rc = run_symbolic(p, A, F, TSSPGEMM_OR_AND, visited, nullptr, c_rowptr, c_nnz, (hipStream_t)stream);
     if (rc) return rc;

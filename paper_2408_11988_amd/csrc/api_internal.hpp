@@ -75,6 +75,9 @@ struct Plan {
   DevBuf em_cnt, em_split, em_slot_off, em_split_off, em_slot_row, em_split_list, em_partial, em_scan;
   DevBuf em_done;          // embedding update: finished chunks of each long row
   size_t hstrips_zeroed = 0;
+  hipEvent_t ord_ev = nullptr;     // cached plans: end of the last call (see order_after_last)
+  hipStream_t ord_last = nullptr;  //   and its stream
+  bool ord_valid = false;
   Counters* host_ctr = nullptr;  // pinned
   // results of the last symbolic call
   int64_t nnz = 0, flops_total = 0, n_split_items = 0, n_block_items = 0, n_wave_rows = 0, n_light_rows = 0;
@@ -83,6 +86,7 @@ struct Plan {
   ~Plan() {
     if (host_ctr) (void)hipHostFree(host_ctr);
     host_ctr = nullptr;
+    if (ord_ev) (void)hipEventDestroy(ord_ev);
   }
 };
 
@@ -95,6 +99,22 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
 int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* c_colidx, void* c_vals,
                 hipStream_t st);
 void plan_free(Plan* p);
-Plan* cached_plan(int dev);
+Plan* cached_plan(int dev);  // workspace of the one-shot entry points, per device
+// Cross-stream ordering of the calls that share a cached plan: call
+// order_after_last before queuing a call's work and mark_done after.
+int order_after_last(Plan* p, hipStream_t st);
+int mark_done(Plan* p, hipStream_t st);
+// Scope of one call on a cached plan (held under the plan's mutex): waits
+// for the previous call on another stream, records this call's end when the
+// scope closes (also on an error return, for whatever was queued).
+struct StreamOrder {
+  Plan* p;
+  hipStream_t st;
+  int rc;
+  StreamOrder(Plan* p_, hipStream_t st_) : p(p_), st(st_), rc(order_after_last(p_, st_)) {}
+  ~StreamOrder() { (void)mark_done(p, st); }
+  StreamOrder(const StreamOrder&) = delete;
+  StreamOrder& operator=(const StreamOrder&) = delete;
+};
 
 }  // namespace tss

@@ -90,31 +90,34 @@ __device__ __forceinline__ void bm_store(uint32_t* __restrict__ dst, const BmRow
 }
 
 
-// OR of each of the WP words of `acc` over the 64 lanes, reduce-scattered:
-// at the step of lane bit o (32, 16, ...) the lanes with that bit set keep
-// the upper half of their words and send the lower half, the others the
-// reverse, until one word is left; the remaining steps OR that word over
-// the rest of the lanes. WP - 1 + 6 - log2(WP) shuffles in all (7 for WP = 4,
-// where a word-by-word reduction takes 24). Lane l ends with word
-// bm_word_of<WP>(l), fully reduced.
-template <int WP>
-__device__ __forceinline__ int bm_word_of(int lane) {
+// OR of each of the WP words of `acc` over a group of G aligned lanes
+// (WP <= G), reduce-scattered: at the step of lane bit o (G/2, G/4, ...) the
+// lanes with that bit set keep the upper half of their words and send the
+// lower half, the others the reverse, until one word is left; the remaining
+// steps OR that word over the rest of the group. WP - 1 + log2(G / WP)
+// shuffles in all (7 for WP = 4 over a wavefront, where a word-by-word
+// reduction takes 24). Lane gl of the group ends with word
+// bm_word_of<WP, G>(gl), fully reduced.
+template <int WP, int G = kWave>
+__device__ __forceinline__ int bm_word_of(int gl) {
+  static_assert(WP <= G, "a group needs at least one lane per word");
   int w = 0;
 #pragma unroll
-  for (int h = WP / 2, o = 32; h >= 1; h >>= 1, o >>= 1)
-    if (lane & o) w += h;
+  for (int h = WP / 2, o = G / 2; h >= 1; h >>= 1, o >>= 1)
+    if (gl & o) w += h;
   return w;
 }
 
-template <int WP>
-__device__ __forceinline__ uint32_t bm_wave_or(const BmRow<WP>& acc, int lane) {
+template <int WP, int G = kWave>
+__device__ __forceinline__ uint32_t bm_wave_or(const BmRow<WP>& acc, int gl) {
+  static_assert(WP <= G, "a group needs at least one lane per word");
   uint32_t v[WP];
 #pragma unroll
   for (int i = 0; i < WP; ++i) v[i] = acc.w[i];
-  int o = 32;
+  int o = G / 2;
 #pragma unroll
   for (int h = WP / 2; h >= 1; h >>= 1, o >>= 1) {
-    const bool hi = (lane & o) != 0;
+    const bool hi = (gl & o) != 0;
 #pragma unroll
     for (int i = 0; i < h; ++i) {
       const uint32_t send = hi ? v[i] : v[h + i];

@@ -430,6 +430,8 @@ static int run_embed_epoch(const tsspgemm_csr* A, int64_t d, int64_t k, int32_t*
     return TSSPGEMM_ERR_NOMEM;
   }
   std::lock_guard<std::mutex> lk(p->mu);
+  StreamOrder so(p, st);
+  if (so.rc) return so.rc;
   const size_t zbytes = (size_t)n * (size_t)k * 4;
   const int chunk = batch <= kEmbedFuseRows ? kEmbedChunkSmall : kEmbedChunkLarge;
   // a row of len > chunk entries has ceil(len / chunk) < 2 len / chunk chunks

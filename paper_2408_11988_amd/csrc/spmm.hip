@@ -316,6 +316,8 @@ static int run_spmm(const tsspgemm_csr* A, const float* B, int64_t d, int64_t ld
     return TSSPGEMM_ERR_NOMEM;
   }
   std::lock_guard<std::mutex> lk(p->mu);
+  StreamOrder so(p, st);
+  if (so.rc) return so.rc;
   const int64_t chunk_cap = spmm_chunk_cap(nnz), long_cap = spmm_long_cap(nnz);
   if ((rc = p->sp_chunks.ensure((size_t)chunk_cap * sizeof(int2))) ||
       (rc = p->sp_rows.ensure((size_t)long_cap * sizeof(int4))) ||

@@ -107,3 +107,28 @@ def test_spmm_rmat16_equals_spgemm_on_dense_b():
     got = C.cpu().numpy()
     rel = np.abs(got.astype(np.float64) - ref) / np.maximum(np.abs(ref), 1e-30)
     assert np.all((ref == 0) == (got == 0)) and rel.max() <= 2 * RTOL
+
+
+def test_spmm_on_two_streams():
+    """Calls on two streams share the device's workspace; the library orders
+    them on the device, so every result still matches the oracle."""
+    import paper_2408_11988_amd as tss
+
+    rng = np.random.default_rng(77)
+    probs = []
+    for n, d in ((3000, 96), (2500, 130)):
+        a = random_csr(rng, n, n, 0.004, kind="normal", empty_rows=0.1, dense_rows=3)
+        b = rng.standard_normal((n, d)).astype(np.float32)
+        probs.append((a, b, to_dev(a), torch.from_numpy(b).cuda()))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    note("spmm on two streams, 4 rounds")
+    outs = [[], []]
+    for _ in range(4):
+        for t, (s, (_, _, A, B)) in enumerate(zip(streams, probs)):
+            with torch.cuda.stream(s):
+                outs[t].append(tss.spmm(A, B))
+    torch.cuda.synchronize()
+    for t, (a, b, _, _) in enumerate(probs):
+        for C in outs[t]:
+            _check(a, b, C)
