@@ -187,6 +187,62 @@ __global__ __launch_bounds__(256) void k_bfs_levels(int64_t n, int32_t d, int wp
   }
 }
 
+// The same levels when d is a multiple of 32, a lane per bitmap word: the
+// lane loads its word of every frontier (a wavefront reads 256 contiguous
+// bytes per frontier) and folds the frontiers from last to first into bit
+// planes of the level (five planes: up to 32 frontiers) and an any-frontier
+// mask, so the earliest frontier holding a bit wins, as above. The 64 words
+// of a wavefront are 8 KB of levels, contiguous (word q holds columns
+// 32 q .. 32 q + 31 of the flattened n x d array): in store round c, lane l
+// takes the planes of word 8 c + l / 8 by shuffle and writes its 4 levels
+// at 16 l bytes into the round's kilobyte, so every store is coalesced.
+__global__ __launch_bounds__(256) void k_bfs_levels_words(int64_t n, int32_t d, int wp, int32_t nfront,
+                                                          const uint32_t* const* __restrict__ fronts,
+                                                          int32_t* __restrict__ levels) {
+  const int wpd = d >> 5;  // words of a row that hold columns
+  const int64_t words = n * wpd;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t q0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * kWave; q0 < words;
+       q0 += nwaves * kWave) {
+    const int64_t q = q0 + lane;
+    uint32_t pl0 = 0, pl1 = 0, pl2 = 0, pl3 = 0, pl4 = 0, any = 0;
+    if (q < words) {
+      const int64_t row = q / wpd;
+      const int64_t word = row * wp + (q - row * wpd);
+#pragma unroll 4
+      for (int t = nfront - 1; t >= 0; --t) {
+        const uint32_t x = fronts[t][word];
+        any |= x;
+        pl0 = (pl0 & ~x) | ((t & 1) ? x : 0u);
+        pl1 = (pl1 & ~x) | ((t & 2) ? x : 0u);
+        pl2 = (pl2 & ~x) | ((t & 4) ? x : 0u);
+        pl3 = (pl3 & ~x) | ((t & 8) ? x : 0u);
+        pl4 = (pl4 & ~x) | ((t & 16) ? x : 0u);
+      }
+    }
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const int sh = 4 * (lane & 7);  // this lane's 4 bits of the source word
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int src = 8 * c + (lane >> 3);
+      const uint32_t a = shfl_u32(any, src), b0 = shfl_u32(pl0, src), b1 = shfl_u32(pl1, src);
+      const uint32_t b2 = shfl_u32(pl2, src), b3 = shfl_u32(pl3, src), b4 = shfl_u32(pl4, src);
+      if (q0 + src >= words) continue;
+      v4i v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int j = sh + e;
+        const int l = (int)(((b0 >> j) & 1u) | (((b1 >> j) & 1u) << 1) | (((b2 >> j) & 1u) << 2) |
+                            (((b3 >> j) & 1u) << 3) | (((b4 >> j) & 1u) << 4));
+        v[e] = ((a >> j) & 1u) ? l : -1;
+      }
+      // streamed out, never re-read here
+      __builtin_nontemporal_store(v, reinterpret_cast<v4i*>(levels + (q0 + src) * 32 + sh));
+    }
+  }
+}
+
 struct BfsWork {
   DevBuf S, fnz, active, part_or, part_cnt, count, fronts_dev;
   std::vector<DevBuf> fronts;
@@ -316,11 +372,20 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
   for (int t = 0; t < nfront; ++t) fp[t] = (const uint32_t*)w.fronts[t].p;
   if ((rc = w.fronts_dev.ensure(sizeof(void*) * (nfront + 1)))) return rc;
   TSS_HIP(hipMemcpyAsync(w.fronts_dev.p, fp.data(), sizeof(void*) * nfront, hipMemcpyHostToDevice, st));
-  const int64_t waves = n * ((d + 255) / 256);
-  if (waves > 0) {
-    k_bfs_levels<<<(int)std::min<int64_t>((waves + 3) / 4, 8192), 256, 0, st>>>(n, d, wp, nfront, (const uint32_t* const*)w.fronts_dev.p,
-                                                      levels);
-    TSS_CHECK_LAUNCH();
+  if (nfront <= 32 && (d & 31) == 0 && ((uintptr_t)levels & 15) == 0) {
+    const int64_t words = n * (d >> 5);
+    if (words > 0) {
+      k_bfs_levels_words<<<(int)std::min<int64_t>((words + 255) / 256, 2048), 256, 0, st>>>(
+          n, d, wp, nfront, (const uint32_t* const*)w.fronts_dev.p, levels);
+      TSS_CHECK_LAUNCH();
+    }
+  } else {
+    const int64_t waves = n * ((d + 255) / 256);
+    if (waves > 0) {
+      k_bfs_levels<<<(int)std::min<int64_t>((waves + 3) / 4, 8192), 256, 0, st>>>(
+          n, d, wp, nfront, (const uint32_t* const*)w.fronts_dev.p, levels);
+      TSS_CHECK_LAUNCH();
+    }
   }
   TSS_HIP(hipStreamSynchronize(st));
   *iterations = it;

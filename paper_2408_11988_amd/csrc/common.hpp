@@ -24,6 +24,10 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src_lane) {
+  return (uint32_t)__shfl((int)v, src_lane, kWave);
+}
+
 __device__ __forceinline__ uint32_t shfl_xor_u32(uint32_t v, int mask) {
   return (uint32_t)__shfl_xor((int)v, mask, kWave);
 }
