@@ -95,7 +95,8 @@ static int plan_alloc_host(Plan* p) {
 void plan_free(Plan* p) {
   for (DevBuf* b : {&p->bbits, &p->cbits, &p->flops, &p->cnt, &p->scan, &p->sym_items, &p->num_items,
                     &p->split_rows, &p->partial, &p->ctr, &p->maskbits, &p->gb_items, &p->gb_split,
-                    &p->gb_partial, &p->gb_ctr, &p->gb_gbuf, &p->gb_off, &p->gb_slot_a, &p->gb_words, &p->gb_scan})
+                    &p->gb_partial, &p->gb_ctr, &p->gb_gbuf, &p->gb_off, &p->gb_slot_a, &p->gb_words, &p->gb_scan,
+                    &p->ebnd})
     b->release();
   if (p->host_ctr) (void)hipHostFree(p->host_ctr);
   p->host_ctr = nullptr;
@@ -181,6 +182,7 @@ static int run_symbolic_hash(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr*
   p->gb_pos_ready = false;
   p->gb_items_ready = false;
   p->hash = true;
+  p->ebnd_valid = false;
   p->masked = M && M->kind != TSSPGEMM_MASK_NONE;
   if ((rc = plan_alloc_host(p))) return rc;
   if ((rc = p->ctr.ensure(sizeof(Counters))) || (rc = p->flops.ensure((size_t)n * 8)) ||
@@ -390,6 +392,8 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   pr.cbits = (uint32_t*)p->cbits.p;
   pr.flops = (int64_t*)p->flops.p;
   pr.crp = c_rowptr;
+  p->ebnd_valid = false;  // new patterns: the B row bounds are recorded again (run_numeric)
+  p->numeric_calls = 0;
 
   if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
   // B's bitmap; for value semirings the same pass narrows B's column ids
@@ -487,6 +491,17 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
                                &((Counters*)p->ctr.p)->hash_error, (int32_t*)p->hnext.p, st);
   }
   if (!vals) return launch_emit_pattern(pr, st);
+  // A plan whose numeric phase repeats (a training loop): the second call
+  // records each A entry's B row bounds as its staging gathers them (8 B per
+  // A entry), and later calls and the backward read them instead.
+  bool recording = false;
+  if (p->ebnd_valid) {
+    pr.ebnd = (const int2*)p->ebnd.p;
+  } else if (++p->numeric_calls >= 2) {
+    if ((rc = p->ebnd.ensure((size_t)p->a_nnz * sizeof(int2)))) return rc;
+    pr.ebnd_w = (int2*)p->ebnd.p;
+    recording = true;
+  }
   NumParams np{};
   np.pr = pr;
   np.items = (const Item*)p->num_items.p;
@@ -502,6 +517,7 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   int products = p->tune.products;
   if (products == TSSPGEMM_PRODUCTS_VEC4 && ((uintptr_t)B->vals % 16) != 0) products = TSSPGEMM_PRODUCTS_PER_B_ROW;
   if ((rc = launch_numeric(p->sr, p->tune.group_lanes, products, np, grid, st))) return rc;
+  if (recording) p->ebnd_valid = true;  // the staging of this call writes every staged entry's bounds
   return launch_split_finalize(p->sr, pr, (const SplitRow*)p->split_rows.p, (int32_t)p->n_split_rows,
                                (const double*)p->partial.p, (const int32_t*)p->partial.p, st);
 }

@@ -46,6 +46,9 @@ struct Plan {
   DevBuf bbits, cbits, flops, cnt, scan, sym_items, num_items, split_rows, partial, ctr, maskbits;
   DevBuf gb_items, gb_split, gb_partial, gb_ctr;  // dL/dB work lists
   DevBuf bcol;             // B's column ids narrowed to col_id_bytes(d) bytes (numeric phase)
+  DevBuf ebnd;             // per A entry, its B row's bounds (int2), recorded by the second numeric call
+  bool ebnd_valid = false; //   of the plan (run_numeric); read by later calls and the backward
+  int numeric_calls = 0;   // numeric calls since the plan's symbolic phase
   // dL/dB from sampled G: one block per A entry (i,k) holding A(i,k) and
   // G(i, pat(B_k)) in a 64-byte-multiple slot, blocks in A^T order; the start
   // of each B row's blocks and of each A entry's block, and the per-row sizes

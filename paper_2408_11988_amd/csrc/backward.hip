@@ -156,9 +156,9 @@ template <bool GATHER>
 __device__ __forceinline__ void grad_a_stage(const GradAParams& gp, int base, int nb, int t, int4* stage) {
   int4 e = make_int4(0, 0, -1, 0);
   if (t < nb) {
-    const int k = gp.pr.aci[base + t];
-    e.x = gp.pr.brp[k];
-    e.y = gp.pr.brp[k + 1];
+    const int2 bnd = entry_bounds(gp.pr, base + t);
+    e.x = bnd.x;
+    e.y = bnd.y;
     if constexpr (GATHER) {
       e.z = gp.slot_a[base + t];
       e.w = __builtin_bit_cast(int32_t, ((const float*)gp.pr.aval)[base + t]);
@@ -468,6 +468,7 @@ static Problem plan_problem(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* 
   pr.cbits = (uint32_t*)p->cbits.p;
   pr.flops = (int64_t*)p->flops.p;
   pr.crp = p->crp;
+  pr.ebnd = p->ebnd_valid ? (const int2*)p->ebnd.p : nullptr;
   return pr;
 }
 

@@ -70,6 +70,9 @@ struct Problem {
   const uint32_t* bbits;  // B pattern, n x wp
   uint32_t* cbits;        // C pattern, n x wp
   int64_t* flops;         // per row
+  const int2* ebnd;       // per A entry (brp[k], brp[k+1]) of its B row, or null: read by the
+                          //   numeric staging instead of gathering B's row pointers
+  int2* ebnd_w;           // or null: where the staging records the bounds it gathers
   const int32_t* crp;     // C row pointers
   int32_t* cci;
   void* cval;

@@ -64,6 +64,17 @@ struct BSep {
 };
 
 
+// B row bounds (brp[k], brp[k+1]) of A entry p = (i, k): from the plan's
+// per-entry record when there is one (no dependent gather), else through
+// A's column, recorded when the plan asks for it.
+__device__ __forceinline__ int2 entry_bounds(const Problem& pr, int p) {
+  if (pr.ebnd) return pr.ebnd[p];
+  const int k = pr.aci[p];
+  const int2 b = make_int2(pr.brp[k], pr.brp[k + 1]);
+  if (pr.ebnd_w) pr.ebnd_w[p] = b;
+  return b;
+}
+
 // Accumulate entries [p_begin, p_end) of one A row into `strip`, taking
 // 64-entry batches number wstart, wstart + wstride, ... (one wavefront): the
 // batch is staged (entry, B row bounds, value) through LDS, and the 64/GL
@@ -77,19 +88,17 @@ __device__ __forceinline__ void accumulate_range_rows(const Problem& pr, int p_b
   constexpr int U = kHeavyUnroll;
   const int lane = threadIdx.x & (kWave - 1);
   const int grp = lane / GL, gl = lane % GL;
-  const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
-  const int32_t* __restrict__ brp = pr.brp;
   const BR br(pr);
 
   for (int base = p_begin + kWave * wstart; base < p_end; base += kWave * wstride) {
     const int nb = min(kWave, p_end - base);
     int4 e = make_int4(0, 0, 0, 0);
     if (lane < nb) {
-      const int k = aci[base + lane];
+      const int2 bnd = entry_bounds(pr, base + lane);
       T a = aval[base + lane];
-      e.x = brp[k];
-      e.y = brp[k + 1];
+      e.x = bnd.x;
+      e.y = bnd.y;
       e.z = __builtin_bit_cast(int32_t, a);
     }
     wave_sync();
@@ -137,9 +146,7 @@ __device__ __forceinline__ void accumulate_range_flat(const Problem& pr, int p_b
   using S = SemiringT<T>;
   constexpr int U = kHeavyUnroll;
   const int lane = threadIdx.x & (kWave - 1);
-  const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
-  const int32_t* __restrict__ brp = pr.brp;
   const BR br(pr);
 
   for (int base = p_begin + kWave * wstart; base < p_end; base += kWave * wstride) {
@@ -147,10 +154,10 @@ __device__ __forceinline__ void accumulate_range_flat(const Problem& pr, int p_b
     int q0 = 0, len = 0;
     T a = T(0);
     if (lane < nb) {
-      const int k = aci[base + lane];
+      const int2 bnd = entry_bounds(pr, base + lane);
       a = aval[base + lane];
-      q0 = brp[k];
-      len = brp[k + 1] - q0;
+      q0 = bnd.x;
+      len = bnd.y - q0;
     }
     int incl = len;
 #pragma unroll
@@ -271,20 +278,18 @@ __device__ __forceinline__ void accumulate_range_vec(const Problem& pr, int p_be
   constexpr int U = kHeavyUnroll;
   const int lane = threadIdx.x & (kWave - 1);
   const int grp = lane / GL, gl = lane % GL;
-  const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
-  const int32_t* __restrict__ brp = pr.brp;
   const BR br(pr);
-  const int bend = brp[pr.n];
+  const int bend = pr.brp[pr.n];
 
   for (int base = p_begin + kWave * wstart; base < p_end; base += kWave * wstride) {
     const int nb = min(kWave, p_end - base);
     int4 e = make_int4(0, 0, 0, 0);
     if (lane < nb) {
-      const int k = aci[base + lane];
+      const int2 bnd = entry_bounds(pr, base + lane);
       T a = aval[base + lane];
-      e.x = brp[k];
-      e.y = brp[k + 1];
+      e.x = bnd.x;
+      e.y = bnd.y;
       e.z = __builtin_bit_cast(int32_t, a);
     }
     wave_sync();
@@ -400,17 +405,15 @@ __device__ __forceinline__ void accumulate_light_rows(const Problem& pr, int p0,
                                                  typename SemiringT<T>::acc* strip, int4* stage, int gl) {
   using S = SemiringT<T>;
   constexpr int U = kLightUnroll;
-  const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
-  const int32_t* __restrict__ brp = pr.brp;
   const BR br(pr);
   for (int base = p0; base < p1; base += GL) {
     const int nb = min(GL, p1 - base);
     int4 e = make_int4(0, 0, 0, 0);
     if (gl < nb) {
-      const int k = aci[base + gl];
-      e.x = brp[k];
-      e.y = brp[k + 1];
+      const int2 bnd = entry_bounds(pr, base + gl);
+      e.x = bnd.x;
+      e.y = bnd.y;
       e.z = __builtin_bit_cast(int32_t, aval[base + gl]);
     }
     wave_sync();
@@ -460,19 +463,17 @@ __device__ __forceinline__ void accumulate_light_flat(const Problem& pr, int p0,
   using S = SemiringT<T>;
   constexpr int U = kLightUnroll;
   const int lane = threadIdx.x & (kWave - 1);
-  const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
-  const int32_t* __restrict__ brp = pr.brp;
   const BR br(pr);
   for (int base = p0; base < p1; base += GL) {
     const int nb = min(GL, p1 - base);
     int q0 = 0, len = 0;
     T a = T(0);
     if (gl < nb) {
-      const int k = aci[base + gl];
+      const int2 bnd = entry_bounds(pr, base + gl);
       a = aval[base + gl];
-      q0 = brp[k];
-      len = brp[k + 1] - q0;
+      q0 = bnd.x;
+      len = bnd.y - q0;
     }
     int incl = len;  // inclusive scan of the lengths over the group
 #pragma unroll
@@ -525,18 +526,16 @@ template <int GL, typename T, typename BR>
 __device__ __forceinline__ void accumulate_light_vec(const Problem& pr, int p0, int p1,
                                                      typename SemiringT<T>::acc* strip, int4* stage, int gl) {
   constexpr int U = kLightUnroll;
-  const int32_t* __restrict__ aci = pr.aci;
   const T* __restrict__ aval = (const T*)pr.aval;
-  const int32_t* __restrict__ brp = pr.brp;
   const BR br(pr);
-  const int bend = brp[pr.n];
+  const int bend = pr.brp[pr.n];
   for (int base = p0; base < p1; base += GL) {
     const int nb = min(GL, p1 - base);
     int4 e = make_int4(0, 0, 0, 0);
     if (gl < nb) {
-      const int k = aci[base + gl];
-      e.x = brp[k];
-      e.y = brp[k + 1];
+      const int2 bnd = entry_bounds(pr, base + gl);
+      e.x = bnd.x;
+      e.y = bnd.y;
       e.z = __builtin_bit_cast(int32_t, aval[base + gl]);
     }
     wave_sync();

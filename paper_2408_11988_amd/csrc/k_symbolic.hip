@@ -433,6 +433,111 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_lanes(SymParams sp) {
   }
 }
 
+// Masked symbolic pass (a complement mask, optionally the active columns,
+// the frontier summary fnz and early exit), one lane per light row or per A
+// entry with whole B bitmap rows in registers (at most 16 words): the same
+// results as k_symbolic_light / k_symbolic, with 64 rows or entries per
+// wavefront in flight instead of 64 / WP. A light row's lane keeps its open
+// columns (not masked, active) and stops once its accumulator covers them.
+__device__ __forceinline__ bool fnz_set(const uint32_t* fnz, int k) {
+  return fnz == nullptr || ((fnz[k >> 5] >> (k & 31)) & 1u);
+}
+
+template <int WP>
+__global__ __launch_bounds__(kBlock) void k_symbolic_light_lanes_m(SymParams sp) {
+  const Problem& pr = sp.pr;
+  const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (row >= pr.n) return;
+  const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
+  if (p1 - p0 > kSlotRowMax) return;  // a heavy row: done from the item list
+  const uint32_t* __restrict__ bb = pr.bbits;
+  const uint32_t* __restrict__ fnz = sp.fnz;
+  BmRow<WP> need, acc;
+  uint32_t open = 0u;
+#pragma unroll
+  for (int w = 0; w < WP; ++w) {
+    const uint32_t m = sp.mask ? sp.mask[row * WP + w] : 0u;
+    need.w[w] = ~m & (sp.active ? sp.active[w] : 0xffffffffu);
+    open |= need.w[w];
+    acc.w[w] = 0u;
+  }
+  int fl = 0;
+  if (p1 > p0 && (sp.mask == nullptr || open != 0u)) {
+    for (int p = p0; p < p1; p += 2) {
+      const int k0 = pr.aci[p];
+      const int k1 = p + 1 < p1 ? pr.aci[p + 1] : -1;
+      const bool v0 = fnz_set(fnz, k0), v1 = k1 >= 0 && fnz_set(fnz, k1);
+      if (v0) bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
+      if (v1) bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
+      if (sp.early_exit) {
+        uint32_t left = 0u;
+#pragma unroll
+        for (int w = 0; w < WP; ++w) left |= need.w[w] & ~acc.w[w];
+        if (left == 0u) break;
+      }
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < WP; ++w) {
+    const uint32_t m = sp.mask ? sp.mask[row * WP + w] : 0u;
+    acc.w[w] &= ~m;
+  }
+  bm_store<WP>(pr.cbits + row * WP, acc);
+  pr.flops[row] = fl;
+}
+
+template <int WP>
+__global__ __launch_bounds__(kBlock) void k_symbolic_lanes_m(SymParams sp) {
+  const Problem& pr = sp.pr;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int total = sp.ctr->sym_total;
+  const int wave_global = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  const int wave_stride = gridDim.x * kWavesPerBlock;
+  const uint32_t* __restrict__ bb = pr.bbits;
+  const uint32_t* __restrict__ fnz = sp.fnz;
+  const int myw = bm_word_of<WP>(lane);  // the word this lane holds after the reduction
+  for (int t = wave_global; t < total; t += wave_stride) {
+    const Item it = sp.items[t];
+    const bool split = (it.aux & kSplitFlag) != 0;
+    const int64_t row = it.row;
+    const uint32_t mword = sp.mask ? sp.mask[row * WP + myw] : 0u;
+    const uint32_t need = ~mword & (sp.active ? sp.active[myw] : 0xffffffffu);
+    // every column that could be produced is masked out: nothing to do
+    const bool skip = sp.mask && !split && __ballot(need != 0u) == 0ull;
+    BmRow<WP> acc;
+#pragma unroll
+    for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
+    int fl = 0;
+    if (!skip) {
+      for (int base = it.p0; base < it.p1; base += kWave) {  // wavefront-uniform steps
+        const int p = base + lane;
+        const int k = p < it.p1 ? pr.aci[p] : -1;
+        if (k >= 0 && fnz_set(fnz, k)) bm_load_or<WP>(bb + (int64_t)k * WP, acc, fl);
+        if (sp.early_exit) {
+          const uint32_t word = bm_wave_or<WP>(acc, lane);
+          if (__ballot((need & ~word) != 0u) == 0ull) break;
+        }
+      }
+    }
+    const uint32_t word = bm_wave_or<WP>(acc, lane);
+    const long long fsum = wave_sum_i64((long long)fl);
+    if ((lane & (kWave / WP - 1)) == 0) {  // the first lane holding each word
+      uint32_t* dst = &pr.cbits[row * WP + myw];
+      if (split) {
+        if (word) atomicOr(dst, word);
+      } else {
+        *dst = word & ~mword;
+      }
+    }
+    if (lane == 0) {
+      if (split)
+        atomicAdd((unsigned long long*)&pr.flops[row], (unsigned long long)fsum);
+      else
+        pr.flops[row] = fsum;
+    }
+  }
+}
+
 int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st) {
   const int64_t n = sp.pr.n;
   if (n == 0) return TSSPGEMM_OK;
@@ -444,12 +549,20 @@ int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st) {
   // without a mask, and for bitmap rows of at most 8 words (registers): one
   // lane per A entry (k_symbolic_*_lanes)
   const bool lanes = sp.mask == nullptr && sp.fnz == nullptr && sp.pr.wp <= 8;
+  // with a mask, or bitmap rows of 16 words: the same lane-per-row /
+  // lane-per-entry form with the mask. Not with the frontier filter and early
+  // exit of the BFS: there the slot kernels stop a row after fewer gathers
+  // (R-MAT 22 x 512 BFS: 27.9 ms with these kernels, 23.5 ms without)
+  const bool lanes_m = !lanes && sp.pr.wp <= 16 && sp.fnz == nullptr;
   const unsigned g_lanes = grid_for(n, kBlock);
 #define TSS_SYM_CASE(W)                                                           \
   case W:                                                                         \
     if (lanes) {                                                                  \
       k_symbolic_light_lanes<W><<<g_lanes, kBlock, 0, st>>>(sp);                  \
       if (max_items > 0) k_symbolic_lanes<W><<<g_heavy, kBlock, 0, st>>>(sp);     \
+    } else if (lanes_m) {                                                         \
+      k_symbolic_light_lanes_m<(W <= 16 ? W : 16)><<<g_lanes, kBlock, 0, st>>>(sp); \
+      if (max_items > 0) k_symbolic_lanes_m<(W <= 16 ? W : 16)><<<g_heavy, kBlock, 0, st>>>(sp); \
     } else {                                                                      \
       k_symbolic_light<W><<<g_light, kBlock, 0, st>>>(sp);                        \
       if (max_items > 0) k_symbolic<W><<<g_heavy, kBlock, 0, st>>>(sp);           \

@@ -13,7 +13,7 @@ import torch
 import oracle
 import synth
 from tests._util import random_csr, rows_of
-from tests.gpu_util import note, require_gpu, to_dev
+from tests.gpu_util import compare_f32, note, require_gpu, to_dev
 
 pytestmark = pytest.mark.gpu
 RTOL = 1e-5
@@ -241,3 +241,41 @@ def test_gradients_reject_masked_plan():
     with pytest.raises(tss.TSSpGEMMError) as e:
         tss.grad_a(plan, A, B, G)
     assert "mask" in str(e.value)
+
+
+@pytest.mark.parametrize("d", [64, 256])
+def test_numeric_repeats_record_b_row_bounds(d):
+    """A plan whose numeric phase repeats records each A entry's B row bounds
+    at its second numeric call and reads them from the third on (and in the
+    backward). Every call, with new values of A and B on the same patterns,
+    matches the oracle; the backward before and after the record is the
+    same bit for bit (the same sums in the same order)."""
+    rng = np.random.default_rng(1200 + d)
+    n = 1500
+    a = random_csr(rng, n, n, 0.006, kind="normal", empty_rows=0.1, dense_rows=2)
+    b = random_csr(rng, n, d, min(0.5, 6.0 / d + 0.02), kind="normal", empty_rows=0.1)
+    tss = _tss()
+    A, B = to_dev(a), to_dev(b)
+    C, plan = tss.spgemm(A, B, return_plan=True)  # symbolic + numeric call 1
+    crp, cci, _ = oracle.spgemm(a.rp, a.ci, a.val, b.rp, b.ci, b.val)
+    g = rng.standard_normal(len(cci)).astype(np.float32)
+    G = C.with_vals(torch.from_numpy(g).cuda())
+    AT, perm = tss.transpose(A)
+    ga0, gb0 = tss.backward(plan, AT, perm, A, B, G)
+    torch.cuda.synchronize()
+    ga0, gb0 = ga0.clone(), gb0.clone()
+    for call in (2, 3, 4):
+        av = rng.standard_normal(a.nnz).astype(np.float32)
+        bv = rng.standard_normal(b.nnz).astype(np.float32)
+        a2, b2 = a.with_values(av), b.with_values(bv)
+        A2 = A.with_vals(torch.from_numpy(av).cuda())
+        B2 = B.with_vals(torch.from_numpy(bv).cuda())
+        ci = torch.empty(max(C.nnz, 1), dtype=torch.int32, device="cuda")
+        cv = torch.empty(max(C.nnz, 1), dtype=torch.float32, device="cuda")
+        note(f"numeric call {call} d={d}")
+        tss.numeric(plan, A2, B2, ci, cv)
+        torch.cuda.synchronize()
+        compare_f32(a2, b2, tss.DeviceCsr(C.nrows, C.ncols, C.rowptr, ci[:C.nnz], cv[:C.nnz]), signed=True)
+    ga1, gb1 = tss.backward(plan, AT, perm, A, B, G)
+    torch.cuda.synchronize()
+    assert torch.equal(ga0, ga1) and torch.equal(gb0, gb1)
