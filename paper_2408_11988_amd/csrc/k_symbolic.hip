@@ -550,19 +550,24 @@ int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st) {
   // lane per A entry (k_symbolic_*_lanes)
   const bool lanes = sp.mask == nullptr && sp.fnz == nullptr && sp.pr.wp <= 8;
   // with a mask, or bitmap rows of 16 words: the same lane-per-row /
-  // lane-per-entry form with the mask. Not with the frontier filter and early
-  // exit of the BFS: there the slot kernels stop a row after fewer gathers
-  // (R-MAT 22 x 512 BFS: 27.9 ms with these kernels, 23.5 ms without)
-  const bool lanes_m = !lanes && sp.pr.wp <= 16 && sp.fnz == nullptr;
+  // lane-per-entry form with the mask. Heavy items with early exit (the BFS)
+  // keep the slot kernel, which tests coverage without a wavefront-wide
+  // reduction (R-MAT 22 x 512 BFS: heavy items 0.97 ms per product in slots,
+  // 1.81 ms in the lane form; light rows 0.83 ms in slots, 0.48 ms as lanes)
+  const bool light_m = !lanes && sp.pr.wp <= 16;
+  const bool heavy_m = light_m && !sp.early_exit;
   const unsigned g_lanes = grid_for(n, kBlock);
 #define TSS_SYM_CASE(W)                                                           \
   case W:                                                                         \
     if (lanes) {                                                                  \
       k_symbolic_light_lanes<W><<<g_lanes, kBlock, 0, st>>>(sp);                  \
       if (max_items > 0) k_symbolic_lanes<W><<<g_heavy, kBlock, 0, st>>>(sp);     \
-    } else if (lanes_m) {                                                         \
+    } else if (light_m) {                                                         \
       k_symbolic_light_lanes_m<(W <= 16 ? W : 16)><<<g_lanes, kBlock, 0, st>>>(sp); \
-      if (max_items > 0) k_symbolic_lanes_m<(W <= 16 ? W : 16)><<<g_heavy, kBlock, 0, st>>>(sp); \
+      if (max_items > 0 && heavy_m)                                               \
+        k_symbolic_lanes_m<(W <= 16 ? W : 16)><<<g_heavy, kBlock, 0, st>>>(sp);   \
+      else if (max_items > 0)                                                     \
+        k_symbolic<W><<<g_heavy, kBlock, 0, st>>>(sp);                            \
     } else {                                                                      \
       k_symbolic_light<W><<<g_light, kBlock, 0, st>>>(sp);                        \
       if (max_items > 0) k_symbolic<W><<<g_heavy, kBlock, 0, st>>>(sp);           \
