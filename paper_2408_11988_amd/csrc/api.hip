@@ -396,6 +396,17 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   p->numeric_calls = 0;
 
   if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
+  // Two streams: the binning of A's rows (it does not need B) and then the
+  // heavy items run on the plan's side stream, while `stream` builds B's
+  // bitmap and then walks the light rows; the heavy items wait for the
+  // bitmap, and `stream` waits for the heavy items before the counts.
+  if (!p->side) TSS_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&p->ev_fork, &p->ev_bm, &p->ev_join})
+    if (!*e) TSS_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  TSS_HIP(hipEventRecord(p->ev_fork, st));
+  TSS_HIP(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+  if ((rc = launch_sym_bin(pr, tn.sym_split_nnz, (Item*)p->sym_items.p, ctr, p->side))) return rc;
+  if ((rc = launch_sym_split_zero(pr, (const Item*)p->sym_items.p, ctr, sym_cap, p->side))) return rc;
   // B's bitmap; for value semirings the same pass narrows B's column ids
   // (the numeric phase reads them; B's pattern is fixed for the plan)
   const int cb = sr != TSSPGEMM_OR_AND ? col_id_bytes(d) : 0;
@@ -411,14 +422,17 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   } else if (M && M->kind == TSSPGEMM_MASK_COMPLEMENT_BITMAP) {
     mask = M->bits;
   }
-  if ((rc = launch_sym_bin(pr, tn.sym_split_nnz, (Item*)p->sym_items.p, ctr, st))) return rc;
   SymParams sp{};
   sp.pr = pr;
   sp.items = (const Item*)p->sym_items.p;
   sp.ctr = ctr;
   sp.mask = mask;
-  if ((rc = launch_sym_split_zero(pr, (const Item*)p->sym_items.p, ctr, sym_cap, st))) return rc;
-  if ((rc = launch_symbolic(sp, sym_cap, st))) return rc;
+  TSS_HIP(hipEventRecord(p->ev_bm, st));
+  if ((rc = launch_symbolic_part(sp, sym_cap, kSymLight, st))) return rc;
+  TSS_HIP(hipStreamWaitEvent(p->side, p->ev_bm, 0));
+  if ((rc = launch_symbolic_part(sp, sym_cap, kSymHeavy, p->side))) return rc;
+  TSS_HIP(hipEventRecord(p->ev_join, p->side));
+  TSS_HIP(hipStreamWaitEvent(st, p->ev_join, 0));
   if ((rc = launch_sym_split_mask(pr, (const Item*)p->sym_items.p, mask, ctr, sym_cap, st))) return rc;
   if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
   if (sr != TSSPGEMM_OR_AND) {
@@ -516,7 +530,7 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   // plan's own, aligned); otherwise one entry per lane
   int products = p->tune.products;
   if (products == TSSPGEMM_PRODUCTS_VEC4 && ((uintptr_t)B->vals % 16) != 0) products = TSSPGEMM_PRODUCTS_PER_B_ROW;
-  if ((rc = launch_numeric(p->sr, p->tune.group_lanes, products, np, grid, st))) return rc;
+  if ((rc = launch_numeric(p->sr, p->tune.group_lanes, products, np, grid, st, st))) return rc;
   if (recording) p->ebnd_valid = true;  // the staging of this call writes every staged entry's bounds
   return launch_split_finalize(p->sr, pr, (const SplitRow*)p->split_rows.p, (int32_t)p->n_split_rows,
                                (const double*)p->partial.p, (const int32_t*)p->partial.p, st);

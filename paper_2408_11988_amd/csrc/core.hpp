@@ -116,6 +116,10 @@ int launch_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t
 
 int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st);
 int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st);
+// The light-row kernel, the heavy-item kernel, or both (they touch disjoint
+// rows, so they may run on two streams at once).
+constexpr int kSymLight = 1, kSymHeavy = 2;
+int launch_symbolic_part(const SymParams& sp, int64_t max_items, int part, hipStream_t st);
 int launch_sym_split_zero(const Problem& pr, const Item* items, Counters* ctr, int64_t max_items, hipStream_t st);
 int launch_sym_split_mask(const Problem& pr, const Item* items, const uint32_t* mask, Counters* ctr,
                           int64_t max_items, hipStream_t st);
@@ -131,7 +135,10 @@ int launch_exscan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* block
 int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
                    hipStream_t st);
 
-int launch_numeric(int sr, int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st);
+// The light-row kernel runs on st_light (may equal st; its rows are disjoint
+// from the other kernels' items).
+int launch_numeric(int sr, int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st,
+                   hipStream_t st_light);
 int col_id_bytes(int64_t d);  // 1 or 2: width of the narrowed column ids
 int launch_split_finalize(int sr, const Problem& pr, const SplitRow* rows, int32_t nrows, const double* partial,
                           const int32_t* ipartial, hipStream_t st);

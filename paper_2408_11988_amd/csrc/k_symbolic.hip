@@ -539,8 +539,14 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_lanes_m(SymParams sp) {
 }
 
 int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st) {
+  return launch_symbolic_part(sp, max_items, kSymLight | kSymHeavy, st);
+}
+
+int launch_symbolic_part(const SymParams& sp, int64_t max_items, int part, hipStream_t st) {
   const int64_t n = sp.pr.n;
   if (n == 0) return TSSPGEMM_OK;
+  const bool do_light = (part & kSymLight) != 0;
+  if (!(part & kSymHeavy)) max_items = 0;  // no heavy launch
   const int ns = kWave / sp.pr.wp;
   const unsigned g_light = grid_for(n, ns * kWavesPerBlock);
   // heavy items: enough wavefronts to fill the chip, never more than items
@@ -560,16 +566,17 @@ int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st) {
 #define TSS_SYM_CASE(W)                                                           \
   case W:                                                                         \
     if (lanes) {                                                                  \
-      k_symbolic_light_lanes<W><<<g_lanes, kBlock, 0, st>>>(sp);                  \
+      if (do_light) k_symbolic_light_lanes<W><<<g_lanes, kBlock, 0, st>>>(sp);    \
       if (max_items > 0) k_symbolic_lanes<W><<<g_heavy, kBlock, 0, st>>>(sp);     \
     } else if (light_m) {                                                         \
-      k_symbolic_light_lanes_m<(W <= 16 ? W : 16)><<<g_lanes, kBlock, 0, st>>>(sp); \
+      if (do_light)                                                               \
+        k_symbolic_light_lanes_m<(W <= 16 ? W : 16)><<<g_lanes, kBlock, 0, st>>>(sp); \
       if (max_items > 0 && heavy_m)                                               \
         k_symbolic_lanes_m<(W <= 16 ? W : 16)><<<g_heavy, kBlock, 0, st>>>(sp);   \
       else if (max_items > 0)                                                     \
         k_symbolic<W><<<g_heavy, kBlock, 0, st>>>(sp);                            \
     } else {                                                                      \
-      k_symbolic_light<W><<<g_light, kBlock, 0, st>>>(sp);                        \
+      if (do_light) k_symbolic_light<W><<<g_light, kBlock, 0, st>>>(sp);          \
       if (max_items > 0) k_symbolic<W><<<g_heavy, kBlock, 0, st>>>(sp);           \
     }                                                                             \
     break;
