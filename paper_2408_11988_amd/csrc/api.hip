@@ -530,7 +530,7 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   // plan's own, aligned); otherwise one entry per lane
   int products = p->tune.products;
   if (products == TSSPGEMM_PRODUCTS_VEC4 && ((uintptr_t)B->vals % 16) != 0) products = TSSPGEMM_PRODUCTS_PER_B_ROW;
-  if ((rc = launch_numeric(p->sr, p->tune.group_lanes, products, np, grid, st, st))) return rc;
+  if ((rc = launch_numeric(p->sr, p->tune.group_lanes, products, np, grid, st))) return rc;
   if (recording) p->ebnd_valid = true;  // the staging of this call writes every staged entry's bounds
   return launch_split_finalize(p->sr, pr, (const SplitRow*)p->split_rows.p, (int32_t)p->n_split_rows,
                                (const double*)p->partial.p, (const int32_t*)p->partial.p, st);

@@ -135,10 +135,7 @@ int launch_exscan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* block
 int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
                    hipStream_t st);
 
-// The light-row kernel runs on st_light (may equal st; its rows are disjoint
-// from the other kernels' items).
-int launch_numeric(int sr, int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st,
-                   hipStream_t st_light);
+int launch_numeric(int sr, int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st);
 int col_id_bytes(int64_t d);  // 1 or 2: width of the narrowed column ids
 int launch_split_finalize(int sr, const Problem& pr, const SplitRow* rows, int32_t nrows, const double* partial,
                           const int32_t* ipartial, hipStream_t st);

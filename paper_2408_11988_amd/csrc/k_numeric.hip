@@ -126,8 +126,7 @@ static int64_t light_grid(int64_t n_light, int gl) {
 int col_id_bytes(int64_t d) { return d <= 256 ? 1 : 2; }
 
 template <typename T, typename BR, int LAYOUT>
-static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st,
-                            hipStream_t st_light) {
+static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid, hipStream_t st) {
   const size_t ab = sizeof(typename SemiringT<T>::acc);
   if (n_grid > 0) {
     const size_t lds = (size_t)kWavesPerBlock * np.pr.d * ab + kWavesPerBlock * kWave * sizeof(int4);
@@ -149,11 +148,11 @@ static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid
     const unsigned g = (unsigned)light_grid(np.n_light, gl);
     const size_t lds = (size_t)(kBlock / gl) * np.pr.d * ab + kBlock * sizeof(int4);
     switch (gl) {
-      case 4: k_numeric_light<4, T, BR, LAYOUT><<<g, kBlock, lds, st_light>>>(np); break;
-      case 8: k_numeric_light<8, T, BR, LAYOUT><<<g, kBlock, lds, st_light>>>(np); break;
-      case 16: k_numeric_light<16, T, BR, LAYOUT><<<g, kBlock, lds, st_light>>>(np); break;
-      case 32: k_numeric_light<32, T, BR, LAYOUT><<<g, kBlock, lds, st_light>>>(np); break;
-      case 64: k_numeric_light<64, T, BR, LAYOUT><<<g, kBlock, lds, st_light>>>(np); break;
+      case 4: k_numeric_light<4, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
+      case 8: k_numeric_light<8, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
+      case 16: k_numeric_light<16, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
+      case 32: k_numeric_light<32, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
+      case 64: k_numeric_light<64, T, BR, LAYOUT><<<g, kBlock, lds, st>>>(np); break;
       default:
         set_error("numeric: bad light group width");
         return TSSPGEMM_ERR_INVALID_ARG;
@@ -164,29 +163,27 @@ static int launch_numeric_t(int group_lanes, const NumParams& np, int64_t n_grid
 }
 
 template <typename T, typename BR>
-static int launch_numeric_l(int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st,
-                            hipStream_t st_light) {
+static int launch_numeric_l(int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st) {
   switch (products) {
-    case TSSPGEMM_PRODUCTS_FLAT: return launch_numeric_t<T, BR, kLayoutFlat>(group_lanes, np, n_grid, st, st_light);
-    case TSSPGEMM_PRODUCTS_VEC4: return launch_numeric_t<T, BR, kLayoutVec>(group_lanes, np, n_grid, st, st_light);
-    default: return launch_numeric_t<T, BR, kLayoutRows>(group_lanes, np, n_grid, st, st_light);
+    case TSSPGEMM_PRODUCTS_FLAT: return launch_numeric_t<T, BR, kLayoutFlat>(group_lanes, np, n_grid, st);
+    case TSSPGEMM_PRODUCTS_VEC4: return launch_numeric_t<T, BR, kLayoutVec>(group_lanes, np, n_grid, st);
+    default: return launch_numeric_t<T, BR, kLayoutRows>(group_lanes, np, n_grid, st);
   }
 }
 
 // B's column ids are read narrowed (np.pr.bcol, col_id_bytes(d) bytes each).
 // products: tsspgemm_products (resolved, not AUTO).
-int launch_numeric(int sr, int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st,
-                   hipStream_t st_light) {
+int launch_numeric(int sr, int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st) {
   const bool b8 = col_id_bytes(np.pr.d) == 1;
   if (!np.pr.bcol && np.pr.n > 0) {
     set_error("numeric: narrowed column ids missing");
     return TSSPGEMM_ERR_INVALID_ARG;
   }
   if (sr == TSSPGEMM_PLUS_TIMES_F32)
-    return b8 ? launch_numeric_l<float, BSep<uint8_t>>(group_lanes, products, np, n_grid, st, st_light)
-              : launch_numeric_l<float, BSep<uint16_t>>(group_lanes, products, np, n_grid, st, st_light);
-  return b8 ? launch_numeric_l<int32_t, BSep<uint8_t>>(group_lanes, products, np, n_grid, st, st_light)
-            : launch_numeric_l<int32_t, BSep<uint16_t>>(group_lanes, products, np, n_grid, st, st_light);
+    return b8 ? launch_numeric_l<float, BSep<uint8_t>>(group_lanes, products, np, n_grid, st)
+              : launch_numeric_l<float, BSep<uint16_t>>(group_lanes, products, np, n_grid, st);
+  return b8 ? launch_numeric_l<int32_t, BSep<uint8_t>>(group_lanes, products, np, n_grid, st)
+            : launch_numeric_l<int32_t, BSep<uint16_t>>(group_lanes, products, np, n_grid, st);
 }
 
 // Split rows: add the chunks' partial strips in chunk order, then emit.
