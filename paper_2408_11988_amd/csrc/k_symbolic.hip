@@ -312,24 +312,25 @@ __global__ __launch_bounds__(kBlock) void k_symbolic(SymParams sp) {
           fl += __popc(x);
         }
       } else {
-        // wavefront-uniform steps of 4 * NS entries (entry base + slot + u NS),
-        // so the early-exit test below sees every lane
-        for (int base = it.p0; base < it.p1; base += 4 * NS) {
-          int k[4];
-          bool v[4];
+        // wavefront-uniform steps of 16 * NS entries (entry base + slot + u NS),
+        // so the early-exit test below sees every lane (16 per slot in flight:
+        // R-MAT 22 x 512 BFS 18.6 ms, against 19.4 with 8 and 21.1 with 4)
+        for (int base = it.p0; base < it.p1; base += 16 * NS) {
+          int k[16];
+          bool v[16];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 16; ++u) {
             const int q = base + slot + u * NS;
             v[u] = q < it.p1;
             k[u] = v[u] ? aci[q] : 0;
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) v[u] = v[u] && ((fnz[k[u] >> 5] >> (k[u] & 31)) & 1u);
-          uint32_t x[4];
+          for (int u = 0; u < 16; ++u) v[u] = v[u] && ((fnz[k[u] >> 5] >> (k[u] & 31)) & 1u);
+          uint32_t x[16];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) x[u] = v[u] ? bb[(int64_t)k[u] * WP + w] : 0u;
+          for (int u = 0; u < 16; ++u) x[u] = v[u] ? bb[(int64_t)k[u] * WP + w] : 0u;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 16; ++u) {
             acc |= x[u];
             fl += __popc(x[u]);
           }
