@@ -136,6 +136,16 @@ def test_argument_errors_of_the_extra_entry_points(lib):
     assert lib.tsspgemm_merge_count(2, two, p, ctypes.byref(nnz), None) == _lib.ERR_INVALID_ARG  # shapes differ
     wide = (_lib.CsrDesc * 1)(_desc(4, 2048, 2))
     assert lib.tsspgemm_merge_values(1, wide, p, p, p, None) == _lib.ERR_UNSUPPORTED
+    # batched plan: an instance with d > 1024 (the batch has no hash accumulator)
+    batch = ctypes.c_void_p(None)
+    pool, rps = ctypes.c_int64(0), ctypes.c_int64(0)
+    As = (_lib.CsrDesc * 2)(_desc(4, 4, 2), _desc(4, 4, 2))
+    Bs = (_lib.CsrDesc * 2)(_desc(4, 64, 2), _desc(4, 2048, 2))
+    rc = lib.tsspgemm_batched_plan(2, As, Bs, None, ctypes.byref(batch), ctypes.byref(pool), ctypes.byref(rps), None)
+    assert rc == _lib.ERR_UNSUPPORTED and b"d > 1024" in lib.tsspgemm_last_error() and not batch.value
+    Bs = (_lib.CsrDesc * 2)(_desc(4, 64, 2), _desc(5, 64, 2))  # B's rows differ from A's columns
+    rc = lib.tsspgemm_batched_plan(2, As, Bs, None, ctypes.byref(batch), ctypes.byref(pool), ctypes.byref(rps), None)
+    assert rc == _lib.ERR_INVALID_ARG and not batch.value
 
 
 def test_tiled_spgemm_rejects_tile_counts_outside_the_merge_limit():
