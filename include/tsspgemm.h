@@ -160,7 +160,12 @@ int tsspgemm_symbolic(const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t sr, 
  * FP32 values are summed in FP64 and rounded once. With the LDS strip every
  * order of addition is fixed (results repeat bit for bit); the hash
  * accumulator adds with atomics in an order that may vary.
- * Asynchronous. Errors: INVALID_ARG, HIP. */
+ * With the LDS strip and values, the plan's second numeric call records each
+ * A entry's B row bounds (8 B per A entry of plan workspace, allocated by
+ * that call), which later calls and tsspgemm_backward read instead of
+ * gathering B's row pointers; a call being captured into a graph neither
+ * records nor counts toward the second call.
+ * Asynchronous. Errors: INVALID_ARG, NOMEM (the record's workspace), HIP. */
 int tsspgemm_numeric(tsspgemm_plan plan, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* c_colidx,
                      void* c_vals, void* stream);
 

@@ -11,6 +11,12 @@
 
 namespace tss {
 
+// True while `st` is capturing into a graph.
+static bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 const std::string& get_error() { return g_last_error; }
@@ -396,17 +402,19 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   p->numeric_calls = 0;
 
   if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
-  // Two streams: the binning of A's rows (it does not need B) and then the
-  // heavy items run on the plan's side stream, while `stream` builds B's
-  // bitmap and then walks the light rows; the heavy items wait for the
-  // bitmap, and `stream` waits for the heavy items before the counts.
+  // Two streams. The plan's side stream bins A's rows (no need of B; split
+  // rows' bitmap rows and counts are cleared there too), then runs the heavy
+  // items once B's bitmap is built, then (value semirings) bins the rows for
+  // the numeric phase once the light rows' product counts are in. `stream`
+  // builds B's bitmap, walks the light rows, and after the heavy items
+  // counts the rows and scans them into C's row pointers, beside that
+  // numeric binning; it waits for the side stream before the read-back.
   if (!p->side) TSS_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&p->ev_fork, &p->ev_bm, &p->ev_join})
+  for (hipEvent_t* e : {&p->ev_fork, &p->ev_bm, &p->ev_light, &p->ev_heavy, &p->ev_join})
     if (!*e) TSS_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   TSS_HIP(hipEventRecord(p->ev_fork, st));
   TSS_HIP(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-  if ((rc = launch_sym_bin(pr, tn.sym_split_nnz, (Item*)p->sym_items.p, ctr, p->side))) return rc;
-  if ((rc = launch_sym_split_zero(pr, (const Item*)p->sym_items.p, ctr, sym_cap, p->side))) return rc;
+  if ((rc = launch_sym_bin(pr, tn.sym_split_nnz, (Item*)p->sym_items.p, ctr, p->side, true))) return rc;
   // B's bitmap; for value semirings the same pass narrows B's column ids
   // (the numeric phase reads them; B's pattern is fixed for the plan)
   const int cb = sr != TSSPGEMM_OR_AND ? col_id_bytes(d) : 0;
@@ -429,17 +437,21 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   sp.mask = mask;
   TSS_HIP(hipEventRecord(p->ev_bm, st));
   if ((rc = launch_symbolic_part(sp, sym_cap, kSymLight, st))) return rc;
+  TSS_HIP(hipEventRecord(p->ev_light, st));
   TSS_HIP(hipStreamWaitEvent(p->side, p->ev_bm, 0));
   if ((rc = launch_symbolic_part(sp, sym_cap, kSymHeavy, p->side))) return rc;
-  TSS_HIP(hipEventRecord(p->ev_join, p->side));
-  TSS_HIP(hipStreamWaitEvent(st, p->ev_join, 0));
-  if ((rc = launch_sym_split_mask(pr, (const Item*)p->sym_items.p, mask, ctr, sym_cap, st))) return rc;
-  if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
-  if (sr != TSSPGEMM_OR_AND) {
+  TSS_HIP(hipEventRecord(p->ev_heavy, p->side));
+  if (sr != TSSPGEMM_OR_AND) {  // needs every row's product count, not C's
+    TSS_HIP(hipStreamWaitEvent(p->side, p->ev_light, 0));
     const NumThresholds th{tn.light_max_flops, tn.wave_max_flops, tn.split_flops};
-    if ((rc = launch_num_bin(pr, th, (Item*)p->num_items.p, (SplitRow*)p->split_rows.p, ctr, st)))
+    if ((rc = launch_num_bin(pr, th, (Item*)p->num_items.p, (SplitRow*)p->split_rows.p, ctr, p->side)))
       return rc;
   }
+  TSS_HIP(hipEventRecord(p->ev_join, p->side));
+  TSS_HIP(hipStreamWaitEvent(st, p->ev_heavy, 0));
+  if ((rc = launch_sym_split_mask(pr, (const Item*)p->sym_items.p, mask, ctr, sym_cap, st))) return rc;
+  if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
+  TSS_HIP(hipStreamWaitEvent(st, p->ev_join, 0));
   TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   TSS_HIP(hipStreamSynchronize(st));
   const Counters& h = *p->host_ctr;
@@ -507,11 +519,14 @@ int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* 
   if (!vals) return launch_emit_pattern(pr, st);
   // A plan whose numeric phase repeats (a training loop): the second call
   // records each A entry's B row bounds as its staging gathers them (8 B per
-  // A entry), and later calls and the backward read them instead.
+  // A entry), and later calls and the backward read them instead. A call
+  // being captured into a graph neither records nor counts: its kernels run
+  // only when the graph is replayed, and the record's buffer may not be
+  // allocated under capture.
   bool recording = false;
   if (p->ebnd_valid) {
     pr.ebnd = (const int2*)p->ebnd.p;
-  } else if (++p->numeric_calls >= 2) {
+  } else if (!capturing(st) && ++p->numeric_calls >= 2) {
     if ((rc = p->ebnd.ensure((size_t)p->a_nnz * sizeof(int2)))) return rc;
     pr.ebnd_w = (int2*)p->ebnd.p;
     recording = true;
@@ -553,10 +568,6 @@ Plan* cached_plan(int dev) {
 // the device: a call waits for the previous call's event when that call ran
 // on another stream, and records its own at the end. Work being captured
 // into a graph neither waits nor records (the caller orders graph replays).
-static bool capturing(hipStream_t st) {
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
-}
 
 int order_after_last(Plan* p, hipStream_t st) {
   if (!p->ord_valid || p->ord_last == st || capturing(st)) return TSSPGEMM_OK;

@@ -240,20 +240,9 @@ __global__ __launch_bounds__(kBlock) void k_b_symbolic_lanes(BatchDev b) {
   for (int x = x0 + blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); x < x1; x += gridDim.x * kWavesPerBlock) {
     const Item it = b.sym_items[x];
     const Problem& pr = b.insts[b.sym_inst[x]].pr;
-    const uint32_t* __restrict__ bb = pr.bbits;
     const bool split = (it.aux & kSplitFlag) != 0;
-    BmRow<WP> acc;
-#pragma unroll
-    for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
     int fl = 0;
-    int p = it.p0 + lane;
-    for (; p + kWave < it.p1; p += 2 * kWave) {
-      const int k0 = pr.aci[p], k1 = pr.aci[p + kWave];
-      bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
-      bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
-    }
-    if (p < it.p1) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
-    const uint32_t word = bm_wave_or<WP>(acc, lane);  // word bm_word_of<WP>(lane), OR-ed over the wavefront
+    const uint32_t word = sym_item_or<WP>(pr, it.p0, it.p1, lane, fl);
     const long long fsum = (int64_t)(it.p1 - it.p0) * 32 * WP < (1ll << 31) ? (long long)wave_sum_i32(fl)
                                                                               : wave_sum_i64((long long)fl);
     if ((lane & (kWave / WP - 1)) == 0) {  // the first lane holding each word
@@ -318,13 +307,8 @@ __global__ __launch_bounds__(kBlock) void k_b_symbolic(BatchDev b, int wp) {
     const Item it = b.sym_items[x];
     const Problem& pr = b.insts[b.sym_inst[x]].pr;
     const bool split = (it.aux & kSplitFlag) != 0;
-    uint32_t acc = 0u;
     int fl = 0;
-    for (int p = it.p0 + slot; p < it.p1; p += ns) {
-      const uint32_t v = pr.bbits[(int64_t)pr.aci[p] * wp + w];
-      acc |= v;
-      fl += __popc(v);
-    }
+    uint32_t acc = sym_item_or_slots(pr, it.p0, it.p1, wp, lane, word_cols(pr.d, w), fl);
     for (int o = wp; o < kWave; o <<= 1) acc |= shfl_xor_u32(acc, o);
     const long long fsum = wave_sum_i64((long long)fl);
     if (slot == 0) {

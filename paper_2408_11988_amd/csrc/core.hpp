@@ -114,7 +114,10 @@ int launch_nonempty_bits(int64_t n, const int32_t* rp, uint32_t* bits, hipStream
 int launch_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t* rp, const int32_t* ci,
                         Counters* ctr, hipStream_t st);
 
-int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st);
+// zero_split: also clear the C bitmap row and product count of every split
+// row (its chunks OR and add into them), in place of launch_sym_split_zero
+int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st,
+                   bool zero_split = false);
 int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st);
 // The light-row kernel, the heavy-item kernel, or both (they touch disjoint
 // rows, so they may run on two streams at once).

@@ -191,4 +191,109 @@ __device__ __forceinline__ void sym_bin(int m, int32_t split_nnz, int& bin, int&
   }
 }
 
+// Columns < d in bitmap word w (all ones for a whole word, none past d).
+__device__ __forceinline__ uint32_t word_cols(int d, int w) {
+  const int wb = 32 * w;
+  return d >= wb + 32 ? 0xffffffffu : (d > wb ? (1u << (d - wb)) - 1u : 0u);
+}
+
+// One heavy item's pattern over a wavefront, a lane per A entry: the OR of
+// the B bitmap rows of A entries [p0, p1), returned reduce-scattered (this
+// lane's word bm_word_of<WP>(lane), OR-ed over the wavefront); the products
+// (the B rows' lengths) are added to fl, per lane. Whole rounds of 2 * 64
+// entries, each followed by a check: once the accumulator holds every column
+// < d no later B row can change the pattern, and the rest of the item only
+// adds its B rows' lengths, read from B's row pointers instead of gathering
+// their bitmaps (in R-MAT rows a hub's pattern fills after a few dozen B
+// rows). B's columns are strictly increasing, so a bitmap row's popcount is
+// its length.
+template <int WP>
+__device__ __forceinline__ uint32_t sym_item_or(const Problem& pr, int p0, int p1, int lane, int& fl) {
+  const uint32_t* __restrict__ bb = pr.bbits;
+  const int32_t* __restrict__ aci = pr.aci;
+  const uint32_t wfull = word_cols(pr.d, bm_word_of<WP>(lane));
+  BmRow<WP> acc;
+#pragma unroll
+  for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
+  uint32_t word = 0u;
+  bool full = false;
+  int p = p0;
+  for (; p + 2 * kWave <= p1; p += 2 * kWave) {  // wavefront-uniform rounds
+    const int k0 = aci[p + lane], k1 = aci[p + kWave + lane];
+    bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
+    bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
+    word = bm_wave_or<WP>(acc, lane);
+    if (__ballot(word != wfull) == 0ull) {
+      full = true;
+      p += 2 * kWave;
+      break;
+    }
+  }
+  p += lane;
+  if (full) {
+    const int32_t* __restrict__ brp = pr.brp;
+    for (; p + 3 * kWave < p1; p += 4 * kWave) {
+      const int k0 = aci[p], k1 = aci[p + kWave], k2 = aci[p + 2 * kWave], k3 = aci[p + 3 * kWave];
+      fl += (brp[k0 + 1] - brp[k0]) + (brp[k1 + 1] - brp[k1]) + (brp[k2 + 1] - brp[k2]) + (brp[k3 + 1] - brp[k3]);
+    }
+    for (; p < p1; p += kWave) {
+      const int k = aci[p];
+      fl += brp[k + 1] - brp[k];
+    }
+    return word;
+  }
+  for (; p < p1; p += kWave) bm_load_or<WP>(bb + (int64_t)aci[p] * WP, acc, fl);
+  return bm_wave_or<WP>(acc, lane);
+}
+
+// One heavy item's pattern in slots of wp lanes (a lane per bitmap word,
+// 64 / wp B rows in flight): lane (slot, w) ORs word w of the B rows of
+// entries p0 + slot, p0 + slot + ns, ... and returns it (not yet OR-ed over
+// the slots); its popcounts are added to fl. Whole rounds of 4 * ns entries,
+// each followed by a check: once the accumulator, OR-ed over the slots, holds
+// every column of `need` (this lane's word: the columns the result can still
+// gain), the rest of the item only adds its B rows' lengths (B's row
+// pointers, counted by the slot's word-0 lane) without gathering bitmaps.
+__device__ __forceinline__ uint32_t sym_item_or_slots(const Problem& pr, int p0, int p1, int wp, int lane,
+                                                      uint32_t need, int& fl) {
+  const int ns = kWave / wp, slot = lane / wp, w = lane & (wp - 1);
+  const uint32_t* __restrict__ bb = pr.bbits;
+  const int32_t* __restrict__ aci = pr.aci;
+  uint32_t acc = 0u;
+  bool full = false;
+  int p = p0;
+  for (; p + 4 * ns <= p1; p += 4 * ns) {  // wavefront-uniform rounds
+    const int q = p + slot;
+    const int k0 = aci[q], k1 = aci[q + ns], k2 = aci[q + 2 * ns], k3 = aci[q + 3 * ns];
+    const uint32_t x0 = bb[(int64_t)k0 * wp + w], x1 = bb[(int64_t)k1 * wp + w];
+    const uint32_t x2 = bb[(int64_t)k2 * wp + w], x3 = bb[(int64_t)k3 * wp + w];
+    acc |= (x0 | x1) | (x2 | x3);
+    fl += __popc(x0) + __popc(x1) + __popc(x2) + __popc(x3);
+    uint32_t all = acc;
+    for (int o = wp; o < kWave; o <<= 1) all |= shfl_xor_u32(all, o);
+    if (__ballot((need & ~all) != 0u) == 0ull) {
+      full = true;
+      p += 4 * ns;
+      break;
+    }
+  }
+  p += slot;
+  if (full) {
+    if (w == 0) {
+      const int32_t* __restrict__ brp = pr.brp;
+      for (; p < p1; p += ns) {
+        const int k = aci[p];
+        fl += brp[k + 1] - brp[k];
+      }
+    }
+    return acc;
+  }
+  for (; p < p1; p += ns) {
+    const uint32_t x = bb[(int64_t)aci[p] * wp + w];
+    acc |= x;
+    fl += __popc(x);
+  }
+  return acc;
+}
+
 }  // namespace tss

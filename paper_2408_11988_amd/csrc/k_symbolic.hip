@@ -136,7 +136,7 @@ __global__ void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
 // counts, done by every workgroup) plus the bin's fill counter (sym_cursor,
 // zero at the start); the slot inside the workgroup's range comes from an
 // LDS counter in the second pass. Workgroup 0 stores the item total.
-__global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Counters* ctr) {
+__global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Counters* ctr, bool zero_split) {
   __shared__ int32_t cnt[kBins], base[kBins], off[kBins];
   if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
@@ -175,15 +175,20 @@ __global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Count
         const int p0 = a + c * split_nnz;
         items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + split_nnz), kSplitFlag | c};
       }
+      if (zero_split) {
+        for (int w = 0; w < pr.wp; ++w) pr.cbits[i * pr.wp + w] = 0u;
+        pr.flops[i] = 0;
+      }
     }
   }
 }
 
-int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st) {
+int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st,
+                   bool zero_split) {
   if (pr.n == 0) return TSSPGEMM_OK;  // the zeroed counters are the totals
   const unsigned g = grid_for(pr.n, kBinRowsPerBlock);
   k_sym_bin_count<<<g, 256, 0, st>>>(pr, split_nnz, ctr);
-  k_sym_bin_fill<<<g, 256, 0, st>>>(pr, split_nnz, items, ctr);
+  k_sym_bin_fill<<<g, 256, 0, st>>>(pr, split_nnz, items, ctr, zero_split);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }
@@ -297,20 +302,8 @@ __global__ __launch_bounds__(kBlock) void k_symbolic(SymParams sp) {
     uint32_t acc = 0u;
     int fl = 0;
     if (!skip) {
-      int p = it.p0 + slot;
       if (fnz == nullptr) {
-        for (; p + 3 * NS < it.p1; p += 4 * NS) {
-          const int k0 = aci[p], k1 = aci[p + NS], k2 = aci[p + 2 * NS], k3 = aci[p + 3 * NS];
-          const uint32_t x0 = bb[(int64_t)k0 * WP + w], x1 = bb[(int64_t)k1 * WP + w];
-          const uint32_t x2 = bb[(int64_t)k2 * WP + w], x3 = bb[(int64_t)k3 * WP + w];
-          acc |= (x0 | x1) | (x2 | x3);
-          fl += __popc(x0) + __popc(x1) + __popc(x2) + __popc(x3);
-        }
-        for (; p < it.p1; p += NS) {
-          const uint32_t x = bb[(int64_t)aci[p] * WP + w];
-          acc |= x;
-          fl += __popc(x);
-        }
+        acc = sym_item_or_slots(pr, it.p0, it.p1, WP, lane, need & word_cols(pr.d, w), fl);
       } else {
         // wavefront-uniform steps of 16 * NS entries (entry base + slot + u NS),
         // so the early-exit test below sees every lane (16 per slot in flight:
@@ -366,7 +359,8 @@ __global__ __launch_bounds__(kBlock) void k_symbolic(SymParams sp) {
 // bitmap row of its entry's B row (WP words, 16-byte loads), so a wavefront
 // has 64 B rows per load instruction in flight. Light rows: a lane owns a
 // row and walks its entries. Heavy items: the lanes of a wavefront take the
-// item's entries in turn and OR their words together at the end.
+// item's entries in turn and OR their words together, stopping the gathers
+// once the row holds every column (sym_item_or).
 template <int WP>
 __global__ __launch_bounds__(kBlock) void k_symbolic_light_lanes(SymParams sp) {
   const Problem& pr = sp.pr;
@@ -397,23 +391,12 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_lanes(SymParams sp) {
   const int total = sp.ctr->sym_total;
   const int wave_global = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   const int wave_stride = gridDim.x * kWavesPerBlock;
-  const uint32_t* __restrict__ bb = pr.bbits;
   for (int t = wave_global; t < total; t += wave_stride) {
     const Item it = sp.items[t];
     const bool split = (it.aux & kSplitFlag) != 0;
     const int64_t row = it.row;
-    BmRow<WP> acc;
-#pragma unroll
-    for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
     int fl = 0;
-    int p = it.p0 + lane;
-    for (; p + kWave < it.p1; p += 2 * kWave) {
-      const int k0 = pr.aci[p], k1 = pr.aci[p + kWave];
-      bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
-      bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
-    }
-    if (p < it.p1) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
-    const uint32_t word = bm_wave_or<WP>(acc, lane);  // word bm_word_of<WP>(lane), OR-ed over the wavefront
+    const uint32_t word = sym_item_or<WP>(pr, it.p0, it.p1, lane, fl);
     // products: at most 32 * WP per entry, so an int32 sum holds below 2^31 / (32 WP) entries
     const long long fsum = (int64_t)(it.p1 - it.p0) * 32 * WP < (1ll << 31) ? (long long)wave_sum_i32(fl)
                                                                               : wave_sum_i64((long long)fl);

@@ -279,3 +279,46 @@ def test_numeric_repeats_record_b_row_bounds(d):
     ga1, gb1 = tss.backward(plan, AT, perm, A, B, G)
     torch.cuda.synchronize()
     assert torch.equal(ga0, ga1) and torch.equal(gb0, gb1)
+
+
+def test_numeric_captured_in_graph_before_the_record():
+    """A numeric call captured into a HIP graph as the plan's second call
+    allocates nothing and records nothing (its kernels only run at replay):
+    the next eager call records the B row bounds, and the graph's replays
+    (new values copied into its inputs), the eager calls and the backward all
+    match the oracle."""
+    rng = np.random.default_rng(1300)
+    n, d = 1500, 128
+    a = random_csr(rng, n, n, 0.006, kind="normal", empty_rows=0.1, dense_rows=2)
+    b = random_csr(rng, n, d, 0.08, kind="normal", empty_rows=0.1)
+    tss = _tss()
+    A, B = to_dev(a), to_dev(b)
+    C, plan = tss.spgemm(A, B, return_plan=True)  # symbolic + numeric call 1
+    A2 = A.with_vals(torch.from_numpy(a.val.copy()).cuda())
+    B2 = B.with_vals(torch.from_numpy(b.val.copy()).cuda())
+    gci = torch.empty(max(C.nnz, 1), dtype=torch.int32, device="cuda")
+    gcv = torch.empty(max(C.nnz, 1), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    note("capture numeric call 2")
+    with torch.cuda.graph(graph):
+        tss.numeric(plan, A2, B2, gci, gcv)
+    torch.cuda.synchronize()
+    for step in range(4):
+        av = rng.standard_normal(a.nnz).astype(np.float32)
+        bv = rng.standard_normal(b.nnz).astype(np.float32)
+        a2, b2 = a.with_values(av), b.with_values(bv)
+        A2.vals.copy_(torch.from_numpy(av))
+        B2.vals.copy_(torch.from_numpy(bv))
+        note(f"replay {step}")
+        graph.replay()
+        torch.cuda.synchronize()
+        compare_f32(a2, b2, tss.DeviceCsr(C.nrows, C.ncols, C.rowptr, gci[:C.nnz], gcv[:C.nnz]), signed=True)
+        # eager calls between the replays: the first records the bounds, the
+        # rest read them
+        ci = torch.empty_like(gci)
+        cv = torch.empty_like(gcv)
+        note(f"eager numeric after replay {step}")
+        tss.numeric(plan, A2, B2, ci, cv)
+        torch.cuda.synchronize()
+        compare_f32(a2, b2, tss.DeviceCsr(C.nrows, C.ncols, C.rowptr, ci[:C.nnz], cv[:C.nnz]), signed=True)

@@ -53,10 +53,13 @@ def test_plus_times_random(d, acc, classes):
     if classes == "all_vec4":
         tun["products"] = "vec4"
     note(f"plus_times random n={n} d={d} nnzA={a.nnz} nnzB={b.nnz} tuning={tun}")
-    C = _tss().spgemm(to_dev(a), to_dev(b), tuning=tun)
+    C, plan = _tss().spgemm(to_dev(a), to_dev(b), tuning=tun, return_plan=True)
     torch.cuda.synchronize()
     frac = compare_f32(a, b, C)
     assert frac > 0.999
+    # the dense A rows fill their patterns early: the symbolic pass counts the
+    # rest of their products from B's row lengths
+    assert plan.stats()["flops"] == int(oracle.row_flops(a.rp, a.ci, b.rp).sum())
 
 
 @pytest.mark.parametrize("d", WIDE_D)
