@@ -402,15 +402,14 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   p->numeric_calls = 0;
 
   if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
-  // Two streams. The plan's side stream bins A's rows (no need of B; split
-  // rows' bitmap rows and counts are cleared there too), then runs the heavy
-  // items once B's bitmap is built, then (value semirings) bins the rows for
-  // the numeric phase once the light rows' product counts are in. `stream`
-  // builds B's bitmap, walks the light rows, and after the heavy items
-  // counts the rows and scans them into C's row pointers, beside that
-  // numeric binning; it waits for the side stream before the read-back.
+  // Two streams: the binning of A's rows (it does not need B; split rows'
+  // bitmap rows and counts are cleared there too) and then the heavy items
+  // run on the plan's side stream, while `stream` builds B's bitmap and then
+  // walks the light rows; the heavy items wait for the bitmap, and `stream`
+  // waits for the heavy items before the counts. (Each wait across the
+  // streams costs about 10 us on the device, so there is one each way.)
   if (!p->side) TSS_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-  for (hipEvent_t* e : {&p->ev_fork, &p->ev_bm, &p->ev_light, &p->ev_heavy, &p->ev_join})
+  for (hipEvent_t* e : {&p->ev_fork, &p->ev_bm, &p->ev_join})
     if (!*e) TSS_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
   TSS_HIP(hipEventRecord(p->ev_fork, st));
   TSS_HIP(hipStreamWaitEvent(p->side, p->ev_fork, 0));
@@ -437,21 +436,18 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   sp.mask = mask;
   TSS_HIP(hipEventRecord(p->ev_bm, st));
   if ((rc = launch_symbolic_part(sp, sym_cap, kSymLight, st))) return rc;
-  TSS_HIP(hipEventRecord(p->ev_light, st));
   TSS_HIP(hipStreamWaitEvent(p->side, p->ev_bm, 0));
   if ((rc = launch_symbolic_part(sp, sym_cap, kSymHeavy, p->side))) return rc;
-  TSS_HIP(hipEventRecord(p->ev_heavy, p->side));
-  if (sr != TSSPGEMM_OR_AND) {  // needs every row's product count, not C's
-    TSS_HIP(hipStreamWaitEvent(p->side, p->ev_light, 0));
-    const NumThresholds th{tn.light_max_flops, tn.wave_max_flops, tn.split_flops};
-    if ((rc = launch_num_bin(pr, th, (Item*)p->num_items.p, (SplitRow*)p->split_rows.p, ctr, p->side)))
-      return rc;
-  }
   TSS_HIP(hipEventRecord(p->ev_join, p->side));
-  TSS_HIP(hipStreamWaitEvent(st, p->ev_heavy, 0));
-  if ((rc = launch_sym_split_mask(pr, (const Item*)p->sym_items.p, mask, ctr, sym_cap, st))) return rc;
-  if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st))) return rc;
   TSS_HIP(hipStreamWaitEvent(st, p->ev_join, 0));
+  if ((rc = launch_sym_split_mask(pr, (const Item*)p->sym_items.p, mask, ctr, sym_cap, st))) return rc;
+  // the numeric phase's work binning (value semirings) rides on the count
+  // and row-pointer passes over the rows
+  const NumBinArgs nb{NumThresholds{tn.light_max_flops, tn.wave_max_flops, tn.split_flops}, (Item*)p->num_items.p,
+                      (SplitRow*)p->split_rows.p};
+  if ((rc = launch_count_scan(pr, (int32_t*)p->cnt.p, (int64_t*)p->scan.p, c_rowptr, ctr, st,
+                              sr != TSSPGEMM_OR_AND ? &nb : nullptr)))
+    return rc;
   TSS_HIP(hipMemcpyAsync(p->host_ctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, st));
   TSS_HIP(hipStreamSynchronize(st));
   const Counters& h = *p->host_ctr;

@@ -82,10 +82,10 @@ struct Plan {
   hipStream_t ord_last = nullptr;  //   and its stream
   bool ord_valid = false;
   Counters* host_ctr = nullptr;  // pinned
-  // symbolic phase: a second stream of the plan (default priority) and the
-  // events that order the two streams' work (see run_symbolic)
+  // symbolic phase: a second stream of the plan (default priority) for the
+  // work that does not wait for B's bitmap, and its fork / join events
   hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_bm = nullptr, ev_light = nullptr, ev_heavy = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_bm = nullptr, ev_join = nullptr;
   // results of the last symbolic call
   int64_t nnz = 0, flops_total = 0, n_split_items = 0, n_block_items = 0, n_wave_rows = 0, n_light_rows = 0;
   int64_t n_split_rows = 0;
@@ -94,7 +94,7 @@ struct Plan {
     if (host_ctr) (void)hipHostFree(host_ctr);
     host_ctr = nullptr;
     if (ord_ev) (void)hipEventDestroy(ord_ev);
-    for (hipEvent_t e : {ev_fork, ev_bm, ev_light, ev_heavy, ev_join})
+    for (hipEvent_t e : {ev_fork, ev_bm, ev_join})
       if (e) (void)hipEventDestroy(e);
     if (side) (void)hipStreamDestroy(side);
   }

@@ -208,9 +208,16 @@ __global__ void k_b_sym_split_zero(BatchDev b) {
 // bitmap rows (16-byte loads), as in the single-product pass.
 template <int WP>
 __global__ __launch_bounds__(kBlock) void k_b_sym_light_lanes(BatchDev b) {
-  const int64_t x = b.rrow_off[b.r_lo] + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (x >= b.rrow_off[b.r_hi]) return;
-  const int r = find_rank(b.rrow_off, b.r_lo, b.r_hi, x);
+  const int64_t x_end = b.rrow_off[b.r_hi];
+  // the wavefront's first row, and its rank found once for the wavefront
+  // (wave-uniform); lanes past the rank's last row (a wavefront that spans
+  // two instances) search on from the next rank
+  const int64_t xw = b.rrow_off[b.r_lo] + (int64_t)blockIdx.x * kBlock + (threadIdx.x & ~(kWave - 1));
+  if (xw >= x_end) return;
+  int r = __builtin_amdgcn_readfirstlane(find_rank(b.rrow_off, b.r_lo, b.r_hi, xw));
+  const int64_t x = xw + (threadIdx.x & (kWave - 1));
+  if (x >= x_end) return;
+  if (x >= b.rrow_off[r + 1]) r = find_rank(b.rrow_off, r + 1, b.r_hi, x);
   const Problem& pr = b.insts[b.rank_t[r]].pr;
   const int64_t row = x - b.rrow_off[r];
   const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
@@ -221,12 +228,14 @@ __global__ __launch_bounds__(kBlock) void k_b_sym_light_lanes(BatchDev b) {
   for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
   int fl = 0;
   int p = p0;
-  for (; p + 1 < p1; p += 2) {
-    const int k0 = pr.aci[p], k1 = pr.aci[p + 1];
+  for (; p + 3 < p1; p += 4) {  // four B bitmap rows in flight
+    const int k0 = pr.aci[p], k1 = pr.aci[p + 1], k2 = pr.aci[p + 2], k3 = pr.aci[p + 3];
     bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
     bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
+    bm_load_or<WP>(bb + (int64_t)k2 * WP, acc, fl);
+    bm_load_or<WP>(bb + (int64_t)k3 * WP, acc, fl);
   }
-  if (p < p1) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
+  for (; p < p1; ++p) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
   bm_store<WP>(pr.cbits + row * WP, acc);
   pr.flops[row] = fl;
 }
@@ -300,7 +309,6 @@ __global__ __launch_bounds__(kBlock) void k_b_sym_light(BatchDev b, int wp) {
 // of wp lanes per A entry.
 __global__ __launch_bounds__(kBlock) void k_b_symbolic(BatchDev b, int wp) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int ns = kWave / wp;
   const int slot = lane / wp, w = lane & (wp - 1);
   const int x0 = b.sb_kof[b.r_lo * kBins], x1 = b.sb_kof[b.r_hi * kBins];
   for (int x = x0 + blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); x < x1; x += gridDim.x * kWavesPerBlock) {

@@ -127,16 +127,25 @@ int launch_sym_split_zero(const Problem& pr, const Item* items, Counters* ctr, i
 int launch_sym_split_mask(const Problem& pr, const Item* items, const uint32_t* mask, Counters* ctr,
                           int64_t max_items, hipStream_t st);
 
-// popcount of each C bitmap row, exclusive scan -> c_rowptr, nnz(C) -> ctr
+// Work binning of the rows for the numeric phase (items in the layout of
+// NumParams), done inside the count and row-pointer kernels of
+// launch_count_scan: they walk the same rows.
+struct NumBinArgs {
+  NumThresholds th;
+  Item* items;
+  SplitRow* split_rows;
+};
+// popcount of each C bitmap row, exclusive scan -> c_rowptr, nnz(C) -> ctr;
+// nb: null, or the numeric phase's binning of the same rows (by their
+// product counts, set by the symbolic kernels)
 int launch_count_scan(const Problem& pr, int32_t* cnt, int64_t* block_sums, int32_t* c_rowptr, Counters* ctr,
-                      hipStream_t st);
+                      hipStream_t st, const NumBinArgs* nb = nullptr);
 int64_t scan_block_sums_capacity(int64_t n);
 int64_t exscan_workspace_bytes(int64_t n);
 int launch_exscan_i32(const int32_t* in, int64_t n, int32_t* out, int64_t* block_sums, hipStream_t st);
 int launch_exscan_i64(const int64_t* in, int64_t n, int64_t* out, int64_t* block_sums, hipStream_t st);
 
-int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
-                   hipStream_t st);
+
 
 int launch_numeric(int sr, int group_lanes, int products, const NumParams& np, int64_t n_grid, hipStream_t st);
 int col_id_bytes(int64_t d);  // 1 or 2: width of the narrowed column ids

@@ -255,103 +255,5 @@ int launch_emit_pattern(const Problem& pr, hipStream_t st) {
   return TSSPGEMM_OK;
 }
 
-__global__ void k_num_bin_count(Problem pr, NumThresholds th, Counters* ctr) {
-  __shared__ int32_t hist[kNumClasses * kBins];
-  for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) hist[t] = 0;
-  __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
-  const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
-  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const int64_t f = pr.flops[i];
-    if (f > 0) {
-      int cls, key, count, ce;
-      num_key(f, pr.arp[i + 1] - pr.arp[i], th, cls, key, count, ce);
-      atomicAdd(&hist[key], count);
-    }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x)
-    if (hist[t]) atomicAdd(&(&ctr->num_count[0][0])[t], hist[t]);
-}
-
-// Offsets of the (class, bin) buckets: an exclusive scan of the counts in
-// LDS, done by every fill workgroup (128 values), so no separate scan launch.
-__device__ __forceinline__ void num_bucket_offsets(const Counters* ctr, int32_t* off) {
-  if (threadIdx.x == 0) {
-    int32_t o = 0;
-    for (int t = 0; t < kNumClasses * kBins; ++t) {
-      off[t] = o;
-      o += (&ctr->num_count[0][0])[t];
-    }
-  }
-}
-
-// Items are placed with one global reservation per (class, bin) per
-// workgroup (counts from a first pass over its rows): the bucket's offset
-// plus the bucket's fill counter (num_cursor, zero at the start); the slot
-// inside the workgroup's range comes from an LDS counter in the second pass.
-// Workgroup 0 also stores the class totals.
-__global__ void k_num_bin_fill(Problem pr, NumThresholds th, Item* items, SplitRow* split_rows, Counters* ctr) {
-  __shared__ int32_t cnt[kNumClasses * kBins], base[kNumClasses * kBins], off[kNumClasses * kBins];
-  __shared__ int32_t nsplit, split_base;
-  for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) cnt[t] = 0;
-  if (threadIdx.x == 0) nsplit = 0;
-  num_bucket_offsets(ctr, off);
-  if (blockIdx.x == 0 && threadIdx.x < kNumClasses) {
-    int32_t tot = 0;
-    for (int b = 0; b < kBins; ++b) tot += ctr->num_count[threadIdx.x][b];
-    (&ctr->num_split_items)[threadIdx.x] = tot;  // split, block, wave, light: consecutive fields
-  }
-  __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
-  const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
-  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const int64_t f = pr.flops[i];
-    if (f > 0) {
-      int cls, key, count, ce;
-      num_key(f, pr.arp[i + 1] - pr.arp[i], th, cls, key, count, ce);
-      atomicAdd(&cnt[key], count);
-      if (cls == 0) atomicAdd(&nsplit, 1);
-    }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) {
-    if (cnt[t]) base[t] = off[t] + atomicAdd(&(&ctr->num_cursor[0][0])[t], cnt[t]);
-    cnt[t] = 0;
-  }
-  if (threadIdx.x == 0) {
-    if (nsplit) split_base = atomicAdd(&ctr->num_split_rows, nsplit);
-    nsplit = 0;
-  }
-  __syncthreads();
-  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const int64_t f = pr.flops[i];
-    if (f <= 0) continue;
-    const int a = pr.arp[i], m = pr.arp[i + 1] - a;
-    int cls, key, count, ce;
-    num_key(f, m, th, cls, key, count, ce);
-    const int pos = base[key] + atomicAdd(&cnt[key], count);
-    if (cls == 0) {
-      for (int c = 0; c < count; ++c) {
-        const int p0 = a + c * ce;
-        items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + ce), pos + c};
-      }
-      split_rows[split_base + atomicAdd(&nsplit, 1)] = SplitRow{(int32_t)i, pos, count, 0};
-    } else {
-      items[pos] = Item{(int32_t)i, a, a + m, cls == 1 ? kNoSlot : 0};
-    }
-  }
-}
-
-int launch_num_bin(const Problem& pr, const NumThresholds& th, Item* items, SplitRow* split_rows, Counters* ctr,
-                   hipStream_t st) {
-  if (pr.n > 0) {  // (with no rows the zeroed counters are the totals)
-    const unsigned g = grid_for(pr.n, kBinRowsPerBlock);
-    k_num_bin_count<<<g, 256, 0, st>>>(pr, th, ctr);
-    k_num_bin_fill<<<g, 256, 0, st>>>(pr, th, items, split_rows, ctr);
-  }
-  TSS_CHECK_LAUNCH();
-  return TSSPGEMM_OK;
-}
 
 }  // namespace tss

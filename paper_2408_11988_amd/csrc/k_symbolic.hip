@@ -9,6 +9,7 @@
 // Also here: the B-pattern bitmap build, the work binning of rows by A-row
 // length, and the popcount + exclusive scan that turns C's bitmaps into
 // C's row pointers.
+#include "dev_numeric.hpp"
 #include "dev_symbolic.hpp"
 
 namespace tss {
@@ -115,16 +116,36 @@ int launch_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t
 
 // ================================================================ binning (symbolic)
 
-__global__ void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
+// The rows of one binning workgroup (256 threads, kBinRowsPerBlock rows):
+// thread t takes rows r0 + t + 256 u. Their first A entries and A entry
+// counts are loaded into registers up front (all loads in flight at once;
+// rows past n get 0 entries).
+constexpr int kBinThreads = 256;
+constexpr int kBinPer = kBinRowsPerBlock / kBinThreads;
+
+__device__ __forceinline__ void bin_rows(const int32_t* __restrict__ arp, int64_t n, int64_t r0, int (&a)[kBinPer],
+                                         int (&m)[kBinPer]) {
+  int e[kBinPer];
+#pragma unroll
+  for (int u = 0; u < kBinPer; ++u) {
+    const int64_t i = r0 + threadIdx.x + (int64_t)kBinThreads * u;
+    a[u] = i < n ? arp[i] : 0;
+    e[u] = i < n ? arp[i + 1] : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < kBinPer; ++u) m[u] = e[u] - a[u];
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
   __shared__ int32_t hist[kBins];
   if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
+  int a[kBinPer], m[kBinPer];
+  bin_rows(pr.arp, pr.n, (int64_t)blockIdx.x * kBinRowsPerBlock, a, m);
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
-  const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
-  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const int m = pr.arp[i + 1] - pr.arp[i];
+#pragma unroll
+  for (int u = 0; u < kBinPer; ++u) {
     int bin, count;
-    sym_bin(m, split_nnz, bin, count);
+    sym_bin(m[u], split_nnz, bin, count);
     if (count) atomicAdd(&hist[bin], count);
   }
   __syncthreads();
@@ -136,7 +157,8 @@ __global__ void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
 // counts, done by every workgroup) plus the bin's fill counter (sym_cursor,
 // zero at the start); the slot inside the workgroup's range comes from an
 // LDS counter in the second pass. Workgroup 0 stores the item total.
-__global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Counters* ctr, bool zero_split) {
+__global__ __launch_bounds__(kBinThreads) void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items,
+                                                              Counters* ctr, bool zero_split) {
   __shared__ int32_t cnt[kBins], base[kBins], off[kBins];
   if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
@@ -147,12 +169,14 @@ __global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Count
     }
     if (blockIdx.x == 0) ctr->sym_total = o;
   }
-  __syncthreads();
   const int64_t r0 = (int64_t)blockIdx.x * kBinRowsPerBlock;
-  const int64_t r1 = min((int64_t)pr.n, r0 + kBinRowsPerBlock);
-  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+  int a[kBinPer], m[kBinPer];
+  bin_rows(pr.arp, pr.n, r0, a, m);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kBinPer; ++u) {
     int bin, count;
-    sym_bin(pr.arp[i + 1] - pr.arp[i], split_nnz, bin, count);
+    sym_bin(m[u], split_nnz, bin, count);
     if (count) atomicAdd(&cnt[bin], count);
   }
   __syncthreads();
@@ -162,18 +186,19 @@ __global__ void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items, Count
     cnt[threadIdx.x] = 0;
   }
   __syncthreads();
-  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
-    const int a = pr.arp[i], m = pr.arp[i + 1] - a;
+#pragma unroll
+  for (int u = 0; u < kBinPer; ++u) {
     int bin, count;
-    sym_bin(m, split_nnz, bin, count);
+    sym_bin(m[u], split_nnz, bin, count);
     if (!count) continue;
+    const int64_t i = r0 + threadIdx.x + (int64_t)kBinThreads * u;
     const int pos = base[bin] + atomicAdd(&cnt[bin], count);
-    if (m <= split_nnz) {
-      items[pos] = Item{(int32_t)i, a, a + m, 0};
+    if (m[u] <= split_nnz) {
+      items[pos] = Item{(int32_t)i, a[u], a[u] + m[u], 0};
     } else {
       for (int c = 0; c < count; ++c) {
-        const int p0 = a + c * split_nnz;
-        items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + split_nnz), kSplitFlag | c};
+        const int p0 = a[u] + c * split_nnz;
+        items[pos + c] = Item{(int32_t)i, p0, min(a[u] + m[u], p0 + split_nnz), kSplitFlag | c};
       }
       if (zero_split) {
         for (int w = 0; w < pr.wp; ++w) pr.cbits[i * pr.wp + w] = 0u;
@@ -187,8 +212,8 @@ int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* 
                    bool zero_split) {
   if (pr.n == 0) return TSSPGEMM_OK;  // the zeroed counters are the totals
   const unsigned g = grid_for(pr.n, kBinRowsPerBlock);
-  k_sym_bin_count<<<g, 256, 0, st>>>(pr, split_nnz, ctr);
-  k_sym_bin_fill<<<g, 256, 0, st>>>(pr, split_nnz, items, ctr, zero_split);
+  k_sym_bin_count<<<g, kBinThreads, 0, st>>>(pr, split_nnz, ctr);
+  k_sym_bin_fill<<<g, kBinThreads, 0, st>>>(pr, split_nnz, items, ctr, zero_split);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }
@@ -374,12 +399,14 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_light_lanes(SymParams sp) {
   for (int w = 0; w < WP; ++w) acc.w[w] = 0u;
   int fl = 0;
   int p = p0;
-  for (; p + 1 < p1; p += 2) {
-    const int k0 = pr.aci[p], k1 = pr.aci[p + 1];
+  for (; p + 3 < p1; p += 4) {  // four B bitmap rows in flight
+    const int k0 = pr.aci[p], k1 = pr.aci[p + 1], k2 = pr.aci[p + 2], k3 = pr.aci[p + 3];
     bm_load_or<WP>(bb + (int64_t)k0 * WP, acc, fl);
     bm_load_or<WP>(bb + (int64_t)k1 * WP, acc, fl);
+    bm_load_or<WP>(bb + (int64_t)k2 * WP, acc, fl);
+    bm_load_or<WP>(bb + (int64_t)k3 * WP, acc, fl);
   }
-  if (p < p1) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
+  for (; p < p1; ++p) bm_load_or<WP>(bb + (int64_t)pr.aci[p] * WP, acc, fl);
   bm_store<WP>(pr.cbits + row * WP, acc);
   pr.flops[row] = fl;
 }
@@ -620,9 +647,16 @@ int64_t scan_block_sums_capacity(int64_t n) { return 2 * ((n + kScanRows - 1) / 
 
 // Per block of rows: popcount of each C bitmap row (nnz of the row) and the
 // block totals of nnz and of products; block_sums holds nb nnz totals
-// followed by nb product totals.
-__global__ __launch_bounds__(kScanThreads) void k_count_rows(Problem pr, int32_t* cnt, int64_t* block_sums) {
+// followed by nb product totals. With `bin`, also the histogram of the
+// rows' numeric (class, bin) keys into the counters (num_count).
+__global__ __launch_bounds__(kScanThreads) void k_count_rows(Problem pr, int32_t* cnt, int64_t* block_sums,
+                                                             NumBinArgs nb, bool bin, Counters* ctr) {
   __shared__ long long sh[32];
+  __shared__ int32_t hist[kNumClasses * kBins];
+  if (bin) {
+    for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) hist[t] = 0;
+    __syncthreads();
+  }
   const int64_t base = (int64_t)blockIdx.x * kScanRows;
   long long s = 0, f = 0;
 #pragma unroll
@@ -638,7 +672,13 @@ __global__ __launch_bounds__(kScanThreads) void k_count_rows(Problem pr, int32_t
         c = cnt[i];
       }
       s += c;
-      f += pr.flops[i];
+      const int64_t fi = pr.flops[i];
+      f += fi;
+      if (bin && fi > 0) {
+        int cls, key, count, ce;
+        num_key(fi, pr.arp[i + 1] - pr.arp[i], nb.th, cls, key, count, ce);
+        atomicAdd(&hist[key], count);
+      }
     }
   }
   long long tot, ftot;
@@ -647,6 +687,11 @@ __global__ __launch_bounds__(kScanThreads) void k_count_rows(Problem pr, int32_t
   if (threadIdx.x == 0) {
     block_sums[blockIdx.x] = tot;
     block_sums[gridDim.x + blockIdx.x] = ftot;
+  }
+  if (bin) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x)
+      if (hist[t]) atomicAdd(&(&ctr->num_count[0][0])[t], hist[t]);
   }
 }
 
@@ -672,9 +717,76 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_block_sums(int64_t nblock
   }
 }
 
+// Numeric items of rows [r0, r1), one workgroup. Items are placed with one
+// global reservation per (class, bin) bucket per workgroup (counts from a
+// first pass over its rows): the bucket's offset (an exclusive scan of the
+// bucket counts, done by every workgroup: 128 values) plus the bucket's fill
+// counter (num_cursor, zero at the start); the slot inside the workgroup's
+// range comes from an LDS counter in the second pass. Workgroup 0 also
+// stores the class totals.
+__device__ __forceinline__ void num_fill_rows(const Problem& pr, const NumBinArgs& nb, Counters* ctr, int64_t r0,
+                                              int64_t r1) {
+  __shared__ int32_t cnt[kNumClasses * kBins], base[kNumClasses * kBins], off[kNumClasses * kBins];
+  __shared__ int32_t nsplit, split_base;
+  for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) cnt[t] = 0;
+  if (threadIdx.x == 0) {
+    nsplit = 0;
+    int32_t o = 0;
+    for (int t = 0; t < kNumClasses * kBins; ++t) {
+      off[t] = o;
+      o += (&ctr->num_count[0][0])[t];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x < kNumClasses) {
+    int32_t tot = 0;
+    for (int b = 0; b < kBins; ++b) tot += ctr->num_count[threadIdx.x][b];
+    (&ctr->num_split_items)[threadIdx.x] = tot;  // split, block, wave, light: consecutive fields
+  }
+  __syncthreads();
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const int64_t f = pr.flops[i];
+    if (f > 0) {
+      int cls, key, count, ce;
+      num_key(f, pr.arp[i + 1] - pr.arp[i], nb.th, cls, key, count, ce);
+      atomicAdd(&cnt[key], count);
+      if (cls == 0) atomicAdd(&nsplit, 1);
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < kNumClasses * kBins; t += blockDim.x) {
+    if (cnt[t]) base[t] = off[t] + atomicAdd(&(&ctr->num_cursor[0][0])[t], cnt[t]);
+    cnt[t] = 0;
+  }
+  if (threadIdx.x == 0) {
+    if (nsplit) split_base = atomicAdd(&ctr->num_split_rows, nsplit);
+    nsplit = 0;
+  }
+  __syncthreads();
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+    const int64_t f = pr.flops[i];
+    if (f <= 0) continue;
+    const int a = pr.arp[i], m = pr.arp[i + 1] - a;
+    int cls, key, count, ce;
+    num_key(f, m, nb.th, cls, key, count, ce);
+    const int pos = base[key] + atomicAdd(&cnt[key], count);
+    if (cls == 0) {
+      for (int c = 0; c < count; ++c) {
+        const int p0 = a + c * ce;
+        nb.items[pos + c] = Item{(int32_t)i, p0, min(a + m, p0 + ce), pos + c};
+      }
+      nb.split_rows[split_base + atomicAdd(&nsplit, 1)] = SplitRow{(int32_t)i, pos, count, 0};
+    } else {
+      nb.items[pos] = Item{(int32_t)i, a, a + m, cls == 1 ? kNoSlot : 0};
+    }
+  }
+}
+
+// C's row pointers of the block's rows from the scanned block sums; with
+// `bin`, also the block's numeric items (num_fill_rows: the bucket counts
+// are complete once k_count_rows has finished).
 __global__ __launch_bounds__(kScanThreads) void k_write_rowptr(Problem pr, const int32_t* cnt,
                                                                const int64_t* block_sums, int32_t* crp,
-                                                               const Counters* ctr) {
+                                                               NumBinArgs nb, bool bin, Counters* ctr) {
   __shared__ long long sh[32];
   const int64_t base = (int64_t)blockIdx.x * kScanRows;
   long long carry = block_sums[blockIdx.x];
@@ -688,15 +800,18 @@ __global__ __launch_bounds__(kScanThreads) void k_write_rowptr(Problem pr, const
     carry += tot;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) crp[pr.n] = (int32_t)ctr->nnz_total;
+  if (bin) num_fill_rows(pr, nb, ctr, base, min((int64_t)pr.n, base + kScanRows));
 }
 
 int launch_count_scan(const Problem& pr, int32_t* cnt, int64_t* block_sums, int32_t* c_rowptr, Counters* ctr,
-                      hipStream_t st) {
-  const int64_t nb = (pr.n + kScanRows - 1) / kScanRows;
-  if (nb > 0) k_count_rows<<<(unsigned)nb, kScanThreads, 0, st>>>(pr, cnt, block_sums);
-  k_scan_block_sums<<<1, kScanThreads, 0, st>>>(nb, block_sums, ctr);
-  if (nb > 0)
-    k_write_rowptr<<<(unsigned)nb, kScanThreads, 0, st>>>(pr, cnt, block_sums, c_rowptr, ctr);
+                      hipStream_t st, const NumBinArgs* nb) {
+  const int64_t nb_blocks = (pr.n + kScanRows - 1) / kScanRows;
+  const NumBinArgs args = nb ? *nb : NumBinArgs{};
+  const bool bin = nb != nullptr;
+  if (nb_blocks > 0) k_count_rows<<<(unsigned)nb_blocks, kScanThreads, 0, st>>>(pr, cnt, block_sums, args, bin, ctr);
+  k_scan_block_sums<<<1, kScanThreads, 0, st>>>(nb_blocks, block_sums, ctr);
+  if (nb_blocks > 0)
+    k_write_rowptr<<<(unsigned)nb_blocks, kScanThreads, 0, st>>>(pr, cnt, block_sums, c_rowptr, args, bin, ctr);
   else
     k_fill_i32<<<1, 64, 0, st>>>(c_rowptr, 1, 0);
   TSS_CHECK_LAUNCH();
