@@ -340,7 +340,8 @@ int tsspgemm_merge_values(int32_t count, const tsspgemm_csr* parts, const int32_
  * instances with the same group widths, product layout and LDS strip size.
  * tsspgemm_batched_plan sizes everything once (it runs the symbolic phase;
  * synchronizes); the patterns of A_t and B_t must not change afterwards,
- * their values may.
+ * their values may. The plan also records each A entry's B row bounds (8 B
+ * per A entry of batch workspace), which the numeric phase reads.
  *   As, Bs: HOST arrays of `count` descriptors (device data).
  *   tune: NULL (one group width and product layout for the whole batch,
  *   from the mean B row length over all instances), or a HOST array of

@@ -91,6 +91,17 @@ __device__ __forceinline__ int find_rank(const int64_t* off, int lo, int hi, int
   return lo;
 }
 
+// Each A entry's B row bounds (brp[k], brp[k + 1]) for its column k, built
+// once by the batch plan (the patterns are fixed for the batch's life) and
+// read by the numeric staging instead of gathering B's row pointers.
+__global__ void k_b_entry_bounds(const int32_t* __restrict__ aci, const int32_t* __restrict__ brp, int64_t nnz,
+                                 int2* __restrict__ out) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+    const int k = aci[p];
+    out[p] = make_int2(brp[k], brp[k + 1]);
+  }
+}
+
 __global__ void k_b_zero(Counters* ctr) {
   uint32_t* p = (uint32_t*)ctr;
   for (size_t t = threadIdx.x; t < sizeof(Counters) / 4; t += blockDim.x) p[t] = 0u;
@@ -656,6 +667,7 @@ struct Batch {
   };
   std::vector<SymGroup> sym_groups;
   std::vector<BInst> host_insts;
+  DevBuf ebnd;  // per A entry of every instance, its B row bounds (int2), from the plan
   DevBuf insts, offs, work, sym_items, sym_inst, num_items, num_inst, split_rows, partial, block_sums, inst_flops,
       ctr, tmp_rowptrs, tmp_off, nbins;
   int64_t total_rows = 0, total_bm = 0, total_sb = 0, rowptr_total = 0;
@@ -850,8 +862,12 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
       (rc = bt->nbins.ensure((size_t)3 * (kNumClasses + 1) * (count + 1) * kBins * 4)) ||
       (rc = bt->tmp_off.ensure(8 * (count + 1))))
     return rc;
+  int64_t a_nnz_total = 0;
+  for (int t = 0; t < count; ++t) a_nnz_total += As[t].nnz;
+  if ((rc = bt->ebnd.ensure(sizeof(int2) * (a_nnz_total + 1)))) return rc;
   TSS_HIP(hipHostMalloc((void**)&bt->host_ctr, sizeof(Counters), hipHostMallocDefault));
   bt->host_insts.resize(count);
+  int64_t a_off = 0;
   int64_t rp_off = 0;
   std::vector<int64_t> rank_t(count + 1, 0), rrow_off(count + 1, 0);
   for (int t = 0; t < count; ++t) {
@@ -875,6 +891,14 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     in.pr.flops = (int64_t*)(base + 2 * n * wp * 4);
     in.cnt = (int32_t*)(base + 2 * n * wp * 4 + n * 8);
     in.pr.bcol = base + ((2 * n * wp * 4 + n * 8 + n * 4) + 255) / 256 * 256;
+    int2* eb = (int2*)bt->ebnd.p + a_off;
+    in.pr.ebnd = eb;
+    if (A->nnz > 0) {
+      const unsigned g = (unsigned)std::min<int64_t>((A->nnz + 255) / 256, 8192);
+      k_b_entry_bounds<<<g, 256, 0, st>>>(A->colidx, B->rowptr, A->nnz, eb);
+      TSS_CHECK_LAUNCH();
+    }
+    a_off += A->nnz;
     tsspgemm_tuning tn;
     resolve_tuning(tunes ? &tunes[t] : nullptr, B, &tn);
     if (!tunes) {
