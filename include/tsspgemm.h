@@ -201,7 +201,9 @@ int tsspgemm_masked_bool(const tsspgemm_csr* A, const tsspgemm_csr* F, const tss
  *   product (the last entry is 0).
  *   Synchronizes once per iteration. 1 <= d <= 1024. A source outside
  *   [0, n) gives TSSPGEMM_ERR_INVALID_ARG. Device memory: one n x d bitmap per
- *   iteration plus two more, and O(n) workspace. */
+ *   iteration plus two more, and O(n) workspace, kept per device between
+ *   calls (grown as needed); calls on one device are serialized, and a call
+ *   on another stream waits on the device for the previous one. */
 int tsspgemm_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, int32_t* levels, int32_t* iterations,
                    int64_t* frontier_nnz, int32_t capacity, void* stream);
 

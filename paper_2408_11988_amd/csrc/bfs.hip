@@ -252,6 +252,26 @@ struct BfsWork {
   }
 };
 
+// The BFS workspace of a device (counters, item list, visited set, one
+// frontier bitmap per level), kept between calls: the frontiers alone are
+// levels x n x wp words, which would otherwise be allocated and freed by
+// every call. Calls on one device hold its mutex for the whole search; the
+// plan's events order them across streams.
+struct BfsState {
+  std::mutex mu;
+  Plan p;
+  BfsWork w;
+};
+static std::mutex g_bfs_mu;
+static BfsState* g_bfs[64];
+
+static BfsState* bfs_state(int dev) {
+  std::lock_guard<std::mutex> lk(g_bfs_mu);
+  if (dev < 0 || dev >= 64) return nullptr;
+  if (!g_bfs[dev]) g_bfs[dev] = new (std::nothrow) BfsState();
+  return g_bfs[dev];
+}
+
 static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, int32_t* levels,
                      int32_t* iterations, int64_t* frontier_nnz, int32_t capacity, hipStream_t st) {
   int rc;
@@ -270,9 +290,19 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
   }
   const int64_t n = A->nrows;
   const int wp = bitmap_words(d);
-  Plan p;
-  BfsWork w;
-  TSS_HIP(hipHostMalloc((void**)&w.host_count, 2 * sizeof(int64_t), hipHostMallocDefault));
+  int dev = 0;
+  TSS_HIP(hipGetDevice(&dev));
+  BfsState* state = bfs_state(dev);
+  if (!state) {
+    set_error("msbfs: no workspace for this device");
+    return TSSPGEMM_ERR_NOMEM;
+  }
+  std::lock_guard<std::mutex> lk(state->mu);
+  StreamOrder so(&state->p, st);
+  if (so.rc) return so.rc;
+  Plan& p = state->p;
+  BfsWork& w = state->w;
+  if (!w.host_count) TSS_HIP(hipHostMalloc((void**)&w.host_count, 2 * sizeof(int64_t), hipHostMallocDefault));
   p.n = n;
   p.d = d;
   p.wp = wp;
@@ -290,7 +320,7 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
       (rc = w.part_or.ensure((size_t)(nblk + 1) * wp * 4)) || (rc = w.part_cnt.ensure((size_t)(nblk + 1) * 8)) ||
       (rc = w.count.ensure(16)))
     return rc;
-  TSS_HIP(hipHostMalloc((void**)&p.host_ctr, sizeof(Counters), hipHostMallocDefault));
+  if (!p.host_ctr) TSS_HIP(hipHostMalloc((void**)&p.host_ctr, sizeof(Counters), hipHostMallocDefault));
   if (validate_enabled() && (rc = validate_on_device(A, "A", (Counters*)p.ctr.p, p.host_ctr, st))) return rc;
   Counters* ctr = (Counters*)p.ctr.p;
   Problem pr{};
@@ -303,10 +333,12 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
   if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
   if ((rc = launch_sym_bin(pr, tn.sym_split_nnz, (Item*)p.sym_items.p, ctr, st))) return rc;
 
+  size_t nf = 0;  // frontiers of this call: w.fronts[0, nf)
   auto new_front = [&](uint32_t** out) -> int {
-    w.fronts.emplace_back();
-    int r = w.fronts.back().ensure((size_t)n * wp * 4);
-    *out = (uint32_t*)w.fronts.back().p;
+    if (nf == w.fronts.size()) w.fronts.emplace_back();
+    int r = w.fronts[nf].ensure((size_t)n * wp * 4);
+    *out = (uint32_t*)w.fronts[nf].p;
+    ++nf;
     return r;
   };
   auto update = [&](const uint32_t* N, int64_t* cnt_out) -> int {
@@ -350,7 +382,7 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
     ++it;
     uint32_t* nt = nullptr;
     if ((rc = new_front(&nt))) return rc;
-    pr.bbits = (const uint32_t*)w.fronts[w.fronts.size() - 2].p;
+    pr.bbits = (const uint32_t*)w.fronts[nf - 2].p;
     pr.cbits = nt;
     SymParams sp{};
     sp.pr = pr;
@@ -367,7 +399,7 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
     if (frontier_nnz && it <= capacity) frontier_nnz[it - 1] = cnt;
   }
   // levels from the kept frontiers N_0 .. N_T (the last one is empty)
-  const int32_t nfront = (int32_t)w.fronts.size() - 1;
+  const int32_t nfront = (int32_t)nf - 1;
   std::vector<const uint32_t*> fp(nfront);
   for (int t = 0; t < nfront; ++t) fp[t] = (const uint32_t*)w.fronts[t].p;
   if ((rc = w.fronts_dev.ensure(sizeof(void*) * (nfront + 1)))) return rc;

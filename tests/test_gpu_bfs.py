@@ -134,3 +134,21 @@ def test_bad_source_is_an_error():
     with pytest.raises(_lib.TSSpGEMMError) as e:
         tss.msbfs(to_dev(a, with_values=False), torch.tensor([1, 8], dtype=torch.int32, device="cuda"))
     assert e.value.code == _lib.ERR_INVALID_ARG
+
+
+def test_workspace_reused_across_calls():
+    """The device's BFS workspace is kept between calls: a deeper search on a
+    larger graph, then a shallow one on a smaller graph with another d (the
+    kept frontiers are longer than needed), then the first again, each
+    matching the queue BFS exactly."""
+    rng = np.random.default_rng(1700)
+    n1 = 3000
+    path = _sym(n1, [(i, i + 1) for i in range(n1 - 1)] + [(i, i + 3) for i in range(0, n1 - 3, 7)])
+    s1 = rng.choice(n1, size=64, replace=False).astype(np.int32)
+    pat = rng.random((500, 500)) < 0.01
+    small = csr_from_dense_pattern((pat | pat.T).astype(np.int64))
+    s2 = rng.choice(500, size=200, replace=False).astype(np.int32)
+    for a, s in ((path, s1), (small, s2), (path, s1)):
+        note(f"msbfs n={a.nrows} d={len(s)}")
+        lev, fn = _bfs(a, s)
+        assert np.array_equal(lev, oracle.bfs_queue(a.rp, a.ci, s))
