@@ -331,7 +331,7 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
   pr.aci = A->colidx;
   pr.flops = (int64_t*)p.flops.p;
   if ((rc = launch_zero_bytes(ctr, sizeof(Counters), st))) return rc;
-  if ((rc = launch_sym_bin(pr, tn.sym_split_nnz, (Item*)p.sym_items.p, ctr, st))) return rc;
+  if ((rc = launch_sym_bin(pr, tn.sym_split_nnz, (Item*)p.sym_items.p, ctr, st, false, kSlotRowMaxBfs))) return rc;
 
   size_t nf = 0;  // frontiers of this call: w.fronts[0, nf)
   auto new_front = [&](uint32_t** out) -> int {
@@ -392,6 +392,7 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
     sp.active = (const uint32_t*)w.active.p;
     sp.fnz = (const uint32_t*)w.fnz.p;
     sp.early_exit = true;
+    sp.light_max = kSlotRowMaxBfs;
     if ((rc = launch_sym_split_zero(pr, sp.items, ctr, sym_cap, st)) || (rc = launch_symbolic(sp, sym_cap, st)) ||
         (rc = launch_sym_split_mask(pr, sp.items, sp.mask, ctr, sym_cap, st)))
       return rc;

@@ -21,6 +21,17 @@ constexpr int kBins = 32;  // work classes by floor(log2(work)); heavier first
 constexpr int kBinRowsPerBlock = 4096;
 constexpr int kNumClasses = 4;  // numeric: 0 split chunks, 1 workgroup rows, 2 wavefront rows, 3 light rows
 
+// Rows with at most kSlotRowMax A entries ("light" rows, the bulk of a
+// power-law graph) are processed straight from the row index, one row per
+// lane or per slot of wp lanes. Heavier rows are binned into an item list
+// (heaviest first) and take a whole wavefront, or several when split. The
+// multi-source BFS takes rows of up to kSlotRowMaxBfs entries as light: its
+// light rows stop early and skip the neighbours outside the frontier, so a
+// lane can walk longer rows (R-MAT 22 x 512: 18.2 against 18.7 ms; the
+// plain pass is fastest at 32: 0.345 ms, against 0.364 at 64 and 0.359 at 16).
+constexpr int kSlotRowMax = 32;
+constexpr int kSlotRowMaxBfs = 64;
+
 // Product-count thresholds of the numeric work classes.
 struct NumThresholds {
   int64_t light_max, wave_max, split;
@@ -90,6 +101,9 @@ struct SymParams {
   // masked result. Only for pattern-only (OR, AND) work with a mask and fnz;
   // `flops` then counts the products examined, not all of them.
   bool early_exit;
+  // rows with at most this many A entries are light: walked by the light-row
+  // kernels, not listed (the same value as the binning's)
+  int32_t light_max = kSlotRowMax;
 };
 
 // Item list layout: [split chunks][workgroup rows][wavefront rows][light rows].
@@ -116,8 +130,9 @@ int launch_validate_csr(int64_t nrows, int64_t ncols, int64_t nnz, const int32_t
 
 // zero_split: also clear the C bitmap row and product count of every split
 // row (its chunks OR and add into them), in place of launch_sym_split_zero
+// light_max: rows with at most this many A entries are light (not listed)
 int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st,
-                   bool zero_split = false);
+                   bool zero_split = false, int32_t light_max = kSlotRowMax);
 int launch_symbolic(const SymParams& sp, int64_t max_items, hipStream_t st);
 // The light-row kernel, the heavy-item kernel, or both (they touch disjoint
 // rows, so they may run on two streams at once).

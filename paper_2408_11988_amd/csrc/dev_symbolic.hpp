@@ -163,11 +163,6 @@ __device__ __forceinline__ long long block_exscan_1024(long long v, long long* s
 }
 
 
-// Rows with at most kSlotRowMax A entries ("light" rows, the bulk of a
-// power-law graph) are processed straight from the row index, one row per
-// slot of wp lanes. Heavier rows are binned into an item list (heaviest
-// first) and take a whole wavefront, or several when split.
-constexpr int kSlotRowMax = 32;
 
 // Work class of a row with m > 0 entries: floor(log2 m) mapped so that heavier
 // rows get smaller bin numbers; bin 0 holds the chunks of split rows.
@@ -178,8 +173,9 @@ __device__ __forceinline__ int bin_of(int64_t work) {
 }
 
 // bin and item count of row i in the heavy-row list (count 0: not listed)
-__device__ __forceinline__ void sym_bin(int m, int32_t split_nnz, int& bin, int& count) {
-  if (m <= kSlotRowMax) {
+__device__ __forceinline__ void sym_bin(int m, int32_t split_nnz, int& bin, int& count,
+                                        int light_max = kSlotRowMax) {
+  if (m <= light_max) {
     bin = 0;
     count = 0;
   } else if (m <= split_nnz) {

@@ -136,7 +136,8 @@ __device__ __forceinline__ void bin_rows(const int32_t* __restrict__ arp, int64_
   for (int u = 0; u < kBinPer; ++u) m[u] = e[u] - a[u];
 }
 
-__global__ __launch_bounds__(kBinThreads) void k_sym_bin_count(Problem pr, int32_t split_nnz, Counters* ctr) {
+__global__ __launch_bounds__(kBinThreads) void k_sym_bin_count(Problem pr, int32_t split_nnz, int32_t light_max,
+                                                               Counters* ctr) {
   __shared__ int32_t hist[kBins];
   if (threadIdx.x < kBins) hist[threadIdx.x] = 0;
   int a[kBinPer], m[kBinPer];
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(kBinThreads) void k_sym_bin_count(Problem pr, int32
 #pragma unroll
   for (int u = 0; u < kBinPer; ++u) {
     int bin, count;
-    sym_bin(m[u], split_nnz, bin, count);
+    sym_bin(m[u], split_nnz, bin, count, light_max);
     if (count) atomicAdd(&hist[bin], count);
   }
   __syncthreads();
@@ -157,8 +158,8 @@ __global__ __launch_bounds__(kBinThreads) void k_sym_bin_count(Problem pr, int32
 // counts, done by every workgroup) plus the bin's fill counter (sym_cursor,
 // zero at the start); the slot inside the workgroup's range comes from an
 // LDS counter in the second pass. Workgroup 0 stores the item total.
-__global__ __launch_bounds__(kBinThreads) void k_sym_bin_fill(Problem pr, int32_t split_nnz, Item* items,
-                                                              Counters* ctr, bool zero_split) {
+__global__ __launch_bounds__(kBinThreads) void k_sym_bin_fill(Problem pr, int32_t split_nnz, int32_t light_max,
+                                                              Item* items, Counters* ctr, bool zero_split) {
   __shared__ int32_t cnt[kBins], base[kBins], off[kBins];
   if (threadIdx.x < kBins) cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(kBinThreads) void k_sym_bin_fill(Problem pr, int32_
 #pragma unroll
   for (int u = 0; u < kBinPer; ++u) {
     int bin, count;
-    sym_bin(m[u], split_nnz, bin, count);
+    sym_bin(m[u], split_nnz, bin, count, light_max);
     if (count) atomicAdd(&cnt[bin], count);
   }
   __syncthreads();
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kBinThreads) void k_sym_bin_fill(Problem pr, int32_
 #pragma unroll
   for (int u = 0; u < kBinPer; ++u) {
     int bin, count;
-    sym_bin(m[u], split_nnz, bin, count);
+    sym_bin(m[u], split_nnz, bin, count, light_max);
     if (!count) continue;
     const int64_t i = r0 + threadIdx.x + (int64_t)kBinThreads * u;
     const int pos = base[bin] + atomicAdd(&cnt[bin], count);
@@ -209,11 +210,11 @@ __global__ __launch_bounds__(kBinThreads) void k_sym_bin_fill(Problem pr, int32_
 }
 
 int launch_sym_bin(const Problem& pr, int32_t split_nnz, Item* items, Counters* ctr, hipStream_t st,
-                   bool zero_split) {
+                   bool zero_split, int32_t light_max) {
   if (pr.n == 0) return TSSPGEMM_OK;  // the zeroed counters are the totals
   const unsigned g = grid_for(pr.n, kBinRowsPerBlock);
-  k_sym_bin_count<<<g, kBinThreads, 0, st>>>(pr, split_nnz, ctr);
-  k_sym_bin_fill<<<g, kBinThreads, 0, st>>>(pr, split_nnz, items, ctr, zero_split);
+  k_sym_bin_count<<<g, kBinThreads, 0, st>>>(pr, split_nnz, light_max, ctr);
+  k_sym_bin_fill<<<g, kBinThreads, 0, st>>>(pr, split_nnz, light_max, items, ctr, zero_split);
   TSS_CHECK_LAUNCH();
   return TSSPGEMM_OK;
 }
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_light(SymParams sp) {
   const int32_t* __restrict__ aci = pr.aci;
   if (row >= pr.n) return;
   const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
-  if (p1 - p0 > kSlotRowMax) return;  // a heavy row: done from the item list
+  if (p1 - p0 > sp.light_max) return;  // a heavy row: done from the item list
   uint32_t mword = 0u, need = 0xffffffffu;
   bool work = p1 > p0;
   if (sp.mask) {
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_light_lanes(SymParams sp) {
   const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (row >= pr.n) return;
   const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
-  if (p1 - p0 > kSlotRowMax) return;  // a heavy row: done from the item list
+  if (p1 - p0 > sp.light_max) return;  // a heavy row: done from the item list
   const uint32_t* __restrict__ bb = pr.bbits;
   BmRow<WP> acc;
 #pragma unroll
@@ -460,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_symbolic_light_lanes_m(SymParams sp)
   const int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (row >= pr.n) return;
   const int p0 = pr.arp[row], p1 = pr.arp[row + 1];
-  if (p1 - p0 > kSlotRowMax) return;  // a heavy row: done from the item list
+  if (p1 - p0 > sp.light_max) return;  // a heavy row: done from the item list
   const uint32_t* __restrict__ bb = pr.bbits;
   const uint32_t* __restrict__ fnz = sp.fnz;
   BmRow<WP> need, acc;
