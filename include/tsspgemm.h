@@ -120,7 +120,8 @@ typedef struct {
   int32_t group_lanes;     /* lanes that stream one B row: 4,8,16,32,64 (0: from mean B row length) */
   int32_t wave_max_flops;  /* rows with at most this many products use one wavefront             */
   int32_t split_flops;     /* rows above this are split into chunks of about this many products   */
-  int32_t sym_split_nnz;   /* symbolic pass: rows with more A entries than this are split         */
+  int32_t sym_split_nnz;   /* symbolic pass: rows with more A entries than this are split (8192;
+                              a batch: 2048, or its first tuning's)                               */
   int32_t accumulator;     /* tsspgemm_accumulator: 0 auto, 1 LDS strip, 2 hash                    */
   int32_t light_max_flops; /* rows with at most this many products use one lane group            */
   int32_t products;        /* tsspgemm_products: how lanes cover a row's products                  */
@@ -347,7 +348,8 @@ int tsspgemm_merge_values(int32_t count, const tsspgemm_csr* parts, const int32_
  *   As, Bs: HOST arrays of `count` descriptors (device data).
  *   tune: NULL (one group width and product layout for the whole batch,
  *   from the mean B row length over all instances), or a HOST array of
- *   `count` tunings, each instance's own.
+ *   `count` tunings, each instance's own (except sym_split_nnz, the
+ *   batch's: the first tuning's).
  *   pool_capacity: HOST out, sum of nnz(C_t) = entries of the output pool.
  *   rowptr_total: HOST out, sum of (n_t + 1).
  * tsspgemm_batched_run queues the whole batch (symbolic, scans, numeric) on

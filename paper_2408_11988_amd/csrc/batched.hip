@@ -91,6 +91,8 @@ __device__ __forceinline__ int find_rank(const int64_t* off, int lo, int hi, int
   return lo;
 }
 
+constexpr int32_t kBatchSymSplit = 2048;  // symbolic split size of a batch without tunings
+
 // Each A entry's B row bounds (brp[k], brp[k + 1]) for its column k, built
 // once by the batch plan (the patterns are fixed for the batch's life) and
 // read by the numeric staging instead of gathering B's row pointers.
@@ -821,9 +823,6 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     ws_bytes += ((2 * n * wp * 4 + n * 8 + n * 4) + 255) / 256 * 256;
     ws_bytes += (B->nnz * 2 + 255) / 256 * 256;  // narrowed column ids (at most 2 bytes each)
     rp_total += n + 1;
-    tsspgemm_tuning tn;
-    resolve_tuning(tunes ? &tunes[t] : nullptr, B, &tn);
-    sym_cap += n + A->nnz / tn.sym_split_nnz + 2;
     num_cap += 2 * n + A->nnz / 64 + 2;
   }
   bt->dmax = dmax;
@@ -842,10 +841,15 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     const tsspgemm_csr mean_b{bn, dmax, bnnz, nullptr, nullptr, nullptr};
     tsspgemm_tuning t0;
     resolve_tuning(tunes ? &tunes[0] : nullptr, &mean_b, &t0);
-    bt->dev.sym_split = t0.sym_split_nnz;
+    // the single-product default (8192) measured slower on the 64-instance
+    // batch, whose rows are short: 6.26 ms at 4096 against 6.22 at 2048
+    bt->dev.sym_split = tunes && tunes[0].sym_split_nnz > 0 ? tunes[0].sym_split_nnz : kBatchSymSplit;
     batch_gl = t0.group_lanes;
     batch_products = t0.products;
   }
+  // symbolic items: one per heavy row, one per chunk of the batch's split
+  // size (the first tuning's, for every instance)
+  for (int t = 0; t < count; ++t) sym_cap += As[t].nrows + As[t].nnz / bt->dev.sym_split + 2;
   bt->total_rows = row_off[count];
   bt->total_bm = bm_off[count];
   bt->total_sb = sb_off[count];

@@ -86,6 +86,30 @@ def bt_group_lanes(pairs):
     return gl
 
 
+def test_symbolic_split_size_is_the_batchs():
+    """The symbolic split size of a batch is its first tuning's, for every
+    instance: the item list is sized with it even when the other tunings
+    name a far larger one (rows of hundreds of A entries cut in 40-entry
+    chunks)."""
+    from paper_2408_11988_amd.batched import Batched
+
+    rng = np.random.default_rng(77)
+    host = []
+    for n, d in ((600, 64), (800, 128), (500, 32)):
+        a = random_csr(rng, n, n, 0.01, empty_rows=0.1, dense_rows=4)
+        b = random_csr(rng, n, d, 0.1, empty_rows=0.1)
+        host.append((a, b))
+    assert max(np.diff(a.rp).max() for a, _ in host) > 200
+    pairs = [(to_dev(a), to_dev(b)) for a, b in host]
+    tunings = [dict(sym_split_nnz=40)] + [dict(sym_split_nnz=1 << 20) for _ in host[1:]]
+    note("batched with a 40-entry symbolic split from the first tuning")
+    bt = Batched(pairs, tunings)
+    bt.run()
+    torch.cuda.synchronize()
+    for (a, b), C in zip(host, bt.outputs()):
+        compare_f32(a, b, C)
+
+
 def test_graph_replays():
     import paper_2408_11988_amd as tss
     from paper_2408_11988_amd.batched import Batched
