@@ -130,6 +130,16 @@ int default_products(double mean_b_row, int group_lanes) {
   return mean_b_row >= 48.0 ? TSSPGEMM_PRODUCTS_FLAT : TSSPGEMM_PRODUCTS_PER_B_ROW;
 }
 
+// Entries per symbolic chunk of a split row when the caller leaves it open.
+// Heavy kernels that stop once a row's pattern is full (the unmasked lane
+// form, bitmaps of at most 8 words) or its open columns are covered (the
+// BFS) take 8192: at R-MAT 20 x 128 the pass takes 0.345 / 0.343 / 0.336 /
+// 0.362 ms with 2048 / 4096 / 8192 / 16384, the R-MAT 22 x 512 BFS 18.3 /
+// 17.2 / 16.9 / 17.4 ms. The others walk every entry, some 8 per step (the
+// slot form at d > 512), and keep 2048: 8192 took the R-MAT 18 x 1024 pass
+// from 0.51 to 1.03 ms.
+int32_t sym_split_default(int wp, bool stops_early) { return stops_early || wp <= 8 ? 8192 : 2048; }
+
 void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tuning* out) {
   tsspgemm_tuning r{};
   if (t) r = *t;
@@ -141,10 +151,9 @@ void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tu
   if (r.split_flops <= 0) r.split_flops = 262144;
   if (r.wave_max_flops < r.light_max_flops) r.wave_max_flops = r.light_max_flops;
   if (r.split_flops < r.wave_max_flops) r.split_flops = r.wave_max_flops;
-  // symbolic chunks of split rows: at R-MAT 20 x 128 the pass takes 0.345 /
-  // 0.343 / 0.336 / 0.362 ms with 2048 / 4096 / 8192 / 16384 entries, the
-  // R-MAT 22 x 512 BFS 18.3 / 17.2 / 16.9 / 17.4 ms (batches keep 2048)
-  if (r.sym_split_nnz <= 0) r.sym_split_nnz = 8192;
+  // symbolic chunks of split rows (larger ones where the heavy kernel stops
+  // early: see sym_split_default)
+  if (r.sym_split_nnz <= 0) r.sym_split_nnz = 2048;
   if (r.products == TSSPGEMM_PRODUCTS_AUTO) r.products = default_products(mean_b_row(B), r.group_lanes);
   if (r.accumulator == TSSPGEMM_ACC_AUTO)
     r.accumulator = B->ncols > kMaxDenseD ? TSSPGEMM_ACC_HASH : TSSPGEMM_ACC_LDS_STRIP;
@@ -333,6 +342,8 @@ int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, 
   }
   tsspgemm_tuning tn;
   resolve_tuning(tune, B, &tn);
+  if (!(tune && tune->sym_split_nnz > 0))  // masked passes take the lane form with the mask, which walks every entry
+    tn.sym_split_nnz = sym_split_default(M && M->kind != TSSPGEMM_MASK_NONE ? 16 : bitmap_words((int32_t)B->ncols), false);
   if (tn.accumulator != TSSPGEMM_ACC_LDS_STRIP && tn.accumulator != TSSPGEMM_ACC_HASH) {
     set_error("unknown accumulator");
     return TSSPGEMM_ERR_INVALID_ARG;

@@ -104,6 +104,7 @@ int check_csr(const tsspgemm_csr* m, const char* name, bool need_vals);
 bool validate_enabled();
 int validate_on_device(const tsspgemm_csr* m, const char* name, Counters* dctr, Counters* hctr, hipStream_t st);
 void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tuning* out);
+int32_t sym_split_default(int wp, bool stops_early);
 int run_symbolic(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int sr, const tsspgemm_mask* M,
                  const tsspgemm_tuning* tune, int32_t* c_rowptr, int64_t* c_nnz, hipStream_t st);
 int run_numeric(Plan* p, const tsspgemm_csr* A, const tsspgemm_csr* B, int32_t* c_colidx, void* c_vals,

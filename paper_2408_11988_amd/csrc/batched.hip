@@ -841,8 +841,8 @@ static int batch_plan(int32_t count, const tsspgemm_csr* As, const tsspgemm_csr*
     const tsspgemm_csr mean_b{bn, dmax, bnnz, nullptr, nullptr, nullptr};
     tsspgemm_tuning t0;
     resolve_tuning(tunes ? &tunes[0] : nullptr, &mean_b, &t0);
-    // the single-product default (8192) measured slower on the 64-instance
-    // batch, whose rows are short: 6.26 ms at 4096 against 6.22 at 2048
+    // 4096 measured slower than 2048 on the 64-instance batch, whose rows are
+    // short (6.26 against 6.22 ms)
     bt->dev.sym_split = tunes && tunes[0].sym_split_nnz > 0 ? tunes[0].sym_split_nnz : kBatchSymSplit;
     batch_gl = t0.group_lanes;
     batch_products = t0.products;

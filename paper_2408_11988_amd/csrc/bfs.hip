@@ -309,6 +309,7 @@ static int run_msbfs(const tsspgemm_csr* A, const int32_t* sources, int32_t d, i
   tsspgemm_tuning tn{};
   tsspgemm_csr bdummy{n, d, 0, A->rowptr, nullptr, nullptr};
   resolve_tuning(nullptr, &bdummy, &tn);
+  tn.sym_split_nnz = sym_split_default(wp, true);  // heavy items stop once their open columns are covered
   const int64_t sym_cap = n + A->nnz / tn.sym_split_nnz + 2;
   const int upd_v = wp < 4 ? wp : 4;                        // words per lane in k_bfs_update
   const int64_t upd_rows = 256 / (wp / upd_v);              // rows per tile
