@@ -121,8 +121,8 @@ typedef struct {
   int32_t wave_max_flops;  /* rows with at most this many products use one wavefront             */
   int32_t split_flops;     /* rows above this are split into chunks of about this many products   */
   int32_t sym_split_nnz;   /* symbolic pass: rows with more A entries than this are split (8192
-                              unmasked with d <= 256 and in the BFS, else 2048; a batch: 2048, or
-                              its first tuning's)                                                   */
+                              unmasked with d <= 256, 16384 in the BFS, else 2048; a batch: 2048,
+                              or its first tuning's)                                                */
   int32_t accumulator;     /* tsspgemm_accumulator: 0 auto, 1 LDS strip, 2 hash                    */
   int32_t light_max_flops; /* rows with at most this many products use one lane group            */
   int32_t products;        /* tsspgemm_products: how lanes cover a row's products                  */

@@ -132,13 +132,15 @@ int default_products(double mean_b_row, int group_lanes) {
 
 // Entries per symbolic chunk of a split row when the caller leaves it open.
 // Heavy kernels that stop once a row's pattern is full (the unmasked lane
-// form, bitmaps of at most 8 words) or its open columns are covered (the
-// BFS) take 8192: at R-MAT 20 x 128 the pass takes 0.345 / 0.343 / 0.336 /
-// 0.362 ms with 2048 / 4096 / 8192 / 16384, the R-MAT 22 x 512 BFS 18.3 /
-// 17.2 / 16.9 / 17.4 ms. The others walk every entry, some 8 per step (the
-// slot form at d > 512), and keep 2048: 8192 took the R-MAT 18 x 1024 pass
-// from 0.51 to 1.03 ms.
-int32_t sym_split_default(int wp, bool stops_early) { return stops_early || wp <= 8 ? 8192 : 2048; }
+// form, bitmaps of at most 8 words) take 8192: at R-MAT 20 x 128 the pass
+// takes 0.345 / 0.343 / 0.336 / 0.362 ms with 2048 / 4096 / 8192 / 16384
+// (with the heavy walk on eight times the resident wavefronts, 4096 and
+// 8192 tie at 0.314 and 16384 takes 0.320). The BFS, whose items stop once
+// their open columns are covered, takes 16384: R-MAT 22 x 512 in 14.6-14.7
+// ms, against 14.9 with 8192 and 4096. The others walk every entry, some 8
+// per step (the slot form at d > 512), and keep 2048: 8192 took the R-MAT
+// 18 x 1024 pass from 0.51 to 1.03 ms.
+int32_t sym_split_default(int wp, bool stops_early) { return stops_early ? 16384 : (wp <= 8 ? 8192 : 2048); }
 
 void resolve_tuning(const tsspgemm_tuning* t, const tsspgemm_csr* B, tsspgemm_tuning* out) {
   tsspgemm_tuning r{};
